@@ -1,0 +1,117 @@
+"""Statistical pins of the oracle's selection law (CPU only, fixed seeds).
+
+Theorem 1 (Section II-B): one draw selects candidate k with probability
+b_k / sum(b). Without replacement, the held set must follow updated sampling
+(fig:brs(b)): the j-th new candidate is drawn proportionally to the bias among
+those not yet held, which gives the successive-sampling set probabilities
+    P(T) = sum over orders u of T of prod_j b_{u_j} / (W - sum_{i<j} b_{u_i}).
+These are enumerated exactly here (fractions) and compared by chi-square with
+the frequencies over many independent instance ids.
+"""
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+
+N_INST = 120_000
+
+
+def star_graph(b):
+    d = len(b)
+    rowptr = np.array([0, d] + [d] * d, dtype=np.int64)
+    col = np.arange(1, d + 1, dtype=np.int32)
+    return rowptr, col, np.asarray(b, dtype=np.uint32)
+
+
+def exact_set_probs(b, k):
+    b = [int(x) for x in b]
+    W = sum(b)
+    pos = [i for i, x in enumerate(b) if x > 0]
+    probs = {}
+    for T in itertools.combinations(pos, k):
+        p = Fraction(0)
+        for order in itertools.permutations(T):
+            q, rem = Fraction(1), W
+            for u in order:
+                q *= Fraction(b[u], rem)
+                rem -= b[u]
+            p += q
+        probs[T] = p
+    assert sum(probs.values()) == 1
+    return probs
+
+
+def sample_star(b, k, rounds, rng_seed=1):
+    rowptr, col, ew = star_graph(b)
+    offs = np.arange(N_INST + 1, dtype=np.int64)
+    seeds = np.zeros(N_INST, dtype=np.int32)
+    res = oracle.sample(rowptr, col, ew, offs, seeds, [k], bias_kind=oracle.EDGE_WEIGHT,
+                        rng_seed=rng_seed, rounds=rounds)
+    P = int((np.asarray(b) > 0).sum())
+    m = min(k, P)
+    assert res.num_edges == N_INST * m
+    picks = (res.dst.reshape(N_INST, m) - 1).astype(np.int64)   # neighbor x = position + 1
+    return picks, res
+
+
+CASES = [
+    ((3, 6, 2, 2, 2), 1),
+    ((3, 6, 2, 2, 2), 2),
+    ((3, 6, 2, 2, 2), 3),
+    ((5, 1, 0, 9, 2, 7, 1), 4),
+    ((1000, 1, 1, 1, 1, 1), 4),     # skewed: the direct draw is reached often
+    ((1, 1, 1, 1), 3),
+]
+
+
+@pytest.mark.parametrize("rounds", [0, 8])
+@pytest.mark.parametrize("b,k", CASES)
+def test_set_law_is_updated_sampling(b, k, rounds):
+    picks, res = sample_star(b, k, rounds)
+    exact = exact_set_probs(b, k)
+    keys = sorted(exact)
+    index = {T: i for i, T in enumerate(keys)}
+    counts = np.zeros(len(keys), dtype=np.int64)
+    for row in np.sort(picks, axis=1):
+        counts[index[tuple(int(x) for x in row)]] += 1
+    expected = np.array([float(exact[T]) * N_INST for T in keys])
+    if len(keys) > 1:
+        p = stats.chisquare(counts, expected).pvalue
+        assert p > 1e-4, (b, k, rounds, p)
+    if rounds == 0 and k < int((np.asarray(b) > 0).sum()):
+        assert res.fallbacks == N_INST * k      # every slot takes the direct draw
+
+
+@pytest.mark.parametrize("b", [(3, 6, 2, 2, 2), (5, 1, 0, 9, 2, 7, 1), (1, 1 << 20, 3)])
+def test_theorem1_single_draw(b):
+    """k = 1: frequencies of the selected candidate match b_k / W."""
+    picks, _ = sample_star(b, 1, 8, rng_seed=77)
+    counts = np.bincount(picks[:, 0], minlength=len(b))
+    bb = np.asarray(b, dtype=np.float64)
+    nz = bb > 0
+    assert np.all(counts[~nz] == 0)
+    p = stats.chisquare(counts[nz], bb[nz] / bb.sum() * N_INST).pvalue
+    assert p > 1e-4
+
+
+def test_first_slot_follows_theorem1():
+    """Slot 0 draws first in round 0 and is always kept: its marginal law is
+    Theorem 1 even when k > 1."""
+    b = (5, 1, 0, 9, 2, 7, 1)
+    picks, _ = sample_star(b, 3, 8, rng_seed=5)
+    counts = np.bincount(picks[:, 0], minlength=len(b))
+    bb = np.asarray(b, dtype=np.float64)
+    nz = bb > 0
+    p = stats.chisquare(counts[nz], bb[nz] / bb.sum() * N_INST).pvalue
+    assert p > 1e-4
+
+
+def test_direct_draw_used_for_skewed_and_not_needed_for_flat():
+    _, res = sample_star((1000, 1, 1, 1, 1, 1), 4, 8)
+    assert res.fallbacks > 0.1 * N_INST
+    _, res = sample_star((1,) * 50, 4, 8)
+    assert res.fallbacks == 0

@@ -1,0 +1,175 @@
+"""Pins of the oracle's random walks (Section II-A) on CPU.
+
+The exact distribution of the walker's position after t steps is computed here
+from the transition matrix (first-order walks) or from the second-order
+edge-state chain (node2vec), with numpy, and compared by chi-square with the
+positions of many independent walkers.
+"""
+import collections
+
+import networkx as nx
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from paper_2009_09103_amd import inputs
+
+NW = 60_000
+
+
+def small_graph(seed=3, n=10, m=22, directed=False):
+    G = nx.gnm_random_graph(n, m, seed=seed, directed=directed)
+    edges = list(G.edges())
+    if not directed:
+        edges += [(v, u) for u, v in edges]
+    return inputs.csr_from_edges(n, edges)
+
+
+def first_order_matrix(rp, col, b):
+    n = len(rp) - 1
+    P = np.zeros((n + 1, n + 1))          # state n = stopped
+    for v in range(n):
+        w = b[rp[v]:rp[v + 1]].astype(np.float64)
+        if w.sum() == 0:
+            P[v, n] = 1.0
+        else:
+            for x, wx in zip(col[rp[v]:rp[v + 1]], w):
+                P[v, x] += wx / w.sum()
+    P[n, n] = 1.0
+    return P
+
+
+def compare(counts, probs):
+    nz = probs > 0
+    assert np.all(counts[~nz] == 0)
+    if nz.sum() > 1:
+        assert stats.chisquare(counts[nz], probs[nz] / probs[nz].sum() * counts.sum()).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("kind", ["uniform", "edge_weight", "neighbor_degree"])
+def test_first_order_t_step_law(kind):
+    rp, col = small_graph(seed=4, n=9, m=20, directed=True)    # directed: sinks possible
+    n = len(rp) - 1
+    g = np.random.Generator(np.random.PCG64(1))
+    if kind == "uniform":
+        bk, ew, b = oracle.UNIFORM, None, np.ones(len(col))
+    elif kind == "edge_weight":
+        ew = g.integers(0, 9, size=len(col)).astype(np.uint32)
+        bk, b = oracle.EDGE_WEIGHT, ew
+    else:
+        bk, ew, b = oracle.NEIGHBOR_DEGREE, None, np.diff(rp)[col]
+    start = int(np.argmax(np.diff(rp)))
+    T = 4
+    paths, steps, _ = oracle.walk(rp, col, ew, np.full(NW, start, dtype=np.int32), T, bias_kind=bk,
+                                  rng_seed=11)
+    P = first_order_matrix(rp, col, b)
+    p = np.zeros(n + 1)
+    p[start] = 1
+    for t in range(1, T + 1):
+        p = p @ P
+        pos = paths[:, t]
+        counts = np.bincount(np.where(pos < 0, n, pos), minlength=n + 1)
+        compare(counts, p)
+    # padding: -1 only after the walk stopped, steps = number of valid moves
+    valid = (paths[:, 1:] >= 0)
+    assert np.all(valid.sum(axis=1) == steps)
+    assert np.all(np.diff(valid.astype(int), axis=1) <= 0)
+
+
+def test_unbiased_stationary_degree_proportional():
+    """Connected, non-bipartite, undirected: visit frequencies of a simple
+    random walk converge to deg(v) / 2|E|."""
+    G = nx.connected_watts_strogatz_graph(30, 4, 0.3, seed=2)
+    assert nx.is_connected(G) and not nx.is_bipartite(G)
+    edges = list(G.edges()) + [(v, u) for u, v in G.edges()]
+    rp, col = inputs.csr_from_edges(30, edges)
+    paths, _, _ = oracle.walk(rp, col, None, np.zeros(2000, dtype=np.int32), 400, rng_seed=5)
+    visits = np.bincount(paths[:, 100:].ravel(), minlength=30).astype(np.float64)
+    freq = visits / visits.sum()
+    deg = np.diff(rp).astype(np.float64)
+    assert 0.5 * np.abs(freq - deg / deg.sum()).sum() < 0.02
+
+
+def node2vec_exact(rp, col, start, T, wr, wc, wo):
+    """Exact distribution of the position after 1..T steps of node2vec."""
+    n = len(rp) - 1
+    nb = [set(col[rp[v]:rp[v + 1]].tolist()) for v in range(n)]
+    lists = [col[rp[v]:rp[v + 1]].tolist() for v in range(n)]
+    out = []
+    # step 1 is unbiased
+    state = collections.defaultdict(float)
+    for x in lists[start]:
+        state[(start, x)] += 1.0 / len(lists[start])
+    for t in range(1, T + 1):
+        if t > 1:
+            nxt = collections.defaultdict(float)
+            for (tp, v), pr in state.items():
+                w = np.array([wr if x == tp else (wc if x in nb[tp] else wo) for x in lists[v]],
+                             dtype=np.float64)
+                for x, wx in zip(lists[v], w):
+                    nxt[(v, x)] += pr * wx / w.sum()
+            state = nxt
+        p = np.zeros(n)
+        for (_, v), pr in state.items():
+            p[v] += pr
+        out.append(p)
+    return out
+
+
+@pytest.mark.parametrize("weights", [(1, 2, 4), (4, 1, 2), (3, 3, 3)])
+def test_node2vec_t_step_law(weights):
+    rp, col = small_graph(seed=7, n=9, m=18)
+    start = 0
+    T = 4
+    paths, _, _ = oracle.walk(rp, col, None, np.full(NW, start, dtype=np.int32), T,
+                              bias_kind=oracle.NODE2VEC, node2vec=weights, rng_seed=21)
+    exact = node2vec_exact(rp, col, start, T, *weights)
+    for t in range(1, T + 1):
+        compare(np.bincount(paths[:, t], minlength=len(rp) - 1), exact[t - 1])
+
+
+def test_node2vec_equal_weights_is_uniform_walk():
+    """node2vec with w_return = w_common = w_outward equals the unbiased walk
+    (weight-scale invariance), bit for bit."""
+    rp, col = inputs.rmat_csr(10, 8192, 5, symmetrize=True)
+    starts = inputs.walker_starts(rp, col, 500, 1)
+    a, _, _ = oracle.walk(rp, col, None, starts, 20, bias_kind=oracle.NODE2VEC, node2vec=(5, 5, 5))
+    b, _, _ = oracle.walk(rp, col, None, starts, 20, bias_kind=oracle.UNIFORM)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_walk_draw_layout():
+    """Each step uses counter (walker id, step, vertex, 0): recomputed here with
+    the independent Philox and numpy's searchsorted."""
+    from tests.helpers import torch_philox
+    rp, col = inputs.rmat_csr(9, 4096, 8)
+    ew = inputs.dst_outdeg_weights(rp, col) + 1
+    starts = inputs.walker_starts(rp, col, 6, 2)
+    paths, _, _ = oracle.walk(rp, col, ew, starts, 5, bias_kind=oracle.EDGE_WEIGHT, rng_seed=123,
+                              walker_base=1000)
+    for w in range(6):
+        v = int(starts[w])
+        for s in range(5):
+            if rp[v + 1] == rp[v]:
+                assert paths[w, s + 1] == -1
+                break
+            S = np.concatenate([[0], np.cumsum(ew[rp[v]:rp[v + 1]].astype(np.uint64))])
+            r = torch_philox.draw(123, [1000 + w, s, v, 0], int(S[-1]))
+            m = int(np.searchsorted(S[:-1], r, side="right")) - 1
+            v = int(col[rp[v] + m])
+            assert paths[w, s + 1] == v
+
+
+def test_walk_threads_and_subsets_agree():
+    rp, col = inputs.rmat_csr(11, 20000, 9, symmetrize=True)
+    starts = inputs.walker_starts(rp, col, 3000, 3)
+    full, _, _ = oracle.walk(rp, col, None, starts, 15, bias_kind=oracle.NODE2VEC, node2vec=(1, 2, 4),
+                             rng_seed=4, nthreads=4)
+    one, _, _ = oracle.walk(rp, col, None, starts, 15, bias_kind=oracle.NODE2VEC, node2vec=(1, 2, 4),
+                            rng_seed=4, nthreads=1)
+    np.testing.assert_array_equal(full, one)
+    idx = np.arange(5, 3000, 97)
+    sub, _, _ = oracle.walk(rp, col, None, starts[idx], 15, bias_kind=oracle.NODE2VEC,
+                            node2vec=(1, 2, 4), rng_seed=4, walker_ids=idx.astype(np.uint64))
+    np.testing.assert_array_equal(sub, full[idx])
