@@ -1,0 +1,236 @@
+/*
+ * csaw.h -- C-ABI of libcsaw, an MI355X (gfx950) implementation of the hot
+ * path of C-SAW (Pandey et al., "C-SAW: A Framework for Graph Sampling and
+ * Random Walk on GPUs", SC20, arXiv 2009.09103): bias-based neighbor
+ * selection for graph sampling and random walks.
+ *
+ * The method (paper Sections II-B, III and IV):
+ *   - a candidate pool is the adjacency list N(v) of a frontier vertex
+ *     (GatherNeighbors, fig:api(b));
+ *   - every candidate carries a bias (EdgeBias, Eq. edgebias);
+ *   - a candidate is selected with probability proportional to its bias
+ *     (Theorem 1) by inverse transform sampling over the prefix sum of the
+ *     biases (Section II-B, Eq. equ:tp);
+ *   - sampling selects NeighborSize distinct candidates (without
+ *     replacement); a draw that hits an already selected candidate is
+ *     re-drawn (Section IV-B), and after a fixed number of rounds the
+ *     remaining slots draw directly from the prefix with the selected
+ *     candidates removed (updated sampling, fig:brs(b), through the inverse
+ *     map of Theorem 2, Eq. eq:brs_random);
+ *   - Update keeps vertices an instance already visited out of its frontier;
+ *     random walks select one candidate per step.
+ *
+ * Arithmetic is exact: uint32 biases, uint64 prefix sums, a 64-bit draw
+ * mapped onto [0, W) by r = floor(u * W / 2^64); no floating point. Random
+ * numbers come from Philox4x32-10 (Salmon et al., SC'11) keyed by the call's
+ * rng_seed (low 32 bits first) with one counter per draw:
+ *   sampling: (instance id mod 2^32, layer, vertex, slot | round << 16),
+ *             round 0..CSAW_ROUNDS-1, and round 0xFFFF for the direct draw;
+ *   walks:    (walker id mod 2^32, step, vertex, 0).
+ * Results therefore depend only on (graph, bias, seeds, fanouts or length,
+ * rng_seed, instance / walker ids): not on batching, launch shape, stream or
+ * order.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a csaw_status. No exception crosses the ABI.
+ *     csaw_last_error() gives a human-readable message for the calling
+ *     thread's last failure.
+ *   - "DEVICE" pointers are device memory of the graph's device (for
+ *     example a torch tensor's data_ptr()); "HOST" pointers are ordinary host
+ *     memory. The caller owns every buffer it passes; the library never
+ *     keeps a caller pointer after the call returns.
+ *   - stream is a hipStream_t (NULL = the legacy default stream). Work is
+ *     enqueued on it; csaw_sample and csaw_walk return after the stream has
+ *     finished the call's work, so outputs are ready on return.
+ *   - Vertex ids are int32 in [0, n), n < 2^31.
+ */
+#ifndef CSAW_H
+#define CSAW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CSAW_OK = 0,
+    CSAW_ERR_INVALID_ARG = 1,    /* bad argument; nothing was written        */
+    CSAW_ERR_OUT_OF_MEMORY = 2,  /* device allocation failed, or an output
+                                    capacity was too small (counts are still
+                                    reported)                                */
+    CSAW_ERR_DEVICE = 3,         /* a HIP call failed                         */
+    CSAW_ERR_BUSY = 4,           /* server queue full                         */
+    CSAW_ERR_NOT_READY = 5,      /* server result not finished yet            */
+    CSAW_ERR_UNSUPPORTED = 6     /* valid but outside this build's limits     */
+} csaw_status;
+
+/* EdgeBias kinds (Eq. edgebias, Section III-C; Table tbl:samplespace).
+ *   UNIFORM          b = 1: unbiased neighbor sampling, DeepWalk.
+ *   EDGE_WEIGHT      b = edge_weight[e] given at csaw_graph_create.
+ *   NEIGHBOR_DEGREE  b = out-degree of the neighbor: biased neighbor
+ *                    sampling and biased DeepWalk (Section II-A).
+ *   NODE2VEC         walks only: b = w_return if the neighbor is the previous
+ *                    vertex, w_common if it is adjacent to the previous
+ *                    vertex, w_outward otherwise (node2vec's second-order
+ *                    bias, Section II-A); the first step is unbiased.
+ *                    Requires sorted adjacency lists.                      */
+typedef enum {
+    CSAW_BIAS_UNIFORM = 0,
+    CSAW_BIAS_EDGE_WEIGHT = 1,
+    CSAW_BIAS_NEIGHBOR_DEGREE = 2,
+    CSAW_BIAS_NODE2VEC = 3
+} csaw_bias_kind;
+
+/* Fanout value meaning "every neighbor with a positive bias" (snowball). */
+#define CSAW_FANOUT_ALL (-1)
+/* Largest fanout that is drawn (a fanout >= the number of positive-bias
+ * neighbors takes all of them and has no limit). */
+#define CSAW_MAX_FANOUT 64
+/* Repeated-sampling rounds before the direct draw. */
+#define CSAW_ROUNDS 8
+/* Most layers per sampling call. */
+#define CSAW_MAX_LAYERS 16
+
+typedef struct csaw_graph_s* csaw_graph;
+typedef void* csaw_stream; /* hipStream_t */
+
+/* ------------------------------------------------------------------ graph */
+
+/* Upload a CSR graph to the current device; it stays resident in HBM until
+ * csaw_graph_destroy (the paper's in-memory setting, Section IV).
+ *   num_vertices  n, 0 <= n < 2^31
+ *   num_edges     m, 0 <= m < 2^40
+ *   rowptr        HOST int64[n+1], rowptr[0] = 0, non-decreasing, rowptr[n] = m
+ *   col           HOST int32[m], ids in [0, n); N(v) = col[rowptr[v] .. rowptr[v+1])
+ *   edge_weight   HOST uint32[m] or NULL (needed by CSAW_BIAS_EDGE_WEIGHT)
+ *   flags         must be 0
+ *   stream        used for the uploads; the call synchronises it
+ *   out           receives the handle
+ * Errors: INVALID_ARG for any violated bound above (checked on the host in
+ * O(n + m)); OUT_OF_MEMORY if the device allocations fail. Whether every
+ * adjacency list is sorted is recorded; NODE2VEC walks need it. */
+csaw_status csaw_graph_create(int64_t num_vertices, int64_t num_edges, const int64_t* rowptr,
+                              const int32_t* col, const uint32_t* edge_weight, uint32_t flags,
+                              csaw_stream stream, csaw_graph* out);
+
+/* Free the graph and its device memory. No call on it may be running. */
+csaw_status csaw_graph_destroy(csaw_graph g);
+
+/* HOST outputs (each nullable): n, m, largest out-degree, 1 if every
+ * adjacency list is sorted. */
+csaw_status csaw_graph_info(csaw_graph g, int64_t* num_vertices, int64_t* num_edges,
+                            int64_t* max_degree, int32_t* sorted);
+
+/* --------------------------------------------------------------- sampling */
+
+/* Neighbor sampling (fig:api(b) with FrontierSize = all): for every instance
+ * i, F_0 = the distinct seeds of i, which are also its visited set; layer l
+ * selects fanout(i, l) neighbors of every v in F_l (increasing v) and emits
+ * one edge (v, neighbor) per selection; F_{l+1} is the set of selected
+ * neighbors that i has not visited, which then become visited (Update,
+ * Eq. update). Edges to visited vertices are still emitted. An instance stops
+ * at its first zero fanout.
+ *
+ * Selection at v with biases b over N(v), W = sum b, P = #{b > 0}:
+ * W = 0 selects nothing; fanout = CSAW_FANOUT_ALL or fanout >= P selects
+ * every positive-bias neighbor in list order; otherwise fanout distinct
+ * neighbors drawn as described at the top of this file. */
+typedef struct {
+    int32_t num_instances;        /* >= 0                                        */
+    const int64_t* seed_offsets;  /* HOST int64[num_instances+1], non-decreasing,
+                                     seed_offsets[0] = 0                          */
+    const int32_t* seeds;         /* DEVICE int32[seed_offsets[num_instances]],
+                                     ids in [0, n); duplicates are merged          */
+    uint64_t instance_base;       /* instance i has id instance_base + i          */
+    int32_t num_layers;           /* 0 .. CSAW_MAX_LAYERS                         */
+    const int32_t* fanouts;       /* HOST: int32[num_layers] shared by all
+                                     instances if fanout_stride == 0, else row i
+                                     at fanouts + i*fanout_stride; values
+                                     CSAW_FANOUT_ALL, 0 (stop) or 1..65535;
+                                     values above CSAW_MAX_FANOUT are UNSUPPORTED
+                                     when they would need a draw                  */
+    int32_t fanout_stride;        /* 0, or >= num_layers                          */
+    int32_t bias_kind;            /* csaw_bias_kind (not NODE2VEC), used when
+                                     bias_kinds is NULL                           */
+    const int32_t* bias_kinds;    /* HOST int32[num_instances] or NULL            */
+    uint64_t rng_seed;            /* Philox key                                   */
+} csaw_sample_args;
+
+typedef struct {
+    int32_t* src;             /* DEVICE int32[edge_capacity]                       */
+    int32_t* dst;             /* DEVICE int32[edge_capacity]                       */
+    int64_t edge_capacity;
+    int64_t* offsets;         /* DEVICE int64[num_layers*num_instances+1] or NULL:
+                                 offsets[l*num_instances + i] is the first edge of
+                                 (layer l, instance i); the last entry is the total */
+    int64_t num_edges;        /* written: total number of edges                    */
+} csaw_sample_out;
+
+/* Output order: by layer, then instance, then source vertex (increasing),
+ * then slot. Errors: INVALID_ARG (bad argument, or a seed outside [0, n),
+ * detected on the device: outputs are then unspecified); OUT_OF_MEMORY if
+ * edge_capacity < the total (num_edges still receives the total; edges that
+ * fit are written); UNSUPPORTED for a drawn fanout above CSAW_MAX_FANOUT. */
+csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* args, csaw_sample_out* out,
+                        csaw_stream stream);
+
+/* Upper bound of the number of edges csaw_sample can emit for these
+ * arguments (capacity planning; host-only, seeds are not read).
+ * HOST out: max_edges. */
+csaw_status csaw_sample_bound(csaw_graph g, const csaw_sample_args* args, int64_t* max_edges);
+
+/* ------------------------------------------------------------------ walks */
+
+/* Random walks (Section II-A: DeepWalk, biased DeepWalk, node2vec,
+ * multi-independent walks). Walker w (id walker_base + w) starts at
+ * starts[w]; at each step from v the biases of N(v) are evaluated; if v has no
+ * neighbor or W = 0 the walk stops, otherwise one neighbor is drawn (with
+ * replacement) and the walker moves there. */
+typedef struct {
+    int32_t bias_kind;            /* csaw_bias_kind                               */
+    uint32_t w_return;            /* NODE2VEC weights (uint32)                    */
+    uint32_t w_common;
+    uint32_t w_outward;
+    int64_t num_walkers;          /* >= 0                                         */
+    const int32_t* starts;        /* DEVICE int32[num_walkers], ids in [0, n)     */
+    uint64_t walker_base;         /* walker w has id walker_base + w              */
+    int32_t length;               /* number of steps, >= 0                        */
+    uint64_t rng_seed;            /* Philox key                                   */
+} csaw_walk_args;
+
+/* paths: DEVICE int32[num_walkers * (length+1)], walker-major; path[0] is
+ * the start, entries after a stop are -1.
+ * total_steps: HOST int64 or NULL, receives the number of steps taken by all
+ * walkers (sampled edges).
+ * Errors: INVALID_ARG (bad argument, unsorted lists for NODE2VEC, missing
+ * edge weights, or a start outside [0, n) detected on the device). */
+csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* args, int32_t* paths,
+                      int64_t* total_steps, csaw_stream stream);
+
+/* --------------------------------------------------------------- profiling */
+
+/* When enabled, the library brackets each kernel launch with HIP events on
+ * the stream the kernel runs on, so that kernel time can be read without an
+ * external profiler. Process-wide; off by default. */
+csaw_status csaw_profile_enable(int32_t on);
+csaw_status csaw_profile_reset(void);
+/* Sum of event-measured durations (ms) and launch count of the kernels whose
+ * name starts with `prefix` since the last reset. Synchronises the events.
+ * HOST outputs. */
+csaw_status csaw_profile_read(const char* prefix, double* total_ms, int64_t* launches);
+
+/* ------------------------------------------------------------------- misc */
+
+/* Message of the calling thread's last failed call ("" if none). The string
+ * stays valid until the thread's next call into the library. */
+const char* csaw_last_error(void);
+
+/* Library version string (static storage). */
+const char* csaw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSAW_H */

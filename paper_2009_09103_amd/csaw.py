@@ -1,0 +1,259 @@
+"""Thin Python binding of libcsaw (C-ABI in include/csaw.h).
+
+Argument marshalling only: every step of sampling and walking runs in the
+library's HIP kernels. torch provides device memory (tensors) and streams.
+There is no CPU fallback: if the library is missing or fails to load, import
+fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime that libcsaw then shares
+
+from . import _build
+
+UNIFORM, EDGE_WEIGHT, NEIGHBOR_DEGREE, NODE2VEC = 0, 1, 2, 3
+FANOUT_ALL = -1
+MAX_FANOUT = 64
+MAX_LAYERS = 16
+ROUNDS = 8
+
+_BIAS_NAMES = {"uniform": UNIFORM, "edge_weight": EDGE_WEIGHT, "neighbor_degree": NEIGHBOR_DEGREE,
+               "node2vec": NODE2VEC}
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "BUSY", 5: "NOT_READY",
+          6: "UNSUPPORTED"}
+
+
+class CsawError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class SampleArgs(ctypes.Structure):
+    _fields_ = [("num_instances", ctypes.c_int32), ("seed_offsets", ctypes.c_void_p),
+                ("seeds", ctypes.c_void_p), ("instance_base", ctypes.c_uint64),
+                ("num_layers", ctypes.c_int32), ("fanouts", ctypes.c_void_p),
+                ("fanout_stride", ctypes.c_int32), ("bias_kind", ctypes.c_int32),
+                ("bias_kinds", ctypes.c_void_p), ("rng_seed", ctypes.c_uint64)]
+
+
+class SampleOut(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("edge_capacity", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("num_edges", ctypes.c_int64)]
+
+
+class WalkArgs(ctypes.Structure):
+    _fields_ = [("bias_kind", ctypes.c_int32), ("w_return", ctypes.c_uint32),
+                ("w_common", ctypes.c_uint32), ("w_outward", ctypes.c_uint32),
+                ("num_walkers", ctypes.c_int64), ("starts", ctypes.c_void_p),
+                ("walker_base", ctypes.c_uint64), ("length", ctypes.c_int32),
+                ("rng_seed", ctypes.c_uint64)]
+
+
+EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample",
+           "csaw_sample_bound", "csaw_walk", "csaw_profile_enable", "csaw_profile_reset",
+           "csaw_profile_read", "csaw_last_error", "csaw_version"]
+
+
+def _load():
+    if not os.path.exists(_build.LIB):
+        _build.build_hip(force=False)
+    L = ctypes.CDLL(_build.LIB)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.csaw_graph_create.argtypes = [i64, i64, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.csaw_graph_destroy.argtypes = [vp]
+    L.csaw_graph_info.argtypes = [vp, vp, vp, vp, vp]
+    L.csaw_sample.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), vp]
+    L.csaw_sample_bound.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(ctypes.c_int64)]
+    L.csaw_walk.argtypes = [vp, ctypes.POINTER(WalkArgs), vp, ctypes.POINTER(ctypes.c_int64), vp]
+    L.csaw_profile_enable.argtypes = [i32]
+    L.csaw_profile_reset.argtypes = []
+    L.csaw_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64)]
+    for f in EXPORTS:
+        if f not in ("csaw_last_error", "csaw_version"):
+            getattr(L, f).restype = ctypes.c_int
+    L.csaw_last_error.restype = ctypes.c_char_p
+    L.csaw_version.restype = ctypes.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != 0:
+        raise CsawError(status, lib.csaw_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _bias_code(b) -> int:
+    if isinstance(b, str):
+        return _BIAS_NAMES[b]
+    return int(b)
+
+
+def _dev_i32(x, device) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=torch.int32)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).to(device)
+    return t.contiguous()
+
+
+def version() -> str:
+    return lib.csaw_version().decode()
+
+
+class SampleResult:
+    """Edges in (layer, instance, source, slot) order; ``offsets[l*ni + i]`` is
+    the first edge of (layer l, instance i)."""
+
+    def __init__(self, src, dst, offsets, num_layers, num_instances):
+        self.src, self.dst, self.offsets = src, dst, offsets
+        self.num_layers, self.num_instances = num_layers, num_instances
+
+    @property
+    def num_edges(self) -> int:
+        return int(self.src.shape[0])
+
+
+class Graph:
+    """A CSR graph resident in HBM on the current device."""
+
+    def __init__(self, rowptr, col, edge_weight=None, stream=None):
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        ew = None if edge_weight is None else np.ascontiguousarray(edge_weight, dtype=np.uint32)
+        n = len(rowptr) - 1
+        h = ctypes.c_void_p()
+        _check(lib.csaw_graph_create(n, len(col), rowptr.ctypes.data, col.ctypes.data,
+                                     None if ew is None else ew.ctypes.data, 0, _stream(stream),
+                                     ctypes.byref(h)))
+        self._h = h
+        self.n, self.m = n, len(col)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.csaw_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n, m, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        srt = ctypes.c_int32()
+        _check(lib.csaw_graph_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(md),
+                                   ctypes.byref(srt)))
+        return dict(n=n.value, m=m.value, max_degree=md.value, sorted=bool(srt.value))
+
+    # -------------------------------------------------------------- sampling
+    def _sample_args(self, seed_offsets, seeds_dev, fanouts, bias, rng_seed, instance_base):
+        so = np.ascontiguousarray(seed_offsets, dtype=np.int64)
+        fo = np.ascontiguousarray(fanouts, dtype=np.int32)
+        ni = len(so) - 1
+        if fo.ndim == 1:
+            L, stride = fo.shape[0], 0
+        else:
+            L, stride = fo.shape[1], fo.shape[1]
+        a = SampleArgs()
+        a.num_instances = ni
+        a.seed_offsets = so.ctypes.data
+        a.seeds = seeds_dev.data_ptr() if seeds_dev is not None and seeds_dev.numel() else None
+        a.instance_base = int(instance_base)
+        a.num_layers = L
+        a.fanouts = fo.ctypes.data
+        a.fanout_stride = stride
+        keep = [so, fo]
+        if isinstance(bias, (list, tuple, np.ndarray)):
+            bk = np.ascontiguousarray([_bias_code(b) for b in bias], dtype=np.int32)
+            a.bias_kinds = bk.ctypes.data
+            a.bias_kind = 0
+            keep.append(bk)
+        else:
+            a.bias_kinds = None
+            a.bias_kind = _bias_code(bias)
+        a.rng_seed = int(rng_seed)
+        return a, keep, ni, L
+
+    def sample_bound(self, seed_offsets, fanouts, bias=UNIFORM) -> int:
+        a, keep, _, _ = self._sample_args(seed_offsets, None, fanouts, bias, 0, 0)
+        mx = ctypes.c_int64()
+        _check(lib.csaw_sample_bound(self._h, ctypes.byref(a), ctypes.byref(mx)))
+        return mx.value
+
+    def sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
+               capacity=None, stream=None, out=None) -> SampleResult:
+        """Neighbor sampling (csaw_sample). ``seeds`` may be a device tensor
+        (used in place) or host data (copied). ``out`` may pass preallocated
+        (src, dst, offsets) device tensors."""
+        seeds_dev = _dev_i32(seeds, self.device)
+        a, keep, ni, L = self._sample_args(seed_offsets, seeds_dev, fanouts, bias, rng_seed,
+                                           instance_base)
+        if out is None:
+            if capacity is None:
+                mx = ctypes.c_int64()
+                _check(lib.csaw_sample_bound(self._h, ctypes.byref(a), ctypes.byref(mx)))
+                capacity = mx.value
+            src = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+            dst = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+            offsets = torch.empty(L * ni + 1, dtype=torch.int64, device=self.device)
+        else:
+            src, dst, offsets = out
+            capacity = src.numel()
+        o = SampleOut()
+        o.src, o.dst, o.edge_capacity = src.data_ptr(), dst.data_ptr(), int(capacity)
+        o.offsets = offsets.data_ptr() if offsets is not None else None
+        _check(lib.csaw_sample(self._h, ctypes.byref(a), ctypes.byref(o), _stream(stream)))
+        ne = o.num_edges
+        return SampleResult(src[:ne], dst[:ne], offsets, L, ni)
+
+    # ----------------------------------------------------------------- walks
+    def walk(self, starts, length, bias=UNIFORM, rng_seed=1, walker_base=0, node2vec=(1, 1, 1),
+             stream=None, paths=None):
+        """Random walks (csaw_walk). Returns (paths [nw, length+1] int32 device
+        tensor, total steps)."""
+        st = _dev_i32(starts, self.device)
+        nw = st.numel()
+        if paths is None:
+            paths = torch.empty((nw, length + 1), dtype=torch.int32, device=self.device)
+        a = WalkArgs()
+        a.bias_kind = _bias_code(bias)
+        a.w_return, a.w_common, a.w_outward = (int(x) for x in node2vec)
+        a.num_walkers = nw
+        a.starts = st.data_ptr() if nw else None
+        a.walker_base = int(walker_base)
+        a.length = int(length)
+        a.rng_seed = int(rng_seed)
+        steps = ctypes.c_int64()
+        _check(lib.csaw_walk(self._h, ctypes.byref(a), paths.data_ptr() if nw else None,
+                             ctypes.byref(steps), _stream(stream)))
+        return paths, steps.value
+
+
+def profile_enable(on: bool = True):
+    _check(lib.csaw_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib.csaw_profile_reset())
+
+
+def profile_read(prefix: str):
+    """(total ms, launches) of kernels whose name starts with ``prefix``."""
+    t, c = ctypes.c_double(), ctypes.c_int64()
+    _check(lib.csaw_profile_read(prefix.encode(), ctypes.byref(t), ctypes.byref(c)))
+    return t.value, c.value

@@ -1,0 +1,111 @@
+// device_common.h -- wave64 building blocks for the gfx950 kernels of libcsaw.
+//
+// Counter-based draws (Philox4x32-10, Salmon et al. SC'11), the exact
+// 64-bit range reduction r = floor(u * W / 2^64), and wave-level integer
+// scans / reductions / ballots on 64-lane wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace csaw {
+
+constexpr int kWave = 64;
+constexpr uint32_t kFallbackRound = 0xFFFFu;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Philox4x32-10 with key (k0, k1) and counter (c0..c3); returns the first two
+// output words packed as u = x0 + 2^32 * x1, which is all a draw consumes.
+__device__ __forceinline__ uint64_t philox_u64(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
+                                               uint32_t c2, uint32_t c3) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return (uint64_t)c0 | ((uint64_t)c1 << 32);
+}
+
+// floor(u * W / 2^64)
+__device__ __forceinline__ uint64_t range_reduce(uint64_t u, uint64_t W) { return __umul64hi(u, W); }
+
+struct Key {
+    uint32_t k0, k1;
+};
+
+__device__ __forceinline__ uint64_t draw(Key key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint64_t W) {
+    return range_reduce(philox_u64(key.k0, key.k1, c0, c1, c2, c3), W);
+}
+
+// ---------------------------------------------------------------- wave ops
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t t = __shfl_up(x, (unsigned)o, kWave);
+        if (lane >= o) x += t;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t x, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+__device__ __forceinline__ int32_t readlane_i32(int32_t x, int lane) {
+    return __builtin_amdgcn_readlane(x, lane);
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int lane) {
+    const uint32_t lo = readlane_u32((uint32_t)x, lane);
+    const uint32_t hi = readlane_u32((uint32_t)(x >> 32), lane);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ int64_t readlane_i64(int64_t x, int lane) {
+    return (int64_t)readlane_u64((uint64_t)x, lane);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// lanes below the calling lane
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Make LDS writes of this wave visible to all of its lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// wave-uniform value (forces an SGPR)
+__device__ __forceinline__ int32_t uniform_i32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)((uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+}  // namespace csaw

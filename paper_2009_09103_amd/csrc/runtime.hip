@@ -1,0 +1,646 @@
+// runtime.hip -- host runtime and C-ABI of libcsaw (declared in include/csaw.h).
+//
+// Graph residency, argument validation, capacity planning, per-call device
+// workspaces, the per-layer launch sequence of neighbor sampling and the
+// walk launch. Every step of the selection itself runs in the kernels of
+// sample_kernels.hip / walk_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/csaw.h"
+#include "kernels.h"
+
+using namespace csaw;
+
+namespace {
+
+thread_local std::string t_err;
+
+csaw_status fail(csaw_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return st;
+}
+
+#define HIP_OR_FAIL(expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            return fail(e_ == hipErrorOutOfMemory ? CSAW_ERR_OUT_OF_MEMORY : CSAW_ERR_DEVICE,   \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));                           \
+        }                                                                                         \
+    } while (0)
+
+// ------------------------------------------------------------- profiling
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::atomic<bool> g_prof{false};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof_recs;
+
+struct ProfScope {
+    const char* name;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
+        if (g_prof.load(std::memory_order_relaxed)) {
+            if (hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+            else a = nullptr;
+        }
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return;
+        }
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_recs.push_back({name, a, b});
+    }
+};
+
+// ------------------------------------------------------------ workspace
+struct Workspace {
+    char* arena = nullptr;
+    size_t arena_cap = 0;
+    uint32_t* bitmaps = nullptr;  // visited | next, zero between calls
+    size_t bitmap_words = 0;
+    char* pinned = nullptr;
+    size_t pinned_cap = 0;
+
+    ~Workspace() {
+        if (arena) (void)hipFree(arena);
+        if (bitmaps) (void)hipFree(bitmaps);
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Carver {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t count) {
+        const size_t at = off;
+        off = align_up(off + count * sizeof(T), 256);
+        return at;
+    }
+};
+
+}  // namespace
+
+struct csaw_graph_s {
+    int64_t n = 0, m = 0, max_deg = 0;
+    int device = 0;
+    bool sorted = true;
+    int64_t* rowptr = nullptr;
+    int32_t* col = nullptr;
+    uint32_t* ew = nullptr;
+    uint32_t* degw = nullptr;
+    int32_t* ppos_ew = nullptr;
+    int32_t* ppos_deg = nullptr;
+    std::mutex mu;                       // lazy preparation + workspace pool
+    std::vector<Workspace*> pool;
+
+    GraphDev dev() const {
+        GraphDev g;
+        g.n = n;
+        g.m = m;
+        g.rowptr = rowptr;
+        g.col = col;
+        g.ew = ew;
+        g.degw = degw;
+        g.ppos_ew = ppos_ew;
+        g.ppos_deg = ppos_deg;
+        return g;
+    }
+};
+
+namespace {
+
+Workspace* acquire(csaw_graph g) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->pool.empty()) {
+        Workspace* w = g->pool.back();
+        g->pool.pop_back();
+        return w;
+    }
+    return new Workspace();
+}
+
+void release(csaw_graph g, Workspace* w) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->pool.push_back(w);
+}
+
+// A workspace borrowed for one call. If the call did not reach its end (a
+// HIP error after work was enqueued), the stream is drained and the
+// workspace dropped, since its bitmaps may no longer be all-zero.
+struct Lease {
+    csaw_graph g;
+    Workspace* w;
+    hipStream_t s;
+    bool clean = false;
+    ~Lease() {
+        if (clean) {
+            release(g, w);
+        } else {
+            (void)hipStreamSynchronize(s);
+            delete w;
+        }
+    }
+};
+
+csaw_status ensure_arena(Workspace* w, size_t bytes) {
+    if (w->arena_cap >= bytes) return CSAW_OK;
+    if (w->arena) HIP_OR_FAIL(hipFree(w->arena));
+    w->arena = nullptr;
+    w->arena_cap = 0;
+    const size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 20);
+    HIP_OR_FAIL(hipMalloc((void**)&w->arena, cap));
+    w->arena_cap = cap;
+    return CSAW_OK;
+}
+
+csaw_status ensure_pinned(Workspace* w, size_t bytes) {
+    if (w->pinned_cap >= bytes) return CSAW_OK;
+    if (w->pinned) HIP_OR_FAIL(hipHostFree(w->pinned));
+    w->pinned = nullptr;
+    w->pinned_cap = 0;
+    const size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 16);
+    HIP_OR_FAIL(hipHostMalloc((void**)&w->pinned, cap, hipHostMallocDefault));
+    w->pinned_cap = cap;
+    return CSAW_OK;
+}
+
+csaw_status ensure_bitmaps(Workspace* w, size_t words, hipStream_t s) {
+    if (w->bitmap_words >= words) return CSAW_OK;
+    if (w->bitmaps) HIP_OR_FAIL(hipFree(w->bitmaps));
+    w->bitmaps = nullptr;
+    w->bitmap_words = 0;
+    HIP_OR_FAIL(hipMalloc((void**)&w->bitmaps, words * sizeof(uint32_t)));
+    launch_fill_u32(w->bitmaps, 0u, (int64_t)words, s);
+    HIP_OR_FAIL(hipGetLastError());
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    w->bitmap_words = words;
+    return CSAW_OK;
+}
+
+csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (kind == kEdgeWeight && !g->ppos_ew) {
+        if (!g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias needs edge weights");
+        HIP_OR_FAIL(hipMalloc((void**)&g->ppos_ew, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
+        launch_positive_counts(g->rowptr, g->ew, g->n, g->ppos_ew, s);
+        HIP_OR_FAIL(hipGetLastError());
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    }
+    if (kind == kNeighborDegree && !g->ppos_deg) {
+        HIP_OR_FAIL(hipMalloc((void**)&g->degw, std::max<int64_t>(g->m, 1) * sizeof(uint32_t)));
+        HIP_OR_FAIL(hipMalloc((void**)&g->ppos_deg, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
+        launch_degree_weights(g->rowptr, g->col, g->m, g->degw, s);
+        launch_positive_counts(g->rowptr, g->degw, g->n, g->ppos_deg, s);
+        HIP_OR_FAIL(hipGetLastError());
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    }
+    return CSAW_OK;
+}
+
+int64_t sat_mul(int64_t a, int64_t b) {
+    if (a == 0 || b == 0) return 0;
+    if (a > INT64_MAX / b) return INT64_MAX;
+    return a * b;
+}
+int64_t sat_add(int64_t a, int64_t b) { return (a > INT64_MAX - b) ? INT64_MAX : a + b; }
+
+struct SamplePlan {
+    int32_t ni = 0, L = 0;
+    std::vector<int32_t> fan;       // [(L+1) * ni], effective, zero row appended
+    std::vector<int32_t> bias;      // [ni]
+    std::vector<int64_t> fcap;      // [L+1] frontier capacity per layer
+    int64_t max_edges = 0;
+    int64_t total_seeds = 0;
+    bool uses_deg = false, uses_ew = false;
+};
+
+csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P) {
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (!a) return fail(CSAW_ERR_INVALID_ARG, "args is NULL");
+    if (a->num_instances < 0) return fail(CSAW_ERR_INVALID_ARG, "num_instances < 0");
+    if (a->num_layers < 0 || a->num_layers > CSAW_MAX_LAYERS)
+        return fail(CSAW_ERR_INVALID_ARG, "num_layers must be in [0, %d]", CSAW_MAX_LAYERS);
+    const int32_t ni = a->num_instances, L = a->num_layers;
+    P.ni = ni;
+    P.L = L;
+    if (ni > 0 && !a->seed_offsets) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets is NULL");
+    if (L > 0 && ni > 0 && !a->fanouts) return fail(CSAW_ERR_INVALID_ARG, "fanouts is NULL");
+    if (a->fanout_stride != 0 && a->fanout_stride < L)
+        return fail(CSAW_ERR_INVALID_ARG, "fanout_stride must be 0 or >= num_layers");
+    if (ni > 0) {
+        if (a->seed_offsets[0] != 0) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets[0] != 0");
+        for (int32_t i = 0; i < ni; ++i)
+            if (a->seed_offsets[i + 1] < a->seed_offsets[i])
+                return fail(CSAW_ERR_INVALID_ARG, "seed_offsets decreases at %d", i);
+        P.total_seeds = a->seed_offsets[ni];
+        if (P.total_seeds > 0 && !a->seeds) return fail(CSAW_ERR_INVALID_ARG, "seeds is NULL");
+    }
+    P.bias.resize(ni);
+    for (int32_t i = 0; i < ni; ++i) {
+        const int32_t k = a->bias_kinds ? a->bias_kinds[i] : a->bias_kind;
+        if (k != kUniform && k != kEdgeWeight && k != kNeighborDegree)
+            return fail(CSAW_ERR_INVALID_ARG, "bias kind %d is not a sampling bias (instance %d)", k, i);
+        if (k == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
+        P.bias[i] = k;
+        P.uses_deg |= (k == kNeighborDegree);
+        P.uses_ew |= (k == kEdgeWeight);
+    }
+    P.fan.assign((size_t)(L + 1) * ni, 0);
+    P.fcap.assign(L + 1, 0);
+    std::vector<int64_t> B(ni);
+    for (int32_t i = 0; i < ni; ++i) B[i] = std::min<int64_t>(a->seed_offsets[i + 1] - a->seed_offsets[i], g->n);
+    for (int32_t i = 0; i < ni; ++i) P.fcap[0] = sat_add(P.fcap[0], B[i]);
+    for (int32_t i = 0; i < ni; ++i) {
+        const int32_t* row = a->fanouts + (a->fanout_stride ? (int64_t)i * a->fanout_stride : 0);
+        bool stopped = false;
+        for (int32_t l = 0; l < L; ++l) {
+            const int32_t f = row[l];
+            if (f < -1 || f > 0xFFFF) return fail(CSAW_ERR_INVALID_ARG, "fanout %d out of range", f);
+            if (f == 0) stopped = true;
+            P.fan[(size_t)l * ni + i] = stopped ? 0 : f;
+        }
+    }
+    for (int32_t l = 0; l < L; ++l) {
+        int64_t next_cap = 0;
+        for (int32_t i = 0; i < ni; ++i) {
+            const int32_t f = P.fan[(size_t)l * ni + i];
+            if (f == 0) {
+                B[i] = 0;
+                continue;
+            }
+            const int64_t per = f < 0 ? g->max_deg : std::min<int64_t>(f, g->max_deg);
+            const int64_t e = std::min<int64_t>(sat_mul(B[i], per), g->m);
+            P.max_edges = sat_add(P.max_edges, e);
+            B[i] = P.fan[(size_t)(l + 1) * ni + i] != 0 ? std::min<int64_t>(e, g->n) : 0;
+            next_cap = sat_add(next_cap, B[i]);
+        }
+        P.fcap[l + 1] = next_cap;
+    }
+    return CSAW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* csaw_last_error(void) { return t_err.c_str(); }
+
+const char* csaw_version(void) { return "libcsaw 0.1 (gfx950)"; }
+
+csaw_status csaw_graph_create(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                              const uint32_t* edge_weight, uint32_t flags, csaw_stream stream, csaw_graph* out) {
+    t_err.clear();
+    if (!out) return fail(CSAW_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (flags != 0) return fail(CSAW_ERR_INVALID_ARG, "flags must be 0");
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(CSAW_ERR_INVALID_ARG, "num_vertices out of range");
+    if (m < 0 || m >= (int64_t(1) << 40)) return fail(CSAW_ERR_INVALID_ARG, "num_edges out of range");
+    if (!rowptr) return fail(CSAW_ERR_INVALID_ARG, "rowptr is NULL");
+    if (m > 0 && !col) return fail(CSAW_ERR_INVALID_ARG, "col is NULL");
+    if (rowptr[0] != 0 || rowptr[n] != m) return fail(CSAW_ERR_INVALID_ARG, "rowptr must start at 0 and end at m");
+    int64_t max_deg = 0;
+    bool sorted = true;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t d = rowptr[v + 1] - rowptr[v];
+        if (d < 0) return fail(CSAW_ERR_INVALID_ARG, "rowptr decreases at vertex %lld", (long long)v);
+        max_deg = std::max(max_deg, d);
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+            const int32_t x = col[e];
+            if (x < 0 || (int64_t)x >= n) return fail(CSAW_ERR_INVALID_ARG, "col[%lld] = %d out of range", (long long)e, x);
+            if (e > rowptr[v] && col[e - 1] > x) sorted = false;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    csaw_graph g = new csaw_graph_s();
+    g->n = n;
+    g->m = m;
+    g->max_deg = max_deg;
+    g->sorted = sorted;
+    auto cleanup = [&](csaw_status st) {
+        csaw_graph_destroy(g);
+        return st;
+    };
+    if (hipGetDevice(&g->device) != hipSuccess) return cleanup(fail(CSAW_ERR_DEVICE, "hipGetDevice failed"));
+    hipError_t e;
+    if ((e = hipMalloc((void**)&g->rowptr, (n + 1) * sizeof(int64_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&g->col, std::max<int64_t>(m, 1) * sizeof(int32_t))) != hipSuccess ||
+        (edge_weight && (e = hipMalloc((void**)&g->ew, std::max<int64_t>(m, 1) * sizeof(uint32_t))) != hipSuccess))
+        return cleanup(fail(CSAW_ERR_OUT_OF_MEMORY, "graph allocation failed: %s", hipGetErrorString(e)));
+    if ((e = hipMemcpyAsync(g->rowptr, rowptr, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (m > 0 && (e = hipMemcpyAsync(g->col, col, m * sizeof(int32_t), hipMemcpyHostToDevice, s)) != hipSuccess) ||
+        (edge_weight && m > 0 &&
+         (e = hipMemcpyAsync(g->ew, edge_weight, m * sizeof(uint32_t), hipMemcpyHostToDevice, s)) != hipSuccess) ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return cleanup(fail(CSAW_ERR_DEVICE, "graph upload failed: %s", hipGetErrorString(e)));
+    if (edge_weight) {
+        csaw_status st = prepare_bias(g, kEdgeWeight, s);
+        if (st != CSAW_OK) return cleanup(st);
+    }
+    *out = g;
+    return CSAW_OK;
+}
+
+csaw_status csaw_graph_destroy(csaw_graph g) {
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    for (Workspace* w : g->pool) delete w;
+    if (g->rowptr) (void)hipFree(g->rowptr);
+    if (g->col) (void)hipFree(g->col);
+    if (g->ew) (void)hipFree(g->ew);
+    if (g->degw) (void)hipFree(g->degw);
+    if (g->ppos_ew) (void)hipFree(g->ppos_ew);
+    if (g->ppos_deg) (void)hipFree(g->ppos_deg);
+    delete g;
+    return CSAW_OK;
+}
+
+csaw_status csaw_graph_info(csaw_graph g, int64_t* n, int64_t* m, int64_t* max_degree, int32_t* sorted) {
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (max_degree) *max_degree = g->max_deg;
+    if (sorted) *sorted = g->sorted ? 1 : 0;
+    return CSAW_OK;
+}
+
+csaw_status csaw_sample_bound(csaw_graph g, const csaw_sample_args* a, int64_t* max_edges) {
+    t_err.clear();
+    if (!max_edges) return fail(CSAW_ERR_INVALID_ARG, "max_edges is NULL");
+    SamplePlan P;
+    csaw_status st = plan_sample(g, a, P);
+    if (st != CSAW_OK) return st;
+    *max_edges = P.max_edges;
+    return CSAW_OK;
+}
+
+csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out* out, csaw_stream stream) {
+    t_err.clear();
+    if (!out) return fail(CSAW_ERR_INVALID_ARG, "out is NULL");
+    SamplePlan P;
+    csaw_status st = plan_sample(g, a, P);
+    if (st != CSAW_OK) return st;
+    if (out->edge_capacity < 0) return fail(CSAW_ERR_INVALID_ARG, "edge_capacity < 0");
+    if (out->edge_capacity > 0 && (!out->src || !out->dst)) return fail(CSAW_ERR_INVALID_ARG, "src/dst is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OR_FAIL(hipSetDevice(g->device));
+    if (P.uses_deg && (st = prepare_bias(g, kNeighborDegree, s)) != CSAW_OK) return st;
+    if (P.uses_ew && (st = prepare_bias(g, kEdgeWeight, s)) != CSAW_OK) return st;
+
+    const int32_t ni = P.ni, L = P.L;
+    out->num_edges = 0;
+    if (ni == 0) {
+        if (out->offsets) HIP_OR_FAIL(hipMemsetAsync(out->offsets, 0, sizeof(int64_t), s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        return CSAW_OK;
+    }
+    const int64_t nwp = (int64_t)align_up((size_t)((g->n + 31) / 32), 4);
+    const int64_t words = nwp * ni;
+    int64_t maxF = 0, sumF = 0;
+    for (int l = 0; l <= L; ++l) {
+        maxF = std::max(maxF, P.fcap[l]);
+        sumF = sat_add(sumF, P.fcap[l]);
+    }
+    if (sumF > (int64_t(1) << 40)) return fail(CSAW_ERR_OUT_OF_MEMORY, "frontier bound too large");
+    const int64_t nb_scan = std::max<int64_t>((maxF + kScanItems - 1) / kScanItems, (words / 4 + 255) / 256) + 1;
+
+    // device workspace layout
+    Carver cv;
+    const size_t o_ctl = cv.take<SampleCtl>(1);
+    const size_t o_fan = cv.take<int32_t>((size_t)(L + 1) * ni);
+    const size_t o_bias = cv.take<int32_t>(ni);
+    const size_t o_soff = cv.take<int64_t>((size_t)ni + 1);
+    const size_t o_fstart = cv.take<int64_t>(ni);
+    const size_t o_bs = cv.take<int64_t>((size_t)nb_scan);
+    const size_t o_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
+    const size_t o_off = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
+    std::vector<size_t> o_fv(L + 1), o_fi(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        o_fv[l] = cv.take<int32_t>((size_t)std::max<int64_t>(P.fcap[l], 1));
+        o_fi[l] = cv.take<int32_t>((size_t)std::max<int64_t>(P.fcap[l], 1));
+    }
+    Workspace* ws = acquire(g);
+    Lease rel{g, ws, s};
+    if ((st = ensure_arena(ws, cv.off)) != CSAW_OK) return st;
+    if ((st = ensure_bitmaps(ws, (size_t)words * 2, s)) != CSAW_OK) return st;
+    const size_t host_bytes = sizeof(SampleCtl) + ((size_t)(L + 1) * ni + ni) * sizeof(int32_t) +
+                              ((size_t)ni + 1) * sizeof(int64_t) + 64;
+    if ((st = ensure_pinned(ws, host_bytes)) != CSAW_OK) return st;
+
+    char* A = ws->arena;
+    SampleCtl* ctl = (SampleCtl*)(A + o_ctl);
+    int32_t* d_fan = (int32_t*)(A + o_fan);
+    int32_t* d_bias = (int32_t*)(A + o_bias);
+    int64_t* d_soff = (int64_t*)(A + o_soff);
+    int64_t* d_fstart = (int64_t*)(A + o_fstart);
+    int64_t* d_bs = (int64_t*)(A + o_bs);
+    int32_t* d_cnt = (int32_t*)(A + o_cnt);
+    int64_t* d_off = (int64_t*)(A + o_off);
+    uint32_t* visited = ws->bitmaps;
+    uint32_t* next = ws->bitmaps + words;
+
+    // stage the small tables through pinned memory
+    char* H = ws->pinned;
+    int32_t* h_fan = (int32_t*)H;
+    std::memcpy(h_fan, P.fan.data(), P.fan.size() * sizeof(int32_t));
+    int32_t* h_bias = h_fan + P.fan.size();
+    std::memcpy(h_bias, P.bias.data(), ni * sizeof(int32_t));
+    int64_t* h_soff = (int64_t*)align_up((size_t)(h_bias + ni), 8);
+    std::memcpy(h_soff, a->seed_offsets, ((size_t)ni + 1) * sizeof(int64_t));
+    SampleCtl* h_ctl = (SampleCtl*)align_up((size_t)(h_soff + ni + 1), 8);
+    HIP_OR_FAIL(hipMemsetAsync(ctl, 0, sizeof(SampleCtl), s));
+    HIP_OR_FAIL(hipMemcpyAsync(d_fan, h_fan, P.fan.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipMemcpyAsync(d_bias, h_bias, ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipMemcpyAsync(d_soff, h_soff, ((size_t)ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+
+    {
+        ProfScope ps("frontier_init", s);
+        launch_mark_seeds(a->seeds, P.total_seeds, d_soff, ni, g->n, next, nwp, ctl, s);
+        launch_bitmap_compact(next, visited, words, nwp, d_bs, &ctl->fcount[0], (int32_t*)(A + o_fv[0]),
+                              (int32_t*)(A + o_fi[0]), d_fstart, ni, s);
+    }
+    SampleLayer p;
+    p.g = g->dev();
+    p.num_instances = ni;
+    p.k0 = (uint32_t)a->rng_seed;
+    p.k1 = (uint32_t)(a->rng_seed >> 32);
+    p.instance_base = a->instance_base;
+    p.bias = d_bias;
+    p.cnt = d_cnt;
+    p.off = d_off;
+    p.ctl = ctl;
+    p.src = out->src;
+    p.dst = out->dst;
+    p.capacity = out->edge_capacity;
+    p.visited = visited;
+    p.next = next;
+    p.nwp = nwp;
+    int computed_layers = 1;  // frontiers F_0 .. F_{computed_layers-1} exist
+    for (int32_t l = 0; l < L; ++l) {
+        p.layer = l;
+        p.fanout = d_fan + (size_t)l * ni;
+        p.fanout_next = d_fan + (size_t)(l + 1) * ni;
+        p.fv = (const int32_t*)(A + o_fv[l]);
+        p.fi = (const int32_t*)(A + o_fi[l]);
+        const int64_t cap = P.fcap[l];
+        {
+            ProfScope ps("count", s);
+            launch_count(p, d_cnt, cap, s);
+        }
+        {
+            ProfScope ps("scan", s);
+            launch_scan_counts(d_cnt, &ctl->fcount[l], cap, d_bs, d_off, &ctl->total[l], s);
+        }
+        {
+            ProfScope ps("select", s);
+            const int grid = (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 4096);
+            launch_select(p, grid, s);
+        }
+        {
+            ProfScope ps("segments", s);
+            launch_segments(p, d_fstart, out->offsets, s);
+        }
+        if (l + 1 < L && P.fcap[l + 1] > 0) {
+            ProfScope ps("frontier_compact", s);
+            launch_bitmap_compact(next, visited, words, nwp, d_bs, &ctl->fcount[l + 1],
+                                  (int32_t*)(A + o_fv[l + 1]), (int32_t*)(A + o_fi[l + 1]), d_fstart, ni, s);
+            computed_layers = l + 2;
+        }
+    }
+    {
+        ProfScope ps("visited_clear", s);
+        for (int l = 0; l < computed_layers; ++l)
+            launch_clear_visited((const int32_t*)(A + o_fv[l]), (const int32_t*)(A + o_fi[l]), &ctl->fcount[l],
+                                 P.fcap[l], visited, nwp, s);
+    }
+    if (out->offsets)
+        HIP_OR_FAIL(hipMemcpyAsync(out->offsets + (size_t)L * ni, &ctl->out_base[L], sizeof(int64_t),
+                                   hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(hipGetLastError());
+    HIP_OR_FAIL(hipMemcpyAsync(h_ctl, ctl, sizeof(SampleCtl), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    rel.clean = true;
+    out->num_edges = L > 0 ? h_ctl->out_base[L] : 0;
+    if (h_ctl->bad_seed) return fail(CSAW_ERR_INVALID_ARG, "a seed is outside [0, n)");
+    if (h_ctl->unsupported)
+        return fail(CSAW_ERR_UNSUPPORTED, "a drawn fanout exceeds %d", CSAW_MAX_FANOUT);
+    if (h_ctl->overflow || out->num_edges > out->edge_capacity)
+        return fail(CSAW_ERR_OUT_OF_MEMORY, "edge_capacity %lld < %lld edges", (long long)out->edge_capacity,
+                    (long long)out->num_edges);
+    return CSAW_OK;
+}
+
+csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int64_t* total_steps,
+                      csaw_stream stream) {
+    t_err.clear();
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (!a) return fail(CSAW_ERR_INVALID_ARG, "args is NULL");
+    if (a->bias_kind < kUniform || a->bias_kind > kNode2vec) return fail(CSAW_ERR_INVALID_ARG, "bad bias kind");
+    if (a->bias_kind == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
+    if (a->bias_kind == kNode2vec && !g->sorted) return fail(CSAW_ERR_INVALID_ARG, "NODE2VEC needs sorted adjacency lists");
+    if (a->num_walkers < 0 || a->length < 0) return fail(CSAW_ERR_INVALID_ARG, "negative num_walkers or length");
+    if (a->num_walkers > 0 && (!a->starts || !paths)) return fail(CSAW_ERR_INVALID_ARG, "starts/paths is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OR_FAIL(hipSetDevice(g->device));
+    csaw_status st;
+    if (a->bias_kind == kNeighborDegree && (st = prepare_bias(g, kNeighborDegree, s)) != CSAW_OK) return st;
+    if (total_steps) *total_steps = 0;
+    if (a->num_walkers == 0) return CSAW_OK;
+    Workspace* ws = acquire(g);
+    Lease rel{g, ws, s};
+    if ((st = ensure_arena(ws, 512)) != CSAW_OK) return st;
+    if ((st = ensure_pinned(ws, 64)) != CSAW_OK) return st;
+    unsigned long long* d_steps = (unsigned long long*)ws->arena;
+    int32_t* d_bad = (int32_t*)(ws->arena + 256);
+    HIP_OR_FAIL(hipMemsetAsync(ws->arena, 0, 512, s));
+    WalkParams p;
+    p.g = g->dev();
+    p.bias = a->bias_kind;
+    p.w_return = a->w_return;
+    p.w_common = a->w_common;
+    p.w_outward = a->w_outward;
+    p.num_walkers = a->num_walkers;
+    p.starts = a->starts;
+    p.walker_base = a->walker_base;
+    p.length = a->length;
+    p.k0 = (uint32_t)a->rng_seed;
+    p.k1 = (uint32_t)(a->rng_seed >> 32);
+    p.paths = paths;
+    p.steps = d_steps;
+    p.bad_start = d_bad;
+    {
+        ProfScope ps(a->bias_kind == kNode2vec ? "walk_node2vec" : "walk", s);
+        launch_walk(p, 65536, s);
+    }
+    HIP_OR_FAIL(hipGetLastError());
+    HIP_OR_FAIL(hipMemcpyAsync(ws->pinned, ws->arena, 512, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    rel.clean = true;
+    const unsigned long long steps = *(unsigned long long*)ws->pinned;
+    const int32_t bad = *(int32_t*)(ws->pinned + 256);
+    if (total_steps) *total_steps = (int64_t)steps;
+    if (bad) return fail(CSAW_ERR_INVALID_ARG, "a start vertex is outside [0, n)");
+    return CSAW_OK;
+}
+
+csaw_status csaw_profile_enable(int32_t on) {
+    g_prof.store(on != 0);
+    return CSAW_OK;
+}
+
+csaw_status csaw_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& r : g_prof_recs) {
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof_recs.clear();
+    return CSAW_OK;
+}
+
+csaw_status csaw_profile_read(const char* prefix, double* total_ms, int64_t* launches) {
+    if (!prefix || !total_ms || !launches) return fail(CSAW_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double t = 0;
+    int64_t c = 0;
+    const size_t pl = std::strlen(prefix);
+    for (auto& r : g_prof_recs) {
+        if (r.name.compare(0, pl, prefix) != 0) continue;
+        HIP_OR_FAIL(hipEventSynchronize(r.b));
+        float ms = 0;
+        HIP_OR_FAIL(hipEventElapsedTime(&ms, r.a, r.b));
+        t += ms;
+        ++c;
+    }
+    *total_ms = t;
+    *launches = c;
+    return CSAW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+"""GPU parity of neighbor sampling: the HIP path through the C-ABI against the
+CPU oracle, element by element (bit-exact: all integer work)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_09103_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def csaw():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2009_09103_amd import csaw as c
+    return c
+
+
+def assert_same(res, ref):
+    offs = res.offsets.cpu().numpy()
+    np.testing.assert_array_equal(offs, ref.offsets)
+    np.testing.assert_array_equal(res.src.cpu().numpy(), ref.src)
+    np.testing.assert_array_equal(res.dst.cpu().numpy(), ref.dst)
+
+
+def run_both(csaw, g, rp, col, ew, offs, seeds, fanouts, bias, rng_seed, instance_base=0):
+    say("sample n=%d m=%d ni=%d seeds=%d fanouts=%s bias=%s seed=%d" % (
+        len(rp) - 1, len(col), len(offs) - 1, len(seeds), np.asarray(fanouts).tolist()[:4], bias, rng_seed))
+    res = g.sample(offs, seeds, fanouts, bias, rng_seed=rng_seed, instance_base=instance_base)
+    if isinstance(bias, (list, np.ndarray)):
+        ref = oracle.sample(rp, col, ew, offs, seeds, fanouts, bias_kinds=np.asarray(bias, dtype=np.int32),
+                            rng_seed=rng_seed, instance_base=instance_base)
+    else:
+        ref = oracle.sample(rp, col, ew, offs, seeds, fanouts, bias_kind=bias, rng_seed=rng_seed,
+                            instance_base=instance_base)
+    assert_same(res, ref)
+    return res, ref
+
+
+def test_tiny_uniform(csaw):
+    """R-MAT 12, 256 seeds, fanouts [10, 5], unbiased, Philox seed 1."""
+    rp, col = inputs.graph_for(inputs.TINY)
+    offs, seeds = inputs.single_instance_seeds(rp, col, 256, inputs.TINY["seed_rng"])
+    g = csaw.Graph(rp, col)
+    res, ref = run_both(csaw, g, rp, col, None, offs, seeds, [10, 5], csaw.UNIFORM, 1)
+    assert res.num_edges > 1000
+
+
+@pytest.mark.parametrize("rng_seed", [1, 2])
+def test_degree_biased_rmat16(csaw, rng_seed):
+    """Degree bias on R-MAT 16: hubs above the LDS window (coarse search),
+    skewed weights (direct draws)."""
+    rp, col = inputs.rmat_csr(16, 16 << 16, 16)
+    assert np.diff(rp).max() > 1024
+    offs, seeds = inputs.single_instance_seeds(rp, col, 2048, 33)
+    g = csaw.Graph(rp, col)
+    res, ref = run_both(csaw, g, rp, col, None, offs, seeds, [25, 10, 5], csaw.NEIGHBOR_DEGREE, rng_seed)
+    assert ref.fallbacks > 0
+
+
+def test_edge_weight_with_zero_weights(csaw):
+    rp, col = inputs.rmat_csr(14, 16 << 14, 14)
+    g0 = inputs.rng(1)
+    ew = g0.integers(0, 50, size=len(col)).astype(np.uint32)
+    ew[g0.random(len(col)) < 0.3] = 0
+    offs, seeds = inputs.single_instance_seeds(rp, col, 1500, 5)
+    g = csaw.Graph(rp, col, ew)
+    run_both(csaw, g, rp, col, ew, offs, seeds, [10, 5, 3], csaw.EDGE_WEIGHT, 7)
+    run_both(csaw, g, rp, col, ew, offs, seeds, [-1, 3], csaw.EDGE_WEIGHT, 8)   # take all positive
+
+
+def test_batched_instances_mixed_bias(csaw):
+    """Many instances with their own fanout rows and bias kinds, non-zero
+    instance base; each instance's segment equals sampling it alone."""
+    rp, col = inputs.rmat_csr(14, 16 << 14, 15)
+    offs, seeds, fanouts, bias = inputs.batched_instances(rp, col, 96, 3, lo=1, hi=300, median=40)
+    g = csaw.Graph(rp, col)
+    res, ref = run_both(csaw, g, rp, col, None, offs, seeds, fanouts, bias, 11, instance_base=5000)
+    ni = len(offs) - 1
+    o = res.offsets.cpu().numpy()
+    for i in (0, 1, 50):
+        alone = g.sample(offs[i:i + 2] - offs[i], seeds[offs[i]:offs[i + 1]], fanouts[i], int(bias[i]),
+                         rng_seed=11, instance_base=5000 + i)
+        ao = alone.offsets.cpu().numpy()
+        for l in range(fanouts.shape[1]):
+            a, b = o[l * ni + i], o[l * ni + i + 1]
+            np.testing.assert_array_equal(res.dst[a:b].cpu().numpy(), alone.dst[ao[l]:ao[l + 1]].cpu().numpy())
+
+
+def test_take_all_uniform_is_bfs(csaw):
+    rp, col = inputs.graph_for(inputs.TINY)
+    offs, seeds = inputs.single_instance_seeds(rp, col, 8, 2)
+    g = csaw.Graph(rp, col)
+    run_both(csaw, g, rp, col, None, offs, seeds, [-1, -1, -1], csaw.UNIFORM, 1)
+
+
+def test_giant_hub(csaw):
+    """One vertex with 200,000 weighted neighbors (coarse chunks of several
+    64-wide pieces) and the largest drawn fanout, many instances."""
+    d = 200_000
+    rp = np.array([0, d] + [d] * d, dtype=np.int64)
+    col = np.arange(1, d + 1, dtype=np.int32)
+    g0 = inputs.rng(9)
+    ew = g0.integers(0, 1000, size=d).astype(np.uint32)
+    ew[:5] = 1 << 28                                     # a few dominant biases
+    ni = 40
+    offs = np.arange(ni + 1, dtype=np.int64)
+    seeds = np.zeros(ni, dtype=np.int32)
+    g = csaw.Graph(rp, col, ew)
+    run_both(csaw, g, rp, col, ew, offs, seeds, [64], csaw.EDGE_WEIGHT, 3)
+    run_both(csaw, g, rp, col, None, offs, seeds, [64], csaw.UNIFORM, 4)
+
+
+def test_small_lists_and_collisions(csaw):
+    """Lists barely longer than the fanout force long collision chains."""
+    rng = inputs.rng(4)
+    n = 3000
+    edges = set()
+    for u in range(n):
+        for x in rng.choice(n, size=int(rng.integers(0, 40)), replace=False):
+            if x != u:
+                edges.add((u, int(x)))
+    rp, col = inputs.csr_from_edges(n, edges)
+    ew = (rng.integers(1, 5, size=len(col)) ** 6).astype(np.uint32)
+    offs, seeds = inputs.single_instance_seeds(rp, col, 600, 8)
+    g = csaw.Graph(rp, col, ew)
+    for k in (1, 7, 30, 64):
+        run_both(csaw, g, rp, col, ew, offs, seeds, [k, k], csaw.EDGE_WEIGHT, 100 + k)
+        run_both(csaw, g, rp, col, ew, offs, seeds, [k], csaw.UNIFORM, 200 + k)
+
+
+def test_edge_cases(csaw):
+    rp = np.array([0, 2, 2, 2, 2], dtype=np.int64)
+    col = np.array([1, 2], dtype=np.int32)
+    ew = np.array([4, 0], dtype=np.uint32)
+    g = csaw.Graph(rp, col, ew)
+    say("edge cases")
+    # no instances, no layers
+    r = g.sample(np.array([0]), np.array([], dtype=np.int32), [3])
+    assert r.num_edges == 0
+    r = g.sample(np.array([0, 1]), np.array([0], dtype=np.int32), np.zeros(0, dtype=np.int32))
+    assert r.num_edges == 0
+    # empty instance, duplicate seeds, sink seed, zero-weight neighbor
+    offs = np.array([0, 0, 3, 4])
+    seeds = np.array([0, 0, 1, 3], dtype=np.int32)
+    res = g.sample(offs, seeds, [5, 5], csaw.EDGE_WEIGHT)
+    ref = oracle.sample(rp, col, ew, offs, seeds, [5, 5], bias_kind=oracle.EDGE_WEIGHT)
+    assert_same(res, ref)
+    # zero fanout stops the instance
+    res = g.sample(np.array([0, 1]), np.array([0], dtype=np.int32), [1, 0, 1])
+    ref = oracle.sample(rp, col, None, np.array([0, 1]), np.array([0], dtype=np.int32), [1, 0, 1])
+    assert_same(res, ref)
+    # capacity too small: OUT_OF_MEMORY, total still reported
+    with pytest.raises(csaw.CsawError) as ei:
+        g.sample(np.array([0, 1]), np.array([0], dtype=np.int32), [-1], capacity=1)
+    assert ei.value.status == 2
+    # seed outside [0, n)
+    with pytest.raises(csaw.CsawError) as ei:
+        g.sample(np.array([0, 1]), np.array([7], dtype=np.int32), [1])
+    assert ei.value.status == 1
+    # drawn fanout above the limit
+    big = csaw.Graph(np.array([0, 100] + [100] * 100, dtype=np.int64), np.arange(1, 101, dtype=np.int32))
+    with pytest.raises(csaw.CsawError) as ei:
+        big.sample(np.array([0, 1]), np.array([0], dtype=np.int32), [65])
+    assert ei.value.status == 6
+    # the workspace is clean afterwards: a normal call still matches
+    res = g.sample(offs, seeds, [5, 5], csaw.EDGE_WEIGHT)
+    ref = oracle.sample(rp, col, ew, offs, seeds, [5, 5], bias_kind=oracle.EDGE_WEIGHT)
+    assert_same(res, ref)
+
+
+def test_repeat_calls_identical(csaw):
+    """Same arguments, same bits: the reused workspace leaves no state behind."""
+    rp, col = inputs.rmat_csr(14, 16 << 14, 14)
+    offs, seeds = inputs.single_instance_seeds(rp, col, 1000, 5)
+    g = csaw.Graph(rp, col)
+    say("repeat calls")
+    a = g.sample(offs, seeds, [25, 10, 5], csaw.NEIGHBOR_DEGREE, rng_seed=3)
+    b = g.sample(offs, seeds, [25, 10, 5], csaw.NEIGHBOR_DEGREE, rng_seed=3)
+    assert np.array_equal(a.dst.cpu().numpy(), b.dst.cpu().numpy())
+    assert np.array_equal(a.offsets.cpu().numpy(), b.offsets.cpu().numpy())
+
+
+def test_degree_biased_rmat22_full(csaw):
+    """The degree-biased workload at full size (R-MAT 22, 8,192 seeds,
+    fanouts [25, 10, 5]) in the benchmark's launch configuration, whole
+    output compared with the oracle."""
+    rec = inputs.DEGREE_BIASED
+    say("full degree-biased R-MAT 22: generating graph")
+    rp, col = inputs.graph_for(rec)
+    offs, seeds = inputs.single_instance_seeds(rp, col, rec["num_seeds"], rec["seed_rng"])
+    g = csaw.Graph(rp, col)
+    for s in rec["rng_seeds"][:1]:
+        run_both(csaw, g, rp, col, None, offs, seeds, rec["fanouts"], csaw.NEIGHBOR_DEGREE, s)

@@ -1,0 +1,95 @@
+"""GPU parity of random walks against the CPU oracle (bit-exact paths)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_09103_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def csaw():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2009_09103_amd import csaw as c
+    return c
+
+
+def run_both(csaw, g, rp, col, ew, starts, length, bias, rng_seed, walker_base=0, node2vec=(1, 1, 1)):
+    say("walk n=%d nw=%d len=%d bias=%d n2v=%s" % (len(rp) - 1, len(starts), length, bias, node2vec))
+    paths, steps = g.walk(starts, length, bias, rng_seed=rng_seed, walker_base=walker_base, node2vec=node2vec)
+    rp_, rs, _ = oracle.walk(rp, col, ew, starts, length, bias_kind=bias, rng_seed=rng_seed,
+                             walker_base=walker_base, node2vec=node2vec)
+    np.testing.assert_array_equal(paths.cpu().numpy(), rp_)
+    assert steps == int(rs.sum())
+    return paths, steps
+
+
+@pytest.mark.parametrize("bias", [0, 1, 2])
+def test_first_order_walks(csaw, bias):
+    rp, col = inputs.rmat_csr(14, 16 << 14, 21)
+    g0 = inputs.rng(2)
+    ew = g0.integers(0, 20, size=len(col)).astype(np.uint32)
+    ew[g0.random(len(col)) < 0.2] = 0                     # W = 0 stops happen
+    starts = inputs.walker_starts(rp, col, 5000, 3)
+    g = csaw.Graph(rp, col, ew)
+    run_both(csaw, g, rp, col, ew, starts, 40, bias, 5, walker_base=123)
+
+
+@pytest.mark.parametrize("weights", [(1, 2, 4), (4, 1, 2), (0, 1, 3), (3, 3, 3)])
+def test_node2vec(csaw, weights):
+    rp, col = inputs.rmat_csr(14, 8 << 14, 22, symmetrize=True)
+    starts = inputs.walker_starts(rp, col, 4000, 4)
+    g = csaw.Graph(rp, col)
+    run_both(csaw, g, rp, col, None, starts, 30, 3, 9, node2vec=weights)
+
+
+def test_walk_hubs(csaw):
+    """Lists longer than the register cache and hub previous-vertices."""
+    rp, col = inputs.rmat_csr(16, 16 << 16, 23, symmetrize=True)
+    assert np.diff(rp).max() > 2000
+    starts = inputs.walker_starts(rp, col, 1500, 5)
+    g = csaw.Graph(rp, col, inputs.dst_outdeg_weights(rp, col))
+    run_both(csaw, g, rp, col, None, starts, 20, 3, 1, node2vec=(1, 2, 4))
+    run_both(csaw, g, rp, col, inputs.dst_outdeg_weights(rp, col), starts, 20, 1, 2)
+
+
+def test_walk_edge_cases(csaw):
+    rp = np.array([0, 1, 1], dtype=np.int64)
+    col = np.array([1], dtype=np.int32)
+    g = csaw.Graph(rp, col)
+    say("walk edge cases")
+    paths, steps = g.walk(np.array([0, 1], dtype=np.int32), 3)
+    assert paths.cpu().numpy().tolist() == [[0, 1, -1, -1], [1, -1, -1, -1]] and steps == 1
+    paths, steps = g.walk(np.array([0], dtype=np.int32), 0)
+    assert paths.cpu().numpy().tolist() == [[0]] and steps == 0
+    with pytest.raises(csaw.CsawError) as ei:
+        g.walk(np.array([2], dtype=np.int32), 3)
+    assert ei.value.status == 1
+    with pytest.raises(csaw.CsawError):
+        g.walk(np.array([0], dtype=np.int32), 3, csaw.EDGE_WEIGHT)   # no weights
+    paths, _ = g.walk(np.array([0], dtype=np.int32), 2)             # still usable
+    assert paths.cpu().numpy().tolist() == [[0, 1, -1]]
+
+
+def test_node2vec_rmat24_shape_subset(csaw):
+    """node2vec at the symmetrised R-MAT shape used by the benchmark, reduced
+    to scale 18, every 64th walker id checked (ids fix the draws)."""
+    rp, col = inputs.rmat_csr(18, 16 << 18, 24, symmetrize=True)
+    starts = inputs.walker_starts(rp, col, 1 << 14, 2404)
+    g = csaw.Graph(rp, col)
+    say("node2vec rmat18 16k walkers length 80")
+    paths, steps = g.walk(starts, 80, 3, rng_seed=1, node2vec=(1, 2, 4))
+    idx = np.arange(0, len(starts), 64)
+    ref, _, _ = oracle.walk(rp, col, None, starts[idx], 80, bias_kind=3, rng_seed=1, node2vec=(1, 2, 4),
+                            walker_ids=idx.astype(np.uint64))
+    np.testing.assert_array_equal(paths.cpu().numpy()[idx], ref)
+    assert steps == len(starts) * 80
