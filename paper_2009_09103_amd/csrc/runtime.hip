@@ -239,7 +239,7 @@ struct SamplePlan {
     bool uses_deg = false, uses_ew = false;
 };
 
-csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P) {
+csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P, bool need_seeds) {
     if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
     if (!a) return fail(CSAW_ERR_INVALID_ARG, "args is NULL");
     if (a->num_instances < 0) return fail(CSAW_ERR_INVALID_ARG, "num_instances < 0");
@@ -258,7 +258,7 @@ csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P) 
             if (a->seed_offsets[i + 1] < a->seed_offsets[i])
                 return fail(CSAW_ERR_INVALID_ARG, "seed_offsets decreases at %d", i);
         P.total_seeds = a->seed_offsets[ni];
-        if (P.total_seeds > 0 && !a->seeds) return fail(CSAW_ERR_INVALID_ARG, "seeds is NULL");
+        if (need_seeds && P.total_seeds > 0 && !a->seeds) return fail(CSAW_ERR_INVALID_ARG, "seeds is NULL");
     }
     P.bias.resize(ni);
     for (int32_t i = 0; i < ni; ++i) {
@@ -393,7 +393,7 @@ csaw_status csaw_sample_bound(csaw_graph g, const csaw_sample_args* a, int64_t* 
     t_err.clear();
     if (!max_edges) return fail(CSAW_ERR_INVALID_ARG, "max_edges is NULL");
     SamplePlan P;
-    csaw_status st = plan_sample(g, a, P);
+    csaw_status st = plan_sample(g, a, P, false);
     if (st != CSAW_OK) return st;
     *max_edges = P.max_edges;
     return CSAW_OK;
@@ -403,7 +403,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     t_err.clear();
     if (!out) return fail(CSAW_ERR_INVALID_ARG, "out is NULL");
     SamplePlan P;
-    csaw_status st = plan_sample(g, a, P);
+    csaw_status st = plan_sample(g, a, P, true);
     if (st != CSAW_OK) return st;
     if (out->edge_capacity < 0) return fail(CSAW_ERR_INVALID_ARG, "edge_capacity < 0");
     if (out->edge_capacity > 0 && (!out->src || !out->dst)) return fail(CSAW_ERR_INVALID_ARG, "src/dst is NULL");
