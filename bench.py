@@ -133,9 +133,9 @@ def bench_degree_biased(args):
         g.sample(offs, seeds_d, fan, bias, rng_seed=s, out=(src, dst, offsets))
         alg += sum(bytes_of[s])
     torch.cuda.synchronize()
-    sel_ms, sel_n = csaw.profile_read("select")
-    times = {k: csaw.profile_read(k) for k in ("frontier_init", "count", "scan", "select", "segments",
-                                                "frontier_compact", "visited_clear")}
+    sel_ms, sel_n = csaw.profile_read("select_wave")
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "count", "scan", "select_wave", "select_mid", "select_hub",
+                                                "segments", "frontier_compact", "visited_clear")}
     csaw.profile_enable(False)
     csaw.profile_reset()
     achieved = alg / (sel_ms / 1e3) / 1e9 if sel_ms > 0 else 0.0
@@ -160,7 +160,7 @@ def bench_degree_biased(args):
                    "rng_seeds": rng_seeds, "edges_per_step": float(np.mean(list(edges_of.values())))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "select", "launches": sel_n,
+                     "kernel": "select_wave (k_select)", "launches": sel_n,
                      "avg_launch_us": sel_ms / max(sel_n, 1) * 1e3,
                      "alg_bytes_per_launch": alg / max(sel_n, 1)},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in times.items()},

@@ -48,38 +48,48 @@ __device__ __forceinline__ uint64_t draw(Key key, uint32_t c0, uint32_t c1, uint
 }
 
 // ---------------------------------------------------------------- wave ops
+// DPP lane moves (GFX9 encodings): row_shr:n shifts within rows of 16 lanes,
+// row_bcast:15 / row_bcast:31 broadcast the last lane of a row (of a row
+// pair) into the following row(s). Lanes with no source receive 0. All
+// callers run these with every lane of the wave active.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, kCtrl, kRowMask, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), kCtrl, kRowMask, 0xf, false);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Inclusive scan over the 64 lanes (Hillis-Steele inside rows of 16, then
+// two row broadcasts).
 __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint64_t t = __shfl_up(x, (unsigned)o, kWave);
-        if (lane >= o) x += t;
-    }
-    return x;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
-}
-
-__device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    x += dpp_u64<kDppRowShr1, 0xf>(x);
+    x += dpp_u64<kDppRowShr2, 0xf>(x);
+    x += dpp_u64<kDppRowShr4, 0xf>(x);
+    x += dpp_u64<kDppRowShr8, 0xf>(x);
+    x += dpp_u64<kDppRowBcast15, 0xa>(x);
+    x += dpp_u64<kDppRowBcast31, 0xc>(x);
     return x;
 }
 
 __device__ __forceinline__ uint32_t readlane_u32(uint32_t x, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
 }
-__device__ __forceinline__ int32_t readlane_i32(int32_t x, int lane) {
-    return __builtin_amdgcn_readlane(x, lane);
-}
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int lane) {
     const uint32_t lo = readlane_u32((uint32_t)x, lane);
     const uint32_t hi = readlane_u32((uint32_t)(x >> 32), lane);
     return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Sum over the 64 lanes, returned on every lane.
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) { return readlane_u64(wave_incl_scan_u64(x), 63); }
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t x) { return (int64_t)wave_sum_u64((uint64_t)x); }
+
+__device__ __forceinline__ int32_t readlane_i32(int32_t x, int lane) {
+    return __builtin_amdgcn_readlane(x, lane);
 }
 __device__ __forceinline__ int64_t readlane_i64(int64_t x, int lane) {
     return (int64_t)readlane_u64((uint64_t)x, lane);

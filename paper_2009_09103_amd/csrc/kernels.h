@@ -29,6 +29,8 @@ struct SampleCtl {
     int64_t fcount[kMaxLayers + 1];    // frontier sizes
     int64_t total[kMaxLayers];         // edges per layer
     int64_t out_base[kMaxLayers + 1];  // first edge of each layer
+    unsigned long long nmid[kMaxLayers];  // mid-kernel entries per layer
+    unsigned long long nhub[kMaxLayers];  // hub-kernel entries per layer
     int32_t bad_seed;
     int32_t overflow;
     int32_t unsupported;
@@ -48,6 +50,8 @@ struct SampleLayer {
     const int32_t* fi;               // frontier instance indices
     const int32_t* cnt;              // per-entry edge count
     const int64_t* off;              // per-entry exclusive offset
+    int32_t* mids;                   // entries routed to the mid kernel
+    int32_t* hubs;                   // entries routed to the hub kernel
     SampleCtl* ctl;
     int32_t* src;
     int32_t* dst;
@@ -68,6 +72,8 @@ void launch_count(const SampleLayer& p, int32_t* cnt, int64_t cap_entries, hipSt
 void launch_scan_counts(const int32_t* cnt, const int64_t* fcount, int64_t cap_entries,
                         int64_t* blocksum, int64_t* off, int64_t* total_out, hipStream_t s);
 void launch_select(const SampleLayer& p, int grid, hipStream_t s);
+void launch_select_mid(const SampleLayer& p, int grid, hipStream_t s);
+void launch_select_hub(const SampleLayer& p, int grid, hipStream_t s);
 void launch_segments(const SampleLayer& p, const int64_t* fstart, int64_t* offsets, hipStream_t s);
 void launch_clear_visited(const int32_t* fv, const int32_t* fi, const int64_t* fcount,
                           int64_t cap_entries, uint32_t* visited, int64_t nwp, hipStream_t s);

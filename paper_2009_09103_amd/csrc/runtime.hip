@@ -10,6 +10,7 @@
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -83,8 +84,39 @@ struct Workspace {
     size_t bitmap_words = 0;
     char* pinned = nullptr;
     size_t pinned_cap = 0;
+    // side streams for the mid/hub selection kernels, forked from and joined
+    // back into the caller's stream with events (default priority)
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    // captured launch sequences of csaw_sample, keyed by every value they bake in
+    hipStream_t capture = nullptr;
+    std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
+
+    void drop_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+    hipGraphExec_t find_graph(const std::vector<int64_t>& key) const {
+        for (auto& kv : graphs)
+            if (kv.first == key) return kv.second;
+        return nullptr;
+    }
+    void put_graph(const std::vector<int64_t>& key, hipGraphExec_t exec) {
+        if (graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(graphs.front().second);
+            graphs.erase(graphs.begin());
+        }
+        graphs.emplace_back(key, exec);
+    }
 
     ~Workspace() {
+        drop_graphs();
+        if (capture) (void)hipStreamDestroy(capture);
+        for (int i = 0; i < 2; ++i) {
+            if (aux[i]) (void)hipStreamDestroy(aux[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
         if (arena) (void)hipFree(arena);
         if (bitmaps) (void)hipFree(bitmaps);
         if (pinned) (void)hipHostFree(pinned);
@@ -92,6 +124,15 @@ struct Workspace {
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// CSAW_GRAPH=0 in the environment turns off launch-sequence replay.
+bool graphs_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("CSAW_GRAPH");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
 
 struct Carver {
     size_t off = 0;
@@ -169,6 +210,7 @@ struct Lease {
 
 csaw_status ensure_arena(Workspace* w, size_t bytes) {
     if (w->arena_cap >= bytes) return CSAW_OK;
+    w->drop_graphs();
     if (w->arena) HIP_OR_FAIL(hipFree(w->arena));
     w->arena = nullptr;
     w->arena_cap = 0;
@@ -189,8 +231,20 @@ csaw_status ensure_pinned(Workspace* w, size_t bytes) {
     return CSAW_OK;
 }
 
+csaw_status ensure_streams(Workspace* w) {
+    if (w->fork) return CSAW_OK;
+    for (int i = 0; i < 2; ++i) {
+        HIP_OR_FAIL(hipStreamCreateWithFlags(&w->aux[i], hipStreamNonBlocking));
+        HIP_OR_FAIL(hipEventCreateWithFlags(&w->join[i], hipEventDisableTiming));
+    }
+    HIP_OR_FAIL(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+    HIP_OR_FAIL(hipStreamCreateWithFlags(&w->capture, hipStreamNonBlocking));
+    return CSAW_OK;
+}
+
 csaw_status ensure_bitmaps(Workspace* w, size_t words, hipStream_t s) {
     if (w->bitmap_words >= words) return CSAW_OK;
+    w->drop_graphs();
     if (w->bitmaps) HIP_OR_FAIL(hipFree(w->bitmaps));
     w->bitmaps = nullptr;
     w->bitmap_words = 0;
@@ -439,6 +493,8 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     const size_t o_bs = cv.take<int64_t>((size_t)nb_scan);
     const size_t o_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_off = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
+    const size_t o_mids = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
+    const size_t o_hubs = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     std::vector<size_t> o_fv(L + 1), o_fi(L + 1);
     for (int l = 0; l <= L; ++l) {
         o_fv[l] = cv.take<int32_t>((size_t)std::max<int64_t>(P.fcap[l], 1));
@@ -448,6 +504,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     Lease rel{g, ws, s};
     if ((st = ensure_arena(ws, cv.off)) != CSAW_OK) return st;
     if ((st = ensure_bitmaps(ws, (size_t)words * 2, s)) != CSAW_OK) return st;
+    if ((st = ensure_streams(ws)) != CSAW_OK) return st;
     const size_t host_bytes = sizeof(SampleCtl) + ((size_t)(L + 1) * ni + ni) * sizeof(int32_t) +
                               ((size_t)ni + 1) * sizeof(int64_t) + 64;
     if ((st = ensure_pinned(ws, host_bytes)) != CSAW_OK) return st;
@@ -473,76 +530,126 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     int64_t* h_soff = (int64_t*)align_up((size_t)(h_bias + ni), 8);
     std::memcpy(h_soff, a->seed_offsets, ((size_t)ni + 1) * sizeof(int64_t));
     SampleCtl* h_ctl = (SampleCtl*)align_up((size_t)(h_soff + ni + 1), 8);
-    HIP_OR_FAIL(hipMemsetAsync(ctl, 0, sizeof(SampleCtl), s));
-    HIP_OR_FAIL(hipMemcpyAsync(d_fan, h_fan, P.fan.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIP_OR_FAIL(hipMemcpyAsync(d_bias, h_bias, ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIP_OR_FAIL(hipMemcpyAsync(d_soff, h_soff, ((size_t)ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    // every device step of the call, enqueued on stream s
+    auto enqueue = [&](hipStream_t s) -> csaw_status {
+        launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)(sizeof(SampleCtl) / 4), s);
+        HIP_OR_FAIL(hipMemcpyAsync(d_fan, h_fan, P.fan.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(d_bias, h_bias, ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(d_soff, h_soff, ((size_t)ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
 
-    {
-        ProfScope ps("frontier_init", s);
-        launch_mark_seeds(a->seeds, P.total_seeds, d_soff, ni, g->n, next, nwp, ctl, s);
-        launch_bitmap_compact(next, visited, words, nwp, d_bs, &ctl->fcount[0], (int32_t*)(A + o_fv[0]),
-                              (int32_t*)(A + o_fi[0]), d_fstart, ni, s);
+        {
+            ProfScope ps("frontier_init", s);
+            launch_mark_seeds(a->seeds, P.total_seeds, d_soff, ni, g->n, next, nwp, ctl, s);
+            launch_bitmap_compact(next, visited, words, nwp, d_bs, &ctl->fcount[0], (int32_t*)(A + o_fv[0]),
+                                  (int32_t*)(A + o_fi[0]), d_fstart, ni, s);
+        }
+        SampleLayer p;
+        p.g = g->dev();
+        p.num_instances = ni;
+        p.k0 = (uint32_t)a->rng_seed;
+        p.k1 = (uint32_t)(a->rng_seed >> 32);
+        p.instance_base = a->instance_base;
+        p.bias = d_bias;
+        p.cnt = d_cnt;
+        p.off = d_off;
+        p.mids = (int32_t*)(A + o_mids);
+        p.hubs = (int32_t*)(A + o_hubs);
+        p.ctl = ctl;
+        p.src = out->src;
+        p.dst = out->dst;
+        p.capacity = out->edge_capacity;
+        p.visited = visited;
+        p.next = next;
+        p.nwp = nwp;
+        int computed_layers = 1;  // frontiers F_0 .. F_{computed_layers-1} exist
+        for (int32_t l = 0; l < L; ++l) {
+            p.layer = l;
+            p.fanout = d_fan + (size_t)l * ni;
+            p.fanout_next = d_fan + (size_t)(l + 1) * ni;
+            p.fv = (const int32_t*)(A + o_fv[l]);
+            p.fi = (const int32_t*)(A + o_fi[l]);
+            const int64_t cap = P.fcap[l];
+            {
+                ProfScope ps("count", s);
+                launch_count(p, d_cnt, cap, s);
+            }
+            {
+                ProfScope ps("scan", s);
+                launch_scan_counts(d_cnt, &ctl->fcount[l], cap, d_bs, d_off, &ctl->total[l], s);
+            }
+            // the three selection kernels touch disjoint outputs: run them side by side
+            HIP_OR_FAIL(hipEventRecord(ws->fork, s));
+            HIP_OR_FAIL(hipStreamWaitEvent(ws->aux[0], ws->fork, 0));
+            HIP_OR_FAIL(hipStreamWaitEvent(ws->aux[1], ws->fork, 0));
+            {
+                ProfScope ps("select_hub", ws->aux[1]);
+                launch_select_hub(p, 256, ws->aux[1]);
+            }
+            {
+                ProfScope ps("select_mid", ws->aux[0]);
+                launch_select_mid(p, 768, ws->aux[0]);
+            }
+            {
+                ProfScope ps("select_wave", s);
+                const int grid = (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 4096);
+                launch_select(p, grid, s);
+            }
+            HIP_OR_FAIL(hipEventRecord(ws->join[0], ws->aux[0]));
+            HIP_OR_FAIL(hipEventRecord(ws->join[1], ws->aux[1]));
+            HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join[0], 0));
+            HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join[1], 0));
+            {
+                ProfScope ps("segments", s);
+                launch_segments(p, d_fstart, out->offsets, s);
+            }
+            if (l + 1 < L && P.fcap[l + 1] > 0) {
+                ProfScope ps("frontier_compact", s);
+                launch_bitmap_compact(next, visited, words, nwp, d_bs, &ctl->fcount[l + 1],
+                                      (int32_t*)(A + o_fv[l + 1]), (int32_t*)(A + o_fi[l + 1]), d_fstart, ni, s);
+                computed_layers = l + 2;
+            }
+        }
+        {
+            ProfScope ps("visited_clear", s);
+            for (int l = 0; l < computed_layers; ++l)
+                launch_clear_visited((const int32_t*)(A + o_fv[l]), (const int32_t*)(A + o_fi[l]), &ctl->fcount[l],
+                                     P.fcap[l], visited, nwp, s);
+        }
+        if (out->offsets)
+            HIP_OR_FAIL(hipMemcpyAsync(out->offsets + (size_t)L * ni, &ctl->out_base[L], sizeof(int64_t),
+                                       hipMemcpyDeviceToDevice, s));
+        HIP_OR_FAIL(hipGetLastError());
+        HIP_OR_FAIL(hipMemcpyAsync(h_ctl, ctl, sizeof(SampleCtl), hipMemcpyDeviceToHost, s));
+    return CSAW_OK;
+    };
+
+    if (graphs_enabled() && !g_prof.load(std::memory_order_relaxed)) {
+        std::vector<int64_t> key = {ni, L, words, nwp, P.total_seeds, out->edge_capacity, (int64_t)a->rng_seed,
+                                    (int64_t)a->instance_base, (int64_t)(intptr_t)a->seeds,
+                                    (int64_t)(intptr_t)out->src, (int64_t)(intptr_t)out->dst,
+                                    (int64_t)(intptr_t)out->offsets, (int64_t)(intptr_t)ws->arena,
+                                    (int64_t)(intptr_t)ws->bitmaps};
+        key.insert(key.end(), P.fcap.begin(), P.fcap.end());
+        hipGraphExec_t exec = ws->find_graph(key);
+        if (!exec) {
+            HIP_OR_FAIL(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeRelaxed));
+            const csaw_status cst = enqueue(ws->capture);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(ws->capture, &graph);
+            if (cst != CSAW_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return cst;
+            }
+            if (e != hipSuccess) return fail(CSAW_ERR_DEVICE, "capture failed: %s", hipGetErrorString(e));
+            const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e2 != hipSuccess) return fail(CSAW_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e2));
+            ws->put_graph(key, exec);
+        }
+        HIP_OR_FAIL(hipGraphLaunch(exec, s));
+    } else {
+        if ((st = enqueue(s)) != CSAW_OK) return st;
     }
-    SampleLayer p;
-    p.g = g->dev();
-    p.num_instances = ni;
-    p.k0 = (uint32_t)a->rng_seed;
-    p.k1 = (uint32_t)(a->rng_seed >> 32);
-    p.instance_base = a->instance_base;
-    p.bias = d_bias;
-    p.cnt = d_cnt;
-    p.off = d_off;
-    p.ctl = ctl;
-    p.src = out->src;
-    p.dst = out->dst;
-    p.capacity = out->edge_capacity;
-    p.visited = visited;
-    p.next = next;
-    p.nwp = nwp;
-    int computed_layers = 1;  // frontiers F_0 .. F_{computed_layers-1} exist
-    for (int32_t l = 0; l < L; ++l) {
-        p.layer = l;
-        p.fanout = d_fan + (size_t)l * ni;
-        p.fanout_next = d_fan + (size_t)(l + 1) * ni;
-        p.fv = (const int32_t*)(A + o_fv[l]);
-        p.fi = (const int32_t*)(A + o_fi[l]);
-        const int64_t cap = P.fcap[l];
-        {
-            ProfScope ps("count", s);
-            launch_count(p, d_cnt, cap, s);
-        }
-        {
-            ProfScope ps("scan", s);
-            launch_scan_counts(d_cnt, &ctl->fcount[l], cap, d_bs, d_off, &ctl->total[l], s);
-        }
-        {
-            ProfScope ps("select", s);
-            const int grid = (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 4096);
-            launch_select(p, grid, s);
-        }
-        {
-            ProfScope ps("segments", s);
-            launch_segments(p, d_fstart, out->offsets, s);
-        }
-        if (l + 1 < L && P.fcap[l + 1] > 0) {
-            ProfScope ps("frontier_compact", s);
-            launch_bitmap_compact(next, visited, words, nwp, d_bs, &ctl->fcount[l + 1],
-                                  (int32_t*)(A + o_fv[l + 1]), (int32_t*)(A + o_fi[l + 1]), d_fstart, ni, s);
-            computed_layers = l + 2;
-        }
-    }
-    {
-        ProfScope ps("visited_clear", s);
-        for (int l = 0; l < computed_layers; ++l)
-            launch_clear_visited((const int32_t*)(A + o_fv[l]), (const int32_t*)(A + o_fi[l]), &ctl->fcount[l],
-                                 P.fcap[l], visited, nwp, s);
-    }
-    if (out->offsets)
-        HIP_OR_FAIL(hipMemcpyAsync(out->offsets + (size_t)L * ni, &ctl->out_base[L], sizeof(int64_t),
-                                   hipMemcpyDeviceToDevice, s));
-    HIP_OR_FAIL(hipGetLastError());
-    HIP_OR_FAIL(hipMemcpyAsync(h_ctl, ctl, sizeof(SampleCtl), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
     rel.clean = true;
     out->num_edges = L > 0 ? h_ctl->out_base[L] : 0;

@@ -19,7 +19,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kWin = 1024;  // LDS prefix window (uint64 entries) per wavefront
 
 inline int grid_for(int64_t items, int per_block, int cap = 1 << 20) {
     int64_t g = (items + per_block - 1) / per_block;
@@ -29,10 +28,13 @@ inline int grid_for(int64_t items, int per_block, int cap = 1 << 20) {
 }
 
 // ----------------------------------------------------------- block helpers
-// Exclusive scan of one int64 per thread over a 256-thread block; returns the
-// exclusive prefix and writes the block total to *total.
+// Exclusive scan of one int64 per thread over a block of kThreads threads;
+// returns the exclusive prefix and writes the block total to *total. Every
+// thread of the block must call it.
+template <int kThreads = kBlock>
 __device__ __forceinline__ int64_t block_excl_scan_i64(int64_t x, int64_t* total) {
-    __shared__ int64_t wsum[kWavesPerBlock];
+    constexpr int kW = kThreads / kWave;
+    __shared__ int64_t wsum[kW];
     const int lane = lane_id();
     const int wid = threadIdx.x / kWave;
     const uint64_t incl = wave_incl_scan_u64((uint64_t)x);
@@ -40,7 +42,7 @@ __device__ __forceinline__ int64_t block_excl_scan_i64(int64_t x, int64_t* total
     __syncthreads();
     int64_t base = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWavesPerBlock; ++w) {
+    for (int w = 0; w < kW; ++w) {
         const int64_t s = wsum[w];
         if (w < wid) base += s;
         tot += s;
@@ -127,28 +129,19 @@ __global__ void __launch_bounds__(1024) k_scan_blocksums(int64_t* __restrict__ b
         const int64_t used = (items + items_per_block - 1) / items_per_block;
         if (used < nb) nb = used;
     }
-    __shared__ int64_t part[1024];
     const int t = threadIdx.x;
     const int64_t seg = (nb + 1023) / 1024;
     const int64_t b0 = t * seg, b1 = (b0 + seg < nb) ? b0 + seg : nb;
     int64_t s = 0;
     for (int64_t b = b0; b < b1; ++b) s += bs[b];
-    part[t] = s;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over 1024 partials
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int64_t add = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
-    }
-    int64_t run = part[t] - s;
+    int64_t tot;
+    int64_t run = block_excl_scan_i64<1024>(s, &tot);
     for (int64_t b = b0; b < b1; ++b) {
         const int64_t x = bs[b];
         bs[b] = run;
         run += x;
     }
-    if (t == 1023) *total = part[1023];
+    if (t == 0) *total = tot;
 }
 
 // Bitmap compaction, pass 2: emit (vertex, instance) for every set bit in
@@ -187,6 +180,20 @@ __global__ void k_bm_emit(uint4* __restrict__ next4, uint4* __restrict__ visited
 }
 
 // ------------------------------------------------------------------ count
+// Weighted lists that need draws are routed by length: up to kWaveMaxD to the
+// wavefront kernel (list resident in a per-wave LDS tile), up to kMidMaxD to
+// the mid kernel (one block per list, whole list resident in LDS), longer ones
+// to the hub kernel (one block per list, coarse prefix only).
+constexpr int kWaveMaxD = 1024;
+constexpr int kMidMaxD = 8192;
+
+enum { kRouteWave = 0, kRouteMid = 1, kRouteHub = 2 };
+
+__device__ __forceinline__ int route_of(int32_t kind, int32_t k, int32_t P, int64_t d) {
+    if (kind == kUniform || k <= 0 || k >= P || d <= kWaveMaxD) return kRouteWave;
+    return d <= kMidMaxD ? kRouteMid : kRouteHub;
+}
+
 __device__ __forceinline__ int32_t positive_count(const GraphDev& g, int32_t kind, int32_t v, int64_t d) {
     if (kind == kUniform) return (int32_t)d;
     return kind == kEdgeWeight ? g.ppos_ew[v] : g.ppos_deg[v];
@@ -208,7 +215,17 @@ __global__ void k_count(SampleLayer p, int32_t* __restrict__ cnt) {
         else if (k > kMaxDrawFanout) {
             p.ctl->unsupported = 1;
             c = 0;
-        } else c = k;
+        } else {
+            c = k;
+            const int route = route_of(kind, k, P, d);
+            if (route == kRouteMid) {
+                const unsigned long long h = atomicAdd(&p.ctl->nmid[p.layer], 1ull);
+                p.mids[h] = (int32_t)e;
+            } else if (route == kRouteHub) {
+                const unsigned long long h = atomicAdd(&p.ctl->nhub[p.layer], 1ull);
+                p.hubs[h] = (int32_t)e;
+            }
+        }
         cnt[e] = c;
     }
 }
@@ -254,223 +271,138 @@ __global__ void k_scan_apply(const int32_t* __restrict__ cnt, const int64_t* __r
 }
 
 // ----------------------------------------------------------------- select
-// Where the wavefront finds the candidate owning r:
-//   kModeUniform : S_i = i, no weights
-//   kModeWindow  : full exclusive prefix S[0..d] in LDS (d <= kWin)
-//   kModeCoarse  : S at every G = 64*q-th position in LDS; the owning chunk
-//                  is re-read from global memory and scanned by the wave
-enum { kModeUniform = 0, kModeWindow = 1, kModeCoarse = 2 };
+// Prefix layout used by the inverse transform search of a weighted list:
+// groups of g consecutive candidates (g = 16 in the wavefront path, 16 * 2^p
+// in the hub path); C[t] = S[t*g] (exclusive prefix at the group starts) and
+// C[nc] = W live in LDS. A search finds the group by binary search in C and
+// the candidate by scanning the group's g weights (from the LDS tile when the
+// whole list is resident there, otherwise from global memory / L2).
+//
+// Weights reach LDS in tiles of 1024: 16 coalesced loads per lane are issued
+// together, stored transposed (element i at i + i/16, so that lane L's 16
+// consecutive elements sit in 16 distinct banks), summed per lane, and one
+// 64-lane scan turns the 64 group sums of a tile into 64 entries of C.
+constexpr int kTile = 1024;
+constexpr int kTilePad = kTile + kTile / 16;
+constexpr int kWaveC = kWaveMaxD / 16;     // coarse entries per wavefront
+constexpr int kMidThreads = 256;
+constexpr int kMidWaves = kMidThreads / kWave;
+constexpr int kHubThreads = 512;
+constexpr int kHubWaves = kHubThreads / kWave;
+constexpr int kHubC = 8192;                // coarse entries per hub block
 
-struct Pool {
-    int mode;
-    int64_t d;
-    int64_t beg;
-    const uint32_t* w;
-    const uint64_t* S;  // LDS
-    int64_t nc;         // coarse chunks
-    int64_t G;          // coarse chunk length
+__device__ __forceinline__ int tpad(int i) { return i + (i >> 4); }
+
+struct CoarsePool {
+    const uint64_t* C;      // LDS, nc + 1 entries
+    int64_t nc;             // groups
+    int64_t g;              // group length
+    int64_t d;              // list length
+    const uint32_t* w;      // weights of the list in global memory
+    const uint32_t* tile;   // LDS tile holding the whole list, or null
 };
 
-// Inverse transform search: m = max{i in [0,d) : S_i <= r}, with S_m and b_m.
-// Per lane for the uniform and window modes (lanes with want = false are
-// untouched); cooperatively, one wanted lane at a time, for the coarse mode.
-__device__ __forceinline__ void its_search(const Pool& pl, bool want, uint64_t r, int64_t& m,
-                                           uint64_t& Sm, uint32_t& bm) {
-    if (pl.mode == kModeUniform) {
-        if (want) {
-            m = (int64_t)r;
-            Sm = r;
-            bm = 1;
-        }
-        return;
+// m = max{i in [0,d) : S_i <= r} with S_m and b_m; per lane. kResident: the
+// group's weights are read from the LDS copy of the list (pl.tile), otherwise
+// 16 at a time from global memory.
+template <bool kResident>
+__device__ __forceinline__ void coarse_search(const CoarsePool& pl, uint64_t r, int64_t& m, uint64_t& Sm,
+                                              uint32_t& bm) {
+    int64_t lo = 0, hi = pl.nc;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (pl.C[mid] <= r) lo = mid;
+        else hi = mid;
     }
-    if (pl.mode == kModeWindow) {
-        if (want) {
-            int64_t lo = 0, hi = pl.d;
-            while (hi - lo > 1) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (pl.S[mid] <= r) lo = mid;
-                else hi = mid;
-            }
-            m = lo;
-            Sm = pl.S[lo];
-            bm = (uint32_t)(pl.S[lo + 1] - pl.S[lo]);
-        }
-        return;
-    }
-    const int lane = lane_id();
-    uint64_t wm = ballot(want);
-    while (wm) {
-        const int j = __ffsll((unsigned long long)wm) - 1;
-        const uint64_t rj = readlane_u64(r, j);
-        int64_t lo = 0, hi = pl.nc;
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (pl.S[mid] <= rj) lo = mid;
-            else hi = mid;
-        }
-        uint64_t acc = pl.S[lo];
-        const int64_t cs = lo * pl.G;
-        const int64_t ce = (cs + pl.G < pl.d) ? cs + pl.G : pl.d;
-        int64_t mj = cs;
-        uint64_t Smj = acc;
-        uint32_t bmj = 0;
-        for (int64_t base = cs; base < ce; base += kWave) {
-            const int64_t idx = base + lane;
-            const uint32_t x = idx < ce ? pl.w[pl.beg + idx] : 0u;
-            const uint64_t incl = wave_incl_scan_u64(x);
-            const uint64_t tot = readlane_u64(incl, kWave - 1);
-            if (acc + tot > rj) {
-                const int L = __popcll(ballot(acc + incl <= rj));
-                const uint64_t inclL = readlane_u64(incl, L);
-                const uint32_t xL = readlane_u32(x, L);
-                mj = base + L;
-                Smj = acc + inclL - xL;
-                bmj = xL;
-                break;
-            }
-            acc += tot;
-        }
-        if (lane == j) {
-            m = mj;
-            Sm = Smj;
-            bm = bmj;
-        }
-        wm &= wm - 1;
-    }
-}
-
-__device__ __forceinline__ void claim(bool do_claim, const uint32_t* visb, uint32_t* nextb, int32_t x) {
-    if (!do_claim) return;
-    const uint32_t bit = 1u << (x & 31);
-    if (!(visb[x >> 5] & bit)) atomicOr(&nextb[x >> 5], bit);
-}
-
-__device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, uint64_t* S) {
-    const int lane = lane_id();
-    const int32_t c = uniform_i32(p.cnt[e]);
-    if (c == 0) return;
-    const int32_t v = uniform_i32(p.fv[e]);
-    const int32_t inst = uniform_i32(p.fi[e]);
-    const int64_t o = out_base + uniform_i64(p.off[e]);
-    if (o + c > p.capacity) {
-        if (lane == 0) p.ctl->overflow = 1;
-        return;
-    }
-    const int32_t k = uniform_i32(p.fanout[inst]);
-    const int32_t kind = uniform_i32(p.bias[inst]);
-    const bool do_claim = p.fanout_next[inst] != 0;
-    const int64_t beg = uniform_i64(p.g.rowptr[v]);
-    const int64_t d = uniform_i64(p.g.rowptr[v + 1]) - beg;
-    const uint32_t* visb = p.visited + (int64_t)inst * p.nwp;
-    uint32_t* nextb = p.next + (int64_t)inst * p.nwp;
-    const bool weighted = kind != kUniform;
-    const uint32_t* w = kind == kEdgeWeight ? p.g.ew : p.g.degw;
-    const int32_t P = weighted ? uniform_i32(kind == kEdgeWeight ? p.g.ppos_ew[v] : p.g.ppos_deg[v])
-                               : (int32_t)d;
-    int32_t* src = p.src + o;
-    int32_t* dst = p.dst + o;
-
-    // ---- NeighborSize >= pool: every positive-bias neighbor, list order
-    if (k < 0 || k >= P) {
-        if (!weighted || P == d) {
-            for (int64_t j = lane; j < d; j += kWave) {
-                const int32_t x = p.g.col[beg + j];
-                src[j] = v;
-                dst[j] = x;
-                claim(do_claim, visb, nextb, x);
-            }
-        } else {
-            int64_t run = 0;
-            for (int64_t base = 0; base < d; base += kWave) {
-                const int64_t idx = base + lane;
-                const bool pos = idx < d && w[beg + idx] > 0;
-                const uint64_t mask = ballot(pos);
-                if (pos) {
-                    const int64_t slot = run + __popcll(mask & lanemask_lt());
-                    const int32_t x = p.g.col[beg + idx];
-                    src[slot] = v;
-                    dst[slot] = x;
-                    claim(do_claim, visb, nextb, x);
+    uint64_t acc = pl.C[lo];
+    int64_t i = lo * pl.g;
+    const int64_t end = (i + pl.g < pl.d) ? i + pl.g : pl.d;
+    m = i;
+    Sm = acc;
+    bm = 0;
+    if (kResident) {  // g == 16: one batch of LDS reads
+        uint32_t x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[q] = i + q < end ? pl.tile[tpad((int)(i + q))] : 0u;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (!found && i + q < end) {
+                if (acc + x[q] > r) {
+                    m = i + q;
+                    Sm = acc;
+                    bm = x[q];
+                    found = true;
+                } else {
+                    acc += x[q];
                 }
-                run += __popcll(mask);
             }
         }
         return;
     }
-
-    // ---- k < P <= d: draw k distinct candidates (k <= kMaxDrawFanout)
-    Pool pl;
-    pl.d = d;
-    pl.beg = beg;
-    pl.w = w;
-    pl.S = S;
-    pl.nc = 0;
-    pl.G = 0;
-    uint64_t W;
-    wave_lds_sync();
-    if (!weighted) {
-        pl.mode = kModeUniform;
-        W = (uint64_t)d;
-    } else if (d <= kWin) {
-        pl.mode = kModeWindow;
-        uint64_t carry = 0;
-        if (lane == 0) S[0] = 0;
-        for (int64_t base = 0; base < d; base += kWave) {
-            const int64_t idx = base + lane;
-            const uint32_t x = idx < d ? w[beg + idx] : 0u;
-            const uint64_t incl = wave_incl_scan_u64(x);
-            S[idx + 1] = carry + incl;
-            carry += readlane_u64(incl, kWave - 1);
+    for (; i < end; i += 16) {
+        uint32_t x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[q] = i + q < end ? pl.w[i + q] : 0u;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (!found && i + q < end) {
+                if (acc + x[q] > r) {
+                    m = i + q;
+                    Sm = acc;
+                    bm = x[q];
+                    found = true;
+                } else {
+                    acc += x[q];
+                }
+            }
         }
-        W = carry;
-    } else {
-        pl.mode = kModeCoarse;
-        int64_t q = 1;
-        while ((d + kWave * q - 1) / (kWave * q) > kWin) q <<= 1;
-        pl.G = kWave * q;
-        pl.nc = (d + pl.G - 1) / pl.G;
-        uint64_t carry = 0;
-        if (lane == 0) S[0] = 0;
-        for (int64_t t = 0; t < pl.nc; ++t) {
-            const int64_t cs = t * pl.G;
-            const int64_t ce = (cs + pl.G < d) ? cs + pl.G : d;
-            uint64_t part = 0;
-            for (int64_t idx = cs + lane; idx < ce; idx += kWave) part += w[beg + idx];
-            carry += wave_sum_u64(part);
-            if (lane == 0) S[t + 1] = carry;
-        }
-        W = carry;
+        if (found) break;
     }
-    wave_lds_sync();
+}
 
-    const Key key{p.k0, p.k1};
-    const uint32_t c0 = (uint32_t)(p.instance_base + (uint64_t)inst);
-    const uint32_t c1 = (uint32_t)p.layer;
-    const uint32_t c2 = (uint32_t)v;
+// Draw k distinct candidates with one lane per slot (lane j = slot j < k):
+// repeated-sampling rounds where the lowest slot wins a collision, then
+// direct draws from the prefix without the held candidates, in slot order.
+// search(r, m, Sm, bm) is the per-lane inverse transform search.
+//
+// Collisions: with own != null (lists of at most kWaveMaxD candidates) an
+// LDS array holds, per position, -1 once held, else the lowest open slot
+// that picked it this round (ds_min); otherwise each open slot compares with
+// every slot through lane reads.
+template <class Search>
+__device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k,
+                                              uint64_t W, const Search& search, int32_t* own = nullptr) {
+    const int lane = lane_id();
     const bool active = lane < k;
     bool held = false;
     int64_t pos = 0;
     uint64_t Spos = 0;
     uint32_t bpos = 0;
-
-    // repeated sampling rounds; lowest slot wins a collision
     for (int a = 0; a < kRounds; ++a) {
         const bool open = active && !held;
         if (ballot(open) == 0) break;
-        uint64_t r = 0;
-        if (open) r = draw(key, c0, c1, c2, (uint32_t)lane | ((uint32_t)a << 16), W);
         int64_t m = -1;
         uint64_t Sm = 0;
         uint32_t bm = 0;
-        its_search(pl, open, r, m, Sm, bm);
-        const uint64_t heldmask = ballot(held);
-        const int64_t val = held ? pos : m;
+        if (open) search(draw(key, c0, c1, c2, (uint32_t)lane | ((uint32_t)a << 16), W), m, Sm, bm);
         bool reject = false;
-        for (int q = 0; q < k; ++q) {
-            const int64_t pq = readlane_i64(val, q);
-            const bool qheld = (heldmask >> q) & 1ull;
-            if (q != lane && pq == m && (qheld || q < lane)) reject = true;
+        if (own) {
+            wave_lds_sync();
+            if (open) atomicMin(&own[m], lane);
+            wave_lds_sync();
+            reject = open && own[m] != lane;
+            wave_lds_sync();
+            if (open && !reject) own[m] = -1;
+        } else {
+            const uint64_t heldmask = ballot(held);
+            const int64_t val = held ? pos : m;
+            for (int q = 0; q < k; ++q) {
+                const int64_t pq = readlane_i64(val, q);
+                const bool qheld = (heldmask >> q) & 1ull;
+                if (q != lane && pq == m && (qheld || q < lane)) reject = true;
+            }
         }
         if (open && !reject) {
             held = true;
@@ -479,11 +411,8 @@ __device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, 
             bpos = bm;
         }
     }
-
-    // direct draws from the prefix without the held candidates, slot order
-    uint64_t heldmask = ballot(held);
-    const uint64_t activemask = ballot(active);
-    uint64_t openmask = activemask & ~heldmask;
+    const uint64_t heldmask = ballot(held);
+    uint64_t openmask = ballot(active) & ~heldmask;
     if (openmask) {
         // before = total bias of held candidates at smaller positions
         uint64_t before = 0;
@@ -497,12 +426,13 @@ __device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, 
         while (openmask) {
             const int j = __ffsll((unsigned long long)openmask) - 1;
             const uint64_t r0 = draw(key, c0, c1, c2, (uint32_t)j | (kFallbackRound << 16), W - removed);
-            const uint64_t skip = wave_sum_u64((held && Spos - before <= r0) ? (uint64_t)bpos : 0ull);
-            const uint64_t r = r0 + skip;
+            // skip map: every held region starting at or below the updated-prefix
+            // position r0 (shifted by the held mass before it) is stepped over
+            const uint64_t r = r0 + wave_sum_u64((held && Spos - before <= r0) ? (uint64_t)bpos : 0ull);
             int64_t m = 0;
             uint64_t Sm = 0;
             uint32_t bm = 0;
-            its_search(pl, pl.mode == kModeCoarse ? lane == j : true, r, m, Sm, bm);
+            search(r, m, Sm, bm);  // same r on every lane
             m = readlane_i64(m, j);
             Sm = readlane_u64(Sm, j);
             bm = readlane_u32(bm, j);
@@ -519,24 +449,290 @@ __device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, 
             openmask &= openmask - 1;
         }
     }
+    return pos;
+}
 
-    if (active) {
-        const int32_t x = p.g.col[beg + pos];
-        src[lane] = v;
-        dst[lane] = x;
-        claim(do_claim, visb, nextb, x);
+__device__ __forceinline__ void claim(bool do_claim, const uint32_t* visb, uint32_t* nextb, int32_t x) {
+    if (!do_claim) return;
+    const uint32_t bit = 1u << (x & 31);
+    if (!(visb[x >> 5] & bit)) atomicOr(&nextb[x >> 5], bit);
+}
+
+// Load one tile of up to 1024 weights (from list offset base) into an LDS
+// tile and return this lane's sum of its 16 consecutive elements.
+__device__ __forceinline__ uint64_t tile_group_sums(const uint32_t* __restrict__ w, int64_t base, int64_t d,
+                                                    uint32_t* tile) {
+    const int lane = lane_id();
+    uint32_t x[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int64_t idx = base + c * kWave + lane;
+        x[c] = idx < d ? w[idx] : 0u;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) tile[tpad(c * kWave + lane)] = x[c];
+    wave_lds_sync();
+    uint64_t s = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += tile[tpad(lane * 16 + q)];
+    return s;
+}
+
+struct EntryInfo {
+    int32_t c, v, inst, k, kind, P;
+    int64_t o, beg, d;
+    bool do_claim;
+};
+
+__device__ __forceinline__ bool load_entry(const SampleLayer& p, int64_t e, int64_t out_base, EntryInfo& E) {
+    E.c = uniform_i32(p.cnt[e]);
+    if (E.c == 0) return false;
+    E.v = uniform_i32(p.fv[e]);
+    E.inst = uniform_i32(p.fi[e]);
+    E.o = out_base + uniform_i64(p.off[e]);
+    E.k = uniform_i32(p.fanout[E.inst]);
+    E.kind = uniform_i32(p.bias[E.inst]);
+    E.do_claim = p.fanout_next[E.inst] != 0;
+    E.beg = uniform_i64(p.g.rowptr[E.v]);
+    E.d = uniform_i64(p.g.rowptr[E.v + 1]) - E.beg;
+    E.P = E.kind == kUniform ? (int32_t)E.d
+                             : uniform_i32(E.kind == kEdgeWeight ? p.g.ppos_ew[E.v] : p.g.ppos_deg[E.v]);
+    return true;
+}
+
+__device__ __forceinline__ void emit_slots(const SampleLayer& p, const EntryInfo& E, int64_t pos) {
+    const int lane = lane_id();
+    if (lane < E.k) {
+        const int32_t x = p.g.col[E.beg + pos];
+        p.src[E.o + lane] = E.v;
+        p.dst[E.o + lane] = x;
+        claim(E.do_claim, p.visited + (int64_t)E.inst * p.nwp, p.next + (int64_t)E.inst * p.nwp, x);
     }
 }
 
+__device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, uint32_t* tile, uint64_t* C,
+                             int32_t* own) {
+    const int lane = lane_id();
+    EntryInfo E;
+    if (!load_entry(p, e, out_base, E)) return;
+    if (E.o + E.c > p.capacity) {
+        if (lane == 0) p.ctl->overflow = 1;
+        return;
+    }
+    if (route_of(E.kind, E.k, E.P, E.d) != kRouteWave) return;  // mid / hub kernels
+    const uint32_t* visb = p.visited + (int64_t)E.inst * p.nwp;
+    uint32_t* nextb = p.next + (int64_t)E.inst * p.nwp;
+    const bool weighted = E.kind != kUniform;
+    const uint32_t* w = weighted ? (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg : nullptr;
+    const int32_t* col = p.g.col + E.beg;
+    int32_t* src = p.src + E.o;
+    int32_t* dst = p.dst + E.o;
+    const int64_t d = E.d;
+
+    // ---- NeighborSize >= pool: every positive-bias neighbor, list order
+    if (E.k < 0 || E.k >= E.P) {
+        if (!weighted || E.P == d) {
+            for (int64_t j = lane; j < d; j += kWave) {
+                const int32_t x = col[j];
+                src[j] = E.v;
+                dst[j] = x;
+                claim(E.do_claim, visb, nextb, x);
+            }
+        } else {
+            int64_t run = 0;
+            for (int64_t base = 0; base < d; base += 8 * kWave) {
+                uint32_t x[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int64_t idx = base + c * kWave + lane;
+                    x[c] = idx < d ? w[idx] : 0u;
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int64_t idx = base + c * kWave + lane;
+                    const bool pos = x[c] > 0;
+                    const uint64_t mask = ballot(pos);
+                    if (pos) {
+                        const int64_t slot = run + __popcll(mask & lanemask_lt());
+                        const int32_t nb = col[idx];
+                        src[slot] = E.v;
+                        dst[slot] = nb;
+                        claim(E.do_claim, visb, nextb, nb);
+                    }
+                    run += __popcll(mask);
+                }
+            }
+        }
+        return;
+    }
+
+    // ---- k < P <= d: draw k distinct candidates (k <= kMaxDrawFanout)
+    const Key key{p.k0, p.k1};
+    const uint32_t c0 = (uint32_t)(p.instance_base + (uint64_t)E.inst);
+    const uint32_t c1 = (uint32_t)p.layer;
+    const uint32_t c2 = (uint32_t)E.v;
+    int64_t pos;
+    int32_t* ownp = nullptr;
+    if (d <= kWaveMaxD) {
+        for (int64_t i = lane; i < d; i += kWave) own[i] = kWave;
+        ownp = own;
+    }
+    if (!weighted) {
+        pos = draw_slots(key, c0, c1, c2, E.k, (uint64_t)d,
+                         [](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+                             m = (int64_t)r;
+                             Sm = r;
+                             bm = 1;
+                         },
+                         ownp);
+    } else {
+        uint64_t carry = 0;
+        if (lane == 0) C[0] = 0;
+        for (int64_t t = 0; t * kTile < d; ++t) {
+            const uint64_t s = tile_group_sums(w, t * kTile, d, tile);
+            const uint64_t incl = wave_incl_scan_u64(s);
+            C[t * kWave + lane + 1] = carry + incl;
+            carry += readlane_u64(incl, kWave - 1);
+        }
+        wave_lds_sync();
+        const CoarsePool pl{C, (d + 15) / 16, 16, d, w, tile};
+        pos = draw_slots(key, c0, c1, c2, E.k, carry,
+                         [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+                             coarse_search<true>(pl, r, m, Sm, bm);
+                         },
+                         ownp);
+    }
+    emit_slots(p, E, pos);
+}
+
 __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
-    __shared__ uint64_t lds[kWavesPerBlock][kWin + 1];
-    const int wid = threadIdx.x / kWave;
-    uint64_t* S = lds[wid];
+    __shared__ uint32_t tiles[kWavesPerBlock][kTilePad];
+    __shared__ uint64_t coarse[kWavesPerBlock][kWaveC + 1];
+    __shared__ int32_t owners[kWavesPerBlock][kWaveMaxD];
+    const int wid = uniform_i32(threadIdx.x / kWave);
     const int64_t fcount = p.ctl->fcount[p.layer];
     const int64_t out_base = p.ctl->out_base[p.layer];
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t e = blockIdx.x * (int64_t)kWavesPerBlock + wid; e < fcount; e += waves)
-        select_entry(p, e, out_base, S);
+        select_entry(p, e, out_base, tiles[wid], coarse[wid], owners[wid]);
+}
+
+// One block per mid-size weighted list (kWaveMaxD < d <= kMidMaxD): the
+// block's waves load the list's tiles in parallel into LDS (transposed layout,
+// the whole list stays resident), one thread per 16-group sums it, a block
+// scan builds the coarse prefix, and wave 0 draws the slots with every search
+// served from LDS.
+__global__ void __launch_bounds__(kMidThreads) k_select_mid(SampleLayer p, const int32_t* __restrict__ mids) {
+    __shared__ uint32_t wt[kMidMaxD + kMidMaxD / 16];
+    __shared__ uint64_t C[kMidMaxD / 16 + 1];
+    const int tid = threadIdx.x;
+    const int wid = uniform_i32(tid / kWave);
+    const int lane = lane_id();
+    const int64_t nm = (int64_t)p.ctl->nmid[p.layer];
+    const int64_t out_base = p.ctl->out_base[p.layer];
+    for (int64_t h = blockIdx.x; h < nm; h += gridDim.x) {
+        EntryInfo E;
+        load_entry(p, mids[h], out_base, E);
+        const int64_t d = E.d;
+        const uint32_t* w = (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg;
+        for (int64_t t = wid; t * kTile < d; t += kMidWaves) {
+            uint32_t x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int64_t idx = t * kTile + c * kWave + lane;
+                x[c] = idx < d ? w[idx] : 0u;
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) wt[tpad((int)(t * kTile) + c * kWave + lane)] = x[c];
+        }
+        __syncthreads();
+        const int ng = (int)((d + 15) / 16);
+        // group sums, then inclusive scan of C[1..ng] (thread tid owns 2 groups)
+        uint64_t s0 = 0, s1 = 0;
+        const int g0 = 2 * tid, g1 = 2 * tid + 1;
+        if (g0 < ng)
+            for (int q = 0; q < 16; ++q) s0 += (16 * g0 + q < d) ? wt[tpad(16 * g0 + q)] : 0u;
+        if (g1 < ng)
+            for (int q = 0; q < 16; ++q) s1 += (16 * g1 + q < d) ? wt[tpad(16 * g1 + q)] : 0u;
+        int64_t tot;
+        const uint64_t before = (uint64_t)block_excl_scan_i64<kMidThreads>((int64_t)(s0 + s1), &tot);
+        if (g0 < ng) C[g0 + 1] = before + s0;
+        if (g1 < ng) C[g1 + 1] = before + s0 + s1;
+        if (tid == 0) C[0] = 0;
+        __syncthreads();
+        if (wid == 0) {
+            if (E.o + E.c > p.capacity) {
+                if (lane == 0) p.ctl->overflow = 1;
+            } else {
+                const CoarsePool pl{C, ng, 16, d, w, wt};
+                const int64_t pos = draw_slots(Key{p.k0, p.k1}, (uint32_t)(p.instance_base + (uint64_t)E.inst),
+                                               (uint32_t)p.layer, (uint32_t)E.v, E.k, C[ng],
+                                               [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+                                                   coarse_search<true>(pl, r, m, Sm, bm);
+                                               });
+                emit_slots(p, E, pos);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One block per hub list: the block's waves stream the list in tiles and add
+// group sums into C (LDS atomics), a block scan turns them into the coarse
+// prefix, then wave 0 draws the slots.
+__global__ void __launch_bounds__(kHubThreads) k_select_hub(SampleLayer p, const int32_t* __restrict__ hubs) {
+    __shared__ uint64_t C[kHubC + 1];
+    __shared__ uint32_t tiles[kHubWaves][kTilePad];
+    const int tid = threadIdx.x;
+    const int wid = uniform_i32(tid / kWave);
+    const int lane = lane_id();
+    const int64_t nh = (int64_t)p.ctl->nhub[p.layer];
+    const int64_t out_base = p.ctl->out_base[p.layer];
+    for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
+        EntryInfo E;
+        load_entry(p, hubs[h], out_base, E);
+        const int64_t d = E.d;
+        const uint32_t* w = (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg;
+        int64_t g = 16;
+        while ((d + g - 1) / g > kHubC) g <<= 1;
+        const int64_t ng = (d + g - 1) / g;
+        for (int64_t i = tid; i <= ng; i += kHubThreads) C[i] = 0;
+        __syncthreads();
+        for (int64_t t = wid; t * kTile < d; t += kHubWaves) {
+            const uint64_t s = tile_group_sums(w, t * kTile, d, tiles[wid]);
+            const int64_t first = t * kTile + lane * 16;
+            if (first < d && s) atomicAdd((unsigned long long*)&C[1 + first / g], (unsigned long long)s);
+        }
+        __syncthreads();
+        // inclusive scan of C[1..ng]; thread tid owns a contiguous segment
+        const int64_t seg = (ng + kHubThreads - 1) / kHubThreads;
+        const int64_t b0 = 1 + tid * seg;
+        const int64_t b1 = (b0 + seg < ng + 1) ? b0 + seg : ng + 1;
+        uint64_t local = 0;
+        for (int64_t b = b0; b < b1; ++b) local += C[b];
+        int64_t tot;
+        uint64_t run = (uint64_t)block_excl_scan_i64<kHubThreads>((int64_t)local, &tot);
+        for (int64_t b = b0; b < b1; ++b) {
+            run += C[b];
+            C[b] = run;
+        }
+        __syncthreads();
+        if (wid == 0) {
+            if (E.o + E.c > p.capacity) {
+                if (lane == 0) p.ctl->overflow = 1;
+            } else {
+                const CoarsePool pl{C, ng, g, d, w, nullptr};
+                const int64_t pos = draw_slots(Key{p.k0, p.k1}, (uint32_t)(p.instance_base + (uint64_t)E.inst),
+                                               (uint32_t)p.layer, (uint32_t)E.v, E.k, C[ng],
+                                               [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+                                                   coarse_search<false>(pl, r, m, Sm, bm);
+                                               });
+                emit_slots(p, E, pos);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void k_segments(SampleLayer p, const int64_t* __restrict__ fstart, int64_t* __restrict__ offsets) {
@@ -598,7 +794,7 @@ void launch_bitmap_compact(uint32_t* next, uint32_t* visited, int64_t words, int
     const int64_t n4 = words / 4;
     const int64_t nb = (n4 + kBlock - 1) / kBlock;
     if (nb <= 0) {
-        (void)hipMemsetAsync(fcount_out, 0, sizeof(int64_t), s);
+        launch_fill_u32((uint32_t*)fcount_out, 0u, 2, s);
         return;
     }
     hipLaunchKernelGGL(k_bm_count, dim3((unsigned)nb), dim3(kBlock), 0, s, (const uint4*)next, n4, blocksum);
@@ -617,7 +813,7 @@ void launch_scan_counts(const int32_t* cnt, const int64_t* fcount, int64_t cap_e
                         int64_t* off, int64_t* total_out, hipStream_t s) {
     const int64_t nb = (cap_entries + kScanItems - 1) / kScanItems;
     if (nb <= 0) {
-        (void)hipMemsetAsync(total_out, 0, sizeof(int64_t), s);
+        launch_fill_u32((uint32_t*)total_out, 0u, 2, s);
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, fcount, blocksum);
@@ -628,6 +824,14 @@ void launch_scan_counts(const int32_t* cnt, const int64_t* fcount, int64_t cap_e
 
 void launch_select(const SampleLayer& p, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(grid), dim3(kBlock), 0, s, p);
+}
+
+void launch_select_mid(const SampleLayer& p, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_mid, dim3(grid), dim3(kMidThreads), 0, s, p, (const int32_t*)p.mids);
+}
+
+void launch_select_hub(const SampleLayer& p, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_hub, dim3(grid), dim3(kHubThreads), 0, s, p, (const int32_t*)p.hubs);
 }
 
 void launch_segments(const SampleLayer& p, const int64_t* fstart, int64_t* offsets, hipStream_t s) {

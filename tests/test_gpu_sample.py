@@ -200,3 +200,52 @@ def test_degree_biased_rmat22_full(csaw):
     g = csaw.Graph(rp, col)
     for s in rec["rng_seeds"][:1]:
         run_both(csaw, g, rp, col, None, offs, seeds, rec["fanouts"], csaw.NEIGHBOR_DEGREE, s)
+
+
+def test_route_boundaries(csaw):
+    """Weighted lists at the lengths where the kernels hand over (wavefront /
+    mid / hub): 1024, 1025, 8192, 8193, plus short ones, with zero weights and
+    dominant weights, many instances and fanouts up to 64."""
+    degs = [16, 1024, 1025, 8192, 8193, 20000]
+    hubs = len(degs)
+    n = hubs + max(degs)
+    rng = inputs.rng(17)
+    edges = []
+    for h, d in enumerate(degs):
+        for x in rng.choice(np.arange(hubs, n), size=d, replace=False):
+            edges.append((h, int(x)))
+    rp, col = inputs.csr_from_edges(n, edges)
+    ew = rng.integers(0, 300, size=len(col)).astype(np.uint32)
+    ew[rng.random(len(col)) < 0.2] = 0
+    ew[rng.random(len(col)) < 0.002] = 1 << 24
+    g = csaw.Graph(rp, col, ew)
+    ni = 4 * hubs
+    offs = np.arange(ni + 1, dtype=np.int64)
+    seeds = np.tile(np.arange(hubs, dtype=np.int32), 4)
+    for k in (1, 25, 64):
+        run_both(csaw, g, rp, col, ew, offs, seeds, [k], csaw.EDGE_WEIGHT, 50 + k, instance_base=7)
+
+
+def test_replayed_launch_sequence_matches_eager(csaw):
+    """Calls are replayed from a captured launch sequence when possible; with
+    kernel profiling on they run eagerly. Both give the same bits, also when
+    table contents change under the same shapes."""
+    rp, col = inputs.rmat_csr(14, 16 << 14, 19)
+    offs, seeds = inputs.single_instance_seeds(rp, col, 700, 21)
+    g = csaw.Graph(rp, col)
+    say("graph replay vs eager")
+    outs = []
+    for prof in (False, True, False, False):
+        csaw.profile_enable(prof)
+        r = g.sample(offs, seeds, [25, 10], csaw.NEIGHBOR_DEGREE, rng_seed=5)
+        outs.append((r.dst.cpu().numpy().copy(), r.offsets.cpu().numpy().copy()))
+    csaw.profile_enable(False)
+    csaw.profile_reset()
+    for d, o in outs[1:]:
+        np.testing.assert_array_equal(d, outs[0][0])
+        np.testing.assert_array_equal(o, outs[0][1])
+    # same shapes, different seeds and bias kind: must not reuse stale values
+    offs2, seeds2 = inputs.single_instance_seeds(rp, col, 700, 22)
+    res = g.sample(offs2, seeds2, [25, 10], csaw.UNIFORM, rng_seed=5)
+    ref = oracle.sample(rp, col, None, offs2, seeds2, [25, 10], bias_kind=oracle.UNIFORM, rng_seed=5)
+    assert_same(res, ref)
