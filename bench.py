@@ -134,8 +134,8 @@ def bench_degree_biased(args):
         alg += sum(bytes_of[s])
     torch.cuda.synchronize()
     sel_ms, sel_n = csaw.profile_read("select_wave")
-    times = {k: csaw.profile_read(k) for k in ("frontier_init", "count", "scan", "select_wave", "select_mid", "select_hub",
-                                                "segments", "frontier_compact", "visited_clear")}
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_wave", "select_mid", "select_hub",
+                                                "frontier_build", "visited_clear")}
     csaw.profile_enable(False)
     csaw.profile_reset()
     achieved = alg / (sel_ms / 1e3) / 1e9 if sel_ms > 0 else 0.0

@@ -154,7 +154,12 @@ typedef struct {
     int32_t bias_kind;            /* csaw_bias_kind (not NODE2VEC), used when
                                      bias_kinds is NULL                           */
     const int32_t* bias_kinds;    /* HOST int32[num_instances] or NULL            */
-    uint64_t rng_seed;            /* Philox key                                   */
+    uint64_t rng_seed;            /* Philox key, used when rng_seeds is NULL      */
+    const uint64_t* instance_ids; /* HOST uint64[num_instances] or NULL: instance
+                                     i has this id instead of instance_base + i   */
+    const uint64_t* rng_seeds;    /* HOST uint64[num_instances] or NULL: a Philox
+                                     key per instance, so that instances from
+                                     unrelated requests share one call            */
 } csaw_sample_args;
 
 typedef struct {
@@ -197,6 +202,9 @@ typedef struct {
     uint64_t walker_base;         /* walker w has id walker_base + w              */
     int32_t length;               /* number of steps, >= 0                        */
     uint64_t rng_seed;            /* Philox key                                   */
+    const uint64_t* walker_ids;   /* DEVICE uint64[num_walkers] or NULL: walker w
+                                     has this id instead of walker_base + w (an
+                                     exact subset of a larger run)                */
 } csaw_walk_args;
 
 /* paths: DEVICE int32[num_walkers * (length+1)], walker-major; path[0] is
@@ -207,6 +215,81 @@ typedef struct {
  * edge weights, or a start outside [0, n) detected on the device). */
 csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* args, int32_t* paths,
                       int64_t* total_steps, csaw_stream stream);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A request server over one resident graph: requests (one sampling instance
+ * or one batch of walkers each) are submitted from any thread with host
+ * inputs; they are admitted while the device memory they need fits the
+ * budget; executor threads, each with its own stream, take every admitted
+ * sampling request that is waiting at that moment into one multi-instance
+ * csaw_sample call (continuous batching) and run walk requests as they come,
+ * so that requests arriving while others run overlap with them on the device.
+ * A request's result is bit-identical to running it alone: its draws are
+ * keyed by its own id and rng_seed. */
+typedef struct csaw_server_s* csaw_server;
+
+typedef struct {
+    int64_t memory_budget_bytes;  /* device memory of admitted requests (0: 32 GiB)  */
+    int32_t max_batch;            /* most sampling requests per call (0: 512)        */
+    int32_t queue_capacity;       /* most waiting requests before BUSY (0: 65536)    */
+    int32_t num_streams;          /* executor threads/streams (0: 2)                 */
+} csaw_server_config;
+
+typedef enum { CSAW_REQUEST_SAMPLE = 0, CSAW_REQUEST_WALK = 1 } csaw_request_kind;
+
+typedef struct {
+    int32_t kind;                 /* csaw_request_kind                             */
+    uint64_t id;                  /* sampling: instance id; walks: id of walker 0  */
+    uint64_t rng_seed;            /* Philox key                                    */
+    int32_t bias_kind;            /* csaw_bias_kind                                */
+    /* sampling */
+    const int32_t* seeds;         /* HOST int32[num_seeds], copied at submit       */
+    int64_t num_seeds;
+    const int32_t* fanouts;       /* HOST int32[num_layers], copied at submit      */
+    int32_t num_layers;
+    /* walks */
+    const int32_t* starts;        /* HOST int32[num_walkers], copied at submit     */
+    int64_t num_walkers;
+    int32_t length;
+    uint32_t w_return, w_common, w_outward;
+} csaw_request;
+
+typedef struct {
+    csaw_status status;           /* outcome of this request                       */
+    int32_t kind;
+    /* sampling: edges in (layer, source, slot) order; layer l is
+       [layer_offsets[l], layer_offsets[l+1]) */
+    int64_t num_edges;
+    int32_t* src;
+    int32_t* dst;
+    int32_t num_layers;
+    int64_t* layer_offsets;
+    /* walks: int32[num_walkers * (length+1)], -1 after a stop */
+    int32_t* paths;
+    int64_t num_walkers;
+    int32_t length;
+    int64_t steps;                /* sampled edges of a walk request               */
+    /* latency, microseconds from submit */
+    double queued_us;             /* until its batch started                       */
+    double total_us;              /* until its result was in host memory           */
+} csaw_result;
+
+/* Errors: INVALID_ARG (bad config). The server keeps g; g must outlive it. */
+csaw_status csaw_server_create(csaw_graph g, const csaw_server_config* cfg, csaw_server* out);
+/* Validates and copies the request (INVALID_ARG: bad ids, bias kind, sizes;
+ * OUT_OF_MEMORY: the request alone exceeds the budget; BUSY: queue full).
+ * HOST out: ticket, used to fetch the result. */
+csaw_status csaw_server_submit(csaw_server s, const csaw_request* req, uint64_t* ticket);
+/* NOT_READY until the request is done; then hands over *result (the caller
+ * frees it with csaw_result_free). INVALID_ARG for an unknown ticket. */
+csaw_status csaw_server_poll(csaw_server s, uint64_t ticket, csaw_result** result);
+/* As poll, but waits up to timeout_us (< 0: no limit). */
+csaw_status csaw_server_wait(csaw_server s, uint64_t ticket, int64_t timeout_us, csaw_result** result);
+void csaw_result_free(csaw_result* r);
+/* Finishes every submitted request, stops the executors and frees the
+ * server. Results not fetched are freed. */
+csaw_status csaw_server_destroy(csaw_server s);
 
 /* --------------------------------------------------------------- profiling */
 

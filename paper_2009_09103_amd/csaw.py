@@ -38,7 +38,8 @@ class SampleArgs(ctypes.Structure):
                 ("seeds", ctypes.c_void_p), ("instance_base", ctypes.c_uint64),
                 ("num_layers", ctypes.c_int32), ("fanouts", ctypes.c_void_p),
                 ("fanout_stride", ctypes.c_int32), ("bias_kind", ctypes.c_int32),
-                ("bias_kinds", ctypes.c_void_p), ("rng_seed", ctypes.c_uint64)]
+                ("bias_kinds", ctypes.c_void_p), ("rng_seed", ctypes.c_uint64),
+                ("instance_ids", ctypes.c_void_p), ("rng_seeds", ctypes.c_void_p)]
 
 
 class SampleOut(ctypes.Structure):
@@ -51,12 +52,36 @@ class WalkArgs(ctypes.Structure):
                 ("w_common", ctypes.c_uint32), ("w_outward", ctypes.c_uint32),
                 ("num_walkers", ctypes.c_int64), ("starts", ctypes.c_void_p),
                 ("walker_base", ctypes.c_uint64), ("length", ctypes.c_int32),
-                ("rng_seed", ctypes.c_uint64)]
+                ("rng_seed", ctypes.c_uint64), ("walker_ids", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("num_streams", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("id", ctypes.c_uint64), ("rng_seed", ctypes.c_uint64),
+                ("bias_kind", ctypes.c_int32), ("seeds", ctypes.c_void_p), ("num_seeds", ctypes.c_int64),
+                ("fanouts", ctypes.c_void_p), ("num_layers", ctypes.c_int32),
+                ("starts", ctypes.c_void_p), ("num_walkers", ctypes.c_int64), ("length", ctypes.c_int32),
+                ("w_return", ctypes.c_uint32), ("w_common", ctypes.c_uint32), ("w_outward", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("num_edges", ctypes.c_int64),
+                ("src", ctypes.POINTER(ctypes.c_int32)), ("dst", ctypes.POINTER(ctypes.c_int32)),
+                ("num_layers", ctypes.c_int32), ("layer_offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("paths", ctypes.POINTER(ctypes.c_int32)), ("num_walkers", ctypes.c_int64),
+                ("length", ctypes.c_int32), ("steps", ctypes.c_int64), ("queued_us", ctypes.c_double),
+                ("total_us", ctypes.c_double)]
 
 
 EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample",
            "csaw_sample_bound", "csaw_walk", "csaw_profile_enable", "csaw_profile_reset",
-           "csaw_profile_read", "csaw_last_error", "csaw_version"]
+           "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
+           "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_result_free",
+           "csaw_server_destroy"]
 
 
 def _load():
@@ -74,9 +99,16 @@ def _load():
     L.csaw_profile_reset.argtypes = []
     L.csaw_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64)]
+    L.csaw_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    L.csaw_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.csaw_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.POINTER(Result))]
+    L.csaw_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ctypes.POINTER(Result))]
+    L.csaw_result_free.argtypes = [ctypes.POINTER(Result)]
+    L.csaw_server_destroy.argtypes = [vp]
     for f in EXPORTS:
-        if f not in ("csaw_last_error", "csaw_version"):
+        if f not in ("csaw_last_error", "csaw_version", "csaw_result_free"):
             getattr(L, f).restype = ctypes.c_int
+    L.csaw_result_free.restype = None
     L.csaw_last_error.restype = ctypes.c_char_p
     L.csaw_version.restype = ctypes.c_char_p
     return L
@@ -161,7 +193,8 @@ class Graph:
         return dict(n=n.value, m=m.value, max_degree=md.value, sorted=bool(srt.value))
 
     # -------------------------------------------------------------- sampling
-    def _sample_args(self, seed_offsets, seeds_dev, fanouts, bias, rng_seed, instance_base):
+    def _sample_args(self, seed_offsets, seeds_dev, fanouts, bias, rng_seed, instance_base,
+                     instance_ids=None, rng_seeds=None):
         so = np.ascontiguousarray(seed_offsets, dtype=np.int64)
         fo = np.ascontiguousarray(fanouts, dtype=np.int32)
         ni = len(so) - 1
@@ -187,6 +220,18 @@ class Graph:
             a.bias_kinds = None
             a.bias_kind = _bias_code(bias)
         a.rng_seed = int(rng_seed)
+        a.instance_ids = None
+        a.rng_seeds = None
+        if instance_ids is not None:
+            ids = np.ascontiguousarray(instance_ids, dtype=np.uint64)
+            assert len(ids) == ni
+            a.instance_ids = ids.ctypes.data
+            keep.append(ids)
+        if rng_seeds is not None:
+            rs = np.ascontiguousarray(rng_seeds, dtype=np.uint64)
+            assert len(rs) == ni
+            a.rng_seeds = rs.ctypes.data
+            keep.append(rs)
         return a, keep, ni, L
 
     def sample_bound(self, seed_offsets, fanouts, bias=UNIFORM) -> int:
@@ -196,13 +241,13 @@ class Graph:
         return mx.value
 
     def sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
-               capacity=None, stream=None, out=None) -> SampleResult:
+               capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None) -> SampleResult:
         """Neighbor sampling (csaw_sample). ``seeds`` may be a device tensor
         (used in place) or host data (copied). ``out`` may pass preallocated
         (src, dst, offsets) device tensors."""
         seeds_dev = _dev_i32(seeds, self.device)
         a, keep, ni, L = self._sample_args(seed_offsets, seeds_dev, fanouts, bias, rng_seed,
-                                           instance_base)
+                                           instance_base, instance_ids, rng_seeds)
         if out is None:
             if capacity is None:
                 mx = ctypes.c_int64()
@@ -223,7 +268,7 @@ class Graph:
 
     # ----------------------------------------------------------------- walks
     def walk(self, starts, length, bias=UNIFORM, rng_seed=1, walker_base=0, node2vec=(1, 1, 1),
-             stream=None, paths=None):
+             stream=None, paths=None, walker_ids=None):
         """Random walks (csaw_walk). Returns (paths [nw, length+1] int32 device
         tensor, total steps)."""
         st = _dev_i32(starts, self.device)
@@ -238,6 +283,12 @@ class Graph:
         a.walker_base = int(walker_base)
         a.length = int(length)
         a.rng_seed = int(rng_seed)
+        ids_dev = None
+        if walker_ids is not None:
+            ids_dev = torch.from_numpy(np.ascontiguousarray(walker_ids, dtype=np.uint64).view(np.int64)).to(
+                self.device)
+            assert ids_dev.numel() == nw
+        a.walker_ids = ids_dev.data_ptr() if ids_dev is not None and nw else None
         steps = ctypes.c_int64()
         _check(lib.csaw_walk(self._h, ctypes.byref(a), paths.data_ptr() if nw else None,
                              ctypes.byref(steps), _stream(stream)))
@@ -257,3 +308,89 @@ def profile_read(prefix: str):
     t, c = ctypes.c_double(), ctypes.c_int64()
     _check(lib.csaw_profile_read(prefix.encode(), ctypes.byref(t), ctypes.byref(c)))
     return t.value, c.value
+
+
+class ServedResult:
+    """A finished server request (host arrays, copied out of the library)."""
+
+    def __init__(self, r: Result):
+        self.status = r.status
+        self.kind = r.kind
+        self.queued_us, self.total_us = r.queued_us, r.total_us
+        if r.kind == 0 and r.status == 0:
+            ne = r.num_edges
+            self.src = np.ctypeslib.as_array(r.src, shape=(max(ne, 1),))[:ne].copy()
+            self.dst = np.ctypeslib.as_array(r.dst, shape=(max(ne, 1),))[:ne].copy()
+            self.layer_offsets = np.ctypeslib.as_array(r.layer_offsets, shape=(r.num_layers + 1,)).copy()
+            self.num_edges = ne
+        elif r.kind == 1 and r.status == 0:
+            n = r.num_walkers * (r.length + 1)
+            arr = np.ctypeslib.as_array(r.paths, shape=(max(n, 1),))[:n].copy()
+            self.paths = arr.reshape(r.num_walkers, r.length + 1)
+            self.steps = r.steps
+            self.num_edges = r.steps
+
+
+class Server:
+    """Request server over a resident graph (csaw_server_*)."""
+
+    def __init__(self, graph: Graph, memory_budget_bytes=0, max_batch=0, queue_capacity=0, num_streams=0):
+        cfg = ServerConfig(int(memory_budget_bytes), int(max_batch), int(queue_capacity), int(num_streams))
+        h = ctypes.c_void_p()
+        _check(lib.csaw_server_create(graph._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.graph = graph
+
+    def submit_sample(self, seeds, fanouts, bias=UNIFORM, rng_seed=1, request_id=0) -> int:
+        sd = np.ascontiguousarray(seeds, dtype=np.int32)
+        fo = np.ascontiguousarray(fanouts, dtype=np.int32)
+        q = Request()
+        q.kind, q.id, q.rng_seed, q.bias_kind = 0, int(request_id), int(rng_seed), _bias_code(bias)
+        q.seeds, q.num_seeds = sd.ctypes.data, len(sd)
+        q.fanouts, q.num_layers = fo.ctypes.data, len(fo)
+        t = ctypes.c_uint64()
+        _check(lib.csaw_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        return t.value
+
+    def submit_walk(self, starts, length, bias=UNIFORM, rng_seed=1, request_id=0, node2vec=(1, 1, 1)) -> int:
+        st = np.ascontiguousarray(starts, dtype=np.int32)
+        q = Request()
+        q.kind, q.id, q.rng_seed, q.bias_kind = 1, int(request_id), int(rng_seed), _bias_code(bias)
+        q.starts, q.num_walkers, q.length = st.ctypes.data, len(st), int(length)
+        q.w_return, q.w_common, q.w_outward = (int(x) for x in node2vec)
+        t = ctypes.c_uint64()
+        _check(lib.csaw_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        return t.value
+
+    def _take(self, rp):
+        try:
+            return ServedResult(rp.contents)
+        finally:
+            lib.csaw_result_free(rp)
+
+    def poll(self, ticket: int):
+        rp = ctypes.POINTER(Result)()
+        st = lib.csaw_server_poll(self._h, ticket, ctypes.byref(rp))
+        if st == 5:
+            return None
+        _check(st)
+        return self._take(rp)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        rp = ctypes.POINTER(Result)()
+        st = lib.csaw_server_wait(self._h, ticket, int(timeout_us), ctypes.byref(rp))
+        if st == 5:
+            return None
+        _check(st)
+        return self._take(rp)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.csaw_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

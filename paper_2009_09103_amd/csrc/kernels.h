@@ -29,20 +29,46 @@ struct SampleCtl {
     int64_t fcount[kMaxLayers + 1];    // frontier sizes
     int64_t total[kMaxLayers];         // edges per layer
     int64_t out_base[kMaxLayers + 1];  // first edge of each layer
+    unsigned long long tickets[kMaxLayers];  // block order of the frontier builds
     unsigned long long nmid[kMaxLayers];  // mid-kernel entries per layer
     unsigned long long nhub[kMaxLayers];  // hub-kernel entries per layer
     int32_t bad_seed;
     int32_t overflow;
     int32_t unsupported;
-    int32_t pad;
+    int32_t lookback_stuck;
+};
+
+// One frontier build: next bitmap -> sorted frontier entries with their edge
+// counts, edge offsets, kernel routes and per-instance segment offsets.
+struct FrontierBuild {
+    GraphDev g;
+    uint4* next4;
+    uint4* visited4;
+    int64_t n4;                      // uint4 groups of all bitmaps
+    int64_t nwp4;                    // uint4 groups per instance
+    int64_t nb;                      // blocks of the launch
+    int32_t layer;
+    int32_t num_layers;
+    int32_t num_instances;
+    const int32_t* fanout;           // [ni] fanout of this layer
+    const int32_t* bias;             // [ni]
+    int32_t* fv;
+    int32_t* fi;
+    int32_t* cnt;
+    int64_t* off;
+    int32_t* mids;
+    int32_t* hubs;
+    int64_t* offsets;                // [L*ni+1] or null
+    SampleCtl* ctl;
+    unsigned long long* status;      // [4 * nb] look-back words
 };
 
 struct SampleLayer {
     GraphDev g;
     int32_t layer;
     int32_t num_instances;
-    uint32_t k0, k1;                 // Philox key
-    uint64_t instance_base;
+    const uint32_t* inst_id;         // [ni] instance id mod 2^32 (counter word 0)
+    const uint64_t* inst_key;        // [ni] Philox key per instance
     const int32_t* fanout;           // [ni] fanout of this layer per instance
     const int32_t* fanout_next;      // [ni] fanout of the next layer (0 = none)
     const int32_t* bias;             // [ni]
@@ -65,16 +91,11 @@ struct SampleLayer {
 void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* seed_offsets,
                        int32_t ni, int64_t n, uint32_t* next, int64_t nwp, SampleCtl* ctl,
                        hipStream_t s);
-void launch_bitmap_compact(uint32_t* next, uint32_t* visited, int64_t words, int64_t nwp,
-                           int64_t* blocksum, int64_t* fcount_out, int32_t* fv, int32_t* fi,
-                           int64_t* fstart, int32_t ni, hipStream_t s);
-void launch_count(const SampleLayer& p, int32_t* cnt, int64_t cap_entries, hipStream_t s);
-void launch_scan_counts(const int32_t* cnt, const int64_t* fcount, int64_t cap_entries,
-                        int64_t* blocksum, int64_t* off, int64_t* total_out, hipStream_t s);
+int64_t frontier_build_blocks(int64_t words);
+void launch_frontier_build(const FrontierBuild& fb, hipStream_t s);
 void launch_select(const SampleLayer& p, int grid, hipStream_t s);
 void launch_select_mid(const SampleLayer& p, int grid, hipStream_t s);
 void launch_select_hub(const SampleLayer& p, int grid, hipStream_t s);
-void launch_segments(const SampleLayer& p, const int64_t* fstart, int64_t* offsets, hipStream_t s);
 void launch_clear_visited(const int32_t* fv, const int32_t* fi, const int64_t* fcount,
                           int64_t cap_entries, uint32_t* visited, int64_t nwp, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
@@ -95,6 +116,7 @@ struct WalkParams {
     uint64_t walker_base;
     int32_t length;
     uint32_t k0, k1;
+    const uint64_t* walker_ids;      // [nw] or null
     int32_t* paths;
     unsigned long long* steps;       // device counter
     int32_t* bad_start;              // device flag

@@ -481,16 +481,17 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         sumF = sat_add(sumF, P.fcap[l]);
     }
     if (sumF > (int64_t(1) << 40)) return fail(CSAW_ERR_OUT_OF_MEMORY, "frontier bound too large");
-    const int64_t nb_scan = std::max<int64_t>((maxF + kScanItems - 1) / kScanItems, (words / 4 + 255) / 256) + 1;
+    const int64_t nb_build = frontier_build_blocks(words);
 
     // device workspace layout
     Carver cv;
     const size_t o_ctl = cv.take<SampleCtl>(1);
     const size_t o_fan = cv.take<int32_t>((size_t)(L + 1) * ni);
     const size_t o_bias = cv.take<int32_t>(ni);
+    const size_t o_iid = cv.take<uint32_t>(ni);
+    const size_t o_key = cv.take<uint64_t>(ni);
     const size_t o_soff = cv.take<int64_t>((size_t)ni + 1);
-    const size_t o_fstart = cv.take<int64_t>(ni);
-    const size_t o_bs = cv.take<int64_t>((size_t)nb_scan);
+    const size_t o_status = cv.take<unsigned long long>((size_t)nb_build * 4);
     const size_t o_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_off = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_mids = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
@@ -505,8 +506,8 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     if ((st = ensure_arena(ws, cv.off)) != CSAW_OK) return st;
     if ((st = ensure_bitmaps(ws, (size_t)words * 2, s)) != CSAW_OK) return st;
     if ((st = ensure_streams(ws)) != CSAW_OK) return st;
-    const size_t host_bytes = sizeof(SampleCtl) + ((size_t)(L + 1) * ni + ni) * sizeof(int32_t) +
-                              ((size_t)ni + 1) * sizeof(int64_t) + 64;
+    const size_t host_bytes = sizeof(SampleCtl) + ((size_t)(L + 1) * ni + 2 * (size_t)ni) * sizeof(int32_t) +
+                              (2 * (size_t)ni + 1) * sizeof(int64_t) + 128;
     if ((st = ensure_pinned(ws, host_bytes)) != CSAW_OK) return st;
 
     char* A = ws->arena;
@@ -514,8 +515,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     int32_t* d_fan = (int32_t*)(A + o_fan);
     int32_t* d_bias = (int32_t*)(A + o_bias);
     int64_t* d_soff = (int64_t*)(A + o_soff);
-    int64_t* d_fstart = (int64_t*)(A + o_fstart);
-    int64_t* d_bs = (int64_t*)(A + o_bs);
+    unsigned long long* d_status = (unsigned long long*)(A + o_status);
     int32_t* d_cnt = (int32_t*)(A + o_cnt);
     int64_t* d_off = (int64_t*)(A + o_off);
     uint32_t* visited = ws->bitmaps;
@@ -527,7 +527,12 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     std::memcpy(h_fan, P.fan.data(), P.fan.size() * sizeof(int32_t));
     int32_t* h_bias = h_fan + P.fan.size();
     std::memcpy(h_bias, P.bias.data(), ni * sizeof(int32_t));
-    int64_t* h_soff = (int64_t*)align_up((size_t)(h_bias + ni), 8);
+    uint32_t* h_iid = (uint32_t*)(h_bias + ni);
+    for (int32_t i = 0; i < ni; ++i)
+        h_iid[i] = (uint32_t)(a->instance_ids ? a->instance_ids[i] : a->instance_base + (uint64_t)i);
+    uint64_t* h_key = (uint64_t*)align_up((size_t)(h_iid + ni), 8);
+    for (int32_t i = 0; i < ni; ++i) h_key[i] = a->rng_seeds ? a->rng_seeds[i] : a->rng_seed;
+    int64_t* h_soff = (int64_t*)(h_key + ni);
     std::memcpy(h_soff, a->seed_offsets, ((size_t)ni + 1) * sizeof(int64_t));
     SampleCtl* h_ctl = (SampleCtl*)align_up((size_t)(h_soff + ni + 1), 8);
     // every device step of the call, enqueued on stream s
@@ -535,20 +540,45 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)(sizeof(SampleCtl) / 4), s);
         HIP_OR_FAIL(hipMemcpyAsync(d_fan, h_fan, P.fan.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIP_OR_FAIL(hipMemcpyAsync(d_bias, h_bias, ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(A + o_iid, h_iid, ni * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(A + o_key, h_key, ni * sizeof(uint64_t), hipMemcpyHostToDevice, s));
         HIP_OR_FAIL(hipMemcpyAsync(d_soff, h_soff, ((size_t)ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
 
+        launch_fill_u32((uint32_t*)d_status, 0u, nb_build * 8, s);
+        FrontierBuild fb;
+        fb.g = g->dev();
+        fb.next4 = (uint4*)next;
+        fb.visited4 = (uint4*)visited;
+        fb.n4 = words / 4;
+        fb.nwp4 = nwp / 4;
+        fb.nb = nb_build;
+        fb.num_layers = L;
+        fb.num_instances = ni;
+        fb.bias = d_bias;
+        fb.cnt = d_cnt;
+        fb.off = d_off;
+        fb.mids = (int32_t*)(A + o_mids);
+        fb.hubs = (int32_t*)(A + o_hubs);
+        fb.offsets = out->offsets;
+        fb.ctl = ctl;
+        fb.status = d_status;
+        auto build = [&](int32_t l) {
+            fb.layer = l;
+            fb.fanout = d_fan + (size_t)l * ni;
+            fb.fv = (int32_t*)(A + o_fv[l]);
+            fb.fi = (int32_t*)(A + o_fi[l]);
+            launch_frontier_build(fb, s);
+        };
         {
             ProfScope ps("frontier_init", s);
             launch_mark_seeds(a->seeds, P.total_seeds, d_soff, ni, g->n, next, nwp, ctl, s);
-            launch_bitmap_compact(next, visited, words, nwp, d_bs, &ctl->fcount[0], (int32_t*)(A + o_fv[0]),
-                                  (int32_t*)(A + o_fi[0]), d_fstart, ni, s);
+            build(0);
         }
         SampleLayer p;
         p.g = g->dev();
         p.num_instances = ni;
-        p.k0 = (uint32_t)a->rng_seed;
-        p.k1 = (uint32_t)(a->rng_seed >> 32);
-        p.instance_base = a->instance_base;
+        p.inst_id = (const uint32_t*)(A + o_iid);
+        p.inst_key = (const uint64_t*)(A + o_key);
         p.bias = d_bias;
         p.cnt = d_cnt;
         p.off = d_off;
@@ -569,14 +599,6 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             p.fv = (const int32_t*)(A + o_fv[l]);
             p.fi = (const int32_t*)(A + o_fi[l]);
             const int64_t cap = P.fcap[l];
-            {
-                ProfScope ps("count", s);
-                launch_count(p, d_cnt, cap, s);
-            }
-            {
-                ProfScope ps("scan", s);
-                launch_scan_counts(d_cnt, &ctl->fcount[l], cap, d_bs, d_off, &ctl->total[l], s);
-            }
             // the three selection kernels touch disjoint outputs: run them side by side
             HIP_OR_FAIL(hipEventRecord(ws->fork, s));
             HIP_OR_FAIL(hipStreamWaitEvent(ws->aux[0], ws->fork, 0));
@@ -598,14 +620,9 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             HIP_OR_FAIL(hipEventRecord(ws->join[1], ws->aux[1]));
             HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join[0], 0));
             HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join[1], 0));
-            {
-                ProfScope ps("segments", s);
-                launch_segments(p, d_fstart, out->offsets, s);
-            }
             if (l + 1 < L && P.fcap[l + 1] > 0) {
-                ProfScope ps("frontier_compact", s);
-                launch_bitmap_compact(next, visited, words, nwp, d_bs, &ctl->fcount[l + 1],
-                                      (int32_t*)(A + o_fv[l + 1]), (int32_t*)(A + o_fi[l + 1]), d_fstart, ni, s);
+                ProfScope ps("frontier_build", s);
+                build(l + 1);
                 computed_layers = l + 2;
             }
         }
@@ -615,17 +632,13 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
                 launch_clear_visited((const int32_t*)(A + o_fv[l]), (const int32_t*)(A + o_fi[l]), &ctl->fcount[l],
                                      P.fcap[l], visited, nwp, s);
         }
-        if (out->offsets)
-            HIP_OR_FAIL(hipMemcpyAsync(out->offsets + (size_t)L * ni, &ctl->out_base[L], sizeof(int64_t),
-                                       hipMemcpyDeviceToDevice, s));
         HIP_OR_FAIL(hipGetLastError());
         HIP_OR_FAIL(hipMemcpyAsync(h_ctl, ctl, sizeof(SampleCtl), hipMemcpyDeviceToHost, s));
     return CSAW_OK;
     };
 
     if (graphs_enabled() && !g_prof.load(std::memory_order_relaxed)) {
-        std::vector<int64_t> key = {ni, L, words, nwp, P.total_seeds, out->edge_capacity, (int64_t)a->rng_seed,
-                                    (int64_t)a->instance_base, (int64_t)(intptr_t)a->seeds,
+        std::vector<int64_t> key = {ni, L, words, nwp, P.total_seeds, out->edge_capacity, (int64_t)(intptr_t)a->seeds,
                                     (int64_t)(intptr_t)out->src, (int64_t)(intptr_t)out->dst,
                                     (int64_t)(intptr_t)out->offsets, (int64_t)(intptr_t)ws->arena,
                                     (int64_t)(intptr_t)ws->bitmaps};
@@ -653,6 +666,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     HIP_OR_FAIL(hipStreamSynchronize(s));
     rel.clean = true;
     out->num_edges = L > 0 ? h_ctl->out_base[L] : 0;
+    if (h_ctl->lookback_stuck) return fail(CSAW_ERR_DEVICE, "frontier build did not complete its block chain");
     if (h_ctl->bad_seed) return fail(CSAW_ERR_INVALID_ARG, "a seed is outside [0, n)");
     if (h_ctl->unsupported)
         return fail(CSAW_ERR_UNSUPPORTED, "a drawn fanout exceeds %d", CSAW_MAX_FANOUT);
@@ -697,6 +711,7 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int
     p.length = a->length;
     p.k0 = (uint32_t)a->rng_seed;
     p.k1 = (uint32_t)(a->rng_seed >> 32);
+    p.walker_ids = a->walker_ids;
     p.paths = paths;
     p.steps = d_steps;
     p.bad_start = d_bad;

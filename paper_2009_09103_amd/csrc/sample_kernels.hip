@@ -109,76 +109,6 @@ __global__ void k_mark_seeds(const int32_t* __restrict__ seeds, int64_t num_seed
     }
 }
 
-// Bitmap compaction, pass 1: set bits per block of 256 x 4 words.
-__global__ void k_bm_count(const uint4* __restrict__ next4, int64_t n4, int64_t* __restrict__ blocksum) {
-    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    int64_t c = 0;
-    if (i < n4) c = popc4(next4[i]);
-    int64_t tot;
-    block_excl_scan_i64(c, &tot);
-    if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
-}
-
-// Exclusive scan of nb block sums in place by one 1024-thread block; each
-// thread owns a contiguous segment. *total receives the sum.
-__global__ void __launch_bounds__(1024) k_scan_blocksums(int64_t* __restrict__ bs, int64_t nb,
-                                                         const int64_t* __restrict__ nb_from_count,
-                                                         int64_t items_per_block, int64_t* total) {
-    if (nb_from_count) {
-        const int64_t items = *nb_from_count;
-        const int64_t used = (items + items_per_block - 1) / items_per_block;
-        if (used < nb) nb = used;
-    }
-    const int t = threadIdx.x;
-    const int64_t seg = (nb + 1023) / 1024;
-    const int64_t b0 = t * seg, b1 = (b0 + seg < nb) ? b0 + seg : nb;
-    int64_t s = 0;
-    for (int64_t b = b0; b < b1; ++b) s += bs[b];
-    int64_t tot;
-    int64_t run = block_excl_scan_i64<1024>(s, &tot);
-    for (int64_t b = b0; b < b1; ++b) {
-        const int64_t x = bs[b];
-        bs[b] = run;
-        run += x;
-    }
-    if (t == 0) *total = tot;
-}
-
-// Bitmap compaction, pass 2: emit (vertex, instance) for every set bit in
-// (instance, word, bit) order; visited |= next; next = 0; record where each
-// instance's entries start.
-__global__ void k_bm_emit(uint4* __restrict__ next4, uint4* __restrict__ visited4, int64_t n4,
-                          int64_t nwp4, const int64_t* __restrict__ blocksum, int32_t* __restrict__ fv,
-                          int32_t* __restrict__ fi, int64_t* __restrict__ fstart) {
-    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    uint4 w = make_uint4(0, 0, 0, 0);
-    if (i < n4) w = next4[i];
-    int64_t tot;
-    int64_t pos = blocksum[blockIdx.x] + block_excl_scan_i64(popc4(w), &tot);
-    if (i >= n4) return;
-    const int64_t inst = i / nwp4;
-    const int64_t local4 = i - inst * nwp4;
-    if (local4 == 0) fstart[inst] = pos;
-    if ((w.x | w.y | w.z | w.w) == 0) return;
-    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        uint32_t bits = ws[q];
-        const int32_t vbase = (int32_t)((local4 * 4 + q) * 32);
-        while (bits) {
-            const int b = __ffs(bits) - 1;
-            fv[pos] = vbase + b;
-            fi[pos] = (int32_t)inst;
-            ++pos;
-            bits &= bits - 1;
-        }
-    }
-    uint4 vis = visited4[i];
-    vis.x |= w.x; vis.y |= w.y; vis.z |= w.z; vis.w |= w.w;
-    visited4[i] = vis;
-    next4[i] = make_uint4(0, 0, 0, 0);
-}
-
 // ------------------------------------------------------------------ count
 // Weighted lists that need draws are routed by length: up to kWaveMaxD to the
 // wavefront kernel (list resident in a per-wave LDS tile), up to kMidMaxD to
@@ -199,74 +129,189 @@ __device__ __forceinline__ int32_t positive_count(const GraphDev& g, int32_t kin
     return kind == kEdgeWeight ? g.ppos_ew[v] : g.ppos_deg[v];
 }
 
-__global__ void k_count(SampleLayer p, int32_t* __restrict__ cnt) {
-    const int64_t fcount = p.ctl->fcount[p.layer];
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < fcount;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t v = p.fv[e];
-        const int32_t i = p.fi[e];
-        const int32_t k = p.fanout[i];
-        const int32_t kind = p.bias[i];
-        const int64_t d = p.g.rowptr[v + 1] - p.g.rowptr[v];
-        const int32_t P = positive_count(p.g, kind, v, d);
-        int32_t c;
-        if (k == 0 || P == 0) c = 0;
-        else if (k < 0 || k >= P) c = P;
-        else if (k > kMaxDrawFanout) {
-            p.ctl->unsupported = 1;
-            c = 0;
-        } else {
-            c = k;
-            const int route = route_of(kind, k, P, d);
-            if (route == kRouteMid) {
-                const unsigned long long h = atomicAdd(&p.ctl->nmid[p.layer], 1ull);
-                p.mids[h] = (int32_t)e;
-            } else if (route == kRouteHub) {
-                const unsigned long long h = atomicAdd(&p.ctl->nhub[p.layer], 1ull);
-                p.hubs[h] = (int32_t)e;
+__device__ __forceinline__ int32_t entry_count(const GraphDev& g, int32_t k, int32_t kind, int32_t v,
+                                               int32_t& route, SampleCtl* ctl) {
+    const int64_t d = g.rowptr[v + 1] - g.rowptr[v];
+    const int32_t P = positive_count(g, kind, v, d);
+    route = kRouteWave;
+    if (k == 0 || P == 0) return 0;
+    if (k < 0 || k >= P) return P;
+    if (k > kMaxDrawFanout) {
+        ctl->unsupported = 1;
+        return 0;
+    }
+    route = route_of(kind, k, P, d);
+    return k;
+}
+
+// Look-back status words: a 48-bit value, a valid bit and the build's epoch
+// in one 64-bit word, so a reader never sees a value without its flag.
+constexpr uint64_t kStatusValid = 1ull << 48;
+constexpr uint64_t kStatusMask = kStatusValid - 1;
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ uint64_t status_pack(int64_t v, uint32_t epoch) {
+    return ((uint64_t)v & kStatusMask) | kStatusValid | ((uint64_t)(epoch & 0x7FFF) << 49);
+}
+__device__ __forceinline__ bool status_ok(uint64_t w, uint32_t epoch) {
+    return (w & kStatusValid) && (w >> 49) == (epoch & 0x7FFF);
+}
+__device__ __forceinline__ void status_store(unsigned long long* p, uint64_t v) {
+    __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t status_load(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Next set bit of a 128-bit mask (lo, hi), or -1.
+__device__ __forceinline__ int32_t pop_bit(uint64_t& lo, uint64_t& hi) {
+    if (lo) {
+        const int32_t b = __ffsll((unsigned long long)lo) - 1;
+        lo &= lo - 1;
+        return b;
+    }
+    if (hi) {
+        const int32_t b = __ffsll((unsigned long long)hi) - 1;
+        hi &= hi - 1;
+        return 64 + b;
+    }
+    return -1;
+}
+
+// Frontier build of one layer, one pass: every block takes the next 1024
+// bitmap words in ticket order; each thread counts its set bits (entries)
+// and their edge counts min(k, P) (edges); a block scan plus a decoupled
+// look-back over the blocks before it give global positions; then the thread
+// writes its entries in (instance, vertex) order with count, edge offset and
+// route, sets visited |= next, clears next, and the first word of an instance
+// writes that instance's segment offset. The last block writes the layer's
+// totals and the output base of the next layer.
+__global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
+    __shared__ int64_t s_ticket, s_base_e, s_base_g;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_ticket = (int64_t)atomicAdd(&fb.ctl->tickets[fb.layer], 1ull);
+    __syncthreads();
+    const int64_t b = s_ticket;
+    const int64_t i4 = b * kBlock + tid;
+    const bool valid = i4 < fb.n4;
+    uint4 w = make_uint4(0, 0, 0, 0);
+    int64_t inst = 0, local4 = 0;
+    int32_t k = 0, kind = 0;
+    if (valid) {
+        w = fb.next4[i4];
+        inst = i4 / fb.nwp4;
+        local4 = i4 - inst * fb.nwp4;
+        k = fb.fanout[inst];
+        kind = fb.bias[inst];
+    }
+    const uint64_t lo0 = (uint64_t)w.x | ((uint64_t)w.y << 32);
+    const uint64_t hi0 = (uint64_t)w.z | ((uint64_t)w.w << 32);
+    const int32_t vbase = (int32_t)(local4 * 128);
+    const int64_t ne = __popcll(lo0) + __popcll(hi0);
+    int64_t ng = 0;
+    {
+        uint64_t lo = lo0, hi = hi0;
+        while (lo | hi) {  // four bits at a time so that their loads overlap
+            int32_t bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bv[t] = pop_bit(lo, hi);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int32_t route;
+                if (bv[t] >= 0) ng += entry_count(fb.g, k, kind, vbase + bv[t], route, fb.ctl);
             }
         }
-        cnt[e] = c;
     }
-}
-
-// scan of counts: per-block sums, then apply
-__global__ void k_scan_reduce(const int32_t* __restrict__ cnt, const int64_t* __restrict__ fcount_p,
-                              int64_t* __restrict__ blocksum) {
-    const int64_t fcount = *fcount_p;
-    const int64_t b0 = blockIdx.x * (int64_t)kScanItems;
-    if (b0 >= fcount) return;
-    int64_t s = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t e = b0 + threadIdx.x * 4 + q;
-        if (e < fcount) s += cnt[e];
+    int64_t tot_e, tot_g;
+    const int64_t ex_e = block_excl_scan_i64(ne, &tot_e);
+    const int64_t ex_g = block_excl_scan_i64(ng, &tot_g);
+    if (tid == 0) {
+        const uint32_t epoch = (uint32_t)fb.layer + 1;
+        unsigned long long* st = fb.status + 4 * b;
+        int64_t pe = 0, pg = 0;
+        if (b > 0) {
+            status_store(st + 0, status_pack(tot_e, epoch));
+            status_store(st + 1, status_pack(tot_g, epoch));
+            int64_t q = b - 1;
+            uint32_t spins = 0;
+            while (q >= 0) {
+                unsigned long long* sq = fb.status + 4 * q;
+                const uint64_t ie = status_load(sq + 2), ig = status_load(sq + 3);
+                if (status_ok(ie, epoch) && status_ok(ig, epoch)) {
+                    pe += (int64_t)(ie & kStatusMask);
+                    pg += (int64_t)(ig & kStatusMask);
+                    break;
+                }
+                const uint64_t ae = status_load(sq + 0), ag = status_load(sq + 1);
+                if (status_ok(ae, epoch) && status_ok(ag, epoch)) {
+                    pe += (int64_t)(ae & kStatusMask);
+                    pg += (int64_t)(ag & kStatusMask);
+                    --q;
+                    spins = 0;
+                    continue;
+                }
+                if (++spins > kSpinLimit) {  // never expected: report instead of hanging
+                    fb.ctl->lookback_stuck = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        status_store(st + 2, status_pack(pe + tot_e, epoch));
+        status_store(st + 3, status_pack(pg + tot_g, epoch));
+        s_base_e = pe;
+        s_base_g = pg;
     }
-    int64_t tot;
-    block_excl_scan_i64(s, &tot);
-    if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
-}
-
-__global__ void k_scan_apply(const int32_t* __restrict__ cnt, const int64_t* __restrict__ fcount_p,
-                             const int64_t* __restrict__ blocksum, int64_t* __restrict__ off) {
-    const int64_t fcount = *fcount_p;
-    const int64_t b0 = blockIdx.x * (int64_t)kScanItems;
-    if (b0 >= fcount) return;
-    int32_t c[4];
-    int64_t s = 0;
+    __syncthreads();
+    const int64_t out_base = fb.ctl->out_base[fb.layer];
+    int64_t pos = s_base_e + ex_e;
+    int64_t eoff = s_base_g + ex_g;
+    if (valid) {
+        if (local4 == 0 && fb.offsets && fb.layer < fb.num_layers)
+            fb.offsets[(int64_t)fb.layer * fb.num_instances + inst] = out_base + eoff;
+        if (lo0 | hi0) {
+            uint64_t lo = lo0, hi = hi0;
+            while (lo | hi) {
+                int32_t bv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t e = b0 + threadIdx.x * 4 + q;
-        c[q] = e < fcount ? cnt[e] : 0;
-        s += c[q];
+                for (int t = 0; t < 4; ++t) bv[t] = pop_bit(lo, hi);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (bv[t] < 0) continue;
+                    const int32_t v = vbase + bv[t];
+                    int32_t route;
+                    const int32_t c = entry_count(fb.g, k, kind, v, route, fb.ctl);
+                    fb.fv[pos] = v;
+                    fb.fi[pos] = (int32_t)inst;
+                    fb.cnt[pos] = c;
+                    fb.off[pos] = eoff;
+                    if (route == kRouteMid) fb.mids[atomicAdd(&fb.ctl->nmid[fb.layer], 1ull)] = (int32_t)pos;
+                    else if (route == kRouteHub) fb.hubs[atomicAdd(&fb.ctl->nhub[fb.layer], 1ull)] = (int32_t)pos;
+                    ++pos;
+                    eoff += c;
+                }
+            }
+            uint4 vis = fb.visited4[i4];
+            vis.x |= w.x; vis.y |= w.y; vis.z |= w.z; vis.w |= w.w;
+            fb.visited4[i4] = vis;
+            fb.next4[i4] = make_uint4(0, 0, 0, 0);
+        }
     }
-    int64_t tot;
-    int64_t run = blocksum[blockIdx.x] + block_excl_scan_i64(s, &tot);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t e = b0 + threadIdx.x * 4 + q;
-        if (e < fcount) off[e] = run;
-        run += c[q];
+    if (b == fb.nb - 1) {  // last block: totals, and the bases of the layers after this one
+        const int64_t te = s_base_e + tot_e, tg = s_base_g + tot_g;
+        const int64_t ob = out_base + tg;
+        if (tid == 0) {
+            fb.ctl->fcount[fb.layer] = te;
+            fb.ctl->total[fb.layer] = tg;
+            for (int j = fb.layer + 1; j <= fb.num_layers; ++j) fb.ctl->out_base[j] = ob;
+        }
+        if (fb.offsets) {
+            const int64_t ni = fb.num_instances;
+            const int64_t first = fb.nwp4 > 0 ? fb.layer + 1 : fb.layer;
+            for (int64_t j = first; j < fb.num_layers; ++j)
+                for (int64_t i = tid; i < ni; i += kBlock) fb.offsets[j * ni + i] = (j == fb.layer ? out_base : ob);
+            if (tid == 0) fb.offsets[(int64_t)fb.num_layers * ni] = ob;
+        }
     }
 }
 
@@ -501,6 +546,11 @@ __device__ __forceinline__ bool load_entry(const SampleLayer& p, int64_t e, int6
     return true;
 }
 
+__device__ __forceinline__ Key inst_key(const SampleLayer& p, int32_t inst) {
+    const uint64_t seed = p.inst_key[inst];
+    return Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
+}
+
 __device__ __forceinline__ void emit_slots(const SampleLayer& p, const EntryInfo& E, int64_t pos) {
     const int lane = lane_id();
     if (lane < E.k) {
@@ -568,8 +618,9 @@ __device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, 
     }
 
     // ---- k < P <= d: draw k distinct candidates (k <= kMaxDrawFanout)
-    const Key key{p.k0, p.k1};
-    const uint32_t c0 = (uint32_t)(p.instance_base + (uint64_t)E.inst);
+    const uint64_t seed = p.inst_key[E.inst];
+    const Key key{(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const uint32_t c0 = p.inst_id[E.inst];
     const uint32_t c1 = (uint32_t)p.layer;
     const uint32_t c2 = (uint32_t)E.v;
     int64_t pos;
@@ -666,7 +717,7 @@ __global__ void __launch_bounds__(kMidThreads) k_select_mid(SampleLayer p, const
                 if (lane == 0) p.ctl->overflow = 1;
             } else {
                 const CoarsePool pl{C, ng, 16, d, w, wt};
-                const int64_t pos = draw_slots(Key{p.k0, p.k1}, (uint32_t)(p.instance_base + (uint64_t)E.inst),
+                const int64_t pos = draw_slots(inst_key(p, E.inst), p.inst_id[E.inst],
                                                (uint32_t)p.layer, (uint32_t)E.v, E.k, C[ng],
                                                [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
                                                    coarse_search<true>(pl, r, m, Sm, bm);
@@ -723,7 +774,7 @@ __global__ void __launch_bounds__(kHubThreads) k_select_hub(SampleLayer p, const
                 if (lane == 0) p.ctl->overflow = 1;
             } else {
                 const CoarsePool pl{C, ng, g, d, w, nullptr};
-                const int64_t pos = draw_slots(Key{p.k0, p.k1}, (uint32_t)(p.instance_base + (uint64_t)E.inst),
+                const int64_t pos = draw_slots(inst_key(p, E.inst), p.inst_id[E.inst],
                                                (uint32_t)p.layer, (uint32_t)E.v, E.k, C[ng],
                                                [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
                                                    coarse_search<false>(pl, r, m, Sm, bm);
@@ -733,20 +784,6 @@ __global__ void __launch_bounds__(kHubThreads) k_select_hub(SampleLayer p, const
         }
         __syncthreads();
     }
-}
-
-__global__ void k_segments(SampleLayer p, const int64_t* __restrict__ fstart, int64_t* __restrict__ offsets) {
-    const int64_t fcount = p.ctl->fcount[p.layer];
-    const int64_t total = p.ctl->total[p.layer];
-    const int64_t base = p.ctl->out_base[p.layer];
-    if (offsets) {
-        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.num_instances;
-             i += (int64_t)gridDim.x * blockDim.x) {
-            const int64_t fs = fstart[i];
-            offsets[(int64_t)p.layer * p.num_instances + i] = base + (fs < fcount ? p.off[fs] : total);
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.ctl->out_base[p.layer + 1] = base + total;
 }
 
 __global__ void k_clear_visited(const int32_t* __restrict__ fv, const int32_t* __restrict__ fi,
@@ -787,39 +824,14 @@ void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* s
                        num_seeds, seed_offsets, ni, n, next, nwp, ctl);
 }
 
-void launch_bitmap_compact(uint32_t* next, uint32_t* visited, int64_t words, int64_t nwp,
-                           int64_t* blocksum, int64_t* fcount_out, int32_t* fv, int32_t* fi,
-                           int64_t* fstart, int32_t ni, hipStream_t s) {
-    (void)ni;
+int64_t frontier_build_blocks(int64_t words) {
     const int64_t n4 = words / 4;
     const int64_t nb = (n4 + kBlock - 1) / kBlock;
-    if (nb <= 0) {
-        launch_fill_u32((uint32_t*)fcount_out, 0u, 2, s);
-        return;
-    }
-    hipLaunchKernelGGL(k_bm_count, dim3((unsigned)nb), dim3(kBlock), 0, s, (const uint4*)next, n4, blocksum);
-    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(1024), 0, s, blocksum, nb, (const int64_t*)nullptr,
-                       (int64_t)1, fcount_out);
-    hipLaunchKernelGGL(k_bm_emit, dim3((unsigned)nb), dim3(kBlock), 0, s, (uint4*)next, (uint4*)visited, n4,
-                       nwp / 4, blocksum, fv, fi, fstart);
+    return nb > 0 ? nb : 1;
 }
 
-void launch_count(const SampleLayer& p, int32_t* cnt, int64_t cap_entries, hipStream_t s) {
-    if (cap_entries <= 0) return;
-    hipLaunchKernelGGL(k_count, dim3(grid_for(cap_entries, kBlock, 16384)), dim3(kBlock), 0, s, p, cnt);
-}
-
-void launch_scan_counts(const int32_t* cnt, const int64_t* fcount, int64_t cap_entries, int64_t* blocksum,
-                        int64_t* off, int64_t* total_out, hipStream_t s) {
-    const int64_t nb = (cap_entries + kScanItems - 1) / kScanItems;
-    if (nb <= 0) {
-        launch_fill_u32((uint32_t*)total_out, 0u, 2, s);
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, fcount, blocksum);
-    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(1024), 0, s, blocksum, nb, fcount, (int64_t)kScanItems,
-                       total_out);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, fcount, blocksum, off);
+void launch_frontier_build(const FrontierBuild& fb, hipStream_t s) {
+    hipLaunchKernelGGL(k_frontier_build, dim3((unsigned)fb.nb), dim3(kBlock), 0, s, fb);
 }
 
 void launch_select(const SampleLayer& p, int grid, hipStream_t s) {
@@ -832,11 +844,6 @@ void launch_select_mid(const SampleLayer& p, int grid, hipStream_t s) {
 
 void launch_select_hub(const SampleLayer& p, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_select_hub, dim3(grid), dim3(kHubThreads), 0, s, p, (const int32_t*)p.hubs);
-}
-
-void launch_segments(const SampleLayer& p, const int64_t* fstart, int64_t* offsets, hipStream_t s) {
-    hipLaunchKernelGGL(k_segments, dim3(grid_for(p.num_instances, kBlock, 4096)), dim3(kBlock), 0, s, p,
-                       fstart, offsets);
 }
 
 void launch_clear_visited(const int32_t* fv, const int32_t* fi, const int64_t* fcount, int64_t cap_entries,

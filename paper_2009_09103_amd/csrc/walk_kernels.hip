@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
                 for (int64_t q = 0; q < L1; ++q) path[q] = -1;
             } else {
                 path[0] = v;
-                const uint32_t c0 = (uint32_t)(p.walker_base + (uint64_t)w);
+                const uint32_t c0 = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
                 for (; s < p.length; ++s) {
                     const int64_t beg = p.g.rowptr[v];
                     const int64_t d = p.g.rowptr[v + 1] - beg;
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
             continue;
         }
         if (lane == 0) path[0] = v;
-        const uint32_t c0 = (uint32_t)(p.walker_base + (uint64_t)w);
+        const uint32_t c0 = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
         sb.t = -1;
         sb.tb = sb.te = 0;
         int32_t s = 0;

@@ -1,0 +1,111 @@
+"""The request server: continuous batching over a resident graph. Every
+request's result equals the same request run alone (and the oracle), in a
+mix, under a tight memory budget and with several executor streams."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_09103_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2009_09103_amd import csaw
+    rp, col = inputs.rmat_csr(15, 16 << 15, 31)
+    ew = inputs.dst_outdeg_weights(rp, col)
+    g = csaw.Graph(rp, col, ew)
+    trace = inputs.request_trace(rp, col, 60, qps=1000.0, trace_rng=7)
+    for r in trace:   # smaller than the served workload, same mix
+        if r["kind"] == "sample":
+            r["seeds"] = r["seeds"][:300]
+        else:
+            r["starts"] = r["starts"][:2000]
+    return csaw, rp, col, ew, g, trace
+
+
+def submit(srv, r):
+    if r["kind"] == "sample":
+        return srv.submit_sample(r["seeds"], r["fanouts"], r["bias"], rng_seed=r["rng_seed"], request_id=r["id"])
+    return srv.submit_walk(r["starts"], r["length"], r["bias"], rng_seed=r["rng_seed"], request_id=r["id"])
+
+
+def check_alone(csaw, g, rp, col, ew, r, res, with_oracle):
+    assert res.status == 0
+    if r["kind"] == "sample":
+        alone = g.sample(np.array([0, len(r["seeds"])]), r["seeds"], r["fanouts"], r["bias"],
+                         rng_seed=r["rng_seed"], instance_base=r["id"])
+        np.testing.assert_array_equal(res.src, alone.src.cpu().numpy())
+        np.testing.assert_array_equal(res.dst, alone.dst.cpu().numpy())
+        np.testing.assert_array_equal(res.layer_offsets, alone.offsets.cpu().numpy())
+        if with_oracle:
+            ref = oracle.sample(rp, col, ew, np.array([0, len(r["seeds"])]), r["seeds"], r["fanouts"],
+                                bias_kind=r["bias"], rng_seed=r["rng_seed"], instance_base=r["id"])
+            np.testing.assert_array_equal(res.dst, ref.dst)
+    else:
+        paths, steps = g.walk(r["starts"], r["length"], r["bias"], rng_seed=r["rng_seed"], walker_base=r["id"])
+        np.testing.assert_array_equal(res.paths, paths.cpu().numpy())
+        assert res.steps == steps
+        if with_oracle:
+            ref, _, _ = oracle.walk(rp, col, ew, r["starts"], r["length"], bias_kind=r["bias"],
+                                    rng_seed=r["rng_seed"], walker_base=r["id"])
+            np.testing.assert_array_equal(res.paths, ref)
+
+
+@pytest.mark.parametrize("streams,budget", [(2, 0), (3, 64 << 20), (1, 0)])
+def test_mix_equals_alone(setup, streams, budget):
+    csaw, rp, col, ew, g, trace = setup
+    say("server streams=%d budget=%d, %d requests" % (streams, budget, len(trace)))
+    srv = csaw.Server(g, memory_budget_bytes=budget, num_streams=streams, max_batch=64)
+    tickets = [submit(srv, r) for r in trace]
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for k, (r, res) in enumerate(zip(trace, results)):
+        check_alone(csaw, g, rp, col, ew, r, res, with_oracle=(k % 10 == 0))
+        assert res.total_us >= res.queued_us >= 0
+
+
+def test_submit_errors_and_poll(setup):
+    csaw, rp, col, ew, g, trace = setup
+    say("server errors")
+    srv = csaw.Server(g, memory_budget_bytes=1 << 20, num_streams=1)
+    with pytest.raises(csaw.CsawError) as ei:
+        srv.submit_sample(np.array([len(rp) + 5], dtype=np.int32), [5])        # vertex out of range
+    assert ei.value.status == 1
+    with pytest.raises(csaw.CsawError) as ei:
+        srv.submit_walk(np.zeros(1 << 20, dtype=np.int32), 80)                  # alone exceeds the budget
+    assert ei.value.status == 2
+    t = srv.submit_walk(trace[1]["starts"][:10], 5, 1, rng_seed=3, request_id=9)
+    res = srv.wait(t)
+    assert res.status == 0 and res.paths.shape == (10, 6)
+    with pytest.raises(csaw.CsawError):
+        srv.poll(t)                                                              # already handed over
+    srv.close()
+
+
+def test_queue_full_reports_busy(setup):
+    csaw, rp, col, ew, g, trace = setup
+    say("server busy")
+    srv = csaw.Server(g, num_streams=1, queue_capacity=2)
+    starts = inputs.walker_starts(rp, col, 20000, 1)
+    tickets, busy = [], 0
+    for i in range(50):
+        try:
+            tickets.append(srv.submit_walk(starts, 60, 1, rng_seed=i, request_id=i))
+        except csaw.CsawError as e:
+            assert e.status == 4
+            busy += 1
+    assert busy > 0
+    for t in tickets:
+        assert srv.wait(t).status == 0
+    srv.close()
