@@ -33,30 +33,40 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def frontier_bytes(rowptr, offs, seeds, src, dst, offsets, fanouts, weighted):
-    """Algorithmic bytes of the select launches of one call, from the graph
-    and the call's own output: per expanded frontier vertex 8 (frontier entry)
-    + 16 (row-offset pair) + 4*deg if the bias reads a weight array, plus 12
-    per emitted edge (neighbor id read + edge written)."""
+WAVE_MAX_D = 1024  # longer weighted lists that need draws take the long-list path
+
+
+def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted):
+    """Algorithmic bytes of one call, per kernel, from the graph and the
+    call's own output. Per frontier vertex: 8 (frontier entry) + 16 (row-offset
+    pair) bytes of metadata. Lists drawn by the wavefront kernel (select_wave)
+    add 4*deg if the bias reads a weight array; long weighted lists read their
+    4*deg weight bytes in chunk_prefix, which writes one 8-byte group prefix
+    per 16 weights that select_big reads back. Every emitted edge costs 12
+    (neighbor id read + edge written) in the kernel that draws it."""
     deg = np.diff(rowptr)
     L = len(fanouts)
-    ni = len(offs) - 1
-    assert ni == 1
     visited = np.unique(seeds)
     frontier = visited
-    per_layer = []
+    out = {"select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
     for l in range(L):
         a, b = offsets[l], offsets[l + 1]
-        e = b - a
-        byts = frontier.size * 24.0 + 12.0 * e
-        if weighted:
-            byts += 4.0 * float(deg[frontier].sum())
-        per_layer.append(byts)
+        k = int(fanouts[l])
+        d = deg[frontier].astype(np.float64)
+        P = ppos[frontier] if weighted else deg[frontier]
+        c = np.where((k == 0) | (P == 0), 0, np.where((k < 0) | (k >= P), P, k)).astype(np.float64)
+        assert int(c.sum()) == b - a
+        long_ = weighted & (k > 0) & (k < P) & (deg[frontier] > WAVE_MAX_D)
+        w = ~long_
+        out["select_wave"] += 24.0 * w.sum() + 12.0 * c[w].sum() + (4.0 * d[w].sum() if weighted else 0.0)
+        groups = np.ceil(d[long_] / 16.0)
+        out["chunk_prefix"] += 4.0 * d[long_].sum() + 8.0 * groups.sum() + 8.0 * np.ceil(d[long_] / 1024.0).sum()
+        out["select_big"] += 24.0 * long_.sum() + 8.0 * groups.sum() + 12.0 * c[long_].sum()
         if l + 1 < L:
             nxt = np.setdiff1d(np.unique(dst[a:b]), visited, assume_unique=True)
             visited = np.union1d(visited, nxt)
             frontier = nxt
-    return per_layer
+    return out
 
 
 def cpu_baseline(rp, col, offs, seeds, fanouts, bias, budget_s=20.0):
@@ -103,12 +113,15 @@ def bench_degree_biased(args):
     rng_seeds = list(rec["rng_seeds"])
 
     # per-seed edge counts and algorithmic bytes (deterministic per seed)
+    deg = np.diff(rp)
+    ppos = np.add.reduceat(np.append((deg[col] > 0).astype(np.int64), 0), rp[:-1])
+    ppos[deg == 0] = 0
     edges_of, bytes_of = {}, {}
     for s in rng_seeds:
         r = g.sample(offs, seeds_d, fan, bias, rng_seed=s, out=(src, dst, offsets))
         o = offsets.cpu().numpy()
         edges_of[s] = r.num_edges
-        bytes_of[s] = frontier_bytes(rp, offs, seeds, None, dst[:r.num_edges].cpu().numpy(), o, fan, True)
+        bytes_of[s] = path_bytes(rp, ppos, seeds, dst[:r.num_edges].cpu().numpy(), o, fan, True)
         log("seed %d: %d edges" % (s, r.num_edges))
 
     for i in range(args.warmup):
@@ -127,18 +140,23 @@ def bench_degree_biased(args):
     # kernel times from HIP events on the call's stream (separate pass)
     csaw.profile_reset()
     csaw.profile_enable(True)
-    alg = 0.0
+    alg = {"select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
     for i in range(args.steps):
         s = rng_seeds[i % 3]
         g.sample(offs, seeds_d, fan, bias, rng_seed=s, out=(src, dst, offsets))
-        alg += sum(bytes_of[s])
+        for k in alg:
+            alg[k] += bytes_of[s][k]
     torch.cuda.synchronize()
-    sel_ms, sel_n = csaw.profile_read("select_wave")
-    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_wave", "select_mid", "select_hub",
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_wave", "chunk_prefix", "select_big",
                                                 "frontier_build", "visited_clear")}
     csaw.profile_enable(False)
     csaw.profile_reset()
-    achieved = alg / (sel_ms / 1e3) / 1e9 if sel_ms > 0 else 0.0
+    sel_ms, sel_n = times["select_wave"]
+    achieved = alg["select_wave"] / (sel_ms / 1e3) / 1e9 if sel_ms > 0 else 0.0
+    per_kernel = {k: {"alg_bytes_per_step": alg[k] / args.steps, "ms_per_step": times[k][0] / args.steps,
+                      "GB_per_s": alg[k] / (times[k][0] / 1e3) / 1e9 if times[k][0] > 0 else 0.0}
+                  for k in alg}
+    step_bytes = sum(alg.values()) / args.steps
     log("kernel ms per step: " + ", ".join("%s %.3f" % (k, v[0] / args.steps) for k, v in times.items()))
 
     line = {
@@ -162,13 +180,172 @@ def bench_degree_biased(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "select_wave (k_select)", "launches": sel_n,
                      "avg_launch_us": sel_ms / max(sel_n, 1) * 1e3,
-                     "alg_bytes_per_launch": alg / max(sel_n, 1)},
+                     "alg_bytes_per_launch": alg["select_wave"] / max(sel_n, 1)},
+        "roofline_step": {"alg_bytes": step_bytes, "achieved": step_bytes / (dt / args.steps) / 1e9,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": step_bytes / (dt / args.steps) / 1e9 / HBM_PEAK_GBS},
+        "kernels": per_kernel,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in times.items()},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(rp, col, offs, seeds, rec["fanouts"], 2)
     return line
+
+
+def bench_batched(args):
+    """4,096 uneven instances in one csaw_sample call (the launch sequence is
+    replayed from a captured graph) against the same instances as 4,096 plain
+    calls; both outputs are identical by construction of the draws."""
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    rec = inputs.BATCHED
+    log("generating R-MAT %d graph" % rec["scale"])
+    rp, col = inputs.graph_for(rec)
+    offs, seeds, fanouts, bias = inputs.batched_instances(rp, col, rec["num_instances"], rec["seed_rng"])
+    g = csaw.Graph(rp, col)
+    dev = g.device
+    ni = len(offs) - 1
+    seeds_d = torch.from_numpy(seeds).to(dev)
+    cap = g.sample_bound(offs, fanouts, bias)
+    src = torch.empty(cap, dtype=torch.int32, device=dev)
+    dst = torch.empty(cap, dtype=torch.int32, device=dev)
+    offsets = torch.empty(fanouts.shape[1] * ni + 1, dtype=torch.int64, device=dev)
+    r = g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+    edges = r.num_edges
+    for _ in range(args.warmup):
+        g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # plain: one call per instance (same ids, same seed)
+    per = []
+    for i in range(ni):
+        so = np.array([0, offs[i + 1] - offs[i]], dtype=np.int64)
+        per.append((so, seeds_d[offs[i]:offs[i + 1]], fanouts[i], int(bias[i])))
+    pcap = max(g.sample_bound(so, f, b) for so, _, f, b in per)
+    psrc = torch.empty(max(pcap, 1), dtype=torch.int32, device=dev)
+    pdst = torch.empty(max(pcap, 1), dtype=torch.int32, device=dev)
+    poff = torch.empty(fanouts.shape[1] + 1, dtype=torch.int64, device=dev)
+    plain_edges = 0
+    for i, (so, sd, f, b) in enumerate(per[:64]):
+        g.sample(so, sd, f, b, rng_seed=1, instance_base=i, out=(psrc, pdst, poff))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (so, sd, f, b) in enumerate(per):
+        plain_edges += g.sample(so, sd, f, b, rng_seed=1, instance_base=i, out=(psrc, pdst, poff)).num_edges
+    torch.cuda.synchronize()
+    pdt = time.perf_counter() - t0
+    assert plain_edges == edges
+    return {
+        "metric": "sampled edges/sec (SEPS), batched multi-instance vs plain per-instance calls",
+        "value": edges / dt, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": rec["name"], "instances": ni, "seeds": int(len(seeds)),
+                   "edges_per_step": int(edges)},
+        "plain_calls": {"value": plain_edges / pdt, "calls": ni, "seconds": pdt},
+        "batched_over_plain": (edges / dt) / (plain_edges / pdt),
+    }
+
+
+def bench_served(args):
+    """Poisson trace of mixed requests against the request server on R-MAT
+    26 (edge weights = destination out-degree), swept over QPS; the same trace
+    through a one-stream, one-request-at-a-time server is the plain path."""
+    import threading
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    rec = inputs.SERVED
+    scale = args.served_scale or rec["scale"]
+    log("generating R-MAT %d graph" % scale)
+    t0 = time.perf_counter()
+    rp, col = inputs.graph_for(rec, scale=scale, num_edges=16 << scale)
+    ew = inputs.dst_outdeg_weights(rp, col)
+    g = csaw.Graph(rp, col, ew)
+    log("graph n=%d m=%d ready in %.1fs" % (len(rp) - 1, len(col), time.perf_counter() - t0))
+    points = []
+    for qps in args.qps:
+        trace = inputs.request_trace(rp, col, args.requests, qps, rec["trace_rng"], rec["sample_fraction"])
+        row = {"qps": qps}
+        for name, kw in (("served", dict(num_streams=3, max_batch=256)), ("plain", dict(num_streams=1, max_batch=1))):
+            srv = csaw.Server(g, **kw)
+            tickets = [None] * len(trace)
+            start = time.perf_counter()
+
+            def client():
+                for k, r in enumerate(trace):
+                    delay = r["arrival_s"] - (time.perf_counter() - start)
+                    if delay > 0:
+                        time.sleep(delay)
+                    if r["kind"] == "sample":
+                        tickets[k] = srv.submit_sample(r["seeds"], r["fanouts"], r["bias"], rng_seed=r["rng_seed"],
+                                                       request_id=r["id"])
+                    else:
+                        tickets[k] = srv.submit_walk(r["starts"], r["length"], r["bias"], rng_seed=r["rng_seed"],
+                                                     request_id=r["id"])
+            th = threading.Thread(target=client)
+            th.start()
+            th.join()
+            lat, edges = [], 0
+            for t in tickets:
+                res = srv.wait(t)
+                assert res.status == 0
+                lat.append(res.total_us)
+                edges += res.num_edges
+            wall = time.perf_counter() - start
+            srv.close()
+            lat = np.array(lat) / 1e3
+            row[name] = {"seps": edges / wall, "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "wall_s": wall, "edges": int(edges)}
+            log("qps %g %s: %.3g SEPS, p50 %.1f ms, p99 %.1f ms" % (qps, name, edges / wall, row[name]["p50_ms"],
+                                                                 row[name]["p99_ms"]))
+        points.append(row)
+    best = max(points, key=lambda r: r["served"]["seps"])
+    return {
+        "metric": "served SEPS and p50/p99 latency",
+        "value": best["served"]["seps"], "unit": "sampled edges/s", "n_gpus": 1, "steps": len(points),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": rec["name"], "scale": scale, "requests_per_point": args.requests},
+        "points": points,
+    }
+
+
+def bench_node2vec(args):
+    """node2vec walks on symmetrised R-MAT 24 (or a smaller scale) with
+    weights {1, 2, 4}, length 80; walkers strided over the 2^20 workload."""
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    rec = inputs.NODE2VEC
+    scale = args.n2v_scale or rec["scale"]
+    log("generating symmetrised R-MAT %d graph" % scale)
+    rp, col = inputs.graph_for(rec, scale=scale, num_edges=16 << scale)
+    g = csaw.Graph(rp, col)
+    starts_all = inputs.walker_starts(rp, col, rec["num_walkers"], rec["start_rng"])
+    ids = np.arange(0, rec["num_walkers"], args.n2v_stride, dtype=np.uint64)
+    starts = torch.from_numpy(starts_all[ids.astype(np.int64)]).to(g.device)
+    paths, steps = g.walk(starts, rec["length"], csaw.NODE2VEC, rng_seed=1, node2vec=rec["node2vec"], walker_ids=ids)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, steps = g.walk(starts, rec["length"], csaw.NODE2VEC, rng_seed=1, node2vec=rec["node2vec"],
+                          walker_ids=ids, paths=paths)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    return {
+        "metric": "sampled edges/sec (walk steps/s), node2vec",
+        "value": steps / dt, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": rec["name"], "scale": scale, "walkers": int(len(ids)), "length": rec["length"]},
+    }
 
 
 def main():
@@ -178,6 +355,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="degree_biased")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--qps", type=float, nargs="*", default=[50.0, 200.0, 800.0])
+    ap.add_argument("--requests", type=int, default=500)
+    ap.add_argument("--served-scale", type=int, default=0)
+    ap.add_argument("--n2v-scale", type=int, default=0)
+    ap.add_argument("--n2v-stride", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole path on a single MI355X "
@@ -191,6 +373,12 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "degree_biased":
         line = bench_degree_biased(args)
+    elif args.workload == "batched":
+        line = bench_batched(args)
+    elif args.workload == "served":
+        line = bench_served(args)
+    elif args.workload == "node2vec":
+        line = bench_node2vec(args)
     else:
         print("unknown workload %s" % args.workload, file=sys.stderr)
         sys.exit(2)

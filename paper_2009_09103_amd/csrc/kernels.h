@@ -10,6 +10,8 @@ constexpr int kMaxLayers = 16;
 constexpr int kMaxDrawFanout = 64;   // slots of one wave
 constexpr int kRounds = 8;           // repeated-sampling rounds
 constexpr int kScanItems = 1024;     // items per scan block (256 threads x 4)
+constexpr int kChunk = 1024;         // weights per chunk of a long list
+constexpr int kChunkGroups = 64;     // 16-weight groups per chunk
 
 enum BiasKind : int32_t { kUniform = 0, kEdgeWeight = 1, kNeighborDegree = 2, kNode2vec = 3 };
 
@@ -30,8 +32,8 @@ struct SampleCtl {
     int64_t total[kMaxLayers];         // edges per layer
     int64_t out_base[kMaxLayers + 1];  // first edge of each layer
     unsigned long long tickets[kMaxLayers];  // block order of the frontier builds
-    unsigned long long nmid[kMaxLayers];  // mid-kernel entries per layer
-    unsigned long long nhub[kMaxLayers];  // hub-kernel entries per layer
+    unsigned long long nbig[kMaxLayers];    // long weighted lists per layer
+    unsigned long long nchunk[kMaxLayers];  // their 1024-weight chunks (may exceed chunk_cap)
     int32_t bad_seed;
     int32_t overflow;
     int32_t unsupported;
@@ -56,8 +58,10 @@ struct FrontierBuild {
     int32_t* fi;
     int32_t* cnt;
     int64_t* off;
-    int32_t* mids;
-    int32_t* hubs;
+    int32_t* bigs;                   // long-list entries (frontier positions)
+    int64_t* big_cb;                 // first chunk of each long list
+    uint64_t* chunks;                // [chunk_cap] chunk records
+    int64_t chunk_cap;
     int64_t* offsets;                // [L*ni+1] or null
     SampleCtl* ctl;
     unsigned long long* status;      // [4 * nb] look-back words
@@ -76,8 +80,11 @@ struct SampleLayer {
     const int32_t* fi;               // frontier instance indices
     const int32_t* cnt;              // per-entry edge count
     const int64_t* off;              // per-entry exclusive offset
-    int32_t* mids;                   // entries routed to the mid kernel
-    int32_t* hubs;                   // entries routed to the hub kernel
+    const int32_t* bigs;             // long weighted lists (frontier positions)
+    const int64_t* big_cb;           // first chunk of each long list
+    const uint64_t* chunks;          // chunk records: start | (len-1) << 40 | degree-bias bit 50
+    uint64_t* G;                     // [chunk_cap * 64] group prefixes within each chunk
+    int64_t chunk_cap;
     SampleCtl* ctl;
     int32_t* src;
     int32_t* dst;
@@ -94,8 +101,8 @@ void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* s
 int64_t frontier_build_blocks(int64_t words);
 void launch_frontier_build(const FrontierBuild& fb, hipStream_t s);
 void launch_select(const SampleLayer& p, int grid, hipStream_t s);
-void launch_select_mid(const SampleLayer& p, int grid, hipStream_t s);
-void launch_select_hub(const SampleLayer& p, int grid, hipStream_t s);
+void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s);
+void launch_select_big(const SampleLayer& p, int grid, hipStream_t s);
 void launch_clear_visited(const int32_t* fv, const int32_t* fi, const int64_t* fcount,
                           int64_t cap_entries, uint32_t* visited, int64_t nwp, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);

@@ -84,10 +84,15 @@ struct Workspace {
     size_t bitmap_words = 0;
     char* pinned = nullptr;
     size_t pinned_cap = 0;
-    // side streams for the mid/hub selection kernels, forked from and joined
-    // back into the caller's stream with events (default priority)
-    hipStream_t aux[2] = {nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    // side stream for the long-list kernels, forked from and joined back into
+    // the caller's stream with events (default priority)
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    // long-list scratch: chunk records and G rows (kChunkGroups u64 per chunk);
+    // chunk_hint is the largest per-layer chunk count seen by this workspace
+    uint64_t* chunkbuf = nullptr;
+    int64_t chunk_cap = 0;
+    int64_t chunk_hint = 0;
     // captured launch sequences of csaw_sample, keyed by every value they bake in
     hipStream_t capture = nullptr;
     std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
@@ -112,11 +117,10 @@ struct Workspace {
     ~Workspace() {
         drop_graphs();
         if (capture) (void)hipStreamDestroy(capture);
-        for (int i = 0; i < 2; ++i) {
-            if (aux[i]) (void)hipStreamDestroy(aux[i]);
-            if (join[i]) (void)hipEventDestroy(join[i]);
-        }
+        if (aux) (void)hipStreamDestroy(aux);
+        if (join) (void)hipEventDestroy(join);
         if (fork) (void)hipEventDestroy(fork);
+        if (chunkbuf) (void)hipFree(chunkbuf);
         if (arena) (void)hipFree(arena);
         if (bitmaps) (void)hipFree(bitmaps);
         if (pinned) (void)hipHostFree(pinned);
@@ -124,6 +128,8 @@ struct Workspace {
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr int64_t kInitialChunks = 4096;  // first long-list scratch of a workspace (2.1 MB)
 
 // CSAW_GRAPH=0 in the environment turns off launch-sequence replay.
 bool graphs_enabled() {
@@ -222,6 +228,7 @@ csaw_status ensure_arena(Workspace* w, size_t bytes) {
 
 csaw_status ensure_pinned(Workspace* w, size_t bytes) {
     if (w->pinned_cap >= bytes) return CSAW_OK;
+    w->drop_graphs();  // captured copies name the old staging buffer
     if (w->pinned) HIP_OR_FAIL(hipHostFree(w->pinned));
     w->pinned = nullptr;
     w->pinned_cap = 0;
@@ -233,12 +240,21 @@ csaw_status ensure_pinned(Workspace* w, size_t bytes) {
 
 csaw_status ensure_streams(Workspace* w) {
     if (w->fork) return CSAW_OK;
-    for (int i = 0; i < 2; ++i) {
-        HIP_OR_FAIL(hipStreamCreateWithFlags(&w->aux[i], hipStreamNonBlocking));
-        HIP_OR_FAIL(hipEventCreateWithFlags(&w->join[i], hipEventDisableTiming));
-    }
+    HIP_OR_FAIL(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
+    HIP_OR_FAIL(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
     HIP_OR_FAIL(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
     HIP_OR_FAIL(hipStreamCreateWithFlags(&w->capture, hipStreamNonBlocking));
+    return CSAW_OK;
+}
+
+csaw_status ensure_chunks(Workspace* w, int64_t chunks) {
+    if (w->chunk_cap >= chunks) return CSAW_OK;
+    w->drop_graphs();
+    if (w->chunkbuf) HIP_OR_FAIL(hipFree(w->chunkbuf));
+    w->chunkbuf = nullptr;
+    w->chunk_cap = 0;
+    HIP_OR_FAIL(hipMalloc((void**)&w->chunkbuf, (size_t)chunks * (1 + kChunkGroups) * sizeof(uint64_t)));
+    w->chunk_cap = chunks;
     return CSAW_OK;
 }
 
@@ -494,8 +510,8 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     const size_t o_status = cv.take<unsigned long long>((size_t)nb_build * 4);
     const size_t o_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_off = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
-    const size_t o_mids = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
-    const size_t o_hubs = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
+    const size_t o_bigs = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
+    const size_t o_bigcb = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
     std::vector<size_t> o_fv(L + 1), o_fi(L + 1);
     for (int l = 0; l <= L; ++l) {
         o_fv[l] = cv.take<int32_t>((size_t)std::max<int64_t>(P.fcap[l], 1));
@@ -506,6 +522,17 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     if ((st = ensure_arena(ws, cv.off)) != CSAW_OK) return st;
     if ((st = ensure_bitmaps(ws, (size_t)words * 2, s)) != CSAW_OK) return st;
     if ((st = ensure_streams(ws)) != CSAW_OK) return st;
+    // long-list scratch: at most the bound below, at first a modest guess that
+    // grows to the largest per-layer chunk count this workspace has seen
+    const bool big_path = (P.uses_deg || P.uses_ew) && g->max_deg > kChunk;
+    if (big_path) {
+        const int64_t per = (g->max_deg + kChunk - 1) / kChunk;
+        int64_t bound = 1;
+        for (int l = 0; l < L; ++l)
+            bound = std::max(bound, std::min(sat_mul(P.fcap[l], per), sat_add(sat_mul(ni, g->m) / kChunk, P.fcap[l])));
+        const int64_t want = std::min(bound, std::max<int64_t>(ws->chunk_hint, kInitialChunks));
+        if ((st = ensure_chunks(ws, want)) != CSAW_OK) return st;
+    }
     const size_t host_bytes = sizeof(SampleCtl) + ((size_t)(L + 1) * ni + 2 * (size_t)ni) * sizeof(int32_t) +
                               (2 * (size_t)ni + 1) * sizeof(int64_t) + 128;
     if ((st = ensure_pinned(ws, host_bytes)) != CSAW_OK) return st;
@@ -557,8 +584,10 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         fb.bias = d_bias;
         fb.cnt = d_cnt;
         fb.off = d_off;
-        fb.mids = (int32_t*)(A + o_mids);
-        fb.hubs = (int32_t*)(A + o_hubs);
+        fb.bigs = (int32_t*)(A + o_bigs);
+        fb.big_cb = (int64_t*)(A + o_bigcb);
+        fb.chunks = ws->chunkbuf;
+        fb.chunk_cap = ws->chunk_cap;
         fb.offsets = out->offsets;
         fb.ctl = ctl;
         fb.status = d_status;
@@ -582,8 +611,11 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         p.bias = d_bias;
         p.cnt = d_cnt;
         p.off = d_off;
-        p.mids = (int32_t*)(A + o_mids);
-        p.hubs = (int32_t*)(A + o_hubs);
+        p.bigs = (const int32_t*)(A + o_bigs);
+        p.big_cb = (const int64_t*)(A + o_bigcb);
+        p.chunks = ws->chunkbuf;
+        p.G = ws->chunkbuf + ws->chunk_cap;
+        p.chunk_cap = ws->chunk_cap;
         p.ctl = ctl;
         p.src = out->src;
         p.dst = out->dst;
@@ -599,27 +631,27 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             p.fv = (const int32_t*)(A + o_fv[l]);
             p.fi = (const int32_t*)(A + o_fi[l]);
             const int64_t cap = P.fcap[l];
-            // the three selection kernels touch disjoint outputs: run them side by side
+            // the long-list path and the wavefront kernel touch disjoint outputs:
+            // run them side by side
             HIP_OR_FAIL(hipEventRecord(ws->fork, s));
-            HIP_OR_FAIL(hipStreamWaitEvent(ws->aux[0], ws->fork, 0));
-            HIP_OR_FAIL(hipStreamWaitEvent(ws->aux[1], ws->fork, 0));
-            {
-                ProfScope ps("select_hub", ws->aux[1]);
-                launch_select_hub(p, 256, ws->aux[1]);
-            }
-            {
-                ProfScope ps("select_mid", ws->aux[0]);
-                launch_select_mid(p, 768, ws->aux[0]);
+            HIP_OR_FAIL(hipStreamWaitEvent(ws->aux, ws->fork, 0));
+            if (big_path) {
+                {
+                    ProfScope ps("chunk_prefix", ws->aux);
+                    launch_chunk_prefix(p, (int)std::min<int64_t>((ws->chunk_cap + 3) / 4, 4096), ws->aux);
+                }
+                {
+                    ProfScope ps("select_big", ws->aux);
+                    launch_select_big(p, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), ws->aux);
+                }
             }
             {
                 ProfScope ps("select_wave", s);
                 const int grid = (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 4096);
                 launch_select(p, grid, s);
             }
-            HIP_OR_FAIL(hipEventRecord(ws->join[0], ws->aux[0]));
-            HIP_OR_FAIL(hipEventRecord(ws->join[1], ws->aux[1]));
-            HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join[0], 0));
-            HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join[1], 0));
+            HIP_OR_FAIL(hipEventRecord(ws->join, ws->aux));
+            HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join, 0));
             if (l + 1 < L && P.fcap[l + 1] > 0) {
                 ProfScope ps("frontier_build", s);
                 build(l + 1);
@@ -637,33 +669,48 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     return CSAW_OK;
     };
 
-    if (graphs_enabled() && !g_prof.load(std::memory_order_relaxed)) {
-        std::vector<int64_t> key = {ni, L, words, nwp, P.total_seeds, out->edge_capacity, (int64_t)(intptr_t)a->seeds,
-                                    (int64_t)(intptr_t)out->src, (int64_t)(intptr_t)out->dst,
-                                    (int64_t)(intptr_t)out->offsets, (int64_t)(intptr_t)ws->arena,
-                                    (int64_t)(intptr_t)ws->bitmaps};
-        key.insert(key.end(), P.fcap.begin(), P.fcap.end());
-        hipGraphExec_t exec = ws->find_graph(key);
-        if (!exec) {
-            HIP_OR_FAIL(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeRelaxed));
-            const csaw_status cst = enqueue(ws->capture);
-            hipGraph_t graph = nullptr;
-            const hipError_t e = hipStreamEndCapture(ws->capture, &graph);
-            if (cst != CSAW_OK) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return cst;
+    // A layer whose long lists need more chunk scratch than the workspace holds
+    // leaves those lists undrawn; the call is then repeated with room for the
+    // count the device reported (every draw is keyed by its counter, so the
+    // repeat returns exactly what a first run with enough room would have).
+    // Layers before the first short one are exact, and so is that layer's
+    // count, so each repeat settles at least one more layer.
+    for (int attempt = 0;; ++attempt) {
+        if (graphs_enabled() && !g_prof.load(std::memory_order_relaxed)) {
+            std::vector<int64_t> key = {ni, L, words, nwp, P.total_seeds, out->edge_capacity, (int64_t)(intptr_t)a->seeds,
+                                        (int64_t)(intptr_t)out->src, (int64_t)(intptr_t)out->dst,
+                                        (int64_t)(intptr_t)out->offsets, (int64_t)(intptr_t)ws->arena,
+                                        (int64_t)(intptr_t)ws->bitmaps, (int64_t)(intptr_t)ws->pinned,
+                                        (int64_t)(intptr_t)ws->chunkbuf, ws->chunk_cap, (int64_t)big_path};
+            key.insert(key.end(), P.fcap.begin(), P.fcap.end());
+            hipGraphExec_t exec = ws->find_graph(key);
+            if (!exec) {
+                HIP_OR_FAIL(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeRelaxed));
+                const csaw_status cst = enqueue(ws->capture);
+                hipGraph_t graph = nullptr;
+                const hipError_t e = hipStreamEndCapture(ws->capture, &graph);
+                if (cst != CSAW_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return cst;
+                }
+                if (e != hipSuccess) return fail(CSAW_ERR_DEVICE, "capture failed: %s", hipGetErrorString(e));
+                const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e2 != hipSuccess) return fail(CSAW_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e2));
+                ws->put_graph(key, exec);
             }
-            if (e != hipSuccess) return fail(CSAW_ERR_DEVICE, "capture failed: %s", hipGetErrorString(e));
-            const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e2 != hipSuccess) return fail(CSAW_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e2));
-            ws->put_graph(key, exec);
+            HIP_OR_FAIL(hipGraphLaunch(exec, s));
+        } else {
+            if ((st = enqueue(s)) != CSAW_OK) return st;
         }
-        HIP_OR_FAIL(hipGraphLaunch(exec, s));
-    } else {
-        if ((st = enqueue(s)) != CSAW_OK) return st;
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        int64_t chunk_max = 0;
+        for (int l = 0; l < L; ++l) chunk_max = std::max<int64_t>(chunk_max, (int64_t)h_ctl->nchunk[l]);
+        ws->chunk_hint = std::max(ws->chunk_hint, chunk_max);
+        if (!big_path || chunk_max <= ws->chunk_cap) break;
+        if (attempt >= L) return fail(CSAW_ERR_DEVICE, "long-list scratch still short after resizing");
+        if ((st = ensure_chunks(ws, chunk_max + chunk_max / 2)) != CSAW_OK) return st;
     }
-    HIP_OR_FAIL(hipStreamSynchronize(s));
     rel.clean = true;
     out->num_edges = L > 0 ? h_ctl->out_base[L] : 0;
     if (h_ctl->lookback_stuck) return fail(CSAW_ERR_DEVICE, "frontier build did not complete its block chain");

@@ -111,17 +111,17 @@ __global__ void k_mark_seeds(const int32_t* __restrict__ seeds, int64_t num_seed
 
 // ------------------------------------------------------------------ count
 // Weighted lists that need draws are routed by length: up to kWaveMaxD to the
-// wavefront kernel (list resident in a per-wave LDS tile), up to kMidMaxD to
-// the mid kernel (one block per list, whole list resident in LDS), longer ones
-// to the hub kernel (one block per list, coarse prefix only).
+// wavefront kernel (list resident in a per-wave LDS tile); longer ones to the
+// long-list path, which first reduces every 1024-weight chunk of every long
+// list in one bandwidth-bound pass (group prefixes within the chunk) and then
+// draws with one wavefront per list from a coarse table built out of them.
 constexpr int kWaveMaxD = 1024;
-constexpr int kMidMaxD = 8192;
 
-enum { kRouteWave = 0, kRouteMid = 1, kRouteHub = 2 };
+enum { kRouteWave = 0, kRouteBig = 1 };
 
 __device__ __forceinline__ int route_of(int32_t kind, int32_t k, int32_t P, int64_t d) {
     if (kind == kUniform || k <= 0 || k >= P || d <= kWaveMaxD) return kRouteWave;
-    return d <= kMidMaxD ? kRouteMid : kRouteHub;
+    return kRouteBig;
 }
 
 __device__ __forceinline__ int32_t positive_count(const GraphDev& g, int32_t kind, int32_t v, int64_t d) {
@@ -130,8 +130,9 @@ __device__ __forceinline__ int32_t positive_count(const GraphDev& g, int32_t kin
 }
 
 __device__ __forceinline__ int32_t entry_count(const GraphDev& g, int32_t k, int32_t kind, int32_t v,
-                                               int32_t& route, SampleCtl* ctl) {
-    const int64_t d = g.rowptr[v + 1] - g.rowptr[v];
+                                               int32_t& route, int64_t& beg, int64_t& d, SampleCtl* ctl) {
+    beg = g.rowptr[v];
+    d = g.rowptr[v + 1] - beg;
     const int32_t P = positive_count(g, kind, v, d);
     route = kRouteWave;
     if (k == 0 || P == 0) return 0;
@@ -143,6 +144,8 @@ __device__ __forceinline__ int32_t entry_count(const GraphDev& g, int32_t k, int
     route = route_of(kind, k, P, d);
     return k;
 }
+
+__device__ __forceinline__ int64_t chunks_of(int64_t d) { return (d + kChunk - 1) / kChunk; }
 
 // Look-back status words: a 48-bit value, a valid bit and the build's epoch
 // in one 64-bit word, so a reader never sees a value without its flag.
@@ -208,7 +211,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     const uint64_t hi0 = (uint64_t)w.z | ((uint64_t)w.w << 32);
     const int32_t vbase = (int32_t)(local4 * 128);
     const int64_t ne = __popcll(lo0) + __popcll(hi0);
-    int64_t ng = 0;
+    int64_t ng = 0, nbig = 0, nchk = 0;
     {
         uint64_t lo = lo0, hi = hi0;
         while (lo | hi) {  // four bits at a time so that their loads overlap
@@ -218,49 +221,84 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 int32_t route;
-                if (bv[t] >= 0) ng += entry_count(fb.g, k, kind, vbase + bv[t], route, fb.ctl);
+                int64_t beg, d;
+                if (bv[t] >= 0) {
+                    ng += entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, fb.ctl);
+                    if (route == kRouteBig) {
+                        ++nbig;
+                        nchk += chunks_of(d);
+                    }
+                }
             }
         }
     }
-    int64_t tot_e, tot_g;
+    int64_t tot_e, tot_g, tot_big, tot_chk;
     const int64_t ex_e = block_excl_scan_i64(ne, &tot_e);
     const int64_t ex_g = block_excl_scan_i64(ng, &tot_g);
-    if (tid == 0) {
+    int64_t ex_big = block_excl_scan_i64(nbig, &tot_big);
+    int64_t ex_chk = block_excl_scan_i64(nchk, &tot_chk);
+    __shared__ int64_t s_big_base, s_chk_base;
+    if (tid == 0) {  // one reservation per block for its long lists and their chunks
+        s_big_base = tot_big ? (int64_t)atomicAdd(&fb.ctl->nbig[fb.layer], (unsigned long long)tot_big) : 0;
+        s_chk_base = tot_chk ? (int64_t)atomicAdd(&fb.ctl->nchunk[fb.layer], (unsigned long long)tot_chk) : 0;
+    }
+    if (tid < kWave) {  // wave 0: publish, then look back 64 predecessors per step
+        const int lane = tid;
         const uint32_t epoch = (uint32_t)fb.layer + 1;
         unsigned long long* st = fb.status + 4 * b;
-        int64_t pe = 0, pg = 0;
-        if (b > 0) {
+        if (b > 0 && lane == 0) {
             status_store(st + 0, status_pack(tot_e, epoch));
             status_store(st + 1, status_pack(tot_g, epoch));
-            int64_t q = b - 1;
-            uint32_t spins = 0;
-            while (q >= 0) {
+        }
+        int64_t pe = 0, pg = 0;
+        int64_t end = b - 1;  // window covers predecessors end, end-1, ..., end-63
+        uint32_t spins = 0;
+        while (end >= 0) {
+            const int64_t q = end - lane;
+            int flag = 2;  // before block 0: an inclusive prefix of zero
+            int64_t ve = 0, vg = 0;
+            if (q >= 0) {
                 unsigned long long* sq = fb.status + 4 * q;
                 const uint64_t ie = status_load(sq + 2), ig = status_load(sq + 3);
                 if (status_ok(ie, epoch) && status_ok(ig, epoch)) {
-                    pe += (int64_t)(ie & kStatusMask);
-                    pg += (int64_t)(ig & kStatusMask);
-                    break;
+                    ve = (int64_t)(ie & kStatusMask);
+                    vg = (int64_t)(ig & kStatusMask);
+                } else {
+                    const uint64_t ae = status_load(sq + 0), ag = status_load(sq + 1);
+                    if (status_ok(ae, epoch) && status_ok(ag, epoch)) {
+                        flag = 1;
+                        ve = (int64_t)(ae & kStatusMask);
+                        vg = (int64_t)(ag & kStatusMask);
+                    } else {
+                        flag = 0;
+                    }
                 }
-                const uint64_t ae = status_load(sq + 0), ag = status_load(sq + 1);
-                if (status_ok(ae, epoch) && status_ok(ag, epoch)) {
-                    pe += (int64_t)(ae & kStatusMask);
-                    pg += (int64_t)(ag & kStatusMask);
-                    --q;
-                    spins = 0;
-                    continue;
-                }
+            }
+            const uint64_t incl = ballot(flag == 2);
+            const uint64_t notready = ballot(flag == 0);
+            const int first = incl ? __ffsll((unsigned long long)incl) - 1 : kWave;  // nearest inclusive
+            const uint64_t upto = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1);
+            if (notready & upto) {  // a nearer predecessor has published nothing yet
                 if (++spins > kSpinLimit) {  // never expected: report instead of hanging
-                    fb.ctl->lookback_stuck = 1;
+                    if (lane == 0) fb.ctl->lookback_stuck = 1;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
+                continue;
             }
+            const bool take = ((upto >> lane) & 1ull) != 0;
+            pe += (int64_t)wave_sum_u64(take ? (uint64_t)ve : 0ull);
+            pg += (int64_t)wave_sum_u64(take ? (uint64_t)vg : 0ull);
+            if (first < kWave) break;
+            end -= kWave;
+            spins = 0;
         }
-        status_store(st + 2, status_pack(pe + tot_e, epoch));
-        status_store(st + 3, status_pack(pg + tot_g, epoch));
-        s_base_e = pe;
-        s_base_g = pg;
+        if (lane == 0) {
+            status_store(st + 2, status_pack(pe + tot_e, epoch));
+            status_store(st + 3, status_pack(pg + tot_g, epoch));
+            s_base_e = pe;
+            s_base_g = pg;
+        }
     }
     __syncthreads();
     const int64_t out_base = fb.ctl->out_base[fb.layer];
@@ -280,13 +318,27 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                     if (bv[t] < 0) continue;
                     const int32_t v = vbase + bv[t];
                     int32_t route;
-                    const int32_t c = entry_count(fb.g, k, kind, v, route, fb.ctl);
+                    int64_t beg, d;
+                    const int32_t c = entry_count(fb.g, k, kind, v, route, beg, d, fb.ctl);
                     fb.fv[pos] = v;
                     fb.fi[pos] = (int32_t)inst;
                     fb.cnt[pos] = c;
                     fb.off[pos] = eoff;
-                    if (route == kRouteMid) fb.mids[atomicAdd(&fb.ctl->nmid[fb.layer], 1ull)] = (int32_t)pos;
-                    else if (route == kRouteHub) fb.hubs[atomicAdd(&fb.ctl->nhub[fb.layer], 1ull)] = (int32_t)pos;
+                    if (route == kRouteBig) {
+                        const int64_t bi = s_big_base + ex_big++;
+                        const int64_t cb = s_chk_base + ex_chk;
+                        const int64_t nc = chunks_of(d);
+                        ex_chk += nc;
+                        fb.bigs[bi] = (int32_t)pos;
+                        fb.big_cb[bi] = cb;
+                        // chunk records beyond the scratch capacity are not written; the
+                        // host sees nchunk > chunk_cap and repeats the call with more room
+                        const uint64_t kbit = kind == kNeighborDegree ? 1ull << 50 : 0ull;
+                        for (int64_t j = 0; j < nc && cb + j < fb.chunk_cap; ++j) {
+                            const int64_t len = d - j * kChunk < kChunk ? d - j * kChunk : kChunk;
+                            fb.chunks[cb + j] = (uint64_t)(beg + j * kChunk) | ((uint64_t)(len - 1) << 40) | kbit;
+                        }
+                    }
                     ++pos;
                     eoff += c;
                 }
@@ -317,9 +369,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
 
 // ----------------------------------------------------------------- select
 // Prefix layout used by the inverse transform search of a weighted list:
-// groups of g consecutive candidates (g = 16 in the wavefront path, 16 * 2^p
-// in the hub path); C[t] = S[t*g] (exclusive prefix at the group starts) and
-// C[nc] = W live in LDS. A search finds the group by binary search in C and
+// groups of g = 16 consecutive candidates; C[t] = S[t*g] (exclusive prefix
+// at the group starts) and C[nc] = W live in LDS. A search finds the group by binary search in C and
 // the candidate by scanning the group's g weights (from the LDS tile when the
 // whole list is resident there, otherwise from global memory / L2).
 //
@@ -330,11 +381,6 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
 constexpr int kTile = 1024;
 constexpr int kTilePad = kTile + kTile / 16;
 constexpr int kWaveC = kWaveMaxD / 16;     // coarse entries per wavefront
-constexpr int kMidThreads = 256;
-constexpr int kMidWaves = kMidThreads / kWave;
-constexpr int kHubThreads = 512;
-constexpr int kHubWaves = kHubThreads / kWave;
-constexpr int kHubC = 8192;                // coarse entries per hub block
 
 __device__ __forceinline__ int tpad(int i) { return i + (i >> 4); }
 
@@ -346,6 +392,36 @@ struct CoarsePool {
     const uint32_t* w;      // weights of the list in global memory
     const uint32_t* tile;   // LDS tile holding the whole list, or null
 };
+
+// Scan weights w[i..end) from global memory, 16 loads in flight, for the
+// first candidate whose running total (from acc) exceeds r.
+__device__ __forceinline__ void fine_scan_global(const uint32_t* __restrict__ w, int64_t i, int64_t end,
+                                                 uint64_t acc, uint64_t r, int64_t& m, uint64_t& Sm,
+                                                 uint32_t& bm) {
+    m = i;
+    Sm = acc;
+    bm = 0;
+    for (; i < end; i += 16) {
+        uint32_t x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[q] = i + q < end ? w[i + q] : 0u;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (!found && i + q < end) {
+                if (acc + x[q] > r) {
+                    m = i + q;
+                    Sm = acc;
+                    bm = x[q];
+                    found = true;
+                } else {
+                    acc += x[q];
+                }
+            }
+        }
+        if (found) break;
+    }
+}
 
 // m = max{i in [0,d) : S_i <= r} with S_m and b_m; per lane. kResident: the
 // group's weights are read from the LDS copy of the list (pl.tile), otherwise
@@ -385,26 +461,7 @@ __device__ __forceinline__ void coarse_search(const CoarsePool& pl, uint64_t r, 
         }
         return;
     }
-    for (; i < end; i += 16) {
-        uint32_t x[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) x[q] = i + q < end ? pl.w[i + q] : 0u;
-        bool found = false;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if (!found && i + q < end) {
-                if (acc + x[q] > r) {
-                    m = i + q;
-                    Sm = acc;
-                    bm = x[q];
-                    found = true;
-                } else {
-                    acc += x[q];
-                }
-            }
-        }
-        if (found) break;
-    }
+    fine_scan_global(pl.w, i, end, acc, r, m, Sm, bm);
 }
 
 // Draw k distinct candidates with one lane per slot (lane j = slot j < k):
@@ -416,9 +473,10 @@ __device__ __forceinline__ void coarse_search(const CoarsePool& pl, uint64_t r, 
 // LDS array holds, per position, -1 once held, else the lowest open slot
 // that picked it this round (ds_min); otherwise each open slot compares with
 // every slot through lane reads.
-template <class Search>
-__device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k,
-                                              uint64_t W, const Search& search, int32_t* own = nullptr) {
+template <class Search, class SearchAll>
+__device__ __forceinline__ int64_t draw_slots2(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k,
+                                               uint64_t W, const Search& search, const SearchAll& search_all,
+                                               int32_t* own = nullptr) {
     const int lane = lane_id();
     const bool active = lane < k;
     bool held = false;
@@ -477,7 +535,7 @@ __device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1,
             int64_t m = 0;
             uint64_t Sm = 0;
             uint32_t bm = 0;
-            search(r, m, Sm, bm);  // same r on every lane
+            search_all(r, m, Sm, bm);  // same r on every lane
             m = readlane_i64(m, j);
             Sm = readlane_u64(Sm, j);
             bm = readlane_u32(bm, j);
@@ -495,6 +553,12 @@ __device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1,
         }
     }
     return pos;
+}
+
+template <class Search>
+__device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k,
+                                              uint64_t W, const Search& search, int32_t* own = nullptr) {
+    return draw_slots2(key, c0, c1, c2, k, W, search, search, own);
 }
 
 __device__ __forceinline__ void claim(bool do_claim, const uint32_t* visb, uint32_t* nextb, int32_t x) {
@@ -669,121 +733,157 @@ __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
         select_entry(p, e, out_base, tiles[wid], coarse[wid], owners[wid]);
 }
 
-// One block per mid-size weighted list (kWaveMaxD < d <= kMidMaxD): the
-// block's waves load the list's tiles in parallel into LDS (transposed layout,
-// the whole list stays resident), one thread per 16-group sums it, a block
-// scan builds the coarse prefix, and wave 0 draws the slots with every search
-// served from LDS.
-__global__ void __launch_bounds__(kMidThreads) k_select_mid(SampleLayer p, const int32_t* __restrict__ mids) {
-    __shared__ uint32_t wt[kMidMaxD + kMidMaxD / 16];
-    __shared__ uint64_t C[kMidMaxD / 16 + 1];
-    const int tid = threadIdx.x;
-    const int wid = uniform_i32(tid / kWave);
+// ------------------------------------------------------ long-list path
+// Pass 1: one wavefront per 1024-weight chunk of every long list in the
+// layer: coalesced loads, LDS transpose, one 16-weight group per lane, and a
+// 64-lane scan gives G[c][i] = total weight of groups 0..i of chunk c.
+__global__ void __launch_bounds__(kBlock) k_chunk_prefix(SampleLayer p) {
+    __shared__ uint32_t tiles[kWavesPerBlock][kTilePad];
+    const int wid = uniform_i32(threadIdx.x / kWave);
     const int lane = lane_id();
-    const int64_t nm = (int64_t)p.ctl->nmid[p.layer];
-    const int64_t out_base = p.ctl->out_base[p.layer];
-    for (int64_t h = blockIdx.x; h < nm; h += gridDim.x) {
-        EntryInfo E;
-        load_entry(p, mids[h], out_base, E);
-        const int64_t d = E.d;
-        const uint32_t* w = (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg;
-        for (int64_t t = wid; t * kTile < d; t += kMidWaves) {
-            uint32_t x[16];
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const int64_t idx = t * kTile + c * kWave + lane;
-                x[c] = idx < d ? w[idx] : 0u;
-            }
-#pragma unroll
-            for (int c = 0; c < 16; ++c) wt[tpad((int)(t * kTile) + c * kWave + lane)] = x[c];
-        }
-        __syncthreads();
-        const int ng = (int)((d + 15) / 16);
-        // group sums, then inclusive scan of C[1..ng] (thread tid owns 2 groups)
-        uint64_t s0 = 0, s1 = 0;
-        const int g0 = 2 * tid, g1 = 2 * tid + 1;
-        if (g0 < ng)
-            for (int q = 0; q < 16; ++q) s0 += (16 * g0 + q < d) ? wt[tpad(16 * g0 + q)] : 0u;
-        if (g1 < ng)
-            for (int q = 0; q < 16; ++q) s1 += (16 * g1 + q < d) ? wt[tpad(16 * g1 + q)] : 0u;
-        int64_t tot;
-        const uint64_t before = (uint64_t)block_excl_scan_i64<kMidThreads>((int64_t)(s0 + s1), &tot);
-        if (g0 < ng) C[g0 + 1] = before + s0;
-        if (g1 < ng) C[g1 + 1] = before + s0 + s1;
-        if (tid == 0) C[0] = 0;
-        __syncthreads();
-        if (wid == 0) {
-            if (E.o + E.c > p.capacity) {
-                if (lane == 0) p.ctl->overflow = 1;
-            } else {
-                const CoarsePool pl{C, ng, 16, d, w, wt};
-                const int64_t pos = draw_slots(inst_key(p, E.inst), p.inst_id[E.inst],
-                                               (uint32_t)p.layer, (uint32_t)E.v, E.k, C[ng],
-                                               [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
-                                                   coarse_search<true>(pl, r, m, Sm, bm);
-                                               });
-                emit_slots(p, E, pos);
-            }
-        }
-        __syncthreads();
+    const int64_t need = (int64_t)p.ctl->nchunk[p.layer];
+    const int64_t nch = need < p.chunk_cap ? need : p.chunk_cap;
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t c = blockIdx.x * (int64_t)kWavesPerBlock + wid; c < nch; c += waves) {
+        const uint64_t rec = (uint64_t)uniform_i64((int64_t)p.chunks[c]);
+        const uint32_t* w = (((rec >> 50) & 1ull) ? p.g.degw : p.g.ew) + (int64_t)(rec & ((1ull << 40) - 1));
+        const int64_t len = (int64_t)((rec >> 40) & 1023ull) + 1;
+        const uint64_t s = tile_group_sums(w, 0, len, tiles[wid]);
+        p.G[c * kChunkGroups + lane] = wave_incl_scan_u64(s);
     }
 }
 
-// One block per hub list: the block's waves stream the list in tiles and add
-// group sums into C (LDS atomics), a block scan turns them into the coarse
-// prefix, then wave 0 draws the slots.
-__global__ void __launch_bounds__(kHubThreads) k_select_hub(SampleLayer p, const int32_t* __restrict__ hubs) {
-    __shared__ uint64_t C[kHubC + 1];
-    __shared__ uint32_t tiles[kHubWaves][kTilePad];
-    const int tid = threadIdx.x;
-    const int wid = uniform_i32(tid / kWave);
-    const int lane = lane_id();
-    const int64_t nh = (int64_t)p.ctl->nhub[p.layer];
-    const int64_t out_base = p.ctl->out_base[p.layer];
-    for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
-        EntryInfo E;
-        load_entry(p, hubs[h], out_base, E);
-        const int64_t d = E.d;
-        const uint32_t* w = (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg;
-        int64_t g = 16;
-        while ((d + g - 1) / g > kHubC) g <<= 1;
-        const int64_t ng = (d + g - 1) / g;
-        for (int64_t i = tid; i <= ng; i += kHubThreads) C[i] = 0;
-        __syncthreads();
-        for (int64_t t = wid; t * kTile < d; t += kHubWaves) {
-            const uint64_t s = tile_group_sums(w, t * kTile, d, tiles[wid]);
-            const int64_t first = t * kTile + lane * 16;
-            if (first < d && s) atomicAdd((unsigned long long*)&C[1 + first / g], (unsigned long long)s);
-        }
-        __syncthreads();
-        // inclusive scan of C[1..ng]; thread tid owns a contiguous segment
-        const int64_t seg = (ng + kHubThreads - 1) / kHubThreads;
-        const int64_t b0 = 1 + tid * seg;
-        const int64_t b1 = (b0 + seg < ng + 1) ? b0 + seg : ng + 1;
-        uint64_t local = 0;
-        for (int64_t b = b0; b < b1; ++b) local += C[b];
-        int64_t tot;
-        uint64_t run = (uint64_t)block_excl_scan_i64<kHubThreads>((int64_t)local, &tot);
-        for (int64_t b = b0; b < b1; ++b) {
-            run += C[b];
-            C[b] = run;
-        }
-        __syncthreads();
-        if (wid == 0) {
-            if (E.o + E.c > p.capacity) {
-                if (lane == 0) p.ctl->overflow = 1;
-            } else {
-                const CoarsePool pl{C, ng, g, d, w, nullptr};
-                const int64_t pos = draw_slots(inst_key(p, E.inst), p.inst_id[E.inst],
-                                               (uint32_t)p.layer, (uint32_t)E.v, E.k, C[ng],
-                                               [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
-                                                   coarse_search<false>(pl, r, m, Sm, bm);
-                                               });
-                emit_slots(p, E, pos);
-            }
-        }
-        __syncthreads();
+// Per-lane search of a long list through its chunk prefixes (pass 1) and a
+// coarse LDS table over units of 2^shift chunks: tab[u] = total weight of
+// the chunks before unit u, tab[nu] = W. Finds the unit by binary search in
+// LDS, the chunk by a walk over the unit's chunk totals, the group by binary
+// search in the chunk's G row and the candidate by scanning the group's
+// weights (global memory / L2).
+struct UnitPool {
+    const uint64_t* tab;    // LDS, nu + 1 entries
+    int64_t nu;
+    int shift;
+    int64_t nch;            // chunks of the list
+    const uint64_t* G;      // G rows of the list's chunks
+    const uint32_t* w;      // weights of the list
+    int64_t d;
+};
+
+__device__ __forceinline__ void unit_search(const UnitPool& pl, uint64_t r, int64_t& m, uint64_t& Sm,
+                                            uint32_t& bm) {
+    int64_t lo = 0, hi = pl.nu;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (pl.tab[mid] <= r) lo = mid;
+        else hi = mid;
     }
+    uint64_t acc = pl.tab[lo];
+    int64_t j = lo << pl.shift;
+    const int64_t jend = ((lo + 1) << pl.shift) < pl.nch ? ((lo + 1) << pl.shift) : pl.nch;
+    for (; j + 1 < jend; ++j) {  // chunk totals of the unit
+        const uint64_t t = pl.G[j * kChunkGroups + kChunkGroups - 1];
+        if (acc + t > r) break;
+        acc += t;
+    }
+    const uint64_t* row = pl.G + j * kChunkGroups;
+    int32_t glo = -1, ghi = kChunkGroups - 1;  // first group i with acc + row[i] > r
+    uint64_t before = 0;
+    while (ghi - glo > 1) {
+        const int32_t mid = (glo + ghi) >> 1;
+        const uint64_t v = row[mid];
+        if (acc + v > r) {
+            ghi = mid;
+        } else {
+            glo = mid;
+            before = v;
+        }
+    }
+    const int64_t i = j * kChunk + (int64_t)ghi * 16;
+    const int64_t end = i + 16 < pl.d ? i + 16 : pl.d;
+    fine_scan_global(pl.w, i, end, acc + before, r, m, Sm, bm);
+}
+
+// Pass 2: one wavefront per long list. Lists of up to kGroupTabD weights get
+// a group-level table (C[t] = weight before group t, from the chunk totals
+// and the G rows), searched like the wavefront path with the group's weights
+// read from global memory; longer lists get a unit-level table (UnitPool).
+constexpr int kBigTab = 512;
+constexpr int64_t kGroupTabD = (int64_t)kBigTab * 16;
+
+__device__ void select_big_entry(const SampleLayer& p, int64_t h, int64_t out_base, uint64_t* tab) {
+    const int lane = lane_id();
+    EntryInfo E;
+    if (!load_entry(p, p.bigs[h], out_base, E)) return;
+    if (E.o + E.c > p.capacity) {
+        if (lane == 0) p.ctl->overflow = 1;
+        return;
+    }
+    const int64_t cb = uniform_i64(p.big_cb[h]);
+    const int64_t d = E.d;
+    const int64_t nch = chunks_of(d);
+    if (cb + nch > p.chunk_cap) return;  // no scratch room this time; the call is repeated
+    const uint32_t* w = (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg;
+    const uint64_t* G = p.G + cb * kChunkGroups;
+    const Key key = inst_key(p, E.inst);
+    const uint32_t c0 = p.inst_id[E.inst], c1 = (uint32_t)p.layer, c2 = (uint32_t)E.v;
+    int64_t pos;
+    if (d <= kGroupTabD) {
+        const int64_t nc = (d + 15) / 16;
+        uint64_t rows[kGroupTabD / kChunk];
+#pragma unroll
+        for (int j = 0; j < kGroupTabD / kChunk; ++j) rows[j] = j < nch ? G[j * kChunkGroups + lane] : 0ull;
+        const uint64_t tj = lane < nch ? G[lane * kChunkGroups + kChunkGroups - 1] : 0ull;
+        const uint64_t cincl = wave_incl_scan_u64(tj);
+        const uint64_t cex = cincl - tj;
+#pragma unroll
+        for (int j = 0; j < kGroupTabD / kChunk; ++j) {
+            const uint64_t base = readlane_u64(cex, j);
+            const int64_t t = (int64_t)j * kChunkGroups + lane;
+            if (j < nch && t < nc) tab[t + 1] = base + rows[j];
+        }
+        if (lane == 0) tab[0] = 0;
+        const uint64_t W = readlane_u64(cincl, (int)nch - 1);
+        wave_lds_sync();
+        const CoarsePool pl{tab, nc, 16, d, w, nullptr};
+        pos = draw_slots(key, c0, c1, c2, E.k, W,
+                         [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+                             coarse_search<false>(pl, r, m, Sm, bm);
+                         });
+    } else {
+        int shift = 0;
+        while (((nch + (1ll << shift) - 1) >> shift) > kBigTab) ++shift;
+        const int64_t nu = (nch + (1ll << shift) - 1) >> shift;
+        uint64_t carry = 0;
+        for (int64_t u0 = 0; u0 < nu; u0 += kWave) {
+            const int64_t u = u0 + lane;
+            uint64_t s = 0;
+            if (u < nu) {
+                const int64_t j0 = u << shift;
+                const int64_t j1 = j0 + (1ll << shift) < nch ? j0 + (1ll << shift) : nch;
+                for (int64_t j = j0; j < j1; ++j) s += G[j * kChunkGroups + kChunkGroups - 1];
+            }
+            const uint64_t incl = wave_incl_scan_u64(s);
+            if (u < nu) tab[u + 1] = carry + incl;
+            carry += readlane_u64(incl, kWave - 1);
+        }
+        if (lane == 0) tab[0] = 0;
+        wave_lds_sync();
+        const UnitPool pl{tab, nu, shift, nch, G, w, d};
+        pos = draw_slots(key, c0, c1, c2, E.k, carry,
+                         [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) { unit_search(pl, r, m, Sm, bm); });
+    }
+    emit_slots(p, E, pos);
+    wave_lds_sync();  // the table is rewritten by the wave's next list
+}
+
+__global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
+    __shared__ uint64_t tabs[kWavesPerBlock][kBigTab + 1];
+    const int wid = uniform_i32(threadIdx.x / kWave);
+    const int64_t nb = (int64_t)p.ctl->nbig[p.layer];
+    const int64_t out_base = p.ctl->out_base[p.layer];
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t h = blockIdx.x * (int64_t)kWavesPerBlock + wid; h < nb; h += waves)
+        select_big_entry(p, h, out_base, tabs[wid]);
 }
 
 __global__ void k_clear_visited(const int32_t* __restrict__ fv, const int32_t* __restrict__ fi,
@@ -838,12 +938,12 @@ void launch_select(const SampleLayer& p, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(grid), dim3(kBlock), 0, s, p);
 }
 
-void launch_select_mid(const SampleLayer& p, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_mid, dim3(grid), dim3(kMidThreads), 0, s, p, (const int32_t*)p.mids);
+void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_chunk_prefix, dim3(grid), dim3(kBlock), 0, s, p);
 }
 
-void launch_select_hub(const SampleLayer& p, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_hub, dim3(grid), dim3(kHubThreads), 0, s, p, (const int32_t*)p.hubs);
+void launch_select_big(const SampleLayer& p, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_big, dim3(grid), dim3(kBlock), 0, s, p);
 }
 
 void launch_clear_visited(const int32_t* fv, const int32_t* fi, const int64_t* fcount, int64_t cap_entries,

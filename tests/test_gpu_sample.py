@@ -119,6 +119,27 @@ def test_giant_hub(csaw):
     run_both(csaw, g, rp, col, None, offs, seeds, [64], csaw.UNIFORM, 4)
 
 
+def test_longest_lists_and_scratch_growth(csaw):
+    """Lists of 1.2M weights (more chunks than the coarse table holds, so it
+    covers four chunks per entry) in 8 instances: 9,376 chunks, more than a
+    fresh workspace's long-list scratch, so the first call is repeated with
+    more room; a second call must return the same edges without that."""
+    d = 1_200_000
+    rp = np.array([0, d] + [d] * d, dtype=np.int64)
+    col = np.arange(1, d + 1, dtype=np.int32)
+    g0 = inputs.rng(21)
+    ew = g0.integers(0, 5000, size=d).astype(np.uint32)
+    ew[g0.random(d) < 0.3] = 0
+    ew[g0.choice(d, 7, replace=False)] = 1 << 26
+    ni = 8
+    offs = np.arange(ni + 1, dtype=np.int64)
+    seeds = np.zeros(ni, dtype=np.int32)
+    g = csaw.Graph(rp, col, ew)
+    res, ref = run_both(csaw, g, rp, col, ew, offs, seeds, [25], csaw.EDGE_WEIGHT, 13)
+    again = g.sample(offs, seeds, [25], csaw.EDGE_WEIGHT, rng_seed=13)
+    np.testing.assert_array_equal(again.dst.cpu().numpy(), ref.dst)
+
+
 def test_small_lists_and_collisions(csaw):
     """Lists barely longer than the fanout force long collision chains."""
     rng = inputs.rng(4)
@@ -203,8 +224,9 @@ def test_degree_biased_rmat22_full(csaw):
 
 
 def test_route_boundaries(csaw):
-    """Weighted lists at the lengths where the kernels hand over (wavefront /
-    mid / hub): 1024, 1025, 8192, 8193, plus short ones, with zero weights and
+    """Weighted lists at the lengths where the kernels hand over (wavefront
+    kernel / long-list path with a group-level table / with a chunk-level
+    table): 1024, 1025, 8192, 8193, plus short ones, with zero weights and
     dominant weights, many instances and fanouts up to 64."""
     degs = [16, 1024, 1025, 8192, 8193, 20000]
     hubs = len(degs)
@@ -249,3 +271,40 @@ def test_replayed_launch_sequence_matches_eager(csaw):
     res = g.sample(offs2, seeds2, [25, 10], csaw.UNIFORM, rng_seed=5)
     ref = oracle.sample(rp, col, None, offs2, seeds2, [25, 10], bias_kind=oracle.UNIFORM, rng_seed=5)
     assert_same(res, ref)
+
+
+def test_replay_key_covers_bias_kind(csaw):
+    """A uniform call and a degree-biased call with the same shapes, seeds
+    and output buffers: the biased call needs the long-list kernels that the
+    uniform launch sequence does not contain, so it must not replay it."""
+    import torch
+    rp, col = inputs.rmat_csr(15, 16 << 15, 31)
+    assert np.diff(rp).max() > 1024
+    offs, seeds = inputs.single_instance_seeds(rp, col, 300, 8)
+    g = csaw.Graph(rp, col)
+    seeds_dev = torch.from_numpy(seeds).cuda()
+    cap = max(g.sample_bound(offs, [25, 10], csaw.UNIFORM), g.sample_bound(offs, [25, 10], csaw.NEIGHBOR_DEGREE))
+    out = (torch.empty(cap, dtype=torch.int32, device="cuda"), torch.empty(cap, dtype=torch.int32, device="cuda"),
+           torch.empty(3, dtype=torch.int64, device="cuda"))
+    say("replay key: uniform then degree-biased, same buffers")
+    for bias in (csaw.UNIFORM, csaw.NEIGHBOR_DEGREE, csaw.UNIFORM, csaw.NEIGHBOR_DEGREE):
+        res = g.sample(offs, seeds_dev, [25, 10], bias, rng_seed=6, out=out)
+        ref = oracle.sample(rp, col, None, offs, seeds, [25, 10], bias_kind=bias, rng_seed=6)
+        assert_same(res, ref)
+
+
+def test_replay_after_staging_growth(csaw):
+    """A replayed launch sequence must not outlive the buffers it names: a
+    large call grows the workspace's staging buffers between two small calls
+    of the same shape, and the second small call still matches the oracle."""
+    rp, col = inputs.rmat_csr(13, 16 << 13, 41)
+    g = csaw.Graph(rp, col)
+    offs, seeds = inputs.single_instance_seeds(rp, col, 50, 3)
+    say("replay after staging growth")
+    a = g.sample(offs, seeds, [10, 5], csaw.UNIFORM, rng_seed=2)
+    big_offs, big_seeds, big_fan, big_bias = inputs.batched_instances(rp, col, 2000, 5, lo=1, hi=20, median=4)
+    g.sample(big_offs, big_seeds, big_fan, big_bias, rng_seed=2)
+    b = g.sample(offs, seeds, [10, 5], csaw.UNIFORM, rng_seed=2)
+    ref = oracle.sample(rp, col, None, offs, seeds, [10, 5], bias_kind=oracle.UNIFORM, rng_seed=2)
+    assert_same(a, ref)
+    assert_same(b, ref)

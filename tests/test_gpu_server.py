@@ -85,7 +85,8 @@ def test_submit_errors_and_poll(setup):
     with pytest.raises(csaw.CsawError) as ei:
         srv.submit_walk(np.zeros(1 << 20, dtype=np.int32), 80)                  # alone exceeds the budget
     assert ei.value.status == 2
-    t = srv.submit_walk(trace[1]["starts"][:10], 5, 1, rng_seed=3, request_id=9)
+    walk = next(r for r in trace if r["kind"] == "walk")
+    t = srv.submit_walk(walk["starts"][:10], 5, 1, rng_seed=3, request_id=9)
     res = srv.wait(t)
     assert res.status == 0 and res.paths.shape == (10, 6)
     with pytest.raises(csaw.CsawError):
