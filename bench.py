@@ -33,7 +33,7 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-WAVE_MAX_D = 1024  # longer weighted lists that need draws take the long-list path
+WAVE_MAX_D = 512  # longer (or 2^32-heavy) weighted lists that need draws take the long-list path
 
 
 def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted):

@@ -74,6 +74,16 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
     return x;
 }
 
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr2, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr4, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr8, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast15, 0xa, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast31, 0xc, 0xf, false);
+    return x;
+}
+
 __device__ __forceinline__ uint32_t readlane_u32(uint32_t x, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
 }
@@ -87,6 +97,12 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int lane) {
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) { return readlane_u64(wave_incl_scan_u64(x), 63); }
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t x) { return (int64_t)wave_sum_u64((uint64_t)x); }
+
+// Width-generic forms for code templated on the prefix type.
+__device__ __forceinline__ uint32_t readlane_t(uint32_t x, int lane) { return readlane_u32(x, lane); }
+__device__ __forceinline__ uint64_t readlane_t(uint64_t x, int lane) { return readlane_u64(x, lane); }
+__device__ __forceinline__ uint32_t wave_incl_scan_t(uint32_t x) { return wave_incl_scan_u32(x); }
+__device__ __forceinline__ uint64_t wave_incl_scan_t(uint64_t x) { return wave_incl_scan_u64(x); }
 
 __device__ __forceinline__ int32_t readlane_i32(int32_t x, int lane) {
     return __builtin_amdgcn_readlane(x, lane);

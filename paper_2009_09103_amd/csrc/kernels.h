@@ -12,6 +12,7 @@ constexpr int kRounds = 8;           // repeated-sampling rounds
 constexpr int kScanItems = 1024;     // items per scan block (256 threads x 4)
 constexpr int kChunk = 1024;         // weights per chunk of a long list
 constexpr int kChunkGroups = 64;     // 16-weight groups per chunk
+constexpr int32_t kWideList = (int32_t)0x80000000u;  // ppos flag: the list's total weight is >= 2^32
 
 enum BiasKind : int32_t { kUniform = 0, kEdgeWeight = 1, kNeighborDegree = 2, kNode2vec = 3 };
 
@@ -22,7 +23,7 @@ struct GraphDev {
     const int32_t* col;        // m
     const uint32_t* ew;        // m or null (EDGE_WEIGHT)
     const uint32_t* degw;      // m or null (NEIGHBOR_DEGREE, materialised)
-    const int32_t* ppos_ew;    // n: #positive weights per list, or null
+    const int32_t* ppos_ew;    // n: #positive weights per list | kWideList, or null
     const int32_t* ppos_deg;   // n
 };
 
@@ -103,8 +104,17 @@ void launch_frontier_build(const FrontierBuild& fb, hipStream_t s);
 void launch_select(const SampleLayer& p, int grid, hipStream_t s);
 void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s);
 void launch_select_big(const SampleLayer& p, int grid, hipStream_t s);
-void launch_clear_visited(const int32_t* fv, const int32_t* fi, const int64_t* fcount,
-                          int64_t cap_entries, uint32_t* visited, int64_t nwp, hipStream_t s);
+// Clears the visited bits of every frontier entry of the call's layers.
+struct ClearVisited {
+    const int32_t* fv[kMaxLayers + 1];
+    const int32_t* fi[kMaxLayers + 1];
+    const int64_t* fcount;           // device: entries per layer
+    int32_t num_layers;
+    int64_t cap_entries;             // largest frontier capacity (grid sizing)
+    uint32_t* visited;
+    int64_t nwp;
+};
+void launch_clear_visited(const ClearVisited& c, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 
 // --- graph preparation (sample_kernels.hip)

@@ -501,13 +501,25 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
 
     // device workspace layout
     Carver cv;
+    // small per-call tables: one block with the same layout in pinned memory
+    // and in the arena, so one copy moves them all
+    size_t tb = 0;
+    const size_t t_fan = tb;
+    tb += P.fan.size() * sizeof(int32_t);
+    const size_t t_bias = tb;
+    tb += (size_t)ni * sizeof(int32_t);
+    const size_t t_iid = tb;
+    tb = align_up(tb + (size_t)ni * sizeof(uint32_t), 8);
+    const size_t t_key = tb;
+    tb += (size_t)ni * sizeof(uint64_t);
+    const size_t t_soff = tb;
+    tb += ((size_t)ni + 1) * sizeof(int64_t);
+    const size_t tab_bytes = tb;
+    // the control block and the look-back words are adjacent: one fill clears both
     const size_t o_ctl = cv.take<SampleCtl>(1);
-    const size_t o_fan = cv.take<int32_t>((size_t)(L + 1) * ni);
-    const size_t o_bias = cv.take<int32_t>(ni);
-    const size_t o_iid = cv.take<uint32_t>(ni);
-    const size_t o_key = cv.take<uint64_t>(ni);
-    const size_t o_soff = cv.take<int64_t>((size_t)ni + 1);
     const size_t o_status = cv.take<unsigned long long>((size_t)nb_build * 4);
+    const size_t ctl_words = (o_status - o_ctl) / 4 + (size_t)nb_build * 8;
+    const size_t o_tab = cv.take<char>(tab_bytes);
     const size_t o_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_off = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_bigs = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
@@ -533,15 +545,14 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         const int64_t want = std::min(bound, std::max<int64_t>(ws->chunk_hint, kInitialChunks));
         if ((st = ensure_chunks(ws, want)) != CSAW_OK) return st;
     }
-    const size_t host_bytes = sizeof(SampleCtl) + ((size_t)(L + 1) * ni + 2 * (size_t)ni) * sizeof(int32_t) +
-                              (2 * (size_t)ni + 1) * sizeof(int64_t) + 128;
-    if ((st = ensure_pinned(ws, host_bytes)) != CSAW_OK) return st;
+    const size_t o_hctl = align_up(tab_bytes, 64);
+    if ((st = ensure_pinned(ws, o_hctl + sizeof(SampleCtl))) != CSAW_OK) return st;
 
     char* A = ws->arena;
     SampleCtl* ctl = (SampleCtl*)(A + o_ctl);
-    int32_t* d_fan = (int32_t*)(A + o_fan);
-    int32_t* d_bias = (int32_t*)(A + o_bias);
-    int64_t* d_soff = (int64_t*)(A + o_soff);
+    int32_t* d_fan = (int32_t*)(A + o_tab + t_fan);
+    int32_t* d_bias = (int32_t*)(A + o_tab + t_bias);
+    int64_t* d_soff = (int64_t*)(A + o_tab + t_soff);
     unsigned long long* d_status = (unsigned long long*)(A + o_status);
     int32_t* d_cnt = (int32_t*)(A + o_cnt);
     int64_t* d_off = (int64_t*)(A + o_off);
@@ -550,28 +561,20 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
 
     // stage the small tables through pinned memory
     char* H = ws->pinned;
-    int32_t* h_fan = (int32_t*)H;
-    std::memcpy(h_fan, P.fan.data(), P.fan.size() * sizeof(int32_t));
-    int32_t* h_bias = h_fan + P.fan.size();
-    std::memcpy(h_bias, P.bias.data(), ni * sizeof(int32_t));
-    uint32_t* h_iid = (uint32_t*)(h_bias + ni);
+    std::memcpy(H + t_fan, P.fan.data(), P.fan.size() * sizeof(int32_t));
+    std::memcpy(H + t_bias, P.bias.data(), ni * sizeof(int32_t));
+    uint32_t* h_iid = (uint32_t*)(H + t_iid);
     for (int32_t i = 0; i < ni; ++i)
         h_iid[i] = (uint32_t)(a->instance_ids ? a->instance_ids[i] : a->instance_base + (uint64_t)i);
-    uint64_t* h_key = (uint64_t*)align_up((size_t)(h_iid + ni), 8);
+    uint64_t* h_key = (uint64_t*)(H + t_key);
     for (int32_t i = 0; i < ni; ++i) h_key[i] = a->rng_seeds ? a->rng_seeds[i] : a->rng_seed;
-    int64_t* h_soff = (int64_t*)(h_key + ni);
-    std::memcpy(h_soff, a->seed_offsets, ((size_t)ni + 1) * sizeof(int64_t));
-    SampleCtl* h_ctl = (SampleCtl*)align_up((size_t)(h_soff + ni + 1), 8);
+    std::memcpy(H + t_soff, a->seed_offsets, ((size_t)ni + 1) * sizeof(int64_t));
+    SampleCtl* h_ctl = (SampleCtl*)(H + o_hctl);
     // every device step of the call, enqueued on stream s
     auto enqueue = [&](hipStream_t s) -> csaw_status {
-        launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)(sizeof(SampleCtl) / 4), s);
-        HIP_OR_FAIL(hipMemcpyAsync(d_fan, h_fan, P.fan.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_OR_FAIL(hipMemcpyAsync(d_bias, h_bias, ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_OR_FAIL(hipMemcpyAsync(A + o_iid, h_iid, ni * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        HIP_OR_FAIL(hipMemcpyAsync(A + o_key, h_key, ni * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-        HIP_OR_FAIL(hipMemcpyAsync(d_soff, h_soff, ((size_t)ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)ctl_words, s);
+        HIP_OR_FAIL(hipMemcpyAsync(A + o_tab, H, tab_bytes, hipMemcpyHostToDevice, s));
 
-        launch_fill_u32((uint32_t*)d_status, 0u, nb_build * 8, s);
         FrontierBuild fb;
         fb.g = g->dev();
         fb.next4 = (uint4*)next;
@@ -606,8 +609,8 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         SampleLayer p;
         p.g = g->dev();
         p.num_instances = ni;
-        p.inst_id = (const uint32_t*)(A + o_iid);
-        p.inst_key = (const uint64_t*)(A + o_key);
+        p.inst_id = (const uint32_t*)(A + o_tab + t_iid);
+        p.inst_key = (const uint64_t*)(A + o_tab + t_key);
         p.bias = d_bias;
         p.cnt = d_cnt;
         p.off = d_off;
@@ -660,9 +663,17 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         }
         {
             ProfScope ps("visited_clear", s);
-            for (int l = 0; l < computed_layers; ++l)
-                launch_clear_visited((const int32_t*)(A + o_fv[l]), (const int32_t*)(A + o_fi[l]), &ctl->fcount[l],
-                                     P.fcap[l], visited, nwp, s);
+            ClearVisited cl{};
+            cl.num_layers = computed_layers;
+            cl.fcount = ctl->fcount;
+            cl.visited = visited;
+            cl.nwp = nwp;
+            for (int l = 0; l < computed_layers; ++l) {
+                cl.fv[l] = (const int32_t*)(A + o_fv[l]);
+                cl.fi[l] = (const int32_t*)(A + o_fi[l]);
+                cl.cap_entries = std::max(cl.cap_entries, P.fcap[l]);
+            }
+            launch_clear_visited(cl, s);
         }
         HIP_OR_FAIL(hipGetLastError());
         HIP_OR_FAIL(hipMemcpyAsync(h_ctl, ctl, sizeof(SampleCtl), hipMemcpyDeviceToHost, s));

@@ -72,7 +72,8 @@ __global__ void k_degree_weights(const int64_t* __restrict__ rowptr, const int32
     }
 }
 
-// one wavefront per vertex: number of positive weights in its list
+// one wavefront per vertex: number of positive weights in its list, with
+// kWideList set when the list's total weight needs more than 32 bits
 __global__ void k_positive_counts(const int64_t* __restrict__ rowptr, const uint32_t* __restrict__ w,
                                   int64_t n, int32_t* __restrict__ ppos) {
     const int lane = lane_id();
@@ -80,9 +81,14 @@ __global__ void k_positive_counts(const int64_t* __restrict__ rowptr, const uint
     for (int64_t v = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; v < n; v += waves) {
         const int64_t b = rowptr[v], e = rowptr[v + 1];
         int64_t c = 0;
-        for (int64_t i = b + lane; i < e; i += kWave) c += (w[i] > 0);
+        uint64_t tot = 0;
+        for (int64_t i = b + lane; i < e; i += kWave) {
+            c += (w[i] > 0);
+            tot += w[i];
+        }
         c = wave_sum_i64(c);
-        if (lane == 0) ppos[v] = (int32_t)c;
+        tot = wave_sum_u64(tot);
+        if (lane == 0) ppos[v] = (int32_t)c | ((tot >> 32) ? kWideList : 0);
     }
 }
 
@@ -110,30 +116,37 @@ __global__ void k_mark_seeds(const int32_t* __restrict__ seeds, int64_t num_seed
 }
 
 // ------------------------------------------------------------------ count
-// Weighted lists that need draws are routed by length: up to kWaveMaxD to the
-// wavefront kernel (list resident in a per-wave LDS tile); longer ones to the
-// long-list path, which first reduces every 1024-weight chunk of every long
-// list in one bandwidth-bound pass (group prefixes within the chunk) and then
-// draws with one wavefront per list from a coarse table built out of them.
-constexpr int kWaveMaxD = 1024;
+// Weighted lists that need draws are routed by length: up to kWaveMaxD
+// candidates with a total weight below 2^32 to the wavefront kernel (list and
+// 32-bit prefix resident in registers); the others to the long-list path,
+// which first reduces every 1024-weight chunk of every such list in one
+// bandwidth-bound pass (group prefixes within the chunk) and then draws with
+// one wavefront per list from a coarse table built out of them.
+constexpr int kWaveMaxD = 512;
 
 enum { kRouteWave = 0, kRouteBig = 1 };
 
-__device__ __forceinline__ int route_of(int32_t kind, int32_t k, int32_t P, int64_t d) {
-    if (kind == kUniform || k <= 0 || k >= P || d <= kWaveMaxD) return kRouteWave;
+__device__ __forceinline__ int route_of(int32_t kind, int32_t k, int32_t P, int64_t d, bool wide) {
+    if (kind == kUniform || k <= 0 || k >= P || (d <= kWaveMaxD && !wide)) return kRouteWave;
     return kRouteBig;
 }
 
-__device__ __forceinline__ int32_t positive_count(const GraphDev& g, int32_t kind, int32_t v, int64_t d) {
+// P (positive biases) and the wide flag of v's list under a bias kind
+__device__ __forceinline__ int32_t positive_count(const GraphDev& g, int32_t kind, int32_t v, int64_t d,
+                                                  bool& wide) {
+    wide = false;
     if (kind == kUniform) return (int32_t)d;
-    return kind == kEdgeWeight ? g.ppos_ew[v] : g.ppos_deg[v];
+    const int32_t x = kind == kEdgeWeight ? g.ppos_ew[v] : g.ppos_deg[v];
+    wide = (x & kWideList) != 0;
+    return x & ~kWideList;
 }
 
 __device__ __forceinline__ int32_t entry_count(const GraphDev& g, int32_t k, int32_t kind, int32_t v,
                                                int32_t& route, int64_t& beg, int64_t& d, SampleCtl* ctl) {
     beg = g.rowptr[v];
     d = g.rowptr[v + 1] - beg;
-    const int32_t P = positive_count(g, kind, v, d);
+    bool wide;
+    const int32_t P = positive_count(g, kind, v, d, wide);
     route = kRouteWave;
     if (k == 0 || P == 0) return 0;
     if (k < 0 || k >= P) return P;
@@ -141,7 +154,7 @@ __device__ __forceinline__ int32_t entry_count(const GraphDev& g, int32_t k, int
         ctl->unsupported = 1;
         return 0;
     }
-    route = route_of(kind, k, P, d);
+    route = route_of(kind, k, P, d, wide);
     return k;
 }
 
@@ -368,19 +381,19 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
 }
 
 // ----------------------------------------------------------------- select
-// Prefix layout used by the inverse transform search of a weighted list:
-// groups of g = 16 consecutive candidates; C[t] = S[t*g] (exclusive prefix
-// at the group starts) and C[nc] = W live in LDS. A search finds the group by binary search in C and
-// the candidate by scanning the group's g weights (from the LDS tile when the
-// whole list is resident there, otherwise from global memory / L2).
+// Lists of the wavefront kernel (weighted d <= kWaveMaxD, and every unbiased
+// list) are searched in registers (draw_resident) or directly (r is the
+// position for unbiased lists). Long lists use a coarse table: groups of
+// g = 16 consecutive candidates, C[t] = S[t*g] (exclusive prefix at the group
+// starts) and C[nc] = W in LDS; a search finds the group by binary search in
+// C and the candidate by scanning the group's weights from global memory / L2.
 //
-// Weights reach LDS in tiles of 1024: 16 coalesced loads per lane are issued
-// together, stored transposed (element i at i + i/16, so that lane L's 16
-// consecutive elements sit in 16 distinct banks), summed per lane, and one
-// 64-lane scan turns the 64 group sums of a tile into 64 entries of C.
+// Chunk reduction stages weights through LDS in tiles of 1024: 16 coalesced
+// loads per lane are issued together, stored transposed (element i at
+// i + i/16, so that lane L's 16 consecutive elements sit in 16 distinct
+// banks) and summed per lane.
 constexpr int kTile = 1024;
 constexpr int kTilePad = kTile + kTile / 16;
-constexpr int kWaveC = kWaveMaxD / 16;     // coarse entries per wavefront
 
 __device__ __forceinline__ int tpad(int i) { return i + (i >> 4); }
 
@@ -390,11 +403,11 @@ struct CoarsePool {
     int64_t g;              // group length
     int64_t d;              // list length
     const uint32_t* w;      // weights of the list in global memory
-    const uint32_t* tile;   // LDS tile holding the whole list, or null
 };
 
 // Scan weights w[i..end) from global memory, 16 loads in flight, for the
-// first candidate whose running total (from acc) exceeds r.
+// first candidate whose running total (from acc) exceeds r: running totals
+// are monotone, so its index in a batch is the number of totals <= r.
 __device__ __forceinline__ void fine_scan_global(const uint32_t* __restrict__ w, int64_t i, int64_t end,
                                                  uint64_t acc, uint64_t r, int64_t& m, uint64_t& Sm,
                                                  uint32_t& bm) {
@@ -402,31 +415,33 @@ __device__ __forceinline__ void fine_scan_global(const uint32_t* __restrict__ w,
     Sm = acc;
     bm = 0;
     for (; i < end; i += 16) {
+        const uint32_t* wp = w + i;
+        const int n = end - i < 16 ? (int)(end - i) : 16;
         uint32_t x[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) x[q] = i + q < end ? w[i + q] : 0u;
-        bool found = false;
+        for (int q = 0; q < 16; ++q) x[q] = q < n ? wp[q] : 0u;
+        int cnt = 0;
+        uint64_t run = acc, before = acc;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            if (!found && i + q < end) {
-                if (acc + x[q] > r) {
-                    m = i + q;
-                    Sm = acc;
-                    bm = x[q];
-                    found = true;
-                } else {
-                    acc += x[q];
-                }
-            }
+            run += x[q];
+            const bool le = run <= r;
+            cnt += le;
+            before = le ? run : before;
         }
-        if (found) break;
+        if (cnt < n) {
+            m = i + cnt;
+            Sm = before;
+            bm = wp[cnt];
+            return;
+        }
+        acc = run;
     }
 }
 
-// m = max{i in [0,d) : S_i <= r} with S_m and b_m; per lane. kResident: the
-// group's weights are read from the LDS copy of the list (pl.tile), otherwise
-// 16 at a time from global memory.
-template <bool kResident>
+// m = max{i in [0,d) : S_i <= r} with S_m and b_m; per lane: binary search
+// for the group in the LDS table C, then the group's weights from global
+// memory / L2.
 __device__ __forceinline__ void coarse_search(const CoarsePool& pl, uint64_t r, int64_t& m, uint64_t& Sm,
                                               uint32_t& bm) {
     int64_t lo = 0, hi = pl.nc;
@@ -435,88 +450,50 @@ __device__ __forceinline__ void coarse_search(const CoarsePool& pl, uint64_t r, 
         if (pl.C[mid] <= r) lo = mid;
         else hi = mid;
     }
-    uint64_t acc = pl.C[lo];
-    int64_t i = lo * pl.g;
+    const int64_t i = lo * pl.g;
     const int64_t end = (i + pl.g < pl.d) ? i + pl.g : pl.d;
-    m = i;
-    Sm = acc;
-    bm = 0;
-    if (kResident) {  // g == 16: one batch of LDS reads
-        uint32_t x[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) x[q] = i + q < end ? pl.tile[tpad((int)(i + q))] : 0u;
-        bool found = false;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if (!found && i + q < end) {
-                if (acc + x[q] > r) {
-                    m = i + q;
-                    Sm = acc;
-                    bm = x[q];
-                    found = true;
-                } else {
-                    acc += x[q];
-                }
-            }
-        }
-        return;
-    }
-    fine_scan_global(pl.w, i, end, acc, r, m, Sm, bm);
+    fine_scan_global(pl.w, i, end, pl.C[lo], r, m, Sm, bm);
 }
 
-// Draw k distinct candidates with one lane per slot (lane j = slot j < k):
-// repeated-sampling rounds where the lowest slot wins a collision, then
-// direct draws from the prefix without the held candidates, in slot order.
-// search(r, m, Sm, bm) is the per-lane inverse transform search.
-//
-// Collisions: with own != null (lists of at most kWaveMaxD candidates) an
-// LDS array holds, per position, -1 once held, else the lowest open slot
-// that picked it this round (ds_min); otherwise each open slot compares with
-// every slot through lane reads.
+// Draw k distinct candidates with one lane per slot (lane j = slot j < k) and
+// a per-lane inverse transform search(r, m, Sm, bm). Each round every open
+// slot draws; taken in slot order, a slot keeps its candidate unless it is
+// already held -- which also covers a lower slot that took the same candidate
+// in this round, so the lowest slot wins. Slots still open after kRounds take
+// direct draws from the prefix without the held candidates, in slot order:
+// r0 in [0, W - held mass), mapped by the skip map (every held candidate whose
+// start in the updated prefix is at or below r0 adds its bias) and searched
+// with search_all (same r on every lane).
 template <class Search, class SearchAll>
-__device__ __forceinline__ int64_t draw_slots2(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k,
-                                               uint64_t W, const Search& search, const SearchAll& search_all,
-                                               int32_t* own = nullptr) {
+__device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k,
+                                              uint64_t W, const Search& search, const SearchAll& search_all) {
     const int lane = lane_id();
-    const bool active = lane < k;
     bool held = false;
     int64_t pos = 0;
     uint64_t Spos = 0;
     uint32_t bpos = 0;
-    for (int a = 0; a < kRounds; ++a) {
-        const bool open = active && !held;
-        if (ballot(open) == 0) break;
+    uint64_t open = k >= kWave ? ~0ull : ((1ull << k) - 1);
+    for (int a = 0; a < kRounds && open; ++a) {
         int64_t m = -1;
         uint64_t Sm = 0;
         uint32_t bm = 0;
-        if (open) search(draw(key, c0, c1, c2, (uint32_t)lane | ((uint32_t)a << 16), W), m, Sm, bm);
-        bool reject = false;
-        if (own) {
-            wave_lds_sync();
-            if (open) atomicMin(&own[m], lane);
-            wave_lds_sync();
-            reject = open && own[m] != lane;
-            wave_lds_sync();
-            if (open && !reject) own[m] = -1;
-        } else {
-            const uint64_t heldmask = ballot(held);
-            const int64_t val = held ? pos : m;
-            for (int q = 0; q < k; ++q) {
-                const int64_t pq = readlane_i64(val, q);
-                const bool qheld = (heldmask >> q) & 1ull;
-                if (q != lane && pq == m && (qheld || q < lane)) reject = true;
+        if ((open >> lane) & 1ull) search(draw(key, c0, c1, c2, (uint32_t)lane | ((uint32_t)a << 16), W), m, Sm, bm);
+        for (uint64_t todo = open; todo; todo &= todo - 1) {
+            const int j = __ffsll((unsigned long long)todo) - 1;
+            const int64_t mj = readlane_i64(m, j);
+            if (ballot(held && pos == mj) == 0) {
+                if (lane == j) {
+                    held = true;
+                    pos = m;
+                    Spos = Sm;
+                    bpos = bm;
+                }
+                open &= ~(1ull << j);
             }
         }
-        if (open && !reject) {
-            held = true;
-            pos = m;
-            Spos = Sm;
-            bpos = bm;
-        }
     }
-    const uint64_t heldmask = ballot(held);
-    uint64_t openmask = ballot(active) & ~heldmask;
-    if (openmask) {
+    if (open) {
+        const uint64_t heldmask = ballot(held);
         // before = total bias of held candidates at smaller positions
         uint64_t before = 0;
         for (uint64_t hm = heldmask; hm; hm &= hm - 1) {
@@ -526,11 +503,9 @@ __device__ __forceinline__ int64_t draw_slots2(Key key, uint32_t c0, uint32_t c1
             if (held && pq < pos) before += bq;
         }
         uint64_t removed = wave_sum_u64(held ? (uint64_t)bpos : 0ull);
-        while (openmask) {
-            const int j = __ffsll((unsigned long long)openmask) - 1;
+        for (; open; open &= open - 1) {
+            const int j = __ffsll((unsigned long long)open) - 1;
             const uint64_t r0 = draw(key, c0, c1, c2, (uint32_t)j | (kFallbackRound << 16), W - removed);
-            // skip map: every held region starting at or below the updated-prefix
-            // position r0 (shifted by the held mass before it) is stepped over
             const uint64_t r = r0 + wave_sum_u64((held && Spos - before <= r0) ? (uint64_t)bpos : 0ull);
             int64_t m = 0;
             uint64_t Sm = 0;
@@ -549,16 +524,101 @@ __device__ __forceinline__ int64_t draw_slots2(Key key, uint32_t c0, uint32_t c1
                 before = bef_new;
             }
             removed += bm;
-            openmask &= openmask - 1;
         }
     }
     return pos;
 }
 
-template <class Search>
-__device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k,
-                                              uint64_t W, const Search& search, int32_t* own = nullptr) {
-    return draw_slots2(key, c0, c1, c2, k, W, search, search, own);
+// Weighted lists of at most 64*E candidates, resident in registers: lane L
+// holds candidates [L*E, L*E+E) and their inclusive prefix S (width T; the
+// wavefront route sends only lists with W < 2^32, so T = 32 bits there). A draw r is resolved by the whole wavefront: the
+// owning lane is the number of lanes whose last prefix is <= r, the position
+// inside it the number of its prefixes <= r. Held candidates are one bit per
+// element in the owning lane. Slots are taken in slot order within a round,
+// as in draw_slots; direct draws rescan the prefix with held weights removed,
+// which is the updated prefix whose inverse the skip map computes.
+template <int E, typename T>
+__device__ __forceinline__ int32_t find_resident(const T (&S)[E], T r) {
+    const int L = __popcll(ballot(S[E - 1] <= r));
+    if (E == 1) return L;
+    int32_t cl = 0;
+#pragma unroll
+    for (int e = 0; e < E - 1; ++e) cl += S[e] <= r ? 1 : 0;
+    return L * E + readlane_i32(cl, L);
+}
+
+template <int E, typename T>
+__device__ __forceinline__ int32_t draw_resident_t(const uint32_t (&x)[E], T excl, T W, Key key, uint32_t c0,
+                                                   uint32_t c1, uint32_t c2, int32_t k) {
+    const int lane = lane_id();
+    T S[E];
+    {
+        T acc = excl;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            acc += (T)x[e];
+            S[e] = acc;
+        }
+    }
+    uint32_t hb = 0;  // held bits of this lane's candidates
+    int32_t pos = 0;
+    uint64_t open = k >= kWave ? ~0ull : ((1ull << k) - 1);
+    for (int a = 0; a < kRounds && open; ++a) {
+        T rl = 0;
+        if ((open >> lane) & 1ull) rl = (T)draw(key, c0, c1, c2, (uint32_t)lane | ((uint32_t)a << 16), (uint64_t)W);
+        for (uint64_t todo = open; todo; todo &= todo - 1) {
+            const int j = __ffsll((unsigned long long)todo) - 1;
+            const int32_t m = find_resident<E, T>(S, readlane_t(rl, j));
+            const int owner = m / E, bit = m % E;
+            if (((readlane_u32(hb, owner) >> bit) & 1u) == 0) {
+                if (lane == owner) hb |= 1u << bit;
+                if (lane == j) pos = m;
+                open &= ~(1ull << j);
+            }
+        }
+    }
+    if (open) {
+        uint64_t u = 0;
+        if ((open >> lane) & 1ull) u = philox_u64(key.k0, key.k1, c0, c1, c2, (uint32_t)lane | (kFallbackRound << 16));
+        for (; open; open &= open - 1) {
+            const int j = __ffsll((unsigned long long)open) - 1;
+            T Sp[E];
+            T ls = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                ls += ((hb >> e) & 1u) ? (T)0 : (T)x[e];
+                Sp[e] = ls;
+            }
+            const T incl = wave_incl_scan_t(ls);
+            const T ex = incl - ls;
+#pragma unroll
+            for (int e = 0; e < E; ++e) Sp[e] += ex;
+            const T Wp = readlane_t(incl, kWave - 1);
+            const T r0 = (T)range_reduce(readlane_u64(u, j), (uint64_t)Wp);
+            const int32_t m = find_resident<E, T>(Sp, r0);
+            if (lane == m / E) hb |= 1u << (m % E);
+            if (lane == j) pos = m;
+        }
+    }
+    return pos;
+}
+
+template <int E>
+__device__ __forceinline__ int32_t draw_resident(const uint32_t* __restrict__ w, int64_t d, Key key, uint32_t c0,
+                                                 uint32_t c1, uint32_t c2, int32_t k) {
+    const int lane = lane_id();
+    uint32_t x[E];
+    uint32_t ls = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t i = (int64_t)lane * E + e;
+        x[e] = i < d ? w[i] : 0u;
+        ls += x[e];
+    }
+    // routing guarantees W < 2^32, so every prefix fits 32 bits
+    const uint32_t incl = wave_incl_scan_u32((uint32_t)ls);
+    const uint32_t W = readlane_u32(incl, kWave - 1);
+    return draw_resident_t<E, uint32_t>(x, incl - (uint32_t)ls, W, key, c0, c1, c2, k);
 }
 
 __device__ __forceinline__ void claim(bool do_claim, const uint32_t* visb, uint32_t* nextb, int32_t x) {
@@ -591,7 +651,7 @@ __device__ __forceinline__ uint64_t tile_group_sums(const uint32_t* __restrict__
 struct EntryInfo {
     int32_t c, v, inst, k, kind, P;
     int64_t o, beg, d;
-    bool do_claim;
+    bool do_claim, wide;
 };
 
 __device__ __forceinline__ bool load_entry(const SampleLayer& p, int64_t e, int64_t out_base, EntryInfo& E) {
@@ -605,8 +665,10 @@ __device__ __forceinline__ bool load_entry(const SampleLayer& p, int64_t e, int6
     E.do_claim = p.fanout_next[E.inst] != 0;
     E.beg = uniform_i64(p.g.rowptr[E.v]);
     E.d = uniform_i64(p.g.rowptr[E.v + 1]) - E.beg;
-    E.P = E.kind == kUniform ? (int32_t)E.d
-                             : uniform_i32(E.kind == kEdgeWeight ? p.g.ppos_ew[E.v] : p.g.ppos_deg[E.v]);
+    const int32_t x = E.kind == kUniform ? (int32_t)E.d
+                                         : uniform_i32(E.kind == kEdgeWeight ? p.g.ppos_ew[E.v] : p.g.ppos_deg[E.v]);
+    E.P = x & ~kWideList;
+    E.wide = (x & kWideList) != 0;
     return true;
 }
 
@@ -625,8 +687,7 @@ __device__ __forceinline__ void emit_slots(const SampleLayer& p, const EntryInfo
     }
 }
 
-__device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, uint32_t* tile, uint64_t* C,
-                             int32_t* own) {
+__device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base) {
     const int lane = lane_id();
     EntryInfo E;
     if (!load_entry(p, e, out_base, E)) return;
@@ -634,7 +695,7 @@ __device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, 
         if (lane == 0) p.ctl->overflow = 1;
         return;
     }
-    if (route_of(E.kind, E.k, E.P, E.d) != kRouteWave) return;  // mid / hub kernels
+    if (route_of(E.kind, E.k, E.P, E.d, E.wide) != kRouteWave) return;  // long-list path
     const uint32_t* visb = p.visited + (int64_t)E.inst * p.nwp;
     uint32_t* nextb = p.next + (int64_t)E.inst * p.nwp;
     const bool weighted = E.kind != kUniform;
@@ -688,49 +749,32 @@ __device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base, 
     const uint32_t c1 = (uint32_t)p.layer;
     const uint32_t c2 = (uint32_t)E.v;
     int64_t pos;
-    int32_t* ownp = nullptr;
-    if (d <= kWaveMaxD) {
-        for (int64_t i = lane; i < d; i += kWave) own[i] = kWave;
-        ownp = own;
-    }
     if (!weighted) {
-        pos = draw_slots(key, c0, c1, c2, E.k, (uint64_t)d,
-                         [](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
-                             m = (int64_t)r;
-                             Sm = r;
-                             bm = 1;
-                         },
-                         ownp);
+        const auto pick = [](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+            m = (int64_t)r;
+            Sm = r;
+            bm = 1;
+        };
+        pos = draw_slots(key, c0, c1, c2, E.k, (uint64_t)d, pick, pick);
+    } else if (d <= 64) {
+        pos = draw_resident<1>(w, d, key, c0, c1, c2, E.k);
+    } else if (d <= 128) {
+        pos = draw_resident<2>(w, d, key, c0, c1, c2, E.k);
+    } else if (d <= 256) {
+        pos = draw_resident<4>(w, d, key, c0, c1, c2, E.k);
     } else {
-        uint64_t carry = 0;
-        if (lane == 0) C[0] = 0;
-        for (int64_t t = 0; t * kTile < d; ++t) {
-            const uint64_t s = tile_group_sums(w, t * kTile, d, tile);
-            const uint64_t incl = wave_incl_scan_u64(s);
-            C[t * kWave + lane + 1] = carry + incl;
-            carry += readlane_u64(incl, kWave - 1);
-        }
-        wave_lds_sync();
-        const CoarsePool pl{C, (d + 15) / 16, 16, d, w, tile};
-        pos = draw_slots(key, c0, c1, c2, E.k, carry,
-                         [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
-                             coarse_search<true>(pl, r, m, Sm, bm);
-                         },
-                         ownp);
+        pos = draw_resident<8>(w, d, key, c0, c1, c2, E.k);
     }
     emit_slots(p, E, pos);
 }
 
 __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
-    __shared__ uint32_t tiles[kWavesPerBlock][kTilePad];
-    __shared__ uint64_t coarse[kWavesPerBlock][kWaveC + 1];
-    __shared__ int32_t owners[kWavesPerBlock][kWaveMaxD];
     const int wid = uniform_i32(threadIdx.x / kWave);
     const int64_t fcount = p.ctl->fcount[p.layer];
     const int64_t out_base = p.ctl->out_base[p.layer];
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t e = blockIdx.x * (int64_t)kWavesPerBlock + wid; e < fcount; e += waves)
-        select_entry(p, e, out_base, tiles[wid], coarse[wid], owners[wid]);
+        select_entry(p, e, out_base);
 }
 
 // ------------------------------------------------------ long-list path
@@ -844,11 +888,11 @@ __device__ void select_big_entry(const SampleLayer& p, int64_t h, int64_t out_ba
         if (lane == 0) tab[0] = 0;
         const uint64_t W = readlane_u64(cincl, (int)nch - 1);
         wave_lds_sync();
-        const CoarsePool pl{tab, nc, 16, d, w, nullptr};
-        pos = draw_slots(key, c0, c1, c2, E.k, W,
-                         [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
-                             coarse_search<false>(pl, r, m, Sm, bm);
-                         });
+        const CoarsePool pl{tab, nc, 16, d, w};
+        const auto search = [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+            coarse_search(pl, r, m, Sm, bm);
+        };
+        pos = draw_slots(key, c0, c1, c2, E.k, W, search, search);
     } else {
         int shift = 0;
         while (((nch + (1ll << shift) - 1) >> shift) > kBigTab) ++shift;
@@ -869,8 +913,10 @@ __device__ void select_big_entry(const SampleLayer& p, int64_t h, int64_t out_ba
         if (lane == 0) tab[0] = 0;
         wave_lds_sync();
         const UnitPool pl{tab, nu, shift, nch, G, w, d};
-        pos = draw_slots(key, c0, c1, c2, E.k, carry,
-                         [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) { unit_search(pl, r, m, Sm, bm); });
+        const auto search = [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+            unit_search(pl, r, m, Sm, bm);
+        };
+        pos = draw_slots(key, c0, c1, c2, E.k, carry, search, search);
     }
     emit_slots(p, E, pos);
     wave_lds_sync();  // the table is rewritten by the wave's next list
@@ -886,13 +932,15 @@ __global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
         select_big_entry(p, h, out_base, tabs[wid]);
 }
 
-__global__ void k_clear_visited(const int32_t* __restrict__ fv, const int32_t* __restrict__ fi,
-                                const int64_t* __restrict__ fcount_p, uint32_t* __restrict__ visited,
-                                int64_t nwp) {
-    const int64_t fcount = *fcount_p;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < fcount;
-         e += (int64_t)gridDim.x * blockDim.x)
-        visited[(int64_t)fi[e] * nwp + (fv[e] >> 5)] = 0u;
+__global__ void k_clear_visited(ClearVisited c) {
+    for (int l = 0; l < c.num_layers; ++l) {
+        const int64_t fcount = c.fcount[l];
+        const int32_t* __restrict__ fv = c.fv[l];
+        const int32_t* __restrict__ fi = c.fi[l];
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < fcount;
+             e += (int64_t)gridDim.x * blockDim.x)
+            c.visited[(int64_t)fi[e] * c.nwp + (fv[e] >> 5)] = 0u;
+    }
 }
 
 }  // namespace
@@ -946,11 +994,9 @@ void launch_select_big(const SampleLayer& p, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_select_big, dim3(grid), dim3(kBlock), 0, s, p);
 }
 
-void launch_clear_visited(const int32_t* fv, const int32_t* fi, const int64_t* fcount, int64_t cap_entries,
-                          uint32_t* visited, int64_t nwp, hipStream_t s) {
-    if (cap_entries <= 0) return;
-    hipLaunchKernelGGL(k_clear_visited, dim3(grid_for(cap_entries, kBlock, 16384)), dim3(kBlock), 0, s, fv,
-                       fi, fcount, visited, nwp);
+void launch_clear_visited(const ClearVisited& c, hipStream_t s) {
+    if (c.cap_entries <= 0 || c.num_layers <= 0) return;
+    hipLaunchKernelGGL(k_clear_visited, dim3(grid_for(c.cap_entries, kBlock, 16384)), dim3(kBlock), 0, s, c);
 }
 
 }  // namespace csaw

@@ -6,13 +6,12 @@
 // independent, so no host round trip is needed between steps.
 //   - unbiased walks: one lane per walker (a step is two row-offset loads,
 //     one Philox draw and one neighbor load);
-//   - biased walks: one wavefront per walker; the wave sums the biases of
-//     N(v) (pass 1), draws r in [0, W), and finds the owning candidate with
-//     chunked inclusive scans and a ballot (pass 2). Biases of the first
-//     kCache*64 neighbors stay in registers between the passes.
+//   - biased walks: one wavefront per walker; pass 1 streams the biases of
+//     N(v) into a coarse prefix table in LDS, r is drawn in [0, W), and pass
+//     2 rescans only the group of the table that holds r (scan + ballot).
 //   - node2vec: the bias of x in N(v) needs "is x adjacent to the previous
-//     vertex t"; adjacency lists are sorted, so each lane binary-searches
-//     N(t).
+//     vertex t"; adjacency lists are sorted, so N(v) is merged with N(t)
+//     (or, for a much longer N(t), each candidate binary-searches it).
 #include "device_common.h"
 #include "kernels.h"
 
@@ -22,7 +21,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kCache = 4;  // register-cached 64-wide chunks per lane
 
 __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
     const Key key{p.k0, p.k1};
@@ -70,38 +68,177 @@ __device__ __forceinline__ bool in_sorted(const int32_t* __restrict__ col, int64
     return lo < e && col[lo] == x;
 }
 
-struct StepBias {
-    int32_t kind;
-    const uint32_t* w;
-    const int32_t* col;
-    uint32_t wr, wc, wo;
-    int32_t t;         // previous vertex, -1 before the first step
-    int64_t tb, te;    // its list
+// Weighted and node2vec steps: one wavefront per walker. Pass 1 streams
+// N(v) in tiles of kWalkTile candidates (kWalkPer coalesced loads per lane),
+// evaluates the biases and records the inclusive prefix at the end of every
+// group of 2^shift tiles in an LDS table (at most kWalkTab groups). After the
+// draw, a binary search in the table finds the group and pass 2 rescans only
+// that group, 64 candidates at a time (scan + ballot).
+// node2vec: x in N(t) is found by merging N(v) with N(t) -- both sorted --
+// through an LDS window of kWalkWin entries of N(t), or, when N(t) is much
+// longer than N(v), by a binary search per candidate; membership of the first
+// kWalkBits candidates is kept as bits for pass 2.
+constexpr int kWalkPer = 4;
+constexpr int kWalkTile = kWalkPer * kWave;   // 256
+constexpr int kWalkTileLog = 8;
+constexpr int kWalkTab = 512;
+constexpr int kWalkWin = 256;
+constexpr int kWalkBits = 32768;
+constexpr int64_t kMergeRatio = 8;              // merge while d_t <= 8 d_v + kWalkWin
+
+template <bool kN2v>
+struct WalkLds {
+    uint64_t tab[kWalkTab + 1];
+    uint32_t bits[kN2v ? kWalkBits / 32 : 1];
+    int32_t win[kN2v ? kWalkWin : 1];
 };
 
-__device__ __forceinline__ uint32_t bias_of(const StepBias& sb, int64_t e) {
-    if (sb.kind == kNode2vec) {
-        if (sb.t < 0) return 1u;
-        const int32_t x = sb.col[e];
-        if (x == sb.t) return sb.wr;
-        return in_sorted(sb.col, sb.tb, sb.te, x) ? sb.wc : sb.wo;
-    }
-    return sb.w[e];
+// lower bound of x in win[0, n), n <= kWalkWin
+__device__ __forceinline__ int32_t win_lower_bound(const int32_t* win, int32_t n, int32_t x) {
+    int32_t pos = 0;
+#pragma unroll
+    for (int step = kWalkWin / 2; step >= 1; step >>= 1)
+        if (pos + step <= n && win[pos + step - 1] < x) pos += step;
+    if (pos < n && win[pos] < x) ++pos;
+    return pos;
 }
 
+template <bool kN2v>
+__device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds<kN2v>& lds, Key key, uint32_t c0,
+                                                    int32_t s, int32_t v, int64_t beg, int64_t d, int32_t t,
+                                                    int64_t tb, int64_t te, bool& stop) {
+    const int lane = lane_id();
+    const int32_t* col = p.g.col;
+    const uint32_t* wts = p.bias == kEdgeWeight ? p.g.ew : p.g.degw;
+    stop = false;
+    int shift = 0;
+    while (((d + ((int64_t)kWalkTile << shift) - 1) >> (kWalkTileLog + shift)) > kWalkTab) ++shift;
+    const int64_t g = (int64_t)kWalkTile << shift;
+    const int64_t ng = (d + g - 1) / g;
+    const bool merge = kN2v && (te - tb) <= kMergeRatio * d + kWalkWin;
+    int64_t jw = tb;  // N(t) window: win[0, wn) = col[jw, jw + wn)
+    int32_t wn = 0;
+    uint64_t run = 0;
+    for (int64_t base = 0; base < d; base += kWalkTile) {
+        uint32_t x[kWalkPer];
+        if (!kN2v) {
+#pragma unroll
+            for (int q = 0; q < kWalkPer; ++q) {
+                const int64_t idx = base + q * kWave + lane;
+                x[q] = idx < d ? wts[beg + idx] : 0u;
+            }
+        } else {
+            int32_t a[kWalkPer];
+            bool open[kWalkPer], found[kWalkPer];
+#pragma unroll
+            for (int q = 0; q < kWalkPer; ++q) {
+                const int64_t idx = base + q * kWave + lane;
+                open[q] = idx < d;
+                a[q] = open[q] ? col[beg + idx] : 0;
+                found[q] = false;
+            }
+            if (merge) {
+                while (true) {
+                    const int32_t wmax = wn > 0 ? lds.win[wn - 1] : INT32_MIN;
+                    bool pending = false;
+#pragma unroll
+                    for (int q = 0; q < kWalkPer; ++q) {
+                        if (open[q] && a[q] <= wmax) {
+                            const int32_t pos = win_lower_bound(lds.win, wn, a[q]);
+                            found[q] = pos < wn && lds.win[pos] == a[q];
+                            open[q] = false;
+                        }
+                        pending |= open[q];
+                    }
+                    if (ballot(pending) == 0) break;
+                    jw += wn;  // every entry of this window is below the open candidates
+                    if (jw >= te) break;
+                    wn = (int32_t)(te - jw < kWalkWin ? te - jw : kWalkWin);
+                    int32_t y[kWalkWin / kWave];
+#pragma unroll
+                    for (int q = 0; q < kWalkWin / kWave; ++q) {
+                        const int i = q * kWave + lane;
+                        y[q] = i < wn ? col[jw + i] : INT32_MAX;
+                    }
+                    wave_lds_sync();
+#pragma unroll
+                    for (int q = 0; q < kWalkWin / kWave; ++q) lds.win[q * kWave + lane] = y[q];
+                    wave_lds_sync();
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < kWalkPer; ++q)
+                    if (open[q]) found[q] = in_sorted(col, tb, te, a[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < kWalkPer; ++q) {
+                const int64_t idx = base + q * kWave + lane;
+                const bool valid = idx < d;
+                x[q] = !valid ? 0u : (a[q] == t ? p.w_return : (found[q] ? p.w_common : p.w_outward));
+                const uint64_t fm = ballot(valid && found[q]);
+                const int64_t i0 = base + q * kWave;
+                if (i0 < kWalkBits && lane < 2) lds.bits[i0 / 32 + lane] = (uint32_t)(fm >> (32 * lane));
+            }
+        }
+        uint64_t ls = 0;
+#pragma unroll
+        for (int q = 0; q < kWalkPer; ++q) ls += x[q];
+        run += wave_sum_u64(ls);
+        const int64_t tile = base >> kWalkTileLog;
+        if (((tile + 1) & ((1ll << shift) - 1)) == 0 || base + kWalkTile >= d)
+            if (lane == 0) lds.tab[(tile >> shift) + 1] = run;
+    }
+    const uint64_t W = run;
+    if (W == 0) {
+        stop = true;
+        return 0;
+    }
+    if (lane == 0) lds.tab[0] = 0;
+    wave_lds_sync();
+    const uint64_t r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+    int64_t lo = 0, hi = ng;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (lds.tab[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    uint64_t acc = lds.tab[lo];
+    const int64_t end = (lo + 1) * g < d ? (lo + 1) * g : d;
+    int64_t m = end - 1;
+    for (int64_t base = lo * g; base < end; base += kWave) {
+        const int64_t idx = base + lane;
+        uint32_t x = 0;
+        if (idx < end) {
+            if (!kN2v) {
+                x = wts[beg + idx];
+            } else {
+                const int32_t a = col[beg + idx];
+                const bool found = idx < kWalkBits ? ((lds.bits[idx >> 5] >> (idx & 31)) & 1u) != 0
+                                                   : in_sorted(col, tb, te, a);
+                x = a == t ? p.w_return : (found ? p.w_common : p.w_outward);
+            }
+        }
+        const uint64_t incl = wave_incl_scan_u64(x);
+        const uint64_t tot = readlane_u64(incl, kWave - 1);
+        if (acc + tot > r) {
+            m = base + __popcll(ballot(acc + incl <= r));
+            break;
+        }
+        acc += tot;
+    }
+    wave_lds_sync();  // the table and bits are rewritten by the next step
+    return m;
+}
+
+template <bool kN2v>
 __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
+    __shared__ WalkLds<kN2v> lds_all[kWavesPerBlock];
     const int lane = lane_id();
     const int wid = uniform_i32(threadIdx.x / kWave);
+    WalkLds<kN2v>& lds = lds_all[wid];
     const Key key{p.k0, p.k1};
     const int64_t L1 = (int64_t)p.length + 1;
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-    StepBias sb;
-    sb.kind = p.bias;
-    sb.w = p.bias == kEdgeWeight ? p.g.ew : p.g.degw;
-    sb.col = p.g.col;
-    sb.wr = p.w_return;
-    sb.wc = p.w_common;
-    sb.wo = p.w_outward;
     for (int64_t w = blockIdx.x * (int64_t)kWavesPerBlock + wid; w < p.num_walkers; w += waves) {
         int32_t* path = p.paths + w * L1;
         int32_t v = uniform_i32(p.starts[w]);
@@ -112,54 +249,26 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
         }
         if (lane == 0) path[0] = v;
         const uint32_t c0 = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
-        sb.t = -1;
-        sb.tb = sb.te = 0;
+        int32_t t = -1;
+        int64_t tb = 0, te = 0;
         int32_t s = 0;
         for (; s < p.length; ++s) {
             const int64_t beg = uniform_i64(p.g.rowptr[v]);
             const int64_t d = uniform_i64(p.g.rowptr[v + 1]) - beg;
             if (d == 0) break;
-            // pass 1: total bias (first kCache chunks kept in registers)
-            uint32_t cache[kCache];
-            uint64_t part = 0;
-#pragma unroll
-            for (int c = 0; c < kCache; ++c) {
-                const int64_t idx = (int64_t)c * kWave + lane;
-                cache[c] = idx < d ? bias_of(sb, beg + idx) : 0u;
-                part += cache[c];
-            }
-            for (int64_t idx = (int64_t)kCache * kWave + lane; idx < d; idx += kWave) part += bias_of(sb, beg + idx);
-            const uint64_t W = wave_sum_u64(part);
-            if (W == 0) break;
-            const uint64_t r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
-            // pass 2: first chunk whose inclusive prefix passes r
-            uint64_t acc = 0;
-            int64_t m = 0;
-            for (int64_t base = 0; base < d; base += kWave) {
-                const int64_t idx = base + lane;
-                const int64_t c = base / kWave;
-                uint32_t x;
-                if (c < kCache) {
-                    x = cache[0];
-#pragma unroll
-                    for (int q = 1; q < kCache; ++q)
-                        if (c == q) x = cache[q];
-                } else {
-                    x = idx < d ? bias_of(sb, beg + idx) : 0u;
-                }
-                const uint64_t incl = wave_incl_scan_u64(x);
-                const uint64_t tot = readlane_u64(incl, kWave - 1);
-                if (acc + tot > r) {
-                    m = base + __popcll(ballot(acc + incl <= r));
-                    break;
-                }
-                acc += tot;
+            int64_t m;
+            if (kN2v && t < 0) {  // first step: no previous vertex, every bias is 1
+                m = (int64_t)draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, (uint64_t)d);
+            } else {
+                bool stop;
+                m = walk_step_biased<kN2v>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
+                if (stop) break;
             }
             const int32_t nx = uniform_i32(p.g.col[beg + m]);
             if (lane == 0) path[s + 1] = nx;
-            sb.t = v;
-            sb.tb = beg;
-            sb.te = beg + d;
+            t = v;
+            tb = beg;
+            te = beg + d;
             v = nx;
         }
         for (int64_t q = s + 1 + lane; q < L1; q += kWave) path[q] = -1;
@@ -180,7 +289,8 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s) {
     } else {
         int64_t g = (p.num_walkers + kWavesPerBlock - 1) / kWavesPerBlock;
         if (g > grid) g = grid;
-        hipLaunchKernelGGL(k_walk_wave, dim3((unsigned)g), dim3(kBlock), 0, s, p);
+        if (p.bias == kNode2vec) hipLaunchKernelGGL(k_walk_wave<true>, dim3((unsigned)g), dim3(kBlock), 0, s, p);
+        else hipLaunchKernelGGL(k_walk_wave<false>, dim3((unsigned)g), dim3(kBlock), 0, s, p);
     }
 }
 

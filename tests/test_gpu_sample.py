@@ -226,9 +226,10 @@ def test_degree_biased_rmat22_full(csaw):
 def test_route_boundaries(csaw):
     """Weighted lists at the lengths where the kernels hand over (wavefront
     kernel / long-list path with a group-level table / with a chunk-level
-    table): 1024, 1025, 8192, 8193, plus short ones, with zero weights and
-    dominant weights, many instances and fanouts up to 64."""
-    degs = [16, 1024, 1025, 8192, 8193, 20000]
+    table): 512, 513, 8192, 8193, plus short ones, with zero weights and
+    dominant weights; two short lists (64, 300) have a total weight above
+    2^32 and take the long-list path. Many instances, fanouts up to 64."""
+    degs = [16, 64, 300, 512, 513, 1024, 1025, 8192, 8193, 20000]
     hubs = len(degs)
     n = hubs + max(degs)
     rng = inputs.rng(17)
@@ -240,6 +241,11 @@ def test_route_boundaries(csaw):
     ew = rng.integers(0, 300, size=len(col)).astype(np.uint32)
     ew[rng.random(len(col)) < 0.2] = 0
     ew[rng.random(len(col)) < 0.002] = 1 << 24
+    for h in (1, 2):   # the lists of length 64 and 300: total weight >= 2^32
+        a, b = rp[h], rp[h + 1]
+        ew[a:b] = rng.integers(1 << 27, 1 << 32, size=b - a, dtype=np.uint64).astype(np.uint32)
+        ew[a:b][rng.random(b - a) < 0.2] = 0
+        assert int(ew[a:b].astype(np.uint64).sum()) >= 1 << 32
     g = csaw.Graph(rp, col, ew)
     ni = 4 * hubs
     offs = np.arange(ni + 1, dtype=np.int64)

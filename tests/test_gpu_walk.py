@@ -62,6 +62,28 @@ def test_walk_hubs(csaw):
     run_both(csaw, g, rp, col, inputs.dst_outdeg_weights(rp, col), starts, 20, 1, 2)
 
 
+def test_node2vec_long_list_membership(csaw):
+    """A hub adjacent to 40,000 leaves that form a ring: from the hub with a
+    leaf as previous vertex, the common neighbors are the leaf's two ring
+    neighbors, and for leaves past position 32,768 of the hub's list pass 2
+    recomputes membership instead of reading kept bits. Merge (hub after a
+    leaf) and per-candidate search (leaf after the hub) both occur."""
+    nl = 40_000
+    hub = 0
+    edges = []
+    for i in range(1, nl + 1):
+        edges.append((hub, i))
+        edges.append((i, hub))
+        j = i % nl + 1
+        edges.append((i, j))
+        edges.append((j, i))
+    rp, col = inputs.csr_from_edges(nl + 1, edges)
+    g = csaw.Graph(rp, col)
+    starts = np.arange(1, nl + 1, 7, dtype=np.int32)
+    run_both(csaw, g, rp, col, None, starts, 24, 3, 4, node2vec=(1, 2, 4))
+    run_both(csaw, g, rp, col, None, starts, 24, 3, 5, node2vec=(4, 1, 2))
+
+
 def test_walk_edge_cases(csaw):
     rp = np.array([0, 1, 1], dtype=np.int64)
     col = np.array([1], dtype=np.int32)

@@ -268,3 +268,57 @@ def test_skewed_list_reaches_direct_draw():
         assert len(set(pos.tolist())) == 5 and 0 in pos
         total_fb += fb
     assert total_fb > 0
+
+
+def _select_from_definition(b, k, seed, c0, c1, c2, rounds=8):
+    """Selection written from its definition, with the independent Philox:
+    rounds where slots are taken in slot order and a slot keeps its candidate
+    unless it is already held, then direct draws in slot order, each an
+    inverse transform search of the prefix rebuilt with held biases removed
+    (the updated-sampling law that the skip map inverts)."""
+    b = np.asarray(b, dtype=np.uint64)
+    P = int((b > 0).sum())
+    if k >= P:
+        return [i for i in range(len(b)) if b[i] > 0]
+    S = np.cumsum(b)
+    W = int(S[-1])
+    held, pos, open_ = set(), [None] * k, list(range(k))
+    for a in range(rounds):
+        nxt = []
+        for j in open_:
+            m = int(np.searchsorted(S, torch_philox.draw(seed, [c0, c1, c2, j | (a << 16)], W), side="right"))
+            if m in held:
+                nxt.append(j)
+            else:
+                held.add(m)
+                pos[j] = m
+        open_ = nxt
+    for j in open_:
+        bp = b.copy()
+        bp[list(held)] = 0
+        Sp = np.cumsum(bp)
+        m = int(np.searchsorted(Sp, torch_philox.draw(seed, [c0, c1, c2, j | (0xFFFF << 16)], int(Sp[-1])),
+                                side="right"))
+        held.add(m)
+        pos[j] = m
+    return pos
+
+
+def test_select_equals_definition_with_rebuilt_prefix():
+    """The whole selection, including many direct draws (skewed lists with k
+    close to P), equals the definition above bit for bit."""
+    g = np.random.Generator(np.random.PCG64(14))
+    fallbacks = 0
+    for t in range(160):
+        d = int(g.integers(2, 60))
+        b = _random_weights(g, d, zero_frac=0.2, hi=50)
+        if t % 2 == 0:
+            b[g.integers(0, d, size=3)] = int(g.integers(1000, 1 << 20))
+        P = int((b > 0).sum())
+        if P == 0:
+            continue
+        k = int(g.integers(1, min(P + 2, 64) + 1))
+        pos, fb = oracle.select(b, k, 21, t, 4, 8, with_fallback=True)
+        assert pos.tolist() == _select_from_definition(b, k, 21, t, 4, 8)
+        fallbacks += fb
+    assert fallbacks > 80
