@@ -9,7 +9,6 @@ namespace csaw {
 constexpr int kMaxLayers = 16;
 constexpr int kMaxDrawFanout = 64;   // slots of one wave
 constexpr int kRounds = 8;           // repeated-sampling rounds
-constexpr int kScanItems = 1024;     // items per scan block (256 threads x 4)
 constexpr int kChunk = 1024;         // weights per chunk of a long list
 constexpr int kChunkGroups = 64;     // 16-weight groups per chunk
 constexpr int32_t kWideList = (int32_t)0x80000000u;  // ppos flag: the list's total weight is >= 2^32
@@ -32,7 +31,6 @@ struct SampleCtl {
     int64_t fcount[kMaxLayers + 1];    // frontier sizes
     int64_t total[kMaxLayers];         // edges per layer
     int64_t out_base[kMaxLayers + 1];  // first edge of each layer
-    unsigned long long tickets[kMaxLayers];  // block order of the frontier builds
     unsigned long long nbig[kMaxLayers];    // long weighted lists per layer
     unsigned long long nchunk[kMaxLayers];  // their 1024-weight chunks (may exceed chunk_cap)
     int32_t bad_seed;
@@ -41,14 +39,16 @@ struct SampleCtl {
     int32_t lookback_stuck;
 };
 
+static_assert(sizeof(SampleCtl) % 4 == 0, "control block is copied in 32-bit words");
+
 // One frontier build: next bitmap -> sorted frontier entries with their edge
 // counts, edge offsets, kernel routes and per-instance segment offsets.
 struct FrontierBuild {
     GraphDev g;
-    uint4* next4;
-    uint4* visited4;
-    int64_t n4;                      // uint4 groups of all bitmaps
-    int64_t nwp4;                    // uint4 groups per instance
+    uint32_t* next;
+    uint32_t* visited;
+    int64_t nwords;                  // words of all instances' bitmaps
+    int64_t nwp;                     // words per instance
     int64_t nb;                      // blocks of the launch
     int32_t layer;
     int32_t num_layers;
@@ -109,12 +109,17 @@ struct ClearVisited {
     const int32_t* fv[kMaxLayers + 1];
     const int32_t* fi[kMaxLayers + 1];
     const int64_t* fcount;           // device: entries per layer
+    const SampleCtl* ctl;            // final control block of the call ...
+    SampleCtl* host_ctl;             // ... copied here (host memory, device address)
     int32_t num_layers;
     int64_t cap_entries;             // largest frontier capacity (grid sizing)
     uint32_t* visited;
     int64_t nwp;
 };
 void launch_clear_visited(const ClearVisited& c, hipStream_t s);
+// Start of a call: zero ctl[0, nctl) and copy tab[0, ntab) words from host memory.
+void launch_call_setup(uint32_t* ctl, int64_t nctl, const uint32_t* host_tab, uint32_t* tab, int64_t ntab,
+                       hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 
 // --- graph preparation (sample_kernels.hip)

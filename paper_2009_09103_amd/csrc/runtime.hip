@@ -82,7 +82,8 @@ struct Workspace {
     size_t arena_cap = 0;
     uint32_t* bitmaps = nullptr;  // visited | next, zero between calls
     size_t bitmap_words = 0;
-    char* pinned = nullptr;
+    char* pinned = nullptr;        // fine-grained host memory: kernels read and write it directly
+    char* pinned_dev = nullptr;    // its device address
     size_t pinned_cap = 0;
     // side stream for the long-list kernels, forked from and joined back into
     // the caller's stream with events (default priority)
@@ -233,7 +234,8 @@ csaw_status ensure_pinned(Workspace* w, size_t bytes) {
     w->pinned = nullptr;
     w->pinned_cap = 0;
     const size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 16);
-    HIP_OR_FAIL(hipHostMalloc((void**)&w->pinned, cap, hipHostMallocDefault));
+    HIP_OR_FAIL(hipHostMalloc((void**)&w->pinned, cap, hipHostMallocCoherent | hipHostMallocMapped));
+    HIP_OR_FAIL(hipHostGetDevicePointer((void**)&w->pinned_dev, w->pinned, 0));
     w->pinned_cap = cap;
     return CSAW_OK;
 }
@@ -572,15 +574,17 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     SampleCtl* h_ctl = (SampleCtl*)(H + o_hctl);
     // every device step of the call, enqueued on stream s
     auto enqueue = [&](hipStream_t s) -> csaw_status {
-        launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)ctl_words, s);
-        HIP_OR_FAIL(hipMemcpyAsync(A + o_tab, H, tab_bytes, hipMemcpyHostToDevice, s));
+        // one kernel clears the control block and look-back words and copies
+        // the table block straight from host memory
+        launch_call_setup((uint32_t*)ctl, (int64_t)ctl_words, (const uint32_t*)ws->pinned_dev,
+                          (uint32_t*)(A + o_tab), (int64_t)(tab_bytes / 4), s);
 
         FrontierBuild fb;
         fb.g = g->dev();
-        fb.next4 = (uint4*)next;
-        fb.visited4 = (uint4*)visited;
-        fb.n4 = words / 4;
-        fb.nwp4 = nwp / 4;
+        fb.next = next;
+        fb.visited = visited;
+        fb.nwords = words;
+        fb.nwp = nwp;
         fb.nb = nb_build;
         fb.num_layers = L;
         fb.num_instances = ni;
@@ -666,6 +670,8 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             ClearVisited cl{};
             cl.num_layers = computed_layers;
             cl.fcount = ctl->fcount;
+            cl.ctl = ctl;
+            cl.host_ctl = (SampleCtl*)(ws->pinned_dev + o_hctl);
             cl.visited = visited;
             cl.nwp = nwp;
             for (int l = 0; l < computed_layers; ++l) {
@@ -676,8 +682,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             launch_clear_visited(cl, s);
         }
         HIP_OR_FAIL(hipGetLastError());
-        HIP_OR_FAIL(hipMemcpyAsync(h_ctl, ctl, sizeof(SampleCtl), hipMemcpyDeviceToHost, s));
-    return CSAW_OK;
+        return CSAW_OK;
     };
 
     // A layer whose long lists need more chunk scratch than the workspace holds

@@ -27,35 +27,6 @@ inline int grid_for(int64_t items, int per_block, int cap = 1 << 20) {
     return (int)g;
 }
 
-// ----------------------------------------------------------- block helpers
-// Exclusive scan of one int64 per thread over a block of kThreads threads;
-// returns the exclusive prefix and writes the block total to *total. Every
-// thread of the block must call it.
-template <int kThreads = kBlock>
-__device__ __forceinline__ int64_t block_excl_scan_i64(int64_t x, int64_t* total) {
-    constexpr int kW = kThreads / kWave;
-    __shared__ int64_t wsum[kW];
-    const int lane = lane_id();
-    const int wid = threadIdx.x / kWave;
-    const uint64_t incl = wave_incl_scan_u64((uint64_t)x);
-    if (lane == kWave - 1) wsum[wid] = (int64_t)incl;
-    __syncthreads();
-    int64_t base = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kW; ++w) {
-        const int64_t s = wsum[w];
-        if (w < wid) base += s;
-        tot += s;
-    }
-    __syncthreads();
-    *total = tot;
-    return base + (int64_t)incl - x;
-}
-
-__device__ __forceinline__ int popc4(uint4 w) {
-    return __popc(w.x) + __popc(w.y) + __popc(w.z) + __popc(w.w);
-}
-
 // ------------------------------------------------------------------ misc
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
@@ -179,79 +150,116 @@ __device__ __forceinline__ uint64_t status_load(unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Next set bit of a 128-bit mask (lo, hi), or -1.
-__device__ __forceinline__ int32_t pop_bit(uint64_t& lo, uint64_t& hi) {
-    if (lo) {
-        const int32_t b = __ffsll((unsigned long long)lo) - 1;
-        lo &= lo - 1;
-        return b;
-    }
-    if (hi) {
-        const int32_t b = __ffsll((unsigned long long)hi) - 1;
-        hi &= hi - 1;
-        return 64 + b;
-    }
-    return -1;
+// Next set bit of a word (cleared from it), or -1.
+__device__ __forceinline__ int32_t pop_bit(uint32_t& bits) {
+    if (!bits) return -1;
+    const int32_t b = __ffs(bits) - 1;
+    bits &= bits - 1;
+    return b;
 }
 
-// Frontier build of one layer, one pass: every block takes the next 1024
-// bitmap words in ticket order; each thread counts its set bits (entries)
-// and their edge counts min(k, P) (edges); a block scan plus a decoupled
-// look-back over the blocks before it give global positions; then the thread
-// writes its entries in (instance, vertex) order with count, edge offset and
-// route, sets visited |= next, clears next, and the first word of an instance
-// writes that instance's segment offset. The last block writes the layer's
-// totals and the output base of the next layer.
-__global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
-    __shared__ int64_t s_ticket, s_base_e, s_base_g;
-    const int tid = threadIdx.x;
-    if (tid == 0) s_ticket = (int64_t)atomicAdd(&fb.ctl->tickets[fb.layer], 1ull);
-    __syncthreads();
-    const int64_t b = s_ticket;
-    const int64_t i4 = b * kBlock + tid;
-    const bool valid = i4 < fb.n4;
-    uint4 w = make_uint4(0, 0, 0, 0);
-    int64_t inst = 0, local4 = 0;
-    int32_t k = 0, kind = 0;
-    if (valid) {
-        w = fb.next4[i4];
-        inst = i4 / fb.nwp4;
-        local4 = i4 - inst * fb.nwp4;
-        k = fb.fanout[inst];
-        kind = fb.bias[inst];
+// Exclusive scans of four int64 per thread over the block in one pass (one
+// pair of barriers); totals in tot[0..3]. Every thread must call it.
+__device__ __forceinline__ void block_excl_scan4(int64_t (&x)[4], int64_t (&tot)[4]) {
+    constexpr int kW = kBlock / kWave;
+    __shared__ int64_t wsum[4][kW];
+    const int lane = lane_id();
+    const int wid = threadIdx.x / kWave;
+    uint64_t incl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        incl[j] = wave_incl_scan_u64((uint64_t)x[j]);
+        if (lane == kWave - 1) wsum[j][wid] = (int64_t)incl[j];
     }
-    const uint64_t lo0 = (uint64_t)w.x | ((uint64_t)w.y << 32);
-    const uint64_t hi0 = (uint64_t)w.z | ((uint64_t)w.w << 32);
-    const int32_t vbase = (int32_t)(local4 * 128);
-    const int64_t ne = __popcll(lo0) + __popcll(hi0);
-    int64_t ng = 0, nbig = 0, nchk = 0;
-    {
-        uint64_t lo = lo0, hi = hi0;
-        while (lo | hi) {  // four bits at a time so that their loads overlap
-            int32_t bv[4];
+    __syncthreads();
 #pragma unroll
-            for (int t = 0; t < 4; ++t) bv[t] = pop_bit(lo, hi);
+    for (int j = 0; j < 4; ++j) {
+        int64_t base = 0, t = 0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                int32_t route;
-                int64_t beg, d;
-                if (bv[t] >= 0) {
-                    ng += entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, fb.ctl);
-                    if (route == kRouteBig) {
-                        ++nbig;
-                        nchk += chunks_of(d);
-                    }
-                }
-            }
+        for (int w = 0; w < kW; ++w) {
+            const int64_t v = wsum[j][w];
+            if (w < wid) base += v;
+            t += v;
+        }
+        tot[j] = t;
+        x[j] = base + (int64_t)incl[j] - x[j];
+    }
+    __syncthreads();
+}
+
+// Frontier build of one layer, one pass: block b takes bitmap words
+// [256 b, 256 b + 256), one per thread; each thread counts its set bits
+// (entries), their edge counts min(k, P) (edges) and their long-list route;
+// a block scan plus a decoupled look-back over the blocks before it give
+// global positions (blocks are dispatched in index order, so predecessors
+// are resident or done; the spin is bounded and reports instead of
+// hanging). The thread then writes its entries in (instance, vertex) order
+// with count, edge offset and route, sets visited |= next, clears next, and
+// the first word of an instance writes that instance's segment offset. The
+// last block writes the layer's totals and the output base of the next layer.
+__global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
+    __shared__ int64_t s_base_e, s_base_g;
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t iw = b * kBlock + tid;
+    const bool valid = iw < fb.nwords;
+    uint32_t w = 0, vis = 0;
+    int64_t inst = 0, local = 0;
+    int32_t k = 0, kind = 0;
+    const int64_t out_base = fb.ctl->out_base[fb.layer];
+    if (valid) {
+        w = fb.next[iw];
+        vis = fb.visited[iw];
+        inst = iw / fb.nwp;
+        local = iw - inst * fb.nwp;
+        if (w) {
+            k = fb.fanout[inst];
+            kind = fb.bias[inst];
         }
     }
-    int64_t tot_e, tot_g, tot_big, tot_chk;
-    const int64_t ex_e = block_excl_scan_i64(ne, &tot_e);
-    const int64_t ex_g = block_excl_scan_i64(ng, &tot_g);
-    int64_t ex_big = block_excl_scan_i64(nbig, &tot_big);
-    int64_t ex_chk = block_excl_scan_i64(nchk, &tot_chk);
+    const int32_t vbase = (int32_t)(local * 32);
+    // the first four entries' counts stay in registers for the write pass
+    int32_t cc[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0};
+    int64_t cbeg[4] = {0, 0, 0, 0}, cd[4] = {0, 0, 0, 0};
+    int64_t cnt4[4] = {__popc(w), 0, 0, 0};  // entries, edges, long lists, chunks
+    {
+        uint32_t bits = w;
+        bool first = true;
+        while (bits) {  // four bits at a time so that their loads overlap
+            int32_t bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bv[t] = pop_bit(bits);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int32_t route = kRouteWave;
+                int64_t beg = 0, d = 0;
+                int32_t c = 0;
+                if (bv[t] >= 0) {
+                    c = entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, fb.ctl);
+                    cnt4[1] += c;
+                    if (route == kRouteBig) {
+                        ++cnt4[2];
+                        cnt4[3] += chunks_of(d);
+                    }
+                }
+                if (first) {
+                    cc[t] = c;
+                    cr[t] = route;
+                    cbeg[t] = beg;
+                    cd[t] = d;
+                }
+            }
+            first = false;
+        }
+    }
+    int64_t tot4[4];
+    int64_t ex4[4] = {cnt4[0], cnt4[1], cnt4[2], cnt4[3]};
+    block_excl_scan4(ex4, tot4);
+    const int64_t ex_e = ex4[0], ex_g = ex4[1];
+    int64_t ex_big = ex4[2], ex_chk = ex4[3];
+    const int64_t tot_e = tot4[0], tot_g = tot4[1], tot_big = tot4[2], tot_chk = tot4[3];
     __shared__ int64_t s_big_base, s_chk_base;
-    if (tid == 0) {  // one reservation per block for its long lists and their chunks
+    if (tid == kWave) {  // wave 1: one reservation per block for its long lists and their chunks
         s_big_base = tot_big ? (int64_t)atomicAdd(&fb.ctl->nbig[fb.layer], (unsigned long long)tot_big) : 0;
         s_chk_base = tot_chk ? (int64_t)atomicAdd(&fb.ctl->nchunk[fb.layer], (unsigned long long)tot_chk) : 0;
     }
@@ -314,25 +322,32 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
         }
     }
     __syncthreads();
-    const int64_t out_base = fb.ctl->out_base[fb.layer];
     int64_t pos = s_base_e + ex_e;
     int64_t eoff = s_base_g + ex_g;
     if (valid) {
-        if (local4 == 0 && fb.offsets && fb.layer < fb.num_layers)
+        if (local == 0 && fb.offsets && fb.layer < fb.num_layers)
             fb.offsets[(int64_t)fb.layer * fb.num_instances + inst] = out_base + eoff;
-        if (lo0 | hi0) {
-            uint64_t lo = lo0, hi = hi0;
-            while (lo | hi) {
+        if (w) {
+            uint32_t bits = w;
+            bool first = true;
+            while (bits) {
                 int32_t bv[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) bv[t] = pop_bit(lo, hi);
+                for (int t = 0; t < 4; ++t) bv[t] = pop_bit(bits);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     if (bv[t] < 0) continue;
                     const int32_t v = vbase + bv[t];
-                    int32_t route;
+                    int32_t route, c;
                     int64_t beg, d;
-                    const int32_t c = entry_count(fb.g, k, kind, v, route, beg, d, fb.ctl);
+                    if (first) {
+                        c = cc[t];
+                        route = cr[t];
+                        beg = cbeg[t];
+                        d = cd[t];
+                    } else {
+                        c = entry_count(fb.g, k, kind, v, route, beg, d, fb.ctl);
+                    }
                     fb.fv[pos] = v;
                     fb.fi[pos] = (int32_t)inst;
                     fb.cnt[pos] = c;
@@ -355,11 +370,10 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                     ++pos;
                     eoff += c;
                 }
+                first = false;
             }
-            uint4 vis = fb.visited4[i4];
-            vis.x |= w.x; vis.y |= w.y; vis.z |= w.z; vis.w |= w.w;
-            fb.visited4[i4] = vis;
-            fb.next4[i4] = make_uint4(0, 0, 0, 0);
+            fb.visited[iw] = vis | w;
+            fb.next[iw] = 0u;
         }
     }
     if (b == fb.nb - 1) {  // last block: totals, and the bases of the layers after this one
@@ -372,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
         }
         if (fb.offsets) {
             const int64_t ni = fb.num_instances;
-            const int64_t first = fb.nwp4 > 0 ? fb.layer + 1 : fb.layer;
+            const int64_t first = fb.nwp > 0 ? fb.layer + 1 : fb.layer;
             for (int64_t j = first; j < fb.num_layers; ++j)
                 for (int64_t i = tid; i < ni; i += kBlock) fb.offsets[j * ni + i] = (j == fb.layer ? out_base : ob);
             if (tid == 0) fb.offsets[(int64_t)fb.num_layers * ni] = ob;
@@ -932,7 +946,23 @@ __global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
         select_big_entry(p, h, out_base, tabs[wid]);
 }
 
+__global__ void k_call_setup(uint32_t* __restrict__ ctl, int64_t nctl, const uint32_t* __restrict__ host_tab,
+                             uint32_t* __restrict__ tab, int64_t ntab) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nctl; i += stride) ctl[i] = 0u;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntab; i += stride) tab[i] = host_tab[i];
+}
+
+// End of a call: clear the visited bits of every frontier entry, and hand
+// the control block to the host.
 __global__ void k_clear_visited(ClearVisited c) {
+    if (blockIdx.x == 0) {
+        constexpr int kWords = (int)(sizeof(SampleCtl) / 4);
+        const uint32_t* from = (const uint32_t*)c.ctl;
+        uint32_t* to = (uint32_t*)c.host_ctl;
+        for (int i = threadIdx.x; i < kWords; i += blockDim.x) to[i] = from[i];
+        __threadfence_system();
+    }
     for (int l = 0; l < c.num_layers; ++l) {
         const int64_t fcount = c.fcount[l];
         const int32_t* __restrict__ fv = c.fv[l];
@@ -973,8 +1003,7 @@ void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* s
 }
 
 int64_t frontier_build_blocks(int64_t words) {
-    const int64_t n4 = words / 4;
-    const int64_t nb = (n4 + kBlock - 1) / kBlock;
+    const int64_t nb = (words + kBlock - 1) / kBlock;
     return nb > 0 ? nb : 1;
 }
 
@@ -995,8 +1024,13 @@ void launch_select_big(const SampleLayer& p, int grid, hipStream_t s) {
 }
 
 void launch_clear_visited(const ClearVisited& c, hipStream_t s) {
-    if (c.cap_entries <= 0 || c.num_layers <= 0) return;
     hipLaunchKernelGGL(k_clear_visited, dim3(grid_for(c.cap_entries, kBlock, 16384)), dim3(kBlock), 0, s, c);
+}
+
+void launch_call_setup(uint32_t* ctl, int64_t nctl, const uint32_t* host_tab, uint32_t* tab, int64_t ntab,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_call_setup, dim3(grid_for(nctl > ntab ? nctl : ntab, kBlock, 1024)), dim3(kBlock), 0, s,
+                       ctl, nctl, host_tab, tab, ntab);
 }
 
 }  // namespace csaw

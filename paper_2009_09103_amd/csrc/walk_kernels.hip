@@ -69,21 +69,24 @@ __device__ __forceinline__ bool in_sorted(const int32_t* __restrict__ col, int64
 }
 
 // Weighted and node2vec steps: one wavefront per walker. Pass 1 streams
-// N(v) in tiles of kWalkTile candidates (kWalkPer coalesced loads per lane),
+// N(v) in tiles of kWalkTile candidates (kWalkPer coalesced loads per lane,
+// the next tile's loads in flight while the current one is processed),
 // evaluates the biases and records the inclusive prefix at the end of every
 // group of 2^shift tiles in an LDS table (at most kWalkTab groups). After the
 // draw, a binary search in the table finds the group and pass 2 rescans only
 // that group, 64 candidates at a time (scan + ballot).
 // node2vec: x in N(t) is found by merging N(v) with N(t) -- both sorted --
-// through an LDS window of kWalkWin entries of N(t), or, when N(t) is much
-// longer than N(v), by a binary search per candidate; membership of the first
-// kWalkBits candidates is kept as bits for pass 2.
+// through an LDS window of kWalkWin entries of N(t) (the following window is
+// prefetched into registers), or, when N(t) is much longer than N(v), by a
+// binary search per candidate; membership of the first kWalkBits candidates
+// is kept as bits for pass 2.
 constexpr int kWalkPer = 4;
 constexpr int kWalkTile = kWalkPer * kWave;   // 256
 constexpr int kWalkTileLog = 8;
-constexpr int kWalkTab = 512;
+constexpr int kWalkTab = 256;
 constexpr int kWalkWin = 256;
-constexpr int kWalkBits = 32768;
+constexpr int kWinPer = kWalkWin / kWave;
+constexpr int kWalkBits = 16384;
 constexpr int64_t kMergeRatio = 8;              // merge while d_t <= 8 d_v + kWalkWin
 
 template <bool kN2v>
@@ -103,6 +106,17 @@ __device__ __forceinline__ int32_t win_lower_bound(const int32_t* win, int32_t n
     return pos;
 }
 
+// N(t) window loads: entries [at, at + kWalkWin) of col, clipped to te
+__device__ __forceinline__ void load_window(const int32_t* __restrict__ col, int64_t at, int64_t te,
+                                            int32_t (&y)[kWinPer]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int q = 0; q < kWinPer; ++q) {
+        const int64_t i = at + q * kWave + lane;
+        y[q] = i < te ? col[i] : INT32_MAX;
+    }
+}
+
 template <bool kN2v>
 __device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds<kN2v>& lds, Key key, uint32_t c0,
                                                     int32_t s, int32_t v, int64_t beg, int64_t d, int32_t t,
@@ -110,6 +124,8 @@ __device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds
     const int lane = lane_id();
     const int32_t* col = p.g.col;
     const uint32_t* wts = p.bias == kEdgeWeight ? p.g.ew : p.g.degw;
+    // pass 1 reads weights (first-order) or neighbor ids (node2vec)
+    const uint32_t* src = kN2v ? (const uint32_t*)col + beg : wts + beg;
     stop = false;
     int shift = 0;
     while (((d + ((int64_t)kWalkTile << shift) - 1) >> (kWalkTileLog + shift)) > kWalkTab) ++shift;
@@ -118,23 +134,32 @@ __device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds
     const bool merge = kN2v && (te - tb) <= kMergeRatio * d + kWalkWin;
     int64_t jw = tb;  // N(t) window: win[0, wn) = col[jw, jw + wn)
     int32_t wn = 0;
+    int32_t ynext[kWinPer];
+    if (merge) load_window(col, jw, te, ynext);
+    uint32_t cur[kWalkPer], nxt[kWalkPer];
+#pragma unroll
+    for (int q = 0; q < kWalkPer; ++q) {
+        const int64_t idx = q * kWave + lane;
+        cur[q] = idx < d ? src[idx] : 0u;
+    }
     uint64_t run = 0;
     for (int64_t base = 0; base < d; base += kWalkTile) {
+#pragma unroll
+        for (int q = 0; q < kWalkPer; ++q) {  // next tile in flight
+            const int64_t idx = base + kWalkTile + q * kWave + lane;
+            nxt[q] = idx < d ? src[idx] : 0u;
+        }
         uint32_t x[kWalkPer];
         if (!kN2v) {
 #pragma unroll
-            for (int q = 0; q < kWalkPer; ++q) {
-                const int64_t idx = base + q * kWave + lane;
-                x[q] = idx < d ? wts[beg + idx] : 0u;
-            }
+            for (int q = 0; q < kWalkPer; ++q) x[q] = cur[q];
         } else {
             int32_t a[kWalkPer];
             bool open[kWalkPer], found[kWalkPer];
 #pragma unroll
             for (int q = 0; q < kWalkPer; ++q) {
-                const int64_t idx = base + q * kWave + lane;
-                open[q] = idx < d;
-                a[q] = open[q] ? col[beg + idx] : 0;
+                open[q] = base + q * kWave + lane < d;
+                a[q] = (int32_t)cur[q];
                 found[q] = false;
             }
             if (merge) {
@@ -154,16 +179,11 @@ __device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds
                     jw += wn;  // every entry of this window is below the open candidates
                     if (jw >= te) break;
                     wn = (int32_t)(te - jw < kWalkWin ? te - jw : kWalkWin);
-                    int32_t y[kWalkWin / kWave];
-#pragma unroll
-                    for (int q = 0; q < kWalkWin / kWave; ++q) {
-                        const int i = q * kWave + lane;
-                        y[q] = i < wn ? col[jw + i] : INT32_MAX;
-                    }
                     wave_lds_sync();
 #pragma unroll
-                    for (int q = 0; q < kWalkWin / kWave; ++q) lds.win[q * kWave + lane] = y[q];
+                    for (int q = 0; q < kWinPer; ++q) lds.win[q * kWave + lane] = ynext[q];
                     wave_lds_sync();
+                    load_window(col, jw + wn, te, ynext);  // the window after it, in flight
                 }
             } else {
 #pragma unroll
@@ -187,6 +207,8 @@ __device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds
         const int64_t tile = base >> kWalkTileLog;
         if (((tile + 1) & ((1ll << shift) - 1)) == 0 || base + kWalkTile >= d)
             if (lane == 0) lds.tab[(tile >> shift) + 1] = run;
+#pragma unroll
+        for (int q = 0; q < kWalkPer; ++q) cur[q] = nxt[q];
     }
     const uint64_t W = run;
     if (W == 0) {
