@@ -177,7 +177,8 @@ def bench_degree_biased(args):
                    "seeds": int(len(seeds)), "fanouts": rec["fanouts"], "bias": "out-degree of neighbor",
                    "rng_seeds": rng_seeds, "edges_per_step": float(np.mean(list(edges_of.values())))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("traffic_select_degree_biased_rmat22.md"),
                      "kernel": "select_wave (k_select)", "launches": sel_n,
                      "avg_launch_us": sel_ms / max(sel_n, 1) * 1e3,
                      "alg_bytes_per_launch": alg["select_wave"] / max(sel_n, 1)},
@@ -348,6 +349,61 @@ def bench_node2vec(args):
     }
 
 
+def bench_copy(args):
+    """A plain device-to-device copy of 1 GiB (torch), K times: the known
+    byte count that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(max(args.warmup, 1)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    return {"metric": "device copy bandwidth (read + write)", "value": 2 * nbytes / dt / 1e9, "unit": "GB/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "copy_1GiB", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes}}
+
+
+KERNEL_SOURCES = ("paper_2009_09103_amd/csrc/sample_kernels.hip", "paper_2009_09103_amd/csrc/device_common.h",
+                  "paper_2009_09103_amd/csrc/kernels.h")
+
+
+def kernel_source_sha(files=KERNEL_SOURCES):
+    import hashlib
+    h = hashlib.sha256()
+    for name in files:
+        with open(os.path.join(ROOT, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(record):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel sources have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", record)
+    if not os.path.exists(path):
+        return None
+    sha = kernel_source_sha()
+    fields = {}
+    with open(path) as f:
+        for ln in f:
+            if ":" in ln and ln.startswith("- "):
+                k, v = ln[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +435,8 @@ def main():
         line = bench_served(args)
     elif args.workload == "node2vec":
         line = bench_node2vec(args)
+    elif args.workload == "copy":
+        line = bench_copy(args)
     else:
         print("unknown workload %s" % args.workload, file=sys.stderr)
         sys.exit(2)

@@ -1,6 +1,7 @@
 // kernels.h -- host-side launchers of the gfx950 kernels (internal to libcsaw).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -59,6 +60,9 @@ struct FrontierBuild {
     int32_t* fi;
     int32_t* cnt;
     int64_t* off;
+    int64_t* fbeg;                   // per entry: first edge of its list
+    int32_t* fdeg;                   // per entry: list length
+    int32_t* fpos;                   // per entry: positive biases | kWideList (list length if unbiased)
     int32_t* bigs;                   // long-list entries (frontier positions)
     int64_t* big_cb;                 // first chunk of each long list
     uint64_t* chunks;                // [chunk_cap] chunk records
@@ -81,6 +85,9 @@ struct SampleLayer {
     const int32_t* fi;               // frontier instance indices
     const int32_t* cnt;              // per-entry edge count
     const int64_t* off;              // per-entry exclusive offset
+    const int64_t* fbeg;             // per-entry first edge of its list
+    const int32_t* fdeg;             // per-entry list length
+    const int32_t* fpos;             // per-entry positive biases | kWideList
     const int32_t* bigs;             // long weighted lists (frontier positions)
     const int64_t* big_cb;           // first chunk of each long list
     const uint64_t* chunks;          // chunk records: start | (len-1) << 40 | degree-bias bit 50
@@ -95,15 +102,28 @@ struct SampleLayer {
     int64_t nwp;                     // bitmap words per instance (multiple of 4)
 };
 
+// Optional events that a launch fills with its kernel's own start and stop
+// times (hipExtLaunchKernel), for kernel timing without dispatch latency.
+// Only profiled calls pass them; those run eagerly, never under capture.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+template <class... A>
+inline void launch_kernel(void (*kernel)(A...), dim3 grid, dim3 block, hipStream_t s, LaunchEvents ev, A... args) {
+    if (ev.start || ev.stop) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev.start, ev.stop, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 // --- sampling (sample_kernels.hip)
 void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* seed_offsets,
                        int32_t ni, int64_t n, uint32_t* next, int64_t nwp, SampleCtl* ctl,
                        hipStream_t s);
 int64_t frontier_build_blocks(int64_t words);
-void launch_frontier_build(const FrontierBuild& fb, hipStream_t s);
-void launch_select(const SampleLayer& p, int grid, hipStream_t s);
-void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s);
-void launch_select_big(const SampleLayer& p, int grid, hipStream_t s);
+void launch_frontier_build(const FrontierBuild& fb, hipStream_t s, LaunchEvents ev = {});
+void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
+void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
+void launch_select_big(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
 // Clears the visited bits of every frontier entry of the call's layers.
 struct ClearVisited {
     const int32_t* fv[kMaxLayers + 1];
@@ -116,7 +136,7 @@ struct ClearVisited {
     uint32_t* visited;
     int64_t nwp;
 };
-void launch_clear_visited(const ClearVisited& c, hipStream_t s);
+void launch_clear_visited(const ClearVisited& c, hipStream_t s, LaunchEvents ev = {});
 // Start of a call: zero ctl[0, nctl) and copy tab[0, ntab) words from host memory.
 void launch_call_setup(uint32_t* ctl, int64_t nctl, const uint32_t* host_tab, uint32_t* tab, int64_t ntab,
                        hipStream_t s);
@@ -143,6 +163,6 @@ struct WalkParams {
     unsigned long long* steps;       // device counter
     int32_t* bad_start;              // device flag
 };
-void launch_walk(const WalkParams& p, int grid, hipStream_t s);
+void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev = {});
 
 }  // namespace csaw

@@ -53,24 +53,38 @@ std::atomic<bool> g_prof{false};
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof_recs;
 
+// Timing of a scope while profiling is on. A scope around one kernel hands
+// its events to the launch (ev()), which fills them with the kernel's own
+// start and stop; a scope around several launches records them on the stream.
 struct ProfScope {
     const char* name;
     hipStream_t s;
-    hipEvent_t a = nullptr;
-    ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
-        if (g_prof.load(std::memory_order_relaxed)) {
-            if (hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
-            else a = nullptr;
+    bool kernel;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(const char* n, hipStream_t st, bool one_kernel = false) : name(n), s(st), kernel(one_kernel) {
+        if (!g_prof.load(std::memory_order_relaxed)) return;
+        if (hipEventCreate(&a) != hipSuccess) {
+            a = nullptr;
+            return;
         }
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = b = nullptr;
+            return;
+        }
+        if (!kernel) (void)hipEventRecord(a, s);
+    }
+    LaunchEvents ev() const {
+        LaunchEvents e;
+        if (kernel && a) {
+            e.start = a;
+            e.stop = b;
+        }
+        return e;
     }
     ~ProfScope() {
         if (!a) return;
-        hipEvent_t b;
-        if (hipEventCreate(&b) != hipSuccess) {
-            (void)hipEventDestroy(a);
-            return;
-        }
-        (void)hipEventRecord(b, s);
+        if (!kernel) (void)hipEventRecord(b, s);
         std::lock_guard<std::mutex> lk(g_prof_mu);
         g_prof_recs.push_back({name, a, b});
     }
@@ -524,6 +538,9 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     const size_t o_tab = cv.take<char>(tab_bytes);
     const size_t o_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_off = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
+    const size_t o_fbeg = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
+    const size_t o_fdeg = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
+    const size_t o_fpos = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_bigs = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_bigcb = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
     std::vector<size_t> o_fv(L + 1), o_fi(L + 1);
@@ -591,6 +608,9 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         fb.bias = d_bias;
         fb.cnt = d_cnt;
         fb.off = d_off;
+        fb.fbeg = (int64_t*)(A + o_fbeg);
+        fb.fdeg = (int32_t*)(A + o_fdeg);
+        fb.fpos = (int32_t*)(A + o_fpos);
         fb.bigs = (int32_t*)(A + o_bigs);
         fb.big_cb = (int64_t*)(A + o_bigcb);
         fb.chunks = ws->chunkbuf;
@@ -598,17 +618,17 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         fb.offsets = out->offsets;
         fb.ctl = ctl;
         fb.status = d_status;
-        auto build = [&](int32_t l) {
+        auto build = [&](int32_t l, LaunchEvents ev) {
             fb.layer = l;
             fb.fanout = d_fan + (size_t)l * ni;
             fb.fv = (int32_t*)(A + o_fv[l]);
             fb.fi = (int32_t*)(A + o_fi[l]);
-            launch_frontier_build(fb, s);
+            launch_frontier_build(fb, s, ev);
         };
         {
             ProfScope ps("frontier_init", s);
             launch_mark_seeds(a->seeds, P.total_seeds, d_soff, ni, g->n, next, nwp, ctl, s);
-            build(0);
+            build(0, LaunchEvents{});
         }
         SampleLayer p;
         p.g = g->dev();
@@ -618,6 +638,9 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         p.bias = d_bias;
         p.cnt = d_cnt;
         p.off = d_off;
+        p.fbeg = (const int64_t*)(A + o_fbeg);
+        p.fdeg = (const int32_t*)(A + o_fdeg);
+        p.fpos = (const int32_t*)(A + o_fpos);
         p.bigs = (const int32_t*)(A + o_bigs);
         p.big_cb = (const int64_t*)(A + o_bigcb);
         p.chunks = ws->chunkbuf;
@@ -644,29 +667,32 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             HIP_OR_FAIL(hipStreamWaitEvent(ws->aux, ws->fork, 0));
             if (big_path) {
                 {
-                    ProfScope ps("chunk_prefix", ws->aux);
-                    launch_chunk_prefix(p, (int)std::min<int64_t>((ws->chunk_cap + 3) / 4, 4096), ws->aux);
+                    ProfScope ps("chunk_prefix", ws->aux, true);
+                    launch_chunk_prefix(p, (int)std::min<int64_t>((ws->chunk_cap + 3) / 4, 4096), ws->aux, ps.ev());
                 }
                 {
-                    ProfScope ps("select_big", ws->aux);
-                    launch_select_big(p, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), ws->aux);
+                    ProfScope ps("select_big", ws->aux, true);
+                    launch_select_big(p, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), ws->aux,
+                                      ps.ev());
                 }
             }
             {
-                ProfScope ps("select_wave", s);
+                ProfScope ps("select_wave", s, true);
+                // more wavefronts than resident slots (the dispatcher balances them),
+                // each taking a short run of consecutive entries
                 const int grid = (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 4096);
-                launch_select(p, grid, s);
+                launch_select(p, grid, s, ps.ev());
             }
             HIP_OR_FAIL(hipEventRecord(ws->join, ws->aux));
             HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join, 0));
             if (l + 1 < L && P.fcap[l + 1] > 0) {
-                ProfScope ps("frontier_build", s);
-                build(l + 1);
+                ProfScope ps("frontier_build", s, true);
+                build(l + 1, ps.ev());
                 computed_layers = l + 2;
             }
         }
         {
-            ProfScope ps("visited_clear", s);
+            ProfScope ps("visited_clear", s, true);
             ClearVisited cl{};
             cl.num_layers = computed_layers;
             cl.fcount = ctl->fcount;
@@ -679,7 +705,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
                 cl.fi[l] = (const int32_t*)(A + o_fi[l]);
                 cl.cap_entries = std::max(cl.cap_entries, P.fcap[l]);
             }
-            launch_clear_visited(cl, s);
+            launch_clear_visited(cl, s, ps.ev());
         }
         HIP_OR_FAIL(hipGetLastError());
         return CSAW_OK;
@@ -779,8 +805,8 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int
     p.steps = d_steps;
     p.bad_start = d_bad;
     {
-        ProfScope ps(a->bias_kind == kNode2vec ? "walk_node2vec" : "walk", s);
-        launch_walk(p, 65536, s);
+        ProfScope ps(a->bias_kind == kNode2vec ? "walk_node2vec" : "walk", s, true);
+        launch_walk(p, 65536, s, ps.ev());
     }
     HIP_OR_FAIL(hipGetLastError());
     HIP_OR_FAIL(hipMemcpyAsync(ws->pinned, ws->arena, 512, hipMemcpyDeviceToHost, s));

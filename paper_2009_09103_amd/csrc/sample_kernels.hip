@@ -102,22 +102,21 @@ __device__ __forceinline__ int route_of(int32_t kind, int32_t k, int32_t P, int6
     return kRouteBig;
 }
 
-// P (positive biases) and the wide flag of v's list under a bias kind
-__device__ __forceinline__ int32_t positive_count(const GraphDev& g, int32_t kind, int32_t v, int64_t d,
-                                                  bool& wide) {
-    wide = false;
+// Positive biases of v's list with the kWideList flag (the list length if
+// unbiased).
+__device__ __forceinline__ int32_t positive_info(const GraphDev& g, int32_t kind, int32_t v, int64_t d) {
     if (kind == kUniform) return (int32_t)d;
-    const int32_t x = kind == kEdgeWeight ? g.ppos_ew[v] : g.ppos_deg[v];
-    wide = (x & kWideList) != 0;
-    return x & ~kWideList;
+    return kind == kEdgeWeight ? g.ppos_ew[v] : g.ppos_deg[v];
 }
 
 __device__ __forceinline__ int32_t entry_count(const GraphDev& g, int32_t k, int32_t kind, int32_t v,
-                                               int32_t& route, int64_t& beg, int64_t& d, SampleCtl* ctl) {
+                                               int32_t& route, int64_t& beg, int64_t& d, int32_t& pinfo,
+                                               SampleCtl* ctl) {
     beg = g.rowptr[v];
     d = g.rowptr[v + 1] - beg;
-    bool wide;
-    const int32_t P = positive_count(g, kind, v, d, wide);
+    pinfo = positive_info(g, kind, v, d);
+    const int32_t P = pinfo & ~kWideList;
+    const bool wide = (pinfo & kWideList) != 0;
     route = kRouteWave;
     if (k == 0 || P == 0) return 0;
     if (k < 0 || k >= P) return P;
@@ -203,13 +202,14 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     const int64_t b = blockIdx.x;
     const int64_t iw = b * kBlock + tid;
     const bool valid = iw < fb.nwords;
-    uint32_t w = 0, vis = 0;
+    uint32_t w = 0, vis = 0, raw = 0;
     int64_t inst = 0, local = 0;
     int32_t k = 0, kind = 0;
     const int64_t out_base = fb.ctl->out_base[fb.layer];
     if (valid) {
-        w = fb.next[iw];
         vis = fb.visited[iw];
+        raw = fb.next[iw];
+        w = raw & ~vis;  // picks of visited vertices are not new
         inst = iw / fb.nwp;
         local = iw - inst * fb.nwp;
         if (w) {
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     }
     const int32_t vbase = (int32_t)(local * 32);
     // the first four entries' counts stay in registers for the write pass
-    int32_t cc[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0};
+    int32_t cc[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0}, cp[4] = {0, 0, 0, 0};
     int64_t cbeg[4] = {0, 0, 0, 0}, cd[4] = {0, 0, 0, 0};
     int64_t cnt4[4] = {__popc(w), 0, 0, 0};  // entries, edges, long lists, chunks
     {
@@ -231,11 +231,11 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
             for (int t = 0; t < 4; ++t) bv[t] = pop_bit(bits);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                int32_t route = kRouteWave;
+                int32_t route = kRouteWave, pinfo = 0;
                 int64_t beg = 0, d = 0;
                 int32_t c = 0;
                 if (bv[t] >= 0) {
-                    c = entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, fb.ctl);
+                    c = entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, pinfo, fb.ctl);
                     cnt4[1] += c;
                     if (route == kRouteBig) {
                         ++cnt4[2];
@@ -245,6 +245,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                 if (first) {
                     cc[t] = c;
                     cr[t] = route;
+                    cp[t] = pinfo;
                     cbeg[t] = beg;
                     cd[t] = d;
                 }
@@ -338,20 +339,24 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                 for (int t = 0; t < 4; ++t) {
                     if (bv[t] < 0) continue;
                     const int32_t v = vbase + bv[t];
-                    int32_t route, c;
+                    int32_t route, c, pinfo;
                     int64_t beg, d;
                     if (first) {
                         c = cc[t];
                         route = cr[t];
+                        pinfo = cp[t];
                         beg = cbeg[t];
                         d = cd[t];
                     } else {
-                        c = entry_count(fb.g, k, kind, v, route, beg, d, fb.ctl);
+                        c = entry_count(fb.g, k, kind, v, route, beg, d, pinfo, fb.ctl);
                     }
                     fb.fv[pos] = v;
                     fb.fi[pos] = (int32_t)inst;
                     fb.cnt[pos] = c;
                     fb.off[pos] = eoff;
+                    fb.fbeg[pos] = beg;
+                    fb.fdeg[pos] = (int32_t)d;
+                    fb.fpos[pos] = pinfo;
                     if (route == kRouteBig) {
                         const int64_t bi = s_big_base + ex_big++;
                         const int64_t cb = s_chk_base + ex_chk;
@@ -373,8 +378,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                 first = false;
             }
             fb.visited[iw] = vis | w;
-            fb.next[iw] = 0u;
         }
+        if (raw) fb.next[iw] = 0u;  // also words that held only visited picks
     }
     if (b == fb.nb - 1) {  // last block: totals, and the bases of the layers after this one
         const int64_t te = s_base_e + tot_e, tg = s_base_g + tot_g;
@@ -635,10 +640,15 @@ __device__ __forceinline__ int32_t draw_resident(const uint32_t* __restrict__ w,
     return draw_resident_t<E, uint32_t>(x, incl - (uint32_t)ls, W, key, c0, c1, c2, k);
 }
 
+// A picked neighbor joins the instance's next bitmap unless it is visited or
+// already there: picks concentrate on hubs, and skipping those atomics keeps
+// them from queueing on a few hot words. (The frontier build also masks
+// visited vertices.)
 __device__ __forceinline__ void claim(bool do_claim, const uint32_t* visb, uint32_t* nextb, int32_t x) {
     if (!do_claim) return;
     const uint32_t bit = 1u << (x & 31);
-    if (!(visb[x >> 5] & bit)) atomicOr(&nextb[x >> 5], bit);
+    const int64_t wd = x >> 5;
+    if (!((visb[wd] | nextb[wd]) & bit)) atomicOr(&nextb[wd], bit);
 }
 
 // Load one tile of up to 1024 weights (from list offset base) into an LDS
@@ -666,29 +676,59 @@ struct EntryInfo {
     int32_t c, v, inst, k, kind, P;
     int64_t o, beg, d;
     bool do_claim, wide;
+    uint64_t key;
+    uint32_t c0;
 };
 
-__device__ __forceinline__ bool load_entry(const SampleLayer& p, int64_t e, int64_t out_base, EntryInfo& E) {
-    E.c = uniform_i32(p.cnt[e]);
-    if (E.c == 0) return false;
-    E.v = uniform_i32(p.fv[e]);
-    E.inst = uniform_i32(p.fi[e]);
-    E.o = out_base + uniform_i64(p.off[e]);
-    E.k = uniform_i32(p.fanout[E.inst]);
-    E.kind = uniform_i32(p.bias[E.inst]);
-    E.do_claim = p.fanout_next[E.inst] != 0;
-    E.beg = uniform_i64(p.g.rowptr[E.v]);
-    E.d = uniform_i64(p.g.rowptr[E.v + 1]) - E.beg;
-    const int32_t x = E.kind == kUniform ? (int32_t)E.d
-                                         : uniform_i32(E.kind == kEdgeWeight ? p.g.ppos_ew[E.v] : p.g.ppos_deg[E.v]);
-    E.P = x & ~kWideList;
-    E.wide = (x & kWideList) != 0;
-    return true;
+// A run of up to 64 consecutive frontier entries, one per lane: the entry's
+// fields are read coalesced, then its instance's tables, so a wavefront pays
+// two memory round trips for the whole run instead of several per entry.
+struct EntryRun {
+    int32_t c, v, inst, pinfo, k, kind, do_claim, c0;
+    int32_t d;
+    int64_t o, beg;
+    uint64_t key;
+};
+
+__device__ __forceinline__ void load_run(const SampleLayer& p, int64_t e, bool valid, int64_t out_base,
+                                         EntryRun& R) {
+    R.c = valid ? p.cnt[e] : 0;
+    R.v = valid ? p.fv[e] : 0;
+    R.inst = valid ? p.fi[e] : 0;
+    R.o = valid ? out_base + p.off[e] : 0;
+    R.beg = valid ? p.fbeg[e] : 0;
+    R.d = valid ? p.fdeg[e] : 0;
+    R.pinfo = valid ? p.fpos[e] : 0;
+    R.k = R.kind = R.do_claim = 0;
+    R.c0 = 0;
+    R.key = 0;
+    if (R.c) {
+        R.k = p.fanout[R.inst];
+        R.kind = p.bias[R.inst];
+        R.do_claim = p.fanout_next[R.inst] != 0;
+        R.key = p.inst_key[R.inst];
+        R.c0 = p.inst_id[R.inst];
+    }
 }
 
-__device__ __forceinline__ Key inst_key(const SampleLayer& p, int32_t inst) {
-    const uint64_t seed = p.inst_key[inst];
-    return Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
+// The fields of run entry j, wave-uniform.
+__device__ __forceinline__ EntryInfo run_entry(const EntryRun& R, int j) {
+    EntryInfo E;
+    E.c = readlane_i32(R.c, j);
+    E.v = readlane_i32(R.v, j);
+    E.inst = readlane_i32(R.inst, j);
+    E.o = readlane_i64(R.o, j);
+    E.beg = readlane_i64(R.beg, j);
+    E.d = readlane_i32(R.d, j);
+    const int32_t pinfo = readlane_i32(R.pinfo, j);
+    E.P = pinfo & ~kWideList;
+    E.wide = (pinfo & kWideList) != 0;
+    E.k = readlane_i32(R.k, j);
+    E.kind = readlane_i32(R.kind, j);
+    E.do_claim = readlane_i32(R.do_claim, j) != 0;
+    E.key = readlane_u64(R.key, j);
+    E.c0 = readlane_u32(R.c0, j);
+    return E;
 }
 
 __device__ __forceinline__ void emit_slots(const SampleLayer& p, const EntryInfo& E, int64_t pos) {
@@ -701,10 +741,9 @@ __device__ __forceinline__ void emit_slots(const SampleLayer& p, const EntryInfo
     }
 }
 
-__device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base) {
+__device__ void select_entry(const SampleLayer& p, const EntryInfo& E) {
     const int lane = lane_id();
-    EntryInfo E;
-    if (!load_entry(p, e, out_base, E)) return;
+    if (E.c == 0) return;
     if (E.o + E.c > p.capacity) {
         if (lane == 0) p.ctl->overflow = 1;
         return;
@@ -757,9 +796,8 @@ __device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base) 
     }
 
     // ---- k < P <= d: draw k distinct candidates (k <= kMaxDrawFanout)
-    const uint64_t seed = p.inst_key[E.inst];
-    const Key key{(uint32_t)seed, (uint32_t)(seed >> 32)};
-    const uint32_t c0 = p.inst_id[E.inst];
+    const Key key{(uint32_t)E.key, (uint32_t)(E.key >> 32)};
+    const uint32_t c0 = E.c0;
     const uint32_t c1 = (uint32_t)p.layer;
     const uint32_t c2 = (uint32_t)E.v;
     int64_t pos;
@@ -782,13 +820,25 @@ __device__ void select_entry(const SampleLayer& p, int64_t e, int64_t out_base) 
     emit_slots(p, E, pos);
 }
 
+// Each wavefront takes a contiguous share of the frontier (a short run when
+// the grid has more wavefronts than resident slots), loaded 64 entries at a
+// time.
 __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
     const int wid = uniform_i32(threadIdx.x / kWave);
+    const int lane = lane_id();
     const int64_t fcount = p.ctl->fcount[p.layer];
     const int64_t out_base = p.ctl->out_base[p.layer];
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t e = blockIdx.x * (int64_t)kWavesPerBlock + wid; e < fcount; e += waves)
-        select_entry(p, e, out_base);
+    const int64_t wave = blockIdx.x * (int64_t)kWavesPerBlock + wid;
+    const int64_t per = (fcount + waves - 1) / waves;
+    const int64_t lo = wave * per < fcount ? wave * per : fcount;
+    const int64_t hi = lo + per < fcount ? lo + per : fcount;
+    for (int64_t e0 = lo; e0 < hi; e0 += kWave) {
+        const int n = (int)(hi - e0 < kWave ? hi - e0 : kWave);
+        EntryRun R;
+        load_run(p, e0 + lane, lane < n, out_base, R);
+        for (int j = 0; j < n; ++j) select_entry(p, run_entry(R, j));
+    }
 }
 
 // ------------------------------------------------------ long-list path
@@ -868,22 +918,20 @@ __device__ __forceinline__ void unit_search(const UnitPool& pl, uint64_t r, int6
 constexpr int kBigTab = 512;
 constexpr int64_t kGroupTabD = (int64_t)kBigTab * 16;
 
-__device__ void select_big_entry(const SampleLayer& p, int64_t h, int64_t out_base, uint64_t* tab) {
+__device__ void select_big_entry(const SampleLayer& p, const EntryInfo& E, int64_t cb, uint64_t* tab) {
     const int lane = lane_id();
-    EntryInfo E;
-    if (!load_entry(p, p.bigs[h], out_base, E)) return;
+    if (E.c == 0) return;
     if (E.o + E.c > p.capacity) {
         if (lane == 0) p.ctl->overflow = 1;
         return;
     }
-    const int64_t cb = uniform_i64(p.big_cb[h]);
     const int64_t d = E.d;
     const int64_t nch = chunks_of(d);
     if (cb + nch > p.chunk_cap) return;  // no scratch room this time; the call is repeated
     const uint32_t* w = (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg;
     const uint64_t* G = p.G + cb * kChunkGroups;
-    const Key key = inst_key(p, E.inst);
-    const uint32_t c0 = p.inst_id[E.inst], c1 = (uint32_t)p.layer, c2 = (uint32_t)E.v;
+    const Key key{(uint32_t)E.key, (uint32_t)(E.key >> 32)};
+    const uint32_t c0 = E.c0, c1 = (uint32_t)p.layer, c2 = (uint32_t)E.v;
     int64_t pos;
     if (d <= kGroupTabD) {
         const int64_t nc = (d + 15) / 16;
@@ -939,11 +987,23 @@ __device__ void select_big_entry(const SampleLayer& p, int64_t h, int64_t out_ba
 __global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
     __shared__ uint64_t tabs[kWavesPerBlock][kBigTab + 1];
     const int wid = uniform_i32(threadIdx.x / kWave);
+    const int lane = lane_id();
     const int64_t nb = (int64_t)p.ctl->nbig[p.layer];
     const int64_t out_base = p.ctl->out_base[p.layer];
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t h = blockIdx.x * (int64_t)kWavesPerBlock + wid; h < nb; h += waves)
-        select_big_entry(p, h, out_base, tabs[wid]);
+    const int64_t wave = blockIdx.x * (int64_t)kWavesPerBlock + wid;
+    const int64_t per = (nb + waves - 1) / waves;
+    const int64_t lo = wave * per < nb ? wave * per : nb;
+    const int64_t hi = lo + per < nb ? lo + per : nb;
+    for (int64_t h0 = lo; h0 < hi; h0 += kWave) {
+        const int n = (int)(hi - h0 < kWave ? hi - h0 : kWave);
+        const bool valid = lane < n;
+        const int64_t pos = valid ? p.bigs[h0 + lane] : 0;
+        const int64_t cb = valid ? p.big_cb[h0 + lane] : 0;
+        EntryRun R;
+        load_run(p, pos, valid, out_base, R);
+        for (int j = 0; j < n; ++j) select_big_entry(p, run_entry(R, j), readlane_i64(cb, j), tabs[wid]);
+    }
 }
 
 __global__ void k_call_setup(uint32_t* __restrict__ ctl, int64_t nctl, const uint32_t* __restrict__ host_tab,
@@ -1007,24 +1067,24 @@ int64_t frontier_build_blocks(int64_t words) {
     return nb > 0 ? nb : 1;
 }
 
-void launch_frontier_build(const FrontierBuild& fb, hipStream_t s) {
-    hipLaunchKernelGGL(k_frontier_build, dim3((unsigned)fb.nb), dim3(kBlock), 0, s, fb);
+void launch_frontier_build(const FrontierBuild& fb, hipStream_t s, LaunchEvents ev) {
+    launch_kernel(k_frontier_build, dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
 }
 
-void launch_select(const SampleLayer& p, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_select, dim3(grid), dim3(kBlock), 0, s, p);
+void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
+    launch_kernel(k_select, dim3(grid), dim3(kBlock), s, ev, p);
 }
 
-void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_chunk_prefix, dim3(grid), dim3(kBlock), 0, s, p);
+void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
+    launch_kernel(k_chunk_prefix, dim3(grid), dim3(kBlock), s, ev, p);
 }
 
-void launch_select_big(const SampleLayer& p, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_big, dim3(grid), dim3(kBlock), 0, s, p);
+void launch_select_big(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
+    launch_kernel(k_select_big, dim3(grid), dim3(kBlock), s, ev, p);
 }
 
-void launch_clear_visited(const ClearVisited& c, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_visited, dim3(grid_for(c.cap_entries, kBlock, 16384)), dim3(kBlock), 0, s, c);
+void launch_clear_visited(const ClearVisited& c, hipStream_t s, LaunchEvents ev) {
+    launch_kernel(k_clear_visited, dim3(grid_for(c.cap_entries, kBlock, 16384)), dim3(kBlock), s, ev, c);
 }
 
 void launch_call_setup(uint32_t* ctl, int64_t nctl, const uint32_t* host_tab, uint32_t* tab, int64_t ntab,

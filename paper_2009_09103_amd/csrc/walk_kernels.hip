@@ -300,19 +300,21 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
 
 }  // namespace
 
-void launch_walk(const WalkParams& p, int grid, hipStream_t s) {
+void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev) {
     if (p.num_walkers <= 0) return;
     const bool flat_n2v = p.bias == kNode2vec && p.w_return == p.w_common && p.w_common == p.w_outward &&
                           p.w_return > 0;
     if (p.bias == kUniform || flat_n2v) {
         int64_t g = (p.num_walkers + kBlock - 1) / kBlock;
         if (g > grid) g = grid;
-        hipLaunchKernelGGL(k_walk_uniform, dim3((unsigned)g), dim3(kBlock), 0, s, p);
+        launch_kernel(k_walk_uniform, dim3((unsigned)g), dim3(kBlock), s, ev, p);
     } else {
         int64_t g = (p.num_walkers + kWavesPerBlock - 1) / kWavesPerBlock;
         if (g > grid) g = grid;
-        if (p.bias == kNode2vec) hipLaunchKernelGGL(k_walk_wave<true>, dim3((unsigned)g), dim3(kBlock), 0, s, p);
-        else hipLaunchKernelGGL(k_walk_wave<false>, dim3((unsigned)g), dim3(kBlock), 0, s, p);
+        if (p.bias == kNode2vec)
+            launch_kernel(k_walk_wave<true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+        else
+            launch_kernel(k_walk_wave<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
     }
 }
 

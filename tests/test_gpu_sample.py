@@ -299,6 +299,25 @@ def test_replay_key_covers_bias_kind(csaw):
         assert_same(res, ref)
 
 
+def test_visited_picks_leave_no_trace(csaw):
+    """Dense graph (cliques of 40): most picks of the second layer are
+    already visited. The next bitmap must come back all-zero, so the calls
+    that follow (other seeds, other sizes) still match the oracle."""
+    n, clique = 4000, 40
+    edges = []
+    for c0 in range(0, n, clique):
+        for u in range(c0, c0 + clique):
+            for v in range(c0, c0 + clique):
+                if u != v:
+                    edges.append((u, v))
+    rp, col = inputs.csr_from_edges(n, edges)
+    g = csaw.Graph(rp, col)
+    say("visited picks, repeated calls")
+    for seed_rng, ns, fan in ((1, 300, [20, 20, 20]), (2, 50, [30, 5]), (3, 800, [10, 10, 10])):
+        offs, seeds = inputs.single_instance_seeds(rp, col, ns, seed_rng)
+        run_both(csaw, g, rp, col, None, offs, seeds, fan, csaw.UNIFORM, seed_rng)
+
+
 def test_replay_after_staging_growth(csaw):
     """A replayed launch sequence must not outlive the buffers it names: a
     large call grows the workspace's staging buffers between two small calls
