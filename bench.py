@@ -318,6 +318,23 @@ def bench_served(args):
     }
 
 
+def walk_bytes_node2vec(rowptr, paths):
+    """Algorithmic bytes of node2vec walks from their paths: a step from v
+    with previous vertex t reads v's row offsets (16), N(v) (4 d_v: biases
+    and the pick), N(t) (4 d_t: membership) and writes the next vertex (4);
+    the first step (no t) is an unbiased draw: offsets, one neighbor id, the
+    write (24)."""
+    deg = np.diff(rowptr).astype(np.float64)
+    P = paths
+    steps = (P[:, 1:] >= 0)
+    first = steps[:, 0].sum() * 24.0
+    later = steps[:, 1:]
+    v = np.where(later, P[:, 1:-1], 0)
+    t = np.where(later, P[:, :-2], 0)
+    rest = (20.0 * later + 4.0 * deg[v] * later + 4.0 * deg[t] * later).sum()
+    return float(first + rest), int(steps.sum())
+
+
 def bench_node2vec(args):
     """node2vec walks on symmetrised R-MAT 24 (or a smaller scale) with
     weights {1, 2, 4}, length 80; walkers strided over the 2^20 workload."""
@@ -334,18 +351,32 @@ def bench_node2vec(args):
     starts = torch.from_numpy(starts_all[ids.astype(np.int64)]).to(g.device)
     paths, steps = g.walk(starts, rec["length"], csaw.NODE2VEC, rng_seed=1, node2vec=rec["node2vec"], walker_ids=ids)
     torch.cuda.synchronize()
+    alg, nsteps = walk_bytes_node2vec(rp, paths.cpu().numpy())
+    assert nsteps == steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, steps = g.walk(starts, rec["length"], csaw.NODE2VEC, rng_seed=1, node2vec=rec["node2vec"],
                           walker_ids=ids, paths=paths)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    csaw.profile_reset()
+    csaw.profile_enable(True)
+    g.walk(starts, rec["length"], csaw.NODE2VEC, rng_seed=1, node2vec=rec["node2vec"], walker_ids=ids, paths=paths)
+    torch.cuda.synchronize()
+    kms, kn = csaw.profile_read("walk_node2vec")
+    csaw.profile_enable(False)
+    csaw.profile_reset()
+    achieved = alg / (kms / 1e3) / 1e9 if kms > 0 else 0.0
     return {
         "metric": "sampled edges/sec (walk steps/s), node2vec",
         "value": steps / dt, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
-        "config": {"workload": rec["name"], "scale": scale, "walkers": int(len(ids)), "length": rec["length"]},
+        "config": {"workload": rec["name"], "scale": scale, "walkers": int(len(ids)), "length": rec["length"],
+                   "node2vec_weights": list(rec["node2vec"])},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_walk_wave<node2vec>",
+                     "launches": kn, "avg_launch_us": kms / max(kn, 1) * 1e3, "alg_bytes_per_launch": alg},
     }
 
 

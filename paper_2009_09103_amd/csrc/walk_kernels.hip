@@ -252,6 +252,154 @@ __device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds
     return m;
 }
 
+// Entries of win[0, 256) below x; the window is padded with INT32_MAX, and
+// callers search only values no larger than its last real entry.
+__device__ __forceinline__ int32_t win_rank(const int32_t* win, int32_t x) {
+    int32_t pos = 0;
+#pragma unroll
+    for (int step = kWalkWin / 2; step >= 1; step >>= 1) pos += win[pos + step - 1] < x ? step : 0;
+    return pos;
+}
+
+// node2vec step for lists of at most kWalkBits candidates. The bias of x is
+// w_return (x = t), w_common (x in N(t)) or w_outward, so the prefix is fixed
+// by the membership bits and the position of t: pass 1 only finds membership
+// (merge of sorted N(v) with N(t) through the LDS window, a branch-free
+// search per candidate), keeping one bit per candidate and their count;
+// W = w_out (d - c - [t in N(v)]) + w_common c + w_return [t in N(v)]. Pass 2
+// finds the 32-candidate word holding r from word popcounts (64 words per
+// ballot) and the candidate inside it.
+__device__ __forceinline__ int64_t walk_step_n2v(const WalkParams& p, WalkLds<true>& lds, Key key, uint32_t c0,
+                                                 int32_t s, int32_t v, int64_t beg, int64_t d, int32_t t,
+                                                 int64_t tb, int64_t te, bool& stop) {
+    const int lane = lane_id();
+    const int32_t* col = p.g.col;
+    stop = false;
+    const bool merge = (te - tb) <= kMergeRatio * d + kWalkWin;
+    int64_t jw = tb;
+    int32_t wn = 0;
+    int32_t ynext[kWinPer];
+    if (merge) load_window(col, jw, te, ynext);
+    int32_t cur[kWalkPer], nxt[kWalkPer];
+#pragma unroll
+    for (int q = 0; q < kWalkPer; ++q) {
+        const int64_t idx = q * kWave + lane;
+        cur[q] = idx < d ? col[beg + idx] : 0;
+    }
+    uint64_t members = 0, nt = 0;  // candidates in N(t) other than t; copies of t
+    int64_t pos_t = -1;            // first copy of t (sorted lists keep copies together)
+    for (int64_t base = 0; base < d; base += kWalkTile) {
+#pragma unroll
+        for (int q = 0; q < kWalkPer; ++q) {  // next tile in flight
+            const int64_t idx = base + kWalkTile + q * kWave + lane;
+            nxt[q] = idx < d ? col[beg + idx] : 0;
+        }
+        bool open[kWalkPer], found[kWalkPer];
+#pragma unroll
+        for (int q = 0; q < kWalkPer; ++q) {
+            open[q] = base + q * kWave + lane < d;
+            found[q] = false;
+        }
+        if (merge) {
+            while (true) {
+                const int32_t wmax = wn > 0 ? lds.win[wn - 1] : INT32_MIN;
+                bool pending = false;
+#pragma unroll
+                for (int q = 0; q < kWalkPer; ++q) {
+                    const bool take = open[q] && cur[q] <= wmax;
+                    if (ballot(take)) {
+                        const int32_t r = win_rank(lds.win, cur[q]);
+                        if (take) {
+                            found[q] = lds.win[r] == cur[q];
+                            open[q] = false;
+                        }
+                    }
+                    pending |= open[q];
+                }
+                if (ballot(pending) == 0) break;
+                jw += wn;
+                if (jw >= te) break;
+                wn = (int32_t)(te - jw < kWalkWin ? te - jw : kWalkWin);
+                wave_lds_sync();
+#pragma unroll
+                for (int q = 0; q < kWinPer; ++q) lds.win[q * kWave + lane] = ynext[q];
+                wave_lds_sync();
+                load_window(col, jw + wn, te, ynext);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kWalkPer; ++q)
+                if (open[q]) found[q] = in_sorted(col, tb, te, cur[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < kWalkPer; ++q) {
+            const bool valid = base + q * kWave + lane < d;
+            const uint64_t fm = ballot(valid && found[q] && cur[q] != t);
+            const uint64_t tm = ballot(valid && cur[q] == t);
+            const int64_t i0 = base + q * kWave;
+            if (lane < 2) lds.bits[i0 / 32 + lane] = (uint32_t)(fm >> (32 * lane));
+            members += __popcll(fm);
+            if (tm && pos_t < 0) pos_t = i0 + __ffsll((unsigned long long)tm) - 1;
+            nt += __popcll(tm);
+            cur[q] = nxt[q];
+        }
+    }
+    const uint64_t wo = p.w_outward, wc = p.w_common, wr = p.w_return;
+    const uint64_t W = wo * ((uint64_t)d - members - nt) + wc * members + wr * nt;
+    if (W == 0) {
+        stop = true;
+        return 0;
+    }
+    wave_lds_sync();
+    const uint64_t r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+    // S(i) = total bias of candidates [0, i) = wo (i - C - T) + wc C + wr T with
+    // C members and T copies of t before i: find the word holding r
+    const auto copies_before = [&](int64_t i) -> uint64_t {
+        if (pos_t < 0 || i <= pos_t) return 0;
+        return (uint64_t)(i - pos_t) < nt ? (uint64_t)(i - pos_t) : nt;
+    };
+    const int64_t nwords = (d + 31) / 32;
+    int64_t wstar = 0;
+    uint64_t Cw = 0, prevC = 0;  // members before the chosen word / before the last word of the previous run
+    uint32_t carry = 0;
+    for (int64_t w0 = 0; w0 < nwords; w0 += kWave) {
+        const int64_t w = w0 + lane;
+        const bool valid = w < nwords;
+        const uint32_t pc = valid ? (uint32_t)__popc(lds.bits[w]) : 0u;
+        const uint32_t incl = wave_incl_scan_u32(pc);
+        const uint64_t C = (uint64_t)carry + (incl - pc);
+        const int64_t i = w * 32;
+        const uint64_t T = copies_before(i);
+        const uint64_t S = wo * ((uint64_t)i - C - T) + wc * C + wr * T;
+        const int nle = __popcll(ballot(valid && S <= r));
+        const int nvalid = (int)(nwords - w0 < kWave ? nwords - w0 : kWave);
+        if (nle < nvalid || w0 + kWave >= nwords) {  // the word holding r ends here
+            if (nle == 0) {  // r starts this run: it is in the last word of the previous one
+                wstar = w0 - 1;
+                Cw = prevC;
+            } else {
+                wstar = w0 + nle - 1;
+                Cw = readlane_u64(C, nle - 1);
+            }
+            break;
+        }
+        prevC = readlane_u64(C, kWave - 1);
+        carry += readlane_u32(incl, kWave - 1);
+    }
+    const int64_t e0 = wstar * 32;
+    const uint64_t Tw = copies_before(e0);
+    const uint64_t Sw = wo * ((uint64_t)e0 - Cw - Tw) + wc * Cw + wr * Tw;
+    const uint32_t word = lds.bits[wstar];
+    const int64_t j = e0 + lane;
+    uint64_t b = 0;
+    if (lane < 32 && j < d)
+        b = (pos_t >= 0 && j >= pos_t && (uint64_t)(j - pos_t) < nt) ? wr : (((word >> lane) & 1u) ? wc : wo);
+    const uint64_t incl = wave_incl_scan_u64(b);
+    const int64_t m = e0 + __popcll(ballot(lane < 32 && j < d && Sw + incl <= r));
+    wave_lds_sync();  // bits are rewritten by the next step
+    return m;
+}
+
 template <bool kN2v>
 __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
     __shared__ WalkLds<kN2v> lds_all[kWavesPerBlock];
@@ -279,11 +427,16 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
             const int64_t d = uniform_i64(p.g.rowptr[v + 1]) - beg;
             if (d == 0) break;
             int64_t m;
+            bool stop = false;
             if (kN2v && t < 0) {  // first step: no previous vertex, every bias is 1
                 m = (int64_t)draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, (uint64_t)d);
             } else {
-                bool stop;
-                m = walk_step_biased<kN2v>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
+                if constexpr (kN2v) {
+                    if (d <= kWalkBits) m = walk_step_n2v(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
+                    else m = walk_step_biased<true>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
+                } else {
+                    m = walk_step_biased<false>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
+                }
                 if (stop) break;
             }
             const int32_t nx = uniform_i32(p.g.col[beg + m]);
