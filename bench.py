@@ -463,7 +463,14 @@ def main():
     elif args.workload == "batched":
         line = bench_batched(args)
     elif args.workload == "served":
-        line = bench_served(args)
+        # The Poisson-trace run through csaw_server_* ended in a host-side
+        # segmentation fault after building the R-MAT 26 graph; no cause has
+        # been found in the server or runtime host code, so this workload stays
+        # switched off until one is. The server itself is covered by
+        # tests/test_gpu_server.py (mixes equal to each request alone).
+        print("the served workload is disabled: its run crashed with a host-side segmentation fault "
+              "whose cause has not been found", file=sys.stderr)
+        sys.exit(3)
     elif args.workload == "node2vec":
         line = bench_node2vec(args)
     elif args.workload == "copy":
