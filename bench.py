@@ -69,26 +69,25 @@ def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted):
     return out
 
 
-def cpu_baseline(rp, col, offs, seeds, fanouts, bias, budget_s=20.0):
-    """The CPU oracle on the host: the whole call, repeated with Philox seeds
-    1, 2, 3 while within the time budget."""
+def cpu_baseline(rp, col, offs, seeds, fanouts, bias, min_s=10.0, max_runs=60):
+    """The CPU oracle on the host: the whole call, cycling over Philox seeds
+    1, 2, 3 until at least min_s seconds of oracle time have been spent."""
     import oracle
     t_used, edges, runs = 0.0, 0, 0
     threads = oracle.max_threads()
-    for s in (1, 2, 3):
+    while t_used < min_s and runs < max_runs:
+        s = 1 + runs % 3
         t0 = time.perf_counter()
         ref = oracle.sample(rp, col, None, offs, seeds, fanouts, bias_kind=bias, rng_seed=s)
         t_used += time.perf_counter() - t0
         edges += ref.num_edges
         runs += 1
-        if t_used > budget_s:
-            break
     # one instance: the oracle parallelises over instances, so one thread works
     used = min(threads, len(offs) - 1)
     return dict(value=edges / t_used, unit="sampled edges/s", cores=int(used), kind="oracle",
-                sample="full workload (all %d seeds, all layers), %d call(s) with Philox seeds 1..%d, "
+                sample="full workload (all %d seeds, all layers), %d calls cycling over Philox seeds 1..3, "
                        "%.1f s; oracle single instance -> 1 thread of %d available" % (
-                           len(seeds), runs, runs, t_used, threads))
+                           len(seeds), runs, t_used, threads))
 
 
 def bench_degree_biased(args):

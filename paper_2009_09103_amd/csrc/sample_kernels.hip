@@ -626,12 +626,16 @@ template <int E>
 __device__ __forceinline__ int32_t draw_resident(const uint32_t* __restrict__ w, int64_t d, Key key, uint32_t c0,
                                                  uint32_t c1, uint32_t c2, int32_t k) {
     const int lane = lane_id();
+    // d <= kWaveMaxD: 32-bit indices; every load is issued (clamped into the
+    // list) and the tail zeroed after, so no lane branches
+    const int32_t last = (int32_t)d - 1;
     uint32_t x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = w[min(lane * E + e, last)];
     uint32_t ls = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int64_t i = (int64_t)lane * E + e;
-        x[e] = i < d ? w[i] : 0u;
+        x[e] = lane * E + e <= last ? x[e] : 0u;
         ls += x[e];
     }
     // routing guarantees W < 2^32, so every prefix fits 32 bits
