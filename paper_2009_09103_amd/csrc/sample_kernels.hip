@@ -186,71 +186,101 @@ __device__ __forceinline__ void block_excl_scan4(int64_t (&x)[4], int64_t (&tot)
     __syncthreads();
 }
 
-// Frontier build of one layer, one pass: block b takes bitmap words
-// [256 b, 256 b + 256), one per thread; each thread counts its set bits
-// (entries), their edge counts min(k, P) (edges) and their long-list route;
-// a block scan plus a decoupled look-back over the blocks before it give
-// global positions (blocks are dispatched in index order, so predecessors
-// are resident or done; the spin is bounded and reports instead of
-// hanging). The thread then writes its entries in (instance, vertex) order
-// with count, edge offset and route, sets visited |= next, clears next, and
-// the first word of an instance writes that instance's segment offset. The
-// last block writes the layer's totals and the output base of the next layer.
+// Frontier build of one layer, one pass: each thread takes G*V consecutive
+// bitmap words (G loads of V words of next and of visited; small bitmaps use
+// one word per thread for the most parallel blocks, large ones many, so that
+// the number of blocks, each a short latency-bound chain of loads, stays
+// small); it counts the new bits (entries), their edge counts min(k, P)
+// (edges) and their long-list route; a block scan plus a decoupled look-back
+// over the blocks before it give global positions (blocks are dispatched in
+// index order, so predecessors are resident or done; the spin is bounded and
+// reports instead of hanging). The thread then writes its entries in
+// (instance, vertex) order with count, edge offset, list fields and route,
+// sets visited |= next, clears next, and the first word of an instance writes
+// that instance's segment offset. The last block writes the layer's totals
+// and the output base of the next layer.
+template <int G, int V>
 __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
+    static_assert(V == 1 || V == 4, "one word or one 16-byte group per load");
     __shared__ int64_t s_base_e, s_base_g;
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
-    const int64_t iw = b * kBlock + tid;
-    const bool valid = iw < fb.nwords;
-    uint32_t w = 0, vis = 0, raw = 0;
-    int64_t inst = 0, local = 0;
-    int32_t k = 0, kind = 0;
+    const int64_t w0 = (b * kBlock + tid) * (G * V);  // first word of the thread (nwords is a multiple of 4)
     const int64_t out_base = fb.ctl->out_base[fb.layer];
-    if (valid) {
-        vis = fb.visited[iw];
-        raw = fb.next[iw];
-        w = raw & ~vis;  // picks of visited vertices are not new
-        inst = iw / fb.nwp;
-        local = iw - inst * fb.nwp;
-        if (w) {
-            k = fb.fanout[inst];
-            kind = fb.bias[inst];
+    uint32_t raws[G][V], viss[G][V];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t iw = w0 + V * g;
+        if (V == 4) {
+            uint4 r4 = make_uint4(0u, 0u, 0u, 0u), v4 = make_uint4(0u, 0u, 0u, 0u);
+            if (iw < fb.nwords) {
+                r4 = *(const uint4*)(fb.next + iw);
+                v4 = *(const uint4*)(fb.visited + iw);
+            }
+            const uint32_t rr[4] = {r4.x, r4.y, r4.z, r4.w}, vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                raws[g][q] = rr[q];
+                viss[g][q] = vv[q];
+            }
+        } else {
+            raws[g][0] = iw < fb.nwords ? fb.next[iw] : 0u;
+            viss[g][0] = iw < fb.nwords ? fb.visited[iw] : 0u;
         }
     }
-    const int32_t vbase = (int32_t)(local * 32);
-    // the first four entries' counts stay in registers for the write pass
+    // the thread's first four entries (first bits of its first non-empty word)
+    // keep their counts in registers for the write pass
     int32_t cc[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0}, cp[4] = {0, 0, 0, 0};
     int64_t cbeg[4] = {0, 0, 0, 0}, cd[4] = {0, 0, 0, 0};
-    int64_t cnt4[4] = {__popc(w), 0, 0, 0};  // entries, edges, long lists, chunks
+    int64_t cnt4[4] = {0, 0, 0, 0};  // entries, edges, long lists, chunks
     {
-        uint32_t bits = w;
         bool first = true;
-        while (bits) {  // four bits at a time so that their loads overlap
-            int32_t bv[4];
+        int64_t inst_k = -1;
+        int32_t k = 0, kind = 0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) bv[t] = pop_bit(bits);
+        for (int g = 0; g < G; ++g) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                int32_t route = kRouteWave, pinfo = 0;
-                int64_t beg = 0, d = 0;
-                int32_t c = 0;
-                if (bv[t] >= 0) {
-                    c = entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, pinfo, fb.ctl);
-                    cnt4[1] += c;
-                    if (route == kRouteBig) {
-                        ++cnt4[2];
-                        cnt4[3] += chunks_of(d);
-                    }
+            for (int q = 0; q < V; ++q) {
+                const uint32_t w = raws[g][q] & ~viss[g][q];  // picks of visited vertices are not new
+                if (!w) continue;
+                const int64_t iw = w0 + V * g + q;
+                const int64_t inst = iw / fb.nwp;
+                if (inst != inst_k) {
+                    inst_k = inst;
+                    k = fb.fanout[inst];
+                    kind = fb.bias[inst];
                 }
-                if (first) {
-                    cc[t] = c;
-                    cr[t] = route;
-                    cp[t] = pinfo;
-                    cbeg[t] = beg;
-                    cd[t] = d;
+                const int32_t vbase = (int32_t)((iw - inst * fb.nwp) * 32);
+                cnt4[0] += __popc(w);
+                uint32_t bits = w;
+                while (bits) {  // four bits at a time so that their loads overlap
+                    int32_t bv[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) bv[t] = pop_bit(bits);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        int32_t route = kRouteWave, pinfo = 0;
+                        int64_t beg = 0, d = 0;
+                        int32_t c = 0;
+                        if (bv[t] >= 0) {
+                            c = entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, pinfo, fb.ctl);
+                            cnt4[1] += c;
+                            if (route == kRouteBig) {
+                                ++cnt4[2];
+                                cnt4[3] += chunks_of(d);
+                            }
+                        }
+                        if (first) {
+                            cc[t] = c;
+                            cr[t] = route;
+                            cp[t] = pinfo;
+                            cbeg[t] = beg;
+                            cd[t] = d;
+                        }
+                    }
+                    first = false;
                 }
             }
-            first = false;
         }
     }
     int64_t tot4[4];
@@ -325,12 +355,34 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     __syncthreads();
     int64_t pos = s_base_e + ex_e;
     int64_t eoff = s_base_g + ex_g;
-    if (valid) {
-        if (local == 0 && fb.offsets && fb.layer < fb.num_layers)
-            fb.offsets[(int64_t)fb.layer * fb.num_instances + inst] = out_base + eoff;
-        if (w) {
+    bool first = true;
+    int64_t inst_k = -1;
+    int32_t k = 0, kind = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t iw4 = w0 + V * g;
+        if (iw4 >= fb.nwords) break;
+        uint32_t newv[V];
+        bool any_raw = false, any_new = false;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const int64_t iw = iw4 + q;
+            const uint32_t w = raws[g][q] & ~viss[g][q];
+            newv[q] = viss[g][q] | w;
+            any_raw |= raws[g][q] != 0u;
+            any_new |= w != 0u;
+            const int64_t inst = iw / fb.nwp;
+            const int64_t local = iw - inst * fb.nwp;
+            if (local == 0 && fb.offsets && fb.layer < fb.num_layers)
+                fb.offsets[(int64_t)fb.layer * fb.num_instances + inst] = out_base + eoff;
+            if (!w) continue;
+            if (inst != inst_k) {
+                inst_k = inst;
+                k = fb.fanout[inst];
+                kind = fb.bias[inst];
+            }
+            const int32_t vbase = (int32_t)(local * 32);
             uint32_t bits = w;
-            bool first = true;
             while (bits) {
                 int32_t bv[4];
 #pragma unroll
@@ -377,9 +429,15 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                 }
                 first = false;
             }
-            fb.visited[iw] = vis | w;
         }
-        if (raw) fb.next[iw] = 0u;  // also words that held only visited picks
+        if (V == 4) {
+            if (any_new) *(uint4*)(fb.visited + iw4) = make_uint4(newv[0], newv[V > 1 ? 1 : 0], newv[V > 2 ? 2 : 0],
+                                                                  newv[V > 3 ? 3 : 0]);
+            if (any_raw) *(uint4*)(fb.next + iw4) = make_uint4(0u, 0u, 0u, 0u);  // also words that held only visited picks
+        } else {
+            if (any_new) fb.visited[iw4] = newv[0];
+            if (any_raw) fb.next[iw4] = 0u;
+        }
     }
     if (b == fb.nb - 1) {  // last block: totals, and the bases of the layers after this one
         const int64_t te = s_base_e + tot_e, tg = s_base_g + tot_g;
@@ -391,8 +449,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
         }
         if (fb.offsets) {
             const int64_t ni = fb.num_instances;
-            const int64_t first = fb.nwp > 0 ? fb.layer + 1 : fb.layer;
-            for (int64_t j = first; j < fb.num_layers; ++j)
+            const int64_t first_l = fb.nwp > 0 ? fb.layer + 1 : fb.layer;
+            for (int64_t j = first_l; j < fb.num_layers; ++j)
                 for (int64_t i = tid; i < ni; i += kBlock) fb.offsets[j * ni + i] = (j == fb.layer ? out_base : ob);
             if (tid == 0) fb.offsets[(int64_t)fb.num_layers * ni] = ob;
         }
@@ -1066,13 +1124,21 @@ void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* s
                        num_seeds, seed_offsets, ni, n, next, nwp, ctl);
 }
 
+// Bitmap words per thread of the frontier build: one up to 2^20 words (one
+// instance of a 2^25-vertex graph), 16 above.
+static int frontier_build_words(int64_t words) { return words > (int64_t(1) << 20) ? 16 : 1; }
+
 int64_t frontier_build_blocks(int64_t words) {
-    const int64_t nb = (words + kBlock - 1) / kBlock;
+    const int64_t per = (int64_t)kBlock * frontier_build_words(words);
+    const int64_t nb = (words + per - 1) / per;
     return nb > 0 ? nb : 1;
 }
 
 void launch_frontier_build(const FrontierBuild& fb, hipStream_t s, LaunchEvents ev) {
-    launch_kernel(k_frontier_build, dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
+    if (frontier_build_words(fb.nwords) == 16)
+        launch_kernel(k_frontier_build<4, 4>, dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
+    else
+        launch_kernel(k_frontier_build<1, 1>, dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
 }
 
 void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
