@@ -193,6 +193,45 @@ def bench_degree_biased(args):
     return line
 
 
+def path_bytes_multi(rowptr, ppos, seed_offs, seeds, dst, offsets, fanouts, bias):
+    """path_bytes for a multi-instance call: frontier entries are (instance,
+    vertex) pairs (keys instance * n + vertex), each instance with its own
+    fanout row and bias kind; offsets[l * ni + i] is the first edge of (layer
+    l, instance i). Same per-entry figures as path_bytes."""
+    n = len(rowptr) - 1
+    deg = np.diff(rowptr)
+    ni = len(seed_offs) - 1
+    L = fanouts.shape[1]
+    inst_of_seed = np.repeat(np.arange(ni, dtype=np.int64), np.diff(seed_offs))
+    visited = np.unique(inst_of_seed * n + seeds.astype(np.int64))
+    frontier = visited
+    out = {"select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
+    for l in range(L):
+        inst = frontier // n
+        v = frontier % n
+        k = fanouts[inst, l].astype(np.int64)
+        wflag = bias[inst] != 0
+        d = deg[v].astype(np.float64)
+        P = np.where(wflag, ppos[v], deg[v])
+        c = np.where((k == 0) | (P == 0), 0, np.where((k < 0) | (k >= P), P, k)).astype(np.float64)
+        assert int(c.sum()) == offsets[(l + 1) * ni] - offsets[l * ni]
+        long_ = wflag & (k > 0) & (k < P) & (deg[v] > WAVE_MAX_D)
+        w = ~long_
+        out["select_wave"] += 24.0 * w.sum() + 12.0 * c[w].sum() + 4.0 * d[w & wflag].sum()
+        groups = np.ceil(d[long_] / 16.0)
+        out["chunk_prefix"] += 4.0 * d[long_].sum() + 8.0 * groups.sum() + 8.0 * np.ceil(d[long_] / 1024.0).sum()
+        out["select_big"] += 24.0 * long_.sum() + 8.0 * groups.sum() + 12.0 * c[long_].sum()
+        if l + 1 < L:
+            a, b = offsets[l * ni], offsets[(l + 1) * ni]
+            edge_inst = np.repeat(np.arange(ni, dtype=np.int64), np.diff(offsets[l * ni:(l + 1) * ni + 1]))
+            keys = np.unique(edge_inst * n + dst[a:b].astype(np.int64))
+            keys = keys[fanouts[keys // n, l + 1] != 0]  # picks are claimed only for a next layer
+            nxt = np.setdiff1d(keys, visited, assume_unique=True)
+            visited = np.union1d(visited, nxt)
+            frontier = nxt
+    return out
+
+
 def bench_batched(args):
     """4,096 uneven instances in one csaw_sample call (the launch sequence is
     replayed from a captured graph) against the same instances as 4,096 plain
@@ -222,6 +261,22 @@ def bench_batched(args):
         g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    # algorithmic bytes of the call and kernel times from one event-timed pass
+    deg = np.diff(rp)
+    ppos = np.add.reduceat(np.append((deg[col] > 0).astype(np.int64), 0), rp[:-1])
+    ppos[deg == 0] = 0
+    alg = path_bytes_multi(rp, ppos, offs, seeds, dst[:edges].cpu().numpy(), offsets.cpu().numpy(), fanouts, bias)
+    csaw.profile_reset()
+    csaw.profile_enable(True)
+    g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+    torch.cuda.synchronize()
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_wave", "chunk_prefix", "select_big",
+                                                "frontier_build", "visited_clear")}
+    csaw.profile_enable(False)
+    csaw.profile_reset()
+    sel_ms, sel_n = times["select_wave"]
+    achieved = alg["select_wave"] / (sel_ms / 1e3) / 1e9 if sel_ms > 0 else 0.0
+    step_bytes = sum(alg.values())
     # plain: one call per instance (same ids, same seed)
     per = []
     for i in range(ni):
@@ -248,6 +303,15 @@ def bench_batched(args):
         "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
         "config": {"workload": rec["name"], "instances": ni, "seeds": int(len(seeds)),
                    "edges_per_step": int(edges)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "select_wave (k_select)",
+                     "launches": sel_n, "avg_launch_us": sel_ms / max(sel_n, 1) * 1e3,
+                     "alg_bytes_per_launch": alg["select_wave"] / max(sel_n, 1)},
+        "roofline_step": {"alg_bytes": step_bytes, "achieved": step_bytes / dt / 1e9, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": step_bytes / dt / 1e9 / HBM_PEAK_GBS},
+        "kernels": {k: {"alg_bytes_per_step": alg[k], "ms_per_step": times[k][0],
+                        "GB_per_s": alg[k] / (times[k][0] / 1e3) / 1e9 if times[k][0] > 0 else 0.0} for k in alg},
+        "kernel_ms_per_step": {k: v[0] for k, v in times.items()},
         "plain_calls": {"value": plain_edges / pdt, "calls": ni, "seconds": pdt},
         "batched_over_plain": (edges / dt) / (plain_edges / pdt),
     }
