@@ -208,22 +208,31 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     const int64_t w0 = (b * kBlock + tid) * (G * V);  // first word of the thread (nwords is a multiple of 4)
     const int64_t out_base = fb.ctl->out_base[fb.layer];
     uint32_t raws[G][V], viss[G][V];
+    if (V == 4) {
+        // next first; visited only where next has bits (large bitmaps are sparse)
+        uint4 r4[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const int64_t iw = w0 + V * g;
-        if (V == 4) {
-            uint4 r4 = make_uint4(0u, 0u, 0u, 0u), v4 = make_uint4(0u, 0u, 0u, 0u);
-            if (iw < fb.nwords) {
-                r4 = *(const uint4*)(fb.next + iw);
-                v4 = *(const uint4*)(fb.visited + iw);
-            }
-            const uint32_t rr[4] = {r4.x, r4.y, r4.z, r4.w}, vv[4] = {v4.x, v4.y, v4.z, v4.w};
+        for (int g = 0; g < G; ++g) {
+            const int64_t iw = w0 + V * g;
+            r4[g] = iw < fb.nwords ? *(const uint4*)(fb.next + iw) : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t iw = w0 + V * g;
+            const bool any = (r4[g].x | r4[g].y | r4[g].z | r4[g].w) != 0u;
+            const uint4 v4 = any ? *(const uint4*)(fb.visited + iw) : make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t rr[4] = {r4[g].x, r4[g].y, r4[g].z, r4[g].w}, vv[4] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 raws[g][q] = rr[q];
                 viss[g][q] = vv[q];
             }
-        } else {
+        }
+    }
+    if (V == 1) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t iw = w0 + g;
             raws[g][0] = iw < fb.nwords ? fb.next[iw] : 0u;
             viss[g][0] = iw < fb.nwords ? fb.visited[iw] : 0u;
         }
