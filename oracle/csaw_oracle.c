@@ -164,7 +164,7 @@ uint64_t orc_skip_map(const uint64_t* S, const uint32_t* b, const int64_t* acc_s
 
 /*
  * Select up to k distinct candidates out of d with biases b (the Select
- * call at line 6 of fig:api(b) for one frontier vertex).
+ * step of the generic loop of fig:api(b), for one frontier vertex).
  *
  *   W = sum b, P = #{i : b_i > 0}.
  *   W == 0            -> nothing is selected.
@@ -256,7 +256,7 @@ int32_t orc_select(const uint32_t* b, int64_t d, int64_t k, int32_t rounds,
 
 /* ---------------------------------------------------------------------------
  * Graph helpers. CSR: rowptr int64[n+1], col int32[m]; adjacency lists are
- * sorted. GatherNeighbors (fig:api(b) line 5) of v is col[rowptr[v] ..
+ * sorted. GatherNeighbors (fig:api(b)) of v is col[rowptr[v] ..
  * rowptr[v+1]).
  * ------------------------------------------------------------------------- */
 typedef struct {

@@ -1,13 +1,17 @@
 // sample_kernels.hip -- gfx950 kernels of neighbor sampling.
 //
-// One layer of the generic sampling loop (fig:api(b), lines 5-8) is
-//   count    : per frontier entry, how many edges it will emit (min(k, P))
-//   scan     : exclusive offsets of those counts (output position per entry)
-//   select   : one wavefront per frontier vertex: EdgeBias, exact uint64
-//              prefix sum, Philox draws, inverse transform search, collision
-//              rounds, direct draw from the updated prefix; writes the edges
-//              and marks new neighbors in the instance's "next" bitmap
-//   compact  : next bitmap -> sorted next frontier; visited |= next
+// One layer of the generic sampling loop (fig:api(b)) is
+//   frontier build : next bitmap -> sorted frontier entries, each with its
+//                    edge count min(k, P), edge offset, list fields and
+//                    route (one pass with a decoupled look-back);
+//                    visited |= next
+//   select         : one wavefront per frontier vertex: EdgeBias, exact
+//                    prefix, Philox draws, inverse transform search,
+//                    collision rounds, direct draw from the updated prefix;
+//                    writes the edges and marks new neighbors in the
+//                    instance's next bitmap. Weighted lists longer than
+//                    kWaveMaxD first get their 1024-weight chunk prefixes
+//                    (chunk pass), then one wavefront each (select_big).
 // Frontier entries are (vertex, instance) pairs sorted by (instance, vertex),
 // so edges come out in (layer, instance, source, slot) order without a sort.
 #include "device_common.h"
