@@ -95,6 +95,20 @@ def test_batched_instances_mixed_bias(csaw):
             np.testing.assert_array_equal(res.dst[a:b].cpu().numpy(), alone.dst[ao[l]:ao[l + 1]].cpu().numpy())
 
 
+def test_wide_build_instance_boundaries(csaw):
+    """Bitmaps above 2^20 words are built 16 words per thread; with 4,100
+    words per instance (n = 2^17 + 100) a thread's words straddle instance
+    boundaries. 300 instances, mixed fanout rows and bias kinds."""
+    rp0, col = inputs.rmat_csr(17, 8 << 17, 23)
+    rp = np.concatenate([rp0, np.full(100, rp0[-1], dtype=rp0.dtype)])  # 100 isolated vertices
+    n = len(rp) - 1
+    nwp = ((n + 31) // 32 + 3) // 4 * 4
+    assert nwp % 16 != 0 and 300 * nwp > (1 << 20)
+    offs, seeds, fanouts, bias = inputs.batched_instances(rp, col, 300, 9, lo=1, hi=40, median=8)
+    g = csaw.Graph(rp, col)
+    run_both(csaw, g, rp, col, None, offs, seeds, fanouts, bias, 5, instance_base=77)
+
+
 def test_take_all_uniform_is_bfs(csaw):
     rp, col = inputs.graph_for(inputs.TINY)
     offs, seeds = inputs.single_instance_seeds(rp, col, 8, 2)
