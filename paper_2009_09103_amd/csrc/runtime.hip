@@ -755,6 +755,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     }
     rel.clean = true;
     out->num_edges = L > 0 ? h_ctl->out_base[L] : 0;
+    if (out->num_edges < 0) return fail(CSAW_ERR_DEVICE, "the device reported a negative edge count");
     if (h_ctl->lookback_stuck) return fail(CSAW_ERR_DEVICE, "frontier build did not complete its block chain");
     if (h_ctl->bad_seed) return fail(CSAW_ERR_INVALID_ARG, "a seed is outside [0, n)");
     if (h_ctl->unsupported)

@@ -268,6 +268,14 @@ void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Cloc
         for (Request* r : batch) finish(r, new_result(CSAW_REQUEST_SAMPLE, CSAW_ERR_DEVICE));
         return;
     }
+    // the segment offsets come from device memory: check them before they size
+    // host copies (monotone, inside [0, ne])
+    bool offsets_ok = h_off.p[0] >= 0 && h_off.p[noff - 1] == ne;
+    for (size_t j = 1; offsets_ok && j < noff; ++j) offsets_ok = h_off.p[j] >= h_off.p[j - 1];
+    if (!offsets_ok) {
+        for (Request* r : batch) finish(r, new_result(CSAW_REQUEST_SAMPLE, CSAW_ERR_DEVICE));
+        return;
+    }
     const Clock::time_point t_end = Clock::now();
     for (int32_t i = 0; i < ni; ++i) {
         Request* r = batch[i];
