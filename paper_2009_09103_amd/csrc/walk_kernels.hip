@@ -96,14 +96,18 @@ struct WalkLds {
     int32_t win[kN2v ? kWalkWin : 1];
 };
 
-// lower bound of x in win[0, n), n <= kWalkWin
-__device__ __forceinline__ int32_t win_lower_bound(const int32_t* win, int32_t n, int32_t x) {
-    int32_t pos = 0;
+// Entries of win[0, kWalkWin) below each of x[0..kWalkPer): four branch-free
+// binary searches stepped together, so their LDS reads overlap. The window
+// is padded with INT32_MAX; callers use a rank only for x no larger than the
+// window's last real entry, where it is the lower bound among the real ones.
+__device__ __forceinline__ void win_rank4(const int32_t* win, const int32_t (&x)[kWalkPer], int32_t (&r)[kWalkPer]) {
 #pragma unroll
-    for (int step = kWalkWin / 2; step >= 1; step >>= 1)
-        if (pos + step <= n && win[pos + step - 1] < x) pos += step;
-    if (pos < n && win[pos] < x) ++pos;
-    return pos;
+    for (int q = 0; q < kWalkPer; ++q) r[q] = 0;
+#pragma unroll
+    for (int step = kWalkWin / 2; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int q = 0; q < kWalkPer; ++q) r[q] += win[r[q] + step - 1] < x[q] ? step : 0;
+    }
 }
 
 // N(t) window loads: entries [at, at + kWalkWin) of col, clipped to te
@@ -165,16 +169,26 @@ __device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds
             if (merge) {
                 while (true) {
                     const int32_t wmax = wn > 0 ? lds.win[wn - 1] : INT32_MIN;
-                    bool pending = false;
+                    bool take[kWalkPer], any = false;
 #pragma unroll
                     for (int q = 0; q < kWalkPer; ++q) {
-                        if (open[q] && a[q] <= wmax) {
-                            const int32_t pos = win_lower_bound(lds.win, wn, a[q]);
-                            found[q] = pos < wn && lds.win[pos] == a[q];
-                            open[q] = false;
-                        }
-                        pending |= open[q];
+                        take[q] = open[q] && a[q] <= wmax;
+                        any |= take[q];
                     }
+                    if (ballot(any)) {
+                        int32_t r[kWalkPer];
+                        win_rank4(lds.win, a, r);
+#pragma unroll
+                        for (int q = 0; q < kWalkPer; ++q) {
+                            if (take[q]) {
+                                found[q] = lds.win[r[q]] == a[q];
+                                open[q] = false;
+                            }
+                        }
+                    }
+                    bool pending = false;
+#pragma unroll
+                    for (int q = 0; q < kWalkPer; ++q) pending |= open[q];
                     if (ballot(pending) == 0) break;
                     jw += wn;  // every entry of this window is below the open candidates
                     if (jw >= te) break;
@@ -252,15 +266,6 @@ __device__ __forceinline__ int64_t walk_step_biased(const WalkParams& p, WalkLds
     return m;
 }
 
-// Entries of win[0, 256) below x; the window is padded with INT32_MAX, and
-// callers search only values no larger than its last real entry.
-__device__ __forceinline__ int32_t win_rank(const int32_t* win, int32_t x) {
-    int32_t pos = 0;
-#pragma unroll
-    for (int step = kWalkWin / 2; step >= 1; step >>= 1) pos += win[pos + step - 1] < x ? step : 0;
-    return pos;
-}
-
 // node2vec step for lists of at most kWalkBits candidates. The bias of x is
 // w_return (x = t), w_common (x in N(t)) or w_outward, so the prefix is fixed
 // by the membership bits and the position of t: pass 1 only finds membership
@@ -303,19 +308,26 @@ __device__ __forceinline__ int64_t walk_step_n2v(const WalkParams& p, WalkLds<tr
         if (merge) {
             while (true) {
                 const int32_t wmax = wn > 0 ? lds.win[wn - 1] : INT32_MIN;
-                bool pending = false;
+                bool take[kWalkPer], any = false;
 #pragma unroll
                 for (int q = 0; q < kWalkPer; ++q) {
-                    const bool take = open[q] && cur[q] <= wmax;
-                    if (ballot(take)) {
-                        const int32_t r = win_rank(lds.win, cur[q]);
-                        if (take) {
-                            found[q] = lds.win[r] == cur[q];
+                    take[q] = open[q] && cur[q] <= wmax;
+                    any |= take[q];
+                }
+                if (ballot(any)) {
+                    int32_t r[kWalkPer];
+                    win_rank4(lds.win, cur, r);
+#pragma unroll
+                    for (int q = 0; q < kWalkPer; ++q) {
+                        if (take[q]) {
+                            found[q] = lds.win[r[q]] == cur[q];
                             open[q] = false;
                         }
                     }
-                    pending |= open[q];
                 }
+                bool pending = false;
+#pragma unroll
+                for (int q = 0; q < kWalkPer; ++q) pending |= open[q];
                 if (ballot(pending) == 0) break;
                 jw += wn;
                 if (jw >= te) break;
