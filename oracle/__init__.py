@@ -84,6 +84,8 @@ def lib():
             L.orc_walk.argtypes = [i64, vp, vp, vp, i32, u32, u32, u32, i64, vp, u64, vp, i32, u64,
                                    vp, vp, vp, i32]
             L.orc_walk.restype = i32
+            L.orc_mdrw.argtypes = [i64, vp, vp, i32, vp, vp, u64, i64, u64, vp, vp, vp]
+            L.orc_mdrw.restype = i32
             L.orc_max_threads.argtypes = []
             L.orc_max_threads.restype = i32
             _lib = L
@@ -221,6 +223,25 @@ def walk(rowptr, col, ew, starts, length, bias_kind=UNIFORM, rng_seed=1, walker_
     if rc != 0:
         raise ValueError("oracle: invalid walk input")
     return paths, steps, tuple(stats)
+
+
+def mdrw(rowptr, col, pool_offsets, pool, budget, rng_seed=1, instance_base=0):
+    """Multi-dimensional random walks (see ``orc_mdrw``): one frontier pool
+    per instance. Returns (src [ni, budget], dst [ni, budget], steps [ni]);
+    -1 marks edges after an instance has ended."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    pool_offsets = np.ascontiguousarray(pool_offsets, dtype=np.int64)
+    pool = np.ascontiguousarray(pool, dtype=np.int32)
+    ni = len(pool_offsets) - 1
+    src = np.zeros((ni, budget), dtype=np.int32)
+    dst = np.zeros((ni, budget), dtype=np.int32)
+    steps = np.zeros(max(ni, 1), dtype=np.int64)
+    rc = lib().orc_mdrw(len(rowptr) - 1, _p(rowptr), _p(col), ni, _p(pool_offsets), _p(pool), instance_base,
+                        budget, rng_seed, _p(src), _p(dst), _p(steps))
+    if rc != 0:
+        raise ValueError("oracle: invalid multi-dimensional random walk input")
+    return src, dst, steps[:ni]
 
 
 def max_threads() -> int:

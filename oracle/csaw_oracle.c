@@ -566,6 +566,65 @@ int32_t orc_walk(int64_t n, const int64_t* rowptr, const int32_t* col, const uin
     return 0;
 }
 
+/*
+ * Multi-dimensional random walk, a.k.a. frontier sampling (Section II-A; the
+ * VertexBias select site of fig:api(b); worked example fig:layer_example).
+ * Instance i (id iid = instance_base + i) keeps a pool of
+ * P_i = pool_off[i+1] - pool_off[i] vertices, initially
+ * pool[pool_off[i] .. pool_off[i+1]). Step s = 0 .. budget-1:
+ *   VertexBias: b_j = out-degree of pool vertex j, W = sum b_j; W = 0 ends
+ *   the instance.
+ *   Select one frontier vertex: r = draw(iid, s, 0xFFFFFFFF, 0) in [0, W),
+ *   j = its(prefix of b in pool order, r), v = pool[j].
+ *   EdgeBias 1, NeighborSize 1: m = draw(iid, s, v, 1) in [0, deg v),
+ *   u = col[rowptr[v] + m].
+ *   Sampled: edge s of the instance is (v, u).
+ *   Update: pool[j] = u.
+ * Output: src/dst[i * budget + s], -1 once the instance has ended;
+ * steps[i] (nullable) = edges sampled. Returns 0, or 1 on invalid input.
+ */
+int32_t orc_mdrw(int64_t n, const int64_t* rowptr, const int32_t* col, int32_t ni,
+                 const int64_t* pool_off, const int32_t* pool, uint64_t instance_base,
+                 int64_t budget, uint64_t rng_seed, int32_t* src, int32_t* dst, int64_t* steps)
+{
+    if (ni < 0 || budget < 0) return 1;
+    for (int32_t i = 0; i < ni; ++i) {
+        if (pool_off[i + 1] < pool_off[i]) return 1;
+        for (int64_t j = pool_off[i]; j < pool_off[i + 1]; ++j)
+            if (pool[j] < 0 || pool[j] >= n) return 1;
+    }
+    for (int32_t i = 0; i < ni; ++i) {
+        const uint64_t iid = instance_base + (uint64_t)i;
+        const int64_t P = pool_off[i + 1] - pool_off[i];
+        int32_t* fp = (int32_t*)malloc((size_t)(P > 0 ? P : 1) * sizeof(int32_t));
+        uint32_t* b = (uint32_t*)malloc((size_t)(P > 0 ? P : 1) * sizeof(uint32_t));
+        uint64_t* S = (uint64_t*)malloc((size_t)(P + 1) * sizeof(uint64_t));
+        memcpy(fp, pool + pool_off[i], (size_t)P * sizeof(int32_t));
+        int64_t s = 0;
+        for (; s < budget; ++s) {
+            for (int64_t j = 0; j < P; ++j) b[j] = (uint32_t)(rowptr[fp[j] + 1] - rowptr[fp[j]]);
+            prefix(b, P, S);
+            if (S[P] == 0) break;
+            const uint64_t r = orc_draw(rng_seed, (uint32_t)iid, (uint32_t)s, 0xFFFFFFFFu, 0u, S[P]);
+            const int64_t j = orc_its(S, P, r);
+            const int32_t v = fp[j];
+            const int64_t d = rowptr[v + 1] - rowptr[v];
+            const uint64_t m = orc_draw(rng_seed, (uint32_t)iid, (uint32_t)s, (uint32_t)v, 1u, (uint64_t)d);
+            const int32_t u = col[rowptr[v] + (int64_t)m];
+            src[(int64_t)i * budget + s] = v;
+            dst[(int64_t)i * budget + s] = u;
+            fp[j] = u;
+        }
+        if (steps) steps[i] = s;
+        for (int64_t q = s; q < budget; ++q) {
+            src[(int64_t)i * budget + q] = -1;
+            dst[(int64_t)i * budget + q] = -1;
+        }
+        free(fp); free(b); free(S);
+    }
+    return 0;
+}
+
 /* Number of OpenMP threads a parallel region would use (for reporting). */
 int32_t orc_max_threads(void)
 {
