@@ -216,6 +216,43 @@ typedef struct {
 csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* args, int32_t* paths,
                       int64_t* total_steps, csaw_stream stream);
 
+/* ------------------------------------------- multi-dimensional random walk */
+
+/* Multi-dimensional random walk, a.k.a. frontier sampling (Section II-A;
+ * the VertexBias select site of fig:api(b); example fig:layer_example).
+ * Instance i (id instance_base + i) keeps a pool of
+ * P_i = pool_offsets[i+1] - pool_offsets[i] vertices (the FrontierPool),
+ * initially pool[pool_offsets[i] .. pool_offsets[i+1]). At step
+ * s = 0 .. budget-1 one pool vertex v is selected with probability
+ * deg(v) / (total pool degree) (VertexBias = out-degree, Philox counter
+ * (instance id, s, 0xFFFFFFFF, 0) over the degree prefix in pool order),
+ * one neighbor u of v uniformly (counter (instance id, s, v, 1)), the edge
+ * (v, u) is sampled and u replaces v in the pool (Update). An instance whose
+ * pool has total degree 0 ends. */
+#define CSAW_MAX_POOL 2048
+
+typedef struct {
+    int32_t num_instances;        /* >= 0                                         */
+    const int64_t* pool_offsets;  /* HOST int64[num_instances+1], non-decreasing,
+                                     pool_offsets[0] = 0, every pool of at most
+                                     CSAW_MAX_POOL vertices                       */
+    const int32_t* pool;          /* DEVICE int32[pool_offsets[num_instances]],
+                                     ids in [0, n)                                */
+    uint64_t instance_base;       /* instance i has id instance_base + i          */
+    int64_t budget;               /* edges sampled per instance, >= 0             */
+    uint64_t rng_seed;            /* Philox key                                   */
+} csaw_mdrw_args;
+
+/* src, dst: DEVICE int32[num_instances * budget], instance-major in step
+ * order; entries after an instance has ended are -1.
+ * steps: DEVICE int64[num_instances] or NULL: edges sampled per instance.
+ * total_edges: HOST int64 or NULL: edges sampled by all instances.
+ * Errors: INVALID_ARG (bad argument, or a pool vertex outside [0, n)
+ * detected on the device: outputs are then unspecified); UNSUPPORTED for a
+ * pool larger than CSAW_MAX_POOL. */
+csaw_status csaw_mdrw(csaw_graph g, const csaw_mdrw_args* args, int32_t* src, int32_t* dst, int64_t* steps,
+                      int64_t* total_edges, csaw_stream stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A request server over one resident graph: requests (one sampling instance

@@ -55,6 +55,11 @@ class WalkArgs(ctypes.Structure):
                 ("rng_seed", ctypes.c_uint64), ("walker_ids", ctypes.c_void_p)]
 
 
+class MdrwArgs(ctypes.Structure):
+    _fields_ = [("num_instances", ctypes.c_int32), ("pool_offsets", ctypes.c_void_p), ("pool", ctypes.c_void_p),
+                ("instance_base", ctypes.c_uint64), ("budget", ctypes.c_int64), ("rng_seed", ctypes.c_uint64)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("num_streams", ctypes.c_int32)]
@@ -78,7 +83,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample",
-           "csaw_sample_bound", "csaw_walk", "csaw_profile_enable", "csaw_profile_reset",
+           "csaw_sample_bound", "csaw_walk", "csaw_mdrw", "csaw_profile_enable", "csaw_profile_reset",
            "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
            "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_result_free",
            "csaw_server_destroy"]
@@ -95,6 +100,7 @@ def _load():
     L.csaw_sample.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), vp]
     L.csaw_sample_bound.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(ctypes.c_int64)]
     L.csaw_walk.argtypes = [vp, ctypes.POINTER(WalkArgs), vp, ctypes.POINTER(ctypes.c_int64), vp]
+    L.csaw_mdrw.argtypes = [vp, ctypes.POINTER(MdrwArgs), vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
     L.csaw_profile_enable.argtypes = [i32]
     L.csaw_profile_reset.argtypes = []
     L.csaw_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -293,6 +299,33 @@ class Graph:
         _check(lib.csaw_walk(self._h, ctypes.byref(a), paths.data_ptr() if nw else None,
                              ctypes.byref(steps), _stream(stream)))
         return paths, steps.value
+
+    def mdrw(self, pool_offsets, pool, budget, rng_seed=1, instance_base=0, stream=None, out=None):
+        """Multi-dimensional random walks (csaw_mdrw): one frontier pool per
+        instance, ``budget`` steps each. Returns (src [ni, budget], dst
+        [ni, budget], steps [ni] int64, all device tensors, total edges)."""
+        po = np.ascontiguousarray(pool_offsets, dtype=np.int64)
+        ni = len(po) - 1
+        pl = _dev_i32(pool, self.device)
+        if out is None:
+            src = torch.empty((ni, budget), dtype=torch.int32, device=self.device)
+            dst = torch.empty((ni, budget), dtype=torch.int32, device=self.device)
+            steps = torch.empty(max(ni, 1), dtype=torch.int64, device=self.device)
+        else:
+            src, dst, steps = out
+        a = MdrwArgs()
+        a.num_instances = ni
+        a.pool_offsets = po.ctypes.data
+        a.pool = pl.data_ptr() if pl.numel() else None
+        a.instance_base = int(instance_base)
+        a.budget = int(budget)
+        a.rng_seed = int(rng_seed)
+        total = ctypes.c_int64()
+        big = ni * budget > 0
+        _check(lib.csaw_mdrw(self._h, ctypes.byref(a), src.data_ptr() if big else None,
+                             dst.data_ptr() if big else None, steps.data_ptr(), ctypes.byref(total),
+                             _stream(stream)))
+        return src, dst, steps[:ni], total.value
 
 
 def profile_enable(on: bool = True):

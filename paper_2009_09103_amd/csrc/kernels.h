@@ -165,4 +165,22 @@ struct WalkParams {
 };
 void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev = {});
 
+// --- multi-dimensional random walk (mdrw_kernels.hip)
+constexpr int kMaxPool = 2048;
+struct MdrwParams {
+    GraphDev g;
+    int32_t num_instances;
+    const int64_t* pool_off;         // [ni+1], host-mapped memory
+    const int32_t* pool;
+    uint64_t instance_base;
+    int64_t budget;
+    uint32_t k0, k1;
+    int32_t* src;
+    int32_t* dst;
+    int64_t* steps;                  // [ni] or null
+    unsigned long long* total;       // device counter
+    int32_t* bad;                    // device flag
+};
+void launch_mdrw(const MdrwParams& p, hipStream_t s, LaunchEvents ev = {});
+
 }  // namespace csaw

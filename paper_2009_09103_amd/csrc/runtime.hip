@@ -820,6 +820,66 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int
     return CSAW_OK;
 }
 
+csaw_status csaw_mdrw(csaw_graph g, const csaw_mdrw_args* a, int32_t* src, int32_t* dst, int64_t* steps,
+                      int64_t* total_edges, csaw_stream stream) {
+    t_err.clear();
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (!a) return fail(CSAW_ERR_INVALID_ARG, "args is NULL");
+    if (a->num_instances < 0 || a->budget < 0) return fail(CSAW_ERR_INVALID_ARG, "negative num_instances or budget");
+    const int32_t ni = a->num_instances;
+    if (ni > 0 && !a->pool_offsets) return fail(CSAW_ERR_INVALID_ARG, "pool_offsets is NULL");
+    if (ni > 0 && a->pool_offsets[0] != 0) return fail(CSAW_ERR_INVALID_ARG, "pool_offsets[0] != 0");
+    for (int32_t i = 0; i < ni; ++i) {
+        const int64_t P = a->pool_offsets[i + 1] - a->pool_offsets[i];
+        if (P < 0) return fail(CSAW_ERR_INVALID_ARG, "pool_offsets decreases at %d", i);
+        if (P > kMaxPool) return fail(CSAW_ERR_UNSUPPORTED, "pool %d has %lld vertices (most %d)", i, (long long)P, kMaxPool);
+    }
+    if (ni > 0 && a->pool_offsets[ni] > 0 && !a->pool) return fail(CSAW_ERR_INVALID_ARG, "pool is NULL");
+    if ((int64_t)ni * a->budget > 0 && (!src || !dst)) return fail(CSAW_ERR_INVALID_ARG, "src/dst is NULL");
+    if (total_edges) *total_edges = 0;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OR_FAIL(hipSetDevice(g->device));
+    if (ni == 0) return CSAW_OK;
+    Workspace* ws = acquire(g);
+    Lease rel{g, ws, s};
+    csaw_status st;
+    if ((st = ensure_arena(ws, 512)) != CSAW_OK) return st;
+    // pinned block: [0, 512) read-back of the counters, then the pool offsets
+    const size_t o_off = 512;
+    if ((st = ensure_pinned(ws, o_off + ((size_t)ni + 1) * sizeof(int64_t))) != CSAW_OK) return st;
+    std::memcpy(ws->pinned + o_off, a->pool_offsets, ((size_t)ni + 1) * sizeof(int64_t));
+    unsigned long long* d_total = (unsigned long long*)ws->arena;
+    int32_t* d_bad = (int32_t*)(ws->arena + 256);
+    HIP_OR_FAIL(hipMemsetAsync(ws->arena, 0, 512, s));
+    MdrwParams p;
+    p.g = g->dev();
+    p.num_instances = ni;
+    p.pool_off = (const int64_t*)(ws->pinned_dev + o_off);
+    p.pool = a->pool;
+    p.instance_base = a->instance_base;
+    p.budget = a->budget;
+    p.k0 = (uint32_t)a->rng_seed;
+    p.k1 = (uint32_t)(a->rng_seed >> 32);
+    p.src = src;
+    p.dst = dst;
+    p.steps = steps;
+    p.total = d_total;
+    p.bad = d_bad;
+    {
+        ProfScope ps("mdrw", s, true);
+        launch_mdrw(p, s, ps.ev());
+    }
+    HIP_OR_FAIL(hipGetLastError());
+    HIP_OR_FAIL(hipMemcpyAsync(ws->pinned, ws->arena, 512, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    rel.clean = true;
+    const unsigned long long tot = *(unsigned long long*)ws->pinned;
+    const int32_t bad = *(int32_t*)(ws->pinned + 256);
+    if (total_edges) *total_edges = (int64_t)tot;
+    if (bad) return fail(CSAW_ERR_INVALID_ARG, "a pool vertex is outside [0, n)");
+    return CSAW_OK;
+}
+
 csaw_status csaw_profile_enable(int32_t on) {
     g_prof.store(on != 0);
     return CSAW_OK;
