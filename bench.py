@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark of the biased neighbor-selection hot path on one MI355X.
 
-A step is one full csaw_sample call (every layer: count, scan, select,
-frontier update) over the degree-biased workload: R-MAT 22 (edge factor 16),
+A step is one full csaw_sample call (every layer: frontier build, select,
+long-list pass) over the degree-biased workload: R-MAT 22 (edge factor 16),
 one instance of 8,192 distinct seeds, fanouts [25, 10, 5], bias = out-degree
 of the neighbor, Philox seeds cycling over {1, 2, 3}. Inputs (graph, seeds,
 output buffers) are resident in HBM before timing starts.
@@ -10,6 +10,10 @@ output buffers) are resident in HBM before timing starts.
 Prints one JSON line: SEPS (sampled edges per second), the roofline of the
 dominant kernel (select) from HIP-event kernel times and the algorithmic byte
 model, and the CPU oracle timed on the host.
+
+Other workloads (--workload): batched (4,096 instances in one call against
+4,096 plain calls), node2vec (R-MAT 24 walks), mdrw (multi-dimensional
+random walks), copy (a 1 GiB device copy, the HBM counter calibration).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -381,6 +385,60 @@ def bench_served(args):
     }
 
 
+def bench_mdrw(args):
+    """Multi-dimensional random walks at the paper's setting (2,000
+    instances, frontier pools of 2,000 vertices, 1,703 sampled edges each) on
+    the degree-biased R-MAT 22 graph."""
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    rec = inputs.DEGREE_BIASED
+    log("generating R-MAT %d graph" % rec["scale"])
+    rp, col = inputs.graph_for(rec)
+    g = csaw.Graph(rp, col)
+    ni, P, budget = 2000, 2000, 1703
+    pool_vertices = inputs.non_isolated(rp, col)
+    gen = inputs.rng(7707)
+    pool = pool_vertices[gen.integers(0, len(pool_vertices), size=ni * P)].astype(np.int32)
+    po = np.arange(ni + 1, dtype=np.int64) * P
+    pool_d = torch.from_numpy(pool).to(g.device)
+    src = torch.empty((ni, budget), dtype=torch.int32, device=g.device)
+    dst = torch.empty_like(src)
+    steps = torch.empty(ni, dtype=torch.int64, device=g.device)
+    out = (src, dst, steps)
+    _, _, _, total = g.mdrw(po, pool_d, budget, rng_seed=1, out=out)
+    for i in range(args.warmup):
+        g.mdrw(po, pool_d, budget, rng_seed=1 + (i % 3), out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    edges = 0
+    for i in range(args.steps):
+        edges += g.mdrw(po, pool_d, budget, rng_seed=1 + (i % 3), out=out)[3]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    csaw.profile_reset()
+    csaw.profile_enable(True)
+    g.mdrw(po, pool_d, budget, rng_seed=1, out=out)
+    torch.cuda.synchronize()
+    kms, kn = csaw.profile_read("mdrw")
+    csaw.profile_enable(False)
+    csaw.profile_reset()
+    # per instance: the pool (4 B id + 16 B row offsets per slot), per step the
+    # sampled neighbor id (4), its row offsets (16) and the edge written (8)
+    alg = ni * P * 20.0 + total * 28.0
+    achieved = alg / (kms / 1e3) / 1e9 if kms > 0 else 0.0
+    return {
+        "metric": "sampled edges/sec (SEPS), multi-dimensional random walk",
+        "value": edges / args.steps / dt, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": "mdrw_rmat22", "instances": ni, "pool": P, "edges_per_instance": budget},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_mdrw", "launches": kn,
+                     "avg_launch_us": kms / max(kn, 1) * 1e3, "alg_bytes_per_launch": alg},
+    }
+
+
 def walk_bytes_node2vec(rowptr, paths):
     """Algorithmic bytes of node2vec walks from their paths: a step from v
     with previous vertex t reads v's row offsets (16), N(v) (4 d_v: biases
@@ -536,6 +594,8 @@ def main():
         sys.exit(3)
     elif args.workload == "node2vec":
         line = bench_node2vec(args)
+    elif args.workload == "mdrw":
+        line = bench_mdrw(args)
     elif args.workload == "copy":
         line = bench_copy(args)
     else:
