@@ -82,7 +82,7 @@ def lib():
                                      u64, i32, i64, vp, vp, vp, vp, vp, i32]
             L.orc_sample.restype = i32
             L.orc_walk.argtypes = [i64, vp, vp, vp, i32, u32, u32, u32, i64, vp, u64, vp, i32, u64,
-                                   vp, vp, vp, i32]
+                                   u32, u32, vp, vp, vp, i32]
             L.orc_walk.restype = i32
             L.orc_mdrw.argtypes = [i64, vp, vp, i32, vp, vp, u64, i64, u64, vp, vp, vp]
             L.orc_mdrw.restype = i32
@@ -205,8 +205,10 @@ def sample(rowptr, col, ew, seed_offsets, seeds, fanouts, bias_kind=UNIFORM, rng
 
 
 def walk(rowptr, col, ew, starts, length, bias_kind=UNIFORM, rng_seed=1, walker_base=0,
-         walker_ids=None, node2vec=(1, 1, 1), nthreads=0):
-    """Random walks (see ``orc_walk``). Returns (paths [nw, length+1], steps [nw], stats)."""
+         walker_ids=None, node2vec=(1, 1, 1), nthreads=0, restart=0, jump=0):
+    """Random walks (see ``orc_walk``); restart / jump are the per-step
+    thresholds in [0, 2^32] (probability * 2^32). Returns (paths [nw,
+    length+1], steps [nw], stats)."""
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
     col = np.ascontiguousarray(col, dtype=np.int32)
     ew = None if ew is None else np.ascontiguousarray(ew, dtype=np.uint32)
@@ -218,8 +220,8 @@ def walk(rowptr, col, ew, starts, length, bias_kind=UNIFORM, rng_seed=1, walker_
     stats = np.zeros(2, dtype=np.float64)
     wr, wc, wo = node2vec
     rc = lib().orc_walk(len(rowptr) - 1, _p(rowptr), _p(col), _p(ew), bias_kind, wr, wc, wo, nw,
-                        _p(starts), walker_base, _p(ids), length, rng_seed, _p(paths), _p(steps),
-                        _p(stats), nthreads)
+                        _p(starts), walker_base, _p(ids), length, rng_seed, restart, jump, _p(paths),
+                        _p(steps), _p(stats), nthreads)
     if rc != 0:
         raise ValueError("oracle: invalid walk input")
     return paths, steps, tuple(stats)

@@ -487,6 +487,14 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
  * drawn with replacement (round 0, slot 0): counter (wid mod 2^32, s, v, 0),
  * r in [0, W), m = its(r), and the walk moves to col[rowptr[v] + m].
  * NODE2VEC tests membership of x in N(t) with a marker array.
+ * Restart and jump (Section II-A, random walk with restart / with jump, as
+ * Update rules): when restart_threshold or jump_threshold is non-zero, every
+ * step first draws x in [0, 2^32) with counter (wid, s, v, 2); x <
+ * restart_threshold moves the walker back to its start, otherwise x <
+ * restart_threshold + jump_threshold moves it to the vertex drawn in [0, n)
+ * with counter (wid, s, v, 3); either move is a step and forgets the
+ * previous vertex (the next node2vec step is unbiased). Otherwise the step is
+ * the one above, including the stop at a dead end.
  *
  * paths: int32[nw * (length+1)], walker-major. steps (nullable): int64[nw],
  * number of steps taken. stats (nullable, double[2]): algorithmic bytes,
@@ -495,11 +503,13 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
 int32_t orc_walk(int64_t n, const int64_t* rowptr, const int32_t* col, const uint32_t* ew,
                  int32_t bias_kind, uint32_t w_return, uint32_t w_common, uint32_t w_outward,
                  int64_t nw, const int32_t* starts, uint64_t walker_base, const uint64_t* walker_ids,
-                 int32_t length, uint64_t rng_seed, int32_t* paths, int64_t* steps,
-                 double* stats, int32_t nthreads)
+                 int32_t length, uint64_t rng_seed, uint32_t restart_threshold, uint32_t jump_threshold,
+                 int32_t* paths, int64_t* steps, double* stats, int32_t nthreads)
 {
     orc_graph g = {n, rowptr, col, ew};
     if (length < 0 || nw < 0) return 1;
+    if ((uint64_t)restart_threshold + (uint64_t)jump_threshold > ((uint64_t)1 << 32)) return 1;
+    if (jump_threshold && n == 0) return 1;
     if (bias_kind < ORC_UNIFORM || bias_kind > ORC_NODE2VEC) return 1;
     if (bias_kind == ORC_EDGE_WEIGHT && !ew) return 1;
     for (int64_t w = 0; w < nw; ++w)
@@ -523,6 +533,21 @@ int32_t orc_walk(int64_t n, const int64_t* rowptr, const int32_t* col, const uin
             path[0] = (int32_t)v;
             int32_t s = 0;
             for (; s < length; ++s) {
+                if (restart_threshold | jump_threshold) {
+                    const uint64_t x = orc_draw(rng_seed, (uint32_t)wid, (uint32_t)s, (uint32_t)v, 2u,
+                                                (uint64_t)1 << 32);
+                    int64_t to = -1;
+                    if (x < restart_threshold) to = starts[w];
+                    else if (x < (uint64_t)restart_threshold + jump_threshold)
+                        to = (int64_t)orc_draw(rng_seed, (uint32_t)wid, (uint32_t)s, (uint32_t)v, 3u, (uint64_t)n);
+                    if (to >= 0) {
+                        path[s + 1] = (int32_t)to;
+                        t = -1;
+                        v = to;
+                        tot_bytes += 8.0;
+                        continue;
+                    }
+                }
                 int64_t d = deg(&g, v), beg = rowptr[v];
                 if (d == 0) break;
                 if (d > bcap) { bcap = d; b = (uint32_t*)realloc(b, (size_t)bcap * sizeof(uint32_t)); }

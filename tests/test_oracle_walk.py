@@ -173,3 +173,81 @@ def test_walk_threads_and_subsets_agree():
     sub, _, _ = oracle.walk(rp, col, None, starts[idx], 15, bias_kind=oracle.NODE2VEC,
                             node2vec=(1, 2, 4), rng_seed=4, walker_ids=idx.astype(np.uint64))
     np.testing.assert_array_equal(sub, full[idx])
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.25, 0.0), (0.0, 0.125), (0.25, 0.125)])
+def test_restart_jump_t_step_law(alpha, beta):
+    """Random walk with restart / with jump: each step moves to the start
+    with probability alpha, to a uniform vertex with probability beta, and
+    otherwise takes the biased step (or stops at a dead end); the exact t-step
+    law is the matrix power of that chain."""
+    rp, col = small_graph(seed=4, n=9, m=20, directed=True)    # sinks possible
+    n = len(rp) - 1
+    ew = np.random.Generator(np.random.PCG64(2)).integers(0, 9, size=len(col)).astype(np.uint32)
+    start = int(np.argmax(np.diff(rp)))
+    T = 4
+    ra, ja = int(alpha * 2 ** 32), int(beta * 2 ** 32)
+    paths, steps, _ = oracle.walk(rp, col, ew, np.full(NW, start, dtype=np.int32), T,
+                                  bias_kind=oracle.EDGE_WEIGHT, rng_seed=13, restart=ra, jump=ja)
+    P = first_order_matrix(rp, col, ew)
+    Q = (1 - alpha - beta) * P
+    Q[:n, start] += alpha
+    Q[:n, :n] += beta / n
+    Q[n, :] = 0
+    Q[n, n] = 1.0
+    p = np.zeros(n + 1)
+    p[start] = 1
+    for t in range(1, T + 1):
+        p = p @ Q
+        pos = paths[:, t]
+        compare(np.bincount(np.where(pos < 0, n, pos), minlength=n + 1), p)
+    valid = (paths[:, 1:] >= 0)
+    assert np.all(valid.sum(axis=1) == steps)
+
+
+@pytest.mark.parametrize("kind", ["edge_weight", "node2vec"])
+def test_restart_jump_draw_layout(kind):
+    """The move draw uses counter (walker id, step, vertex, 2) over [0, 2^32)
+    and the jump target (walker id, step, vertex, 3) over [0, n); after a
+    move the previous vertex is forgotten (node2vec's next step is unbiased).
+    Recomputed with the independent Philox."""
+    from tests.helpers import torch_philox
+    rp, col = inputs.rmat_csr(9, 4096, 8, symmetrize=True)
+    n = len(rp) - 1
+    ew = inputs.dst_outdeg_weights(rp, col) + 1
+    starts = inputs.walker_starts(rp, col, 5, 4)
+    ra, ja = 1 << 30, 1 << 29
+    if kind == "edge_weight":
+        paths, _, _ = oracle.walk(rp, col, ew, starts, 12, bias_kind=oracle.EDGE_WEIGHT, rng_seed=77,
+                                  walker_base=900, restart=ra, jump=ja)
+    else:
+        paths, _, _ = oracle.walk(rp, col, None, starts, 12, bias_kind=oracle.NODE2VEC, rng_seed=77,
+                                  walker_base=900, restart=ra, jump=ja, node2vec=(1, 2, 4))
+    moves = 0
+    for w in range(5):
+        v, t = int(starts[w]), -1
+        for s in range(12):
+            x = torch_philox.draw(77, [900 + w, s, v, 2], 2 ** 32)
+            if x < ra + ja:
+                nxt = int(starts[w]) if x < ra else torch_philox.draw(77, [900 + w, s, v, 3], n)
+                assert paths[w, s + 1] == nxt
+                v, t = nxt, -1
+                moves += 1
+                continue
+            nb = col[rp[v]:rp[v + 1]]
+            if len(nb) == 0:
+                assert paths[w, s + 1] == -1
+                break
+            if kind == "edge_weight":
+                b = ew[rp[v]:rp[v + 1]].astype(np.uint64)
+            elif t < 0:
+                b = np.ones(len(nb), dtype=np.uint64)
+            else:
+                nt = set(col[rp[t]:rp[t + 1]].tolist())
+                b = np.array([1 if x2 == t else (2 if x2 in nt else 4) for x2 in nb.tolist()], dtype=np.uint64)
+            S = np.concatenate([[0], np.cumsum(b)])
+            r = torch_philox.draw(77, [900 + w, s, v, 0], int(S[-1]))
+            m = int(np.searchsorted(S[:-1], r, side="right")) - 1
+            t, v = v, int(nb[m])
+            assert paths[w, s + 1] == v
+    assert moves > 3
