@@ -205,6 +205,16 @@ typedef struct {
     const uint64_t* walker_ids;   /* DEVICE uint64[num_walkers] or NULL: walker w
                                      has this id instead of walker_base + w (an
                                      exact subset of a larger run)                */
+    uint32_t restart_threshold;   /* random walk with restart / with jump
+                                     (Section II-A): each step first draws x in
+                                     [0, 2^32) (counter (walker id, step, v, 2));
+                                     x < restart_threshold moves the walker back to
+                                     its start, x < restart_threshold +
+                                     jump_threshold to a vertex drawn in [0, n)
+                                     (counter (walker id, step, v, 3)); such a move
+                                     is a step and forgets the previous vertex.
+                                     Both 0: plain walks. Their sum is at most 2^32 */
+    uint32_t jump_threshold;
 } csaw_walk_args;
 
 /* paths: DEVICE int32[num_walkers * (length+1)], walker-major; path[0] is

@@ -52,7 +52,8 @@ class WalkArgs(ctypes.Structure):
                 ("w_common", ctypes.c_uint32), ("w_outward", ctypes.c_uint32),
                 ("num_walkers", ctypes.c_int64), ("starts", ctypes.c_void_p),
                 ("walker_base", ctypes.c_uint64), ("length", ctypes.c_int32),
-                ("rng_seed", ctypes.c_uint64), ("walker_ids", ctypes.c_void_p)]
+                ("rng_seed", ctypes.c_uint64), ("walker_ids", ctypes.c_void_p),
+                ("restart_threshold", ctypes.c_uint32), ("jump_threshold", ctypes.c_uint32)]
 
 
 class MdrwArgs(ctypes.Structure):
@@ -274,8 +275,9 @@ class Graph:
 
     # ----------------------------------------------------------------- walks
     def walk(self, starts, length, bias=UNIFORM, rng_seed=1, walker_base=0, node2vec=(1, 1, 1),
-             stream=None, paths=None, walker_ids=None):
-        """Random walks (csaw_walk). Returns (paths [nw, length+1] int32 device
+             stream=None, paths=None, walker_ids=None, restart=0, jump=0):
+        """Random walks (csaw_walk); restart / jump are the per-step move
+        thresholds over [0, 2^32). Returns (paths [nw, length+1] int32 device
         tensor, total steps)."""
         st = _dev_i32(starts, self.device)
         nw = st.numel()
@@ -295,6 +297,8 @@ class Graph:
                 self.device)
             assert ids_dev.numel() == nw
         a.walker_ids = ids_dev.data_ptr() if ids_dev is not None and nw else None
+        a.restart_threshold = int(restart)
+        a.jump_threshold = int(jump)
         steps = ctypes.c_int64()
         _check(lib.csaw_walk(self._h, ctypes.byref(a), paths.data_ptr() if nw else None,
                              ctypes.byref(steps), _stream(stream)))

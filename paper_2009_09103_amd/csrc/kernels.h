@@ -159,6 +159,7 @@ struct WalkParams {
     int32_t length;
     uint32_t k0, k1;
     const uint64_t* walker_ids;      // [nw] or null
+    uint32_t restart, jump;          // per-step move thresholds over [0, 2^32)
     int32_t* paths;
     unsigned long long* steps;       // device counter
     int32_t* bad_start;              // device flag

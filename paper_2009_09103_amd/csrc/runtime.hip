@@ -775,6 +775,8 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int
     if (a->bias_kind == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
     if (a->bias_kind == kNode2vec && !g->sorted) return fail(CSAW_ERR_INVALID_ARG, "NODE2VEC needs sorted adjacency lists");
     if (a->num_walkers < 0 || a->length < 0) return fail(CSAW_ERR_INVALID_ARG, "negative num_walkers or length");
+    if ((uint64_t)a->restart_threshold + (uint64_t)a->jump_threshold > (uint64_t(1) << 32))
+        return fail(CSAW_ERR_INVALID_ARG, "restart_threshold + jump_threshold exceeds 2^32");
     if (a->num_walkers > 0 && (!a->starts || !paths)) return fail(CSAW_ERR_INVALID_ARG, "starts/paths is NULL");
     hipStream_t s = (hipStream_t)stream;
     HIP_OR_FAIL(hipSetDevice(g->device));
@@ -802,6 +804,8 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int
     p.k0 = (uint32_t)a->rng_seed;
     p.k1 = (uint32_t)(a->rng_seed >> 32);
     p.walker_ids = a->walker_ids;
+    p.restart = a->restart_threshold;
+    p.jump = a->jump_threshold;
     p.paths = paths;
     p.steps = d_steps;
     p.bad_start = d_bad;

@@ -22,6 +22,25 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
+// Restart / jump rule of a step: draws x in [0, 2^32) with counter (walker,
+// step, v, 2); below restart the walker returns to its start, below
+// restart + jump it moves to a vertex drawn in [0, n) with counter (walker,
+// step, v, 3). Returns whether the step is such a move.
+__device__ __forceinline__ bool walk_move(const WalkParams& p, Key key, uint32_t c0, int32_t s, int32_t v,
+                                         int32_t start, int32_t& to) {
+    if ((p.restart | p.jump) == 0) return false;
+    const uint64_t x = draw(key, c0, (uint32_t)s, (uint32_t)v, 2u, 1ull << 32);
+    if (x < (uint64_t)p.restart) {
+        to = start;
+        return true;
+    }
+    if (x < (uint64_t)p.restart + p.jump) {
+        to = (int32_t)draw(key, c0, (uint32_t)s, (uint32_t)v, 3u, (uint64_t)p.g.n);
+        return true;
+    }
+    return false;
+}
+
 __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
     const Key key{p.k0, p.k1};
     const int64_t L1 = (int64_t)p.length + 1;
@@ -38,8 +57,15 @@ __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
                 for (int64_t q = 0; q < L1; ++q) path[q] = -1;
             } else {
                 path[0] = v;
+                const int32_t start = v;
                 const uint32_t c0 = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
                 for (; s < p.length; ++s) {
+                    int32_t to;
+                    if (walk_move(p, key, c0, s, v, start, to)) {
+                        v = to;
+                        path[s + 1] = v;
+                        continue;
+                    }
                     const int64_t beg = p.g.rowptr[v];
                     const int64_t d = p.g.rowptr[v + 1] - beg;
                     if (d == 0) break;
@@ -412,7 +438,7 @@ __device__ __forceinline__ int64_t walk_step_n2v(const WalkParams& p, WalkLds<tr
     return m;
 }
 
-template <bool kN2v>
+template <bool kN2v, bool kMoves>
 __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
     __shared__ WalkLds<kN2v> lds_all[kWavesPerBlock];
     const int lane = lane_id();
@@ -431,10 +457,19 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
         }
         if (lane == 0) path[0] = v;
         const uint32_t c0 = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
+        const int32_t start = v;
         int32_t t = -1;
         int64_t tb = 0, te = 0;
         int32_t s = 0;
         for (; s < p.length; ++s) {
+            int32_t to;
+            if (kMoves && walk_move(p, key, c0, s, v, start, to)) {  // uniform: the draw depends on wave-uniform values
+                if (lane == 0) path[s + 1] = to;
+                v = to;
+                t = -1;
+                tb = te = 0;
+                continue;
+            }
             const int64_t beg = uniform_i64(p.g.rowptr[v]);
             const int64_t d = uniform_i64(p.g.rowptr[v + 1]) - beg;
             if (d == 0) break;
@@ -476,10 +511,14 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev) 
     } else {
         int64_t g = (p.num_walkers + kWavesPerBlock - 1) / kWavesPerBlock;
         if (g > grid) g = grid;
-        if (p.bias == kNode2vec)
-            launch_kernel(k_walk_wave<true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
-        else
-            launch_kernel(k_walk_wave<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+        const bool moves = (p.restart | p.jump) != 0;
+        if (p.bias == kNode2vec) {
+            if (moves) launch_kernel(k_walk_wave<true, true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            else launch_kernel(k_walk_wave<true, false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+        } else {
+            if (moves) launch_kernel(k_walk_wave<false, true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            else launch_kernel(k_walk_wave<false, false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+        }
     }
 }
 

@@ -115,3 +115,23 @@ def test_node2vec_rmat24_shape_subset(csaw):
                             walker_ids=idx.astype(np.uint64))
     np.testing.assert_array_equal(paths.cpu().numpy()[idx], ref)
     assert steps == len(starts) * 80
+
+
+@pytest.mark.parametrize("bias,restart,jump", [(0, 1 << 30, 0), (1, 0, 1 << 29), (2, 1 << 29, 1 << 28),
+                                               (3, 1 << 30, 1 << 29), (3, 0, 1 << 31)])
+def test_restart_and_jump(csaw, bias, restart, jump):
+    """Random walk with restart / with jump: the per-step move rule (to the
+    start, or to a uniform vertex) on every kernel route, bit for bit."""
+    rp, col = inputs.rmat_csr(14, 8 << 14, 24, symmetrize=True)
+    ew = inputs.dst_outdeg_weights(rp, col)
+    starts = inputs.walker_starts(rp, col, 3000, 6)
+    g = csaw.Graph(rp, col, ew)
+    w = (1, 2, 4) if bias == 3 else (1, 1, 1)
+    say("walk restart=%d jump=%d bias=%d" % (restart, jump, bias))
+    paths, steps = g.walk(starts, 25, bias, rng_seed=31, walker_base=7, node2vec=w, restart=restart, jump=jump)
+    ref, rs, _ = oracle.walk(rp, col, ew, starts, 25, bias_kind=bias, rng_seed=31, walker_base=7, node2vec=w,
+                             restart=restart, jump=jump)
+    np.testing.assert_array_equal(paths.cpu().numpy(), ref)
+    assert steps == int(rs.sum())
+    with pytest.raises(csaw.CsawError):
+        g.walk(starts[:4], 5, bias, restart=1 << 31, jump=(1 << 31) + 1)
