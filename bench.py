@@ -40,19 +40,30 @@ def log(msg):
 WAVE_MAX_D = 512  # longer (or 2^32-heavy) weighted lists that need draws take the long-list path
 
 
-def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted):
+def small_bucket(c, d, k, take, wflag, long_, bound):
+    """Entries served by the sub-wave kernel (select_small) under the bucket
+    bound max(bound16, bound32): take-all and weighted lists of at most
+    `bound` candidates, unbiased draws of at most `bound` slots."""
+    if bound <= 0:
+        return np.zeros(len(c), dtype=bool)
+    size = np.where(take | wflag, d, k)
+    return (c > 0) & ~long_ & (size <= bound)
+
+
+def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted, bound=0):
     """Algorithmic bytes of one call, per kernel, from the graph and the
     call's own output. Per frontier vertex: 8 (frontier entry) + 16 (row-offset
-    pair) bytes of metadata. Lists drawn by the wavefront kernel (select_wave)
-    add 4*deg if the bias reads a weight array; long weighted lists read their
-    4*deg weight bytes in chunk_prefix, which writes one 8-byte group prefix
-    per 16 weights that select_big reads back. Every emitted edge costs 12
-    (neighbor id read + edge written) in the kernel that draws it."""
+    pair) bytes of metadata. Lists drawn by the wavefront kernels (select_small
+    for the sub-wave buckets, select_wave for the rest) add 4*deg if the bias
+    reads a weight array; long weighted lists read their 4*deg weight bytes in
+    chunk_prefix, which writes one 8-byte group prefix per 16 weights that
+    select_big reads back. Every emitted edge costs 12 (neighbor id read +
+    edge written) in the kernel that draws it."""
     deg = np.diff(rowptr)
     L = len(fanouts)
     visited = np.unique(seeds)
     frontier = visited
-    out = {"select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
+    out = {"select_small": 0.0, "select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
     for l in range(L):
         a, b = offsets[l], offsets[l + 1]
         k = int(fanouts[l])
@@ -61,8 +72,9 @@ def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted):
         c = np.where((k == 0) | (P == 0), 0, np.where((k < 0) | (k >= P), P, k)).astype(np.float64)
         assert int(c.sum()) == b - a
         long_ = weighted & (k > 0) & (k < P) & (deg[frontier] > WAVE_MAX_D)
-        w = ~long_
-        out["select_wave"] += 24.0 * w.sum() + 12.0 * c[w].sum() + (4.0 * d[w].sum() if weighted else 0.0)
+        sm = small_bucket(c, d, k, (k < 0) | (k >= P), np.full(len(c), weighted), long_, bound)
+        for name, w in (("select_small", sm), ("select_wave", ~long_ & ~sm)):
+            out[name] += 24.0 * w.sum() + 12.0 * c[w].sum() + (4.0 * d[w].sum() if weighted else 0.0)
         groups = np.ceil(d[long_] / 16.0)
         out["chunk_prefix"] += 4.0 * d[long_].sum() + 8.0 * groups.sum() + 8.0 * np.ceil(d[long_] / 1024.0).sum()
         out["select_big"] += 24.0 * long_.sum() + 8.0 * groups.sum() + 12.0 * c[long_].sum()
@@ -94,6 +106,18 @@ def cpu_baseline(rp, col, offs, seeds, fanouts, bias, min_s=10.0, max_runs=60):
                            len(seeds), runs, t_used, threads))
 
 
+def apply_tuning(g, args, *call, **kw):
+    """Sub-wave bucket setting for the timed calls: the library default, a
+    fixed "b16,b32", or "auto" (the library's autotuner run on the timed call
+    itself; every setting gives the same edges)."""
+    if args.tuning == "auto":
+        _, t = g.autotune_sample(*call, reps=3, **kw)
+        log("autotuner chose bound16=%d bound32=%d" % t)
+    elif args.tuning != "default":
+        g.set_tuning(*(int(x) for x in args.tuning.split(",")))
+    return {"bound16": g.get_tuning()[0], "bound32": g.get_tuning()[1], "source": args.tuning}
+
+
 def bench_degree_biased(args):
     import torch
     from paper_2009_09103_amd import csaw, inputs
@@ -120,11 +144,13 @@ def bench_degree_biased(args):
     ppos = np.add.reduceat(np.append((deg[col] > 0).astype(np.int64), 0), rp[:-1])
     ppos[deg == 0] = 0
     edges_of, bytes_of = {}, {}
+    tuning = apply_tuning(g, args, offs, seeds_d, fan, bias, rng_seed=rng_seeds[0], out=(src, dst, offsets))
+    bound = max(tuning["bound16"], tuning["bound32"])
     for s in rng_seeds:
         r = g.sample(offs, seeds_d, fan, bias, rng_seed=s, out=(src, dst, offsets))
         o = offsets.cpu().numpy()
         edges_of[s] = r.num_edges
-        bytes_of[s] = path_bytes(rp, ppos, seeds, dst[:r.num_edges].cpu().numpy(), o, fan, True)
+        bytes_of[s] = path_bytes(rp, ppos, seeds, dst[:r.num_edges].cpu().numpy(), o, fan, True, bound)
         log("seed %d: %d edges" % (s, r.num_edges))
 
     for i in range(args.warmup):
@@ -143,15 +169,15 @@ def bench_degree_biased(args):
     # kernel times from HIP events on the call's stream (separate pass)
     csaw.profile_reset()
     csaw.profile_enable(True)
-    alg = {"select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
+    alg = {"select_small": 0.0, "select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
     for i in range(args.steps):
         s = rng_seeds[i % 3]
         g.sample(offs, seeds_d, fan, bias, rng_seed=s, out=(src, dst, offsets))
         for k in alg:
             alg[k] += bytes_of[s][k]
     torch.cuda.synchronize()
-    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_wave", "chunk_prefix", "select_big",
-                                                "frontier_build", "visited_clear")}
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_small", "select_wave", "chunk_prefix",
+                                                "select_big", "frontier_build", "visited_clear")}
     csaw.profile_enable(False)
     csaw.profile_reset()
     sel_ms, sel_n = times["select_wave"]
@@ -178,7 +204,8 @@ def bench_degree_biased(args):
         "config": {"workload": rec["name"], "graph": "R-MAT scale 22, edge factor 16 (a=.57,b=.19,c=.19)",
                    "n": int(len(rp) - 1), "m": int(len(col)), "instances": 1,
                    "seeds": int(len(seeds)), "fanouts": rec["fanouts"], "bias": "out-degree of neighbor",
-                   "rng_seeds": rng_seeds, "edges_per_step": float(np.mean(list(edges_of.values())))},
+                   "rng_seeds": rng_seeds, "edges_per_step": float(np.mean(list(edges_of.values()))),
+                   "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("traffic_select_degree_biased_rmat22.md"),
@@ -197,7 +224,7 @@ def bench_degree_biased(args):
     return line
 
 
-def path_bytes_multi(rowptr, ppos, seed_offs, seeds, dst, offsets, fanouts, bias):
+def path_bytes_multi(rowptr, ppos, seed_offs, seeds, dst, offsets, fanouts, bias, bound=0):
     """path_bytes for a multi-instance call: frontier entries are (instance,
     vertex) pairs (keys instance * n + vertex), each instance with its own
     fanout row and bias kind; offsets[l * ni + i] is the first edge of (layer
@@ -209,7 +236,7 @@ def path_bytes_multi(rowptr, ppos, seed_offs, seeds, dst, offsets, fanouts, bias
     inst_of_seed = np.repeat(np.arange(ni, dtype=np.int64), np.diff(seed_offs))
     visited = np.unique(inst_of_seed * n + seeds.astype(np.int64))
     frontier = visited
-    out = {"select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
+    out = {"select_small": 0.0, "select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
     for l in range(L):
         inst = frontier // n
         v = frontier % n
@@ -220,8 +247,9 @@ def path_bytes_multi(rowptr, ppos, seed_offs, seeds, dst, offsets, fanouts, bias
         c = np.where((k == 0) | (P == 0), 0, np.where((k < 0) | (k >= P), P, k)).astype(np.float64)
         assert int(c.sum()) == offsets[(l + 1) * ni] - offsets[l * ni]
         long_ = wflag & (k > 0) & (k < P) & (deg[v] > WAVE_MAX_D)
-        w = ~long_
-        out["select_wave"] += 24.0 * w.sum() + 12.0 * c[w].sum() + 4.0 * d[w & wflag].sum()
+        sm = small_bucket(c, d, k, (k < 0) | (k >= P), wflag, long_, bound)
+        for name, w in (("select_small", sm), ("select_wave", ~long_ & ~sm)):
+            out[name] += 24.0 * w.sum() + 12.0 * c[w].sum() + 4.0 * d[w & wflag].sum()
         groups = np.ceil(d[long_] / 16.0)
         out["chunk_prefix"] += 4.0 * d[long_].sum() + 8.0 * groups.sum() + 8.0 * np.ceil(d[long_] / 1024.0).sum()
         out["select_big"] += 24.0 * long_.sum() + 8.0 * groups.sum() + 12.0 * c[long_].sum()
@@ -257,6 +285,7 @@ def bench_batched(args):
     offsets = torch.empty(fanouts.shape[1] * ni + 1, dtype=torch.int64, device=dev)
     r = g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
     edges = r.num_edges
+    tuning = apply_tuning(g, args, offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
     for _ in range(args.warmup):
         g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
     torch.cuda.synchronize()
@@ -269,13 +298,14 @@ def bench_batched(args):
     deg = np.diff(rp)
     ppos = np.add.reduceat(np.append((deg[col] > 0).astype(np.int64), 0), rp[:-1])
     ppos[deg == 0] = 0
-    alg = path_bytes_multi(rp, ppos, offs, seeds, dst[:edges].cpu().numpy(), offsets.cpu().numpy(), fanouts, bias)
+    alg = path_bytes_multi(rp, ppos, offs, seeds, dst[:edges].cpu().numpy(), offsets.cpu().numpy(), fanouts, bias,
+                           max(tuning["bound16"], tuning["bound32"]))
     csaw.profile_reset()
     csaw.profile_enable(True)
     g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
     torch.cuda.synchronize()
-    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_wave", "chunk_prefix", "select_big",
-                                                "frontier_build", "visited_clear")}
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_small", "select_wave", "chunk_prefix",
+                                                "select_big", "frontier_build", "visited_clear")}
     csaw.profile_enable(False)
     csaw.profile_reset()
     sel_ms, sel_n = times["select_wave"]
@@ -306,7 +336,7 @@ def bench_batched(args):
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
         "config": {"workload": rec["name"], "instances": ni, "seeds": int(len(seeds)),
-                   "edges_per_step": int(edges)},
+                   "edges_per_step": int(edges), "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "select_wave (k_select)",
                      "launches": sel_n, "avg_launch_us": sel_ms / max(sel_n, 1) * 1e3,
@@ -567,6 +597,8 @@ def main():
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--served-scale", type=int, default=0)
     ap.add_argument("--n2v-scale", type=int, default=0)
+    ap.add_argument("--tuning", default="auto",
+                    help='sub-wave buckets of the sampling kernel: "auto", "default" or "bound16,bound32"')
     ap.add_argument("--n2v-stride", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:

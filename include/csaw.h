@@ -185,6 +185,33 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* args, csaw_sample_
  * HOST out: max_edges. */
 csaw_status csaw_sample_bound(csaw_graph g, const csaw_sample_args* args, int64_t* max_edges);
 
+/* Work assignment of the sampling kernel by degree bucket (the frontier
+ * queue of Section III-A, with sub-wave groups for small lists). A frontier
+ * entry whose work -- the candidates of a take-all list or of a weighted
+ * draw, the slots of an unbiased draw -- is at most bound16 is served by 16
+ * lanes, four entries to a wavefront; at most bound32, by 32 lanes; the
+ * others by a whole wavefront (or the long-list path). 0 turns a bucket off.
+ * Results never depend on these bounds (the draws are keyed by their
+ * counters and taken in slot order either way); only the speed does.
+ * The setting belongs to the graph and applies to later calls. */
+typedef struct {
+    int32_t bound16;              /* [0, 16], default 16                          */
+    int32_t bound32;              /* [0, 32], default 32                          */
+} csaw_tuning;
+
+/* INVALID_ARG if a bound is outside its range. */
+csaw_status csaw_set_tuning(csaw_graph g, const csaw_tuning* tuning);
+/* HOST out: tuning. */
+csaw_status csaw_get_tuning(csaw_graph g, csaw_tuning* tuning);
+
+/* Autotuner: runs csaw_sample(g, args, out, stream) under each candidate
+ * setting (warm-up call, then `reps` timed calls; reps in [1, 100]), keeps
+ * the fastest median on the graph and writes it to *chosen (HOST, nullable).
+ * The outputs are those of csaw_sample, identical under every setting. An
+ * error of any call is returned as is (the graph keeps its previous setting). */
+csaw_status csaw_autotune_sample(csaw_graph g, const csaw_sample_args* args, csaw_sample_out* out, int32_t reps,
+                                 csaw_stream stream, csaw_tuning* chosen);
+
 /* ------------------------------------------------------------------ walks */
 
 /* Random walks (Section II-A: DeepWalk, biased DeepWalk, node2vec,

@@ -61,6 +61,10 @@ class MdrwArgs(ctypes.Structure):
                 ("instance_base", ctypes.c_uint64), ("budget", ctypes.c_int64), ("rng_seed", ctypes.c_uint64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("bound16", ctypes.c_int32), ("bound32", ctypes.c_int32)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("num_streams", ctypes.c_int32)]
@@ -84,8 +88,8 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample",
-           "csaw_sample_bound", "csaw_walk", "csaw_mdrw", "csaw_profile_enable", "csaw_profile_reset",
-           "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
+           "csaw_sample_bound", "csaw_set_tuning", "csaw_get_tuning", "csaw_autotune_sample", "csaw_walk",
+           "csaw_mdrw", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
            "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_result_free",
            "csaw_server_destroy"]
 
@@ -100,6 +104,10 @@ def _load():
     L.csaw_graph_info.argtypes = [vp, vp, vp, vp, vp]
     L.csaw_sample.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), vp]
     L.csaw_sample_bound.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(ctypes.c_int64)]
+    L.csaw_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.csaw_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.csaw_autotune_sample.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), i32, vp,
+                                       ctypes.POINTER(Tuning)]
     L.csaw_walk.argtypes = [vp, ctypes.POINTER(WalkArgs), vp, ctypes.POINTER(ctypes.c_int64), vp]
     L.csaw_mdrw.argtypes = [vp, ctypes.POINTER(MdrwArgs), vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
     L.csaw_profile_enable.argtypes = [i32]
@@ -252,6 +260,33 @@ class Graph:
         """Neighbor sampling (csaw_sample). ``seeds`` may be a device tensor
         (used in place) or host data (copied). ``out`` may pass preallocated
         (src, dst, offsets) device tensors."""
+        return self._run_sample(lambda a, o: lib.csaw_sample(self._h, a, o, _stream(stream)), seed_offsets, seeds,
+                                fanouts, bias, rng_seed, instance_base, capacity, out, instance_ids, rng_seeds)
+
+    def autotune_sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
+                        capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, reps=3):
+        """Autotuner (csaw_autotune_sample): times the call under each
+        sub-wave bucket setting, keeps the fastest on the graph. Returns
+        (SampleResult, (bound16, bound32))."""
+        t = Tuning()
+        res = self._run_sample(lambda a, o: lib.csaw_autotune_sample(self._h, a, o, int(reps), _stream(stream),
+                                                                     ctypes.byref(t)),
+                               seed_offsets, seeds, fanouts, bias, rng_seed, instance_base, capacity, out,
+                               instance_ids, rng_seeds)
+        return res, (t.bound16, t.bound32)
+
+    def set_tuning(self, bound16: int, bound32: int):
+        """Sub-wave bucket bounds of the sampling kernel (csaw_set_tuning)."""
+        t = Tuning(int(bound16), int(bound32))
+        _check(lib.csaw_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib.csaw_get_tuning(self._h, ctypes.byref(t)))
+        return t.bound16, t.bound32
+
+    def _run_sample(self, call, seed_offsets, seeds, fanouts, bias, rng_seed, instance_base, capacity, out,
+                    instance_ids, rng_seeds) -> SampleResult:
         seeds_dev = _dev_i32(seeds, self.device)
         a, keep, ni, L = self._sample_args(seed_offsets, seeds_dev, fanouts, bias, rng_seed,
                                            instance_base, instance_ids, rng_seeds)
@@ -269,7 +304,7 @@ class Graph:
         o = SampleOut()
         o.src, o.dst, o.edge_capacity = src.data_ptr(), dst.data_ptr(), int(capacity)
         o.offsets = offsets.data_ptr() if offsets is not None else None
-        _check(lib.csaw_sample(self._h, ctypes.byref(a), ctypes.byref(o), _stream(stream)))
+        _check(call(ctypes.byref(a), ctypes.byref(o)))
         ne = o.num_edges
         return SampleResult(src[:ne], dst[:ne], offsets, L, ni)
 

@@ -25,7 +25,15 @@ struct GraphDev {
     const uint32_t* degw;      // m or null (NEIGHBOR_DEGREE, materialised)
     const int32_t* ppos_ew;    // n: #positive weights per list | kWideList, or null
     const int32_t* ppos_deg;   // n
+    // chunk prefix tables of the lists longer than kWaveMaxD, one per weight
+    // array: chunk j of the list starting at edge b is row (b >> 9) + j of
+    // kChunkGroups inclusive group prefixes (built once per graph)
+    const uint64_t* gtab_ew;
+    const uint64_t* gtab_deg;
 };
+
+constexpr int kWaveMaxD = 512;   // longest weighted list of the wavefront kernels
+constexpr int kTabShift = 9;     // row of a list's first chunk: first edge >> kTabShift
 
 // Device-resident control block of one sampling call.
 struct SampleCtl {
@@ -33,7 +41,6 @@ struct SampleCtl {
     int64_t total[kMaxLayers];         // edges per layer
     int64_t out_base[kMaxLayers + 1];  // first edge of each layer
     unsigned long long nbig[kMaxLayers];    // long weighted lists per layer
-    unsigned long long nchunk[kMaxLayers];  // their 1024-weight chunks (may exceed chunk_cap)
     int32_t bad_seed;
     int32_t overflow;
     int32_t unsupported;
@@ -64,9 +71,6 @@ struct FrontierBuild {
     int32_t* fdeg;                   // per entry: list length
     int32_t* fpos;                   // per entry: positive biases | kWideList (list length if unbiased)
     int32_t* bigs;                   // long-list entries (frontier positions)
-    int64_t* big_cb;                 // first chunk of each long list
-    uint64_t* chunks;                // [chunk_cap] chunk records
-    int64_t chunk_cap;
     int64_t* offsets;                // [L*ni+1] or null
     SampleCtl* ctl;
     unsigned long long* status;      // [4 * nb] look-back words
@@ -89,10 +93,6 @@ struct SampleLayer {
     const int32_t* fdeg;             // per-entry list length
     const int32_t* fpos;             // per-entry positive biases | kWideList
     const int32_t* bigs;             // long weighted lists (frontier positions)
-    const int64_t* big_cb;           // first chunk of each long list
-    const uint64_t* chunks;          // chunk records: start | (len-1) << 40 | degree-bias bit 50
-    uint64_t* G;                     // [chunk_cap * 64] group prefixes within each chunk
-    int64_t chunk_cap;
     SampleCtl* ctl;
     int32_t* src;
     int32_t* dst;
@@ -100,7 +100,10 @@ struct SampleLayer {
     const uint32_t* visited;         // [ni * nwp]
     uint32_t* next;                  // [ni * nwp]
     int64_t nwp;                     // bitmap words per instance (multiple of 4)
+    int32_t group16, group32;        // sub-wave bucket bounds (<= 16, <= 32; 0 = off)
 };
+
+constexpr int32_t kDefaultBound16 = 16, kDefaultBound32 = 32;
 
 // Optional events that a launch fills with its kernel's own start and stop
 // times (hipExtLaunchKernel), for kernel timing without dispatch latency.
@@ -122,7 +125,11 @@ void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* s
 int64_t frontier_build_blocks(int64_t words);
 void launch_frontier_build(const FrontierBuild& fb, hipStream_t s, LaunchEvents ev = {});
 void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
-void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
+void launch_select_small(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
+// Chunk prefix table of every list longer than kWaveMaxD (GraphDev::gtab_*),
+// rows ((m >> kTabShift) + 1) * kChunkGroups uint64.
+int64_t chunk_table_rows(int64_t m);
+void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, hipStream_t s);
 void launch_select_big(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
 // Clears the visited bits of every frontier entry of the call's layers.
 struct ClearVisited {

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -103,11 +104,6 @@ struct Workspace {
     // the caller's stream with events (default priority)
     hipStream_t aux = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    // long-list scratch: chunk records and G rows (kChunkGroups u64 per chunk);
-    // chunk_hint is the largest per-layer chunk count seen by this workspace
-    uint64_t* chunkbuf = nullptr;
-    int64_t chunk_cap = 0;
-    int64_t chunk_hint = 0;
     // captured launch sequences of csaw_sample, keyed by every value they bake in
     hipStream_t capture = nullptr;
     std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
@@ -135,7 +131,6 @@ struct Workspace {
         if (aux) (void)hipStreamDestroy(aux);
         if (join) (void)hipEventDestroy(join);
         if (fork) (void)hipEventDestroy(fork);
-        if (chunkbuf) (void)hipFree(chunkbuf);
         if (arena) (void)hipFree(arena);
         if (bitmaps) (void)hipFree(bitmaps);
         if (pinned) (void)hipHostFree(pinned);
@@ -143,8 +138,6 @@ struct Workspace {
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-constexpr int64_t kInitialChunks = 4096;  // first long-list scratch of a workspace (2.1 MB)
 
 // CSAW_GRAPH=0 in the environment turns off launch-sequence replay.
 bool graphs_enabled() {
@@ -177,8 +170,11 @@ struct csaw_graph_s {
     uint32_t* degw = nullptr;
     int32_t* ppos_ew = nullptr;
     int32_t* ppos_deg = nullptr;
+    uint64_t* gtab_ew = nullptr;   // chunk prefix tables of the long lists
+    uint64_t* gtab_deg = nullptr;
     std::mutex mu;                       // lazy preparation + workspace pool
     std::vector<Workspace*> pool;
+    std::atomic<int32_t> bound16{kDefaultBound16}, bound32{kDefaultBound32};  // sub-wave buckets
 
     GraphDev dev() const {
         GraphDev g;
@@ -190,6 +186,8 @@ struct csaw_graph_s {
         g.degw = degw;
         g.ppos_ew = ppos_ew;
         g.ppos_deg = ppos_deg;
+        g.gtab_ew = gtab_ew;
+        g.gtab_deg = gtab_deg;
         return g;
     }
 };
@@ -263,17 +261,6 @@ csaw_status ensure_streams(Workspace* w) {
     return CSAW_OK;
 }
 
-csaw_status ensure_chunks(Workspace* w, int64_t chunks) {
-    if (w->chunk_cap >= chunks) return CSAW_OK;
-    w->drop_graphs();
-    if (w->chunkbuf) HIP_OR_FAIL(hipFree(w->chunkbuf));
-    w->chunkbuf = nullptr;
-    w->chunk_cap = 0;
-    HIP_OR_FAIL(hipMalloc((void**)&w->chunkbuf, (size_t)chunks * (1 + kChunkGroups) * sizeof(uint64_t)));
-    w->chunk_cap = chunks;
-    return CSAW_OK;
-}
-
 csaw_status ensure_bitmaps(Workspace* w, size_t words, hipStream_t s) {
     if (w->bitmap_words >= words) return CSAW_OK;
     w->drop_graphs();
@@ -289,21 +276,39 @@ csaw_status ensure_bitmaps(Workspace* w, size_t words, hipStream_t s) {
 }
 
 csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
+    // a weight array's positive counts and chunk prefix table; ppos_* is set
+    // last, once everything it stands for is on the device
     std::lock_guard<std::mutex> lk(g->mu);
     if (kind == kEdgeWeight && !g->ppos_ew) {
         if (!g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias needs edge weights");
-        HIP_OR_FAIL(hipMalloc((void**)&g->ppos_ew, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
-        launch_positive_counts(g->rowptr, g->ew, g->n, g->ppos_ew, s);
-        HIP_OR_FAIL(hipGetLastError());
-        HIP_OR_FAIL(hipStreamSynchronize(s));
+        int32_t* pp = nullptr;
+        if (!g->gtab_ew)
+            HIP_OR_FAIL(hipMalloc((void**)&g->gtab_ew, (size_t)chunk_table_rows(g->m) * kChunkGroups * sizeof(uint64_t)));
+        HIP_OR_FAIL(hipMalloc((void**)&pp, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
+        launch_positive_counts(g->rowptr, g->ew, g->n, pp, s);
+        launch_chunk_table(g->rowptr, g->ew, g->n, g->gtab_ew, s);
+        const hipError_t e = hipGetLastError() != hipSuccess ? hipErrorLaunchFailure : hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipFree(pp);
+            return fail(CSAW_ERR_DEVICE, "preparing EDGE_WEIGHT tables: %s", hipGetErrorString(e));
+        }
+        g->ppos_ew = pp;
     }
     if (kind == kNeighborDegree && !g->ppos_deg) {
-        HIP_OR_FAIL(hipMalloc((void**)&g->degw, std::max<int64_t>(g->m, 1) * sizeof(uint32_t)));
-        HIP_OR_FAIL(hipMalloc((void**)&g->ppos_deg, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
+        int32_t* pp = nullptr;
+        if (!g->degw) HIP_OR_FAIL(hipMalloc((void**)&g->degw, std::max<int64_t>(g->m, 1) * sizeof(uint32_t)));
+        if (!g->gtab_deg)
+            HIP_OR_FAIL(hipMalloc((void**)&g->gtab_deg, (size_t)chunk_table_rows(g->m) * kChunkGroups * sizeof(uint64_t)));
+        HIP_OR_FAIL(hipMalloc((void**)&pp, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
         launch_degree_weights(g->rowptr, g->col, g->m, g->degw, s);
-        launch_positive_counts(g->rowptr, g->degw, g->n, g->ppos_deg, s);
-        HIP_OR_FAIL(hipGetLastError());
-        HIP_OR_FAIL(hipStreamSynchronize(s));
+        launch_positive_counts(g->rowptr, g->degw, g->n, pp, s);
+        launch_chunk_table(g->rowptr, g->degw, g->n, g->gtab_deg, s);
+        const hipError_t e = hipGetLastError() != hipSuccess ? hipErrorLaunchFailure : hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipFree(pp);
+            return fail(CSAW_ERR_DEVICE, "preparing NEIGHBOR_DEGREE tables: %s", hipGetErrorString(e));
+        }
+        g->ppos_deg = pp;
     }
     return CSAW_OK;
 }
@@ -462,6 +467,8 @@ csaw_status csaw_graph_destroy(csaw_graph g) {
     if (g->degw) (void)hipFree(g->degw);
     if (g->ppos_ew) (void)hipFree(g->ppos_ew);
     if (g->ppos_deg) (void)hipFree(g->ppos_deg);
+    if (g->gtab_ew) (void)hipFree(g->gtab_ew);
+    if (g->gtab_deg) (void)hipFree(g->gtab_deg);
     delete g;
     return CSAW_OK;
 }
@@ -499,6 +506,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     if (P.uses_ew && (st = prepare_bias(g, kEdgeWeight, s)) != CSAW_OK) return st;
 
     const int32_t ni = P.ni, L = P.L;
+    const int32_t b16 = g->bound16.load(std::memory_order_relaxed), b32 = g->bound32.load(std::memory_order_relaxed);
     out->num_edges = 0;
     if (ni == 0) {
         if (out->offsets) HIP_OR_FAIL(hipMemsetAsync(out->offsets, 0, sizeof(int64_t), s));
@@ -542,7 +550,6 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     const size_t o_fdeg = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_fpos = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
     const size_t o_bigs = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
-    const size_t o_bigcb = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
     std::vector<size_t> o_fv(L + 1), o_fi(L + 1);
     for (int l = 0; l <= L; ++l) {
         o_fv[l] = cv.take<int32_t>((size_t)std::max<int64_t>(P.fcap[l], 1));
@@ -553,17 +560,9 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     if ((st = ensure_arena(ws, cv.off)) != CSAW_OK) return st;
     if ((st = ensure_bitmaps(ws, (size_t)words * 2, s)) != CSAW_OK) return st;
     if ((st = ensure_streams(ws)) != CSAW_OK) return st;
-    // long-list scratch: at most the bound below, at first a modest guess that
-    // grows to the largest per-layer chunk count this workspace has seen
-    const bool big_path = (P.uses_deg || P.uses_ew) && g->max_deg > kChunk;
-    if (big_path) {
-        const int64_t per = (g->max_deg + kChunk - 1) / kChunk;
-        int64_t bound = 1;
-        for (int l = 0; l < L; ++l)
-            bound = std::max(bound, std::min(sat_mul(P.fcap[l], per), sat_add(sat_mul(ni, g->m) / kChunk, P.fcap[l])));
-        const int64_t want = std::min(bound, std::max<int64_t>(ws->chunk_hint, kInitialChunks));
-        if ((st = ensure_chunks(ws, want)) != CSAW_OK) return st;
-    }
+    // weighted calls can have long-list entries (lists longer than kWaveMaxD,
+    // or with a total weight of 2^32 or more)
+    const bool big_path = P.uses_deg || P.uses_ew;
     const size_t o_hctl = align_up(tab_bytes, 64);
     if ((st = ensure_pinned(ws, o_hctl + sizeof(SampleCtl))) != CSAW_OK) return st;
 
@@ -612,9 +611,6 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         fb.fdeg = (int32_t*)(A + o_fdeg);
         fb.fpos = (int32_t*)(A + o_fpos);
         fb.bigs = (int32_t*)(A + o_bigs);
-        fb.big_cb = (int64_t*)(A + o_bigcb);
-        fb.chunks = ws->chunkbuf;
-        fb.chunk_cap = ws->chunk_cap;
         fb.offsets = out->offsets;
         fb.ctl = ctl;
         fb.status = d_status;
@@ -642,10 +638,6 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         p.fdeg = (const int32_t*)(A + o_fdeg);
         p.fpos = (const int32_t*)(A + o_fpos);
         p.bigs = (const int32_t*)(A + o_bigs);
-        p.big_cb = (const int64_t*)(A + o_bigcb);
-        p.chunks = ws->chunkbuf;
-        p.G = ws->chunkbuf + ws->chunk_cap;
-        p.chunk_cap = ws->chunk_cap;
         p.ctl = ctl;
         p.src = out->src;
         p.dst = out->dst;
@@ -653,6 +645,8 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         p.visited = visited;
         p.next = next;
         p.nwp = nwp;
+        p.group16 = b16;
+        p.group32 = b32;
         int computed_layers = 1;  // frontiers F_0 .. F_{computed_layers-1} exist
         for (int32_t l = 0; l < L; ++l) {
             p.layer = l;
@@ -666,15 +660,15 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             HIP_OR_FAIL(hipEventRecord(ws->fork, s));
             HIP_OR_FAIL(hipStreamWaitEvent(ws->aux, ws->fork, 0));
             if (big_path) {
-                {
-                    ProfScope ps("chunk_prefix", ws->aux, true);
-                    launch_chunk_prefix(p, (int)std::min<int64_t>((ws->chunk_cap + 3) / 4, 4096), ws->aux, ps.ev());
-                }
-                {
-                    ProfScope ps("select_big", ws->aux, true);
-                    launch_select_big(p, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), ws->aux,
-                                      ps.ev());
-                }
+                ProfScope ps("select_big", ws->aux, true);
+                launch_select_big(p, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), ws->aux,
+                                  ps.ev());
+            }
+            if (b16 > 0 || b32 > 0) {
+                ProfScope ps("select_small", s, true);
+                // one wavefront per run of 64 entries, up to the resident slots
+                const int grid = (int)std::min<int64_t>(std::max<int64_t>((cap + 255) / 256, 1), 2048);
+                launch_select_small(p, grid, s, ps.ev());
             }
             {
                 ProfScope ps("select_wave", s, true);
@@ -711,19 +705,14 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         return CSAW_OK;
     };
 
-    // A layer whose long lists need more chunk scratch than the workspace holds
-    // leaves those lists undrawn; the call is then repeated with room for the
-    // count the device reported (every draw is keyed by its counter, so the
-    // repeat returns exactly what a first run with enough room would have).
-    // Layers before the first short one are exact, and so is that layer's
-    // count, so each repeat settles at least one more layer.
-    for (int attempt = 0;; ++attempt) {
+    // the call's launch sequence, replayed from its captured graph when enabled
+    {
         if (graphs_enabled() && !g_prof.load(std::memory_order_relaxed)) {
             std::vector<int64_t> key = {ni, L, words, nwp, P.total_seeds, out->edge_capacity, (int64_t)(intptr_t)a->seeds,
                                         (int64_t)(intptr_t)out->src, (int64_t)(intptr_t)out->dst,
                                         (int64_t)(intptr_t)out->offsets, (int64_t)(intptr_t)ws->arena,
                                         (int64_t)(intptr_t)ws->bitmaps, (int64_t)(intptr_t)ws->pinned,
-                                        (int64_t)(intptr_t)ws->chunkbuf, ws->chunk_cap, (int64_t)big_path};
+                                        (int64_t)big_path, b16, b32};
             key.insert(key.end(), P.fcap.begin(), P.fcap.end());
             hipGraphExec_t exec = ws->find_graph(key);
             if (!exec) {
@@ -746,12 +735,6 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             if ((st = enqueue(s)) != CSAW_OK) return st;
         }
         HIP_OR_FAIL(hipStreamSynchronize(s));
-        int64_t chunk_max = 0;
-        for (int l = 0; l < L; ++l) chunk_max = std::max<int64_t>(chunk_max, (int64_t)h_ctl->nchunk[l]);
-        ws->chunk_hint = std::max(ws->chunk_hint, chunk_max);
-        if (!big_path || chunk_max <= ws->chunk_cap) break;
-        if (attempt >= L) return fail(CSAW_ERR_DEVICE, "long-list scratch still short after resizing");
-        if ((st = ensure_chunks(ws, chunk_max + chunk_max / 2)) != CSAW_OK) return st;
     }
     rel.clean = true;
     out->num_edges = L > 0 ? h_ctl->out_base[L] : 0;
@@ -763,6 +746,59 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     if (h_ctl->overflow || out->num_edges > out->edge_capacity)
         return fail(CSAW_ERR_OUT_OF_MEMORY, "edge_capacity %lld < %lld edges", (long long)out->edge_capacity,
                     (long long)out->num_edges);
+    return CSAW_OK;
+}
+
+csaw_status csaw_set_tuning(csaw_graph g, const csaw_tuning* t) {
+    t_err.clear();
+    if (!g || !t) return fail(CSAW_ERR_INVALID_ARG, "graph or tuning is NULL");
+    if (t->bound16 < 0 || t->bound16 > 16 || t->bound32 < 0 || t->bound32 > 32)
+        return fail(CSAW_ERR_INVALID_ARG, "bound16 must be in [0, 16] and bound32 in [0, 32]");
+    g->bound16.store(t->bound16);
+    g->bound32.store(t->bound32);
+    return CSAW_OK;
+}
+
+csaw_status csaw_get_tuning(csaw_graph g, csaw_tuning* t) {
+    t_err.clear();
+    if (!g || !t) return fail(CSAW_ERR_INVALID_ARG, "graph or tuning is NULL");
+    t->bound16 = g->bound16.load();
+    t->bound32 = g->bound32.load();
+    return CSAW_OK;
+}
+
+csaw_status csaw_autotune_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out* out, int32_t reps,
+                                 csaw_stream stream, csaw_tuning* chosen) {
+    t_err.clear();
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (reps < 1 || reps > 100) return fail(CSAW_ERR_INVALID_ARG, "reps must be in [1, 100]");
+    static const csaw_tuning kCandidates[] = {{0, 0}, {8, 0}, {16, 0}, {0, 32}, {8, 32}, {16, 32}};
+    csaw_tuning prev;
+    csaw_get_tuning(g, &prev);
+    csaw_tuning best = prev;
+    double best_t = 0;
+    for (const csaw_tuning& c : kCandidates) {
+        csaw_set_tuning(g, &c);
+        std::vector<double> ts;
+        for (int r = 0; r <= reps; ++r) {  // call 0 warms up (and captures this setting's graph)
+            const auto t0 = std::chrono::steady_clock::now();
+            const csaw_status st = csaw_sample(g, a, out, stream);  // returns after its stream drained
+            const auto t1 = std::chrono::steady_clock::now();
+            if (st != CSAW_OK) {
+                csaw_set_tuning(g, &prev);
+                return st;
+            }
+            if (r > 0) ts.push_back(std::chrono::duration<double>(t1 - t0).count());
+        }
+        std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
+        const double med = ts[ts.size() / 2];
+        if (&c == kCandidates || med < best_t) {
+            best_t = med;
+            best = c;
+        }
+    }
+    csaw_set_tuning(g, &best);
+    if (chosen) *chosen = best;
     return CSAW_OK;
 }
 

@@ -9,9 +9,11 @@
 //                    prefix, Philox draws, inverse transform search,
 //                    collision rounds, direct draw from the updated prefix;
 //                    writes the edges and marks new neighbors in the
-//                    instance's next bitmap. Weighted lists longer than
-//                    kWaveMaxD first get their 1024-weight chunk prefixes
-//                    (chunk pass), then one wavefront each (select_big).
+//                    instance's next bitmap. Small entries are served by
+//                    sub-wave groups (select_small); weighted lists longer
+//                    than kWaveMaxD, or with a total weight of 2^32 or more,
+//                    one wavefront each (select_big), searched through the
+//                    graph's chunk prefix tables.
 // Frontier entries are (vertex, instance) pairs sorted by (instance, vertex),
 // so edges come out in (layer, instance, source, slot) order without a sort.
 #include "device_common.h"
@@ -94,10 +96,11 @@ __global__ void k_mark_seeds(const int32_t* __restrict__ seeds, int64_t num_seed
 // Weighted lists that need draws are routed by length: up to kWaveMaxD
 // candidates with a total weight below 2^32 to the wavefront kernel (list and
 // 32-bit prefix resident in registers); the others to the long-list path,
-// which first reduces every 1024-weight chunk of every such list in one
-// bandwidth-bound pass (group prefixes within the chunk) and then draws with
-// one wavefront per list from a coarse table built out of them.
-constexpr int kWaveMaxD = 512;
+// which draws with one wavefront per list from a coarse table built out of
+// the graph's chunk prefix table (lists longer than kWaveMaxD; the table is
+// computed once per graph and weight array, since it depends on the list
+// alone, not on the instance) or, for shorter lists with a wide total, out of
+// the list's one chunk reduced on the spot.
 
 enum { kRouteWave = 0, kRouteBig = 1 };
 
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     // keep their counts in registers for the write pass
     int32_t cc[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0}, cp[4] = {0, 0, 0, 0};
     int64_t cbeg[4] = {0, 0, 0, 0}, cd[4] = {0, 0, 0, 0};
-    int64_t cnt4[4] = {0, 0, 0, 0};  // entries, edges, long lists, chunks
+    int64_t cnt4[4] = {0, 0, 0, 0};  // entries, edges, long lists, (unused)
     {
         bool first = true;
         int64_t inst_k = -1;
@@ -278,10 +281,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                         if (bv[t] >= 0) {
                             c = entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, pinfo, fb.ctl);
                             cnt4[1] += c;
-                            if (route == kRouteBig) {
-                                ++cnt4[2];
-                                cnt4[3] += chunks_of(d);
-                            }
+                            if (route == kRouteBig) ++cnt4[2];
                         }
                         if (first) {
                             cc[t] = c;
@@ -300,12 +300,11 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     int64_t ex4[4] = {cnt4[0], cnt4[1], cnt4[2], cnt4[3]};
     block_excl_scan4(ex4, tot4);
     const int64_t ex_e = ex4[0], ex_g = ex4[1];
-    int64_t ex_big = ex4[2], ex_chk = ex4[3];
-    const int64_t tot_e = tot4[0], tot_g = tot4[1], tot_big = tot4[2], tot_chk = tot4[3];
-    __shared__ int64_t s_big_base, s_chk_base;
-    if (tid == kWave) {  // wave 1: one reservation per block for its long lists and their chunks
+    int64_t ex_big = ex4[2];
+    const int64_t tot_e = tot4[0], tot_g = tot4[1], tot_big = tot4[2];
+    __shared__ int64_t s_big_base;
+    if (tid == kWave) {  // wave 1: one reservation per block for its long lists
         s_big_base = tot_big ? (int64_t)atomicAdd(&fb.ctl->nbig[fb.layer], (unsigned long long)tot_big) : 0;
-        s_chk_base = tot_chk ? (int64_t)atomicAdd(&fb.ctl->nchunk[fb.layer], (unsigned long long)tot_chk) : 0;
     }
     if (tid < kWave) {  // wave 0: publish, then look back 64 predecessors per step
         const int lane = tid;
@@ -422,21 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                     fb.fbeg[pos] = beg;
                     fb.fdeg[pos] = (int32_t)d;
                     fb.fpos[pos] = pinfo;
-                    if (route == kRouteBig) {
-                        const int64_t bi = s_big_base + ex_big++;
-                        const int64_t cb = s_chk_base + ex_chk;
-                        const int64_t nc = chunks_of(d);
-                        ex_chk += nc;
-                        fb.bigs[bi] = (int32_t)pos;
-                        fb.big_cb[bi] = cb;
-                        // chunk records beyond the scratch capacity are not written; the
-                        // host sees nchunk > chunk_cap and repeats the call with more room
-                        const uint64_t kbit = kind == kNeighborDegree ? 1ull << 50 : 0ull;
-                        for (int64_t j = 0; j < nc && cb + j < fb.chunk_cap; ++j) {
-                            const int64_t len = d - j * kChunk < kChunk ? d - j * kChunk : kChunk;
-                            fb.chunks[cb + j] = (uint64_t)(beg + j * kChunk) | ((uint64_t)(len - 1) << 40) | kbit;
-                        }
-                    }
+                    if (route == kRouteBig) fb.bigs[s_big_base + ex_big++] = (int32_t)pos;
                     ++pos;
                     eoff += c;
                 }
@@ -786,6 +771,50 @@ __device__ __forceinline__ void load_run(const SampleLayer& p, int64_t e, bool v
     }
 }
 
+// A run kept in LDS (one array per field), so that its fields need no
+// registers while the wavefront works through the run.
+struct RunLds {
+    int32_t c[kWave], v[kWave], inst[kWave], pinfo[kWave], k[kWave], kind[kWave], do_claim[kWave], c0[kWave],
+        d[kWave];
+    int64_t o[kWave], beg[kWave];
+    uint64_t key[kWave];
+};
+
+__device__ __forceinline__ void store_run(RunLds& L, const EntryRun& R, int lane) {
+    L.c[lane] = R.c;
+    L.v[lane] = R.v;
+    L.inst[lane] = R.inst;
+    L.pinfo[lane] = R.pinfo;
+    L.k[lane] = R.k;
+    L.kind[lane] = R.kind;
+    L.do_claim[lane] = R.do_claim;
+    L.c0[lane] = R.c0;
+    L.d[lane] = R.d;
+    L.o[lane] = R.o;
+    L.beg[lane] = R.beg;
+    L.key[lane] = R.key;
+}
+
+// The fields of run entry j, wave-uniform.
+__device__ __forceinline__ EntryInfo lds_entry(const RunLds& L, int j) {
+    EntryInfo E;
+    E.c = uniform_i32(L.c[j]);
+    E.v = uniform_i32(L.v[j]);
+    E.inst = uniform_i32(L.inst[j]);
+    E.o = uniform_i64(L.o[j]);
+    E.beg = uniform_i64(L.beg[j]);
+    E.d = uniform_i32(L.d[j]);
+    const int32_t pinfo = uniform_i32(L.pinfo[j]);
+    E.P = pinfo & ~kWideList;
+    E.wide = (pinfo & kWideList) != 0;
+    E.k = uniform_i32(L.k[j]);
+    E.kind = uniform_i32(L.kind[j]);
+    E.do_claim = uniform_i32(L.do_claim[j]) != 0;
+    E.key = (uint64_t)uniform_i64((int64_t)L.key[j]);
+    E.c0 = (uint32_t)uniform_i32(L.c0[j]);
+    return E;
+}
+
 // The fields of run entry j, wave-uniform.
 __device__ __forceinline__ EntryInfo run_entry(const EntryRun& R, int j) {
     EntryInfo E;
@@ -895,9 +924,196 @@ __device__ void select_entry(const SampleLayer& p, const EntryInfo& E) {
     emit_slots(p, E, pos);
 }
 
+// ------------------------------------------------------- sub-wave groups
+// Entries whose work fits G lanes -- a take-all list of at most G
+// candidates, an unbiased draw of at most G slots, a weighted draw from at
+// most G candidates -- are served 64/G side by side, G lanes each: slot j of
+// an entry is lane j of its group, a weighted candidate i is lane i. The
+// rounds take each group's slots in slot order exactly as the full-wave path
+// does (one slot index t at a time for all groups), so results do not depend
+// on the grouping. An entry with slots still open after kRounds is returned
+// to the full-wave path, which repeats its rounds and ends with direct draws.
+// The bucket bounds (largest size served by 16- and 32-lane groups) are call
+// parameters, so a tuner can pick them per workload.
+
+// The value of x at lane (group base + t), on every lane of the group.
+template <int G>
+__device__ __forceinline__ uint32_t group_bcast_u32(uint32_t x, int t) {
+    const int lane = lane_id();
+    uint32_t r = readlane_u32(x, t);
+#pragma unroll
+    for (int q = 1; q < kWave / G; ++q) {
+        const uint32_t y = readlane_u32(x, q * G + t);
+        r = lane >= q * G ? y : r;
+    }
+    return r;
+}
+
+// Inclusive scan inside each group of G lanes (every lane active).
+template <int G>
+__device__ __forceinline__ uint32_t group_incl_scan_u32(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr2, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr4, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr8, 0xf, 0xf, false);
+    if (G >= 32) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast15, 0xa, 0xf, false);
+    return x;
+}
+
+// Does run entry R (this lane's) fit groups of G lanes with bucket bound b?
+__device__ __forceinline__ bool group_fits(const EntryRun& R, int64_t capacity, int32_t b) {
+    if (R.c == 0 || R.o + R.c > capacity) return false;
+    const int32_t P = R.pinfo & ~kWideList;
+    if (route_of(R.kind, R.k, P, R.d, (R.pinfo & kWideList) != 0) != kRouteWave) return false;
+    const bool take = R.k < 0 || R.k >= P;
+    return (take || R.kind != kUniform) ? R.d <= b : R.k <= b;
+}
+
+template <int G>
+__device__ uint64_t select_groups(const SampleLayer& p, const RunLds& R, uint64_t elig) {
+    constexpr uint64_t kLow = (1ull << G) - 1;
+    const int lane = lane_id();
+    const int gl = lane & (G - 1);
+    const int gbase = lane & ~(G - 1);
+    const uint64_t gmask = kLow << gbase;
+    uint64_t back = 0;
+    for (uint64_t rem = elig; rem;) {
+        // the next 64/G eligible entries, one per group
+        int srcl = -1;
+#pragma unroll
+        for (int q = 0; q < kWave / G; ++q) {
+            const int s = rem ? __ffsll((unsigned long long)rem) - 1 : -1;
+            rem = rem ? rem & (rem - 1) : 0ull;
+            srcl = gbase == q * G ? s : srcl;
+        }
+        const bool valid = srcl >= 0;
+        const int sl = valid ? srcl : 0;
+        const int32_t v = R.v[sl];
+        const int32_t inst = R.inst[sl];
+        const int64_t o = R.o[sl];
+        const int64_t beg = R.beg[sl];
+        const int32_t d = R.d[sl];
+        const int32_t P = R.pinfo[sl] & ~kWideList;
+        const int32_t k = R.k[sl];
+        const int32_t kind = R.kind[sl];
+        const bool do_claim = R.do_claim[sl] != 0;
+        const uint64_t ekey = R.key[sl];
+        const uint32_t c0 = (uint32_t)R.c0[sl];
+        const bool take = k < 0 || k >= P;
+        const bool weighted = kind != kUniform;
+        const uint32_t* w = (kind == kEdgeWeight ? p.g.ew : p.g.degw) + beg;  // read only if weighted
+
+        // weights of a weighted group, one candidate per lane
+        const bool wlist = valid && weighted && !(take && P == d);
+        uint32_t x = 0;
+        if (wlist && gl < d) x = w[gl];
+
+        // take-all groups: every positive candidate, list order
+        int32_t pos = -1, slot = gl;
+        const uint64_t posm = ballot(valid && take && wlist && x > 0);
+        if (valid && take && gl < d) {
+            if (!wlist) pos = gl;
+            else if (x > 0) {
+                pos = gl;
+                slot = __popcll(posm & gmask & lanemask_lt());
+            }
+        }
+
+        // draw groups: rounds in slot order per group
+        const bool drw = valid && !take;
+        const uint32_t S = group_incl_scan_u32<G>(drw ? x : 0u);
+        const uint32_t Wg = group_bcast_u32<G>(S, G - 1);
+        const uint64_t W = weighted ? (uint64_t)Wg : (uint64_t)(uint32_t)d;
+        const Key key{(uint32_t)ekey, (uint32_t)(ekey >> 32)};
+        uint64_t open = ballot(drw && gl < k);
+        int32_t hid = -1;  // candidate this lane marks held (uniform: its slot's pick; weighted: itself)
+        for (int a = 0; a < kRounds && open; ++a) {
+            uint32_t r = 0;
+            if ((open >> lane) & 1ull) r = (uint32_t)draw(key, c0, (uint32_t)p.layer, (uint32_t)v, (uint32_t)gl | ((uint32_t)a << 16), W);
+            uint64_t tm = 0;
+#pragma unroll
+            for (int q = 0; q < kWave / G; ++q) tm |= (open >> (q * G)) & kLow;
+            for (; tm; tm &= tm - 1) {
+                const int t = __ffsll((unsigned long long)tm) - 1;
+                const uint32_t rt = group_bcast_u32<G>(r, t);
+                const int32_t mt = weighted ? __popcll(ballot(S <= rt) & gmask) : (int32_t)rt;
+                const bool free = (ballot(hid >= 0 && hid == mt) & gmask) == 0;
+                const bool acc = free && ((open >> (gbase + t)) & 1ull);
+                if (acc) {
+                    if (gl == t) pos = mt;
+                    if (weighted ? gl == mt : gl == t) hid = mt;
+                }
+                open &= ~ballot(acc && gl == t);
+            }
+        }
+        // groups with open slots go back to the full-wave path, unwritten
+        const bool unfinished = (open & gmask) != 0;
+        for (uint64_t ub = ballot(unfinished && gl == 0); ub; ub &= ub - 1)
+            back |= 1ull << readlane_i32(sl, __ffsll((unsigned long long)ub) - 1);
+        if (pos >= 0 && !unfinished) {
+            const int32_t nb = p.g.col[beg + pos];
+            p.src[o + slot] = v;
+            p.dst[o + slot] = nb;
+            claim(do_claim, p.visited + (int64_t)inst * p.nwp, p.next + (int64_t)inst * p.nwp, nb);
+        }
+    }
+    return back;
+}
+
+// A sub-wave entry whose slots were still open after the rounds, redone by
+// the whole wavefront: an unbiased draw of at most 32 slots or a weighted
+// draw from at most 32 candidates (the draw branch of select_entry).
+__device__ void select_entry_small_draw(const SampleLayer& p, const EntryInfo& E) {
+    const Key key{(uint32_t)E.key, (uint32_t)(E.key >> 32)};
+    const uint32_t c1 = (uint32_t)p.layer;
+    const uint32_t c2 = (uint32_t)E.v;
+    int64_t pos;
+    if (E.kind == kUniform) {
+        const auto pick = [](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+            m = (int64_t)r;
+            Sm = r;
+            bm = 1;
+        };
+        pos = draw_slots(key, E.c0, c1, c2, E.k, (uint64_t)E.d, pick, pick);
+    } else {
+        pos = draw_resident<1>((E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg, E.d, key, E.c0, c1, c2, E.k);
+    }
+    emit_slots(p, E, pos);
+}
+
+// Sub-wave entries of the layer: each wavefront takes runs of 64 frontier
+// entries (grid-stride), keeps the run in LDS and serves its small entries
+// in groups of 16 and 32 lanes; the other entries are left to k_select.
+__global__ void __launch_bounds__(kBlock, 6) k_select_small(SampleLayer p) {
+    __shared__ RunLds runs[kWavesPerBlock];
+    const int wid = uniform_i32(threadIdx.x / kWave);
+    RunLds& L = runs[wid];
+    const int lane = lane_id();
+    const int64_t fcount = p.ctl->fcount[p.layer];
+    const int64_t out_base = p.ctl->out_base[p.layer];
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t e0 = (blockIdx.x * (int64_t)kWavesPerBlock + wid) * kWave; e0 < fcount; e0 += waves * kWave) {
+        const int n = (int)(fcount - e0 < kWave ? fcount - e0 : kWave);
+        uint64_t e16, e32;
+        {
+            EntryRun R;
+            load_run(p, e0 + lane, lane < n, out_base, R);
+            e16 = p.group16 > 0 ? ballot(lane < n && group_fits(R, p.capacity, p.group16)) : 0ull;
+            e32 = p.group32 > 0 ? ballot(lane < n && group_fits(R, p.capacity, p.group32)) & ~e16 : 0ull;
+            store_run(L, R, lane);
+        }
+        wave_lds_sync();
+        uint64_t back = 0;
+        if (e16) back |= select_groups<16>(p, L, e16);
+        if (e32) back |= select_groups<32>(p, L, e32);
+        for (; back; back &= back - 1) select_entry_small_draw(p, lds_entry(L, __ffsll((unsigned long long)back) - 1));
+        wave_lds_sync();  // the next run overwrites L
+    }
+}
+
 // Each wavefront takes a contiguous share of the frontier (a short run when
 // the grid has more wavefronts than resident slots), loaded 64 entries at a
-// time.
+// time; entries of the sub-wave buckets are skipped (k_select_small).
 __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
     const int wid = uniform_i32(threadIdx.x / kWave);
     const int lane = lane_id();
@@ -908,31 +1124,41 @@ __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
     const int64_t per = (fcount + waves - 1) / waves;
     const int64_t lo = wave * per < fcount ? wave * per : fcount;
     const int64_t hi = lo + per < fcount ? lo + per : fcount;
+    const int32_t bound = p.group32 > p.group16 ? p.group32 : p.group16;
     for (int64_t e0 = lo; e0 < hi; e0 += kWave) {
         const int n = (int)(hi - e0 < kWave ? hi - e0 : kWave);
         EntryRun R;
         load_run(p, e0 + lane, lane < n, out_base, R);
-        for (int j = 0; j < n; ++j) select_entry(p, run_entry(R, j));
+        uint64_t todo = ballot(lane < n && R.c != 0 && !(bound > 0 && group_fits(R, p.capacity, bound)));
+        for (; todo; todo &= todo - 1) select_entry(p, run_entry(R, __ffsll((unsigned long long)todo) - 1));
     }
 }
 
 // ------------------------------------------------------ long-list path
-// Pass 1: one wavefront per 1024-weight chunk of every long list in the
-// layer: coalesced loads, LDS transpose, one 16-weight group per lane, and a
-// 64-lane scan gives G[c][i] = total weight of groups 0..i of chunk c.
-__global__ void __launch_bounds__(kBlock) k_chunk_prefix(SampleLayer p) {
+// Chunk prefix table, once per graph and weight array: one wavefront per
+// list longer than kWaveMaxD, chunk by chunk (coalesced loads, LDS
+// transpose, one 16-weight group per lane, a 64-lane scan): row
+// (b >> kTabShift) + j holds the inclusive group prefixes of chunk j of the
+// list starting at edge b. A list of d > 512 weights spans at least
+// floor(d / 512) >= ceil(d / 1024) rows of 512 edges, so the rows of
+// different lists never meet, and every row is below (m >> kTabShift).
+__global__ void __launch_bounds__(kBlock) k_chunk_table(const int64_t* __restrict__ rowptr,
+                                                        const uint32_t* __restrict__ w, int64_t n,
+                                                        uint64_t* __restrict__ tab) {
     __shared__ uint32_t tiles[kWavesPerBlock][kTilePad];
     const int wid = uniform_i32(threadIdx.x / kWave);
     const int lane = lane_id();
-    const int64_t need = (int64_t)p.ctl->nchunk[p.layer];
-    const int64_t nch = need < p.chunk_cap ? need : p.chunk_cap;
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t c = blockIdx.x * (int64_t)kWavesPerBlock + wid; c < nch; c += waves) {
-        const uint64_t rec = (uint64_t)uniform_i64((int64_t)p.chunks[c]);
-        const uint32_t* w = (((rec >> 50) & 1ull) ? p.g.degw : p.g.ew) + (int64_t)(rec & ((1ull << 40) - 1));
-        const int64_t len = (int64_t)((rec >> 40) & 1023ull) + 1;
-        const uint64_t s = tile_group_sums(w, 0, len, tiles[wid]);
-        p.G[c * kChunkGroups + lane] = wave_incl_scan_u64(s);
+    for (int64_t v = blockIdx.x * (int64_t)kWavesPerBlock + wid; v < n; v += waves) {
+        const int64_t b = uniform_i64(rowptr[v]);
+        const int64_t d = uniform_i64(rowptr[v + 1]) - b;
+        if (d <= kWaveMaxD) continue;
+        uint64_t* row = tab + (b >> kTabShift) * kChunkGroups;
+        for (int64_t j = 0; j < chunks_of(d); ++j) {
+            const int64_t len = d - j * kChunk < kChunk ? d - j * kChunk : kChunk;
+            const uint64_t s = tile_group_sums(w + b + j * kChunk, 0, len, tiles[wid]);
+            row[j * kChunkGroups + lane] = wave_incl_scan_u64(s);
+        }
     }
 }
 
@@ -986,14 +1212,16 @@ __device__ __forceinline__ void unit_search(const UnitPool& pl, uint64_t r, int6
     fine_scan_global(pl.w, i, end, acc + before, r, m, Sm, bm);
 }
 
-// Pass 2: one wavefront per long list. Lists of up to kGroupTabD weights get
-// a group-level table (C[t] = weight before group t, from the chunk totals
-// and the G rows), searched like the wavefront path with the group's weights
+// One wavefront per long list. Lists of up to kGroupTabD weights get a
+// group-level table (C[t] = weight before group t, from the chunk totals and
+// the G rows), searched like the wavefront path with the group's weights
 // read from global memory; longer lists get a unit-level table (UnitPool).
+// The G rows come from the graph's chunk prefix table, or for a list of at
+// most kWaveMaxD weights (wide total) from its one chunk reduced here.
 constexpr int kBigTab = 512;
 constexpr int64_t kGroupTabD = (int64_t)kBigTab * 16;
 
-__device__ void select_big_entry(const SampleLayer& p, const EntryInfo& E, int64_t cb, uint64_t* tab) {
+__device__ void select_big_entry(const SampleLayer& p, const EntryInfo& E, uint64_t* tab) {
     const int lane = lane_id();
     if (E.c == 0) return;
     if (E.o + E.c > p.capacity) {
@@ -1002,18 +1230,30 @@ __device__ void select_big_entry(const SampleLayer& p, const EntryInfo& E, int64
     }
     const int64_t d = E.d;
     const int64_t nch = chunks_of(d);
-    if (cb + nch > p.chunk_cap) return;  // no scratch room this time; the call is repeated
     const uint32_t* w = (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg;
-    const uint64_t* G = p.G + cb * kChunkGroups;
+    const uint64_t* G = (E.kind == kEdgeWeight ? p.g.gtab_ew : p.g.gtab_deg) + (E.beg >> kTabShift) * kChunkGroups;
+    const bool onchip = d <= kWaveMaxD;  // one chunk, not in the table
     const Key key{(uint32_t)E.key, (uint32_t)(E.key >> 32)};
     const uint32_t c0 = E.c0, c1 = (uint32_t)p.layer, c2 = (uint32_t)E.v;
     int64_t pos;
     if (d <= kGroupTabD) {
         const int64_t nc = (d + 15) / 16;
         uint64_t rows[kGroupTabD / kChunk];
+        uint64_t tj;
+        if (onchip) {  // (rare) group sums straight from the list, lane = group
+            const int64_t i0 = (int64_t)lane * 16;
+            uint64_t s = 0;
+#pragma unroll 4
+            for (int q = 0; q < 16; ++q) s += i0 + q < d ? w[i0 + q] : 0u;
+            rows[0] = wave_incl_scan_u64(s);
 #pragma unroll
-        for (int j = 0; j < kGroupTabD / kChunk; ++j) rows[j] = j < nch ? G[j * kChunkGroups + lane] : 0ull;
-        const uint64_t tj = lane < nch ? G[lane * kChunkGroups + kChunkGroups - 1] : 0ull;
+            for (int j = 1; j < kGroupTabD / kChunk; ++j) rows[j] = 0ull;
+            tj = lane == 0 ? readlane_u64(rows[0], kWave - 1) : 0ull;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kGroupTabD / kChunk; ++j) rows[j] = j < nch ? G[j * kChunkGroups + lane] : 0ull;
+            tj = lane < nch ? G[lane * kChunkGroups + kChunkGroups - 1] : 0ull;
+        }
         const uint64_t cincl = wave_incl_scan_u64(tj);
         const uint64_t cex = cincl - tj;
 #pragma unroll
@@ -1074,10 +1314,9 @@ __global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
         const int n = (int)(hi - h0 < kWave ? hi - h0 : kWave);
         const bool valid = lane < n;
         const int64_t pos = valid ? p.bigs[h0 + lane] : 0;
-        const int64_t cb = valid ? p.big_cb[h0 + lane] : 0;
         EntryRun R;
         load_run(p, pos, valid, out_base, R);
-        for (int j = 0; j < n; ++j) select_big_entry(p, run_entry(R, j), readlane_i64(cb, j), tabs[wid]);
+        for (int j = 0; j < n; ++j) select_big_entry(p, run_entry(R, j), tabs[wid]);
     }
 }
 
@@ -1158,8 +1397,16 @@ void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents e
     launch_kernel(k_select, dim3(grid), dim3(kBlock), s, ev, p);
 }
 
-void launch_chunk_prefix(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
-    launch_kernel(k_chunk_prefix, dim3(grid), dim3(kBlock), s, ev, p);
+void launch_select_small(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
+    launch_kernel(k_select_small, dim3(grid), dim3(kBlock), s, ev, p);
+}
+
+int64_t chunk_table_rows(int64_t m) { return (m >> kTabShift) + 1; }
+
+void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_chunk_table, dim3(grid_for(n, kWavesPerBlock, 65536)), dim3(kBlock), 0, s, rowptr, w, n,
+                       tab);
 }
 
 void launch_select_big(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {

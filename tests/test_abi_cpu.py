@@ -73,3 +73,10 @@ def test_no_cpu_fallback_in_binding():
     for f in os.listdir(os.path.join(ROOT, "paper_2009_09103_amd")):
         if f.endswith(".py"):
             assert "import oracle" not in open(os.path.join(ROOT, "paper_2009_09103_amd", f)).read()
+
+
+def test_tuning_calls_validate_on_host(csaw):
+    t = csaw.Tuning(16, 32)
+    assert csaw.lib.csaw_set_tuning(None, ctypes.byref(t)) == 1
+    assert csaw.lib.csaw_get_tuning(None, ctypes.byref(t)) == 1
+    assert csaw.lib.csaw_autotune_sample(None, None, None, 3, None, None) == 1

@@ -135,9 +135,8 @@ def test_giant_hub(csaw):
 
 def test_longest_lists_and_scratch_growth(csaw):
     """Lists of 1.2M weights (more chunks than the coarse table holds, so it
-    covers four chunks per entry) in 8 instances: 9,376 chunks, more than a
-    fresh workspace's long-list scratch, so the first call is repeated with
-    more room; a second call must return the same edges without that."""
+    covers four chunks per entry) in 8 instances, read from the graph's chunk
+    prefix table; a second call must return the same edges."""
     d = 1_200_000
     rp = np.array([0, d] + [d] * d, dtype=np.int64)
     col = np.arange(1, d + 1, dtype=np.int32)
@@ -347,3 +346,102 @@ def test_replay_after_staging_growth(csaw):
     ref = oracle.sample(rp, col, None, offs, seeds, [10, 5], bias_kind=oracle.UNIFORM, rng_seed=2)
     assert_same(a, ref)
     assert_same(b, ref)
+
+
+TUNINGS = [(0, 0), (16, 0), (0, 32), (8, 32), (16, 32), (1, 1), (4, 20)]
+
+
+def small_list_graph(n, degrees, seed):
+    rng = inputs.rng(seed)
+    edges = set()
+    for u in range(n):
+        d = int(rng.choice(degrees))
+        for x in rng.choice(n, size=d, replace=False):
+            if x != u:
+                edges.add((u, int(x)))
+    return inputs.csr_from_edges(n, edges)
+
+
+def test_subwave_buckets_every_setting(csaw):
+    """Sub-wave groups of 16 and 32 lanes against the oracle under every
+    bucket setting: unbiased, edge-weight (with zero weights) and out-degree
+    bias, take-all lists, draws of up to 32 slots, lists one longer than the
+    fanout (slots still open after the rounds go back to the full wavefront)."""
+    rp, col = small_list_graph(5000, [0, 1, 3, 9, 15, 16, 17, 20, 31, 32, 33, 40, 70], 31)
+    rng = inputs.rng(32)
+    ew = rng.integers(0, 4, size=len(col)).astype(np.uint32) ** 5
+    offs, seeds = inputs.batched_instances(rp, col, 40, 33)[:2]
+    g = csaw.Graph(rp, col, ew)
+    bias = [0, 1, 2] * 14
+    try:
+        for t in TUNINGS:
+            g.set_tuning(*t)
+            assert g.get_tuning() == t
+            say("tuning %s" % (t,))
+            for fo in ([15, 5], [16, 31], [32, 3, 2], [8, -1]):
+                run_both(csaw, g, rp, col, ew, offs, seeds, fo, bias[:40], 7 + fo[0])
+    finally:
+        g.set_tuning(16, 32)
+
+
+def test_subwave_fallback_after_rounds(csaw):
+    """Unbiased draws of k from k + 1 or k + 2 candidates leave slots open
+    after the rounds in many groups; those entries are redone by the full
+    wavefront and must match the oracle exactly."""
+    for k in (15, 16, 31, 32):
+        rp, col = small_list_graph(3000, [k + 1, k + 2], 40 + k)
+        offs, seeds = inputs.single_instance_seeds(rp, col, 1500, 41)
+        g = csaw.Graph(rp, col)
+        run_both(csaw, g, rp, col, None, offs, seeds, [k, k], csaw.UNIFORM, 3 + k)
+        g.set_tuning(0, 0)
+        run_both(csaw, g, rp, col, None, offs, seeds, [k, k], csaw.UNIFORM, 3 + k)
+
+
+def test_autotune_keeps_results(csaw):
+    """The autotuner returns the call's exact result and leaves a valid
+    setting on the graph."""
+    rp, col = inputs.rmat_csr(14, 16 << 14, 5)
+    offs, seeds, fan, bias = inputs.batched_instances(rp, col, 64, 9)
+    g = csaw.Graph(rp, col)
+    say("autotune on R-MAT 14, 64 instances")
+    res, t = g.autotune_sample(offs, seeds, fan, bias, rng_seed=4, reps=2)
+    assert t in [(0, 0), (8, 0), (16, 0), (0, 32), (8, 32), (16, 32)] and g.get_tuning() == t
+    ref = oracle.sample(rp, col, None, offs, seeds, fan, bias_kinds=bias, rng_seed=4)
+    assert_same(res, ref)
+    with pytest.raises(csaw.CsawError):
+        g.set_tuning(17, 0)
+    with pytest.raises(csaw.CsawError):
+        g.set_tuning(0, 33)
+    assert g.get_tuning() == t
+
+
+def test_long_lists_without_hubs(csaw):
+    """The long-list path when the longest list is between 513 and 1024
+    weights (one chunk), and for short lists whose total weight is 2^32 or
+    more, with both weight arrays (edge weights and out-degrees) in one call."""
+    rng = inputs.rng(23)
+    degs = [3, 20, 200, 511, 512, 513, 600, 1000, 1024]
+    hubs = len(degs)
+    n = hubs + 1200
+    edges = []
+    for h, d in enumerate(degs):
+        for x in rng.choice(np.arange(hubs, n), size=d, replace=False):
+            edges.append((h, int(x)))
+    for u in range(hubs, n):
+        for x in rng.choice(n, size=int(rng.integers(0, 6)), replace=False):
+            if x != u:
+                edges.append((u, int(x)))
+    rp, col = inputs.csr_from_edges(n, sorted(set(edges)))
+    assert 512 < np.diff(rp).max() <= 1024
+    ew = rng.integers(0, 50, size=len(col)).astype(np.uint32)
+    for h in (1, 2):   # lists of 20 and 200 with a total weight above 2^32
+        a, b = rp[h], rp[h + 1]
+        ew[a:b] = rng.integers(1 << 28, 1 << 32, size=b - a, dtype=np.uint64).astype(np.uint32)
+        assert int(ew[a:b].astype(np.uint64).sum()) >= 1 << 32
+    g = csaw.Graph(rp, col, ew)
+    ni = 3 * hubs
+    offs = np.arange(ni + 1, dtype=np.int64)
+    seeds = np.tile(np.arange(hubs, dtype=np.int32), 3)
+    bias = [1, 2] * (ni // 2) + [1] * (ni % 2)
+    for k in (2, 10, 64):
+        run_both(csaw, g, rp, col, ew, offs, seeds, [k, 3], bias, 70 + k)
