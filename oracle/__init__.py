@@ -76,7 +76,7 @@ def lib():
             L.orc_its.restype = i64
             L.orc_skip_map.argtypes = [vp, vp, vp, i32, u64]
             L.orc_skip_map.restype = u64
-            L.orc_select.argtypes = [vp, i64, i64, i32, u64, u32, u32, u32, vp, vp]
+            L.orc_select.argtypes = [vp, i64, i64, i32, u64, u32, u32, u32, vp, vp, vp]
             L.orc_select.restype = i32
             L.orc_sample.argtypes = [i64, vp, vp, vp, i32, vp, vp, u64, vp, i32, vp, i32, vp, i32,
                                      u64, i32, i64, vp, vp, vp, vp, vp, i32]
@@ -140,7 +140,7 @@ def select(b, k: int, rng_seed: int, c0: int, c1: int, c2: int, rounds: int = DE
     d = len(b)
     out = np.zeros(max(d, 1), dtype=np.int64)
     nfb = ctypes.c_int32(0)
-    c = lib().orc_select(_p(b), d, k, rounds, rng_seed, c0, c1, c2, _p(out), ctypes.byref(nfb))
+    c = lib().orc_select(_p(b), d, k, rounds, rng_seed, c0, c1, c2, _p(out), ctypes.byref(nfb), None)
     res = out[:c].copy()
     return (res, nfb.value) if with_fallback else res
 
@@ -149,7 +149,7 @@ class SampleResult:
     def __init__(self, src, dst, offsets, num_layers, num_instances, stats):
         self.src, self.dst, self.offsets = src, dst, offsets
         self.num_layers, self.num_instances = num_layers, num_instances
-        self.alg_bytes, self.expanded, self.fallbacks, self.sum_degree = stats
+        self.alg_bytes, self.expanded, self.fallbacks, self.sum_degree, self.draws = stats
 
     def segment(self, layer: int, instance: int):
         o = self.offsets
@@ -183,7 +183,7 @@ def sample(rowptr, col, ew, seed_offsets, seeds, fanouts, bias_kind=UNIFORM, rng
     ids = None if instance_ids is None else np.ascontiguousarray(instance_ids, dtype=np.uint64)
     bk = None if bias_kinds is None else np.ascontiguousarray(bias_kinds, dtype=np.int32)
     offsets = np.zeros(L * ni + 1, dtype=np.int64)
-    stats = np.zeros(4, dtype=np.float64)
+    stats = np.zeros(5, dtype=np.float64)
     ne = ctypes.c_int64(0)
     cap = 0
     src = np.zeros(1, dtype=np.int32)

@@ -187,7 +187,8 @@ uint64_t orc_skip_map(const uint64_t* S, const uint32_t* b, const int64_t* acc_s
  *
  * pos_out receives min(k, P) positions in slot order. Returns that count.
  * *n_fallback (nullable) receives the number of slots that needed the
- * direct draw.
+ * direct draw, *n_draws (nullable) the number of draws of either kind (the
+ * attempts of the selection; counting only, no effect on the result).
  * Pinned by: chi-square of set frequencies against the exact successive-
  * sampling probabilities (enumerated), for rounds = 0 and rounds = 8,
  * including a skewed case that always reaches the direct draw; invariants
@@ -195,9 +196,10 @@ uint64_t orc_skip_map(const uint64_t* S, const uint32_t* b, const int64_t* acc_s
  */
 int32_t orc_select(const uint32_t* b, int64_t d, int64_t k, int32_t rounds,
                    uint64_t rng_seed, uint32_t c0, uint32_t c1, uint32_t c2,
-                   int64_t* pos_out, int32_t* n_fallback)
+                   int64_t* pos_out, int32_t* n_fallback, int64_t* n_draws)
 {
     if (n_fallback) *n_fallback = 0;
+    if (n_draws) *n_draws = 0;
     if (d <= 0) return 0;
     uint64_t* S = (uint64_t*)malloc((size_t)(d + 1) * sizeof(uint64_t));
     prefix(b, d, S);
@@ -220,6 +222,7 @@ int32_t orc_select(const uint32_t* b, int64_t d, int64_t k, int32_t rounds,
         for (int64_t j = 0; j < k; ++j) {
             if (held[j] >= 0) continue;
             uint64_t r = orc_draw(rng_seed, c0, c1, c2, (uint32_t)j | ((uint32_t)a << 16), W);
+            if (n_draws) ++*n_draws;
             int64_t m = orc_its(S, d, r);
             int taken = 0;
             for (int64_t q = 0; q < k; ++q)
@@ -248,6 +251,7 @@ int32_t orc_select(const uint32_t* b, int64_t d, int64_t k, int32_t rounds,
         r = orc_skip_map(S, b, acc, na, r);
         held[j] = orc_its(S, d, r);
         if (n_fallback) ++*n_fallback;
+        if (n_draws) ++*n_draws;
     }
     free(acc);
     free(S);
@@ -343,8 +347,9 @@ static int iv_push(ivec* v, int32_t x)
  * offsets[l*ni + i] is the first edge of (layer l, instance i) and
  * offsets[L*ni] the total. Returns 0, 1 on invalid input, 2 if cap is too
  * small (*num_edges still receives the total).
- * stats (nullable, double[4]): algorithmic bytes, number of expanded
- * vertices, number of direct (fallback) draws, sum of degrees expanded.
+ * stats (nullable, double[5]): algorithmic bytes, number of expanded
+ * vertices, number of direct (fallback) draws, sum of degrees expanded,
+ * number of draws of either kind.
  */
 int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const uint32_t* ew,
                    int32_t ni, const int64_t* seed_off, const int32_t* seeds,
@@ -372,14 +377,14 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
     /* per (instance, layer) edge lists */
     ivec* es = (ivec*)calloc((size_t)ni * (size_t)(L > 0 ? L : 1), sizeof(ivec));
     ivec* ed = (ivec*)calloc((size_t)ni * (size_t)(L > 0 ? L : 1), sizeof(ivec));
-    double tot_bytes = 0, tot_expanded = 0, tot_fb = 0, tot_deg = 0;
+    double tot_bytes = 0, tot_expanded = 0, tot_fb = 0, tot_deg = 0, tot_draws = 0;
     int failed = 0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
     (void)nthreads;
 #endif
-    #pragma omp parallel reduction(+ : tot_bytes, tot_expanded, tot_fb, tot_deg)
+    #pragma omp parallel reduction(+ : tot_bytes, tot_expanded, tot_fb, tot_deg, tot_draws)
     {
         unsigned char* visited = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
         uint32_t* b = NULL; int64_t bcap = 0;
@@ -418,8 +423,9 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
                         continue;
                     }
                     int32_t nfb = 0;
+                    int64_t ndr = 0;
                     int32_t s = orc_select(b, d, k, rounds, rng_seed, (uint32_t)inst_id,
-                                           (uint32_t)l, (uint32_t)v, pos, &nfb);
+                                           (uint32_t)l, (uint32_t)v, pos, &nfb, &ndr);
                     for (int32_t j = 0; j < s; ++j) {
                         iv_push(os, v);
                         iv_push(od, col[beg + pos[j]]);
@@ -427,6 +433,7 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
                     tot_bytes += select_bytes(kind, d, s);
                     tot_expanded += 1;
                     tot_fb += nfb;
+                    tot_draws += (double)ndr;
                     tot_deg += (double)d;
                 }
                 if (l + 1 < Li) {
@@ -474,7 +481,10 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
     }
     for (int64_t q = 0; q < (int64_t)ni * L; ++q) { free(es[q].p); free(ed[q].p); }
     free(es); free(ed);
-    if (stats) { stats[0] = tot_bytes; stats[1] = tot_expanded; stats[2] = tot_fb; stats[3] = tot_deg; }
+    if (stats) {
+        stats[0] = tot_bytes; stats[1] = tot_expanded; stats[2] = tot_fb; stats[3] = tot_deg;
+        stats[4] = tot_draws;
+    }
     return rc;
 }
 

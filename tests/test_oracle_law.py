@@ -115,3 +115,40 @@ def test_direct_draw_used_for_skewed_and_not_needed_for_flat():
     assert res.fallbacks > 0.1 * N_INST
     _, res = sample_star((1,) * 50, 4, 8)
     assert res.fallbacks == 0
+
+
+def test_draw_counts():
+    """The draw count of the selection: with no rounds every slot takes
+    exactly one direct draw; with rounds, every slot draws at least once and
+    the count is the open slots of each round plus the direct draws (checked
+    by replaying the rounds with the independent Philox on a small case)."""
+    from tests.helpers import torch_philox
+    from paper_2009_09103_amd import inputs
+    rp, col = inputs.rmat_csr(10, 8000, 3)
+    offs, seeds = inputs.single_instance_seeds(rp, col, 200, 5)
+    res0 = oracle.sample(rp, col, None, offs, seeds, [6, 3], bias_kind=oracle.UNIFORM, rng_seed=9, rounds=0)
+    drawn = int(res0.offsets[-1])
+    assert res0.draws == res0.fallbacks
+    res8 = oracle.sample(rp, col, None, offs, seeds, [6, 3], bias_kind=oracle.UNIFORM, rng_seed=9, rounds=8)
+    assert res8.draws >= res8.fallbacks
+    # a single list: d = 7 uniform candidates, k = 6 slots, 2 rounds
+    d, k, R = 7, 6, 2
+    held, draws = [-1] * k, 0
+    for a in range(R):
+        for j in range(k):
+            if held[j] >= 0:
+                continue
+            m = torch_philox.draw(11, [4, 0, 3, j | (a << 16)], d)
+            draws += 1
+            if m not in held:
+                held[j] = m
+    draws += sum(1 for h in held if h < 0)
+    _, nfb = oracle.select(np.ones(d, dtype=np.uint32), k, 11, 4, 0, 3, rounds=R, with_fallback=True)
+    lib = oracle.lib()
+    import ctypes
+    out = np.zeros(d, dtype=np.int64)
+    nd = ctypes.c_int64(0)
+    lib.orc_select(oracle._p(np.ones(d, dtype=np.uint32)), d, k, R, 11, 4, 0, 3, oracle._p(out), None,
+                   ctypes.byref(nd))
+    assert nd.value == draws and nfb == sum(1 for h in held if h < 0)
+    assert drawn > 0
