@@ -144,23 +144,24 @@ def bench_degree_biased(args):
     ppos = np.add.reduceat(np.append((deg[col] > 0).astype(np.int64), 0), rp[:-1])
     ppos[deg == 0] = 0
     edges_of, bytes_of = {}, {}
-    tuning = apply_tuning(g, args, offs, seeds_d, fan, bias, rng_seed=rng_seeds[0], out=(src, dst, offsets))
+    tuning = apply_tuning(g, args, offs, seeds_d, fan, bias, rng_seed=rng_seeds[0], rounds=args.rounds,
+                          out=(src, dst, offsets))
     bound = max(tuning["bound16"], tuning["bound32"])
     for s in rng_seeds:
-        r = g.sample(offs, seeds_d, fan, bias, rng_seed=s, out=(src, dst, offsets))
+        r = g.sample(offs, seeds_d, fan, bias, rounds=args.rounds, rng_seed=s, out=(src, dst, offsets))
         o = offsets.cpu().numpy()
         edges_of[s] = r.num_edges
         bytes_of[s] = path_bytes(rp, ppos, seeds, dst[:r.num_edges].cpu().numpy(), o, fan, True, bound)
         log("seed %d: %d edges" % (s, r.num_edges))
 
     for i in range(args.warmup):
-        g.sample(offs, seeds_d, fan, bias, rng_seed=rng_seeds[i % 3], out=(src, dst, offsets))
+        g.sample(offs, seeds_d, fan, bias, rounds=args.rounds, rng_seed=rng_seeds[i % 3], out=(src, dst, offsets))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total_edges = 0
     for i in range(args.steps):
         s = rng_seeds[i % 3]
-        g.sample(offs, seeds_d, fan, bias, rng_seed=s, out=(src, dst, offsets))
+        g.sample(offs, seeds_d, fan, bias, rounds=args.rounds, rng_seed=s, out=(src, dst, offsets))
         total_edges += edges_of[s]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -172,7 +173,7 @@ def bench_degree_biased(args):
     alg = {"select_small": 0.0, "select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
     for i in range(args.steps):
         s = rng_seeds[i % 3]
-        g.sample(offs, seeds_d, fan, bias, rng_seed=s, out=(src, dst, offsets))
+        g.sample(offs, seeds_d, fan, bias, rounds=args.rounds, rng_seed=s, out=(src, dst, offsets))
         for k in alg:
             alg[k] += bytes_of[s][k]
     torch.cuda.synchronize()
@@ -205,7 +206,7 @@ def bench_degree_biased(args):
                    "n": int(len(rp) - 1), "m": int(len(col)), "instances": 1,
                    "seeds": int(len(seeds)), "fanouts": rec["fanouts"], "bias": "out-degree of neighbor",
                    "rng_seeds": rng_seeds, "edges_per_step": float(np.mean(list(edges_of.values()))),
-                   "tuning": tuning},
+                   "tuning": tuning, "rounds": args.rounds or 8},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("traffic_select_degree_biased_rmat22.md"),
@@ -283,15 +284,16 @@ def bench_batched(args):
     src = torch.empty(cap, dtype=torch.int32, device=dev)
     dst = torch.empty(cap, dtype=torch.int32, device=dev)
     offsets = torch.empty(fanouts.shape[1] * ni + 1, dtype=torch.int64, device=dev)
-    r = g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+    r = g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, rounds=args.rounds, out=(src, dst, offsets))
     edges = r.num_edges
-    tuning = apply_tuning(g, args, offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+    tuning = apply_tuning(g, args, offs, seeds_d, fanouts, bias, rng_seed=1, rounds=args.rounds,
+                          out=(src, dst, offsets))
     for _ in range(args.warmup):
-        g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+        g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, rounds=args.rounds, out=(src, dst, offsets))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+        g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, rounds=args.rounds, out=(src, dst, offsets))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     # algorithmic bytes of the call and kernel times from one event-timed pass
@@ -302,7 +304,7 @@ def bench_batched(args):
                            max(tuning["bound16"], tuning["bound32"]))
     csaw.profile_reset()
     csaw.profile_enable(True)
-    g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, out=(src, dst, offsets))
+    g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, rounds=args.rounds, out=(src, dst, offsets))
     torch.cuda.synchronize()
     times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_small", "select_wave", "chunk_prefix",
                                                 "select_big", "frontier_build", "visited_clear")}
@@ -322,11 +324,11 @@ def bench_batched(args):
     poff = torch.empty(fanouts.shape[1] + 1, dtype=torch.int64, device=dev)
     plain_edges = 0
     for i, (so, sd, f, b) in enumerate(per[:64]):
-        g.sample(so, sd, f, b, rng_seed=1, instance_base=i, out=(psrc, pdst, poff))
+        g.sample(so, sd, f, b, rng_seed=1, instance_base=i, rounds=args.rounds, out=(psrc, pdst, poff))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i, (so, sd, f, b) in enumerate(per):
-        plain_edges += g.sample(so, sd, f, b, rng_seed=1, instance_base=i, out=(psrc, pdst, poff)).num_edges
+        plain_edges += g.sample(so, sd, f, b, rng_seed=1, instance_base=i, rounds=args.rounds, out=(psrc, pdst, poff)).num_edges
     torch.cuda.synchronize()
     pdt = time.perf_counter() - t0
     assert plain_edges == edges
@@ -336,7 +338,7 @@ def bench_batched(args):
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
         "config": {"workload": rec["name"], "instances": ni, "seeds": int(len(seeds)),
-                   "edges_per_step": int(edges), "tuning": tuning},
+                   "edges_per_step": int(edges), "tuning": tuning, "rounds": args.rounds or 8},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "select_wave (k_select)",
                      "launches": sel_n, "avg_launch_us": sel_ms / max(sel_n, 1) * 1e3,
@@ -597,6 +599,8 @@ def main():
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--served-scale", type=int, default=0)
     ap.add_argument("--n2v-scale", type=int, default=0)
+    ap.add_argument("--rounds", type=int, default=0,
+                    help="repeated-sampling rounds before the direct draws: 0 (default 8), 1..8, -1 (none)")
     ap.add_argument("--tuning", default="auto",
                     help='sub-wave buckets of the sampling kernel: "auto", "default" or "bound16,bound32"')
     ap.add_argument("--n2v-stride", type=int, default=64)

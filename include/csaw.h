@@ -87,8 +87,12 @@ typedef enum {
 /* Largest fanout that is drawn (a fanout >= the number of positive-bias
  * neighbors takes all of them and has no limit). */
 #define CSAW_MAX_FANOUT 64
-/* Repeated-sampling rounds before the direct draw. */
+/* Repeated-sampling rounds before the direct draw: the default and the
+ * largest value of csaw_sample_args.rounds. */
 #define CSAW_ROUNDS 8
+/* csaw_sample_args.rounds value for no rounds at all: every slot takes the
+ * direct draw from the updated prefix (Theorem 2's inverse) in slot order. */
+#define CSAW_DIRECT_ONLY (-1)
 /* Most layers per sampling call. */
 #define CSAW_MAX_LAYERS 16
 
@@ -160,6 +164,11 @@ typedef struct {
     const uint64_t* rng_seeds;    /* HOST uint64[num_instances] or NULL: a Philox
                                      key per instance, so that instances from
                                      unrelated requests share one call            */
+    int32_t rounds;               /* repeated-sampling rounds before the direct
+                                     draws (Section IV-B): 0 = CSAW_ROUNDS (the
+                                     default), 1..CSAW_ROUNDS, or CSAW_DIRECT_ONLY.
+                                     Every value samples the same law; the edges
+                                     differ (other draws are used)                */
 } csaw_sample_args;
 
 typedef struct {

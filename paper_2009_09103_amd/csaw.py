@@ -16,6 +16,7 @@ import torch  # loads the HIP runtime that libcsaw then shares
 from . import _build
 
 UNIFORM, EDGE_WEIGHT, NEIGHBOR_DEGREE, NODE2VEC = 0, 1, 2, 3
+DIRECT_ONLY = -1  # csaw_sample_args.rounds: no repeated-sampling rounds
 FANOUT_ALL = -1
 MAX_FANOUT = 64
 MAX_LAYERS = 16
@@ -39,7 +40,7 @@ class SampleArgs(ctypes.Structure):
                 ("num_layers", ctypes.c_int32), ("fanouts", ctypes.c_void_p),
                 ("fanout_stride", ctypes.c_int32), ("bias_kind", ctypes.c_int32),
                 ("bias_kinds", ctypes.c_void_p), ("rng_seed", ctypes.c_uint64),
-                ("instance_ids", ctypes.c_void_p), ("rng_seeds", ctypes.c_void_p)]
+                ("instance_ids", ctypes.c_void_p), ("rng_seeds", ctypes.c_void_p), ("rounds", ctypes.c_int32)]
 
 
 class SampleOut(ctypes.Structure):
@@ -209,7 +210,7 @@ class Graph:
 
     # -------------------------------------------------------------- sampling
     def _sample_args(self, seed_offsets, seeds_dev, fanouts, bias, rng_seed, instance_base,
-                     instance_ids=None, rng_seeds=None):
+                     instance_ids=None, rng_seeds=None, rounds=0):
         so = np.ascontiguousarray(seed_offsets, dtype=np.int64)
         fo = np.ascontiguousarray(fanouts, dtype=np.int32)
         ni = len(so) - 1
@@ -235,6 +236,7 @@ class Graph:
             a.bias_kinds = None
             a.bias_kind = _bias_code(bias)
         a.rng_seed = int(rng_seed)
+        a.rounds = int(rounds)
         a.instance_ids = None
         a.rng_seeds = None
         if instance_ids is not None:
@@ -256,15 +258,17 @@ class Graph:
         return mx.value
 
     def sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
-               capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None) -> SampleResult:
+               capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, rounds=0) -> SampleResult:
         """Neighbor sampling (csaw_sample). ``seeds`` may be a device tensor
         (used in place) or host data (copied). ``out`` may pass preallocated
-        (src, dst, offsets) device tensors."""
+        (src, dst, offsets) device tensors. ``rounds``: 0 (default, 8), 1..8,
+        or DIRECT_ONLY."""
         return self._run_sample(lambda a, o: lib.csaw_sample(self._h, a, o, _stream(stream)), seed_offsets, seeds,
-                                fanouts, bias, rng_seed, instance_base, capacity, out, instance_ids, rng_seeds)
+                                fanouts, bias, rng_seed, instance_base, capacity, out, instance_ids, rng_seeds,
+                                rounds)
 
     def autotune_sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
-                        capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, reps=3):
+                        capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, reps=3, rounds=0):
         """Autotuner (csaw_autotune_sample): times the call under each
         sub-wave bucket setting, keeps the fastest on the graph. Returns
         (SampleResult, (bound16, bound32))."""
@@ -272,7 +276,7 @@ class Graph:
         res = self._run_sample(lambda a, o: lib.csaw_autotune_sample(self._h, a, o, int(reps), _stream(stream),
                                                                      ctypes.byref(t)),
                                seed_offsets, seeds, fanouts, bias, rng_seed, instance_base, capacity, out,
-                               instance_ids, rng_seeds)
+                               instance_ids, rng_seeds, rounds)
         return res, (t.bound16, t.bound32)
 
     def set_tuning(self, bound16: int, bound32: int):
@@ -286,10 +290,10 @@ class Graph:
         return t.bound16, t.bound32
 
     def _run_sample(self, call, seed_offsets, seeds, fanouts, bias, rng_seed, instance_base, capacity, out,
-                    instance_ids, rng_seeds) -> SampleResult:
+                    instance_ids, rng_seeds, rounds=0) -> SampleResult:
         seeds_dev = _dev_i32(seeds, self.device)
         a, keep, ni, L = self._sample_args(seed_offsets, seeds_dev, fanouts, bias, rng_seed,
-                                           instance_base, instance_ids, rng_seeds)
+                                           instance_base, instance_ids, rng_seeds, rounds)
         if out is None:
             if capacity is None:
                 mx = ctypes.c_int64()

@@ -9,7 +9,7 @@ namespace csaw {
 
 constexpr int kMaxLayers = 16;
 constexpr int kMaxDrawFanout = 64;   // slots of one wave
-constexpr int kRounds = 8;           // repeated-sampling rounds
+constexpr int kDefaultRounds = 8;    // repeated-sampling rounds before the direct draws
 constexpr int kChunk = 1024;         // weights per chunk of a long list
 constexpr int kChunkGroups = 64;     // 16-weight groups per chunk
 constexpr int32_t kWideList = (int32_t)0x80000000u;  // ppos flag: the list's total weight is >= 2^32
@@ -101,6 +101,7 @@ struct SampleLayer {
     uint32_t* next;                  // [ni * nwp]
     int64_t nwp;                     // bitmap words per instance (multiple of 4)
     int32_t group16, group32;        // sub-wave bucket bounds (<= 16, <= 32; 0 = off)
+    int32_t rounds;                  // repeated-sampling rounds (0: every slot by direct draw)
 };
 
 constexpr int32_t kDefaultBound16 = 16, kDefaultBound32 = 32;

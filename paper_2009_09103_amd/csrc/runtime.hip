@@ -328,6 +328,7 @@ struct SamplePlan {
     int64_t max_edges = 0;
     int64_t total_seeds = 0;
     bool uses_deg = false, uses_ew = false;
+    int32_t rounds = kDefaultRounds;
 };
 
 csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P, bool need_seeds) {
@@ -343,6 +344,9 @@ csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P, 
     if (L > 0 && ni > 0 && !a->fanouts) return fail(CSAW_ERR_INVALID_ARG, "fanouts is NULL");
     if (a->fanout_stride != 0 && a->fanout_stride < L)
         return fail(CSAW_ERR_INVALID_ARG, "fanout_stride must be 0 or >= num_layers");
+    if (a->rounds < CSAW_DIRECT_ONLY || a->rounds > CSAW_ROUNDS)
+        return fail(CSAW_ERR_INVALID_ARG, "rounds must be CSAW_DIRECT_ONLY, 0 (default) or 1..%d", CSAW_ROUNDS);
+    P.rounds = a->rounds == 0 ? kDefaultRounds : (a->rounds == CSAW_DIRECT_ONLY ? 0 : a->rounds);
     if (ni > 0) {
         if (a->seed_offsets[0] != 0) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets[0] != 0");
         for (int32_t i = 0; i < ni; ++i)
@@ -647,6 +651,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         p.nwp = nwp;
         p.group16 = b16;
         p.group32 = b32;
+        p.rounds = P.rounds;
         int computed_layers = 1;  // frontiers F_0 .. F_{computed_layers-1} exist
         for (int32_t l = 0; l < L; ++l) {
             p.layer = l;
@@ -712,7 +717,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
                                         (int64_t)(intptr_t)out->src, (int64_t)(intptr_t)out->dst,
                                         (int64_t)(intptr_t)out->offsets, (int64_t)(intptr_t)ws->arena,
                                         (int64_t)(intptr_t)ws->bitmaps, (int64_t)(intptr_t)ws->pinned,
-                                        (int64_t)big_path, b16, b32};
+                                        (int64_t)big_path, b16, b32, P.rounds};
             key.insert(key.end(), P.fcap.begin(), P.fcap.end());
             hipGraphExec_t exec = ws->find_graph(key);
             if (!exec) {

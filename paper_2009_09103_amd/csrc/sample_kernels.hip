@@ -534,13 +534,13 @@ __device__ __forceinline__ void coarse_search(const CoarsePool& pl, uint64_t r, 
 // a per-lane inverse transform search(r, m, Sm, bm). Each round every open
 // slot draws; taken in slot order, a slot keeps its candidate unless it is
 // already held -- which also covers a lower slot that took the same candidate
-// in this round, so the lowest slot wins. Slots still open after kRounds take
+// in this round, so the lowest slot wins. Slots still open after `rounds` take
 // direct draws from the prefix without the held candidates, in slot order:
 // r0 in [0, W - held mass), mapped by the skip map (every held candidate whose
 // start in the updated prefix is at or below r0 adds its bias) and searched
 // with search_all (same r on every lane).
 template <class Search, class SearchAll>
-__device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k,
+__device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1, uint32_t c2, int32_t k, int32_t rounds,
                                               uint64_t W, const Search& search, const SearchAll& search_all) {
     const int lane = lane_id();
     bool held = false;
@@ -548,7 +548,7 @@ __device__ __forceinline__ int64_t draw_slots(Key key, uint32_t c0, uint32_t c1,
     uint64_t Spos = 0;
     uint32_t bpos = 0;
     uint64_t open = k >= kWave ? ~0ull : ((1ull << k) - 1);
-    for (int a = 0; a < kRounds && open; ++a) {
+    for (int a = 0; a < rounds && open; ++a) {
         int64_t m = -1;
         uint64_t Sm = 0;
         uint32_t bm = 0;
@@ -624,7 +624,7 @@ __device__ __forceinline__ int32_t find_resident(const T (&S)[E], T r) {
 
 template <int E, typename T>
 __device__ __forceinline__ int32_t draw_resident_t(const uint32_t (&x)[E], T excl, T W, Key key, uint32_t c0,
-                                                   uint32_t c1, uint32_t c2, int32_t k) {
+                                                   uint32_t c1, uint32_t c2, int32_t k, int32_t rounds) {
     const int lane = lane_id();
     T S[E];
     {
@@ -638,7 +638,7 @@ __device__ __forceinline__ int32_t draw_resident_t(const uint32_t (&x)[E], T exc
     uint32_t hb = 0;  // held bits of this lane's candidates
     int32_t pos = 0;
     uint64_t open = k >= kWave ? ~0ull : ((1ull << k) - 1);
-    for (int a = 0; a < kRounds && open; ++a) {
+    for (int a = 0; a < rounds && open; ++a) {
         T rl = 0;
         if ((open >> lane) & 1ull) rl = (T)draw(key, c0, c1, c2, (uint32_t)lane | ((uint32_t)a << 16), (uint64_t)W);
         for (uint64_t todo = open; todo; todo &= todo - 1) {
@@ -680,7 +680,7 @@ __device__ __forceinline__ int32_t draw_resident_t(const uint32_t (&x)[E], T exc
 
 template <int E>
 __device__ __forceinline__ int32_t draw_resident(const uint32_t* __restrict__ w, int64_t d, Key key, uint32_t c0,
-                                                 uint32_t c1, uint32_t c2, int32_t k) {
+                                                 uint32_t c1, uint32_t c2, int32_t k, int32_t rounds) {
     const int lane = lane_id();
     // d <= kWaveMaxD: 32-bit indices; every load is issued (clamped into the
     // list) and the tail zeroed after, so no lane branches
@@ -697,7 +697,7 @@ __device__ __forceinline__ int32_t draw_resident(const uint32_t* __restrict__ w,
     // routing guarantees W < 2^32, so every prefix fits 32 bits
     const uint32_t incl = wave_incl_scan_u32((uint32_t)ls);
     const uint32_t W = readlane_u32(incl, kWave - 1);
-    return draw_resident_t<E, uint32_t>(x, incl - (uint32_t)ls, W, key, c0, c1, c2, k);
+    return draw_resident_t<E, uint32_t>(x, incl - (uint32_t)ls, W, key, c0, c1, c2, k, rounds);
 }
 
 // A picked neighbor joins the instance's next bitmap unless it is visited or
@@ -911,15 +911,15 @@ __device__ void select_entry(const SampleLayer& p, const EntryInfo& E) {
             Sm = r;
             bm = 1;
         };
-        pos = draw_slots(key, c0, c1, c2, E.k, (uint64_t)d, pick, pick);
+        pos = draw_slots(key, c0, c1, c2, E.k, p.rounds, (uint64_t)d, pick, pick);
     } else if (d <= 64) {
-        pos = draw_resident<1>(w, d, key, c0, c1, c2, E.k);
+        pos = draw_resident<1>(w, d, key, c0, c1, c2, E.k, p.rounds);
     } else if (d <= 128) {
-        pos = draw_resident<2>(w, d, key, c0, c1, c2, E.k);
+        pos = draw_resident<2>(w, d, key, c0, c1, c2, E.k, p.rounds);
     } else if (d <= 256) {
-        pos = draw_resident<4>(w, d, key, c0, c1, c2, E.k);
+        pos = draw_resident<4>(w, d, key, c0, c1, c2, E.k, p.rounds);
     } else {
-        pos = draw_resident<8>(w, d, key, c0, c1, c2, E.k);
+        pos = draw_resident<8>(w, d, key, c0, c1, c2, E.k, p.rounds);
     }
     emit_slots(p, E, pos);
 }
@@ -931,7 +931,7 @@ __device__ void select_entry(const SampleLayer& p, const EntryInfo& E) {
 // an entry is lane j of its group, a weighted candidate i is lane i. The
 // rounds take each group's slots in slot order exactly as the full-wave path
 // does (one slot index t at a time for all groups), so results do not depend
-// on the grouping. An entry with slots still open after kRounds is returned
+// on the grouping. An entry with slots still open after the rounds is returned
 // to the full-wave path, which repeats its rounds and ends with direct draws.
 // The bucket bounds (largest size served by 16- and 32-lane groups) are call
 // parameters, so a tuner can pick them per workload.
@@ -1027,7 +1027,7 @@ __device__ uint64_t select_groups(const SampleLayer& p, const RunLds& R, uint64_
         const Key key{(uint32_t)ekey, (uint32_t)(ekey >> 32)};
         uint64_t open = ballot(drw && gl < k);
         int32_t hid = -1;  // candidate this lane marks held (uniform: its slot's pick; weighted: itself)
-        for (int a = 0; a < kRounds && open; ++a) {
+        for (int a = 0; a < p.rounds && open; ++a) {
             uint32_t r = 0;
             if ((open >> lane) & 1ull) r = (uint32_t)draw(key, c0, (uint32_t)p.layer, (uint32_t)v, (uint32_t)gl | ((uint32_t)a << 16), W);
             uint64_t tm = 0;
@@ -1074,9 +1074,10 @@ __device__ void select_entry_small_draw(const SampleLayer& p, const EntryInfo& E
             Sm = r;
             bm = 1;
         };
-        pos = draw_slots(key, E.c0, c1, c2, E.k, (uint64_t)E.d, pick, pick);
+        pos = draw_slots(key, E.c0, c1, c2, E.k, p.rounds, (uint64_t)E.d, pick, pick);
     } else {
-        pos = draw_resident<1>((E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg, E.d, key, E.c0, c1, c2, E.k);
+        pos = draw_resident<1>((E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg, E.d, key, E.c0, c1, c2, E.k,
+                                 p.rounds);
     }
     emit_slots(p, E, pos);
 }
@@ -1269,7 +1270,7 @@ __device__ void select_big_entry(const SampleLayer& p, const EntryInfo& E, uint6
         const auto search = [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
             coarse_search(pl, r, m, Sm, bm);
         };
-        pos = draw_slots(key, c0, c1, c2, E.k, W, search, search);
+        pos = draw_slots(key, c0, c1, c2, E.k, p.rounds, W, search, search);
     } else {
         int shift = 0;
         while (((nch + (1ll << shift) - 1) >> shift) > kBigTab) ++shift;
@@ -1293,7 +1294,7 @@ __device__ void select_big_entry(const SampleLayer& p, const EntryInfo& E, uint6
         const auto search = [&pl](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
             unit_search(pl, r, m, Sm, bm);
         };
-        pos = draw_slots(key, c0, c1, c2, E.k, carry, search, search);
+        pos = draw_slots(key, c0, c1, c2, E.k, p.rounds, carry, search, search);
     }
     emit_slots(p, E, pos);
     wave_lds_sync();  // the table is rewritten by the wave's next list

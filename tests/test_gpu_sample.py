@@ -445,3 +445,29 @@ def test_long_lists_without_hubs(csaw):
     bias = [1, 2] * (ni // 2) + [1] * (ni % 2)
     for k in (2, 10, 64):
         run_both(csaw, g, rp, col, ew, offs, seeds, [k, 3], bias, 70 + k)
+
+
+@pytest.mark.parametrize("rounds", [-1, 1, 2, 8, 0])
+def test_rounds_and_direct_only(csaw, rounds):
+    """The number of repeated-sampling rounds before the direct draws is a
+    call argument: no rounds at all (every slot by direct draw from the
+    updated prefix), 1, 2, 8 or the default; each against the oracle with the
+    same rounds, on every route (sub-wave groups, wavefront, long lists)."""
+    rp, col = small_list_graph(4000, [0, 2, 5, 12, 16, 30, 60, 200, 700, 1500], 51)
+    rng = inputs.rng(52)
+    ew = rng.integers(0, 9, size=len(col)).astype(np.uint32) ** 4
+    offs, seeds = inputs.batched_instances(rp, col, 24, 53)[:2]
+    g = csaw.Graph(rp, col, ew)
+    orc_rounds = {-1: 0, 0: 8}.get(rounds, rounds)
+    bias = [0, 1, 2] * 8
+    say("rounds %d (oracle %d)" % (rounds, orc_rounds))
+    res = g.sample(offs, seeds, [10, 25], bias, rng_seed=61, rounds=rounds)
+    ref = oracle.sample(rp, col, ew, offs, seeds, [10, 25], bias_kinds=np.asarray(bias, dtype=np.int32),
+                        rng_seed=61, rounds=orc_rounds)
+    assert_same(res, ref)
+    if rounds == -1:
+        assert ref.draws == ref.fallbacks > 0
+    with pytest.raises(csaw.CsawError):
+        g.sample(offs, seeds, [10], 0, rounds=9)
+    with pytest.raises(csaw.CsawError):
+        g.sample(offs, seeds, [10], 0, rounds=-2)
