@@ -55,15 +55,15 @@ def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted, bound=0):
     call's own output. Per frontier vertex: 8 (frontier entry) + 16 (row-offset
     pair) bytes of metadata. Lists drawn by the wavefront kernels (select_small
     for the sub-wave buckets, select_wave for the rest) add 4*deg if the bias
-    reads a weight array; long weighted lists read their 4*deg weight bytes in
-    chunk_prefix, which writes one 8-byte group prefix per 16 weights that
-    select_big reads back. Every emitted edge costs 12 (neighbor id read +
-    edge written) in the kernel that draws it."""
+    reads a weight array; a long weighted list (select_big) reads one 8-byte
+    group prefix per 16 weights from the graph's chunk prefix table (built once
+    per graph, so not part of a call). Every emitted edge costs 12 (neighbor id
+    read + edge written) in the kernel that draws it."""
     deg = np.diff(rowptr)
     L = len(fanouts)
     visited = np.unique(seeds)
     frontier = visited
-    out = {"select_small": 0.0, "select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
+    out = {"select_small": 0.0, "select_wave": 0.0, "select_big": 0.0}
     for l in range(L):
         a, b = offsets[l], offsets[l + 1]
         k = int(fanouts[l])
@@ -76,7 +76,6 @@ def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted, bound=0):
         for name, w in (("select_small", sm), ("select_wave", ~long_ & ~sm)):
             out[name] += 24.0 * w.sum() + 12.0 * c[w].sum() + (4.0 * d[w].sum() if weighted else 0.0)
         groups = np.ceil(d[long_] / 16.0)
-        out["chunk_prefix"] += 4.0 * d[long_].sum() + 8.0 * groups.sum() + 8.0 * np.ceil(d[long_] / 1024.0).sum()
         out["select_big"] += 24.0 * long_.sum() + 8.0 * groups.sum() + 12.0 * c[long_].sum()
         if l + 1 < L:
             nxt = np.setdiff1d(np.unique(dst[a:b]), visited, assume_unique=True)
@@ -170,15 +169,15 @@ def bench_degree_biased(args):
     # kernel times from HIP events on the call's stream (separate pass)
     csaw.profile_reset()
     csaw.profile_enable(True)
-    alg = {"select_small": 0.0, "select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
+    alg = {"select_small": 0.0, "select_wave": 0.0, "select_big": 0.0}
     for i in range(args.steps):
         s = rng_seeds[i % 3]
         g.sample(offs, seeds_d, fan, bias, rounds=args.rounds, rng_seed=s, out=(src, dst, offsets))
         for k in alg:
             alg[k] += bytes_of[s][k]
     torch.cuda.synchronize()
-    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_small", "select_wave", "chunk_prefix",
-                                                "select_big", "frontier_build", "visited_clear")}
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_small", "select_wave", "select_big",
+                                                "frontier_build", "visited_clear")}
     csaw.profile_enable(False)
     csaw.profile_reset()
     sel_ms, sel_n = times["select_wave"]
@@ -237,7 +236,7 @@ def path_bytes_multi(rowptr, ppos, seed_offs, seeds, dst, offsets, fanouts, bias
     inst_of_seed = np.repeat(np.arange(ni, dtype=np.int64), np.diff(seed_offs))
     visited = np.unique(inst_of_seed * n + seeds.astype(np.int64))
     frontier = visited
-    out = {"select_small": 0.0, "select_wave": 0.0, "chunk_prefix": 0.0, "select_big": 0.0}
+    out = {"select_small": 0.0, "select_wave": 0.0, "select_big": 0.0}
     for l in range(L):
         inst = frontier // n
         v = frontier % n
@@ -252,7 +251,6 @@ def path_bytes_multi(rowptr, ppos, seed_offs, seeds, dst, offsets, fanouts, bias
         for name, w in (("select_small", sm), ("select_wave", ~long_ & ~sm)):
             out[name] += 24.0 * w.sum() + 12.0 * c[w].sum() + 4.0 * d[w & wflag].sum()
         groups = np.ceil(d[long_] / 16.0)
-        out["chunk_prefix"] += 4.0 * d[long_].sum() + 8.0 * groups.sum() + 8.0 * np.ceil(d[long_] / 1024.0).sum()
         out["select_big"] += 24.0 * long_.sum() + 8.0 * groups.sum() + 12.0 * c[long_].sum()
         if l + 1 < L:
             a, b = offsets[l * ni], offsets[(l + 1) * ni]
@@ -306,8 +304,8 @@ def bench_batched(args):
     csaw.profile_enable(True)
     g.sample(offs, seeds_d, fanouts, bias, rng_seed=1, rounds=args.rounds, out=(src, dst, offsets))
     torch.cuda.synchronize()
-    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_small", "select_wave", "chunk_prefix",
-                                                "select_big", "frontier_build", "visited_clear")}
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_small", "select_wave", "select_big",
+                                                "frontier_build", "visited_clear")}
     csaw.profile_enable(False)
     csaw.profile_reset()
     sel_ms, sel_n = times["select_wave"]

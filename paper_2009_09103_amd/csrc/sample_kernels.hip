@@ -198,7 +198,9 @@ __device__ __forceinline__ void block_excl_scan4(int64_t (&x)[4], int64_t (&tot)
 // one word per thread for the most parallel blocks, large ones many, so that
 // the number of blocks, each a short latency-bound chain of loads, stays
 // small); it counts the new bits (entries), their edge counts min(k, P)
-// (edges) and their long-list route; a block scan plus a decoupled look-back
+// (edges) and their long-list route (the words and the list fields are
+// loaded again in the write pass rather than held in registers across the
+// scan, which keeps occupancy up); a block scan plus a decoupled look-back
 // over the blocks before it give global positions (blocks are dispatched in
 // index order, so predecessors are resident or done; the spin is bounded and
 // reports instead of hanging). The thread then writes its entries in
@@ -244,13 +246,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
             viss[g][0] = iw < fb.nwords ? fb.visited[iw] : 0u;
         }
     }
-    // the thread's first four entries (first bits of its first non-empty word)
-    // keep their counts in registers for the write pass
-    int32_t cc[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0}, cp[4] = {0, 0, 0, 0};
-    int64_t cbeg[4] = {0, 0, 0, 0}, cd[4] = {0, 0, 0, 0};
     int64_t cnt4[4] = {0, 0, 0, 0};  // entries, edges, long lists, (unused)
     {
-        bool first = true;
         int64_t inst_k = -1;
         int32_t k = 0, kind = 0;
 #pragma unroll
@@ -283,15 +280,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                             cnt4[1] += c;
                             if (route == kRouteBig) ++cnt4[2];
                         }
-                        if (first) {
-                            cc[t] = c;
-                            cr[t] = route;
-                            cp[t] = pinfo;
-                            cbeg[t] = beg;
-                            cd[t] = d;
-                        }
                     }
-                    first = false;
                 }
             }
         }
@@ -367,13 +356,28 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     __syncthreads();
     int64_t pos = s_base_e + ex_e;
     int64_t eoff = s_base_g + ex_g;
-    bool first = true;
     int64_t inst_k = -1;
     int32_t k = 0, kind = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int64_t iw4 = w0 + V * g;
         if (iw4 >= fb.nwords) break;
+        // the words again (L2): keeping them in registers across the scan
+        // costs occupancy
+        if (V == 4) {
+            const uint4 r4 = *(const uint4*)(fb.next + iw4);
+            const bool any = (r4.x | r4.y | r4.z | r4.w) != 0u;
+            const uint4 v4 = any ? *(const uint4*)(fb.visited + iw4) : make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t rr[4] = {r4.x, r4.y, r4.z, r4.w}, vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                raws[g][q] = rr[q];
+                viss[g][q] = vv[q];
+            }
+        } else {
+            raws[g][0] = fb.next[iw4];
+            viss[g][0] = fb.visited[iw4];
+        }
         uint32_t newv[V];
         bool any_raw = false, any_new = false;
 #pragma unroll
@@ -405,15 +409,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                     const int32_t v = vbase + bv[t];
                     int32_t route, c, pinfo;
                     int64_t beg, d;
-                    if (first) {
-                        c = cc[t];
-                        route = cr[t];
-                        pinfo = cp[t];
-                        beg = cbeg[t];
-                        d = cd[t];
-                    } else {
-                        c = entry_count(fb.g, k, kind, v, route, beg, d, pinfo, fb.ctl);
-                    }
+                    c = entry_count(fb.g, k, kind, v, route, beg, d, pinfo, fb.ctl);
                     fb.fv[pos] = v;
                     fb.fi[pos] = (int32_t)inst;
                     fb.cnt[pos] = c;
@@ -425,7 +421,6 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                     ++pos;
                     eoff += c;
                 }
-                first = false;
             }
         }
         if (V == 4) {
