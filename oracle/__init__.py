@@ -79,7 +79,9 @@ def lib():
             L.orc_select.argtypes = [vp, i64, i64, i32, u64, u32, u32, u32, vp, vp, vp]
             L.orc_select.restype = i32
             L.orc_sample.argtypes = [i64, vp, vp, vp, i32, vp, vp, u64, vp, i32, vp, i32, vp, i32,
-                                     u64, i32, i64, vp, vp, vp, vp, vp, i32]
+                                     u64, i32, u32, i64, vp, vp, vp, vp, vp, i32]
+            L.orc_burn_count.argtypes = [u64, u32, u32, u32, u32, i32]
+            L.orc_burn_count.restype = i32
             L.orc_sample.restype = i32
             L.orc_walk.argtypes = [i64, vp, vp, vp, i32, u32, u32, u32, i64, vp, u64, vp, i32, u64,
                                    u32, u32, vp, vp, vp, i32]
@@ -133,6 +135,11 @@ def skip_map(S, b, acc_sorted, r: int) -> int:
     return int(lib().orc_skip_map(_p(S), _p(b), _p(a), len(a), r))
 
 
+def burn_count(rng_seed: int, c0: int, c1: int, c2: int, burn: int, cap: int) -> int:
+    """Forest fire NeighborSize of one vertex (see ``orc_burn_count``)."""
+    return int(lib().orc_burn_count(rng_seed, c0, c1, c2, burn, cap))
+
+
 def select(b, k: int, rng_seed: int, c0: int, c1: int, c2: int, rounds: int = DEFAULT_ROUNDS,
            with_fallback: bool = False):
     """Select min(k, P) distinct positions of the bias list ``b`` (slot order)."""
@@ -163,7 +170,7 @@ class SampleResult:
 
 def sample(rowptr, col, ew, seed_offsets, seeds, fanouts, bias_kind=UNIFORM, rng_seed=1,
            instance_base=0, instance_ids=None, bias_kinds=None, rounds=DEFAULT_ROUNDS,
-           nthreads=0) -> SampleResult:
+           nthreads=0, burn=0) -> SampleResult:
     """Neighbor sampling for a batch of instances (see ``orc_sample``).
 
     fanouts: 1-D (shared by all instances) or 2-D [num_instances, num_layers]."""
@@ -191,7 +198,7 @@ def sample(rowptr, col, ew, seed_offsets, seeds, fanouts, bias_kind=UNIFORM, rng
     for _ in range(2):
         rc = lib().orc_sample(n, _p(rowptr), _p(col), _p(ew), ni, _p(seed_offsets), _p(seeds),
                               instance_base, _p(ids), L, _p(fo), stride, _p(bk), bias_kind,
-                              rng_seed, rounds, cap, _p(src), _p(dst), _p(offsets),
+                              rng_seed, rounds, burn, cap, _p(src), _p(dst), _p(offsets),
                               ctypes.byref(ne), _p(stats), nthreads)
         if rc == 1:
             raise ValueError("oracle: invalid sampling input")

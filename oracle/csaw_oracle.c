@@ -56,6 +56,8 @@ enum { ORC_UNIFORM = 0, ORC_EDGE_WEIGHT = 1, ORC_NEIGHBOR_DEGREE = 2, ORC_NODE2V
 
 /* Round index reserved for the exact conditional draw. */
 #define ORC_FALLBACK_ROUND 0xFFFFu
+#define ORC_BURN_ROUND 0xFFFEu      /* counter word 3 of the forest fire trials */
+#define ORC_BURN_CAP_ALL 64         /* burning cap of a fanout of -1 */
 
 /* ---------------------------------------------------------------------------
  * Philox4x32-10: Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As
@@ -258,6 +260,34 @@ int32_t orc_select(const uint32_t* b, int64_t d, int64_t k, int32_t rounds,
     return (int32_t)k;
 }
 
+/*
+ * Forest fire NeighborSize (Section II-A names forest fire sampling as
+ * neighbor sampling with a variable number of neighbors per vertex set by a
+ * burning probability; the rule is Leskovec and Faloutsos, KDD'06): a vertex
+ * burns G neighbors, G geometric with P(G >= j) = p^j, p = burn / 2^32,
+ * capped at cap. Trial j = 0, 1, ... succeeds iff word (j mod 4) of the
+ * Philox block with counter (c0, c1, c2, 0xFFFE << 16 | j / 4) is below
+ * burn; G is the number of successes before the first failure, or cap.
+ * Pinned by: the capped geometric law (chi-square over many vertices), the
+ * counter layout replayed with the independent Philox, and the two ends
+ * (burn = 2^32 - 1 burns cap neighbors, burn = 0 none).
+ */
+int32_t orc_burn_count(uint64_t rng_seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t burn, int32_t cap)
+{
+    uint32_t key[2] = {(uint32_t)rng_seed, (uint32_t)(rng_seed >> 32)};
+    int32_t g = 0;
+    for (uint32_t blk = 0; g < cap; ++blk) {
+        uint32_t ctr[4] = {c0, c1, c2, (ORC_BURN_ROUND << 16) | blk};
+        uint32_t x[4];
+        orc_philox4x32_10(key, ctr, x);
+        for (int w = 0; w < 4 && g < cap; ++w) {
+            if (x[w] >= burn) return g;
+            ++g;
+        }
+    }
+    return g;
+}
+
 /* ---------------------------------------------------------------------------
  * Graph helpers. CSR: rowptr int64[n+1], col int32[m]; adjacency lists are
  * sorted. GatherNeighbors (fig:api(b)) of v is col[rowptr[v] ..
@@ -341,7 +371,9 @@ static int iv_push(ivec* v, int32_t x)
  * (inst_id mod 2^32, l, v, slot|round)) and emits (v, neighbor) per pick;
  * F_{l+1} = distinct picked neighbors not yet visited, then they are
  * marked visited. Edges to visited vertices are still emitted.
- * Fanout -1 selects every positive-bias neighbor.
+ * Fanout -1 selects every positive-bias neighbor. With burn != 0 (forest
+ * fire), vertex v's NeighborSize is orc_burn_count(rng_seed, inst_id, l, v,
+ * burn, cap) with cap = the fanout (ORC_BURN_CAP_ALL for -1).
  *
  * Output, in order (layer, instance, src, slot): src/dst[cap];
  * offsets[l*ni + i] is the first edge of (layer l, instance i) and
@@ -356,12 +388,12 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
                    uint64_t instance_base, const uint64_t* instance_ids,
                    int32_t L, const int32_t* fanouts, int32_t fanout_stride,
                    const int32_t* bias_kinds, int32_t bias_kind,
-                   uint64_t rng_seed, int32_t rounds,
+                   uint64_t rng_seed, int32_t rounds, uint32_t burn,
                    int64_t cap, int32_t* src, int32_t* dst, int64_t* offsets,
                    int64_t* num_edges, double* stats, int32_t nthreads)
 {
     orc_graph g = {n, rowptr, col, ew};
-    if (ni < 0 || L < 0 || n < 0 || rounds < 0 || rounds >= (int32_t)ORC_FALLBACK_ROUND) return 1;
+    if (ni < 0 || L < 0 || n < 0 || rounds < 0 || rounds >= (int32_t)ORC_BURN_ROUND) return 1;
     for (int32_t i = 0; i < ni; ++i) {
         int32_t kind = bias_kinds ? bias_kinds[i] : bias_kind;
         if (kind != ORC_UNIFORM && kind != ORC_EDGE_WEIGHT && kind != ORC_NEIGHBOR_DEGREE) return 1;
@@ -405,11 +437,16 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
             }
             qsort(cur.p, (size_t)cur.n, sizeof(int32_t), cmp_i32);
             for (int32_t l = 0; l < Li; ++l) {
-                int64_t k = fo[l];
                 ivec* os = &es[(int64_t)l * ni + i];
                 ivec* od = &ed[(int64_t)l * ni + i];
                 for (int64_t f = 0; f < cur.n; ++f) {
                     int32_t v = cur.p[f];
+                    /* NeighborSize: the layer's fanout, or with burning the
+                     * forest fire count capped by it (64 for "all") */
+                    int64_t k = fo[l];
+                    if (burn)
+                        k = orc_burn_count(rng_seed, (uint32_t)inst_id, (uint32_t)l, (uint32_t)v, burn,
+                                           k < 0 ? ORC_BURN_CAP_ALL : (int32_t)k);
                     int64_t d = deg(&g, v), beg = rowptr[v];
                     if (d > bcap) {
                         bcap = d; b = (uint32_t*)realloc(b, (size_t)bcap * sizeof(uint32_t));
