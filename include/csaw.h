@@ -169,6 +169,14 @@ typedef struct {
                                      default), 1..CSAW_ROUNDS, or CSAW_DIRECT_ONLY.
                                      Every value samples the same law; the edges
                                      differ (other draws are used)                */
+    uint32_t burn_threshold;      /* forest fire sampling (Section II-A): 0 = off;
+                                     else each frontier vertex v takes
+                                     NeighborSize = min(G, fanout) (64 for a
+                                     fanout of -1), G geometric with
+                                     P(G >= j) = (burn_threshold / 2^32)^j, from
+                                     Philox trials with counter (instance id,
+                                     layer, v, 0xFFFE << 16 | j / 4), word j mod 4:
+                                     trial j burns iff the word < burn_threshold   */
 } csaw_sample_args;
 
 typedef struct {

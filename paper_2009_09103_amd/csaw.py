@@ -40,7 +40,8 @@ class SampleArgs(ctypes.Structure):
                 ("num_layers", ctypes.c_int32), ("fanouts", ctypes.c_void_p),
                 ("fanout_stride", ctypes.c_int32), ("bias_kind", ctypes.c_int32),
                 ("bias_kinds", ctypes.c_void_p), ("rng_seed", ctypes.c_uint64),
-                ("instance_ids", ctypes.c_void_p), ("rng_seeds", ctypes.c_void_p), ("rounds", ctypes.c_int32)]
+                ("instance_ids", ctypes.c_void_p), ("rng_seeds", ctypes.c_void_p), ("rounds", ctypes.c_int32),
+                ("burn_threshold", ctypes.c_uint32)]
 
 
 class SampleOut(ctypes.Structure):
@@ -210,7 +211,7 @@ class Graph:
 
     # -------------------------------------------------------------- sampling
     def _sample_args(self, seed_offsets, seeds_dev, fanouts, bias, rng_seed, instance_base,
-                     instance_ids=None, rng_seeds=None, rounds=0):
+                     instance_ids=None, rng_seeds=None, rounds=0, burn=0):
         so = np.ascontiguousarray(seed_offsets, dtype=np.int64)
         fo = np.ascontiguousarray(fanouts, dtype=np.int32)
         ni = len(so) - 1
@@ -237,6 +238,7 @@ class Graph:
             a.bias_kind = _bias_code(bias)
         a.rng_seed = int(rng_seed)
         a.rounds = int(rounds)
+        a.burn_threshold = int(burn)
         a.instance_ids = None
         a.rng_seeds = None
         if instance_ids is not None:
@@ -258,14 +260,15 @@ class Graph:
         return mx.value
 
     def sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
-               capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, rounds=0) -> SampleResult:
+               capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, rounds=0,
+               burn=0) -> SampleResult:
         """Neighbor sampling (csaw_sample). ``seeds`` may be a device tensor
         (used in place) or host data (copied). ``out`` may pass preallocated
         (src, dst, offsets) device tensors. ``rounds``: 0 (default, 8), 1..8,
-        or DIRECT_ONLY."""
+        or DIRECT_ONLY. ``burn``: forest fire threshold over [0, 2^32)."""
         return self._run_sample(lambda a, o: lib.csaw_sample(self._h, a, o, _stream(stream)), seed_offsets, seeds,
                                 fanouts, bias, rng_seed, instance_base, capacity, out, instance_ids, rng_seeds,
-                                rounds)
+                                rounds, burn)
 
     def autotune_sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
                         capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, reps=3, rounds=0):
@@ -290,10 +293,10 @@ class Graph:
         return t.bound16, t.bound32
 
     def _run_sample(self, call, seed_offsets, seeds, fanouts, bias, rng_seed, instance_base, capacity, out,
-                    instance_ids, rng_seeds, rounds=0) -> SampleResult:
+                    instance_ids, rng_seeds, rounds=0, burn=0) -> SampleResult:
         seeds_dev = _dev_i32(seeds, self.device)
         a, keep, ni, L = self._sample_args(seed_offsets, seeds_dev, fanouts, bias, rng_seed,
-                                           instance_base, instance_ids, rng_seeds, rounds)
+                                           instance_base, instance_ids, rng_seeds, rounds, burn)
         if out is None:
             if capacity is None:
                 mx = ctypes.c_int64()

@@ -35,6 +35,25 @@ __device__ __forceinline__ uint64_t philox_u64(uint32_t k0, uint32_t k1, uint32_
     return (uint64_t)c0 | ((uint64_t)c1 << 32);
 }
 
+// All four output words of Philox4x32-10 (same rounds as philox_u64).
+__device__ __forceinline__ uint4 philox4(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                                         uint32_t c3) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
 // floor(u * W / 2^64)
 __device__ __forceinline__ uint64_t range_reduce(uint64_t u, uint64_t W) { return __umul64hi(u, W); }
 

@@ -10,6 +10,8 @@ namespace csaw {
 constexpr int kMaxLayers = 16;
 constexpr int kMaxDrawFanout = 64;   // slots of one wave
 constexpr int kDefaultRounds = 8;    // repeated-sampling rounds before the direct draws
+constexpr uint32_t kBurnRound = 0xFFFEu;  // counter word 3 (high half) of the forest fire trials
+constexpr int32_t kBurnCapAll = 64;       // burning cap of a fanout of -1
 constexpr int kChunk = 1024;         // weights per chunk of a long list
 constexpr int kChunkGroups = 64;     // 16-weight groups per chunk
 constexpr int32_t kWideList = (int32_t)0x80000000u;  // ppos flag: the list's total weight is >= 2^32
@@ -63,6 +65,9 @@ struct FrontierBuild {
     int32_t num_instances;
     const int32_t* fanout;           // [ni] fanout of this layer
     const int32_t* bias;             // [ni]
+    const uint32_t* inst_id;         // [ni] instance id mod 2^32 (forest fire counters)
+    const uint64_t* inst_key;        // [ni] Philox key per instance
+    uint32_t burn;                   // forest fire threshold (0: fixed fanout)
     int32_t* fv;
     int32_t* fi;
     int32_t* cnt;
@@ -102,6 +107,7 @@ struct SampleLayer {
     int64_t nwp;                     // bitmap words per instance (multiple of 4)
     int32_t group16, group32;        // sub-wave bucket bounds (<= 16, <= 32; 0 = off)
     int32_t rounds;                  // repeated-sampling rounds (0: every slot by direct draw)
+    uint32_t burn;                   // forest fire threshold (0: fixed fanout)
 };
 
 constexpr int32_t kDefaultBound16 = 16, kDefaultBound32 = 32;

@@ -609,6 +609,9 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         fb.num_layers = L;
         fb.num_instances = ni;
         fb.bias = d_bias;
+        fb.inst_id = (const uint32_t*)(A + o_tab + t_iid);
+        fb.inst_key = (const uint64_t*)(A + o_tab + t_key);
+        fb.burn = a->burn_threshold;
         fb.cnt = d_cnt;
         fb.off = d_off;
         fb.fbeg = (int64_t*)(A + o_fbeg);
@@ -652,6 +655,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         p.group16 = b16;
         p.group32 = b32;
         p.rounds = P.rounds;
+        p.burn = a->burn_threshold;
         int computed_layers = 1;  // frontiers F_0 .. F_{computed_layers-1} exist
         for (int32_t l = 0; l < L; ++l) {
             p.layer = l;
@@ -717,7 +721,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
                                         (int64_t)(intptr_t)out->src, (int64_t)(intptr_t)out->dst,
                                         (int64_t)(intptr_t)out->offsets, (int64_t)(intptr_t)ws->arena,
                                         (int64_t)(intptr_t)ws->bitmaps, (int64_t)(intptr_t)ws->pinned,
-                                        (int64_t)big_path, b16, b32, P.rounds};
+                                        (int64_t)big_path, b16, b32, P.rounds, (int64_t)a->burn_threshold};
             key.insert(key.end(), P.fcap.begin(), P.fcap.end());
             hipGraphExec_t exec = ws->find_graph(key);
             if (!exec) {

@@ -109,6 +109,36 @@ __device__ __forceinline__ int route_of(int32_t kind, int32_t k, int32_t P, int6
     return kRouteBig;
 }
 
+// Forest fire NeighborSize (Section II-A): vertex v burns G neighbors, G
+// geometric with P(G >= j) = (burn / 2^32)^j, capped at cap. Trial j
+// succeeds iff word j mod 4 of the Philox block with counter
+// (c0, c1, c2, kBurnRound << 16 | j / 4) is below burn.
+__device__ __forceinline__ int32_t burn_count(Key key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t burn,
+                                              int32_t cap) {
+    int32_t g = 0;
+    for (uint32_t blk = 0; g < cap; ++blk) {
+        const uint4 x = philox4(key.k0, key.k1, c0, c1, c2, (kBurnRound << 16) | blk);
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (g >= cap || w[q] >= burn) return g;
+            ++g;
+        }
+    }
+    return g;
+}
+
+// NeighborSize of frontier vertex v of an instance with layer fanout k. The
+// kernels that call it are instantiated with and without forest fire, so
+// the burning code costs the fixed-fanout kernels no registers.
+template <bool kBurn>
+__device__ __forceinline__ int32_t neighbor_size(int32_t k, uint32_t burn, uint64_t key, uint32_t c0,
+                                                 int32_t layer, int32_t v) {
+    if (!kBurn || !burn || k == 0) return k;
+    return burn_count(Key{(uint32_t)key, (uint32_t)(key >> 32)}, c0, (uint32_t)layer, (uint32_t)v, burn,
+                      k < 0 ? kBurnCapAll : k);
+}
+
 // Positive biases of v's list with the kWideList flag (the list length if
 // unbiased).
 __device__ __forceinline__ int32_t positive_info(const GraphDev& g, int32_t kind, int32_t v, int64_t d) {
@@ -208,7 +238,7 @@ __device__ __forceinline__ void block_excl_scan4(int64_t (&x)[4], int64_t (&tot)
 // sets visited |= next, clears next, and the first word of an instance writes
 // that instance's segment offset. The last block writes the layer's totals
 // and the output base of the next layer.
-template <int G, int V>
+template <int G, int V, bool kBurn>
 __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     static_assert(V == 1 || V == 4, "one word or one 16-byte group per load");
     __shared__ int64_t s_base_e, s_base_g;
@@ -250,6 +280,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     {
         int64_t inst_k = -1;
         int32_t k = 0, kind = 0;
+        uint64_t key = 0;
+        uint32_t iid = 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
 #pragma unroll
@@ -262,6 +294,10 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                     inst_k = inst;
                     k = fb.fanout[inst];
                     kind = fb.bias[inst];
+                    if (kBurn) {
+                        key = fb.inst_key[inst];
+                        iid = fb.inst_id[inst];
+                    }
                 }
                 const int32_t vbase = (int32_t)((iw - inst * fb.nwp) * 32);
                 cnt4[0] += __popc(w);
@@ -276,7 +312,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                         int64_t beg = 0, d = 0;
                         int32_t c = 0;
                         if (bv[t] >= 0) {
-                            c = entry_count(fb.g, k, kind, vbase + bv[t], route, beg, d, pinfo, fb.ctl);
+                            const int32_t kv = neighbor_size<kBurn>(k, fb.burn, key, iid, fb.layer, vbase + bv[t]);
+                            c = entry_count(fb.g, kv, kind, vbase + bv[t], route, beg, d, pinfo, fb.ctl);
                             cnt4[1] += c;
                             if (route == kRouteBig) ++cnt4[2];
                         }
@@ -358,6 +395,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     int64_t eoff = s_base_g + ex_g;
     int64_t inst_k = -1;
     int32_t k = 0, kind = 0;
+    uint64_t key = 0;
+    uint32_t iid = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int64_t iw4 = w0 + V * g;
@@ -396,6 +435,10 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                 inst_k = inst;
                 k = fb.fanout[inst];
                 kind = fb.bias[inst];
+                if (kBurn) {
+                    key = fb.inst_key[inst];
+                    iid = fb.inst_id[inst];
+                }
             }
             const int32_t vbase = (int32_t)(local * 32);
             uint32_t bits = w;
@@ -409,7 +452,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
                     const int32_t v = vbase + bv[t];
                     int32_t route, c, pinfo;
                     int64_t beg, d;
-                    c = entry_count(fb.g, k, kind, v, route, beg, d, pinfo, fb.ctl);
+                    c = entry_count(fb.g, neighbor_size<kBurn>(k, fb.burn, key, iid, fb.layer, v), kind, v, route, beg, d,
+                                    pinfo, fb.ctl);
                     fb.fv[pos] = v;
                     fb.fi[pos] = (int32_t)inst;
                     fb.cnt[pos] = c;
@@ -745,6 +789,7 @@ struct EntryRun {
     uint64_t key;
 };
 
+template <bool kBurn>
 __device__ __forceinline__ void load_run(const SampleLayer& p, int64_t e, bool valid, int64_t out_base,
                                          EntryRun& R) {
     R.c = valid ? p.cnt[e] : 0;
@@ -763,6 +808,7 @@ __device__ __forceinline__ void load_run(const SampleLayer& p, int64_t e, bool v
         R.do_claim = p.fanout_next[R.inst] != 0;
         R.key = p.inst_key[R.inst];
         R.c0 = p.inst_id[R.inst];
+        R.k = neighbor_size<kBurn>(R.k, p.burn, R.key, (uint32_t)R.c0, p.layer, R.v);
     }
 }
 
@@ -1080,6 +1126,7 @@ __device__ void select_entry_small_draw(const SampleLayer& p, const EntryInfo& E
 // Sub-wave entries of the layer: each wavefront takes runs of 64 frontier
 // entries (grid-stride), keeps the run in LDS and serves its small entries
 // in groups of 16 and 32 lanes; the other entries are left to k_select.
+template <bool kBurn>
 __global__ void __launch_bounds__(kBlock, 6) k_select_small(SampleLayer p) {
     __shared__ RunLds runs[kWavesPerBlock];
     const int wid = uniform_i32(threadIdx.x / kWave);
@@ -1093,7 +1140,7 @@ __global__ void __launch_bounds__(kBlock, 6) k_select_small(SampleLayer p) {
         uint64_t e16, e32;
         {
             EntryRun R;
-            load_run(p, e0 + lane, lane < n, out_base, R);
+            load_run<kBurn>(p, e0 + lane, lane < n, out_base, R);
             e16 = p.group16 > 0 ? ballot(lane < n && group_fits(R, p.capacity, p.group16)) : 0ull;
             e32 = p.group32 > 0 ? ballot(lane < n && group_fits(R, p.capacity, p.group32)) & ~e16 : 0ull;
             store_run(L, R, lane);
@@ -1110,6 +1157,7 @@ __global__ void __launch_bounds__(kBlock, 6) k_select_small(SampleLayer p) {
 // Each wavefront takes a contiguous share of the frontier (a short run when
 // the grid has more wavefronts than resident slots), loaded 64 entries at a
 // time; entries of the sub-wave buckets are skipped (k_select_small).
+template <bool kBurn>
 __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
     const int wid = uniform_i32(threadIdx.x / kWave);
     const int lane = lane_id();
@@ -1124,7 +1172,7 @@ __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
     for (int64_t e0 = lo; e0 < hi; e0 += kWave) {
         const int n = (int)(hi - e0 < kWave ? hi - e0 : kWave);
         EntryRun R;
-        load_run(p, e0 + lane, lane < n, out_base, R);
+        load_run<kBurn>(p, e0 + lane, lane < n, out_base, R);
         uint64_t todo = ballot(lane < n && R.c != 0 && !(bound > 0 && group_fits(R, p.capacity, bound)));
         for (; todo; todo &= todo - 1) select_entry(p, run_entry(R, __ffsll((unsigned long long)todo) - 1));
     }
@@ -1295,6 +1343,7 @@ __device__ void select_big_entry(const SampleLayer& p, const EntryInfo& E, uint6
     wave_lds_sync();  // the table is rewritten by the wave's next list
 }
 
+template <bool kBurn>
 __global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
     __shared__ uint64_t tabs[kWavesPerBlock][kBigTab + 1];
     const int wid = uniform_i32(threadIdx.x / kWave);
@@ -1311,7 +1360,7 @@ __global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
         const bool valid = lane < n;
         const int64_t pos = valid ? p.bigs[h0 + lane] : 0;
         EntryRun R;
-        load_run(p, pos, valid, out_base, R);
+        load_run<kBurn>(p, pos, valid, out_base, R);
         for (int j = 0; j < n; ++j) select_big_entry(p, run_entry(R, j), tabs[wid]);
     }
 }
@@ -1383,18 +1432,21 @@ int64_t frontier_build_blocks(int64_t words) {
 }
 
 void launch_frontier_build(const FrontierBuild& fb, hipStream_t s, LaunchEvents ev) {
-    if (frontier_build_words(fb.nwords) == 16)
-        launch_kernel(k_frontier_build<4, 4>, dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
+    const bool wide = frontier_build_words(fb.nwords) == 16;
+    if (fb.burn)
+        launch_kernel(wide ? k_frontier_build<4, 4, true> : k_frontier_build<1, 1, true>, dim3((unsigned)fb.nb),
+                      dim3(kBlock), s, ev, fb);
     else
-        launch_kernel(k_frontier_build<1, 1>, dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
+        launch_kernel(wide ? k_frontier_build<4, 4, false> : k_frontier_build<1, 1, false>, dim3((unsigned)fb.nb),
+                      dim3(kBlock), s, ev, fb);
 }
 
 void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
-    launch_kernel(k_select, dim3(grid), dim3(kBlock), s, ev, p);
+    launch_kernel(p.burn ? k_select<true> : k_select<false>, dim3(grid), dim3(kBlock), s, ev, p);
 }
 
 void launch_select_small(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
-    launch_kernel(k_select_small, dim3(grid), dim3(kBlock), s, ev, p);
+    launch_kernel(p.burn ? k_select_small<true> : k_select_small<false>, dim3(grid), dim3(kBlock), s, ev, p);
 }
 
 int64_t chunk_table_rows(int64_t m) { return (m >> kTabShift) + 1; }
@@ -1406,7 +1458,7 @@ void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uin
 }
 
 void launch_select_big(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
-    launch_kernel(k_select_big, dim3(grid), dim3(kBlock), s, ev, p);
+    launch_kernel(p.burn ? k_select_big<true> : k_select_big<false>, dim3(grid), dim3(kBlock), s, ev, p);
 }
 
 void launch_clear_visited(const ClearVisited& c, hipStream_t s, LaunchEvents ev) {

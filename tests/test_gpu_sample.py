@@ -471,3 +471,24 @@ def test_rounds_and_direct_only(csaw, rounds):
         g.sample(offs, seeds, [10], 0, rounds=9)
     with pytest.raises(csaw.CsawError):
         g.sample(offs, seeds, [10], 0, rounds=-2)
+
+
+@pytest.mark.parametrize("burn", [int(0.7 * 2 ** 32), 2 ** 31, 2 ** 32 - 1, 1])
+def test_forest_fire(csaw, burn):
+    """Forest fire sampling: each frontier vertex's NeighborSize is its burn
+    count capped by the fanout (64 for -1), on every route (sub-wave groups,
+    wavefront, long lists), all bias kinds, against the oracle."""
+    rp, col = small_list_graph(4000, [0, 1, 3, 8, 20, 40, 90, 300, 900, 2000], 81)
+    rng = inputs.rng(82)
+    ew = rng.integers(0, 7, size=len(col)).astype(np.uint32) ** 3
+    offs, seeds = inputs.batched_instances(rp, col, 30, 83)[:2]
+    g = csaw.Graph(rp, col, ew)
+    bias = [0, 1, 2] * 10
+    for fo in ([10, 5], [40, -1, 3]):
+        say("forest fire burn=%d fanouts=%s" % (burn, fo))
+        res = g.sample(offs, seeds, fo, bias, rng_seed=91, burn=burn)
+        ref = oracle.sample(rp, col, ew, offs, seeds, fo, bias_kinds=np.asarray(bias, dtype=np.int32),
+                            rng_seed=91, burn=burn)
+        assert_same(res, ref)
+    if burn == 1:
+        assert ref.num_edges == 0
