@@ -2,7 +2,7 @@
 """Benchmark of the biased neighbor-selection hot path on one MI355X.
 
 A step is one full csaw_sample call (every layer: frontier build, select,
-long-list pass) over the degree-biased workload: R-MAT 22 (edge factor 16),
+long-list search) over the degree-biased workload: R-MAT 22 (edge factor 16),
 one instance of 8,192 distinct seeds, fanouts [25, 10, 5], bias = out-degree
 of the neighbor, Philox seeds cycling over {1, 2, 3}. Inputs (graph, seeds,
 output buffers) are resident in HBM before timing starts.
@@ -11,9 +11,12 @@ Prints one JSON line: SEPS (sampled edges per second), the roofline of the
 dominant kernel (select) from HIP-event kernel times and the algorithmic byte
 model, and the CPU oracle timed on the host.
 
+The sub-wave bucket setting is autotuned on the timed call first (--tuning).
+
 Other workloads (--workload): batched (4,096 instances in one call against
 4,096 plain calls), node2vec (R-MAT 24 walks), mdrw (multi-dimensional
-random walks), copy (a 1 GiB device copy, the HBM counter calibration).
+random walks), forest_fire (burning probability 0.7, depth 2), copy (a 1 GiB
+device copy, the HBM counter calibration).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -415,6 +418,75 @@ def bench_served(args):
     }
 
 
+def bench_forest_fire(args):
+    """Forest fire sampling at the paper's setting (burning probability 0.7,
+    depth 2, unbiased) on the R-MAT 22 graph, 8,192 seeds in one instance;
+    the fanout -1 caps each burn count at 64."""
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    rec = inputs.DEGREE_BIASED
+    log("generating R-MAT %d graph" % rec["scale"])
+    rp, col = inputs.graph_for(rec)
+    offs, seeds = inputs.single_instance_seeds(rp, col, rec["num_seeds"], rec["seed_rng"])
+    g = csaw.Graph(rp, col)
+    dev = g.device
+    fan = np.array([-1, -1], dtype=np.int32)
+    burn = int(0.7 * 2 ** 32)
+    seeds_d = torch.from_numpy(seeds).to(dev)
+    cap = g.sample_bound(offs, fan, csaw.UNIFORM)
+    src = torch.empty(cap, dtype=torch.int32, device=dev)
+    dst = torch.empty(cap, dtype=torch.int32, device=dev)
+    offsets = torch.empty(len(fan) + 1, dtype=torch.int64, device=dev)
+    call = dict(rng_seed=1, burn=burn, rounds=args.rounds, out=(src, dst, offsets))
+    tuning = apply_tuning(g, args, offs, seeds_d, fan, csaw.UNIFORM, **call)
+    r = g.sample(offs, seeds_d, fan, csaw.UNIFORM, **call)
+    edges = r.num_edges
+    # per layer: frontier entries (24 B each: entry + row offsets) and edges (12 B each)
+    o = offsets.cpu().numpy()
+    d_host = dst[:edges].cpu().numpy()
+    visited = np.unique(seeds)
+    frontier = visited
+    alg = 0.0
+    for l in range(len(fan)):
+        alg += 24.0 * len(frontier) + 12.0 * (o[l + 1] - o[l])
+        nxt = np.setdiff1d(np.unique(d_host[o[l]:o[l + 1]]), visited, assume_unique=True)
+        visited = np.union1d(visited, nxt)
+        frontier = nxt
+    for _ in range(args.warmup):
+        g.sample(offs, seeds_d, fan, csaw.UNIFORM, **call)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.sample(offs, seeds_d, fan, csaw.UNIFORM, **call)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    csaw.profile_reset()
+    csaw.profile_enable(True)
+    for _ in range(args.steps):
+        g.sample(offs, seeds_d, fan, csaw.UNIFORM, **call)
+    torch.cuda.synchronize()
+    times = {k: csaw.profile_read(k) for k in ("frontier_init", "select_small", "select_wave", "select_big",
+                                                "frontier_build", "visited_clear")}
+    csaw.profile_enable(False)
+    csaw.profile_reset()
+    sel_ms = (times["select_small"][0] + times["select_wave"][0]) / args.steps
+    achieved = alg / (sel_ms / 1e3) / 1e9 if sel_ms > 0 else 0.0
+    return {
+        "metric": "sampled edges/sec (SEPS), forest fire sampling",
+        "value": edges / dt, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": "forest_fire_rmat22", "seeds": int(len(seeds)), "burning_probability": 0.7,
+                   "depth": 2, "cap": 64, "edges_per_step": int(edges), "tuning": tuning},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "select_small + select_wave (k_select_small, k_select)",
+                     "ms_per_step": sel_ms, "alg_bytes_per_step": alg},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in times.items()},
+    }
+
+
 def bench_mdrw(args):
     """Multi-dimensional random walks at the paper's setting (2,000
     instances, frontier pools of 2,000 vertices, 1,703 sampled edges each) on
@@ -628,6 +700,8 @@ def main():
         sys.exit(3)
     elif args.workload == "node2vec":
         line = bench_node2vec(args)
+    elif args.workload == "forest_fire":
+        line = bench_forest_fire(args)
     elif args.workload == "mdrw":
         line = bench_mdrw(args)
     elif args.workload == "copy":

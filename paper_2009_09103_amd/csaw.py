@@ -271,7 +271,8 @@ class Graph:
                                 rounds, burn)
 
     def autotune_sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
-                        capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, reps=3, rounds=0):
+                        capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, reps=3, rounds=0,
+                        burn=0):
         """Autotuner (csaw_autotune_sample): times the call under each
         sub-wave bucket setting, keeps the fastest on the graph. Returns
         (SampleResult, (bound16, bound32))."""
@@ -279,7 +280,7 @@ class Graph:
         res = self._run_sample(lambda a, o: lib.csaw_autotune_sample(self._h, a, o, int(reps), _stream(stream),
                                                                      ctypes.byref(t)),
                                seed_offsets, seeds, fanouts, bias, rng_seed, instance_base, capacity, out,
-                               instance_ids, rng_seeds, rounds)
+                               instance_ids, rng_seeds, rounds, burn)
         return res, (t.bound16, t.bound32)
 
     def set_tuning(self, bound16: int, bound32: int):
