@@ -39,7 +39,7 @@ _LIB = os.path.join(_HERE, "libcsaw_oracle.so")
 _lock = threading.Lock()
 _lib = None
 
-UNIFORM, EDGE_WEIGHT, NEIGHBOR_DEGREE, NODE2VEC = 0, 1, 2, 3
+UNIFORM, EDGE_WEIGHT, NEIGHBOR_DEGREE, NODE2VEC, METROPOLIS = 0, 1, 2, 3, 4
 FANOUT_ALL = -1
 DEFAULT_ROUNDS = 8   # repeated-sampling rounds before the direct draw
 

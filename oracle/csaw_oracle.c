@@ -28,7 +28,8 @@
  *     (fig:brs(b)).
  *   - The generic sampling loop of fig:api(b): GatherNeighbors, EdgeBias,
  *     Select(NeighborSize), Update (visited filter), Sampled append.
- *   - Random walks (Section II-A): first-order biased walks and node2vec.
+ *   - Random walks (Section II-A): first-order biased walks, node2vec and
+ *     the Metropolis-Hastings walk.
  *
  * Parity status of each function is listed in its comment ("pinned by").
  */
@@ -52,7 +53,7 @@
  *                    first step of a walk has no previous vertex and is
  *                    unbiased.
  * ------------------------------------------------------------------------- */
-enum { ORC_UNIFORM = 0, ORC_EDGE_WEIGHT = 1, ORC_NEIGHBOR_DEGREE = 2, ORC_NODE2VEC = 3 };
+enum { ORC_UNIFORM = 0, ORC_EDGE_WEIGHT = 1, ORC_NEIGHBOR_DEGREE = 2, ORC_NODE2VEC = 3, ORC_METROPOLIS = 4 };
 
 /* Round index reserved for the exact conditional draw. */
 #define ORC_FALLBACK_ROUND 0xFFFFu
@@ -542,6 +543,12 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
  * with counter (wid, s, v, 3); either move is a step and forgets the
  * previous vertex (the next node2vec step is unbiased). Otherwise the step is
  * the one above, including the stop at a dead end.
+ * METROPOLIS (Section II-A names the Metropolis-Hastings random walk among
+ * the unbiased walks; the rule is the standard one that makes the uniform
+ * distribution over vertices stationary): the drawn neighbor u is a uniform
+ * proposal, accepted iff x * deg(u) < deg(v) * 2^32 for x in [0, 2^32) drawn
+ * with counter (wid, s, v, 4), i.e. with probability min(1, deg(v)/deg(u));
+ * a rejected proposal is a step that stays at v.
  *
  * paths: int32[nw * (length+1)], walker-major. steps (nullable): int64[nw],
  * number of steps taken. stats (nullable, double[2]): algorithmic bytes,
@@ -557,7 +564,7 @@ int32_t orc_walk(int64_t n, const int64_t* rowptr, const int32_t* col, const uin
     if (length < 0 || nw < 0) return 1;
     if ((uint64_t)restart_threshold + (uint64_t)jump_threshold > ((uint64_t)1 << 32)) return 1;
     if (jump_threshold && n == 0) return 1;
-    if (bias_kind < ORC_UNIFORM || bias_kind > ORC_NODE2VEC) return 1;
+    if (bias_kind < ORC_UNIFORM || bias_kind > ORC_METROPOLIS) return 1;
     if (bias_kind == ORC_EDGE_WEIGHT && !ew) return 1;
     for (int64_t w = 0; w < nw; ++w)
         if (starts[w] < 0 || starts[w] >= n) return 1;
@@ -613,6 +620,9 @@ int32_t orc_walk(int64_t n, const int64_t* rowptr, const int32_t* col, const uin
                         bytes += 4.0 * (double)deg(&g, t);
                     }
                     bytes += 4.0 * (double)d;
+                } else if (bias_kind == ORC_METROPOLIS) {
+                    for (int64_t i = 0; i < d; ++i) b[i] = 1;   /* uniform proposal */
+                    bytes += 4.0 + 16.0;
                 } else {
                     edge_bias_static(&g, bias_kind, v, b);
                     if (bias_kind == ORC_UNIFORM) bytes += 4.0;
@@ -623,6 +633,14 @@ int32_t orc_walk(int64_t n, const int64_t* rowptr, const int32_t* col, const uin
                 uint64_t r = orc_draw(rng_seed, (uint32_t)wid, (uint32_t)s, (uint32_t)v, 0u, S[d]);
                 int64_t m = orc_its(S, d, r);
                 int64_t u = col[beg + m];
+                if (bias_kind == ORC_METROPOLIS) {
+                    /* accept u with probability min(1, deg(v) / deg(u)):
+                     * x / 2^32 < d / deg(u), compared exactly in integers;
+                     * a rejected proposal is a step that stays at v */
+                    const uint64_t x = orc_draw(rng_seed, (uint32_t)wid, (uint32_t)s, (uint32_t)v, 4u,
+                                                (uint64_t)1 << 32);
+                    if (x * (uint64_t)deg(&g, u) >= ((uint64_t)d << 32)) u = v;
+                }
                 path[s + 1] = (int32_t)u;
                 t = v;
                 v = u;

@@ -251,3 +251,87 @@ def test_restart_jump_draw_layout(kind):
             t, v = v, int(nb[m])
             assert paths[w, s + 1] == v
     assert moves > 3
+
+
+def mh_matrix(rp, col):
+    """Metropolis-Hastings transition matrix: propose a uniform neighbor u of
+    v, move with probability min(1, deg(v)/deg(u)), else stay; state n =
+    stopped (no neighbor)."""
+    n = len(rp) - 1
+    deg = np.diff(rp).astype(np.float64)
+    P = np.zeros((n + 1, n + 1))
+    for v in range(n):
+        if deg[v] == 0:
+            P[v, n] = 1.0
+            continue
+        for u in col[rp[v]:rp[v + 1]]:
+            a = min(1.0, deg[v] / deg[u]) if deg[u] > 0 else 1.0
+            P[v, u] += a / deg[v]
+            P[v, v] += (1 - a) / deg[v]
+    P[n, n] = 1.0
+    return P
+
+
+def test_metropolis_hastings_t_step_law():
+    """Exact t-step law of the Metropolis-Hastings walk (uniform proposals,
+    acceptance min(1, deg(v)/deg(u)), a rejection stays), on a directed
+    graph with sinks and on an undirected one."""
+    for directed in (True, False):
+        rp, col = small_graph(seed=6, n=9, m=19, directed=directed)
+        n = len(rp) - 1
+        start = int(np.argmin(np.where(np.diff(rp) > 0, np.diff(rp), 99)))
+        T = 4
+        paths, steps, _ = oracle.walk(rp, col, None, np.full(NW, start, dtype=np.int32), T,
+                                      bias_kind=oracle.METROPOLIS, rng_seed=17)
+        P = mh_matrix(rp, col)
+        p = np.zeros(n + 1)
+        p[start] = 1
+        for t in range(1, T + 1):
+            p = p @ P
+            pos = paths[:, t]
+            compare(np.bincount(np.where(pos < 0, n, pos), minlength=n + 1), p)
+        assert np.all((paths[:, 1:] >= 0).sum(axis=1) == steps)
+
+
+def test_metropolis_hastings_stationary_uniform():
+    """On a connected undirected graph with unequal degrees the walk's visit
+    frequencies converge to the uniform distribution over vertices (not to
+    deg(v)/2|E| as for the simple walk)."""
+    G = nx.connected_watts_strogatz_graph(30, 4, 0.5, seed=8)
+    G.add_edges_from([(0, j) for j in range(2, 20)])
+    assert nx.is_connected(G)
+    edges = list(G.edges()) + [(v, u) for u, v in G.edges()]
+    rp, col = inputs.csr_from_edges(30, edges)
+    deg = np.diff(rp)
+    assert deg.max() > 4 * deg.min()
+    paths, _, _ = oracle.walk(rp, col, None, np.zeros(2000, dtype=np.int32), 600, bias_kind=oracle.METROPOLIS,
+                              rng_seed=7)
+    visits = np.bincount(paths[:, 150:].ravel(), minlength=30).astype(np.float64)
+    freq = visits / visits.sum()
+    assert 0.5 * np.abs(freq - 1.0 / 30).sum() < 0.03
+    assert 0.5 * np.abs(freq - deg / deg.sum()).sum() > 0.1
+
+
+def test_metropolis_hastings_draw_layout():
+    """Proposal with counter (walker id, step, v, 0) over [0, deg v),
+    acceptance word with counter (walker id, step, v, 4) over [0, 2^32):
+    replayed with the independent Philox."""
+    from tests.helpers import torch_philox
+    rp, col = inputs.rmat_csr(9, 4096, 12, symmetrize=True)
+    starts = inputs.walker_starts(rp, col, 6, 3)
+    deg = np.diff(rp)
+    paths, _, _ = oracle.walk(rp, col, None, starts, 6, bias_kind=oracle.METROPOLIS, rng_seed=321,
+                              walker_base=50)
+    stays = 0
+    for w in range(6):
+        v = int(starts[w])
+        for s in range(6):
+            m = torch_philox.draw(321, [50 + w, s, v, 0], int(deg[v]))
+            u = int(col[rp[v] + m])
+            x = torch_philox.draw(321, [50 + w, s, v, 4], 2 ** 32)
+            if x * int(deg[u]) >= int(deg[v]) << 32:
+                u = v
+                stays += 1
+            assert paths[w, s + 1] == u
+            v = u
+    assert stays > 0
