@@ -79,7 +79,13 @@ typedef enum {
     CSAW_BIAS_UNIFORM = 0,
     CSAW_BIAS_EDGE_WEIGHT = 1,
     CSAW_BIAS_NEIGHBOR_DEGREE = 2,
-    CSAW_BIAS_NODE2VEC = 3
+    CSAW_BIAS_NODE2VEC = 3,
+    /* walks only: the Metropolis-Hastings random walk (Section II-A). A
+     * uniform neighbor u of v is proposed (counter word 3 = 0) and accepted
+     * iff x * deg(u) < deg(v) * 2^32, x in [0, 2^32) drawn with counter
+     * (walker id, step, v, 4); a rejected proposal is a step that stays at v.
+     * The uniform distribution over vertices is stationary. */
+    CSAW_BIAS_METROPOLIS_HASTINGS = 4
 } csaw_bias_kind;
 
 /* Fanout value meaning "every neighbor with a positive bias" (snowball). */
@@ -155,7 +161,7 @@ typedef struct {
                                      values above CSAW_MAX_FANOUT are UNSUPPORTED
                                      when they would need a draw                  */
     int32_t fanout_stride;        /* 0, or >= num_layers                          */
-    int32_t bias_kind;            /* csaw_bias_kind (not NODE2VEC), used when
+    int32_t bias_kind;            /* UNIFORM, EDGE_WEIGHT or NEIGHBOR_DEGREE, used when
                                      bias_kinds is NULL                           */
     const int32_t* bias_kinds;    /* HOST int32[num_instances] or NULL            */
     uint64_t rng_seed;            /* Philox key, used when rng_seeds is NULL      */

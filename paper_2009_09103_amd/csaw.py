@@ -15,7 +15,7 @@ import torch  # loads the HIP runtime that libcsaw then shares
 
 from . import _build
 
-UNIFORM, EDGE_WEIGHT, NEIGHBOR_DEGREE, NODE2VEC = 0, 1, 2, 3
+UNIFORM, EDGE_WEIGHT, NEIGHBOR_DEGREE, NODE2VEC, METROPOLIS_HASTINGS = 0, 1, 2, 3, 4
 DIRECT_ONLY = -1  # csaw_sample_args.rounds: no repeated-sampling rounds
 FANOUT_ALL = -1
 MAX_FANOUT = 64
@@ -23,7 +23,7 @@ MAX_LAYERS = 16
 ROUNDS = 8
 
 _BIAS_NAMES = {"uniform": UNIFORM, "edge_weight": EDGE_WEIGHT, "neighbor_degree": NEIGHBOR_DEGREE,
-               "node2vec": NODE2VEC}
+               "node2vec": NODE2VEC, "metropolis_hastings": METROPOLIS_HASTINGS}
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "BUSY", 5: "NOT_READY",
           6: "UNSUPPORTED"}
 

@@ -16,7 +16,7 @@ constexpr int kChunk = 1024;         // weights per chunk of a long list
 constexpr int kChunkGroups = 64;     // 16-weight groups per chunk
 constexpr int32_t kWideList = (int32_t)0x80000000u;  // ppos flag: the list's total weight is >= 2^32
 
-enum BiasKind : int32_t { kUniform = 0, kEdgeWeight = 1, kNeighborDegree = 2, kNode2vec = 3 };
+enum BiasKind : int32_t { kUniform = 0, kEdgeWeight = 1, kNeighborDegree = 2, kNode2vec = 3, kMetropolis = 4 };
 
 // Graph resident in HBM.
 struct GraphDev {

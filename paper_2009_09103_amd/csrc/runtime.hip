@@ -816,7 +816,7 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int
     t_err.clear();
     if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
     if (!a) return fail(CSAW_ERR_INVALID_ARG, "args is NULL");
-    if (a->bias_kind < kUniform || a->bias_kind > kNode2vec) return fail(CSAW_ERR_INVALID_ARG, "bad bias kind");
+    if (a->bias_kind < kUniform || a->bias_kind > kMetropolis) return fail(CSAW_ERR_INVALID_ARG, "bad bias kind");
     if (a->bias_kind == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
     if (a->bias_kind == kNode2vec && !g->sorted) return fail(CSAW_ERR_INVALID_ARG, "NODE2VEC needs sorted adjacency lists");
     if (a->num_walkers < 0 || a->length < 0) return fail(CSAW_ERR_INVALID_ARG, "negative num_walkers or length");

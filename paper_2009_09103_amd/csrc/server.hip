@@ -421,7 +421,7 @@ csaw_status csaw_server_submit(csaw_server s, const csaw_request* q, uint64_t* t
         r->mem = sample_request_mem(s, *r);
     } else if (q->kind == CSAW_REQUEST_WALK) {
         if (q->num_walkers < 0 || (q->num_walkers > 0 && !q->starts) || q->length < 0 || q->bias_kind < 0 ||
-            q->bias_kind > CSAW_BIAS_NODE2VEC) {
+            q->bias_kind > CSAW_BIAS_METROPOLIS_HASTINGS) {
             delete r;
             return CSAW_ERR_INVALID_ARG;
         }

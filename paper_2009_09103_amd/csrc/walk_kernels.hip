@@ -41,6 +41,10 @@ __device__ __forceinline__ bool walk_move(const WalkParams& p, Key key, uint32_t
     return false;
 }
 
+// kMH: Metropolis-Hastings (Section II-A): the uniform pick u is a proposal,
+// accepted iff x * deg(u) < deg(v) * 2^32 for x in [0, 2^32) drawn with
+// counter (walker id, step, v, 4); a rejected proposal is a step that stays.
+template <bool kMH>
 __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
     const Key key{p.k0, p.k1};
     const int64_t L1 = (int64_t)p.length + 1;
@@ -70,7 +74,14 @@ __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
                     const int64_t d = p.g.rowptr[v + 1] - beg;
                     if (d == 0) break;
                     const uint64_t r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, (uint64_t)d);
-                    v = p.g.col[beg + (int64_t)r];
+                    const int32_t u = p.g.col[beg + (int64_t)r];
+                    if (kMH) {
+                        const uint64_t du = (uint64_t)(p.g.rowptr[u + 1] - p.g.rowptr[u]);
+                        const uint64_t x = draw(key, c0, (uint32_t)s, (uint32_t)v, 4u, uint64_t(1) << 32);
+                        if (x * du < ((uint64_t)d << 32)) v = u;
+                    } else {
+                        v = u;
+                    }
                     path[s + 1] = v;
                 }
                 for (int64_t q = s + 1; q < L1; ++q) path[q] = -1;
@@ -504,10 +515,11 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev) 
     if (p.num_walkers <= 0) return;
     const bool flat_n2v = p.bias == kNode2vec && p.w_return == p.w_common && p.w_common == p.w_outward &&
                           p.w_return > 0;
-    if (p.bias == kUniform || flat_n2v) {
+    if (p.bias == kUniform || flat_n2v || p.bias == kMetropolis) {
         int64_t g = (p.num_walkers + kBlock - 1) / kBlock;
         if (g > grid) g = grid;
-        launch_kernel(k_walk_uniform, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+        if (p.bias == kMetropolis) launch_kernel(k_walk_uniform<true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+        else launch_kernel(k_walk_uniform<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
     } else {
         int64_t g = (p.num_walkers + kWavesPerBlock - 1) / kWavesPerBlock;
         if (g > grid) g = grid;

@@ -135,3 +135,24 @@ def test_restart_and_jump(csaw, bias, restart, jump):
     assert steps == int(rs.sum())
     with pytest.raises(csaw.CsawError):
         g.walk(starts[:4], 5, bias, restart=1 << 31, jump=(1 << 31) + 1)
+
+
+@pytest.mark.parametrize("restart,jump", [(0, 0), (1 << 29, 1 << 28)])
+def test_metropolis_hastings(csaw, restart, jump):
+    """Metropolis-Hastings walks (uniform proposals, acceptance min(1,
+    deg v / deg u), a rejection stays) on a directed R-MAT with sinks and on a
+    symmetrised one, with and without restart / jump moves, against the
+    oracle."""
+    for sym in (False, True):
+        rp, col = inputs.rmat_csr(14, 16 << 14, 25, symmetrize=sym)
+        starts = inputs.walker_starts(rp, col, 6000, 26)
+        g = csaw.Graph(rp, col)
+        say("metropolis-hastings sym=%s restart=%d jump=%d" % (sym, restart, jump))
+        paths, steps = g.walk(starts, 40, csaw.METROPOLIS_HASTINGS, rng_seed=27, walker_base=9,
+                              restart=restart, jump=jump)
+        ref, rs, _ = oracle.walk(rp, col, None, starts, 40, bias_kind=oracle.METROPOLIS, rng_seed=27,
+                                 walker_base=9, restart=restart, jump=jump)
+        p = paths.cpu().numpy()
+        np.testing.assert_array_equal(p, ref)
+        assert steps == int(rs.sum())
+        assert np.any(p[:, 1:] == p[:, :-1])        # some proposals were rejected
