@@ -15,8 +15,9 @@ The sub-wave bucket setting is autotuned on the timed call first (--tuning).
 
 Other workloads (--workload): batched (4,096 instances in one call against
 4,096 plain calls), node2vec (R-MAT 24 walks), mdrw (multi-dimensional
-random walks), forest_fire (burning probability 0.7, depth 2), copy (a 1 GiB
-device copy, the HBM counter calibration).
+random walks), forest_fire (burning probability 0.7, depth 2), metropolis
+(Metropolis-Hastings walks), copy (a 1 GiB device copy, the HBM counter
+calibration).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -487,6 +488,49 @@ def bench_forest_fire(args):
     }
 
 
+def bench_metropolis(args):
+    """Metropolis-Hastings walks on the symmetrised R-MAT 22 graph: 2^20
+    walkers from uniform starts, length 80."""
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    log("generating symmetrised R-MAT 22 graph")
+    rp, col = inputs.rmat_csr(22, 16 << 22, 22, symmetrize=True)
+    starts = torch.from_numpy(inputs.walker_starts(rp, col, 1 << 20, 2404)).to("cuda")
+    g = csaw.Graph(rp, col)
+    paths = torch.empty((1 << 20, 81), dtype=torch.int32, device=g.device)
+    for i in range(args.warmup):
+        g.walk(starts, 80, csaw.METROPOLIS_HASTINGS, rng_seed=1 + i % 3, paths=paths)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    for i in range(args.steps):
+        steps += g.walk(starts, 80, csaw.METROPOLIS_HASTINGS, rng_seed=1 + i % 3, paths=paths)[1]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    csaw.profile_reset()
+    csaw.profile_enable(True)
+    _, st = g.walk(starts, 80, csaw.METROPOLIS_HASTINGS, rng_seed=1, paths=paths)
+    torch.cuda.synchronize()
+    kms, kn = csaw.profile_read("walk")
+    csaw.profile_enable(False)
+    csaw.profile_reset()
+    # per step: v's row offsets (16), the proposal's id (4), its row offsets
+    # (16), the path entry (4)
+    alg = 40.0 * st
+    achieved = alg / (kms / 1e3) / 1e9 if kms > 0 else 0.0
+    return {
+        "metric": "walk steps/s, Metropolis-Hastings random walk",
+        "value": steps / args.steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 draws (integer)", "data": "synthetic",
+        "config": {"workload": "metropolis_hastings_rmat22_sym", "walkers": 1 << 20, "length": 80},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_walk_uniform<metropolis>",
+                     "launches": kn, "avg_launch_us": kms / max(kn, 1) * 1e3, "alg_bytes_per_launch": alg},
+    }
+
+
 def bench_mdrw(args):
     """Multi-dimensional random walks at the paper's setting (2,000
     instances, frontier pools of 2,000 vertices, 1,703 sampled edges each) on
@@ -702,6 +746,8 @@ def main():
         line = bench_node2vec(args)
     elif args.workload == "forest_fire":
         line = bench_forest_fire(args)
+    elif args.workload == "metropolis":
+        line = bench_metropolis(args)
     elif args.workload == "mdrw":
         line = bench_mdrw(args)
     elif args.workload == "copy":

@@ -222,7 +222,9 @@ typedef struct {
     int32_t bound32;              /* [0, 32], default 32                          */
 } csaw_tuning;
 
-/* INVALID_ARG if a bound is outside its range. */
+/* INVALID_ARG if a bound is outside its range. A call already running keeps
+ * the setting it started with; calls from several threads may see either
+ * setting, with the same results. */
 csaw_status csaw_set_tuning(csaw_graph g, const csaw_tuning* tuning);
 /* HOST out: tuning. */
 csaw_status csaw_get_tuning(csaw_graph g, csaw_tuning* tuning);
@@ -230,6 +232,8 @@ csaw_status csaw_get_tuning(csaw_graph g, csaw_tuning* tuning);
 /* Autotuner: runs csaw_sample(g, args, out, stream) under each candidate
  * setting (warm-up call, then `reps` timed calls; reps in [1, 100]), keeps
  * the fastest median on the graph and writes it to *chosen (HOST, nullable).
+ * Other calls on the same graph while it runs use whichever candidate is
+ * current; their results are unchanged.
  * The outputs are those of csaw_sample, identical under every setting. An
  * error of any call is returned as is (the graph keeps its previous setting). */
 csaw_status csaw_autotune_sample(csaw_graph g, const csaw_sample_args* args, csaw_sample_out* out, int32_t reps,

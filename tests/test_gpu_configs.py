@@ -80,3 +80,36 @@ def test_batched_rmat22_full(csaw):
             np.testing.assert_array_equal(src[a:b], rs)
             np.testing.assert_array_equal(dst[a:b], rd)
     assert res.num_edges > 10_000_000
+
+
+def test_forest_fire_rmat22_full(csaw):
+    """The forest fire bench workload (R-MAT 22, 8,192 seeds, burning
+    probability 0.7, depth 2, cap 64), compared whole with the oracle."""
+    rec = inputs.DEGREE_BIASED
+    say("forest fire R-MAT 22: generating graph")
+    rp, col = inputs.graph_for(rec)
+    offs, seeds = inputs.single_instance_seeds(rp, col, rec["num_seeds"], rec["seed_rng"])
+    g = csaw.Graph(rp, col)
+    burn = int(0.7 * 2 ** 32)
+    say("forest fire R-MAT 22: sampling")
+    res = g.sample(offs, seeds, [-1, -1], csaw.UNIFORM, rng_seed=1, burn=burn)
+    ref = oracle.sample(rp, col, None, offs, seeds, [-1, -1], bias_kind=oracle.UNIFORM, rng_seed=1, burn=burn)
+    np.testing.assert_array_equal(res.offsets.cpu().numpy(), ref.offsets)
+    np.testing.assert_array_equal(res.src.cpu().numpy(), ref.src)
+    np.testing.assert_array_equal(res.dst.cpu().numpy(), ref.dst)
+    assert ref.num_edges > 20000
+
+
+def test_metropolis_hastings_rmat22(csaw):
+    """Metropolis-Hastings walks on the symmetrised R-MAT 22 graph: 2^20
+    walkers of length 80 on the GPU, every 256th walker checked."""
+    say("metropolis-hastings R-MAT 22: generating graph")
+    rp, col = inputs.rmat_csr(22, 16 << 22, 22, symmetrize=True)
+    starts_all = inputs.walker_starts(rp, col, 1 << 20, 2404)
+    g = csaw.Graph(rp, col)
+    say("metropolis-hastings R-MAT 22: walking")
+    paths, _ = g.walk(starts_all, 80, csaw.METROPOLIS_HASTINGS, rng_seed=2)
+    ids = np.arange(0, 1 << 20, 256, dtype=np.uint64)
+    ref, _, _ = oracle.walk(rp, col, None, starts_all[ids.astype(np.int64)], 80, bias_kind=oracle.METROPOLIS,
+                            rng_seed=2, walker_ids=ids)
+    np.testing.assert_array_equal(paths.cpu().numpy()[ids.astype(np.int64)], ref)
