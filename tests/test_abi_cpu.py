@@ -80,3 +80,38 @@ def test_tuning_calls_validate_on_host(csaw):
     assert csaw.lib.csaw_set_tuning(None, ctypes.byref(t)) == 1
     assert csaw.lib.csaw_get_tuning(None, ctypes.byref(t)) == 1
     assert csaw.lib.csaw_autotune_sample(None, None, None, 3, None, None) == 1
+
+
+STRUCTS = {  # C struct -> ctypes mirror in the binding
+    "csaw_sample_args": "SampleArgs",
+    "csaw_sample_out": "SampleOut",
+    "csaw_tuning": "Tuning",
+    "csaw_walk_args": "WalkArgs",
+    "csaw_mdrw_args": "MdrwArgs",
+    "csaw_server_config": "ServerConfig",
+    "csaw_request": "Request",
+    "csaw_result": "Result",
+}
+
+
+def test_binding_structs_match_the_header(csaw, tmp_path):
+    """Every struct of include/csaw.h has the same size and field offsets in
+    the ctypes binding (compiled with the host C compiler)."""
+    import subprocess
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "csaw.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in getattr(csaw, pyname)._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = dict(ln.rsplit(" ", 1) for ln in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                           check=True).stdout.strip().splitlines())
+    for cname, pyname in STRUCTS.items():
+        st = getattr(csaw, pyname)
+        assert int(out["%s size" % cname]) == ctypes.sizeof(st), cname
+        for fname, _ in st._fields_:
+            assert int(out["%s.%s" % (cname, fname)]) == getattr(st, fname).offset, (cname, fname)
