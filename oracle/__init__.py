@@ -86,6 +86,8 @@ def lib():
             L.orc_walk.argtypes = [i64, vp, vp, vp, i32, u32, u32, u32, i64, vp, u64, vp, i32, u64,
                                    u32, u32, vp, vp, vp, i32]
             L.orc_walk.restype = i32
+            L.orc_layer_sample.argtypes = [i64, vp, vp, vp, i32, vp, vp, u64, i32, vp, i32, u64, i32, vp, vp, vp]
+            L.orc_layer_sample.restype = i32
             L.orc_mdrw.argtypes = [i64, vp, vp, i32, vp, vp, u64, i64, u64, vp, vp, vp]
             L.orc_mdrw.restype = i32
             L.orc_max_threads.argtypes = []
@@ -232,6 +234,28 @@ def walk(rowptr, col, ew, starts, length, bias_kind=UNIFORM, rng_seed=1, walker_
     if rc != 0:
         raise ValueError("oracle: invalid walk input")
     return paths, steps, tuple(stats)
+
+
+def layer_sample(rowptr, col, ew, seed_offsets, seeds, fanouts, bias_kind=UNIFORM, rng_seed=1,
+                 instance_base=0, rounds=DEFAULT_ROUNDS):
+    """Layer sampling (see ``orc_layer_sample``). Returns (src [ni, L, K],
+    dst [ni, L, K], counts [ni, L]) with K = max(fanouts), -1 padded."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    ew = None if ew is None else np.ascontiguousarray(ew, dtype=np.uint32)
+    so = np.ascontiguousarray(seed_offsets, dtype=np.int64)
+    sd = np.ascontiguousarray(seeds, dtype=np.int32)
+    fo = np.ascontiguousarray(fanouts, dtype=np.int32)
+    ni, L = len(so) - 1, len(fo)
+    K = int(fo.max()) if L else 0
+    src = np.zeros((ni, L, K), dtype=np.int32)
+    dst = np.zeros((ni, L, K), dtype=np.int32)
+    counts = np.zeros((ni, L), dtype=np.int32)
+    rc = lib().orc_layer_sample(len(rowptr) - 1, _p(rowptr), _p(col), _p(ew), ni, _p(so), _p(sd), instance_base,
+                                L, _p(fo), bias_kind, rng_seed, rounds, _p(src), _p(dst), _p(counts))
+    if rc != 0:
+        raise ValueError("oracle: invalid layer-sampling input")
+    return src, dst, counts
 
 
 def mdrw(rowptr, col, pool_offsets, pool, budget, rng_seed=1, instance_base=0):

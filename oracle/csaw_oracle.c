@@ -657,6 +657,96 @@ int32_t orc_walk(int64_t n, const int64_t* rowptr, const int32_t* col, const uin
 }
 
 /*
+ * Layer sampling (Section II-A: unlike neighbor and forest fire sampling,
+ * which select neighbors per frontier vertex, layer sampling selects a
+ * constant number of neighbors for the whole frontier in each round).
+ * Instance i (id iid = instance_base + i): F_0 = its seeds (sorted, distinct:
+ * checked), visited = F_0. Layer l = 0..L-1 with k = fanouts[l]:
+ *   pool = the lists N(v) of v in F_l, concatenated in increasing v (list
+ *   order inside); b = EdgeBias of each pool position (Eq. edgebias);
+ *   Select: orc_select(b, |pool|, k, rounds, counter (iid, l, 0xFFFFFFFF,
+ *   slot | round << 16)) -- k distinct positions, or every positive one
+ *   when k >= P;
+ *   Sampled: slot j is the edge (owner of position j, neighbor at it);
+ *   Update: F_{l+1} = distinct picked neighbors not visited, increasing;
+ *   visited gains them.
+ * Output: src/dst[(i * L + l) * K + j] for slot j (-1 past the count),
+ * counts[i * L + l] (K = the largest fanout). Returns 0, or 1 on invalid
+ * input (unsorted or repeated seeds, a fanout outside [1, 64]).
+ */
+int32_t orc_layer_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const uint32_t* ew,
+                         int32_t ni, const int64_t* seed_off, const int32_t* seeds, uint64_t instance_base,
+                         int32_t L, const int32_t* fanouts, int32_t bias_kind, uint64_t rng_seed, int32_t rounds,
+                         int32_t* src, int32_t* dst, int32_t* counts)
+{
+    orc_graph g = {n, rowptr, col, ew};
+    if (ni < 0 || L < 0 || rounds < 0 || rounds >= (int32_t)ORC_BURN_ROUND) return 1;
+    if (bias_kind != ORC_UNIFORM && bias_kind != ORC_EDGE_WEIGHT && bias_kind != ORC_NEIGHBOR_DEGREE) return 1;
+    if (bias_kind == ORC_EDGE_WEIGHT && !ew) return 1;
+    int32_t K = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        if (fanouts[l] < 1 || fanouts[l] > 64) return 1;
+        if (fanouts[l] > K) K = fanouts[l];
+    }
+    for (int32_t i = 0; i < ni; ++i) {
+        if (seed_off[i + 1] < seed_off[i]) return 1;
+        for (int64_t s = seed_off[i]; s < seed_off[i + 1]; ++s) {
+            if (seeds[s] < 0 || seeds[s] >= n) return 1;
+            if (s > seed_off[i] && seeds[s] <= seeds[s - 1]) return 1;
+        }
+    }
+    for (int64_t q = 0; q < (int64_t)ni * L * K; ++q) src[q] = dst[q] = -1;
+    unsigned char* visited = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    for (int32_t i = 0; i < ni; ++i) {
+        const uint64_t iid = instance_base + (uint64_t)i;
+        ivec cur = {0}, nxt = {0}, all = {0};
+        for (int64_t s = seed_off[i]; s < seed_off[i + 1]; ++s) {
+            iv_push(&cur, seeds[s]);
+            iv_push(&all, seeds[s]);
+            visited[seeds[s]] = 1;
+        }
+        for (int32_t l = 0; l < L; ++l) {
+            int64_t D = 0;
+            for (int64_t f = 0; f < cur.n; ++f) D += deg(&g, cur.p[f]);
+            uint32_t* b = (uint32_t*)malloc((size_t)(D > 0 ? D : 1) * sizeof(uint32_t));
+            int32_t* own = (int32_t*)malloc((size_t)(D > 0 ? D : 1) * sizeof(int32_t));
+            int32_t* nb = (int32_t*)malloc((size_t)(D > 0 ? D : 1) * sizeof(int32_t));
+            int64_t at = 0;
+            for (int64_t f = 0; f < cur.n; ++f) {
+                const int32_t v = cur.p[f];
+                edge_bias_static(&g, bias_kind, v, b + at);
+                for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e, ++at) {
+                    own[at] = v;
+                    nb[at] = col[e];
+                }
+            }
+            int64_t* pos = (int64_t*)malloc((size_t)(D > 0 ? D : 1) * sizeof(int64_t));
+            const int32_t c = orc_select(b, D, fanouts[l], rounds, rng_seed, (uint32_t)iid, (uint32_t)l,
+                                         0xFFFFFFFFu, pos, NULL, NULL);
+            counts[(int64_t)i * L + l] = c;
+            nxt.n = 0;
+            for (int32_t j = 0; j < c; ++j) {
+                const int64_t o = ((int64_t)i * L + l) * K + j;
+                src[o] = own[pos[j]];
+                dst[o] = nb[pos[j]];
+                if (!visited[nb[pos[j]]]) {
+                    visited[nb[pos[j]]] = 1;
+                    iv_push(&nxt, nb[pos[j]]);
+                    iv_push(&all, nb[pos[j]]);
+                }
+            }
+            qsort(nxt.p, (size_t)nxt.n, sizeof(int32_t), cmp_i32);
+            ivec t = cur; cur = nxt; nxt = t;
+            free(b); free(own); free(nb); free(pos);
+        }
+        for (int64_t q = 0; q < all.n; ++q) visited[all.p[q]] = 0;
+        free(cur.p); free(nxt.p); free(all.p);
+    }
+    free(visited);
+    return 0;
+}
+
+/*
  * Multi-dimensional random walk, a.k.a. frontier sampling (Section II-A; the
  * VertexBias select site of fig:api(b); worked example fig:layer_example).
  * Instance i (id iid = instance_base + i) keeps a pool of
