@@ -317,6 +317,41 @@ typedef struct {
 csaw_status csaw_mdrw(csaw_graph g, const csaw_mdrw_args* args, int32_t* src, int32_t* dst, int64_t* steps,
                       int64_t* total_edges, csaw_stream stream);
 
+/* ---------------------------------------------------------- layer sampling */
+
+/* Layer sampling (Section II-A: a constant number of neighbors selected for
+ * the whole frontier in each round). Instance i (id instance_base + i)
+ * starts from its seeds F_0 (sorted, distinct, at most CSAW_MAX_POOL) and
+ * visits them. Layer l: the lists N(v) of v in F_l, concatenated in
+ * increasing v, form one candidate list with the call's EdgeBias;
+ * min(fanouts[l], P) distinct candidates are selected from it as from one
+ * adjacency list (every positive one when the fanout reaches P), with
+ * counter (instance id, layer, 0xFFFFFFFF, slot | round << 16); slot j is
+ * the edge (owner, neighbor). F_{l+1} = the picked neighbors not visited
+ * (sorted, distinct), which are then visited. */
+typedef struct {
+    int32_t num_instances;        /* >= 0                                         */
+    const int64_t* seed_offsets;  /* HOST int64[num_instances+1], non-decreasing,
+                                     seed_offsets[0] = 0                           */
+    const int32_t* seeds;         /* DEVICE int32: each instance's seeds sorted
+                                     and distinct, ids in [0, n)                   */
+    uint64_t instance_base;
+    int32_t num_layers;           /* 0 .. CSAW_MAX_LAYERS                          */
+    const int32_t* fanouts;       /* HOST int32[num_layers], each 1..64            */
+    int32_t bias_kind;            /* UNIFORM, EDGE_WEIGHT or NEIGHBOR_DEGREE       */
+    uint64_t rng_seed;
+    int32_t rounds;               /* as csaw_sample_args.rounds                    */
+} csaw_layer_args;
+
+/* DEVICE outputs: src/dst int32[num_instances][num_layers][K] with K = the
+ * largest fanout, slot order, -1 past the count; counts
+ * int32[num_instances][num_layers]. Errors: INVALID_ARG (bad argument, or
+ * seeds out of range, unsorted or repeated, detected on the device: outputs
+ * are then unspecified); UNSUPPORTED for more than CSAW_MAX_POOL seeds in an
+ * instance. */
+csaw_status csaw_layer_sample(csaw_graph g, const csaw_layer_args* args, int32_t* src, int32_t* dst,
+                              int32_t* counts, csaw_stream stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A request server over one resident graph: requests (one sampling instance

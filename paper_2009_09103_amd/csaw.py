@@ -63,6 +63,12 @@ class MdrwArgs(ctypes.Structure):
                 ("instance_base", ctypes.c_uint64), ("budget", ctypes.c_int64), ("rng_seed", ctypes.c_uint64)]
 
 
+class LayerArgs(ctypes.Structure):
+    _fields_ = [("num_instances", ctypes.c_int32), ("seed_offsets", ctypes.c_void_p), ("seeds", ctypes.c_void_p),
+                ("instance_base", ctypes.c_uint64), ("num_layers", ctypes.c_int32), ("fanouts", ctypes.c_void_p),
+                ("bias_kind", ctypes.c_int32), ("rng_seed", ctypes.c_uint64), ("rounds", ctypes.c_int32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("bound16", ctypes.c_int32), ("bound32", ctypes.c_int32)]
 
@@ -91,7 +97,7 @@ class Result(ctypes.Structure):
 
 EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample",
            "csaw_sample_bound", "csaw_set_tuning", "csaw_get_tuning", "csaw_autotune_sample", "csaw_walk",
-           "csaw_mdrw", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
+           "csaw_mdrw", "csaw_layer_sample", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
            "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_result_free",
            "csaw_server_destroy"]
 
@@ -111,6 +117,7 @@ def _load():
     L.csaw_autotune_sample.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), i32, vp,
                                        ctypes.POINTER(Tuning)]
     L.csaw_walk.argtypes = [vp, ctypes.POINTER(WalkArgs), vp, ctypes.POINTER(ctypes.c_int64), vp]
+    L.csaw_layer_sample.argtypes = [vp, ctypes.POINTER(LayerArgs), vp, vp, vp, vp]
     L.csaw_mdrw.argtypes = [vp, ctypes.POINTER(MdrwArgs), vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
     L.csaw_profile_enable.argtypes = [i32]
     L.csaw_profile_reset.argtypes = []
@@ -346,6 +353,28 @@ class Graph:
         _check(lib.csaw_walk(self._h, ctypes.byref(a), paths.data_ptr() if nw else None,
                              ctypes.byref(steps), _stream(stream)))
         return paths, steps.value
+
+    def layer_sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0, rounds=0,
+                     stream=None):
+        """Layer sampling (csaw_layer_sample). Each instance's seeds must be
+        sorted and distinct. Returns (src [ni, L, K], dst [ni, L, K], counts
+        [ni, L]) int32 device tensors, K = max(fanouts), -1 padded."""
+        so = np.ascontiguousarray(seed_offsets, dtype=np.int64)
+        fo = np.ascontiguousarray(fanouts, dtype=np.int32)
+        ni, L = len(so) - 1, len(fo)
+        K = int(fo.max()) if L else 0
+        sd = _dev_i32(seeds, self.device)
+        src = torch.empty((ni, L, max(K, 1)), dtype=torch.int32, device=self.device)
+        dst = torch.empty_like(src)
+        counts = torch.empty((ni, max(L, 1)), dtype=torch.int32, device=self.device)
+        a = LayerArgs()
+        a.num_instances, a.seed_offsets = ni, so.ctypes.data
+        a.seeds = sd.data_ptr() if sd.numel() else None
+        a.instance_base, a.num_layers, a.fanouts = int(instance_base), L, fo.ctypes.data
+        a.bias_kind, a.rng_seed, a.rounds = _bias_code(bias), int(rng_seed), int(rounds)
+        _check(lib.csaw_layer_sample(self._h, ctypes.byref(a), src.data_ptr(), dst.data_ptr(), counts.data_ptr(),
+                                     _stream(stream)))
+        return src[:, :, :K], dst[:, :, :K], counts[:, :L]
 
     def mdrw(self, pool_offsets, pool, budget, rng_seed=1, instance_base=0, stream=None, out=None):
         """Multi-dimensional random walks (csaw_mdrw): one frontier pool per

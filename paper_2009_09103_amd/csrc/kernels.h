@@ -32,6 +32,8 @@ struct GraphDev {
     // kChunkGroups inclusive group prefixes (built once per graph)
     const uint64_t* gtab_ew;
     const uint64_t* gtab_deg;
+    const uint64_t* wtot_ew;   // n: total weight of each list, per weight array
+    const uint64_t* wtot_deg;
 };
 
 constexpr int kWaveMaxD = 512;   // longest weighted list of the wavefront kernels
@@ -159,7 +161,7 @@ void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 // --- graph preparation (sample_kernels.hip)
 void launch_degree_weights(const int64_t* rowptr, const int32_t* col, int64_t m, uint32_t* degw,
                            hipStream_t s);
-void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n, int32_t* ppos,
+void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n, int32_t* ppos, uint64_t* wtot,
                             hipStream_t s);
 
 // --- walks (walk_kernels.hip)
@@ -182,6 +184,27 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev =
 
 // --- multi-dimensional random walk (mdrw_kernels.hip)
 constexpr int kMaxPool = 2048;
+
+// Layer sampling: one wavefront per instance; its frontier (at most
+// kMaxPool seeds, then at most 64 picks per layer) and visited list in LDS.
+constexpr int kLayerMaxVisited = kMaxPool + kMaxLayers * 64;
+struct LayerParams {
+    GraphDev g;
+    int32_t num_instances;
+    const int64_t* seed_off;         // [ni+1] (host memory, device address)
+    const int32_t* seeds;            // sorted and distinct per instance (checked)
+    uint64_t instance_base;
+    int32_t L, K;                    // layers, largest fanout (output row length)
+    int32_t fan[kMaxLayers];         // 1..64
+    int32_t bias;                    // kUniform, kEdgeWeight or kNeighborDegree
+    int32_t rounds;
+    uint32_t k0, k1;
+    int32_t* src;                    // [ni, L, K]
+    int32_t* dst;
+    int32_t* counts;                 // [ni, L]
+    int32_t* bad;
+};
+void launch_layer_sample(const LayerParams& p, hipStream_t s, LaunchEvents ev = {});
 struct MdrwParams {
     GraphDev g;
     int32_t num_instances;

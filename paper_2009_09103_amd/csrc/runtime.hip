@@ -172,6 +172,8 @@ struct csaw_graph_s {
     int32_t* ppos_deg = nullptr;
     uint64_t* gtab_ew = nullptr;   // chunk prefix tables of the long lists
     uint64_t* gtab_deg = nullptr;
+    uint64_t* wtot_ew = nullptr;   // list totals per weight array
+    uint64_t* wtot_deg = nullptr;
     std::mutex mu;                       // lazy preparation + workspace pool
     std::vector<Workspace*> pool;
     std::atomic<int32_t> bound16{kDefaultBound16}, bound32{kDefaultBound32};  // sub-wave buckets
@@ -188,6 +190,8 @@ struct csaw_graph_s {
         g.ppos_deg = ppos_deg;
         g.gtab_ew = gtab_ew;
         g.gtab_deg = gtab_deg;
+        g.wtot_ew = wtot_ew;
+        g.wtot_deg = wtot_deg;
         return g;
     }
 };
@@ -284,8 +288,9 @@ csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
         int32_t* pp = nullptr;
         if (!g->gtab_ew)
             HIP_OR_FAIL(hipMalloc((void**)&g->gtab_ew, (size_t)chunk_table_rows(g->m) * kChunkGroups * sizeof(uint64_t)));
+        if (!g->wtot_ew) HIP_OR_FAIL(hipMalloc((void**)&g->wtot_ew, std::max<int64_t>(g->n, 1) * sizeof(uint64_t)));
         HIP_OR_FAIL(hipMalloc((void**)&pp, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
-        launch_positive_counts(g->rowptr, g->ew, g->n, pp, s);
+        launch_positive_counts(g->rowptr, g->ew, g->n, pp, g->wtot_ew, s);
         launch_chunk_table(g->rowptr, g->ew, g->n, g->gtab_ew, s);
         const hipError_t e = hipGetLastError() != hipSuccess ? hipErrorLaunchFailure : hipStreamSynchronize(s);
         if (e != hipSuccess) {
@@ -299,9 +304,10 @@ csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
         if (!g->degw) HIP_OR_FAIL(hipMalloc((void**)&g->degw, std::max<int64_t>(g->m, 1) * sizeof(uint32_t)));
         if (!g->gtab_deg)
             HIP_OR_FAIL(hipMalloc((void**)&g->gtab_deg, (size_t)chunk_table_rows(g->m) * kChunkGroups * sizeof(uint64_t)));
+        if (!g->wtot_deg) HIP_OR_FAIL(hipMalloc((void**)&g->wtot_deg, std::max<int64_t>(g->n, 1) * sizeof(uint64_t)));
         HIP_OR_FAIL(hipMalloc((void**)&pp, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
         launch_degree_weights(g->rowptr, g->col, g->m, g->degw, s);
-        launch_positive_counts(g->rowptr, g->degw, g->n, pp, s);
+        launch_positive_counts(g->rowptr, g->degw, g->n, pp, g->wtot_deg, s);
         launch_chunk_table(g->rowptr, g->degw, g->n, g->gtab_deg, s);
         const hipError_t e = hipGetLastError() != hipSuccess ? hipErrorLaunchFailure : hipStreamSynchronize(s);
         if (e != hipSuccess) {
@@ -473,6 +479,8 @@ csaw_status csaw_graph_destroy(csaw_graph g) {
     if (g->ppos_deg) (void)hipFree(g->ppos_deg);
     if (g->gtab_ew) (void)hipFree(g->gtab_ew);
     if (g->gtab_deg) (void)hipFree(g->gtab_deg);
+    if (g->wtot_ew) (void)hipFree(g->wtot_ew);
+    if (g->wtot_deg) (void)hipFree(g->wtot_deg);
     delete g;
     return CSAW_OK;
 }
@@ -926,6 +934,77 @@ csaw_status csaw_mdrw(csaw_graph g, const csaw_mdrw_args* a, int32_t* src, int32
     const int32_t bad = *(int32_t*)(ws->pinned + 256);
     if (total_edges) *total_edges = (int64_t)tot;
     if (bad) return fail(CSAW_ERR_INVALID_ARG, "a pool vertex is outside [0, n)");
+    return CSAW_OK;
+}
+
+csaw_status csaw_layer_sample(csaw_graph g, const csaw_layer_args* a, int32_t* src, int32_t* dst, int32_t* counts,
+                              csaw_stream stream) {
+    t_err.clear();
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (!a) return fail(CSAW_ERR_INVALID_ARG, "args is NULL");
+    const int32_t ni = a->num_instances, L = a->num_layers;
+    if (ni < 0) return fail(CSAW_ERR_INVALID_ARG, "num_instances < 0");
+    if (L < 0 || L > CSAW_MAX_LAYERS) return fail(CSAW_ERR_INVALID_ARG, "num_layers must be in [0, %d]", CSAW_MAX_LAYERS);
+    if (L > 0 && !a->fanouts) return fail(CSAW_ERR_INVALID_ARG, "fanouts is NULL");
+    int32_t K = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        if (a->fanouts[l] < 1 || a->fanouts[l] > 64) return fail(CSAW_ERR_INVALID_ARG, "fanouts must be in [1, 64]");
+        K = std::max(K, a->fanouts[l]);
+    }
+    if (a->bias_kind != kUniform && a->bias_kind != kEdgeWeight && a->bias_kind != kNeighborDegree)
+        return fail(CSAW_ERR_INVALID_ARG, "bias kind %d is not a sampling bias", a->bias_kind);
+    if (a->bias_kind == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
+    if (a->rounds < CSAW_DIRECT_ONLY || a->rounds > CSAW_ROUNDS)
+        return fail(CSAW_ERR_INVALID_ARG, "rounds must be CSAW_DIRECT_ONLY, 0 (default) or 1..%d", CSAW_ROUNDS);
+    if (ni > 0 && !a->seed_offsets) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets is NULL");
+    if (ni > 0 && a->seed_offsets[0] != 0) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets[0] != 0");
+    for (int32_t i = 0; i < ni; ++i) {
+        const int64_t S = a->seed_offsets[i + 1] - a->seed_offsets[i];
+        if (S < 0) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets decreases at %d", i);
+        if (S > kMaxPool)
+            return fail(CSAW_ERR_UNSUPPORTED, "instance %d has %lld seeds (most %d)", i, (long long)S, kMaxPool);
+    }
+    if (ni > 0 && a->seed_offsets[ni] > 0 && !a->seeds) return fail(CSAW_ERR_INVALID_ARG, "seeds is NULL");
+    if ((int64_t)ni * L > 0 && (!src || !dst || !counts)) return fail(CSAW_ERR_INVALID_ARG, "src/dst/counts is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OR_FAIL(hipSetDevice(g->device));
+    csaw_status st;
+    if (a->bias_kind != kUniform && (st = prepare_bias(g, a->bias_kind, s)) != CSAW_OK) return st;
+    if ((int64_t)ni * L == 0) return CSAW_OK;
+    Workspace* ws = acquire(g);
+    Lease rel{g, ws, s};
+    if ((st = ensure_arena(ws, 512)) != CSAW_OK) return st;
+    // pinned block: [0, 512) read-back of the error flag, then the seed offsets
+    const size_t o_off = 512;
+    if ((st = ensure_pinned(ws, o_off + ((size_t)ni + 1) * sizeof(int64_t))) != CSAW_OK) return st;
+    std::memcpy(ws->pinned + o_off, a->seed_offsets, ((size_t)ni + 1) * sizeof(int64_t));
+    HIP_OR_FAIL(hipMemsetAsync(ws->arena, 0, 512, s));
+    LayerParams p{};
+    p.g = g->dev();
+    p.num_instances = ni;
+    p.seed_off = (const int64_t*)(ws->pinned_dev + o_off);
+    p.seeds = a->seeds;
+    p.instance_base = a->instance_base;
+    p.L = L;
+    p.K = K;
+    for (int32_t l = 0; l < L; ++l) p.fan[l] = a->fanouts[l];
+    p.bias = a->bias_kind;
+    p.rounds = a->rounds == 0 ? kDefaultRounds : (a->rounds == CSAW_DIRECT_ONLY ? 0 : a->rounds);
+    p.k0 = (uint32_t)a->rng_seed;
+    p.k1 = (uint32_t)(a->rng_seed >> 32);
+    p.src = src;
+    p.dst = dst;
+    p.counts = counts;
+    p.bad = (int32_t*)ws->arena;
+    {
+        ProfScope ps("layer_sample", s, true);
+        launch_layer_sample(p, s, ps.ev());
+    }
+    HIP_OR_FAIL(hipGetLastError());
+    HIP_OR_FAIL(hipMemcpyAsync(ws->pinned, ws->arena, 512, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    rel.clean = true;
+    if (*(int32_t*)ws->pinned) return fail(CSAW_ERR_INVALID_ARG, "seeds out of range, unsorted or repeated");
     return CSAW_OK;
 }
 

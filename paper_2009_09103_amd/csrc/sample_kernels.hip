@@ -50,9 +50,10 @@ __global__ void k_degree_weights(const int64_t* __restrict__ rowptr, const int32
 }
 
 // one wavefront per vertex: number of positive weights in its list, with
-// kWideList set when the list's total weight needs more than 32 bits
+// kWideList set when the list's total weight needs more than 32 bits, and
+// the total itself
 __global__ void k_positive_counts(const int64_t* __restrict__ rowptr, const uint32_t* __restrict__ w,
-                                  int64_t n, int32_t* __restrict__ ppos) {
+                                  int64_t n, int32_t* __restrict__ ppos, uint64_t* __restrict__ wtot) {
     const int lane = lane_id();
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t v = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; v < n; v += waves) {
@@ -65,7 +66,10 @@ __global__ void k_positive_counts(const int64_t* __restrict__ rowptr, const uint
         }
         c = wave_sum_i64(c);
         tot = wave_sum_u64(tot);
-        if (lane == 0) ppos[v] = (int32_t)c | ((tot >> 32) ? kWideList : 0);
+        if (lane == 0) {
+            ppos[v] = (int32_t)c | ((tot >> 32) ? kWideList : 0);
+            wtot[v] = tot;
+        }
     }
 }
 
@@ -1365,6 +1369,166 @@ __global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
     }
 }
 
+// ------------------------------------------------------ layer sampling
+// One wavefront per instance, every layer in the kernel (Section II-A:
+// layer sampling selects a constant number of neighbors for the whole
+// frontier). Per layer: per frontier vertex its list's total bias and
+// length, two exclusive prefixes over the frontier in LDS (bias and
+// position), then k slots drawn like one list (rounds in slot order, direct
+// draws) with counter (instance id, layer, 0xFFFFFFFF, slot | round << 16):
+// a draw r finds its frontier vertex by binary search in the bias prefix and
+// its neighbor by a scan of that list's biases (the position itself if
+// unbiased). Picks not visited, deduplicated and sorted, form the next
+// frontier (at most 64 vertices).
+__device__ __forceinline__ int32_t lds_upper(const uint64_t* a, int32_t n, uint64_t r) {
+    // largest f in [0, n) with a[f] <= r (a[0] = 0 <= r)
+    int32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kWave) k_layer_sample(LayerParams p) {
+    __shared__ int32_t F[kMaxPool];
+    __shared__ uint64_t Wp[kMaxPool + 1];
+    __shared__ uint64_t Dp[kMaxPool + 1];
+    __shared__ int32_t vis[kLayerMaxVisited];
+    __shared__ int32_t pk[kWave];  // this layer's picks by slot
+    const int lane = lane_id();
+    const Key key{p.k0, p.k1};
+    const uint32_t* wts = p.bias == kEdgeWeight ? p.g.ew : p.g.degw;
+    const int32_t* ppos = p.bias == kEdgeWeight ? p.g.ppos_ew : p.g.ppos_deg;
+    const uint64_t* wtot = p.bias == kEdgeWeight ? p.g.wtot_ew : p.g.wtot_deg;
+    for (int64_t i = blockIdx.x; i < p.num_instances; i += gridDim.x) {
+        const int64_t o0 = uniform_i64(p.seed_off[i]);
+        int32_t nf = (int32_t)(uniform_i64(p.seed_off[i + 1]) - o0);  // <= kMaxPool (checked by the host)
+        const uint32_t iid = (uint32_t)(p.instance_base + (uint64_t)i);
+        bool bad = false;
+        for (int32_t f = lane; f < nf; f += kWave) {
+            const int32_t v = p.seeds[o0 + f];
+            const int32_t prev = f > 0 ? p.seeds[o0 + f - 1] : -1;
+            bad |= v < 0 || (int64_t)v >= p.g.n || v <= prev;
+            F[f] = v;
+            vis[f] = v;
+        }
+        if (ballot(bad)) {  // outputs of the call are unspecified; the host reports the error
+            if (lane == 0) *p.bad = 1;
+            wave_lds_sync();
+            continue;
+        }
+        int32_t nvis = nf;
+        wave_lds_sync();
+        for (int32_t l = 0; l < p.L; ++l) {
+            const int32_t k = p.fan[l];
+            int32_t* src = p.src + (i * p.L + l) * p.K;
+            int32_t* dst = p.dst + (i * p.L + l) * p.K;
+            // totals per frontier vertex, then both prefixes, 64 vertices at a time
+            uint64_t carry_w = 0, carry_d = 0, npos = 0;
+            if (lane == 0) Wp[0] = Dp[0] = 0;
+            for (int32_t f0 = 0; f0 < nf; f0 += kWave) {
+                const int32_t f = f0 + lane;
+                uint64_t wv = 0, dv = 0, pv = 0;
+                if (f < nf) {
+                    const int32_t v = F[f];
+                    const int64_t beg = p.g.rowptr[v];
+                    dv = (uint64_t)(p.g.rowptr[v + 1] - beg);
+                    if (p.bias == kUniform) {
+                        wv = pv = dv;
+                    } else {
+                        wv = wtot[v];
+                        pv = (uint64_t)(ppos[v] & ~kWideList);
+                    }
+                }
+                const uint64_t iw = wave_incl_scan_u64(wv), id = wave_incl_scan_u64(dv);
+                if (f < nf) {
+                    Wp[f + 1] = carry_w + iw;
+                    Dp[f + 1] = carry_d + id;
+                }
+                carry_w += readlane_u64(iw, kWave - 1);
+                carry_d += readlane_u64(id, kWave - 1);
+                npos += wave_sum_u64(pv);
+            }
+            wave_lds_sync();
+            const uint64_t W = carry_w;
+            const int32_t c = W == 0 ? 0 : ((uint64_t)k >= npos ? (int32_t)npos : k);
+            int64_t pos = -1;  // this lane's pool position (slot lane < c)
+            if (c > 0 && (uint64_t)k >= npos) {
+                // every positive position, pool order
+                int32_t run = 0;
+                for (int32_t f = 0; f < nf; ++f) {
+                    const int64_t beg = p.g.rowptr[F[f]];
+                    const int64_t d = (int64_t)(Dp[f + 1] - Dp[f]);
+                    for (int64_t b0 = 0; b0 < d; b0 += kWave) {
+                        const int64_t e = b0 + lane;
+                        const bool posv = e < d && (p.bias == kUniform || wts[beg + e] > 0);
+                        const uint64_t m = ballot(posv);
+                        const int32_t slot = run + __popcll(m & lanemask_lt());
+                        if (posv) {
+                            const int32_t nb = p.g.col[beg + e];
+                            src[slot] = F[f];
+                            dst[slot] = nb;
+                            pk[slot] = nb;
+                        }
+                        run += __popcll(m);
+                    }
+                }
+            } else if (c > 0) {
+                const auto search = [&](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+                    const int32_t f = lds_upper(Wp, nf, r);
+                    if (p.bias == kUniform) {
+                        m = (int64_t)r;
+                        Sm = r;
+                        bm = 1;
+                    } else {
+                        const int32_t v = F[f];
+                        const int64_t beg = p.g.rowptr[v];
+                        int64_t ml = 0;
+                        fine_scan_global(wts + beg, 0, (int64_t)(Dp[f + 1] - Dp[f]), Wp[f], r, ml, Sm, bm);
+                        m = (int64_t)Dp[f] + ml;
+                    }
+                };
+                pos = draw_slots(key, iid, (uint32_t)l, 0xFFFFFFFFu, c, p.rounds, W, search, search);
+                if (lane < c) {
+                    const int32_t f = lds_upper(Dp, nf, (uint64_t)pos);
+                    const int32_t v = F[f];
+                    const int32_t nb = p.g.col[p.g.rowptr[v] + (pos - (int64_t)Dp[f])];
+                    src[lane] = v;
+                    dst[lane] = nb;
+                    pk[lane] = nb;
+                }
+            }
+            for (int32_t j = c + lane; j < p.K; j += kWave) src[j] = dst[j] = -1;
+            if (lane == 0) p.counts[i * p.L + l] = c;
+            // next frontier: the picks, deduplicated, minus visited, sorted
+            wave_lds_sync();
+            const int32_t x = lane < c ? pk[lane] : -1;
+            bool keep = lane < c;
+            for (int32_t q = 0; q < nvis && keep; ++q) keep = vis[q] != x;
+            for (int j = 0; j < kWave; ++j) {
+                const int32_t y = readlane_i32(x, j);
+                if (j < lane && y == x) keep = false;
+            }
+            const uint64_t km = ballot(keep);
+            int32_t rank = 0;
+            for (int j = 0; j < kWave; ++j) {
+                const int32_t y = readlane_i32(x, j);
+                if (((km >> j) & 1ull) && y < x) ++rank;
+            }
+            wave_lds_sync();
+            if (keep) {
+                F[rank] = x;
+                vis[nvis + rank] = x;
+            }
+            nf = __popcll(km);
+            nvis += nf;
+            wave_lds_sync();
+        }
+    }
+}
+
 __global__ void k_call_setup(uint32_t* __restrict__ ctl, int64_t nctl, const uint32_t* __restrict__ host_tab,
                              uint32_t* __restrict__ tab, int64_t ntab) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1407,11 +1571,11 @@ void launch_degree_weights(const int64_t* rowptr, const int32_t* col, int64_t m,
                        m, degw);
 }
 
-void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n, int32_t* ppos,
+void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n, int32_t* ppos, uint64_t* wtot,
                             hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_positive_counts, dim3(grid_for(n, kWavesPerBlock, 65536)), dim3(kBlock), 0, s,
-                       rowptr, w, n, ppos);
+                       rowptr, w, n, ppos, wtot);
 }
 
 void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* seed_offsets, int32_t ni,
@@ -1447,6 +1611,12 @@ void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents e
 
 void launch_select_small(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {
     launch_kernel(p.burn ? k_select_small<true> : k_select_small<false>, dim3(grid), dim3(kBlock), s, ev, p);
+}
+
+void launch_layer_sample(const LayerParams& p, hipStream_t s, LaunchEvents ev) {
+    if (p.num_instances <= 0) return;
+    const int grid = (int)(p.num_instances < 8192 ? p.num_instances : 8192);
+    launch_kernel(k_layer_sample, dim3(grid), dim3(kWave), s, ev, p);
 }
 
 int64_t chunk_table_rows(int64_t m) { return (m >> kTabShift) + 1; }

@@ -88,6 +88,7 @@ STRUCTS = {  # C struct -> ctypes mirror in the binding
     "csaw_tuning": "Tuning",
     "csaw_walk_args": "WalkArgs",
     "csaw_mdrw_args": "MdrwArgs",
+    "csaw_layer_args": "LayerArgs",
     "csaw_server_config": "ServerConfig",
     "csaw_request": "Request",
     "csaw_result": "Result",
