@@ -16,7 +16,7 @@ The sub-wave bucket setting is autotuned on the timed call first (--tuning).
 Other workloads (--workload): batched (4,096 instances in one call against
 4,096 plain calls), node2vec (R-MAT 24 walks), mdrw (multi-dimensional
 random walks), forest_fire (burning probability 0.7, depth 2), metropolis
-(Metropolis-Hastings walks), copy (a 1 GiB device copy, the HBM counter
+(Metropolis-Hastings walks), layer (layer sampling), copy (a 1 GiB device copy, the HBM counter
 calibration).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -531,6 +531,54 @@ def bench_metropolis(args):
     }
 
 
+def bench_layer(args):
+    """Layer sampling on the degree-biased R-MAT 22 graph: 2,000 instances of
+    512 sorted seeds, fanouts [64, 64], out-degree bias."""
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    rec = inputs.DEGREE_BIASED
+    log("generating R-MAT %d graph" % rec["scale"])
+    rp, col = inputs.graph_for(rec)
+    g = csaw.Graph(rp, col)
+    gen = inputs.rng(8808)
+    pool = inputs.non_isolated(rp, col)
+    ni, S = 2000, 512
+    sets = [np.sort(gen.choice(pool, size=S, replace=False)) for _ in range(ni)]
+    offs = np.arange(ni + 1, dtype=np.int64) * S
+    seeds = torch.from_numpy(np.concatenate(sets).astype(np.int32)).to(g.device)
+    fan = [64, 64]
+    # edges per Philox seed (deterministic), counted outside the timed region
+    edges_of = {s: int(g.layer_sample(offs, seeds, fan, csaw.NEIGHBOR_DEGREE, rng_seed=s)[2].sum())
+                for s in (1, 2, 3)}
+    for i in range(args.warmup):
+        g.layer_sample(offs, seeds, fan, csaw.NEIGHBOR_DEGREE, rng_seed=1 + i % 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    edges = 0
+    for i in range(args.steps):
+        g.layer_sample(offs, seeds, fan, csaw.NEIGHBOR_DEGREE, rng_seed=1 + i % 3)
+        edges += edges_of[1 + i % 3]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    csaw.profile_reset()
+    csaw.profile_enable(True)
+    g.layer_sample(offs, seeds, fan, csaw.NEIGHBOR_DEGREE, rng_seed=1)
+    torch.cuda.synchronize()
+    kms, kn = csaw.profile_read("layer_sample")
+    csaw.profile_enable(False)
+    csaw.profile_reset()
+    return {
+        "metric": "sampled edges/sec (SEPS), layer sampling",
+        "value": edges / args.steps / dt, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": "layer_rmat22", "instances": ni, "seeds": S, "fanouts": fan,
+                   "bias": "out-degree of neighbor", "edges_per_step": edges / args.steps},
+        "kernel_ms": kms, "kernel": "k_layer_sample",
+    }
+
+
 def bench_mdrw(args):
     """Multi-dimensional random walks at the paper's setting (2,000
     instances, frontier pools of 2,000 vertices, 1,703 sampled edges each) on
@@ -748,6 +796,8 @@ def main():
         line = bench_forest_fire(args)
     elif args.workload == "metropolis":
         line = bench_metropolis(args)
+    elif args.workload == "layer":
+        line = bench_layer(args)
     elif args.workload == "mdrw":
         line = bench_mdrw(args)
     elif args.workload == "copy":

@@ -1377,8 +1377,7 @@ __global__ void __launch_bounds__(kBlock) k_select_big(SampleLayer p) {
 // position), then k slots drawn like one list (rounds in slot order, direct
 // draws) with counter (instance id, layer, 0xFFFFFFFF, slot | round << 16):
 // a draw r finds its frontier vertex by binary search in the bias prefix and
-// its neighbor by a scan of that list's biases (the position itself if
-// unbiased). Picks not visited, deduplicated and sorted, form the next
+// its neighbor in that list (list_search; the position itself if unbiased). Picks not visited, deduplicated and sorted, form the next
 // frontier (at most 64 vertices).
 __device__ __forceinline__ int32_t lds_upper(const uint64_t* a, int32_t n, uint64_t r) {
     // largest f in [0, n) with a[f] <= r (a[0] = 0 <= r)
@@ -1389,6 +1388,42 @@ __device__ __forceinline__ int32_t lds_upper(const uint64_t* a, int32_t n, uint6
         else hi = mid;
     }
     return lo;
+}
+
+// m = max{i : S_i <= r} inside one weighted list (weights w, first edge beg,
+// length d, prefix acc before it), with S_m and b_m: a scan of the list for
+// up to kWaveMaxD weights, else through the graph's chunk prefix table
+// (chunk totals, then the chunk's group prefixes, then one group).
+__device__ __forceinline__ void list_search(const uint32_t* __restrict__ w, const uint64_t* __restrict__ gtab,
+                                            int64_t beg, int64_t d, uint64_t acc, uint64_t r, int64_t& m,
+                                            uint64_t& Sm, uint32_t& bm) {
+    if (d <= kWaveMaxD) {
+        fine_scan_global(w, 0, d, acc, r, m, Sm, bm);
+        return;
+    }
+    const uint64_t* G = gtab + (beg >> kTabShift) * kChunkGroups;
+    const int64_t nch = chunks_of(d);
+    int64_t j = 0;
+    for (; j + 1 < nch; ++j) {
+        const uint64_t t = G[j * kChunkGroups + kChunkGroups - 1];
+        if (acc + t > r) break;
+        acc += t;
+    }
+    const uint64_t* row = G + j * kChunkGroups;
+    int32_t glo = -1, ghi = kChunkGroups - 1;  // first group i with acc + row[i] > r
+    uint64_t before = 0;
+    while (ghi - glo > 1) {
+        const int32_t mid = (glo + ghi) >> 1;
+        const uint64_t v = row[mid];
+        if (acc + v > r) {
+            ghi = mid;
+        } else {
+            glo = mid;
+            before = v;
+        }
+    }
+    const int64_t i = j * kChunk + (int64_t)ghi * 16;
+    fine_scan_global(w, i, i + 16 < d ? i + 16 : d, acc + before, r, m, Sm, bm);
 }
 
 __global__ void __launch_bounds__(kWave) k_layer_sample(LayerParams p) {
@@ -1402,6 +1437,7 @@ __global__ void __launch_bounds__(kWave) k_layer_sample(LayerParams p) {
     const uint32_t* wts = p.bias == kEdgeWeight ? p.g.ew : p.g.degw;
     const int32_t* ppos = p.bias == kEdgeWeight ? p.g.ppos_ew : p.g.ppos_deg;
     const uint64_t* wtot = p.bias == kEdgeWeight ? p.g.wtot_ew : p.g.wtot_deg;
+    const uint64_t* gtab = p.bias == kEdgeWeight ? p.g.gtab_ew : p.g.gtab_deg;
     for (int64_t i = blockIdx.x; i < p.num_instances; i += gridDim.x) {
         const int64_t o0 = uniform_i64(p.seed_off[i]);
         int32_t nf = (int32_t)(uniform_i64(p.seed_off[i + 1]) - o0);  // <= kMaxPool (checked by the host)
@@ -1486,7 +1522,7 @@ __global__ void __launch_bounds__(kWave) k_layer_sample(LayerParams p) {
                         const int32_t v = F[f];
                         const int64_t beg = p.g.rowptr[v];
                         int64_t ml = 0;
-                        fine_scan_global(wts + beg, 0, (int64_t)(Dp[f + 1] - Dp[f]), Wp[f], r, ml, Sm, bm);
+                        list_search(wts + beg, gtab, beg, (int64_t)(Dp[f + 1] - Dp[f]), Wp[f], r, ml, Sm, bm);
                         m = (int64_t)Dp[f] + ml;
                     }
                 };
