@@ -47,6 +47,7 @@
 #ifndef CSAW_H
 #define CSAW_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -351,6 +352,22 @@ typedef struct {
  * instance. */
 csaw_status csaw_layer_sample(csaw_graph g, const csaw_layer_args* args, int32_t* src, int32_t* dst,
                               int32_t* counts, csaw_stream stream);
+
+/* ------------------------------------------------------- device scratch */
+
+/* Device scratch of the calls (each graph's workspaces: per-call frontier and
+ * edge-count arrays, instance bitmaps) comes from alloc_fn (bytes, user),
+ * which returns a device pointer or NULL (the call then fails with
+ * OUT_OF_MEMORY); a buffer is returned with the free_fn that was set when it
+ * was allocated, once no work uses it (at a workspace's growth or at
+ * csaw_graph_destroy), so a pair must stay valid until every graph that used
+ * it is destroyed. Both NULL (the default): hipMalloc / hipFree. The graph's
+ * own arrays (CSR, weights, tables) always use hipMalloc. Process-wide; it
+ * applies from the next allocation. INVALID_ARG if only one of the two is
+ * NULL. */
+typedef void* (*csaw_alloc_fn)(size_t bytes, void* user);
+typedef void (*csaw_free_fn)(void* ptr, void* user);
+csaw_status csaw_set_allocator(csaw_alloc_fn alloc_fn, csaw_free_fn free_fn, void* user);
 
 /* ---------------------------------------------------------------- serving */
 

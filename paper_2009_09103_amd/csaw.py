@@ -69,6 +69,10 @@ class LayerArgs(ctypes.Structure):
                 ("bias_kind", ctypes.c_int32), ("rng_seed", ctypes.c_uint64), ("rounds", ctypes.c_int32)]
 
 
+AllocFn = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FreeFn = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("bound16", ctypes.c_int32), ("bound32", ctypes.c_int32)]
 
@@ -97,7 +101,7 @@ class Result(ctypes.Structure):
 
 EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample",
            "csaw_sample_bound", "csaw_set_tuning", "csaw_get_tuning", "csaw_autotune_sample", "csaw_walk",
-           "csaw_mdrw", "csaw_layer_sample", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
+           "csaw_mdrw", "csaw_layer_sample", "csaw_set_allocator", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
            "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_result_free",
            "csaw_server_destroy"]
 
@@ -118,6 +122,7 @@ def _load():
                                        ctypes.POINTER(Tuning)]
     L.csaw_walk.argtypes = [vp, ctypes.POINTER(WalkArgs), vp, ctypes.POINTER(ctypes.c_int64), vp]
     L.csaw_layer_sample.argtypes = [vp, ctypes.POINTER(LayerArgs), vp, vp, vp, vp]
+    L.csaw_set_allocator.argtypes = [AllocFn, FreeFn, vp]
     L.csaw_mdrw.argtypes = [vp, ctypes.POINTER(MdrwArgs), vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
     L.csaw_profile_enable.argtypes = [i32]
     L.csaw_profile_reset.argtypes = []
@@ -163,6 +168,21 @@ def _dev_i32(x, device) -> torch.Tensor:
     else:
         t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).to(device)
     return t.contiguous()
+
+
+_allocator_refs = []  # callbacks must outlive every buffer they handed out
+
+
+def set_allocator(alloc=None, free=None):
+    """Workspace device memory from alloc(nbytes) -> int pointer and
+    free(pointer) (csaw_set_allocator); both None restores hipMalloc."""
+    if alloc is None and free is None:
+        _check(lib.csaw_set_allocator(AllocFn(), FreeFn(), None))
+        return
+    a = AllocFn(lambda n, user: alloc(int(n)) or None)
+    f = FreeFn(lambda p, user: free(int(p)))
+    _allocator_refs.append((a, f))
+    _check(lib.csaw_set_allocator(a, f, None))
 
 
 def version() -> str:

@@ -92,7 +92,36 @@ struct ProfScope {
 };
 
 // ------------------------------------------------------------ workspace
+// Source of workspace device memory: the caller's allocator (csaw_set_allocator)
+// or hipMalloc; each buffer keeps the pair it came from for its release.
+struct DevAllocator {
+    csaw_alloc_fn alloc = nullptr;
+    csaw_free_fn release = nullptr;
+    void* user = nullptr;
+};
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;
+
+hipError_t dev_alloc(DevAllocator& from, void** p, size_t bytes) {
+    DevAllocator a;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        a = g_alloc;
+    }
+    from = a;
+    if (!a.alloc) return hipMalloc(p, bytes);
+    *p = a.alloc(bytes, a.user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_release(const DevAllocator& from, void* p) {
+    if (!p) return;
+    if (from.release) from.release(p, from.user);
+    else (void)hipFree(p);
+}
+
 struct Workspace {
+    DevAllocator arena_from, bitmaps_from;
     char* arena = nullptr;
     size_t arena_cap = 0;
     uint32_t* bitmaps = nullptr;  // visited | next, zero between calls
@@ -131,8 +160,8 @@ struct Workspace {
         if (aux) (void)hipStreamDestroy(aux);
         if (join) (void)hipEventDestroy(join);
         if (fork) (void)hipEventDestroy(fork);
-        if (arena) (void)hipFree(arena);
-        if (bitmaps) (void)hipFree(bitmaps);
+        dev_release(arena_from, arena);
+        dev_release(bitmaps_from, bitmaps);
         if (pinned) (void)hipHostFree(pinned);
     }
 };
@@ -234,11 +263,11 @@ struct Lease {
 csaw_status ensure_arena(Workspace* w, size_t bytes) {
     if (w->arena_cap >= bytes) return CSAW_OK;
     w->drop_graphs();
-    if (w->arena) HIP_OR_FAIL(hipFree(w->arena));
+    dev_release(w->arena_from, w->arena);  // no work uses it: every call drains its stream at its end
     w->arena = nullptr;
     w->arena_cap = 0;
     const size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 20);
-    HIP_OR_FAIL(hipMalloc((void**)&w->arena, cap));
+    HIP_OR_FAIL(dev_alloc(w->arena_from, (void**)&w->arena, cap));
     w->arena_cap = cap;
     return CSAW_OK;
 }
@@ -268,10 +297,10 @@ csaw_status ensure_streams(Workspace* w) {
 csaw_status ensure_bitmaps(Workspace* w, size_t words, hipStream_t s) {
     if (w->bitmap_words >= words) return CSAW_OK;
     w->drop_graphs();
-    if (w->bitmaps) HIP_OR_FAIL(hipFree(w->bitmaps));
+    dev_release(w->bitmaps_from, w->bitmaps);
     w->bitmaps = nullptr;
     w->bitmap_words = 0;
-    HIP_OR_FAIL(hipMalloc((void**)&w->bitmaps, words * sizeof(uint32_t)));
+    HIP_OR_FAIL(dev_alloc(w->bitmaps_from, (void**)&w->bitmaps, words * sizeof(uint32_t)));
     launch_fill_u32(w->bitmaps, 0u, (int64_t)words, s);
     HIP_OR_FAIL(hipGetLastError());
     HIP_OR_FAIL(hipStreamSynchronize(s));
@@ -1005,6 +1034,17 @@ csaw_status csaw_layer_sample(csaw_graph g, const csaw_layer_args* a, int32_t* s
     HIP_OR_FAIL(hipStreamSynchronize(s));
     rel.clean = true;
     if (*(int32_t*)ws->pinned) return fail(CSAW_ERR_INVALID_ARG, "seeds out of range, unsorted or repeated");
+    return CSAW_OK;
+}
+
+csaw_status csaw_set_allocator(csaw_alloc_fn alloc_fn, csaw_free_fn free_fn, void* user) {
+    t_err.clear();
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+        return fail(CSAW_ERR_INVALID_ARG, "alloc_fn and free_fn must both be set or both be NULL");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc_fn;
+    g_alloc.release = free_fn;
+    g_alloc.user = user;
     return CSAW_OK;
 }
 

@@ -116,3 +116,9 @@ def test_binding_structs_match_the_header(csaw, tmp_path):
         assert int(out["%s size" % cname]) == ctypes.sizeof(st), cname
         for fname, _ in st._fields_:
             assert int(out["%s.%s" % (cname, fname)]) == getattr(st, fname).offset, (cname, fname)
+
+
+def test_set_allocator_validates_on_host(csaw):
+    a = csaw.AllocFn(lambda n, u: None)
+    assert csaw.lib.csaw_set_allocator(a, csaw.FreeFn(), None) == 1     # one of two NULL
+    assert csaw.lib.csaw_set_allocator(csaw.AllocFn(), csaw.FreeFn(), None) == 0

@@ -492,3 +492,34 @@ def test_forest_fire(csaw, burn):
         assert_same(res, ref)
     if burn == 1:
         assert ref.num_edges == 0
+
+
+def test_caller_allocator(csaw):
+    """Workspace memory from a caller's allocator (torch's caching allocator
+    here): same edges as the oracle, and every buffer handed out is returned
+    when the graph is destroyed."""
+    import torch
+    calls = {"alloc": 0, "free": 0}
+
+    def alloc(n):
+        calls["alloc"] += 1
+        return torch.cuda.caching_allocator_alloc(n)
+
+    def free(p):
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(p)
+
+    rp, col = inputs.rmat_csr(13, 16 << 13, 44)
+    offs, seeds, fan, bias = inputs.batched_instances(rp, col, 20, 45)
+    csaw.set_allocator(alloc, free)
+    try:
+        g = csaw.Graph(rp, col)
+        say("sample with a caller allocator")
+        res = g.sample(offs, seeds, fan, bias, rng_seed=8)
+        ref = oracle.sample(rp, col, None, offs, seeds, fan, bias_kinds=bias, rng_seed=8)
+        assert_same(res, ref)
+        torch.cuda.synchronize()
+        g.close()
+        assert calls["alloc"] >= 2 and calls["free"] == calls["alloc"]
+    finally:
+        csaw.set_allocator(None, None)
