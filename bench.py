@@ -770,7 +770,7 @@ def main():
     ap.add_argument("--n2v-stride", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole path on a single MI355X "
+        print("bench.py measures one GPU only: the library runs the whole path on a single MI355X "
               "(instances would shard across GPUs with no exchange); --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
