@@ -186,8 +186,8 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev =
 constexpr int kMaxPool = 2048;
 
 // Layer sampling: one wavefront per instance; its frontier (at most
-// kMaxPool seeds, then at most 64 picks per layer) and visited list in LDS.
-constexpr int kLayerMaxVisited = kMaxPool + kMaxLayers * 64;
+// kMaxPool seeds, then at most 64 picks per layer) and visited list in LDS,
+// sized by the call's largest seed set.
 struct LayerParams {
     GraphDev g;
     int32_t num_instances;
@@ -195,6 +195,7 @@ struct LayerParams {
     const int32_t* seeds;            // sorted and distinct per instance (checked)
     uint64_t instance_base;
     int32_t L, K;                    // layers, largest fanout (output row length)
+    int32_t max_f;                   // largest seed set of the call (sizes the LDS)
     int32_t fan[kMaxLayers];         // 1..64
     int32_t bias;                    // kUniform, kEdgeWeight or kNeighborDegree
     int32_t rounds;

@@ -987,11 +987,13 @@ csaw_status csaw_layer_sample(csaw_graph g, const csaw_layer_args* a, int32_t* s
         return fail(CSAW_ERR_INVALID_ARG, "rounds must be CSAW_DIRECT_ONLY, 0 (default) or 1..%d", CSAW_ROUNDS);
     if (ni > 0 && !a->seed_offsets) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets is NULL");
     if (ni > 0 && a->seed_offsets[0] != 0) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets[0] != 0");
+    int64_t max_f = 0;
     for (int32_t i = 0; i < ni; ++i) {
         const int64_t S = a->seed_offsets[i + 1] - a->seed_offsets[i];
         if (S < 0) return fail(CSAW_ERR_INVALID_ARG, "seed_offsets decreases at %d", i);
         if (S > kMaxPool)
             return fail(CSAW_ERR_UNSUPPORTED, "instance %d has %lld seeds (most %d)", i, (long long)S, kMaxPool);
+        max_f = std::max(max_f, S);
     }
     if (ni > 0 && a->seed_offsets[ni] > 0 && !a->seeds) return fail(CSAW_ERR_INVALID_ARG, "seeds is NULL");
     if ((int64_t)ni * L > 0 && (!src || !dst || !counts)) return fail(CSAW_ERR_INVALID_ARG, "src/dst/counts is NULL");
@@ -1016,6 +1018,7 @@ csaw_status csaw_layer_sample(csaw_graph g, const csaw_layer_args* a, int32_t* s
     p.instance_base = a->instance_base;
     p.L = L;
     p.K = K;
+    p.max_f = (int32_t)max_f;
     for (int32_t l = 0; l < L; ++l) p.fan[l] = a->fanouts[l];
     p.bias = a->bias_kind;
     p.rounds = a->rounds == 0 ? kDefaultRounds : (a->rounds == CSAW_DIRECT_ONLY ? 0 : a->rounds);

@@ -1426,12 +1426,24 @@ __device__ __forceinline__ void list_search(const uint32_t* __restrict__ w, cons
     fine_scan_global(w, i, i + 16 < d ? i + 16 : d, acc + before, r, m, Sm, bm);
 }
 
+// LDS of one wavefront, sized by the call's largest seed set mf and its
+// layers. A frontier holds the seeds, then at most 64 picks: cf = max(mf, 64)
+// entries. The two prefixes (uint64, cf + 1 each), then the frontier (cf),
+// the visited list (mf + 64 per layer) and the picks (64).
+__host__ __device__ inline int32_t layer_frontier_cap(int32_t mf) { return mf > kWave ? mf : kWave; }
+inline size_t layer_lds_bytes(int32_t mf, int32_t L) {
+    const size_t cf = (size_t)layer_frontier_cap(mf);
+    return 2 * sizeof(uint64_t) * (cf + 1) + sizeof(int32_t) * (cf + (size_t)mf + 64 * (size_t)L + kWave);
+}
+
 __global__ void __launch_bounds__(kWave) k_layer_sample(LayerParams p) {
-    __shared__ int32_t F[kMaxPool];
-    __shared__ uint64_t Wp[kMaxPool + 1];
-    __shared__ uint64_t Dp[kMaxPool + 1];
-    __shared__ int32_t vis[kLayerMaxVisited];
-    __shared__ int32_t pk[kWave];  // this layer's picks by slot
+    extern __shared__ __align__(16) unsigned char layer_lds[];
+    const int32_t cf = layer_frontier_cap(p.max_f);
+    uint64_t* Wp = (uint64_t*)layer_lds;
+    uint64_t* Dp = Wp + (cf + 1);
+    int32_t* F = (int32_t*)(Dp + (cf + 1));
+    int32_t* vis = F + cf;
+    int32_t* pk = vis + p.max_f + 64 * p.L;  // this layer's picks by slot
     const int lane = lane_id();
     const Key key{p.k0, p.k1};
     const uint32_t* wts = p.bias == kEdgeWeight ? p.g.ew : p.g.degw;
@@ -1652,7 +1664,11 @@ void launch_select_small(const SampleLayer& p, int grid, hipStream_t s, LaunchEv
 void launch_layer_sample(const LayerParams& p, hipStream_t s, LaunchEvents ev) {
     if (p.num_instances <= 0) return;
     const int grid = (int)(p.num_instances < 8192 ? p.num_instances : 8192);
-    launch_kernel(k_layer_sample, dim3(grid), dim3(kWave), s, ev, p);
+    const size_t lds = layer_lds_bytes(p.max_f, p.L);
+    if (ev.start || ev.stop)
+        hipExtLaunchKernelGGL(k_layer_sample, dim3(grid), dim3(kWave), lds, s, ev.start, ev.stop, 0, p);
+    else
+        hipLaunchKernelGGL(k_layer_sample, dim3(grid), dim3(kWave), lds, s, p);
 }
 
 int64_t chunk_table_rows(int64_t m) { return (m >> kTabShift) + 1; }
