@@ -1,0 +1,46 @@
+"""The bench's algorithmic byte model on CPU: computed from the oracle's
+output of a small call, it must count every frontier entry and edge once,
+and the sub-wave split must not change the total."""
+import importlib.util
+import os
+
+import numpy as np
+
+import oracle
+from paper_2009_09103_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_module", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_byte_model_counts_entries_and_edges():
+    bench = load_bench()
+    rp, col = inputs.rmat_csr(12, 40000, 3)
+    deg = np.diff(rp)
+    ppos = np.add.reduceat(np.append((deg[col] > 0).astype(np.int64), 0), rp[:-1])
+    ppos[deg == 0] = 0
+    offs, seeds = inputs.single_instance_seeds(rp, col, 300, 4)
+    fan = [10, 5]
+    for weighted, kind in ((False, oracle.UNIFORM), (True, oracle.NEIGHBOR_DEGREE)):
+        ref = oracle.sample(rp, col, None, offs, seeds, fan, bias_kind=kind, rng_seed=2)
+        base = bench.path_bytes(rp, ppos, seeds, ref.dst, ref.offsets, fan, weighted, 0)
+        split = bench.path_bytes(rp, ppos, seeds, ref.dst, ref.offsets, fan, weighted, 16)
+        assert base["select_small"] == 0
+        assert abs(sum(base.values()) - sum(split.values())) < 1e-6
+        assert split["select_small"] > 0
+        # without weights every frontier entry costs 24 B and every edge 12 B
+        if not weighted:
+            frontier, visited, entries = np.unique(seeds), set(np.unique(seeds).tolist()), 0
+            for l in range(len(fan)):
+                entries += len(frontier)
+                a, b = ref.offsets[l], ref.offsets[l + 1]
+                nxt = sorted(set(ref.dst[a:b].tolist()) - visited)
+                visited |= set(nxt)
+                frontier = np.array(nxt, dtype=np.int64)
+            assert sum(base.values()) == 24.0 * entries + 12.0 * ref.num_edges
