@@ -760,6 +760,16 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
                                         (int64_t)(intptr_t)ws->bitmaps, (int64_t)(intptr_t)ws->pinned,
                                         (int64_t)big_path, b16, b32, P.rounds, (int64_t)a->burn_threshold};
             key.insert(key.end(), P.fcap.begin(), P.fcap.end());
+            // the graph's arrays are baked into the kernel arguments too; the
+            // bias tables of a weight array appear on its first use, so a
+            // sequence captured before then must not serve a later call
+            const GraphDev gd = g->dev();
+            for (const void* q : {(const void*)gd.rowptr, (const void*)gd.col, (const void*)gd.ew, (const void*)gd.degw,
+                                  (const void*)gd.ppos_ew, (const void*)gd.ppos_deg, (const void*)gd.gtab_ew,
+                                  (const void*)gd.gtab_deg, (const void*)gd.wtot_ew, (const void*)gd.wtot_deg})
+                key.push_back((int64_t)(intptr_t)q);
+            key.push_back((int64_t)P.uses_deg);
+            key.push_back((int64_t)P.uses_ew);
             hipGraphExec_t exec = ws->find_graph(key);
             if (!exec) {
                 HIP_OR_FAIL(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeRelaxed));
@@ -782,10 +792,13 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         }
         HIP_OR_FAIL(hipStreamSynchronize(s));
     }
+    // a frontier build that gave up its look-back wrote entries at unknown
+    // positions, so the bitmaps may not be clean: the workspace is dropped
+    // (Lease) instead of going back to the pool
+    if (h_ctl->lookback_stuck) return fail(CSAW_ERR_DEVICE, "frontier build did not complete its block chain");
     rel.clean = true;
     out->num_edges = L > 0 ? h_ctl->out_base[L] : 0;
     if (out->num_edges < 0) return fail(CSAW_ERR_DEVICE, "the device reported a negative edge count");
-    if (h_ctl->lookback_stuck) return fail(CSAW_ERR_DEVICE, "frontier build did not complete its block chain");
     if (h_ctl->bad_seed) return fail(CSAW_ERR_INVALID_ARG, "a seed is outside [0, n)");
     if (h_ctl->unsupported)
         return fail(CSAW_ERR_UNSUPPORTED, "a drawn fanout exceeds %d", CSAW_MAX_FANOUT);

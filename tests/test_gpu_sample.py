@@ -312,6 +312,30 @@ def test_replay_key_covers_bias_kind(csaw):
         assert_same(res, ref)
 
 
+def test_replay_key_covers_bias_tables(csaw):
+    """On a weighted graph the edge-weight tables exist from the start and the
+    out-degree tables only from their first use. An EDGE_WEIGHT call, then a
+    NEIGHBOR_DEGREE call with the same shapes and buffers (both take the
+    long-list path), then EDGE_WEIGHT again: none may replay another's
+    launch sequence, whose kernel arguments name other bias tables."""
+    import torch
+    rp, col = inputs.rmat_csr(15, 16 << 15, 33)
+    assert np.diff(rp).max() > 1024
+    ew = inputs.dst_outdeg_weights(rp, col)
+    ew = (ew * 3 + 1).astype(np.uint32)     # not proportional to the degree bias
+    offs, seeds = inputs.single_instance_seeds(rp, col, 300, 9)
+    g = csaw.Graph(rp, col, ew)
+    seeds_dev = torch.from_numpy(seeds).cuda()
+    cap = max(g.sample_bound(offs, [25, 10], b) for b in (csaw.EDGE_WEIGHT, csaw.NEIGHBOR_DEGREE))
+    out = (torch.empty(cap, dtype=torch.int32, device="cuda"), torch.empty(cap, dtype=torch.int32, device="cuda"),
+           torch.empty(3, dtype=torch.int64, device="cuda"))
+    say("replay key: edge weight, degree, edge weight, same buffers")
+    for bias in (csaw.EDGE_WEIGHT, csaw.NEIGHBOR_DEGREE, csaw.EDGE_WEIGHT, csaw.NEIGHBOR_DEGREE):
+        res = g.sample(offs, seeds_dev, [25, 10], bias, rng_seed=6, out=out)
+        ref = oracle.sample(rp, col, ew, offs, seeds, [25, 10], bias_kind=bias, rng_seed=6)
+        assert_same(res, ref)
+
+
 def test_visited_picks_leave_no_trace(csaw):
     """Dense graph (cliques of 40): most picks of the second layer are
     already visited. The next bitmap must come back all-zero, so the calls
