@@ -27,6 +27,7 @@ Parity status: every function above is pinned by the ``-m "not gpu"`` tests in
 from __future__ import annotations
 
 import ctypes
+import hashlib
 import os
 import subprocess
 import threading
@@ -44,15 +45,44 @@ FANOUT_ALL = -1
 DEFAULT_ROUNDS = 8   # repeated-sampling rounds before the direct draw
 
 
+def _host_stamp() -> str:
+    """The host CPU's model and feature flags: -march=native code is only
+    reused on the CPU it was built for."""
+    model = flags = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if not model and line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                elif not flags and line.startswith("flags"):
+                    flags = line.split(":", 1)[1].strip()
+                if model and flags:
+                    break
+    except OSError:
+        pass
+    return hashlib.sha256((model + "|" + flags).encode()).hexdigest()[:16]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP). Returns the library path."""
+    """Compile the oracle with gcc (-O3 -march=native, OpenMP). Returns the
+    library path. Without force, an existing library is reused only if it is
+    newer than the source and was built on a CPU with the same features."""
+    stamp = _LIB + ".host"
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
+        try:
+            with open(stamp) as f:
+                if f.read().strip() == _host_stamp():
+                    return _LIB
+        except OSError:
+            pass
     tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-Wall", "-Wextra", "-shared", "-fPIC",
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-fopenmp", "-Wall", "-Wextra", "-shared", "-fPIC",
            "-o", tmp, _SRC]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
+    with open(stamp + ".tmp%d" % os.getpid(), "w") as f:
+        f.write(_host_stamp() + "\n")
+    os.replace(stamp + ".tmp%d" % os.getpid(), stamp)
     return _LIB
 
 

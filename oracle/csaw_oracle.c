@@ -11,8 +11,10 @@
  *
  * Plain, slow and obviously correct on purpose: linear scans instead of
  * binary searches, a byte-marker array instead of a bitmap, one sequential
- * loop per definition. OpenMP only runs independent instances / walkers on
- * separate threads; every thread's result is identical to a serial run.
+ * loop per definition. OpenMP only runs independent work on separate
+ * threads -- instances, walkers, or the vertices of one frontier (whose
+ * selections use their own counters) -- and every result is identical to a
+ * serial run.
  *
  * What is computed (each function cites the passage it follows):
  *   - Theorem 1 (Section II-B): a candidate is drawn with probability
@@ -384,6 +386,118 @@ static int iv_push(ivec* v, int32_t x)
  * vertices, number of direct (fallback) draws, sum of degrees expanded,
  * number of draws of either kind.
  */
+/* Per-thread scratch and statistics of the vertex expansions. */
+typedef struct {
+    uint32_t* b; int64_t bcap;
+    int64_t* pos; int64_t poscap;
+    double bytes, expanded, fb, deg, draws;
+} vscratch;
+
+/* One frontier vertex v of instance inst_id at layer l with fanout k0:
+ * NeighborSize (the fanout, or the forest fire count capped by it), biases,
+ * orc_select with counter (inst_id mod 2^32, l, v, .), and its edges appended
+ * to (os, od) in slot order. Returns 0, or 1 if a bias cannot be evaluated. */
+static int expand_vertex(const orc_graph* g, int32_t kind, uint64_t rng_seed, uint64_t inst_id, int32_t l,
+                         int64_t k0, uint32_t burn, int32_t rounds, int32_t v, vscratch* w, ivec* os, ivec* od)
+{
+    int64_t k = k0;
+    if (burn)
+        k = orc_burn_count(rng_seed, (uint32_t)inst_id, (uint32_t)l, (uint32_t)v, burn,
+                           k < 0 ? ORC_BURN_CAP_ALL : (int32_t)k);
+    int64_t d = deg(g, v), beg = g->rowptr[v];
+    if (d > w->bcap) {
+        w->bcap = d; w->b = (uint32_t*)realloc(w->b, (size_t)w->bcap * sizeof(uint32_t));
+    }
+    if (d > w->poscap) {
+        w->poscap = d; w->pos = (int64_t*)realloc(w->pos, (size_t)w->poscap * sizeof(int64_t));
+    }
+    if (d > 0 && edge_bias_static(g, kind, v, w->b) != 0) return 1;
+    int32_t nfb = 0;
+    int64_t ndr = 0;
+    int32_t s = orc_select(w->b, d, k, rounds, rng_seed, (uint32_t)inst_id, (uint32_t)l, (uint32_t)v, w->pos,
+                           &nfb, &ndr);
+    for (int32_t j = 0; j < s; ++j) {
+        iv_push(os, v);
+        iv_push(od, g->col[beg + w->pos[j]]);
+    }
+    w->bytes += select_bytes(kind, d, s);
+    w->expanded += 1;
+    w->fb += nfb;
+    w->draws += (double)ndr;
+    w->deg += (double)d;
+    return 0;
+}
+
+/* Every layer of instance i into es/ed[l*ni + i]. visited is an all-zero
+ * byte array of n entries, left all-zero. With inner_threads > 1 the
+ * vertices of each layer are split into that many contiguous ranges, one per
+ * thread, and the ranges' edges are appended in range order: the same edges
+ * in the same order as one thread. */
+static int sample_instance(const orc_graph* g, int32_t ni, int32_t i, const int64_t* seed_off, const int32_t* seeds,
+                           uint64_t inst_id, int32_t kind, const int32_t* fo, int32_t L, uint64_t rng_seed,
+                           int32_t rounds, uint32_t burn, unsigned char* visited, ivec* es, ivec* ed,
+                           int inner_threads, vscratch* w)
+{
+    int failed = 0;
+    int32_t Li = 0;
+    while (Li < L && fo[Li] != 0) ++Li;
+    ivec all = {0}, cur = {0}, nxt = {0};
+    /* F_0: distinct seeds, ascending */
+    for (int64_t s = seed_off[i]; s < seed_off[i + 1]; ++s) {
+        int32_t v = seeds[s];
+        if (!visited[v]) { visited[v] = 1; iv_push(&cur, v); iv_push(&all, v); }
+    }
+    qsort(cur.p, (size_t)cur.n, sizeof(int32_t), cmp_i32);
+    for (int32_t l = 0; l < Li; ++l) {
+        ivec* os = &es[(int64_t)l * ni + i];
+        ivec* od = &ed[(int64_t)l * ni + i];
+        if (inner_threads <= 1) {
+            for (int64_t f = 0; f < cur.n && !failed; ++f)
+                failed = expand_vertex(g, kind, rng_seed, inst_id, l, fo[l], burn, rounds, cur.p[f], w, os, od);
+        } else {
+            int T = inner_threads;
+            ivec* ts = (ivec*)calloc((size_t)T, sizeof(ivec));
+            ivec* td = (ivec*)calloc((size_t)T, sizeof(ivec));
+            vscratch* tw = (vscratch*)calloc((size_t)T, sizeof(vscratch));
+            int tfail = 0;
+            #pragma omp parallel num_threads(T) reduction(| : tfail)
+            {
+#ifdef _OPENMP
+                int t = omp_get_thread_num(), nt = omp_get_num_threads();
+#else
+                int t = 0, nt = 1;
+#endif
+                int64_t lo = cur.n * t / nt, hi = cur.n * (t + 1) / nt;
+                for (int64_t f = lo; f < hi && !tfail; ++f)
+                    tfail |= expand_vertex(g, kind, rng_seed, inst_id, l, fo[l], burn, rounds, cur.p[f], &tw[t],
+                                           &ts[t], &td[t]);
+            }
+            failed |= tfail;
+            for (int t = 0; t < T; ++t) {
+                for (int64_t q = 0; q < ts[t].n; ++q) { iv_push(os, ts[t].p[q]); iv_push(od, td[t].p[q]); }
+                w->bytes += tw[t].bytes; w->expanded += tw[t].expanded; w->fb += tw[t].fb;
+                w->deg += tw[t].deg; w->draws += tw[t].draws;
+                free(ts[t].p); free(td[t].p); free(tw[t].b); free(tw[t].pos);
+            }
+            free(ts); free(td); free(tw);
+        }
+        if (failed) break;
+        if (l + 1 < Li) {
+            /* Update: next frontier = picked neighbors not visited */
+            nxt.n = 0;
+            for (int64_t e = 0; e < od->n; ++e) {
+                int32_t x = od->p[e];
+                if (!visited[x]) { visited[x] = 1; iv_push(&nxt, x); iv_push(&all, x); }
+            }
+            qsort(nxt.p, (size_t)nxt.n, sizeof(int32_t), cmp_i32);
+            ivec t = cur; cur = nxt; nxt = t;
+        }
+    }
+    for (int64_t q = 0; q < all.n; ++q) visited[all.p[q]] = 0;
+    free(all.p); free(cur.p); free(nxt.p);
+    return failed;
+}
+
 int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const uint32_t* ew,
                    int32_t ni, const int64_t* seed_off, const int32_t* seeds,
                    uint64_t instance_base, const uint64_t* instance_ids,
@@ -413,81 +527,45 @@ int32_t orc_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const u
     double tot_bytes = 0, tot_expanded = 0, tot_fb = 0, tot_deg = 0, tot_draws = 0;
     int failed = 0;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    int T = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
-    (void)nthreads;
+    int T = 1;
 #endif
-    #pragma omp parallel reduction(+ : tot_bytes, tot_expanded, tot_fb, tot_deg, tot_draws)
-    {
+    if (ni >= T || T <= 1) {
+        /* independent instances on separate threads */
+        #pragma omp parallel num_threads(T) reduction(+ : tot_bytes, tot_expanded, tot_fb, tot_deg, tot_draws)
+        {
+            unsigned char* visited = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+            vscratch w = {0};
+            #pragma omp for schedule(dynamic, 1)
+            for (int32_t i = 0; i < ni; ++i) {
+                uint64_t inst_id = instance_ids ? instance_ids[i] : instance_base + (uint64_t)i;
+                int32_t kind = bias_kinds ? bias_kinds[i] : bias_kind;
+                const int32_t* fo = fanouts + (fanout_stride ? (int64_t)i * fanout_stride : 0);
+                if (sample_instance(&g, ni, i, seed_off, seeds, inst_id, kind, fo, L, rng_seed, rounds, burn,
+                                    visited, es, ed, 1, &w)) {
+                    #pragma omp atomic write
+                    failed = 1;
+                }
+            }
+            tot_bytes += w.bytes; tot_expanded += w.expanded; tot_fb += w.fb; tot_deg += w.deg;
+            tot_draws += w.draws;
+            free(visited); free(w.b); free(w.pos);
+        }
+    } else {
+        /* fewer instances than threads: one instance at a time, each layer's
+         * frontier split over the threads */
         unsigned char* visited = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
-        uint32_t* b = NULL; int64_t bcap = 0;
-        int64_t* pos = NULL; int64_t poscap = 0;
-        ivec all = {0}, cur = {0}, nxt = {0};
-        #pragma omp for schedule(dynamic, 1)
-        for (int32_t i = 0; i < ni; ++i) {
+        vscratch w = {0};
+        for (int32_t i = 0; i < ni && !failed; ++i) {
             uint64_t inst_id = instance_ids ? instance_ids[i] : instance_base + (uint64_t)i;
             int32_t kind = bias_kinds ? bias_kinds[i] : bias_kind;
             const int32_t* fo = fanouts + (fanout_stride ? (int64_t)i * fanout_stride : 0);
-            int32_t Li = 0;
-            while (Li < L && fo[Li] != 0) ++Li;
-            all.n = cur.n = nxt.n = 0;
-            /* F_0: distinct seeds, ascending */
-            for (int64_t s = seed_off[i]; s < seed_off[i + 1]; ++s) {
-                int32_t v = seeds[s];
-                if (!visited[v]) { visited[v] = 1; iv_push(&cur, v); iv_push(&all, v); }
-            }
-            qsort(cur.p, (size_t)cur.n, sizeof(int32_t), cmp_i32);
-            for (int32_t l = 0; l < Li; ++l) {
-                ivec* os = &es[(int64_t)l * ni + i];
-                ivec* od = &ed[(int64_t)l * ni + i];
-                for (int64_t f = 0; f < cur.n; ++f) {
-                    int32_t v = cur.p[f];
-                    /* NeighborSize: the layer's fanout, or with burning the
-                     * forest fire count capped by it (64 for "all") */
-                    int64_t k = fo[l];
-                    if (burn)
-                        k = orc_burn_count(rng_seed, (uint32_t)inst_id, (uint32_t)l, (uint32_t)v, burn,
-                                           k < 0 ? ORC_BURN_CAP_ALL : (int32_t)k);
-                    int64_t d = deg(&g, v), beg = rowptr[v];
-                    if (d > bcap) {
-                        bcap = d; b = (uint32_t*)realloc(b, (size_t)bcap * sizeof(uint32_t));
-                    }
-                    if (d > poscap) {
-                        poscap = d; pos = (int64_t*)realloc(pos, (size_t)poscap * sizeof(int64_t));
-                    }
-                    if (d > 0 && edge_bias_static(&g, kind, v, b) != 0) {
-                        #pragma omp atomic write
-                        failed = 1;
-                        continue;
-                    }
-                    int32_t nfb = 0;
-                    int64_t ndr = 0;
-                    int32_t s = orc_select(b, d, k, rounds, rng_seed, (uint32_t)inst_id,
-                                           (uint32_t)l, (uint32_t)v, pos, &nfb, &ndr);
-                    for (int32_t j = 0; j < s; ++j) {
-                        iv_push(os, v);
-                        iv_push(od, col[beg + pos[j]]);
-                    }
-                    tot_bytes += select_bytes(kind, d, s);
-                    tot_expanded += 1;
-                    tot_fb += nfb;
-                    tot_draws += (double)ndr;
-                    tot_deg += (double)d;
-                }
-                if (l + 1 < Li) {
-                    /* Update: next frontier = picked neighbors not visited */
-                    nxt.n = 0;
-                    for (int64_t e = 0; e < od->n; ++e) {
-                        int32_t x = od->p[e];
-                        if (!visited[x]) { visited[x] = 1; iv_push(&nxt, x); iv_push(&all, x); }
-                    }
-                    qsort(nxt.p, (size_t)nxt.n, sizeof(int32_t), cmp_i32);
-                    ivec t = cur; cur = nxt; nxt = t;
-                }
-            }
-            for (int64_t q = 0; q < all.n; ++q) visited[all.p[q]] = 0;
+            failed = sample_instance(&g, ni, i, seed_off, seeds, inst_id, kind, fo, L, rng_seed, rounds, burn,
+                                     visited, es, ed, T, &w);
         }
-        free(visited); free(b); free(pos); free(all.p); free(cur.p); free(nxt.p);
+        tot_bytes = w.bytes; tot_expanded = w.expanded; tot_fb = w.fb; tot_deg = w.deg; tot_draws = w.draws;
+        free(visited); free(w.b); free(w.pos);
     }
     if (failed) {
         for (int64_t q = 0; q < (int64_t)ni * L; ++q) { free(es[q].p); free(ed[q].p); }

@@ -135,6 +135,26 @@ def test_instances_are_independent_of_batch(tiny):
             np.testing.assert_array_equal(batch.segment(l, i)[0], alone.segment(l, 0)[0])
 
 
+def test_frontier_split_over_threads_equals_one_thread(tiny):
+    """With fewer instances than threads the oracle splits each layer's
+    frontier over the threads; edges, order and byte counts equal the
+    one-thread run (one instance, two instances, forest fire)."""
+    rp, col, offs, seeds = tiny
+    deg = np.diff(rp).astype(np.uint32)
+    ew = deg[col] + 1
+    for ni, kw in ((1, {}), (2, {}), (1, dict(burn=int(0.7 * 2 ** 32)))):
+        so = np.array([0, len(seeds)] if ni == 1 else [0, 100, len(seeds)], dtype=np.int64)
+        for bias in (oracle.UNIFORM, oracle.EDGE_WEIGHT, oracle.NEIGHBOR_DEGREE):
+            one = oracle.sample(rp, col, ew, so, seeds, [25, 10, 5], bias_kind=bias, rng_seed=3, nthreads=1, **kw)
+            many = oracle.sample(rp, col, ew, so, seeds, [25, 10, 5], bias_kind=bias, rng_seed=3, nthreads=7, **kw)
+            np.testing.assert_array_equal(one.src, many.src)
+            np.testing.assert_array_equal(one.dst, many.dst)
+            np.testing.assert_array_equal(one.offsets, many.offsets)
+            assert (one.alg_bytes, one.expanded, one.fallbacks, one.draws) == \
+                (many.alg_bytes, many.expanded, many.fallbacks, many.draws)
+            assert one.num_edges > 500
+
+
 def test_degenerate_cases():
     # 0 -> 1, 0 -> 2 (weight 0), 1 -> nothing; 3 isolated
     rp = np.array([0, 2, 2, 2, 2], dtype=np.int64)
