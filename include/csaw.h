@@ -204,6 +204,26 @@ typedef struct {
 csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* args, csaw_sample_out* out,
                         csaw_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): csaw_sample
+ * with the same arguments, outputs and errors, whose device scratch (frontier
+ * arrays, tables, control block, instance bitmaps) is one array of
+ * CSAW_NOALLOC_SCRATCH_BYTES per device, held by the library until the
+ * process ends. It calls no hipMalloc, hipFree, hipHostMalloc or allocator
+ * callback (host-side bookkeeping uses ordinary heap memory), captures no
+ * launch sequence and runs every kernel on `stream`. Calls on one device are
+ * serialised by the library (the array keeps the last call's contents; each
+ * call clears what must start at zero), so overlapping calls wait for each
+ * other rather than race.
+ * Errors, beyond those of csaw_sample: OUT_OF_MEMORY (before any device work)
+ * when the call's scratch -- sized from the seed counts, fanouts and n like
+ * csaw_sample_bound -- exceeds CSAW_NOALLOC_SCRATCH_BYTES; NOT_READY if a
+ * NEIGHBOR_DEGREE instance needs the graph's degree tables before any
+ * csaw_sample or csaw_walk call has built them (building them allocates). */
+#define CSAW_NOALLOC_SCRATCH_BYTES (128ll << 20)
+csaw_status csaw_sample_noalloc(csaw_graph g, const csaw_sample_args* args, csaw_sample_out* out,
+                                csaw_stream stream);
+
 /* Upper bound of the number of edges csaw_sample can emit for these
  * arguments (capacity planning; host-only, seeds are not read).
  * HOST out: max_edges. */

@@ -20,6 +20,7 @@ DIRECT_ONLY = -1  # csaw_sample_args.rounds: no repeated-sampling rounds
 FANOUT_ALL = -1
 MAX_FANOUT = 64
 MAX_LAYERS = 16
+NOALLOC_SCRATCH_BYTES = 128 << 20  # CSAW_NOALLOC_SCRATCH_BYTES
 ROUNDS = 8
 
 _BIAS_NAMES = {"uniform": UNIFORM, "edge_weight": EDGE_WEIGHT, "neighbor_degree": NEIGHBOR_DEGREE,
@@ -99,7 +100,7 @@ class Result(ctypes.Structure):
                 ("total_us", ctypes.c_double)]
 
 
-EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample",
+EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample", "csaw_sample_noalloc",
            "csaw_sample_bound", "csaw_set_tuning", "csaw_get_tuning", "csaw_autotune_sample", "csaw_walk",
            "csaw_mdrw", "csaw_layer_sample", "csaw_set_allocator", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
            "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_result_free",
@@ -115,6 +116,7 @@ def _load():
     L.csaw_graph_destroy.argtypes = [vp]
     L.csaw_graph_info.argtypes = [vp, vp, vp, vp, vp]
     L.csaw_sample.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), vp]
+    L.csaw_sample_noalloc.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), vp]
     L.csaw_sample_bound.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(ctypes.c_int64)]
     L.csaw_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.csaw_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -295,6 +297,21 @@ class Graph:
         or DIRECT_ONLY. ``burn``: forest fire threshold over [0, 2^32)."""
         return self._run_sample(lambda a, o: lib.csaw_sample(self._h, a, o, _stream(stream)), seed_offsets, seeds,
                                 fanouts, bias, rng_seed, instance_base, capacity, out, instance_ids, rng_seeds,
+                                rounds, burn)
+
+    def sample_noalloc(self, seed_offsets, seeds, fanouts, out, bias=UNIFORM, rng_seed=1, instance_base=0,
+                       stream=None, instance_ids=None, rng_seeds=None, rounds=0, burn=0) -> SampleResult:
+        """csaw_sample_noalloc: as ``sample``, with the library's fixed device
+        scratch and no device allocation anywhere on the path. ``seeds`` must
+        be a contiguous int32 tensor on the graph's device and ``out`` the
+        (src, dst, offsets) device tensors; the results are views of them."""
+        if not (isinstance(seeds, torch.Tensor) and seeds.dtype == torch.int32 and seeds.is_contiguous()
+                and seeds.device == self.device):
+            raise ValueError("seeds must be a contiguous int32 tensor on %s" % self.device)
+        if out is None or any(t is not None and t.device != self.device for t in out):
+            raise ValueError("out must be (src, dst, offsets) tensors on %s" % self.device)
+        return self._run_sample(lambda a, o: lib.csaw_sample_noalloc(self._h, a, o, _stream(stream)), seed_offsets,
+                                seeds, fanouts, bias, rng_seed, instance_base, None, out, instance_ids, rng_seeds,
                                 rounds, burn)
 
     def autotune_sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,

@@ -18,9 +18,16 @@
 #include <vector>
 
 #include "../../include/csaw.h"
+#include "internal.h"
 #include "kernels.h"
 
 using namespace csaw;
+
+// Scratch memory of the entry point that allocates nothing (device frontier
+// arrays, control block, tables and instance bitmaps of one sampling call).
+// Host code never passes this name to a kernel: it passes the per-device
+// address from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[CSAW_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -168,6 +175,19 @@ struct Workspace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Device scratch of csaw_sample_noalloc: one array per device, resolved
+// once per device with hipGetSymbolAddress; calls on a device are
+// serialised, and each clears what must start at zero.
+constexpr size_t kNoAllocScratchBytes = size_t(CSAW_NOALLOC_SCRATCH_BYTES);
+constexpr size_t kWalkScratchBytes = kWalkScratch;  // step counter and bad-start flag of a walk call
+constexpr int kMaxDevices = 64;
+struct NoAllocDevice {
+    std::mutex mu;
+    bool ready = false;
+    char* ptr = nullptr;  // device address of this device's scratch
+};
+NoAllocDevice g_noalloc[kMaxDevices];
+
 // CSAW_GRAPH=0 in the environment turns off launch-sequence replay.
 bool graphs_enabled() {
     static const bool on = [] {
@@ -251,6 +271,7 @@ struct Lease {
     hipStream_t s;
     bool clean = false;
     ~Lease() {
+        if (!w) return;  // a call without a workspace (device scratch)
         if (clean) {
             release(g, w);
         } else {
@@ -434,6 +455,67 @@ csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P, 
     return CSAW_OK;
 }
 
+int64_t bitmap_words_per_instance(int64_t n) { return (int64_t)align_up((size_t)((n + 31) / 32), 4); }
+
+// Device memory of one sampling call, from its shape alone: the arena (control
+// block, look-back words, tables, per-entry arrays, frontiers), then, for calls
+// in a caller's scratch, the two bitmaps and the copy of the final control
+// block. The small tables have the same layout in host memory.
+struct SampleLayout {
+    size_t t_fan, t_bias, t_iid, t_key, t_soff, tab_bytes;
+    size_t o_ctl, o_status, ctl_words, o_tab, o_cnt, o_off, o_fbeg, o_fdeg, o_fpos, o_bigs;
+    std::vector<size_t> o_fv, o_fi;
+    size_t arena;                  // bytes of the arena part
+    size_t o_bits, o_copy, scratch;
+    int64_t nb_build;
+};
+
+bool layout_sample(int32_t ni, int32_t L, const std::vector<int64_t>& fcap, int64_t words, SampleLayout& y) {
+    int64_t maxF = 0, sumF = 0;
+    for (int l = 0; l <= L; ++l) {
+        maxF = std::max(maxF, fcap[l]);
+        sumF = sat_add(sumF, fcap[l]);
+    }
+    if (sumF > (int64_t(1) << 40)) return false;
+    y.nb_build = frontier_build_blocks(words);
+    size_t tb = 0;
+    y.t_fan = tb;
+    tb += (size_t)(L + 1) * ni * sizeof(int32_t);
+    y.t_bias = tb;
+    tb += (size_t)ni * sizeof(int32_t);
+    y.t_iid = tb;
+    tb = align_up(tb + (size_t)ni * sizeof(uint32_t), 8);
+    y.t_key = tb;
+    tb += (size_t)ni * sizeof(uint64_t);
+    y.t_soff = tb;
+    tb += ((size_t)ni + 1) * sizeof(int64_t);
+    y.tab_bytes = tb;
+    Carver cv;
+    // the control block and the look-back words are adjacent: one fill clears both
+    y.o_ctl = cv.take<SampleCtl>(1);
+    y.o_status = cv.take<unsigned long long>((size_t)y.nb_build * 4);
+    y.ctl_words = (y.o_status - y.o_ctl) / 4 + (size_t)y.nb_build * 8;
+    y.o_tab = cv.take<char>(y.tab_bytes);
+    const size_t F = (size_t)std::max<int64_t>(maxF, 1);
+    y.o_cnt = cv.take<int32_t>(F);
+    y.o_off = cv.take<int64_t>(F);
+    y.o_fbeg = cv.take<int64_t>(F);
+    y.o_fdeg = cv.take<int32_t>(F);
+    y.o_fpos = cv.take<int32_t>(F);
+    y.o_bigs = cv.take<int32_t>(F);
+    y.o_fv.assign(L + 1, 0);
+    y.o_fi.assign(L + 1, 0);
+    for (int l = 0; l <= L; ++l) {
+        y.o_fv[l] = cv.take<int32_t>((size_t)std::max<int64_t>(fcap[l], 1));
+        y.o_fi[l] = cv.take<int32_t>((size_t)std::max<int64_t>(fcap[l], 1));
+    }
+    y.arena = cv.off;
+    y.o_bits = align_up(cv.off, 256);
+    y.o_copy = align_up(y.o_bits + (size_t)words * 2 * sizeof(uint32_t), 256);
+    y.scratch = y.o_copy + sizeof(SampleCtl);
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -533,8 +615,13 @@ csaw_status csaw_sample_bound(csaw_graph g, const csaw_sample_args* a, int64_t* 
     return CSAW_OK;
 }
 
-csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out* out, csaw_stream stream) {
-    t_err.clear();
+// One sampling call. Device memory comes from a pooled workspace (tables
+// staged through its pinned block, long lists on its side stream, the launch
+// sequence captured and replayed), or, when scratch is set, from that
+// device scratch only: tables copied in, every kernel on the caller's
+// stream, launched directly, no allocation of any kind on the device.
+static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sample_out* out, csaw_stream stream,
+                               char* scratch, size_t scratch_bytes) {
     if (!out) return fail(CSAW_ERR_INVALID_ARG, "out is NULL");
     SamplePlan P;
     csaw_status st = plan_sample(g, a, P, true);
@@ -543,8 +630,21 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     if (out->edge_capacity > 0 && (!out->src || !out->dst)) return fail(CSAW_ERR_INVALID_ARG, "src/dst is NULL");
     hipStream_t s = (hipStream_t)stream;
     HIP_OR_FAIL(hipSetDevice(g->device));
-    if (P.uses_deg && (st = prepare_bias(g, kNeighborDegree, s)) != CSAW_OK) return st;
-    if (P.uses_ew && (st = prepare_bias(g, kEdgeWeight, s)) != CSAW_OK) return st;
+    if (scratch) {
+        // the bias tables are built (and allocated) on a bias kind's first use
+        bool ready;
+        {
+            std::lock_guard<std::mutex> lk(g->mu);
+            ready = (!P.uses_deg || g->ppos_deg) && (!P.uses_ew || g->ppos_ew);
+        }
+        if (!ready)
+            return fail(CSAW_ERR_NOT_READY,
+                        "the NEIGHBOR_DEGREE tables of this graph are not built yet: they are allocated by the first "
+                        "csaw_sample or csaw_walk call with that bias");
+    } else {
+        if (P.uses_deg && (st = prepare_bias(g, kNeighborDegree, s)) != CSAW_OK) return st;
+        if (P.uses_ew && (st = prepare_bias(g, kEdgeWeight, s)) != CSAW_OK) return st;
+    }
 
     const int32_t ni = P.ni, L = P.L;
     const int32_t b16 = g->bound16.load(std::memory_order_relaxed), b32 = g->bound32.load(std::memory_order_relaxed);
@@ -554,60 +654,52 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
         HIP_OR_FAIL(hipStreamSynchronize(s));
         return CSAW_OK;
     }
-    const int64_t nwp = (int64_t)align_up((size_t)((g->n + 31) / 32), 4);
+    const int64_t nwp = bitmap_words_per_instance(g->n);
     const int64_t words = nwp * ni;
-    int64_t maxF = 0, sumF = 0;
-    for (int l = 0; l <= L; ++l) {
-        maxF = std::max(maxF, P.fcap[l]);
-        sumF = sat_add(sumF, P.fcap[l]);
-    }
-    if (sumF > (int64_t(1) << 40)) return fail(CSAW_ERR_OUT_OF_MEMORY, "frontier bound too large");
-    const int64_t nb_build = frontier_build_blocks(words);
-
-    // device workspace layout
-    Carver cv;
-    // small per-call tables: one block with the same layout in pinned memory
-    // and in the arena, so one copy moves them all
-    size_t tb = 0;
-    const size_t t_fan = tb;
-    tb += P.fan.size() * sizeof(int32_t);
-    const size_t t_bias = tb;
-    tb += (size_t)ni * sizeof(int32_t);
-    const size_t t_iid = tb;
-    tb = align_up(tb + (size_t)ni * sizeof(uint32_t), 8);
-    const size_t t_key = tb;
-    tb += (size_t)ni * sizeof(uint64_t);
-    const size_t t_soff = tb;
-    tb += ((size_t)ni + 1) * sizeof(int64_t);
-    const size_t tab_bytes = tb;
-    // the control block and the look-back words are adjacent: one fill clears both
-    const size_t o_ctl = cv.take<SampleCtl>(1);
-    const size_t o_status = cv.take<unsigned long long>((size_t)nb_build * 4);
-    const size_t ctl_words = (o_status - o_ctl) / 4 + (size_t)nb_build * 8;
-    const size_t o_tab = cv.take<char>(tab_bytes);
-    const size_t o_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
-    const size_t o_off = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
-    const size_t o_fbeg = cv.take<int64_t>((size_t)std::max<int64_t>(maxF, 1));
-    const size_t o_fdeg = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
-    const size_t o_fpos = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
-    const size_t o_bigs = cv.take<int32_t>((size_t)std::max<int64_t>(maxF, 1));
-    std::vector<size_t> o_fv(L + 1), o_fi(L + 1);
-    for (int l = 0; l <= L; ++l) {
-        o_fv[l] = cv.take<int32_t>((size_t)std::max<int64_t>(P.fcap[l], 1));
-        o_fi[l] = cv.take<int32_t>((size_t)std::max<int64_t>(P.fcap[l], 1));
-    }
-    Workspace* ws = acquire(g);
-    Lease rel{g, ws, s};
-    if ((st = ensure_arena(ws, cv.off)) != CSAW_OK) return st;
-    if ((st = ensure_bitmaps(ws, (size_t)words * 2, s)) != CSAW_OK) return st;
-    if ((st = ensure_streams(ws)) != CSAW_OK) return st;
+    SampleLayout lay;
+    if (!layout_sample(ni, L, P.fcap, words, lay)) return fail(CSAW_ERR_OUT_OF_MEMORY, "frontier bound too large");
+    const int64_t nb_build = lay.nb_build;
+    const size_t t_fan = lay.t_fan, t_bias = lay.t_bias, t_iid = lay.t_iid, t_key = lay.t_key, t_soff = lay.t_soff;
+    const size_t tab_bytes = lay.tab_bytes;
+    const size_t o_ctl = lay.o_ctl, o_status = lay.o_status, ctl_words = lay.ctl_words, o_tab = lay.o_tab;
+    const size_t o_cnt = lay.o_cnt, o_off = lay.o_off, o_fbeg = lay.o_fbeg, o_fdeg = lay.o_fdeg, o_fpos = lay.o_fpos,
+                 o_bigs = lay.o_bigs;
+    const std::vector<size_t>& o_fv = lay.o_fv;
+    const std::vector<size_t>& o_fi = lay.o_fi;
     // weighted calls can have long-list entries (lists longer than kWaveMaxD,
     // or with a total weight of 2^32 or more)
     const bool big_path = P.uses_deg || P.uses_ew;
     const size_t o_hctl = align_up(tab_bytes, 64);
-    if ((st = ensure_pinned(ws, o_hctl + sizeof(SampleCtl))) != CSAW_OK) return st;
+    Workspace* ws = nullptr;
+    char* A = nullptr;
+    uint32_t* bitmaps = nullptr;
+    char* H = nullptr;                 // host image of the table block
+    std::vector<char> host_tables;     // (device scratch calls)
+    SampleCtl* ctl_copy = nullptr;     // where the final control block is copied (device address)
+    if (scratch) {
+        if (lay.scratch > scratch_bytes)
+            return fail(CSAW_ERR_OUT_OF_MEMORY, "the call needs %zu bytes of device scratch, more than the %zu it has",
+                        lay.scratch, scratch_bytes);
+        A = scratch;
+        bitmaps = (uint32_t*)(scratch + lay.o_bits);
+        ctl_copy = (SampleCtl*)(scratch + lay.o_copy);
+        host_tables.resize(o_hctl + sizeof(SampleCtl));
+        H = host_tables.data();
+    }
+    Lease rel{g, nullptr, s};
+    if (!scratch) {
+        ws = acquire(g);
+        rel.w = ws;
+        if ((st = ensure_arena(ws, lay.arena)) != CSAW_OK) return st;
+        if ((st = ensure_bitmaps(ws, (size_t)words * 2, s)) != CSAW_OK) return st;
+        if ((st = ensure_streams(ws)) != CSAW_OK) return st;
+        if ((st = ensure_pinned(ws, o_hctl + sizeof(SampleCtl))) != CSAW_OK) return st;
+        A = ws->arena;
+        bitmaps = ws->bitmaps;
+        H = ws->pinned;
+        ctl_copy = (SampleCtl*)(ws->pinned_dev + o_hctl);
+    }
 
-    char* A = ws->arena;
     SampleCtl* ctl = (SampleCtl*)(A + o_ctl);
     int32_t* d_fan = (int32_t*)(A + o_tab + t_fan);
     int32_t* d_bias = (int32_t*)(A + o_tab + t_bias);
@@ -615,11 +707,11 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     unsigned long long* d_status = (unsigned long long*)(A + o_status);
     int32_t* d_cnt = (int32_t*)(A + o_cnt);
     int64_t* d_off = (int64_t*)(A + o_off);
-    uint32_t* visited = ws->bitmaps;
-    uint32_t* next = ws->bitmaps + words;
+    uint32_t* visited = bitmaps;
+    uint32_t* next = bitmaps + words;
 
-    // stage the small tables through pinned memory
-    char* H = ws->pinned;
+    // the small tables: one host block (pinned, read by the setup kernel; or
+    // copied into the scratch)
     std::memcpy(H + t_fan, P.fan.data(), P.fan.size() * sizeof(int32_t));
     std::memcpy(H + t_bias, P.bias.data(), ni * sizeof(int32_t));
     uint32_t* h_iid = (uint32_t*)(H + t_iid);
@@ -632,9 +724,13 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     // every device step of the call, enqueued on stream s
     auto enqueue = [&](hipStream_t s) -> csaw_status {
         // one kernel clears the control block and look-back words and copies
-        // the table block straight from host memory
-        launch_call_setup((uint32_t*)ctl, (int64_t)ctl_words, (const uint32_t*)ws->pinned_dev,
-                          (uint32_t*)(A + o_tab), (int64_t)(tab_bytes / 4), s);
+        // the table block straight from host memory (scratch calls copied it
+        // before)
+        if (scratch)
+            launch_call_setup((uint32_t*)ctl, (int64_t)ctl_words, nullptr, nullptr, 0, s);
+        else
+            launch_call_setup((uint32_t*)ctl, (int64_t)ctl_words, (const uint32_t*)ws->pinned_dev,
+                              (uint32_t*)(A + o_tab), (int64_t)(tab_bytes / 4), s);
 
         FrontierBuild fb;
         fb.g = g->dev();
@@ -702,12 +798,15 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             p.fi = (const int32_t*)(A + o_fi[l]);
             const int64_t cap = P.fcap[l];
             // the long-list path and the wavefront kernel touch disjoint outputs:
-            // run them side by side
-            HIP_OR_FAIL(hipEventRecord(ws->fork, s));
-            HIP_OR_FAIL(hipStreamWaitEvent(ws->aux, ws->fork, 0));
+            // run them side by side (scratch calls: one after the other)
+            hipStream_t aux = scratch ? s : ws->aux;
+            if (!scratch) {
+                HIP_OR_FAIL(hipEventRecord(ws->fork, s));
+                HIP_OR_FAIL(hipStreamWaitEvent(aux, ws->fork, 0));
+            }
             if (big_path) {
-                ProfScope ps("select_big", ws->aux, true);
-                launch_select_big(p, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), ws->aux,
+                ProfScope ps("select_big", aux, true);
+                launch_select_big(p, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), aux,
                                   ps.ev());
             }
             if (b16 > 0 || b32 > 0) {
@@ -723,8 +822,10 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
                 const int grid = (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 4096);
                 launch_select(p, grid, s, ps.ev());
             }
-            HIP_OR_FAIL(hipEventRecord(ws->join, ws->aux));
-            HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join, 0));
+            if (!scratch) {
+                HIP_OR_FAIL(hipEventRecord(ws->join, aux));
+                HIP_OR_FAIL(hipStreamWaitEvent(s, ws->join, 0));
+            }
             if (l + 1 < L && P.fcap[l + 1] > 0) {
                 ProfScope ps("frontier_build", s, true);
                 build(l + 1, ps.ev());
@@ -737,7 +838,7 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
             cl.num_layers = computed_layers;
             cl.fcount = ctl->fcount;
             cl.ctl = ctl;
-            cl.host_ctl = (SampleCtl*)(ws->pinned_dev + o_hctl);
+            cl.host_ctl = ctl_copy;
             cl.visited = visited;
             cl.nwp = nwp;
             for (int l = 0; l < computed_layers; ++l) {
@@ -752,7 +853,14 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     };
 
     // the call's launch sequence, replayed from its captured graph when enabled
-    {
+    if (scratch) {
+        // the tables, and zero bitmaps: the scratch keeps the last call's contents
+        HIP_OR_FAIL(hipMemcpyAsync(A + o_tab, H, tab_bytes, hipMemcpyHostToDevice, s));
+        launch_fill_u32(bitmaps, 0u, words * 2, s);
+        if ((st = enqueue(s)) != CSAW_OK) return st;
+        HIP_OR_FAIL(hipMemcpyAsync(h_ctl, ctl, sizeof(SampleCtl), hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    } else {
         if (graphs_enabled() && !g_prof.load(std::memory_order_relaxed)) {
             std::vector<int64_t> key = {ni, L, words, nwp, P.total_seeds, out->edge_capacity, (int64_t)(intptr_t)a->seeds,
                                         (int64_t)(intptr_t)out->src, (int64_t)(intptr_t)out->dst,
@@ -808,6 +916,33 @@ csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out
     return CSAW_OK;
 }
 
+csaw_status csaw_sample(csaw_graph g, const csaw_sample_args* a, csaw_sample_out* out, csaw_stream stream) {
+    t_err.clear();
+    return sample_call(g, a, out, stream, nullptr, 0);
+}
+
+csaw_status csaw_sample_noalloc(csaw_graph g, const csaw_sample_args* a, csaw_sample_out* out, csaw_stream stream) {
+    t_err.clear();
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (g->device < 0 || g->device >= kMaxDevices) return fail(CSAW_ERR_UNSUPPORTED, "device %d", g->device);
+    HIP_OR_FAIL(hipSetDevice(g->device));
+    NoAllocDevice& nd = g_noalloc[g->device];
+    std::lock_guard<std::mutex> lk(nd.mu);
+    if (!nd.ready) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CSAW_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        nd.ptr = (char*)p;
+        nd.ready = true;
+    }
+    const csaw_status st = sample_call(g, a, out, stream, nd.ptr, kNoAllocScratchBytes);
+    // an early error may leave work of this call in flight: it ends before
+    // the next call may use the scratch
+    if (st != CSAW_OK) (void)hipStreamSynchronize((hipStream_t)stream);
+    return st;
+}
+
 csaw_status csaw_set_tuning(csaw_graph g, const csaw_tuning* t) {
     t_err.clear();
     if (!g || !t) return fail(CSAW_ERR_INVALID_ARG, "graph or tuning is NULL");
@@ -861,9 +996,10 @@ csaw_status csaw_autotune_sample(csaw_graph g, const csaw_sample_args* a, csaw_s
     return CSAW_OK;
 }
 
-csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int64_t* total_steps,
-                      csaw_stream stream) {
-    t_err.clear();
+// One walk call; its two device counters live in a pooled workspace, or in
+// `scratch` (kWalkScratchBytes of device memory) when that is set.
+static csaw_status walk_call(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int64_t* total_steps,
+                             csaw_stream stream, char* scratch) {
     if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
     if (!a) return fail(CSAW_ERR_INVALID_ARG, "args is NULL");
     if (a->bias_kind < kUniform || a->bias_kind > kMetropolis) return fail(CSAW_ERR_INVALID_ARG, "bad bias kind");
@@ -876,16 +1012,34 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int
     hipStream_t s = (hipStream_t)stream;
     HIP_OR_FAIL(hipSetDevice(g->device));
     csaw_status st;
-    if (a->bias_kind == kNeighborDegree && (st = prepare_bias(g, kNeighborDegree, s)) != CSAW_OK) return st;
+    if (a->bias_kind == kNeighborDegree) {
+        if (scratch) {
+            std::lock_guard<std::mutex> lk(g->mu);
+            if (!g->ppos_deg)
+                return fail(CSAW_ERR_NOT_READY, "the NEIGHBOR_DEGREE tables of this graph are not built yet");
+        } else if ((st = prepare_bias(g, kNeighborDegree, s)) != CSAW_OK) {
+            return st;
+        }
+    }
     if (total_steps) *total_steps = 0;
     if (a->num_walkers == 0) return CSAW_OK;
-    Workspace* ws = acquire(g);
-    Lease rel{g, ws, s};
-    if ((st = ensure_arena(ws, 512)) != CSAW_OK) return st;
-    if ((st = ensure_pinned(ws, 64)) != CSAW_OK) return st;
-    unsigned long long* d_steps = (unsigned long long*)ws->arena;
-    int32_t* d_bad = (int32_t*)(ws->arena + 256);
-    HIP_OR_FAIL(hipMemsetAsync(ws->arena, 0, 512, s));
+    Lease rel{g, nullptr, s};
+    char* dev = scratch;
+    char* host = nullptr;
+    uint64_t readback[kWalkScratchBytes / 8];
+    if (!scratch) {
+        Workspace* ws = acquire(g);
+        rel.w = ws;
+        if ((st = ensure_arena(ws, kWalkScratchBytes)) != CSAW_OK) return st;
+        if ((st = ensure_pinned(ws, kWalkScratchBytes)) != CSAW_OK) return st;
+        dev = ws->arena;
+        host = ws->pinned;
+    } else {
+        host = (char*)readback;
+    }
+    unsigned long long* d_steps = (unsigned long long*)dev;
+    int32_t* d_bad = (int32_t*)(dev + 256);
+    HIP_OR_FAIL(hipMemsetAsync(dev, 0, kWalkScratchBytes, s));
     WalkParams p;
     p.g = g->dev();
     p.bias = a->bias_kind;
@@ -909,15 +1063,26 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int
         launch_walk(p, 65536, s, ps.ev());
     }
     HIP_OR_FAIL(hipGetLastError());
-    HIP_OR_FAIL(hipMemcpyAsync(ws->pinned, ws->arena, 512, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipMemcpyAsync(host, dev, kWalkScratchBytes, hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
     rel.clean = true;
-    const unsigned long long steps = *(unsigned long long*)ws->pinned;
-    const int32_t bad = *(int32_t*)(ws->pinned + 256);
-    if (total_steps) *total_steps = (int64_t)steps;
+    const unsigned long long steps = *(unsigned long long*)host;
+    const int32_t bad = *(int32_t*)(host + 256);
     if (bad) return fail(CSAW_ERR_INVALID_ARG, "a start vertex is outside [0, n)");
+    // a device-written count: at most one step per walker and step index
+    if (steps > (unsigned long long)a->num_walkers * (unsigned long long)a->length)
+        return fail(CSAW_ERR_DEVICE, "the device reported %llu steps for %lld walkers of length %d", steps,
+                    (long long)a->num_walkers, a->length);
+    if (total_steps) *total_steps = (int64_t)steps;
     return CSAW_OK;
 }
+
+csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int64_t* total_steps,
+                      csaw_stream stream) {
+    t_err.clear();
+    return walk_call(g, a, paths, total_steps, stream, nullptr);
+}
+
 
 csaw_status csaw_mdrw(csaw_graph g, const csaw_mdrw_args* a, int32_t* src, int32_t* dst, int64_t* steps,
                       int64_t* total_edges, csaw_stream stream) {
@@ -1052,6 +1217,53 @@ csaw_status csaw_layer_sample(csaw_graph g, const csaw_layer_args* a, int32_t* s
     if (*(int32_t*)ws->pinned) return fail(CSAW_ERR_INVALID_ARG, "seeds out of range, unsorted or repeated");
     return CSAW_OK;
 }
+
+}  // extern "C"
+
+namespace csaw {
+
+csaw_status sample_plan_caps(csaw_graph g, const csaw_sample_args* a, std::vector<int64_t>& fcap,
+                             int64_t* max_edges) {
+    SamplePlan P;
+    const csaw_status st = plan_sample(g, a, P, false);
+    if (st != CSAW_OK) return st;
+    fcap = P.fcap;
+    *max_edges = P.max_edges;
+    return CSAW_OK;
+}
+
+size_t sample_scratch_bytes(csaw_graph g, int32_t ni, int32_t L, const std::vector<int64_t>& fcap) {
+    SampleLayout lay;
+    if (!layout_sample(ni, L, fcap, bitmap_words_per_instance(g->n) * ni, lay)) return SIZE_MAX;
+    return lay.scratch;
+}
+
+csaw_status sample_in_scratch(csaw_graph g, const csaw_sample_args* a, csaw_sample_out* out, hipStream_t stream,
+                              char* scratch, size_t scratch_bytes) {
+    t_err.clear();
+    if (!scratch) return fail(CSAW_ERR_INVALID_ARG, "scratch is NULL");
+    return sample_call(g, a, out, stream, scratch, scratch_bytes);
+}
+
+csaw_status walk_in_scratch(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int64_t* total_steps,
+                            hipStream_t stream, char* scratch) {
+    t_err.clear();
+    if (!scratch) return fail(CSAW_ERR_INVALID_ARG, "scratch is NULL");
+    return walk_call(g, a, paths, total_steps, stream, scratch);
+}
+
+csaw_status prepare_bias_tables(csaw_graph g, int32_t kind, hipStream_t stream) {
+    t_err.clear();
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (kind == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
+    if (kind != kEdgeWeight && kind != kNeighborDegree) return CSAW_OK;
+    HIP_OR_FAIL(hipSetDevice(g->device));
+    return prepare_bias(g, kind, stream);
+}
+
+}  // namespace csaw
+
+extern "C" {
 
 csaw_status csaw_set_allocator(csaw_alloc_fn alloc_fn, csaw_free_fn free_fn, void* user) {
     t_err.clear();

@@ -1,0 +1,156 @@
+"""csaw_sample_noalloc (device scratch, no allocation) against csaw_sample.
+
+Both entry points share the sampling kernels; the no-allocation one takes
+its device memory from the library's fixed per-device scratch array. Every
+call here is compared whole (edges and per-(layer, instance) offsets) with
+csaw_sample on the same arguments, which the other GPU tests compare with the
+oracle. Two calls in a row, the second smaller, check that the scratch keeps
+no state between calls.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2009_09103_amd import csaw, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def outputs(g, offs, fanouts, bias, fill=-7):
+    cap = max(g.sample_bound(offs, fanouts, bias), 1)
+    L = np.asarray(fanouts).shape[-1]
+    ni = len(offs) - 1
+    return (torch.full((cap,), fill, dtype=torch.int32, device=DEV),
+            torch.full((cap,), fill, dtype=torch.int32, device=DEV),
+            torch.full((L * ni + 1,), fill, dtype=torch.int64, device=DEV))
+
+
+def check_pair(g, offs, seeds, fanouts, bias, rng_seed, **kw):
+    """csaw_sample, then csaw_sample_noalloc on fresh buffers: equal whole."""
+    ref = g.sample(offs, seeds, fanouts, bias, rng_seed=rng_seed, **kw)
+    seeds_dev = torch.from_numpy(np.ascontiguousarray(seeds, dtype=np.int32)).to(DEV)
+    out = outputs(g, offs, fanouts, bias)
+    torch.cuda.synchronize()
+    res = g.sample_noalloc(offs, seeds_dev, fanouts, out, bias, rng_seed=rng_seed, **kw)
+    assert res.num_edges == ref.num_edges
+    assert torch.equal(res.src, ref.src)
+    assert torch.equal(res.dst, ref.dst)
+    assert torch.equal(res.offsets, ref.offsets)
+    return res.num_edges
+
+
+@pytest.fixture(scope="module")
+def rmat16():
+    rp, col = inputs.rmat_csr(16, 16 << 16, 1616)
+    ew = inputs.dst_outdeg_weights(rp, col)
+    g = csaw.Graph(rp, col, ew)
+    return rp, col, ew, g
+
+
+def mixed_instances(rp, col, ni, seed):
+    gen = inputs.rng(seed)
+    pool = inputs.non_isolated(rp, col)
+    counts = gen.integers(1, 300, size=ni)
+    seeds = [inputs.distinct_seeds(gen, pool, int(c)) for c in counts]
+    offs = np.zeros(ni + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(s) for s in seeds])
+    choices = ([25, 10, 5], [10, 5, 0], [64, 3, 0], [-1, 2, 2])
+    fan = np.array([choices[i % len(choices)] for i in range(ni)], dtype=np.int32)
+    bias = [(csaw.UNIFORM, csaw.EDGE_WEIGHT, csaw.NEIGHBOR_DEGREE)[i % 3] for i in range(ni)]
+    return offs, np.concatenate(seeds).astype(np.int32), fan, bias
+
+
+def test_two_calls_in_a_row_second_smaller(rmat16):
+    rp, col, ew, g = rmat16
+    offs, seeds, fan, bias = mixed_instances(rp, col, 24, 71)
+    big = check_pair(g, offs, seeds, fan, bias, rng_seed=5, instance_base=1000)
+    so, sd = inputs.single_instance_seeds(rp, col, 64, 72)
+    small = check_pair(g, so, sd, [10, 5], csaw.UNIFORM, rng_seed=6)
+    assert big > small > 0
+    # the first call again: the smaller one left nothing behind
+    check_pair(g, offs, seeds, fan, bias, rng_seed=5, instance_base=1000)
+
+
+def test_rounds_and_forest_fire(rmat16):
+    rp, col, ew, g = rmat16
+    so, sd = inputs.single_instance_seeds(rp, col, 500, 73)
+    check_pair(g, so, sd, [25, 10], csaw.NEIGHBOR_DEGREE, rng_seed=7, rounds=csaw.DIRECT_ONLY)
+    check_pair(g, so, sd, [25, 10], csaw.EDGE_WEIGHT, rng_seed=8, rounds=2)
+    check_pair(g, so, sd, [-1, -1], csaw.UNIFORM, rng_seed=9, burn=int(0.7 * 2 ** 32))
+
+
+def test_edge_cases(rmat16):
+    rp, col, ew, g = rmat16
+    # no instances, no layers, an empty seed set
+    check_pair(g, np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros((0, 2), dtype=np.int32),
+               csaw.UNIFORM, rng_seed=1)
+    so, sd = inputs.single_instance_seeds(rp, col, 10, 74)
+    check_pair(g, so, sd, np.zeros(0, dtype=np.int32), csaw.UNIFORM, rng_seed=1)
+    check_pair(g, np.array([0, 0, 10], dtype=np.int64), sd, [5, 5], csaw.NEIGHBOR_DEGREE, rng_seed=2)
+    # capacity too small: OUT_OF_MEMORY with the total reported, then a clean call
+    seeds_dev = torch.from_numpy(sd).to(DEV)
+    out = (torch.empty(3, dtype=torch.int32, device=DEV), torch.empty(3, dtype=torch.int32, device=DEV),
+           torch.empty(3, dtype=torch.int64, device=DEV))
+    with pytest.raises(csaw.CsawError) as ei:
+        g.sample_noalloc(so, seeds_dev, [25, 10], out, csaw.UNIFORM, rng_seed=3)
+    assert ei.value.status == 2
+    check_pair(g, so, sd, [25, 10], csaw.UNIFORM, rng_seed=3)
+
+
+def test_rejects_more_than_its_scratch():
+    # 512 instances of a 2^22-vertex graph need 2 * 512 * 2^17 bitmap words
+    # (512 MiB): refused on the host before any device work
+    n = 1 << 22
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.minimum(np.arange(1, n + 1), 4)
+    col = np.array([1, 2, 3, 0], dtype=np.int32)
+    g = csaw.Graph(rp, col)
+    ni = 512
+    offs = np.arange(ni + 1, dtype=np.int64)
+    seeds = torch.zeros(ni, dtype=torch.int32, device=DEV)
+    out = outputs(g, offs, [2], csaw.UNIFORM)
+    with pytest.raises(csaw.CsawError) as ei:
+        g.sample_noalloc(offs, seeds, [2], out, csaw.UNIFORM, rng_seed=1)
+    assert ei.value.status == 2 and "scratch" in str(ei.value)
+    # a call that fits still works
+    check_pair(g, offs[:3], seeds[:2].cpu().numpy(), [2], csaw.UNIFORM, rng_seed=1)
+
+
+def test_degree_tables_must_exist(rmat16):
+    rp, col, ew, _ = rmat16
+    g = csaw.Graph(rp, col, ew)  # fresh graph: no NEIGHBOR_DEGREE tables yet
+    so, sd = inputs.single_instance_seeds(rp, col, 50, 75)
+    seeds_dev = torch.from_numpy(sd).to(DEV)
+    out = outputs(g, so, [5], csaw.NEIGHBOR_DEGREE)
+    with pytest.raises(csaw.CsawError) as ei:
+        g.sample_noalloc(so, seeds_dev, [5], out, csaw.NEIGHBOR_DEGREE, rng_seed=1)
+    assert ei.value.status == 5
+    check_pair(g, so, sd, [5], csaw.NEIGHBOR_DEGREE, rng_seed=1)  # csaw_sample builds them first
+
+
+def test_full_size_degree_biased_rmat22():
+    rec = inputs.DEGREE_BIASED
+    rp, col = inputs.graph_for(rec)
+    g = csaw.Graph(rp, col)
+    offs, seeds = inputs.single_instance_seeds(rp, col, rec["num_seeds"], rec["seed_rng"])
+    for rs in rec["rng_seeds"]:
+        check_pair(g, offs, seeds, rec["fanouts"], csaw.NEIGHBOR_DEGREE, rng_seed=rs)
+
+
+def test_allocates_no_device_memory(rmat16):
+    rp, col, ew, g = rmat16
+    offs, seeds, fan, bias = mixed_instances(rp, col, 16, 76)
+    seeds_dev = torch.from_numpy(seeds).to(DEV)
+    out = outputs(g, offs, fan, bias)
+    g.sample_noalloc(offs, seeds_dev, fan, out, bias, rng_seed=11)  # warm-up
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    alloc0 = torch.cuda.memory_allocated()
+    for rs in (12, 13, 14):
+        g.sample_noalloc(offs, seeds_dev, fan, out, bias, rng_seed=rs)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert torch.cuda.memory_allocated() == alloc0
+    assert free1 >= free0
