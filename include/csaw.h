@@ -63,7 +63,8 @@ typedef enum {
     CSAW_ERR_DEVICE = 3,         /* a HIP call failed                         */
     CSAW_ERR_BUSY = 4,           /* server queue full                         */
     CSAW_ERR_NOT_READY = 5,      /* server result not finished yet            */
-    CSAW_ERR_UNSUPPORTED = 6     /* valid but outside this build's limits     */
+    CSAW_ERR_UNSUPPORTED = 6,    /* valid but outside this build's limits     */
+    CSAW_ERR_CANCELLED = 7       /* server request cancelled before it ran    */
 } csaw_status;
 
 /* EdgeBias kinds (Eq. edgebias, Section III-C; Table tbl:samplespace).
@@ -391,22 +392,30 @@ csaw_status csaw_set_allocator(csaw_alloc_fn alloc_fn, csaw_free_fn free_fn, voi
 
 /* ---------------------------------------------------------------- serving */
 
-/* A request server over one resident graph: requests (one sampling instance
- * or one batch of walkers each) are submitted from any thread with host
- * inputs; they are admitted while the device memory they need fits the
- * budget; executor threads, each with its own stream, take every admitted
- * sampling request that is waiting at that moment into one multi-instance
- * csaw_sample call (continuous batching) and run walk requests as they come,
- * so that requests arriving while others run overlap with them on the device.
- * A request's result is bit-identical to running it alone: its draws are
- * keyed by its own id and rng_seed. */
+/* A request server over one resident graph (the batched multi-instance
+ * setting of Section V taken to a request stream): requests -- one sampling
+ * instance or one batch of walkers each -- are submitted from any thread with
+ * host inputs. Executor threads, each with its own stream and one block of
+ * device memory allocated when the server is created, take the request at the
+ * head of the queue and, if it is a sampling request, every waiting sampling
+ * request whose addition keeps the batch's exact device need (seeds, edge
+ * outputs, offsets, frontiers, instance bitmaps) within the block, into one
+ * multi-instance csaw_sample-equivalent call (continuous batching); walk
+ * requests run one per call. Requests that arrive while others run are
+ * admitted as executors and memory free up, and their work overlaps on the
+ * device. Serving allocates no device memory: the server holds exactly the
+ * blocks it allocated at creation. A request's result is bit-identical to
+ * running it alone: its draws are keyed by its own id and rng_seed. If a batch
+ * fails, its requests are run again one by one, so that only a faulty request
+ * reports an error. */
 typedef struct csaw_server_s* csaw_server;
 
 typedef struct {
-    int64_t memory_budget_bytes;  /* device memory of admitted requests (0: 32 GiB)  */
+    int64_t memory_budget_bytes;  /* device memory the server allocates at creation,
+                                     split evenly among its executors (0: 32 GiB) */
     int32_t max_batch;            /* most sampling requests per call (0: 512)        */
     int32_t queue_capacity;       /* most waiting requests before BUSY (0: 65536)    */
-    int32_t num_streams;          /* executor threads/streams (0: 2)                 */
+    int32_t num_streams;          /* executor threads/streams, 1..16 (0: 2)          */
 } csaw_server_config;
 
 typedef enum { CSAW_REQUEST_SAMPLE = 0, CSAW_REQUEST_WALK = 1 } csaw_request_kind;
@@ -448,11 +457,15 @@ typedef struct {
     double total_us;              /* until its result was in host memory           */
 } csaw_result;
 
-/* Errors: INVALID_ARG (bad config). The server keeps g; g must outlive it. */
+/* Errors: INVALID_ARG (bad config); OUT_OF_MEMORY if the executors' device
+ * blocks or pinned staging buffers cannot be allocated. Builds the graph's
+ * degree (and edge-weight) tables first, so that no request does. The server
+ * keeps g; g must outlive it. */
 csaw_status csaw_server_create(csaw_graph g, const csaw_server_config* cfg, csaw_server* out);
 /* Validates and copies the request (INVALID_ARG: bad ids, bias kind, sizes;
- * OUT_OF_MEMORY: the request alone exceeds the budget; BUSY: queue full).
- * HOST out: ticket, used to fetch the result. */
+ * OUT_OF_MEMORY: the request alone needs more device memory than one
+ * executor's block; BUSY: queue full). HOST out: ticket, used to fetch the
+ * result. */
 csaw_status csaw_server_submit(csaw_server s, const csaw_request* req, uint64_t* ticket);
 /* NOT_READY until the request is done; then hands over *result (the caller
  * frees it with csaw_result_free). INVALID_ARG for an unknown ticket. */
@@ -460,6 +473,13 @@ csaw_status csaw_server_poll(csaw_server s, uint64_t ticket, csaw_result** resul
 /* As poll, but waits up to timeout_us (< 0: no limit). */
 csaw_status csaw_server_wait(csaw_server s, uint64_t ticket, int64_t timeout_us, csaw_result** result);
 void csaw_result_free(csaw_result* r);
+/* Withdraws a request that has not started: its result (fetched with poll or
+ * wait as usual) then has status CANCELLED. BUSY if it is already running or
+ * done; INVALID_ARG for an unknown ticket. */
+csaw_status csaw_server_cancel(csaw_server s, uint64_t ticket);
+/* HOST outputs (each nullable): device bytes and pinned host bytes the server
+ * holds (fixed from creation to destruction). */
+csaw_status csaw_server_memory(csaw_server s, int64_t* device_bytes, int64_t* pinned_host_bytes);
 /* Finishes every submitted request, stops the executors and frees the
  * server. Results not fetched are freed. */
 csaw_status csaw_server_destroy(csaw_server s);

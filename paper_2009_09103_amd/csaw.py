@@ -26,7 +26,7 @@ ROUNDS = 8
 _BIAS_NAMES = {"uniform": UNIFORM, "edge_weight": EDGE_WEIGHT, "neighbor_degree": NEIGHBOR_DEGREE,
                "node2vec": NODE2VEC, "metropolis_hastings": METROPOLIS_HASTINGS}
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "BUSY", 5: "NOT_READY",
-          6: "UNSUPPORTED"}
+          6: "UNSUPPORTED", 7: "CANCELLED"}
 
 
 class CsawError(RuntimeError):
@@ -103,8 +103,8 @@ class Result(ctypes.Structure):
 EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample", "csaw_sample_noalloc",
            "csaw_sample_bound", "csaw_set_tuning", "csaw_get_tuning", "csaw_autotune_sample", "csaw_walk",
            "csaw_mdrw", "csaw_layer_sample", "csaw_set_allocator", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
-           "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_result_free",
-           "csaw_server_destroy"]
+           "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_server_cancel",
+           "csaw_server_memory", "csaw_result_free", "csaw_server_destroy"]
 
 
 def _load():
@@ -134,6 +134,8 @@ def _load():
     L.csaw_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.csaw_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.POINTER(Result))]
     L.csaw_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ctypes.POINTER(Result))]
+    L.csaw_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.csaw_server_memory.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     L.csaw_result_free.argtypes = [ctypes.POINTER(Result)]
     L.csaw_server_destroy.argtypes = [vp]
     for f in EXPORTS:
@@ -529,6 +531,21 @@ class Server:
             return None
         _check(st)
         return self._take(rp)
+
+    def cancel(self, ticket: int) -> bool:
+        """Withdraws a request that has not started (csaw_server_cancel); its
+        result then has status CANCELLED. False if it already runs or ran."""
+        st = lib.csaw_server_cancel(self._h, ticket)
+        if st == 4:
+            return False
+        _check(st)
+        return True
+
+    def memory(self):
+        """(device bytes, pinned host bytes) the server holds."""
+        d, h = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.csaw_server_memory(self._h, ctypes.byref(d), ctypes.byref(h)))
+        return d.value, h.value
 
     def close(self):
         if getattr(self, "_h", None):

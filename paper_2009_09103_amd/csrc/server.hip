@@ -1,7 +1,15 @@
 // server.hip -- request server over one resident graph (csaw_server_* in
-// include/csaw.h): admission by device-memory budget, continuous batching of
-// sampling requests into multi-instance calls, executor threads with their
-// own streams so that batches overlap on the device, per-request latency.
+// include/csaw.h).
+//
+// Executors are threads, each with its own stream and one block of device
+// memory allocated when the server is created (the memory budget split
+// evenly), plus two pinned host staging buffers. A sampling batch lays out its
+// seeds, edge outputs, segment offsets and the sampling call's scratch in
+// that block; requests join a batch while the batch's exact device need
+// fits. Serving therefore allocates no device memory: what the server holds is
+// fixed at creation, and admission is by the very bytes a batch occupies.
+// Results travel device -> pinned staging -> the result's host arrays in
+// chunks, so no copy targets pageable memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,16 +18,23 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/csaw.h"
+#include "internal.h"
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+constexpr size_t kStageBytes = size_t(16) << 20;  // bytes of each pinned staging buffer
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Request {
     uint64_t ticket = 0;
@@ -29,89 +44,15 @@ struct Request {
     std::vector<int32_t> seeds, fanouts, starts;
     int32_t length = 0;
     uint32_t wr = 1, wc = 1, wo = 1;
-    int64_t mem = 0;
+    std::vector<int64_t> fcap;  // sampling: frontier capacity per layer, alone
+    int64_t max_edges = 0;      // sampling: edge bound, alone
+    size_t need = 0;            // device bytes of the request alone
     Clock::time_point t_submit;
-};
-
-template <class T>
-struct DevBuf {
-    T* p = nullptr;
-    size_t cap = 0;
-    bool ensure(size_t n) {
-        if (cap >= n) return true;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-        const size_t c = std::max<size_t>(n + n / 4, 1024);
-        if (hipMalloc((void**)&p, c * sizeof(T)) != hipSuccess) return false;
-        cap = c;
-        return true;
-    }
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-};
-
-template <class T>
-struct HostBuf {
-    T* p = nullptr;
-    size_t cap = 0;
-    bool ensure(size_t n) {
-        if (cap >= n) return true;
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-        cap = 0;
-        const size_t c = std::max<size_t>(n + n / 4, 1024);
-        if (hipHostMalloc((void**)&p, c * sizeof(T), hipHostMallocDefault) != hipSuccess) return false;
-        cap = c;
-        return true;
-    }
-    ~HostBuf() {
-        if (p) (void)hipHostFree(p);
-    }
 };
 
 double us_between(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration<double, std::micro>(b - a).count();
 }
-
-}  // namespace
-
-// Buffers of one executor, kept across batches.
-struct Exec {
-    hipStream_t st = nullptr;
-    DevBuf<int32_t> d_seeds, d_src, d_dst, d_starts, d_paths;
-    DevBuf<int64_t> d_off;
-    HostBuf<int32_t> h_src, h_dst, h_seeds;
-    HostBuf<int64_t> h_off;
-};
-
-struct csaw_server_s {
-    csaw_graph g = nullptr;
-    csaw_server_config cfg{};
-    int device = 0;
-    int64_t n = 0, m = 0, max_deg = 0;
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<Request*> queue;
-    std::unordered_map<uint64_t, csaw_result*> done;
-    std::unordered_map<uint64_t, bool> known;  // ticket -> not yet handed over
-    int64_t inflight_mem = 0;
-    int inflight_batches = 0;
-    uint64_t next_ticket = 1;
-    bool stop = false;
-    std::vector<std::thread> workers;
-
-    void worker();
-    void run_sample_batch(std::vector<Request*>& batch, Exec& x, Clock::time_point t0);
-    void run_walk(Request* r, Exec& x, Clock::time_point t0);
-    void finish(Request* r, csaw_result* res);
-
-};
-
-namespace {
-
-thread_local std::string t_srv_err;
 
 csaw_result* new_result(int32_t kind, csaw_status st) {
     csaw_result* r = (csaw_result*)std::calloc(1, sizeof(csaw_result));
@@ -122,46 +63,140 @@ csaw_result* new_result(int32_t kind, csaw_status st) {
     return r;
 }
 
-int64_t sample_request_mem(const csaw_server_s* s, const Request& r) {
-    // edges out (8 B), frontier entries (~36 B), per-instance bitmaps, seeds
-    int64_t B = std::min<int64_t>((int64_t)r.seeds.size(), s->n), edges = 0, fr = B;
-    for (int32_t f : r.fanouts) {
-        if (f == 0) break;
-        const int64_t per = f < 0 ? s->max_deg : std::min<int64_t>(f, s->max_deg);
-        const int64_t e = std::min<int64_t>(B * per, s->m);
-        edges += e;
-        B = std::min<int64_t>(e, s->n);
-        fr += B;
+// Aggregate shape of a sampling batch: everything its device layout depends on.
+struct BatchShape {
+    int32_t ni = 0, L = 0;
+    int64_t seeds = 0, edges = 0;
+    std::vector<int64_t> fcap;  // [CSAW_MAX_LAYERS + 1], summed over the batch
+
+    BatchShape() : fcap(CSAW_MAX_LAYERS + 1, 0) {}
+    void add(const Request& r) {
+        ++ni;
+        L = std::max<int32_t>(L, (int32_t)r.fanouts.size());
+        seeds += (int64_t)r.seeds.size();
+        edges += r.max_edges;
+        for (size_t l = 0; l < r.fcap.size(); ++l) fcap[l] += r.fcap[l];
     }
-    const int64_t nwp = ((s->n + 31) / 32 + 3) / 4 * 4;
-    return edges * 8 + fr * 36 + nwp * 8 + (int64_t)r.seeds.size() * 4 + 4096;
+};
+
+// Device layout of a sampling batch in an executor's block.
+struct BatchLayout {
+    size_t o_seeds, o_src, o_dst, o_off, o_scratch, scratch, total;
+};
+
+BatchLayout batch_layout(csaw_graph g, const BatchShape& b) {
+    BatchLayout y;
+    size_t at = 0;
+    y.o_seeds = at;
+    at = align_up(at + (size_t)std::max<int64_t>(b.seeds, 1) * sizeof(int32_t));
+    y.o_src = at;
+    at = align_up(at + (size_t)std::max<int64_t>(b.edges, 1) * sizeof(int32_t));
+    y.o_dst = at;
+    at = align_up(at + (size_t)std::max<int64_t>(b.edges, 1) * sizeof(int32_t));
+    y.o_off = at;
+    at = align_up(at + ((size_t)b.L * b.ni + 1) * sizeof(int64_t));
+    y.o_scratch = at;
+    const std::vector<int64_t> fc(b.fcap.begin(), b.fcap.begin() + b.L + 1);
+    y.scratch = csaw::sample_scratch_bytes(g, b.ni, b.L, fc);
+    y.total = y.scratch == SIZE_MAX ? SIZE_MAX : at + y.scratch;
+    return y;
+}
+
+size_t walk_need(int64_t nw, int32_t length) {
+    return align_up((size_t)std::max<int64_t>(nw, 1) * sizeof(int32_t)) +
+           align_up((size_t)std::max<int64_t>(nw, 1) * ((size_t)length + 1) * sizeof(int32_t)) + csaw::kWalkScratch;
 }
 
 }  // namespace
 
+// One executor: its stream, its device block and its staging buffers.
+struct Exec {
+    hipStream_t st = nullptr;
+    char* dev = nullptr;
+    size_t bytes = 0;
+    char* stage[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+
+    // host -> device through the staging buffers
+    bool to_device(char* d, const char* h, size_t n) {
+        for (size_t off = 0, k = 0; off < n; off += kStageBytes, ++k) {
+            const size_t len = std::min(kStageBytes, n - off);
+            char* b = stage[k & 1];
+            if (k >= 2 && hipEventSynchronize(ev[k & 1]) != hipSuccess) return false;
+            std::memcpy(b, h + off, len);
+            if (hipMemcpyAsync(d + off, b, len, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+            if (hipEventRecord(ev[k & 1], st) != hipSuccess) return false;
+        }
+        return hipStreamSynchronize(st) == hipSuccess;
+    }
+    // device -> host: chunk [off, off + len) of the source goes to sink(off, data, len)
+    bool to_host(const char* d, size_t n, const std::function<void(size_t, const char*, size_t)>& sink) {
+        size_t prev_off = 0, prev_len = 0;
+        for (size_t off = 0, k = 0; off < n; off += kStageBytes, ++k) {
+            const size_t len = std::min(kStageBytes, n - off);
+            if (hipMemcpyAsync(stage[k & 1], d + off, len, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
+            if (hipEventRecord(ev[k & 1], st) != hipSuccess) return false;
+            if (k >= 1) {  // the previous chunk, while this one is in flight
+                if (hipEventSynchronize(ev[(k - 1) & 1]) != hipSuccess) return false;
+                sink(prev_off, stage[(k - 1) & 1], prev_len);
+            }
+            prev_off = off;
+            prev_len = len;
+        }
+        if (n == 0) return true;
+        const size_t last = (n - 1) / kStageBytes;
+        if (hipEventSynchronize(ev[last & 1]) != hipSuccess) return false;
+        sink(prev_off, stage[last & 1], prev_len);
+        return true;
+    }
+};
+
+struct csaw_server_s {
+    csaw_graph g = nullptr;
+    csaw_server_config cfg{};
+    int device = 0;
+    int64_t n = 0;
+    std::vector<Exec> execs;
+    size_t exec_bytes = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::unordered_map<uint64_t, csaw_result*> done;
+    std::unordered_map<uint64_t, int> state;  // ticket -> kQueued / kRunning / kDone (not handed over)
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::vector<std::thread> workers;
+
+    enum { kQueued = 0, kRunning = 1, kDone = 2 };
+
+    void worker(Exec& x);
+    void run_sample_batch(std::vector<Request*>& batch, Exec& x, Clock::time_point t0);
+    void run_walk(Request* r, Exec& x, Clock::time_point t0);
+    void finish(Request* r, csaw_result* res);
+    void free_execs();
+};
+
 void csaw_server_s::finish(Request* r, csaw_result* res) {
     std::lock_guard<std::mutex> lk(mu);
     done[r->ticket] = res;
+    state[r->ticket] = kDone;
     cv_done.notify_all();
 }
 
 void csaw_server_s::run_walk(Request* r, Exec& x, Clock::time_point t0) {
-    hipStream_t st = x.st;
     const int64_t nw = (int64_t)r->starts.size();
     const int64_t L1 = (int64_t)r->length + 1;
     csaw_result* res = new_result(CSAW_REQUEST_WALK, CSAW_OK);
     if (!res) return finish(r, nullptr);
     res->num_walkers = nw;
     res->length = r->length;
-    res->paths = (int32_t*)std::malloc(std::max<int64_t>(nw * L1, 1) * sizeof(int32_t));
     res->queued_us = us_between(r->t_submit, t0);
-    DevBuf<int32_t>& d_starts = x.d_starts;
-    DevBuf<int32_t>& d_paths = x.d_paths;
-    csaw_status stt = CSAW_OK;
-    if (!res->paths || !d_starts.ensure(std::max<int64_t>(nw, 1)) || !d_paths.ensure(std::max<int64_t>(nw * L1, 1)))
-        stt = CSAW_ERR_OUT_OF_MEMORY;
-    if (stt == CSAW_OK && nw > 0 &&
-        hipMemcpyAsync(d_starts.p, r->starts.data(), nw * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
+    res->paths = (int32_t*)std::malloc((size_t)std::max<int64_t>(nw * L1, 1) * sizeof(int32_t));
+    csaw_status stt = res->paths ? CSAW_OK : CSAW_ERR_OUT_OF_MEMORY;
+    char* d_starts = x.dev;
+    char* d_paths = x.dev + align_up((size_t)std::max<int64_t>(nw, 1) * sizeof(int32_t));
+    char* d_scratch = d_paths + align_up((size_t)std::max<int64_t>(nw, 1) * (size_t)L1 * sizeof(int32_t));
+    if (stt == CSAW_OK && nw > 0 && !x.to_device(d_starts, (const char*)r->starts.data(), (size_t)nw * sizeof(int32_t)))
         stt = CSAW_ERR_DEVICE;
     if (stt == CSAW_OK) {
         csaw_walk_args a{};
@@ -170,79 +205,63 @@ void csaw_server_s::run_walk(Request* r, Exec& x, Clock::time_point t0) {
         a.w_common = r->wc;
         a.w_outward = r->wo;
         a.num_walkers = nw;
-        a.starts = d_starts.p;
+        a.starts = (const int32_t*)d_starts;
         a.walker_base = r->id;
         a.length = r->length;
         a.rng_seed = r->rng_seed;
-        a.walker_ids = nullptr;
         int64_t steps = 0;
-        stt = csaw_walk(g, &a, d_paths.p, &steps, st);
+        stt = csaw::walk_in_scratch(g, &a, (int32_t*)d_paths, &steps, x.st, d_scratch);
         res->steps = steps;
     }
-    if (stt == CSAW_OK && nw > 0 &&
-        (hipMemcpyAsync(res->paths, d_paths.p, nw * L1 * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-         hipStreamSynchronize(st) != hipSuccess))
-        stt = CSAW_ERR_DEVICE;
+    if (stt == CSAW_OK && nw > 0) {
+        char* out = (char*)res->paths;
+        if (!x.to_host(d_paths, (size_t)(nw * L1) * sizeof(int32_t),
+                       [out](size_t off, const char* p, size_t len) { std::memcpy(out + off, p, len); }))
+            stt = CSAW_ERR_DEVICE;
+    }
     res->status = stt;
     res->total_us = us_between(r->t_submit, Clock::now());
     finish(r, res);
 }
 
 void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Clock::time_point t0) {
-    hipStream_t st = x.st;
     const int32_t ni = (int32_t)batch.size();
-    int32_t L = 0;
-    for (Request* r : batch) L = std::max<int32_t>(L, (int32_t)r->fanouts.size());
+    BatchShape shape;
+    for (Request* r : batch) shape.add(*r);
+    const int32_t L = shape.L;
+    const BatchLayout lay = batch_layout(g, shape);
+    csaw_status stt = lay.total <= x.bytes ? CSAW_OK : CSAW_ERR_OUT_OF_MEMORY;  // batches are formed to fit
     std::vector<int64_t> offs(ni + 1, 0);
     for (int32_t i = 0; i < ni; ++i) offs[i + 1] = offs[i] + (int64_t)batch[i]->seeds.size();
-    std::vector<int32_t> fan((size_t)ni * std::max(L, 1), 0), bias(ni);
+    std::vector<int32_t> fan((size_t)ni * std::max(L, 1), 0), bias(ni), seeds((size_t)offs[ni]);
     std::vector<uint64_t> ids(ni), keys(ni);
     for (int32_t i = 0; i < ni; ++i) {
         std::copy(batch[i]->fanouts.begin(), batch[i]->fanouts.end(), fan.begin() + (size_t)i * L);
+        std::copy(batch[i]->seeds.begin(), batch[i]->seeds.end(), seeds.begin() + offs[i]);
         bias[i] = batch[i]->bias;
         ids[i] = batch[i]->id;
         keys[i] = batch[i]->rng_seed;
     }
-    csaw_sample_args a{};
-    a.num_instances = ni;
-    a.seed_offsets = offs.data();
-    a.num_layers = L;
-    a.fanouts = fan.data();
-    a.fanout_stride = L;
-    a.bias_kinds = bias.data();
-    a.instance_ids = ids.data();
-    a.rng_seeds = keys.data();
-    int64_t bound = 0;
-    csaw_status stt = csaw_sample_bound(g, &a, &bound);
-    DevBuf<int32_t>& d_seeds = x.d_seeds;
-    DevBuf<int32_t>& d_src = x.d_src;
-    DevBuf<int32_t>& d_dst = x.d_dst;
-    DevBuf<int64_t>& d_off = x.d_off;
-    HostBuf<int32_t>& h_src = x.h_src;
-    HostBuf<int32_t>& h_dst = x.h_dst;
-    HostBuf<int64_t>& h_off = x.h_off;
-    const size_t noff = (size_t)L * ni + 1;
-    if (stt == CSAW_OK &&
-        (!d_seeds.ensure(std::max<int64_t>(offs[ni], 1)) || !d_src.ensure(std::max<int64_t>(bound, 1)) ||
-         !d_dst.ensure(std::max<int64_t>(bound, 1)) || !d_off.ensure(noff) || !h_off.ensure(noff)))
-        stt = CSAW_ERR_OUT_OF_MEMORY;
-    if (stt == CSAW_OK && !x.h_seeds.ensure(std::max<int64_t>(offs[ni], 1))) stt = CSAW_ERR_OUT_OF_MEMORY;
-    if (stt == CSAW_OK) {
-        for (int32_t i = 0; i < ni; ++i)
-            std::copy(batch[i]->seeds.begin(), batch[i]->seeds.end(), x.h_seeds.p + offs[i]);
-        if (offs[ni] > 0 &&
-            hipMemcpyAsync(d_seeds.p, x.h_seeds.p, offs[ni] * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
-                hipSuccess)
-            stt = CSAW_ERR_DEVICE;
-    }
+    if (stt == CSAW_OK && offs[ni] > 0 &&
+        !x.to_device(x.dev + lay.o_seeds, (const char*)seeds.data(), (size_t)offs[ni] * sizeof(int32_t)))
+        stt = CSAW_ERR_DEVICE;
     csaw_sample_out out{};
     if (stt == CSAW_OK) {
-        a.seeds = d_seeds.p;
-        out.src = d_src.p;
-        out.dst = d_dst.p;
-        out.edge_capacity = bound;
-        out.offsets = d_off.p;
-        stt = csaw_sample(g, &a, &out, st);
+        csaw_sample_args a{};
+        a.num_instances = ni;
+        a.seed_offsets = offs.data();
+        a.seeds = (const int32_t*)(x.dev + lay.o_seeds);
+        a.num_layers = L;
+        a.fanouts = fan.data();
+        a.fanout_stride = L;
+        a.bias_kinds = bias.data();
+        a.instance_ids = ids.data();
+        a.rng_seeds = keys.data();
+        out.src = (int32_t*)(x.dev + lay.o_src);
+        out.dst = (int32_t*)(x.dev + lay.o_dst);
+        out.edge_capacity = shape.edges;
+        out.offsets = (int64_t*)(x.dev + lay.o_off);
+        stt = csaw::sample_in_scratch(g, &a, &out, x.st, x.dev + lay.o_scratch, x.bytes - lay.o_scratch);
     }
     if (stt != CSAW_OK) {
         if (ni > 1) {  // isolate: every request on its own, so only a faulty one fails
@@ -260,109 +279,128 @@ void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Cloc
         return finish(batch[0], res);
     }
     const int64_t ne = out.num_edges;
-    if (!h_src.ensure(std::max<int64_t>(ne, 1)) || !h_dst.ensure(std::max<int64_t>(ne, 1)) ||
-        (ne > 0 && (hipMemcpyAsync(h_src.p, d_src.p, ne * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-                    hipMemcpyAsync(h_dst.p, d_dst.p, ne * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess)) ||
-        hipMemcpyAsync(h_off.p, d_off.p, noff * sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
-        for (Request* r : batch) finish(r, new_result(CSAW_REQUEST_SAMPLE, CSAW_ERR_DEVICE));
-        return;
-    }
+    const size_t noff = (size_t)L * ni + 1;
+    std::vector<int64_t> h_off(noff);
+    bool ok = x.to_host(x.dev + lay.o_off, noff * sizeof(int64_t), [&h_off](size_t off, const char* p, size_t len) {
+        std::memcpy((char*)h_off.data() + off, p, len);
+    });
     // the segment offsets come from device memory: check them before they size
-    // host copies (monotone, inside [0, ne])
-    bool offsets_ok = h_off.p[0] >= 0 && h_off.p[noff - 1] == ne;
-    for (size_t j = 1; offsets_ok && j < noff; ++j) offsets_ok = h_off.p[j] >= h_off.p[j - 1];
-    if (!offsets_ok) {
-        for (Request* r : batch) finish(r, new_result(CSAW_REQUEST_SAMPLE, CSAW_ERR_DEVICE));
-        return;
-    }
-    const Clock::time_point t_end = Clock::now();
-    for (int32_t i = 0; i < ni; ++i) {
-        Request* r = batch[i];
-        const int32_t Li = (int32_t)r->fanouts.size();
-        csaw_result* res = new_result(CSAW_REQUEST_SAMPLE, CSAW_OK);
-        if (!res) {
-            finish(r, nullptr);
+    // host copies (monotone, from 0 to ne <= capacity)
+    ok = ok && ne >= 0 && ne <= shape.edges && h_off[0] == 0 && h_off[noff - 1] == ne;
+    for (size_t j = 1; ok && j < noff; ++j) ok = h_off[j] >= h_off[j - 1];
+    std::vector<csaw_result*> res(ni, nullptr);
+    std::vector<int64_t> base(ni, 0);  // edges of instance i before its layer l (filled per layer below)
+    for (int32_t i = 0; ok && i < ni; ++i) {
+        const int32_t Li = (int32_t)batch[i]->fanouts.size();
+        res[i] = new_result(CSAW_REQUEST_SAMPLE, CSAW_OK);
+        if (!res[i]) continue;
+        int64_t cnt = 0;
+        for (int32_t l = 0; l < L; ++l) cnt += h_off[(size_t)l * ni + i + 1] - h_off[(size_t)l * ni + i];
+        res[i]->num_edges = cnt;
+        res[i]->num_layers = Li;
+        res[i]->src = (int32_t*)std::malloc((size_t)std::max<int64_t>(cnt, 1) * sizeof(int32_t));
+        res[i]->dst = (int32_t*)std::malloc((size_t)std::max<int64_t>(cnt, 1) * sizeof(int32_t));
+        res[i]->layer_offsets = (int64_t*)std::malloc(((size_t)Li + 1) * sizeof(int64_t));
+        if (!res[i]->src || !res[i]->dst || !res[i]->layer_offsets) {
+            res[i]->status = CSAW_ERR_OUT_OF_MEMORY;
             continue;
         }
-        int64_t cnt = 0;
-        for (int32_t l = 0; l < Li; ++l) cnt += h_off.p[(size_t)l * ni + i + 1] - h_off.p[(size_t)l * ni + i];
-        res->num_edges = cnt;
-        res->num_layers = Li;
-        res->src = (int32_t*)std::malloc(std::max<int64_t>(cnt, 1) * sizeof(int32_t));
-        res->dst = (int32_t*)std::malloc(std::max<int64_t>(cnt, 1) * sizeof(int32_t));
-        res->layer_offsets = (int64_t*)std::malloc(((size_t)Li + 1) * sizeof(int64_t));
-        if (!res->src || !res->dst || !res->layer_offsets) {
-            res->status = CSAW_ERR_OUT_OF_MEMORY;
-        } else {
-            int64_t w = 0;
-            for (int32_t l = 0; l < Li; ++l) {
-                const int64_t b = h_off.p[(size_t)l * ni + i], e = h_off.p[(size_t)l * ni + i + 1];
-                res->layer_offsets[l] = w;
-                std::memcpy(res->src + w, h_src.p + b, (e - b) * sizeof(int32_t));
-                std::memcpy(res->dst + w, h_dst.p + b, (e - b) * sizeof(int32_t));
-                w += e - b;
-            }
-            res->layer_offsets[Li] = w;
+        int64_t w = 0;
+        for (int32_t l = 0; l < Li; ++l) {
+            res[i]->layer_offsets[l] = w;
+            w += h_off[(size_t)l * ni + i + 1] - h_off[(size_t)l * ni + i];
         }
-        res->queued_us = us_between(r->t_submit, t0);
-        res->total_us = us_between(r->t_submit, t_end);
-        finish(r, res);
+        res[i]->layer_offsets[Li] = w;
+        // an instance has no edges in layers beyond its own
+        for (int32_t l = Li; l < L; ++l)
+            ok = ok && h_off[(size_t)l * ni + i + 1] == h_off[(size_t)l * ni + i];
+    }
+    // segment (l, i) = edges [h_off[l*ni+i], h_off[l*ni+i+1]) go to instance i
+    // at its layer-l offset; segments are in increasing edge order
+    auto scatter = [&](int32_t* csaw_result::*field) {
+        return [&, field](size_t off_bytes, const char* p, size_t len_bytes) {
+            const int64_t e0 = (int64_t)(off_bytes / sizeof(int32_t)), e1 = e0 + (int64_t)(len_bytes / sizeof(int32_t));
+            // first segment ending after e0
+            size_t j = std::upper_bound(h_off.begin(), h_off.end(), e0) - h_off.begin();
+            j = j > 0 ? j - 1 : 0;
+            for (; j + 1 < noff && h_off[j] < e1; ++j) {
+                const int64_t s0 = std::max(h_off[j], e0), s1 = std::min(h_off[j + 1], e1);
+                if (s1 <= s0) continue;
+                const int32_t l = (int32_t)(j / ni), i = (int32_t)(j % ni);
+                csaw_result* r = res[i];
+                if (!r || r->status != CSAW_OK) continue;
+                const int64_t at = r->layer_offsets[l] + (s0 - h_off[j]);
+                std::memcpy(r->*field + at, p + (s0 - e0) * sizeof(int32_t), (size_t)(s1 - s0) * sizeof(int32_t));
+            }
+        };
+    };
+    ok = ok && x.to_host(x.dev + lay.o_src, (size_t)ne * sizeof(int32_t), scatter(&csaw_result::src)) &&
+         x.to_host(x.dev + lay.o_dst, (size_t)ne * sizeof(int32_t), scatter(&csaw_result::dst));
+    const Clock::time_point t_end = Clock::now();
+    for (int32_t i = 0; i < ni; ++i) {
+        if (!ok) {
+            csaw_result_free(res[i]);
+            res[i] = new_result(CSAW_REQUEST_SAMPLE, CSAW_ERR_DEVICE);
+        }
+        if (res[i]) {
+            res[i]->queued_us = us_between(batch[i]->t_submit, t0);
+            res[i]->total_us = us_between(batch[i]->t_submit, t_end);
+        }
+        finish(batch[i], res[i]);
     }
 }
 
-void csaw_server_s::worker() {
+void csaw_server_s::worker(Exec& x) {
     (void)hipSetDevice(device);
-    Exec x;
-    if (hipStreamCreateWithFlags(&x.st, hipStreamNonBlocking) != hipSuccess) x.st = nullptr;
     for (;;) {
         std::vector<Request*> batch;
-        int64_t mem = 0;
         {
             std::unique_lock<std::mutex> lk(mu);
-            for (;;) {
-                if (!queue.empty()) {
-                    Request* head = queue.front();
-                    const bool fits = inflight_mem + head->mem <= cfg.memory_budget_bytes || inflight_batches == 0;
-                    if (fits) break;
-                } else if (stop) {
-                    break;
-                }
-                cv_work.wait(lk);
-            }
+            cv_work.wait(lk, [this] { return !queue.empty() || stop; });
             if (queue.empty()) break;  // stop requested and drained
             Request* head = queue.front();
             queue.pop_front();
             batch.push_back(head);
-            mem = head->mem;
             if (head->kind == CSAW_REQUEST_SAMPLE) {
-                // every sampling request waiting now that still fits joins the batch
+                // continuous batching: every waiting sampling request that still
+                // fits this executor's block joins, in arrival order
+                BatchShape shape;
+                shape.add(*head);
                 for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < cfg.max_batch;) {
                     Request* r = *it;
-                    if (r->kind == CSAW_REQUEST_SAMPLE && inflight_mem + mem + r->mem <= cfg.memory_budget_bytes) {
-                        batch.push_back(r);
-                        mem += r->mem;
-                        it = queue.erase(it);
-                    } else {
-                        ++it;
+                    if (r->kind == CSAW_REQUEST_SAMPLE) {
+                        BatchShape with = shape;
+                        with.add(*r);
+                        if (batch_layout(g, with).total <= x.bytes) {
+                            shape = with;
+                            batch.push_back(r);
+                            it = queue.erase(it);
+                            continue;
+                        }
                     }
+                    ++it;
                 }
             }
-            inflight_mem += mem;
-            ++inflight_batches;
+            for (Request* r : batch) state[r->ticket] = kRunning;
         }
         const Clock::time_point t0 = Clock::now();
         if (batch[0]->kind == CSAW_REQUEST_SAMPLE) run_sample_batch(batch, x, t0);
         else run_walk(batch[0], x, t0);
         for (Request* r : batch) delete r;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            inflight_mem -= mem;
-            --inflight_batches;
-        }
-        cv_work.notify_all();
     }
-    if (x.st) (void)hipStreamDestroy(x.st);
+}
+
+void csaw_server_s::free_execs() {
+    for (Exec& x : execs) {
+        if (x.st) (void)hipStreamSynchronize(x.st);
+        for (int k = 0; k < 2; ++k) {
+            if (x.ev[k]) (void)hipEventDestroy(x.ev[k]);
+            if (x.stage[k]) (void)hipHostFree(x.stage[k]);
+        }
+        if (x.dev) (void)hipFree(x.dev);
+        if (x.st) (void)hipStreamDestroy(x.st);
+    }
+    execs.clear();
 }
 
 extern "C" {
@@ -370,24 +408,55 @@ extern "C" {
 csaw_status csaw_server_create(csaw_graph g, const csaw_server_config* cfg, csaw_server* out) {
     if (!g || !out) return CSAW_ERR_INVALID_ARG;
     *out = nullptr;
+    csaw_server_config c{};
+    if (cfg) c = *cfg;
+    if (c.memory_budget_bytes < 0 || c.max_batch < 0 || c.queue_capacity < 0 || c.num_streams < 0)
+        return CSAW_ERR_INVALID_ARG;
+    if (c.memory_budget_bytes == 0) c.memory_budget_bytes = int64_t(32) << 30;
+    if (c.max_batch == 0) c.max_batch = 512;
+    if (c.queue_capacity == 0) c.queue_capacity = 65536;
+    if (c.num_streams == 0) c.num_streams = 2;
+    if (c.num_streams > 16 || c.max_batch > (1 << 20)) return CSAW_ERR_INVALID_ARG;
     csaw_server s = new csaw_server_s();
     s->g = g;
-    if (cfg) s->cfg = *cfg;
-    if (s->cfg.memory_budget_bytes <= 0) s->cfg.memory_budget_bytes = int64_t(32) << 30;
-    if (s->cfg.max_batch <= 0) s->cfg.max_batch = 512;
-    if (s->cfg.queue_capacity <= 0) s->cfg.queue_capacity = 65536;
-    if (s->cfg.num_streams <= 0) s->cfg.num_streams = 2;
-    if (s->cfg.num_streams > 16 || s->cfg.max_batch > (1 << 20)) {
-        delete s;
-        return CSAW_ERR_INVALID_ARG;
-    }
+    s->cfg = c;
+    int64_t m = 0, max_deg = 0;
     int32_t sorted = 0;
-    csaw_graph_info(g, &s->n, &s->m, &s->max_deg, &sorted);
+    csaw_graph_info(g, &s->n, &m, &max_deg, &sorted);
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return CSAW_ERR_DEVICE;
     }
-    for (int i = 0; i < s->cfg.num_streams; ++i) s->workers.emplace_back([s] { s->worker(); });
+    s->exec_bytes = (size_t)(c.memory_budget_bytes / c.num_streams) / kAlign * kAlign;
+    s->execs.resize(c.num_streams);
+    csaw_status st = CSAW_OK;
+    for (Exec& x : s->execs) {
+        x.bytes = s->exec_bytes;
+        if (hipStreamCreateWithFlags(&x.st, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&x.ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&x.ev[1], hipEventDisableTiming) != hipSuccess) {
+            st = CSAW_ERR_DEVICE;
+            break;
+        }
+        if (hipMalloc((void**)&x.dev, std::max<size_t>(x.bytes, kAlign)) != hipSuccess ||
+            hipHostMalloc((void**)&x.stage[0], kStageBytes, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&x.stage[1], kStageBytes, hipHostMallocDefault) != hipSuccess) {
+            st = CSAW_ERR_OUT_OF_MEMORY;
+            break;
+        }
+    }
+    // edge-weight and degree tables are built before serving, so that no
+    // request builds them (and allocates) while others run
+    if (st == CSAW_OK && !s->execs.empty()) {
+        st = csaw::prepare_bias_tables(g, CSAW_BIAS_NEIGHBOR_DEGREE, s->execs[0].st);
+        if (st == CSAW_OK) (void)csaw::prepare_bias_tables(g, CSAW_BIAS_EDGE_WEIGHT, s->execs[0].st);
+    }
+    if (st != CSAW_OK) {
+        s->free_execs();
+        delete s;
+        return st;
+    }
+    for (Exec& x : s->execs) s->workers.emplace_back([s, &x] { s->worker(x); });
     *out = s;
     return CSAW_OK;
 }
@@ -413,12 +482,21 @@ csaw_status csaw_server_submit(csaw_server s, const csaw_request* q, uint64_t* t
                 delete r;
                 return CSAW_ERR_INVALID_ARG;
             }
-        for (int32_t f : r->fanouts)
-            if (f < -1 || f > 0xFFFF) {
-                delete r;
-                return CSAW_ERR_INVALID_ARG;
-            }
-        r->mem = sample_request_mem(s, *r);
+        const int64_t offs[2] = {0, (int64_t)r->seeds.size()};
+        csaw_sample_args a{};
+        a.num_instances = 1;
+        a.seed_offsets = offs;
+        a.num_layers = q->num_layers;
+        a.fanouts = r->fanouts.data();
+        a.bias_kind = q->bias_kind;
+        const csaw_status st = csaw::sample_plan_caps(s->g, &a, r->fcap, &r->max_edges);
+        if (st != CSAW_OK) {
+            delete r;
+            return st;
+        }
+        BatchShape one;
+        one.add(*r);
+        r->need = batch_layout(s->g, one).total;
     } else if (q->kind == CSAW_REQUEST_WALK) {
         if (q->num_walkers < 0 || (q->num_walkers > 0 && !q->starts) || q->length < 0 || q->bias_kind < 0 ||
             q->bias_kind > CSAW_BIAS_METROPOLIS_HASTINGS) {
@@ -435,12 +513,12 @@ csaw_status csaw_server_submit(csaw_server s, const csaw_request* q, uint64_t* t
         r->wr = q->w_return;
         r->wc = q->w_common;
         r->wo = q->w_outward;
-        r->mem = q->num_walkers * ((int64_t)q->length + 2) * 4 + 4096;
+        r->need = walk_need(q->num_walkers, q->length);
     } else {
         delete r;
         return CSAW_ERR_INVALID_ARG;
     }
-    if (r->mem > s->cfg.memory_budget_bytes) {
+    if (r->need > s->exec_bytes) {  // not even alone in one executor's block
         delete r;
         return CSAW_ERR_OUT_OF_MEMORY;
     }
@@ -452,7 +530,7 @@ csaw_status csaw_server_submit(csaw_server s, const csaw_request* q, uint64_t* t
             return CSAW_ERR_BUSY;
         }
         r->ticket = s->next_ticket++;
-        s->known[r->ticket] = true;
+        s->state[r->ticket] = csaw_server_s::kQueued;
         *ticket = r->ticket;
         s->queue.push_back(r);
     }
@@ -465,25 +543,51 @@ static csaw_status take_result(csaw_server s, uint64_t ticket, csaw_result** res
     if (it == s->done.end()) return CSAW_ERR_NOT_READY;
     *result = it->second;
     s->done.erase(it);
-    s->known.erase(ticket);
+    s->state.erase(ticket);
     return *result ? CSAW_OK : CSAW_ERR_OUT_OF_MEMORY;
 }
 
 csaw_status csaw_server_poll(csaw_server s, uint64_t ticket, csaw_result** result) {
     if (!s || !result) return CSAW_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
-    if (!s->known.count(ticket)) return CSAW_ERR_INVALID_ARG;
+    if (!s->state.count(ticket)) return CSAW_ERR_INVALID_ARG;
     return take_result(s, ticket, result);
 }
 
 csaw_status csaw_server_wait(csaw_server s, uint64_t ticket, int64_t timeout_us, csaw_result** result) {
     if (!s || !result) return CSAW_ERR_INVALID_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
-    if (!s->known.count(ticket)) return CSAW_ERR_INVALID_ARG;
+    if (!s->state.count(ticket)) return CSAW_ERR_INVALID_ARG;
     auto ready = [&] { return s->done.count(ticket) > 0; };
     if (timeout_us < 0) s->cv_done.wait(lk, ready);
     else s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
     return take_result(s, ticket, result);
+}
+
+csaw_status csaw_server_cancel(csaw_server s, uint64_t ticket) {
+    if (!s) return CSAW_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto st = s->state.find(ticket);
+    if (st == s->state.end()) return CSAW_ERR_INVALID_ARG;
+    if (st->second != csaw_server_s::kQueued) return CSAW_ERR_BUSY;  // running or done: too late
+    auto it = std::find_if(s->queue.begin(), s->queue.end(), [ticket](Request* r) { return r->ticket == ticket; });
+    if (it == s->queue.end()) return CSAW_ERR_BUSY;
+    Request* r = *it;
+    s->queue.erase(it);
+    csaw_result* res = new_result(r->kind, CSAW_ERR_CANCELLED);
+    if (res) res->queued_us = res->total_us = us_between(r->t_submit, Clock::now());
+    s->done[ticket] = res;
+    st->second = csaw_server_s::kDone;
+    delete r;
+    s->cv_done.notify_all();
+    return CSAW_OK;
+}
+
+csaw_status csaw_server_memory(csaw_server s, int64_t* device_bytes, int64_t* pinned_host_bytes) {
+    if (!s) return CSAW_ERR_INVALID_ARG;
+    if (device_bytes) *device_bytes = (int64_t)(s->exec_bytes * s->execs.size());
+    if (pinned_host_bytes) *pinned_host_bytes = (int64_t)(2 * kStageBytes * s->execs.size());
+    return CSAW_OK;
 }
 
 void csaw_result_free(csaw_result* r) {
@@ -504,6 +608,7 @@ csaw_status csaw_server_destroy(csaw_server s) {
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();
     for (auto& kv : s->done) csaw_result_free(kv.second);
+    s->free_execs();
     delete s;
     return CSAW_OK;
 }

@@ -1,6 +1,7 @@
 """The request server: continuous batching over a resident graph. Every
 request's result equals the same request run alone (and the oracle), in a
-mix, under a tight memory budget and with several executor streams."""
+mix, under a tight memory budget and with several executor streams;
+cancellation and the server's fixed device memory."""
 import sys
 
 import numpy as np
@@ -62,11 +63,13 @@ def check_alone(csaw, g, rp, col, ew, r, res, with_oracle):
             np.testing.assert_array_equal(res.paths, ref)
 
 
-@pytest.mark.parametrize("streams,budget", [(2, 0), (3, 64 << 20), (1, 0)])
+@pytest.mark.parametrize("streams,budget", [(2, 1 << 30), (3, 24 << 20), (1, 1 << 30)])
 def test_mix_equals_alone(setup, streams, budget):
     csaw, rp, col, ew, g, trace = setup
     say("server streams=%d budget=%d, %d requests" % (streams, budget, len(trace)))
     srv = csaw.Server(g, memory_budget_bytes=budget, num_streams=streams, max_batch=64)
+    dev_bytes, pinned = srv.memory()
+    assert budget - 256 * streams < dev_bytes <= budget and pinned > 0
     tickets = [submit(srv, r) for r in trace]
     results = [srv.wait(t) for t in tickets]
     srv.close()
@@ -97,7 +100,7 @@ def test_submit_errors_and_poll(setup):
 def test_queue_full_reports_busy(setup):
     csaw, rp, col, ew, g, trace = setup
     say("server busy")
-    srv = csaw.Server(g, num_streams=1, queue_capacity=2)
+    srv = csaw.Server(g, num_streams=1, queue_capacity=2, memory_budget_bytes=1 << 30)
     starts = inputs.walker_starts(rp, col, 20000, 1)
     tickets, busy = [], 0
     for i in range(50):
@@ -109,4 +112,23 @@ def test_queue_full_reports_busy(setup):
     assert busy > 0
     for t in tickets:
         assert srv.wait(t).status == 0
+    srv.close()
+
+
+def test_cancel_queued_requests(setup):
+    csaw, rp, col, ew, g, trace = setup
+    say("server cancel")
+    srv = csaw.Server(g, num_streams=1, memory_budget_bytes=1 << 30)
+    starts = inputs.walker_starts(rp, col, 20000, 2)
+    tickets = [srv.submit_walk(starts, 80, 1, rng_seed=i, request_id=i) for i in range(8)]
+    cancelled = [t for t in tickets[4:] if srv.cancel(t)]
+    assert cancelled, "requests queued behind long walks can be cancelled"
+    for t in tickets:
+        res = srv.wait(t)
+        if t in cancelled:
+            assert res.status == 7  # CANCELLED
+        else:
+            assert res.status == 0 and res.paths.shape == (20000, 81)
+    with pytest.raises(csaw.CsawError):
+        srv.cancel(1 << 40)  # unknown ticket
     srv.close()
