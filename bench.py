@@ -1,23 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the biased neighbor-selection hot path on one MI355X.
 
-A step is one full csaw_sample call (every layer: frontier build, select,
-long-list search) over the degree-biased workload: R-MAT 22 (edge factor 16),
-one instance of 8,192 distinct seeds, fanouts [25, 10, 5], bias = out-degree
-of the neighbor, Philox seeds cycling over {1, 2, 3}. Inputs (graph, seeds,
-output buffers) are resident in HBM before timing starts.
+Default workload (--workload served): the served stream on R-MAT 26 (edge
+weights = out-degree of the destination), resident in HBM. A Poisson trace of
+mixed requests (60% neighbor sampling with 64-8,192 seeds, 40% weighted
+walks of 1k-64k walkers, length 10-80) is swept over QPS through the
+continuous-batching server and through the plain path (one request at a
+time); each QPS point is one step. Prints one JSON line: served SEPS (sampled
+edges and walk steps per second of wall time) with p50/p99 latency per
+point against the plain path, the roofline of the dominant kernel (the
+weighted walk) from HIP-event kernel times and the algorithmic byte model,
+and the CPU oracle timed on a sample of the trace on the host.
 
-Prints one JSON line: SEPS (sampled edges per second), the roofline of the
-dominant kernel (select) from HIP-event kernel times and the algorithmic byte
-model, and the CPU oracle timed on the host.
+--workload degree_biased: one full csaw_sample call per step (every layer:
+frontier build, select, long-list search) over R-MAT 22 (edge factor 16), one
+instance of 8,192 distinct seeds, fanouts [25, 10, 5], bias = out-degree of
+the neighbor, Philox seeds cycling over {1, 2, 3}; the sub-wave bucket
+setting is autotuned on the timed call first (--tuning).
 
-The sub-wave bucket setting is autotuned on the timed call first (--tuning).
-
-Other workloads (--workload): batched (4,096 instances in one call against
-4,096 plain calls), node2vec (R-MAT 24 walks), mdrw (multi-dimensional
-random walks), forest_fire (burning probability 0.7, depth 2), metropolis
-(Metropolis-Hastings walks), layer (layer sampling), copy (a 1 GiB device copy, the HBM counter
-calibration).
+Other workloads: batched (4,096 instances in one call against 4,096 plain
+calls), node2vec (R-MAT 24 walks), mdrw (multi-dimensional random walks),
+forest_fire (burning probability 0.7, depth 2), metropolis
+(Metropolis-Hastings walks), layer (layer sampling), copy (a 1 GiB device
+copy, the HBM counter calibration).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -91,23 +96,26 @@ def path_bytes(rowptr, ppos, seeds, dst, offsets, fanouts, weighted, bound=0):
 
 def cpu_baseline(rp, col, offs, seeds, fanouts, bias, min_s=10.0, max_runs=60):
     """The CPU oracle on the host: the whole call, cycling over Philox seeds
-    1, 2, 3 until at least min_s seconds of oracle time have been spent."""
+    1, 2, 3 until at least min_s seconds of oracle time have been spent, on
+    every host thread (each layer's frontier split over them; bit-identical
+    to one thread) and on one thread."""
     import oracle
-    t_used, edges, runs = 0.0, 0, 0
-    threads = oracle.max_threads()
-    while t_used < min_s and runs < max_runs:
-        s = 1 + runs % 3
-        t0 = time.perf_counter()
-        ref = oracle.sample(rp, col, None, offs, seeds, fanouts, bias_kind=bias, rng_seed=s)
-        t_used += time.perf_counter() - t0
-        edges += ref.num_edges
-        runs += 1
-    # one instance: the oracle parallelises over instances, so one thread works
-    used = min(threads, len(offs) - 1)
-    return dict(value=edges / t_used, unit="sampled edges/s", cores=int(used), kind="oracle",
-                sample="full workload (all %d seeds, all layers), %d calls cycling over Philox seeds 1..3, "
-                       "%.1f s; oracle single instance -> 1 thread of %d available" % (
-                           len(seeds), runs, t_used, threads))
+    out = {}
+    for nthreads in (oracle.max_threads(), 1):
+        t_used, edges, runs = 0.0, 0, 0
+        while t_used < (min_s if nthreads > 1 else min_s / 2) and runs < max_runs:
+            s = 1 + runs % 3
+            t0 = time.perf_counter()
+            ref = oracle.sample(rp, col, None, offs, seeds, fanouts, bias_kind=bias, rng_seed=s, nthreads=nthreads)
+            t_used += time.perf_counter() - t0
+            edges += ref.num_edges
+            runs += 1
+        out[nthreads] = (edges / t_used, runs, t_used)
+    nt = max(out)
+    return dict(value=out[nt][0], unit="sampled edges/s", cores=int(nt), kind="oracle", value_1thread=out[1][0],
+                sample="full workload (all %d seeds, all layers), %d calls cycling over Philox seeds 1..3, %.1f s "
+                       "on %d host threads; 1 thread: %d calls, %.1f s" % (
+                           len(seeds), out[nt][1], out[nt][2], nt, out[1][1], out[1][2]))
 
 
 def apply_tuning(g, args, *call, **kw):
@@ -356,11 +364,115 @@ def bench_batched(args):
     }
 
 
-def bench_served(args):
-    """Poisson trace of mixed requests against the request server on R-MAT
-    26 (edge weights = destination out-degree), swept over QPS; the same trace
-    through a one-stream, one-request-at-a-time server is the plain path."""
+def walk_step_bytes(rowptr, paths):
+    """Algorithmic bytes of first-order weighted walk steps, per step from v
+    with d = deg(v): 8 (row-offset pair) + 4 (neighbor id at the pick) + 4
+    (path entry), plus the biases the selection needs: for d <= 512, the d
+    weights of N(v) (4 d); for longer lists, the list's total (8), its chunk
+    totals (8 per 1,024 weights), one chunk's 64 group prefixes (512) and one
+    16-weight group (64), read through the graph's per-list tables."""
+    deg = np.diff(rowptr)
+    cur, nxt = paths[:, :-1], paths[:, 1:]
+    taken = nxt >= 0
+    d = deg[cur[taken]].astype(np.float64)
+    long_ = d > WAVE_MAX_D
+    sel = np.where(long_, 8.0 + 8.0 * np.ceil(d / 1024.0) + 512.0 + 64.0, 4.0 * d)
+    return 16.0 * taken.sum() + sel.sum(), int(taken.sum())
+
+
+def run_server(csaw, g, trace, kw, profile=False):
+    """One pass of a request trace through a fresh server: Poisson arrivals
+    from a client thread, then every result. Returns throughput, latency
+    percentiles and the results."""
     import threading
+    srv = csaw.Server(g, **kw)
+    tickets = [None] * len(trace)
+    errors = []
+    if profile:
+        csaw.profile_reset()
+        csaw.profile_enable(True)
+    start = time.perf_counter()
+
+    def client():
+        try:
+            for k, r in enumerate(trace):
+                delay = r["arrival_s"] - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+                if r["kind"] == "sample":
+                    tickets[k] = srv.submit_sample(r["seeds"], r["fanouts"], r["bias"], rng_seed=r["rng_seed"],
+                                                   request_id=r["id"])
+                else:
+                    tickets[k] = srv.submit_walk(r["starts"], r["length"], r["bias"], rng_seed=r["rng_seed"],
+                                                 request_id=r["id"])
+        except Exception as e:  # reported by the caller
+            errors.append(e)
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    if errors:
+        srv.close()
+        raise errors[0]
+    lat, edges, results = [], 0, []
+    for t in tickets:
+        res = srv.wait(t)
+        if res.status != 0:
+            srv.close()
+            raise RuntimeError("a served request failed with status %d" % res.status)
+        lat.append(res.total_us)
+        edges += res.num_edges
+        results.append(res)
+    wall = time.perf_counter() - start
+    if profile:
+        csaw.profile_enable(False)
+    srv.close()
+    lat = np.array(lat) / 1e3
+    row = {"seps": edges / wall, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "wall_s": wall, "edges": int(edges), "requests": len(trace)}
+    return row, results
+
+
+def served_cpu_baseline(rp, col, ew, trace, qps, min_s=10.0):
+    """The CPU oracle on a bounded sample of the served trace: requests in
+    trace order (sampling requests whole, walk requests on every 16th walker
+    id, an exact subset) until min_s seconds of oracle time; edges/s on all
+    host threads and on one."""
+    import oracle
+    out = {}
+    for nthreads in (oracle.max_threads(), 1):
+        t_used, edges, done = 0.0, 0, 0
+        for r in trace:
+            t0 = time.perf_counter()
+            if r["kind"] == "sample":
+                ref = oracle.sample(rp, col, ew, np.array([0, len(r["seeds"])], dtype=np.int64), r["seeds"],
+                                    r["fanouts"], bias_kind=r["bias"], rng_seed=r["rng_seed"],
+                                    instance_base=r["id"], nthreads=nthreads)
+                edges += ref.num_edges
+            else:
+                sub = np.arange(0, len(r["starts"]), 16)
+                _, steps, _ = oracle.walk(rp, col, ew, r["starts"][sub], r["length"], bias_kind=r["bias"],
+                                          rng_seed=r["rng_seed"], walker_ids=r["id"] + sub.astype(np.uint64),
+                                          nthreads=nthreads)
+                edges += int(steps.sum())
+            t_used += time.perf_counter() - t0
+            done += 1
+            if t_used >= min_s / 2 and nthreads == 1 or t_used >= min_s:
+                break
+        out[nthreads] = (edges / t_used, done, t_used)
+    nt = max(out)
+    return dict(value=out[nt][0], unit="sampled edges/s", cores=int(nt), kind="oracle",
+                value_1thread=out[1][0],
+                sample="the first %d requests of the %g-QPS trace (sampling whole, walks on every 16th walker id), "
+                       "%.1f s on %d host threads; 1 thread: %d requests, %.1f s" % (
+                           out[nt][1], qps, out[nt][2], nt, out[1][1], out[1][2]))
+
+
+def bench_served(args):
+    """Served stream on R-MAT 26 (edge weights = destination out-degree): a
+    Poisson trace of mixed requests (60% sampling, 40% weighted walks) swept
+    over QPS, through the continuous-batching server (three executors, batches
+    of up to 256 requests) and through the plain path (one executor, one
+    request at a time). A step is one QPS point of the served server."""
     import torch
     from paper_2009_09103_amd import csaw, inputs
 
@@ -372,51 +484,112 @@ def bench_served(args):
     ew = inputs.dst_outdeg_weights(rp, col)
     g = csaw.Graph(rp, col, ew)
     log("graph n=%d m=%d ready in %.1fs" % (len(rp) - 1, len(col), time.perf_counter() - t0))
+    served_kw = dict(num_streams=3, max_batch=256, memory_budget_bytes=48 << 30)
+    plain_kw = dict(num_streams=1, max_batch=1, memory_budget_bytes=16 << 30)
+    qps_list = args.qps or [400.0, 1600.0, 6400.0, 25600.0]
     points = []
-    for qps in args.qps:
+    for qps in qps_list:
         trace = inputs.request_trace(rp, col, args.requests, qps, rec["trace_rng"], rec["sample_fraction"])
         row = {"qps": qps}
-        for name, kw in (("served", dict(num_streams=3, max_batch=256)), ("plain", dict(num_streams=1, max_batch=1))):
-            srv = csaw.Server(g, **kw)
-            tickets = [None] * len(trace)
-            start = time.perf_counter()
-
-            def client():
-                for k, r in enumerate(trace):
-                    delay = r["arrival_s"] - (time.perf_counter() - start)
-                    if delay > 0:
-                        time.sleep(delay)
-                    if r["kind"] == "sample":
-                        tickets[k] = srv.submit_sample(r["seeds"], r["fanouts"], r["bias"], rng_seed=r["rng_seed"],
-                                                       request_id=r["id"])
-                    else:
-                        tickets[k] = srv.submit_walk(r["starts"], r["length"], r["bias"], rng_seed=r["rng_seed"],
-                                                     request_id=r["id"])
-            th = threading.Thread(target=client)
-            th.start()
-            th.join()
-            lat, edges = [], 0
-            for t in tickets:
-                res = srv.wait(t)
-                assert res.status == 0
-                lat.append(res.total_us)
-                edges += res.num_edges
-            wall = time.perf_counter() - start
-            srv.close()
-            lat = np.array(lat) / 1e3
-            row[name] = {"seps": edges / wall, "p50_ms": float(np.percentile(lat, 50)),
-                         "p99_ms": float(np.percentile(lat, 99)), "wall_s": wall, "edges": int(edges)}
-            log("qps %g %s: %.3g SEPS, p50 %.1f ms, p99 %.1f ms" % (qps, name, edges / wall, row[name]["p50_ms"],
-                                                                 row[name]["p99_ms"]))
+        for name, kw in (("served", served_kw), ("plain", plain_kw)):
+            log("qps %g %s: %d requests" % (qps, name, len(trace)))
+            row[name], _ = run_server(csaw, g, trace, kw)
+            log("qps %g %s: %.3g SEPS, p50 %.1f ms, p99 %.1f ms, %.2f s" % (
+                qps, name, row[name]["seps"], row[name]["p50_ms"], row[name]["p99_ms"], row[name]["wall_s"]))
+        row["served_over_plain"] = row["served"]["seps"] / row["plain"]["seps"]
         points.append(row)
     best = max(points, key=lambda r: r["served"]["seps"])
-    return {
-        "metric": "served SEPS and p50/p99 latency",
+    # roofline: one more served pass at the best point with kernel events on
+    trace = inputs.request_trace(rp, col, args.requests, best["qps"], rec["trace_rng"], rec["sample_fraction"])
+    _, results = run_server(csaw, g, trace, served_kw, profile=True)
+    kernels = {}
+    for name in ("walk", "select_wave", "select_big", "select_small", "frontier_build", "frontier_init",
+                 "visited_clear"):
+        ms, n = csaw.profile_read(name)
+        kernels[name] = {"ms": ms, "launches": n}
+    wbytes, wsteps = 0.0, 0
+    for r, res in zip(trace, results):
+        if r["kind"] == "walk":
+            b, st = walk_step_bytes(rp, res.paths)
+            wbytes += b
+            wsteps += st
+    walk_ms = kernels["walk"]["ms"]
+    achieved = wbytes / (walk_ms * 1e-3) / 1e9 if walk_ms > 0 else 0.0
+    line = {
+        "metric": "sampled edges/sec (SEPS) + HBM roofline % on 1 GPU; p50/p99 served latency",
         "value": best["served"]["seps"], "unit": "sampled edges/s", "n_gpus": 1, "steps": len(points),
-        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
-        "config": {"workload": rec["name"], "scale": scale, "requests_per_point": args.requests},
+        "warmup": 0, "ms_per_step": best["served"]["wall_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": rec["name"], "graph": "R-MAT scale %d, edge factor 16, edge weight = out-degree of "
+                   "the destination" % scale, "n": len(rp) - 1, "m": len(col),
+                   "requests_per_point": args.requests, "qps": qps_list, "sample_fraction": rec["sample_fraction"],
+                   "served": served_kw, "plain": plain_kw},
+        "p50_ms": best["served"]["p50_ms"], "p99_ms": best["served"]["p99_ms"],
         "points": points,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "walk (k_walk_wave, edge-weight walks)", "launches": kernels["walk"]["launches"],
+                     "avg_launch_us": walk_ms * 1e3 / max(kernels["walk"]["launches"], 1),
+                     "alg_bytes_per_launch": wbytes / max(kernels["walk"]["launches"], 1),
+                     "steps": wsteps},
+        "kernels_ms": {k: v["ms"] for k, v in kernels.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample of the trace")
+        line["cpu_baseline"] = served_cpu_baseline(rp, col, ew, trace, best["qps"])
+    return line
+
+
+def bench_streamed(args):
+    """Out-of-memory sampling: the degree-biased R-MAT 22 call with the
+    graph's adjacency and weights in pinned host memory, in 4 vertex-range
+    partitions of which at most 2 are resident (partition loads inside the
+    timed region), against the same call on the resident graph."""
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    rec = inputs.DEGREE_BIASED
+    log("generating R-MAT %d graph" % rec["scale"])
+    rp, col = inputs.graph_for(rec)
+    offs, seeds = inputs.single_instance_seeds(rp, col, rec["num_seeds"], rec["seed_rng"])
+    g = csaw.Graph(rp, col)
+    dev = g.device
+    seeds_d = torch.from_numpy(seeds).to(dev)
+    cap = g.sample_bound(offs, rec["fanouts"], csaw.NEIGHBOR_DEGREE)
+    out = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+           torch.empty(len(rec["fanouts"]) + 1, dtype=torch.int64, device=dev))
+    pg = csaw.PartitionedGraph(rp, col, None, num_partitions=args.partitions, max_resident=args.resident)
+
+    def timed(graph, stats):
+        for k in range(args.warmup):
+            graph.sample(offs, seeds_d, rec["fanouts"], csaw.NEIGHBOR_DEGREE, rng_seed=1 + k % 3, out=out)
+        torch.cuda.synchronize()
+        edges, loads, nbytes = 0, 0, 0
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            r = graph.sample(offs, seeds_d, rec["fanouts"], csaw.NEIGHBOR_DEGREE, rng_seed=1 + k % 3, out=out)
+            edges += r.num_edges
+            if stats:
+                loads += graph.last_stats[0]
+                nbytes += graph.last_stats[1]
+        torch.cuda.synchronize()
+        return edges, time.perf_counter() - t0, loads, nbytes
+
+    e_s, t_s, loads, nbytes = timed(pg, True)
+    e_m, t_m, _, _ = timed(g, False)
+    log("streamed %.3g edges/s (%.2f loads, %.1f MB per call), in memory %.3g edges/s" % (
+        e_s / t_s, loads / args.steps, nbytes / args.steps / 1e6, e_m / t_m))
+    return {
+        "metric": "sampled edges/sec, graph streamed from host memory in partitions",
+        "value": e_s / t_s, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_s / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": "streamed_degree_biased_rmat22", "partitions": args.partitions,
+                   "max_resident": args.resident, "n": len(rp) - 1, "m": len(col), "seeds": len(seeds),
+                   "fanouts": rec["fanouts"]},
+        "partition_loads_per_call": loads / args.steps, "bytes_loaded_per_call": nbytes / args.steps,
+        "load_GB_per_s": nbytes / t_s / 1e9,
+        "in_memory": {"value": e_m / t_m, "ms_per_step": t_m / args.steps * 1e3},
     }
 
 
@@ -757,10 +930,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="degree_biased")
+    ap.add_argument("--workload", default="served")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--qps", type=float, nargs="*", default=[50.0, 200.0, 800.0])
-    ap.add_argument("--requests", type=int, default=500)
+    ap.add_argument("--qps", type=float, nargs="*", default=None)
+    ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--served-scale", type=int, default=0)
     ap.add_argument("--n2v-scale", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=0,
@@ -768,6 +941,8 @@ def main():
     ap.add_argument("--tuning", default="auto",
                     help='sub-wave buckets of the sampling kernel: "auto", "default" or "bound16,bound32"')
     ap.add_argument("--n2v-stride", type=int, default=64)
+    ap.add_argument("--partitions", type=int, default=4)
+    ap.add_argument("--resident", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs the whole path on a single MI355X "
@@ -784,14 +959,9 @@ def main():
     elif args.workload == "batched":
         line = bench_batched(args)
     elif args.workload == "served":
-        # The Poisson-trace run through csaw_server_* ended in a host-side
-        # segmentation fault after building the R-MAT 26 graph; no cause has
-        # been found in the server or runtime host code, so this workload stays
-        # switched off until one is. The server itself is covered by
-        # tests/test_gpu_server.py (mixes equal to each request alone).
-        print("the served workload is disabled: its run crashed with a host-side segmentation fault "
-              "whose cause has not been found", file=sys.stderr)
-        sys.exit(3)
+        line = bench_served(args)
+    elif args.workload == "streamed":
+        line = bench_streamed(args)
     elif args.workload == "node2vec":
         line = bench_node2vec(args)
     elif args.workload == "forest_fire":

@@ -374,6 +374,42 @@ typedef struct {
 csaw_status csaw_layer_sample(csaw_graph g, const csaw_layer_args* args, int32_t* src, int32_t* dst,
                               int32_t* counts, csaw_stream stream);
 
+/* ---------------------------------------------------------- out of memory */
+
+/* A graph larger than device memory (Section V, out-of-memory sampling):
+ * the adjacency and edge weights stay in pinned host memory, split into
+ * num_partitions vertex ranges of about m / num_partitions edges each; the
+ * row offsets and per-vertex tables are resident. At most max_resident
+ * partitions are on the device at once (one slot each, sized for the largest
+ * partition). csaw_sample_streamed loads, for every layer, the partitions
+ * that hold frontier vertices with edges to sample, busiest first (most
+ * edges), those already resident before the others, each load overlapping
+ * the previous partition's selection on a second stream; the selection of a
+ * partition's frontier vertices runs while it is resident. Results are
+ * bit-identical to csaw_sample on the same graph.
+ *   arguments as csaw_graph_create, plus
+ *   num_partitions  1..64
+ *   max_resident    1..num_partitions
+ * Errors: INVALID_ARG (bad CSR or counts), OUT_OF_MEMORY (device slots or
+ * pinned host copies). The graph's degree bias tables are built here, one
+ * partition at a time. */
+typedef struct csaw_pgraph_s* csaw_pgraph;
+csaw_status csaw_pgraph_create(int64_t num_vertices, int64_t num_edges, const int64_t* rowptr, const int32_t* col,
+                               const uint32_t* edge_weight, int32_t num_partitions, int32_t max_resident,
+                               csaw_stream stream, csaw_pgraph* out);
+csaw_status csaw_pgraph_destroy(csaw_pgraph g);
+
+typedef struct {
+    int64_t partition_loads;      /* partitions loaded into a device slot       */
+    int64_t bytes_loaded;         /* host-to-device bytes of those loads        */
+} csaw_stream_stats;
+
+/* csaw_sample on a partitioned graph: same arguments, outputs and errors;
+ * stats (HOST, nullable) receives the call's partition loads. One call runs
+ * at a time per graph (others wait). */
+csaw_status csaw_sample_streamed(csaw_pgraph g, const csaw_sample_args* args, csaw_sample_out* out,
+                                 csaw_stream stream, csaw_stream_stats* stats);
+
 /* ------------------------------------------------------- device scratch */
 
 /* Device scratch of the calls (each graph's workspaces: per-call frontier and

@@ -74,6 +74,10 @@ AllocFn = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FreeFn = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
+class StreamStats(ctypes.Structure):
+    _fields_ = [("partition_loads", ctypes.c_int64), ("bytes_loaded", ctypes.c_int64)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("bound16", ctypes.c_int32), ("bound32", ctypes.c_int32)]
 
@@ -104,7 +108,8 @@ EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_s
            "csaw_sample_bound", "csaw_set_tuning", "csaw_get_tuning", "csaw_autotune_sample", "csaw_walk",
            "csaw_mdrw", "csaw_layer_sample", "csaw_set_allocator", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
            "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_server_cancel",
-           "csaw_server_memory", "csaw_result_free", "csaw_server_destroy"]
+           "csaw_server_memory", "csaw_result_free", "csaw_server_destroy", "csaw_pgraph_create",
+           "csaw_pgraph_destroy", "csaw_sample_streamed"]
 
 
 def _load():
@@ -134,6 +139,10 @@ def _load():
     L.csaw_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.csaw_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.POINTER(Result))]
     L.csaw_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ctypes.POINTER(Result))]
+    L.csaw_pgraph_create.argtypes = [i64, i64, vp, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
+    L.csaw_pgraph_destroy.argtypes = [vp]
+    L.csaw_sample_streamed.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), vp,
+                                       ctypes.POINTER(StreamStats)]
     L.csaw_server_cancel.argtypes = [vp, ctypes.c_uint64]
     L.csaw_server_memory.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     L.csaw_result_free.argtypes = [ctypes.POINTER(Result)]
@@ -441,6 +450,49 @@ class Graph:
                              dst.data_ptr() if big else None, steps.data_ptr(), ctypes.byref(total),
                              _stream(stream)))
         return src, dst, steps[:ni], total.value
+
+
+class PartitionedGraph(Graph):
+    """A graph kept in pinned host memory and streamed to the device in
+    vertex-range partitions (csaw_pgraph_*): only the sampling calls apply."""
+
+    def __init__(self, rowptr, col, edge_weight=None, num_partitions=4, max_resident=2, stream=None):
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        ew = None if edge_weight is None else np.ascontiguousarray(edge_weight, dtype=np.uint32)
+        n = len(rowptr) - 1
+        h = ctypes.c_void_p()
+        _check(lib.csaw_pgraph_create(n, len(col), rowptr.ctypes.data, col.ctypes.data,
+                                      None if ew is None else ew.ctypes.data, int(num_partitions),
+                                      int(max_resident), _stream(stream), ctypes.byref(h)))
+        self._ph = h
+        self._h = None
+        self.n, self.m = n, len(col)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.last_stats = None
+
+    def close(self):
+        if getattr(self, "_ph", None):
+            lib.csaw_pgraph_destroy(self._ph)
+            self._ph = None
+
+    def sample_bound(self, seed_offsets, fanouts, bias=UNIFORM) -> int:
+        raise NotImplementedError("size the outputs with a resident Graph's sample_bound or pass capacity")
+
+    def sample(self, seed_offsets, seeds, fanouts, bias=UNIFORM, rng_seed=1, instance_base=0,
+               capacity=None, stream=None, out=None, instance_ids=None, rng_seeds=None, rounds=0,
+               burn=0) -> SampleResult:
+        """csaw_sample_streamed; ``capacity`` (or ``out``) is required. The
+        call's partition loads are in ``last_stats`` afterwards."""
+        if capacity is None and out is None:
+            raise ValueError("a partitioned graph needs capacity= or out=")
+        st = StreamStats()
+        res = self._run_sample(lambda a, o: lib.csaw_sample_streamed(self._ph, a, o, _stream(stream),
+                                                                     ctypes.byref(st)),
+                               seed_offsets, seeds, fanouts, bias, rng_seed, instance_base, capacity, out,
+                               instance_ids, rng_seeds, rounds, burn)
+        self.last_stats = (st.partition_loads, st.bytes_loaded)
+        return res
 
 
 def profile_enable(on: bool = True):

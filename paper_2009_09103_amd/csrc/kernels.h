@@ -45,6 +45,7 @@ struct SampleCtl {
     int64_t total[kMaxLayers];         // edges per layer
     int64_t out_base[kMaxLayers + 1];  // first edge of each layer
     unsigned long long nbig[kMaxLayers];    // long weighted lists per layer
+    int64_t ndirty[kMaxLayers + 1];    // dirty words per layer (sparse builds)
     int32_t bad_seed;
     int32_t overflow;
     int32_t unsupported;
@@ -80,7 +81,13 @@ struct FrontierBuild {
     int32_t* bigs;                   // long-list entries (frontier positions)
     int64_t* offsets;                // [L*ni+1] or null
     SampleCtl* ctl;
-    unsigned long long* status;      // [4 * nb] look-back words
+    unsigned long long* status;      // [4 * max(nb, nb_dirty)] look-back words
+    // sparse build (large bitmaps): summary bitmap, one bit per next word
+    // (nsw words per instance, a multiple of 4), and the dirty-word list
+    uint32_t* summ;                  // null: dense build over every word
+    int64_t nsw;
+    int64_t* dirty;                  // [frontier capacity]
+    int64_t nb_dirty;                // blocks of the compaction
 };
 
 struct SampleLayer {
@@ -107,9 +114,12 @@ struct SampleLayer {
     const uint32_t* visited;         // [ni * nwp]
     uint32_t* next;                  // [ni * nwp]
     int64_t nwp;                     // bitmap words per instance (multiple of 4)
+    uint32_t* summ;                  // [ni * nsw] summary bitmap of next (sparse builds) or null
+    int64_t nsw;
     int32_t group16, group32;        // sub-wave bucket bounds (<= 16, <= 32; 0 = off)
     int32_t rounds;                  // repeated-sampling rounds (0: every slot by direct draw)
     uint32_t burn;                   // forest fire threshold (0: fixed fanout)
+    int32_t vlo, vhi;                // entries of vertices in [vlo, vhi) only (out-of-memory schedule)
 };
 
 constexpr int32_t kDefaultBound16 = 16, kDefaultBound32 = 32;
@@ -129,9 +139,13 @@ inline void launch_kernel(void (*kernel)(A...), dim3 grid, dim3 block, hipStream
 
 // --- sampling (sample_kernels.hip)
 void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* seed_offsets,
-                       int32_t ni, int64_t n, uint32_t* next, int64_t nwp, SampleCtl* ctl,
-                       hipStream_t s);
+                       int32_t ni, int64_t n, uint32_t* next, int64_t nwp, uint32_t* summ, int64_t nsw,
+                       SampleCtl* ctl, hipStream_t s);
 int64_t frontier_build_blocks(int64_t words);
+int64_t dirty_compact_blocks(int64_t summary_words);
+int64_t sparse_build_blocks(int64_t capacity);
+// Bitmap words (all instances) above which frontier builds are sparse.
+constexpr int64_t kSparseWords = int64_t(1) << 23;
 void launch_frontier_build(const FrontierBuild& fb, hipStream_t s, LaunchEvents ev = {});
 void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
 void launch_select_small(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
@@ -157,6 +171,12 @@ void launch_clear_visited(const ClearVisited& c, hipStream_t s, LaunchEvents ev 
 void launch_call_setup(uint32_t* ctl, int64_t nctl, const uint32_t* host_tab, uint32_t* tab, int64_t ntab,
                        hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+// Out-of-memory schedule: work[2p] = frontier entries and work[2p+1] = their
+// edges in partition p (vertices [bounds[p], bounds[p+1])), accumulated.
+constexpr int kMaxPartitionsHost = 64;
+void launch_partition_work(const int32_t* fv, const int32_t* cnt, const SampleCtl* ctl, int32_t layer,
+                           int64_t capacity, const int64_t* bounds, int32_t np, unsigned long long* work,
+                           hipStream_t s);
 
 // --- graph preparation (sample_kernels.hip)
 void launch_degree_weights(const int64_t* rowptr, const int32_t* col, int64_t m, uint32_t* degw,

@@ -213,6 +213,7 @@ struct csaw_graph_s {
     int64_t n = 0, m = 0, max_deg = 0;
     int device = 0;
     bool sorted = true;
+    bool ew_streamed = false;  // edge weights exist but are streamed by partition (out-of-memory graph)
     int64_t* rowptr = nullptr;
     int32_t* col = nullptr;
     uint32_t* ew = nullptr;
@@ -416,7 +417,8 @@ csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P, 
         const int32_t k = a->bias_kinds ? a->bias_kinds[i] : a->bias_kind;
         if (k != kUniform && k != kEdgeWeight && k != kNeighborDegree)
             return fail(CSAW_ERR_INVALID_ARG, "bias kind %d is not a sampling bias (instance %d)", k, i);
-        if (k == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
+        if (k == kEdgeWeight && !g->ew && !g->ew_streamed)
+            return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
         P.bias[i] = k;
         P.uses_deg |= (k == kNeighborDegree);
         P.uses_ew |= (k == kEdgeWeight);
@@ -456,28 +458,42 @@ csaw_status plan_sample(csaw_graph g, const csaw_sample_args* a, SamplePlan& P, 
 }
 
 int64_t bitmap_words_per_instance(int64_t n) { return (int64_t)align_up((size_t)((n + 31) / 32), 4); }
+// summary words per instance of a sparse build: one bit per bitmap word
+int64_t summary_words_per_instance(int64_t nwp) { return (int64_t)align_up((size_t)((nwp + 31) / 32), 4); }
 
 // Device memory of one sampling call, from its shape alone: the arena (control
 // block, look-back words, tables, per-entry arrays, frontiers), then, for calls
 // in a caller's scratch, the two bitmaps and the copy of the final control
 // block. The small tables have the same layout in host memory.
 struct SampleLayout {
+    bool sparse;                   // frontier builds through a summary bitmap and a dirty-word list
+    int64_t nsw;                   // summary words per instance (sparse)
+    int64_t bitmap_words;          // visited, next and (sparse) the summary
     size_t t_fan, t_bias, t_iid, t_key, t_soff, tab_bytes;
-    size_t o_ctl, o_status, ctl_words, o_tab, o_cnt, o_off, o_fbeg, o_fdeg, o_fpos, o_bigs;
+    size_t o_ctl, o_status, ctl_words, o_tab, o_cnt, o_off, o_fbeg, o_fdeg, o_fpos, o_bigs, o_dirty;
     std::vector<size_t> o_fv, o_fi;
     size_t arena;                  // bytes of the arena part
     size_t o_bits, o_copy, scratch;
     int64_t nb_build;
 };
 
-bool layout_sample(int32_t ni, int32_t L, const std::vector<int64_t>& fcap, int64_t words, SampleLayout& y) {
+bool layout_sample(int32_t ni, int32_t L, const std::vector<int64_t>& fcap, int64_t nwp, SampleLayout& y) {
     int64_t maxF = 0, sumF = 0;
     for (int l = 0; l <= L; ++l) {
         maxF = std::max(maxF, fcap[l]);
         sumF = sat_add(sumF, fcap[l]);
     }
     if (sumF > (int64_t(1) << 40)) return false;
-    y.nb_build = frontier_build_blocks(words);
+    const int64_t words = nwp * ni;
+    y.sparse = words > kSparseWords;
+    y.nsw = y.sparse ? summary_words_per_instance(nwp) : 0;
+    y.bitmap_words = words * 2 + y.nsw * ni;
+    if (y.sparse) {  // look-back words for the compaction and for the widest dirty-word build
+        y.nb_build = dirty_compact_blocks(y.nsw * ni);
+        for (int l = 0; l <= L; ++l) y.nb_build = std::max(y.nb_build, sparse_build_blocks(fcap[l]));
+    } else {
+        y.nb_build = frontier_build_blocks(words);
+    }
     size_t tb = 0;
     y.t_fan = tb;
     tb += (size_t)(L + 1) * ni * sizeof(int32_t);
@@ -503,6 +519,7 @@ bool layout_sample(int32_t ni, int32_t L, const std::vector<int64_t>& fcap, int6
     y.o_fdeg = cv.take<int32_t>(F);
     y.o_fpos = cv.take<int32_t>(F);
     y.o_bigs = cv.take<int32_t>(F);
+    y.o_dirty = y.sparse ? cv.take<int64_t>(F) : 0;  // a dirty word holds at least one frontier vertex
     y.o_fv.assign(L + 1, 0);
     y.o_fi.assign(L + 1, 0);
     for (int l = 0; l <= L; ++l) {
@@ -511,25 +528,15 @@ bool layout_sample(int32_t ni, int32_t L, const std::vector<int64_t>& fcap, int6
     }
     y.arena = cv.off;
     y.o_bits = align_up(cv.off, 256);
-    y.o_copy = align_up(y.o_bits + (size_t)words * 2 * sizeof(uint32_t), 256);
+    y.o_copy = align_up(y.o_bits + (size_t)y.bitmap_words * sizeof(uint32_t), 256);
     y.scratch = y.o_copy + sizeof(SampleCtl);
     return true;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* csaw_last_error(void) { return t_err.c_str(); }
-
-const char* csaw_version(void) { return "libcsaw 0.1 (gfx950)"; }
-
-csaw_status csaw_graph_create(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
-                              const uint32_t* edge_weight, uint32_t flags, csaw_stream stream, csaw_graph* out) {
-    t_err.clear();
-    if (!out) return fail(CSAW_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
-    if (flags != 0) return fail(CSAW_ERR_INVALID_ARG, "flags must be 0");
+// Host check of a CSR graph (O(n + m)): bounds, monotone offsets, ids in
+// range; reports the longest list and whether every list is sorted.
+csaw_status validate_csr(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col, int64_t* max_deg_out = nullptr,
+                         bool* sorted_out = nullptr) {
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(CSAW_ERR_INVALID_ARG, "num_vertices out of range");
     if (m < 0 || m >= (int64_t(1) << 40)) return fail(CSAW_ERR_INVALID_ARG, "num_edges out of range");
     if (!rowptr) return fail(CSAW_ERR_INVALID_ARG, "rowptr is NULL");
@@ -549,6 +556,29 @@ csaw_status csaw_graph_create(int64_t n, int64_t m, const int64_t* rowptr, const
             if (e > rowptr[v] && col[e - 1] > x) sorted = false;
         }
     }
+    if (max_deg_out) *max_deg_out = max_deg;
+    if (sorted_out) *sorted_out = sorted;
+    return CSAW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* csaw_last_error(void) { return t_err.c_str(); }
+
+const char* csaw_version(void) { return "libcsaw 0.1 (gfx950)"; }
+
+csaw_status csaw_graph_create(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                              const uint32_t* edge_weight, uint32_t flags, csaw_stream stream, csaw_graph* out) {
+    t_err.clear();
+    if (!out) return fail(CSAW_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (flags != 0) return fail(CSAW_ERR_INVALID_ARG, "flags must be 0");
+    int64_t max_deg = 0;
+    bool sorted = true;
+    csaw_status vst = validate_csr(n, m, rowptr, col, &max_deg, &sorted);
+    if (vst != CSAW_OK) return vst;
     hipStream_t s = (hipStream_t)stream;
     csaw_graph g = new csaw_graph_s();
     g->n = n;
@@ -620,8 +650,12 @@ csaw_status csaw_sample_bound(csaw_graph g, const csaw_sample_args* a, int64_t* 
 // sequence captured and replayed), or, when scratch is set, from that
 // device scratch only: tables copied in, every kernel on the caller's
 // stream, launched directly, no allocation of any kind on the device.
+struct Streamer;
+static csaw_status stream_layer(Streamer& st, const SampleLayer& p, int32_t l, int64_t cap, bool big_path,
+                                bool uses_ew, bool uses_deg, int32_t b16, int32_t b32, hipStream_t s);
+
 static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sample_out* out, csaw_stream stream,
-                               char* scratch, size_t scratch_bytes) {
+                               char* scratch, size_t scratch_bytes, Streamer* streamer = nullptr) {
     if (!out) return fail(CSAW_ERR_INVALID_ARG, "out is NULL");
     SamplePlan P;
     csaw_status st = plan_sample(g, a, P, true);
@@ -657,7 +691,7 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
     const int64_t nwp = bitmap_words_per_instance(g->n);
     const int64_t words = nwp * ni;
     SampleLayout lay;
-    if (!layout_sample(ni, L, P.fcap, words, lay)) return fail(CSAW_ERR_OUT_OF_MEMORY, "frontier bound too large");
+    if (!layout_sample(ni, L, P.fcap, nwp, lay)) return fail(CSAW_ERR_OUT_OF_MEMORY, "frontier bound too large");
     const int64_t nb_build = lay.nb_build;
     const size_t t_fan = lay.t_fan, t_bias = lay.t_bias, t_iid = lay.t_iid, t_key = lay.t_key, t_soff = lay.t_soff;
     const size_t tab_bytes = lay.tab_bytes;
@@ -691,7 +725,7 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
         ws = acquire(g);
         rel.w = ws;
         if ((st = ensure_arena(ws, lay.arena)) != CSAW_OK) return st;
-        if ((st = ensure_bitmaps(ws, (size_t)words * 2, s)) != CSAW_OK) return st;
+        if ((st = ensure_bitmaps(ws, (size_t)lay.bitmap_words, s)) != CSAW_OK) return st;
         if ((st = ensure_streams(ws)) != CSAW_OK) return st;
         if ((st = ensure_pinned(ws, o_hctl + sizeof(SampleCtl))) != CSAW_OK) return st;
         A = ws->arena;
@@ -709,6 +743,7 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
     int64_t* d_off = (int64_t*)(A + o_off);
     uint32_t* visited = bitmaps;
     uint32_t* next = bitmaps + words;
+    uint32_t* summ = lay.sparse ? bitmaps + 2 * words : nullptr;
 
     // the small tables: one host block (pinned, read by the setup kernel; or
     // copied into the scratch)
@@ -739,6 +774,10 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
         fb.nwords = words;
         fb.nwp = nwp;
         fb.nb = nb_build;
+        fb.summ = summ;
+        fb.nsw = lay.nsw;
+        fb.dirty = lay.sparse ? (int64_t*)(A + lay.o_dirty) : nullptr;
+        fb.nb_dirty = lay.sparse ? dirty_compact_blocks(lay.nsw * ni) : 0;
         fb.num_layers = L;
         fb.num_instances = ni;
         fb.bias = d_bias;
@@ -759,11 +798,12 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
             fb.fanout = d_fan + (size_t)l * ni;
             fb.fv = (int32_t*)(A + o_fv[l]);
             fb.fi = (int32_t*)(A + o_fi[l]);
+            if (lay.sparse) fb.nb = sparse_build_blocks(P.fcap[l]);  // one thread per dirty word, at most one per entry
             launch_frontier_build(fb, s, ev);
         };
         {
             ProfScope ps("frontier_init", s);
-            launch_mark_seeds(a->seeds, P.total_seeds, d_soff, ni, g->n, next, nwp, ctl, s);
+            launch_mark_seeds(a->seeds, P.total_seeds, d_soff, ni, g->n, next, nwp, summ, lay.nsw, ctl, s);
             build(0, LaunchEvents{});
         }
         SampleLayer p;
@@ -785,10 +825,14 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
         p.visited = visited;
         p.next = next;
         p.nwp = nwp;
+        p.summ = summ;
+        p.nsw = lay.nsw;
         p.group16 = b16;
         p.group32 = b32;
         p.rounds = P.rounds;
         p.burn = a->burn_threshold;
+        p.vlo = 0;  // every vertex (an out-of-memory schedule narrows it per partition)
+        p.vhi = INT32_MAX;
         int computed_layers = 1;  // frontiers F_0 .. F_{computed_layers-1} exist
         for (int32_t l = 0; l < L; ++l) {
             p.layer = l;
@@ -797,6 +841,15 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
             p.fv = (const int32_t*)(A + o_fv[l]);
             p.fi = (const int32_t*)(A + o_fi[l]);
             const int64_t cap = P.fcap[l];
+            if (streamer) {  // out of memory: partition by partition, each once resident
+                if ((st = stream_layer(*streamer, p, l, cap, big_path, P.uses_ew, P.uses_deg, b16, b32, s)) != CSAW_OK)
+                    return st;
+                if (l + 1 < L && P.fcap[l + 1] > 0) {
+                    build(l + 1, LaunchEvents{});
+                    computed_layers = l + 2;
+                }
+                continue;
+            }
             // the long-list path and the wavefront kernel touch disjoint outputs:
             // run them side by side (scratch calls: one after the other)
             hipStream_t aux = scratch ? s : ws->aux;
@@ -853,10 +906,13 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
     };
 
     // the call's launch sequence, replayed from its captured graph when enabled
-    if (scratch) {
+    if (streamer) {  // host decisions between layers: eager
+        if ((st = enqueue(s)) != CSAW_OK) return st;
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    } else if (scratch) {
         // the tables, and zero bitmaps: the scratch keeps the last call's contents
         HIP_OR_FAIL(hipMemcpyAsync(A + o_tab, H, tab_bytes, hipMemcpyHostToDevice, s));
-        launch_fill_u32(bitmaps, 0u, words * 2, s);
+        launch_fill_u32(bitmaps, 0u, lay.bitmap_words, s);
         if ((st = enqueue(s)) != CSAW_OK) return st;
         HIP_OR_FAIL(hipMemcpyAsync(h_ctl, ctl, sizeof(SampleCtl), hipMemcpyDeviceToHost, s));
         HIP_OR_FAIL(hipStreamSynchronize(s));
@@ -941,6 +997,344 @@ csaw_status csaw_sample_noalloc(csaw_graph g, const csaw_sample_args* a, csaw_sa
     // the next call may use the scratch
     if (st != CSAW_OK) (void)hipStreamSynchronize((hipStream_t)stream);
     return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- out of memory
+// A graph whose adjacency and weights stay in pinned host memory and reach
+// the device one vertex-range partition at a time (Section V): the row
+// offsets and per-vertex tables (positive counts, list totals) are resident,
+// and so are the calls' frontiers and bitmaps; a partition's column ids,
+// weights and chunk prefix rows are loaded into one of max_resident device
+// slots when a layer has frontier entries in it. Partitions of a layer are
+// taken busiest first (most edges to sample), those already resident before
+// the others, and the next partition's transfer (copy stream) overlaps the
+// current one's selection. The selection kernels see the slot through base
+// pointers shifted by the partition's first edge and row, and take only the
+// frontier entries of the partition's vertices, so every edge is the one the
+// in-memory call writes at the same place.
+struct csaw_pgraph_s {
+    csaw_graph g = nullptr;       // resident part (no column ids or weights)
+    int32_t np = 0;
+    std::vector<int64_t> vb, eb;  // [np + 1] vertex and edge bounds of the partitions
+    int64_t* d_vb = nullptr;
+    bool has_ew = false;
+    int32_t* h_col = nullptr;     // pinned host copies of the partitioned arrays
+    uint32_t* h_ew = nullptr;
+    uint32_t* h_degw = nullptr;
+    uint64_t* h_gtab_ew = nullptr;
+    uint64_t* h_gtab_deg = nullptr;
+    struct Slot {
+        int32_t part = -1;
+        bool col = false, ew = false, degw = false;  // arrays of `part` present
+        int64_t last_use = 0;
+        char* mem = nullptr;
+        int32_t* d_col = nullptr;
+        uint32_t* d_ew = nullptr;
+        uint32_t* d_degw = nullptr;
+        uint64_t* d_gtab_ew = nullptr;
+        uint64_t* d_gtab_deg = nullptr;
+        hipEvent_t ready = nullptr, idle = nullptr;
+    };
+    std::vector<Slot> slots;
+    int64_t slot_edges = 0, slot_rows = 0;
+    hipStream_t copy = nullptr;
+    unsigned long long* d_work = nullptr;  // [2 * np]
+    unsigned long long* h_work = nullptr;  // pinned
+    int64_t tick = 0;
+    std::mutex mu;                         // one call at a time
+    int64_t rows(int32_t q) const { return (eb[q + 1] >> kTabShift) - (eb[q] >> kTabShift); }
+};
+
+struct Streamer {
+    csaw_pgraph pg;
+    csaw_stream_stats* stats;
+};
+
+namespace {
+
+// Loads the arrays of partition q that the call needs into slot x, on the
+// copy stream, after the slot's last selection; the compute stream waits.
+csaw_status load_partition(csaw_pgraph pg, csaw_pgraph_s::Slot& x, int32_t q, bool need_ew, bool need_deg,
+                           hipStream_t s, csaw_stream_stats* stats) {
+    if (x.part != q) {
+        x.part = q;
+        x.col = x.ew = x.degw = false;
+    }
+    const bool want_ew = need_ew && !x.ew, want_deg = need_deg && !x.degw;
+    if (x.col && !want_ew && !want_deg) {
+        HIP_OR_FAIL(hipStreamWaitEvent(s, x.ready, 0));  // a load still in flight from earlier
+        return CSAW_OK;
+    }
+    const int64_t e0 = pg->eb[q], ne = pg->eb[q + 1] - e0;
+    const int64_t r0 = pg->eb[q] >> kTabShift, nr = pg->rows(q);
+    HIP_OR_FAIL(hipStreamWaitEvent(pg->copy, x.idle, 0));
+    int64_t bytes = 0;
+    auto up = [&](void* d, const void* h, size_t n) -> hipError_t {
+        bytes += (int64_t)n;
+        return n ? hipMemcpyAsync(d, h, n, hipMemcpyHostToDevice, pg->copy) : hipSuccess;
+    };
+    if (!x.col) HIP_OR_FAIL(up(x.d_col, pg->h_col + e0, (size_t)ne * 4));
+    if (want_ew) {
+        HIP_OR_FAIL(up(x.d_ew, pg->h_ew + e0, (size_t)ne * 4));
+        HIP_OR_FAIL(up(x.d_gtab_ew, pg->h_gtab_ew + r0 * kChunkGroups, (size_t)nr * kChunkGroups * 8));
+    }
+    if (want_deg) {
+        HIP_OR_FAIL(up(x.d_degw, pg->h_degw + e0, (size_t)ne * 4));
+        HIP_OR_FAIL(up(x.d_gtab_deg, pg->h_gtab_deg + r0 * kChunkGroups, (size_t)nr * kChunkGroups * 8));
+    }
+    HIP_OR_FAIL(hipEventRecord(x.ready, pg->copy));
+    HIP_OR_FAIL(hipStreamWaitEvent(s, x.ready, 0));
+    x.col = true;
+    x.ew |= want_ew;
+    x.degw |= want_deg;
+    if (stats) {
+        stats->partition_loads += 1;
+        stats->bytes_loaded += bytes;
+    }
+    return CSAW_OK;
+}
+
+}  // namespace
+
+static csaw_status stream_layer(Streamer& st, const SampleLayer& p, int32_t l, int64_t cap, bool big_path,
+                                bool uses_ew, bool uses_deg, int32_t b16, int32_t b32, hipStream_t s) {
+    csaw_pgraph pg = st.pg;
+    const int32_t np = pg->np;
+    // the layer's work per partition
+    HIP_OR_FAIL(hipMemsetAsync(pg->d_work, 0, (size_t)np * 2 * sizeof(unsigned long long), s));
+    launch_partition_work(p.fv, p.cnt, p.ctl, l, std::max<int64_t>(cap, 1), pg->d_vb, np, pg->d_work, s);
+    HIP_OR_FAIL(hipMemcpyAsync(pg->h_work, pg->d_work, (size_t)np * 2 * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    std::vector<int32_t> order;
+    for (int32_t q = 0; q < np; ++q)
+        if (pg->h_work[2 * q + 1] > 0) order.push_back(q);  // partitions with edges to sample
+    auto slot_of = [&](int32_t q) -> int {
+        for (size_t k = 0; k < pg->slots.size(); ++k)
+            if (pg->slots[k].part == q) return (int)k;
+        return -1;
+    };
+    // resident partitions first, then busiest first
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const bool ra = slot_of(a) >= 0, rb = slot_of(b) >= 0;
+        if (ra != rb) return ra;
+        return pg->h_work[2 * a + 1] > pg->h_work[2 * b + 1];
+    });
+    for (size_t i = 0; i < order.size(); ++i) {
+        const int32_t q = order[i];
+        int k = slot_of(q);
+        if (k < 0) {  // a slot whose partition this layer no longer needs, least recently used
+            auto needed_later = [&](int32_t part) {
+                return std::find(order.begin() + i, order.end(), part) != order.end();
+            };
+            for (size_t c = 0; c < pg->slots.size(); ++c) {
+                const auto& x = pg->slots[c];
+                const bool free_c = x.part < 0 || !needed_later(x.part);
+                const bool free_k = k >= 0 && (pg->slots[k].part < 0 || !needed_later(pg->slots[k].part));
+                if (k < 0 || (free_c && !free_k) || (free_c == free_k && x.last_use < pg->slots[k].last_use))
+                    k = (int)c;
+            }
+        }
+        csaw_pgraph_s::Slot& x = pg->slots[k];
+        csaw_status ls = load_partition(pg, x, q, uses_ew, uses_deg, s, st.stats);
+        if (ls != CSAW_OK) return ls;
+        x.last_use = ++pg->tick;
+        SampleLayer pp = p;
+        const int64_t e0 = pg->eb[q], r0 = pg->eb[q] >> kTabShift;
+        pp.g.col = x.d_col - e0;  // indexed by global edge ids of the partition's lists
+        pp.g.ew = x.d_ew ? x.d_ew - e0 : nullptr;
+        pp.g.degw = x.d_degw ? x.d_degw - e0 : nullptr;
+        pp.g.gtab_ew = x.d_gtab_ew ? x.d_gtab_ew - r0 * kChunkGroups : nullptr;
+        pp.g.gtab_deg = x.d_gtab_deg ? x.d_gtab_deg - r0 * kChunkGroups : nullptr;
+        pp.vlo = (int32_t)pg->vb[q];
+        pp.vhi = (int32_t)std::min<int64_t>(pg->vb[q + 1], INT32_MAX);
+        if (big_path) launch_select_big(pp, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), s);
+        if (b16 > 0 || b32 > 0)
+            launch_select_small(pp, (int)std::min<int64_t>(std::max<int64_t>((cap + 255) / 256, 1), 2048), s);
+        launch_select(pp, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 4096), s);
+        HIP_OR_FAIL(hipGetLastError());
+        HIP_OR_FAIL(hipEventRecord(x.idle, s));  // the slot may be reloaded after this
+    }
+    return CSAW_OK;
+}
+
+extern "C" {
+
+csaw_status csaw_pgraph_destroy(csaw_pgraph pg) {
+    if (!pg) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (pg->copy) (void)hipStreamSynchronize(pg->copy);
+    for (auto& x : pg->slots) {
+        if (x.ready) (void)hipEventSynchronize(x.ready);
+        if (x.idle) (void)hipEventSynchronize(x.idle);
+        if (x.ready) (void)hipEventDestroy(x.ready);
+        if (x.idle) (void)hipEventDestroy(x.idle);
+        if (x.mem) (void)hipFree(x.mem);
+    }
+    if (pg->copy) (void)hipStreamDestroy(pg->copy);
+    if (pg->d_vb) (void)hipFree(pg->d_vb);
+    if (pg->d_work) (void)hipFree(pg->d_work);
+    if (pg->h_work) (void)hipHostFree(pg->h_work);
+    for (void* h : {(void*)pg->h_col, (void*)pg->h_ew, (void*)pg->h_degw, (void*)pg->h_gtab_ew, (void*)pg->h_gtab_deg})
+        if (h) (void)hipHostFree(h);
+    if (pg->g) csaw_graph_destroy(pg->g);
+    delete pg;
+    return CSAW_OK;
+}
+
+csaw_status csaw_pgraph_create(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                               const uint32_t* edge_weight, int32_t num_partitions, int32_t max_resident,
+                               csaw_stream stream, csaw_pgraph* out) {
+    t_err.clear();
+    if (!out) return fail(CSAW_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (num_partitions < 1 || num_partitions > kMaxPartitionsHost)
+        return fail(CSAW_ERR_INVALID_ARG, "num_partitions must be in [1, %d]", kMaxPartitionsHost);
+    if (max_resident < 1 || max_resident > num_partitions)
+        return fail(CSAW_ERR_INVALID_ARG, "max_resident must be in [1, num_partitions]");
+    csaw_status st = validate_csr(n, m, rowptr, col);
+    if (st != CSAW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    csaw_pgraph pg = new csaw_pgraph_s();
+    auto cleanup = [&](csaw_status e) {
+        csaw_pgraph_destroy(pg);
+        return e;
+    };
+    csaw_graph g = new csaw_graph_s();
+    pg->g = g;
+    g->n = n;
+    g->m = m;
+    pg->has_ew = edge_weight != nullptr;
+    g->ew_streamed = pg->has_ew;
+    for (int64_t v = 0; v < n; ++v) g->max_deg = std::max(g->max_deg, rowptr[v + 1] - rowptr[v]);
+    g->sorted = false;  // walks need sorted resident lists; this graph is for sampling
+    if (hipGetDevice(&g->device) != hipSuccess) return cleanup(fail(CSAW_ERR_DEVICE, "hipGetDevice failed"));
+    // partitions of about m / np edges each (whole lists)
+    const int32_t np = num_partitions;
+    pg->np = np;
+    pg->vb.assign(np + 1, 0);
+    pg->eb.assign(np + 1, 0);
+    for (int32_t q = 1; q < np; ++q) {
+        const int64_t target = (int64_t)((__int128)m * q / np);
+        const int64_t v = std::lower_bound(rowptr, rowptr + n + 1, target) - rowptr;
+        pg->vb[q] = std::max(pg->vb[q - 1], std::min<int64_t>(v, n));
+    }
+    pg->vb[np] = n;
+    for (int32_t q = 0; q <= np; ++q) pg->eb[q] = rowptr[pg->vb[q]];
+    for (int32_t q = 0; q < np; ++q) {
+        pg->slot_edges = std::max(pg->slot_edges, pg->eb[q + 1] - pg->eb[q]);
+        pg->slot_rows = std::max(pg->slot_rows, pg->rows(q));
+    }
+    const int64_t nv = std::max<int64_t>(n, 1);
+    hipError_t e;
+    if ((e = hipMalloc((void**)&g->rowptr, (n + 1) * sizeof(int64_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&g->ppos_deg, nv * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&g->wtot_deg, nv * sizeof(uint64_t))) != hipSuccess ||
+        (pg->has_ew && (e = hipMalloc((void**)&g->ppos_ew, nv * sizeof(int32_t))) != hipSuccess) ||
+        (pg->has_ew && (e = hipMalloc((void**)&g->wtot_ew, nv * sizeof(uint64_t))) != hipSuccess) ||
+        (e = hipMalloc((void**)&pg->d_vb, (np + 1) * sizeof(int64_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&pg->d_work, 2 * np * sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipHostMalloc((void**)&pg->h_work, 2 * np * sizeof(unsigned long long), hipHostMallocDefault)) !=
+            hipSuccess)
+        return cleanup(fail(CSAW_ERR_OUT_OF_MEMORY, "allocation failed: %s", hipGetErrorString(e)));
+    // pinned host copies of the partitioned arrays
+    const size_t me = (size_t)std::max<int64_t>(m, 1);
+    const size_t trows = (size_t)chunk_table_rows(m) * kChunkGroups;
+    if ((e = hipHostMalloc((void**)&pg->h_col, me * 4, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&pg->h_degw, me * 4, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&pg->h_gtab_deg, trows * 8, hipHostMallocDefault)) != hipSuccess ||
+        (pg->has_ew && (e = hipHostMalloc((void**)&pg->h_ew, me * 4, hipHostMallocDefault)) != hipSuccess) ||
+        (pg->has_ew && (e = hipHostMalloc((void**)&pg->h_gtab_ew, trows * 8, hipHostMallocDefault)) != hipSuccess))
+        return cleanup(fail(CSAW_ERR_OUT_OF_MEMORY, "pinned host allocation failed: %s", hipGetErrorString(e)));
+    if (m > 0) std::memcpy(pg->h_col, col, (size_t)m * 4);
+    if (pg->has_ew && m > 0) std::memcpy(pg->h_ew, edge_weight, (size_t)m * 4);
+    // device slots
+    const size_t se = (size_t)std::max<int64_t>(pg->slot_edges, 1), sr = (size_t)std::max<int64_t>(pg->slot_rows, 1);
+    pg->slots.resize(max_resident);
+    if ((e = hipStreamCreateWithFlags(&pg->copy, hipStreamNonBlocking)) != hipSuccess)
+        return cleanup(fail(CSAW_ERR_DEVICE, "stream: %s", hipGetErrorString(e)));
+    for (auto& x : pg->slots) {
+        Carver cv;
+        const size_t o_col = cv.take<int32_t>(se), o_degw = cv.take<uint32_t>(se),
+                     o_gdeg = cv.take<uint64_t>(sr * kChunkGroups);
+        const size_t o_ew = pg->has_ew ? cv.take<uint32_t>(se) : 0,
+                     o_gew = pg->has_ew ? cv.take<uint64_t>(sr * kChunkGroups) : 0;
+        if ((e = hipMalloc((void**)&x.mem, cv.off)) != hipSuccess)
+            return cleanup(fail(CSAW_ERR_OUT_OF_MEMORY, "partition slot: %s", hipGetErrorString(e)));
+        x.d_col = (int32_t*)(x.mem + o_col);
+        x.d_degw = (uint32_t*)(x.mem + o_degw);
+        x.d_gtab_deg = (uint64_t*)(x.mem + o_gdeg);
+        if (pg->has_ew) {
+            x.d_ew = (uint32_t*)(x.mem + o_ew);
+            x.d_gtab_ew = (uint64_t*)(x.mem + o_gew);
+        }
+        if ((e = hipEventCreateWithFlags(&x.ready, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&x.idle, hipEventDisableTiming)) != hipSuccess)
+            return cleanup(fail(CSAW_ERR_DEVICE, "event: %s", hipGetErrorString(e)));
+    }
+    if ((e = hipMemcpyAsync(g->rowptr, rowptr, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(pg->d_vb, pg->vb.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+        return cleanup(fail(CSAW_ERR_DEVICE, "upload: %s", hipGetErrorString(e)));
+    // per-partition preparation through slot 0: the degree bias of every edge,
+    // the positive counts and totals of the partition's lists, their chunk
+    // prefix rows; the edge-sized results go back to pinned host memory
+    auto& x = pg->slots[0];
+    for (int32_t q = 0; q < np; ++q) {
+        const int64_t v0 = pg->vb[q], nvq = pg->vb[q + 1] - v0, e0 = pg->eb[q], ne = pg->eb[q + 1] - e0;
+        const int64_t r0 = e0 >> kTabShift, nr = pg->rows(q);
+        if (ne > 0 && (e = hipMemcpyAsync(x.d_col, pg->h_col + e0, (size_t)ne * 4, hipMemcpyHostToDevice, s)) !=
+                          hipSuccess)
+            return cleanup(fail(CSAW_ERR_DEVICE, "upload: %s", hipGetErrorString(e)));
+        launch_degree_weights(g->rowptr, x.d_col, ne, x.d_degw, s);
+        if (nvq > 0) {
+            launch_positive_counts(g->rowptr + v0, x.d_degw - e0, nvq, g->ppos_deg + v0, g->wtot_deg + v0, s);
+            launch_chunk_table(g->rowptr + v0, x.d_degw - e0, nvq, x.d_gtab_deg - r0 * kChunkGroups, s);
+        }
+        if (pg->has_ew) {
+            if (ne > 0 && (e = hipMemcpyAsync(x.d_ew, pg->h_ew + e0, (size_t)ne * 4, hipMemcpyHostToDevice, s)) !=
+                              hipSuccess)
+                return cleanup(fail(CSAW_ERR_DEVICE, "upload: %s", hipGetErrorString(e)));
+            if (nvq > 0) {
+                launch_positive_counts(g->rowptr + v0, x.d_ew - e0, nvq, g->ppos_ew + v0, g->wtot_ew + v0, s);
+                launch_chunk_table(g->rowptr + v0, x.d_ew - e0, nvq, x.d_gtab_ew - r0 * kChunkGroups, s);
+            }
+        }
+        if ((e = hipGetLastError()) != hipSuccess ||
+            (ne > 0 && (e = hipMemcpyAsync(pg->h_degw + e0, x.d_degw, (size_t)ne * 4, hipMemcpyDeviceToHost, s)) !=
+                           hipSuccess) ||
+            (nr > 0 && (e = hipMemcpyAsync(pg->h_gtab_deg + r0 * kChunkGroups, x.d_gtab_deg,
+                                           (size_t)nr * kChunkGroups * 8, hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+            (pg->has_ew && nr > 0 &&
+             (e = hipMemcpyAsync(pg->h_gtab_ew + r0 * kChunkGroups, x.d_gtab_ew, (size_t)nr * kChunkGroups * 8,
+                                 hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return cleanup(fail(CSAW_ERR_DEVICE, "partition preparation: %s", hipGetErrorString(e)));
+    }
+    // the last partition stays in slot 0 with every array
+    x.part = np - 1;
+    x.col = x.degw = true;
+    x.ew = pg->has_ew;
+    HIP_OR_FAIL(hipEventRecord(x.ready, s));
+    HIP_OR_FAIL(hipEventRecord(x.idle, s));
+    for (size_t k = 1; k < pg->slots.size(); ++k) {
+        HIP_OR_FAIL(hipEventRecord(pg->slots[k].ready, s));
+        HIP_OR_FAIL(hipEventRecord(pg->slots[k].idle, s));
+    }
+    *out = pg;
+    return CSAW_OK;
+}
+
+csaw_status csaw_sample_streamed(csaw_pgraph pg, const csaw_sample_args* a, csaw_sample_out* out, csaw_stream stream,
+                                 csaw_stream_stats* stats) {
+    t_err.clear();
+    if (!pg) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    std::lock_guard<std::mutex> lk(pg->mu);
+    HIP_OR_FAIL(hipSetDevice(pg->g->device));
+    if (stats) *stats = csaw_stream_stats{};
+    Streamer st{pg, stats};
+    return sample_call(pg->g, a, out, stream, nullptr, 0, &st);
 }
 
 csaw_status csaw_set_tuning(csaw_graph g, const csaw_tuning* t) {
@@ -1234,7 +1628,7 @@ csaw_status sample_plan_caps(csaw_graph g, const csaw_sample_args* a, std::vecto
 
 size_t sample_scratch_bytes(csaw_graph g, int32_t ni, int32_t L, const std::vector<int64_t>& fcap) {
     SampleLayout lay;
-    if (!layout_sample(ni, L, fcap, bitmap_words_per_instance(g->n) * ni, lay)) return SIZE_MAX;
+    if (!layout_sample(ni, L, fcap, bitmap_words_per_instance(g->n), lay)) return SIZE_MAX;
     return lay.scratch;
 }
 

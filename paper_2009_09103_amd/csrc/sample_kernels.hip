@@ -78,7 +78,8 @@ __global__ void k_positive_counts(const int64_t* __restrict__ rowptr, const uint
 // with seed_offsets[i] <= s).
 __global__ void k_mark_seeds(const int32_t* __restrict__ seeds, int64_t num_seeds,
                              const int64_t* __restrict__ seed_off, int32_t ni, int64_t n,
-                             uint32_t* __restrict__ next, int64_t nwp, SampleCtl* ctl) {
+                             uint32_t* __restrict__ next, int64_t nwp, uint32_t* __restrict__ summ, int64_t nsw,
+                             SampleCtl* ctl) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < num_seeds;
          s += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = seeds[s];
@@ -92,7 +93,8 @@ __global__ void k_mark_seeds(const int32_t* __restrict__ seeds, int64_t num_seed
             if (seed_off[mid] <= s) lo = mid;
             else hi = mid;
         }
-        atomicOr(&next[(int64_t)lo * nwp + (v >> 5)], 1u << (v & 31));
+        const uint32_t old = atomicOr(&next[(int64_t)lo * nwp + (v >> 5)], 1u << (v & 31));
+        if (summ && old == 0u) atomicOr(&summ[(int64_t)lo * nsw + (v >> 10)], 1u << ((v >> 5) & 31));
     }
 }
 
@@ -198,6 +200,71 @@ __device__ __forceinline__ int32_t pop_bit(uint32_t& bits) {
     return b;
 }
 
+// Decoupled look-back of block b for two running totals (a, c), called by
+// the 64 lanes of one wavefront: publishes b's aggregates, then sums its
+// predecessors' published values 64 blocks at a time, nearest first; a
+// predecessor's inclusive prefix ends the walk (blocks are dispatched in
+// index order, so predecessors are resident or done). The spin is bounded and
+// reports through *stuck instead of hanging. Publishes b's inclusive prefix
+// and returns the exclusive ones (every lane).
+__device__ __forceinline__ void lookback2(unsigned long long* status, int64_t b, int64_t tot_a, int64_t tot_c,
+                                          uint32_t epoch, int32_t* stuck, int64_t& pa, int64_t& pc) {
+    const int lane = lane_id();
+    unsigned long long* st = status + 4 * b;
+    if (b > 0 && lane == 0) {
+        status_store(st + 0, status_pack(tot_a, epoch));
+        status_store(st + 1, status_pack(tot_c, epoch));
+    }
+    pa = 0;
+    pc = 0;
+    int64_t end = b - 1;  // window covers predecessors end, end-1, ..., end-63
+    uint32_t spins = 0;
+    while (end >= 0) {
+        const int64_t q = end - lane;
+        int flag = 2;  // before block 0: an inclusive prefix of zero
+        int64_t va = 0, vc = 0;
+        if (q >= 0) {
+            unsigned long long* sq = status + 4 * q;
+            const uint64_t ia = status_load(sq + 2), ic = status_load(sq + 3);
+            if (status_ok(ia, epoch) && status_ok(ic, epoch)) {
+                va = (int64_t)(ia & kStatusMask);
+                vc = (int64_t)(ic & kStatusMask);
+            } else {
+                const uint64_t aa = status_load(sq + 0), ac = status_load(sq + 1);
+                if (status_ok(aa, epoch) && status_ok(ac, epoch)) {
+                    flag = 1;
+                    va = (int64_t)(aa & kStatusMask);
+                    vc = (int64_t)(ac & kStatusMask);
+                } else {
+                    flag = 0;
+                }
+            }
+        }
+        const uint64_t incl = ballot(flag == 2);
+        const uint64_t notready = ballot(flag == 0);
+        const int first = incl ? __ffsll((unsigned long long)incl) - 1 : kWave;  // nearest inclusive
+        const uint64_t upto = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1);
+        if (notready & upto) {  // a nearer predecessor has published nothing yet
+            if (++spins > kSpinLimit) {  // never expected: report instead of hanging
+                if (lane == 0) *stuck = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        const bool take = ((upto >> lane) & 1ull) != 0;
+        pa += (int64_t)wave_sum_u64(take ? (uint64_t)va : 0ull);
+        pc += (int64_t)wave_sum_u64(take ? (uint64_t)vc : 0ull);
+        if (first < kWave) break;
+        end -= kWave;
+        spins = 0;
+    }
+    if (lane == 0) {
+        status_store(st + 2, status_pack(pa + tot_a, epoch));
+        status_store(st + 3, status_pack(pc + tot_c, epoch));
+    }
+}
+
 // Exclusive scans of four int64 per thread over the block in one pass (one
 // pair of barriers); totals in tot[0..3]. Every thread must call it.
 __device__ __forceinline__ void block_excl_scan4(int64_t (&x)[4], int64_t (&tot)[4]) {
@@ -242,13 +309,23 @@ __device__ __forceinline__ void block_excl_scan4(int64_t (&x)[4], int64_t (&tot)
 // sets visited |= next, clears next, and the first word of an instance writes
 // that instance's segment offset. The last block writes the layer's totals
 // and the output base of the next layer.
-template <int G, int V, bool kBurn>
+template <int G, int V, bool kBurn, bool kSparse>
 __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     static_assert(V == 1 || V == 4, "one word or one 16-byte group per load");
+    static_assert(!kSparse || (G == 1 && V == 1), "the dirty list gives one word per thread");
     __shared__ int64_t s_base_e, s_base_g;
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
+    // dense: every word of the bitmaps; sparse: the words of the dirty list
+    // (grid sized by capacity, blocks past the list end at once)
+    int64_t nwords = fb.nwords, nb = fb.nb;
+    if (kSparse) {
+        nwords = fb.ctl->ndirty[fb.layer];
+        nb = nwords > 0 ? (nwords + kBlock - 1) / kBlock : 1;
+        if (b >= nb) return;
+    }
     const int64_t w0 = (b * kBlock + tid) * (G * V);  // first word of the thread (nwords is a multiple of 4)
+    const int64_t wself = kSparse ? (w0 < nwords ? fb.dirty[w0] : 0) : w0;  // the thread's bitmap word
     const int64_t out_base = fb.ctl->out_base[fb.layer];
     uint32_t raws[G][V], viss[G][V];
     if (V == 4) {
@@ -275,9 +352,9 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     if (V == 1) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int64_t iw = w0 + g;
-            raws[g][0] = iw < fb.nwords ? fb.next[iw] : 0u;
-            viss[g][0] = iw < fb.nwords ? fb.visited[iw] : 0u;
+            const int64_t iw = w0 + g, wd = kSparse ? wself : iw;
+            raws[g][0] = iw < nwords ? fb.next[wd] : 0u;
+            viss[g][0] = iw < nwords ? fb.visited[wd] : 0u;
         }
     }
     int64_t cnt4[4] = {0, 0, 0, 0};  // entries, edges, long lists, (unused)
@@ -292,7 +369,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
             for (int q = 0; q < V; ++q) {
                 const uint32_t w = raws[g][q] & ~viss[g][q];  // picks of visited vertices are not new
                 if (!w) continue;
-                const int64_t iw = w0 + V * g + q;
+                const int64_t iw = kSparse ? wself : w0 + V * g + q;
                 const int64_t inst = iw / fb.nwp;
                 if (inst != inst_k) {
                     inst_k = inst;
@@ -337,59 +414,10 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
         s_big_base = tot_big ? (int64_t)atomicAdd(&fb.ctl->nbig[fb.layer], (unsigned long long)tot_big) : 0;
     }
     if (tid < kWave) {  // wave 0: publish, then look back 64 predecessors per step
-        const int lane = tid;
-        const uint32_t epoch = (uint32_t)fb.layer + 1;
-        unsigned long long* st = fb.status + 4 * b;
-        if (b > 0 && lane == 0) {
-            status_store(st + 0, status_pack(tot_e, epoch));
-            status_store(st + 1, status_pack(tot_g, epoch));
-        }
         int64_t pe = 0, pg = 0;
-        int64_t end = b - 1;  // window covers predecessors end, end-1, ..., end-63
-        uint32_t spins = 0;
-        while (end >= 0) {
-            const int64_t q = end - lane;
-            int flag = 2;  // before block 0: an inclusive prefix of zero
-            int64_t ve = 0, vg = 0;
-            if (q >= 0) {
-                unsigned long long* sq = fb.status + 4 * q;
-                const uint64_t ie = status_load(sq + 2), ig = status_load(sq + 3);
-                if (status_ok(ie, epoch) && status_ok(ig, epoch)) {
-                    ve = (int64_t)(ie & kStatusMask);
-                    vg = (int64_t)(ig & kStatusMask);
-                } else {
-                    const uint64_t ae = status_load(sq + 0), ag = status_load(sq + 1);
-                    if (status_ok(ae, epoch) && status_ok(ag, epoch)) {
-                        flag = 1;
-                        ve = (int64_t)(ae & kStatusMask);
-                        vg = (int64_t)(ag & kStatusMask);
-                    } else {
-                        flag = 0;
-                    }
-                }
-            }
-            const uint64_t incl = ballot(flag == 2);
-            const uint64_t notready = ballot(flag == 0);
-            const int first = incl ? __ffsll((unsigned long long)incl) - 1 : kWave;  // nearest inclusive
-            const uint64_t upto = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1);
-            if (notready & upto) {  // a nearer predecessor has published nothing yet
-                if (++spins > kSpinLimit) {  // never expected: report instead of hanging
-                    if (lane == 0) fb.ctl->lookback_stuck = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            const bool take = ((upto >> lane) & 1ull) != 0;
-            pe += (int64_t)wave_sum_u64(take ? (uint64_t)ve : 0ull);
-            pg += (int64_t)wave_sum_u64(take ? (uint64_t)vg : 0ull);
-            if (first < kWave) break;
-            end -= kWave;
-            spins = 0;
-        }
-        if (lane == 0) {
-            status_store(st + 2, status_pack(pe + tot_e, epoch));
-            status_store(st + 3, status_pack(pg + tot_g, epoch));
+        lookback2(fb.status, b, tot_e, tot_g, kSparse ? 2u * fb.layer + 2u : (uint32_t)fb.layer + 1u,
+                  &fb.ctl->lookback_stuck, pe, pg);
+        if (tid == 0) {
             s_base_e = pe;
             s_base_g = pg;
         }
@@ -403,8 +431,8 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
     uint32_t iid = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t iw4 = w0 + V * g;
-        if (iw4 >= fb.nwords) break;
+        if (w0 + V * g >= nwords) break;
+        const int64_t iw4 = kSparse ? wself : w0 + V * g;
         // the words again (L2): keeping them in registers across the scan
         // costs occupancy
         if (V == 4) {
@@ -432,8 +460,17 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
             any_new |= w != 0u;
             const int64_t inst = iw / fb.nwp;
             const int64_t local = iw - inst * fb.nwp;
-            if (local == 0 && fb.offsets && fb.layer < fb.num_layers)
-                fb.offsets[(int64_t)fb.layer * fb.num_instances + inst] = out_base + eoff;
+            if (fb.offsets && fb.layer < fb.num_layers) {
+                if (!kSparse) {
+                    if (local == 0) fb.offsets[(int64_t)fb.layer * fb.num_instances + inst] = out_base + eoff;
+                } else {
+                    // the first dirty word of an instance starts its segment, and
+                    // those of the instances since the previous dirty word's (empty)
+                    const int64_t prev = w0 > 0 ? fb.dirty[w0 - 1] / fb.nwp : -1;
+                    for (int64_t i = prev + 1; i <= inst; ++i)
+                        fb.offsets[(int64_t)fb.layer * fb.num_instances + i] = out_base + eoff;
+                }
+            }
             if (!w) continue;
             if (inst != inst_k) {
                 inst_k = inst;
@@ -480,7 +517,7 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
             if (any_raw) fb.next[iw4] = 0u;
         }
     }
-    if (b == fb.nb - 1) {  // last block: totals, and the bases of the layers after this one
+    if (b == nb - 1) {  // last block: totals, and the bases of the layers after this one
         const int64_t te = s_base_e + tot_e, tg = s_base_g + tot_g;
         const int64_t ob = out_base + tg;
         if (tid == 0) {
@@ -494,8 +531,47 @@ __global__ void __launch_bounds__(kBlock) k_frontier_build(FrontierBuild fb) {
             for (int64_t j = first_l; j < fb.num_layers; ++j)
                 for (int64_t i = tid; i < ni; i += kBlock) fb.offsets[j * ni + i] = (j == fb.layer ? out_base : ob);
             if (tid == 0) fb.offsets[(int64_t)fb.num_layers * ni] = ob;
+            if (kSparse && fb.layer < fb.num_layers) {  // instances after the last dirty word's: empty at the end
+                const int64_t last = nwords > 0 ? fb.dirty[nwords - 1] / fb.nwp : -1;
+                for (int64_t i = last + 1 + tid; i < ni; i += kBlock) fb.offsets[(int64_t)fb.layer * ni + i] = ob;
+            }
         }
     }
+}
+
+// Sparse frontier build, first pass: the summary bitmap (one bit per word of
+// the instances' next bitmaps, set by the claim that made the word non-zero)
+// is compacted into the list of dirty words, in increasing order, with a
+// decoupled look-back over the blocks; the summary is cleared as it is read.
+// Each thread takes four summary words (the summary of an instance is a
+// multiple of four words).
+__global__ void __launch_bounds__(kBlock) k_dirty_compact(FrontierBuild fb) {
+    __shared__ int64_t s_base;
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t nsumm = (int64_t)fb.num_instances * fb.nsw;
+    const int64_t i0 = (b * kBlock + tid) * 4;
+    const uint4 s4 = i0 < nsumm ? *(const uint4*)(fb.summ + i0) : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t sw[4] = {s4.x, s4.y, s4.z, s4.w};
+    int64_t cnt4[4] = {(int64_t)(__popc(sw[0]) + __popc(sw[1]) + __popc(sw[2]) + __popc(sw[3])), 0, 0, 0};
+    int64_t tot4[4];
+    block_excl_scan4(cnt4, tot4);
+    if (tid < kWave) {
+        int64_t pa = 0, pc = 0;
+        lookback2(fb.status, b, tot4[0], 0, 2u * fb.layer + 1u, &fb.ctl->lookback_stuck, pa, pc);
+        if (tid == 0) s_base = pa;
+    }
+    __syncthreads();
+    int64_t pos = s_base + cnt4[0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = i0 + q;
+        const int64_t inst = i / fb.nsw;
+        const int64_t wbase = inst * fb.nwp + (i - inst * fb.nsw) * 32;
+        for (uint32_t bits = sw[q]; bits; bits &= bits - 1) fb.dirty[pos++] = wbase + (__ffs(bits) - 1);
+    }
+    if ((s4.x | s4.y | s4.z | s4.w) != 0u) *(uint4*)(fb.summ + i0) = make_uint4(0u, 0u, 0u, 0u);
+    if (b == fb.nb_dirty - 1 && tid == 0) fb.ctl->ndirty[fb.layer] = s_base + tot4[0];
 }
 
 // ----------------------------------------------------------------- select
@@ -747,11 +823,21 @@ __device__ __forceinline__ int32_t draw_resident(const uint32_t* __restrict__ w,
 // already there: picks concentrate on hubs, and skipping those atomics keeps
 // them from queueing on a few hot words. (The frontier build also masks
 // visited vertices.)
-__device__ __forceinline__ void claim(bool do_claim, const uint32_t* visb, uint32_t* nextb, int32_t x) {
+__device__ __forceinline__ void claim(bool do_claim, const uint32_t* visb, uint32_t* nextb, uint32_t* summb,
+                                      int32_t x) {
     if (!do_claim) return;
     const uint32_t bit = 1u << (x & 31);
     const int64_t wd = x >> 5;
-    if (!((visb[wd] | nextb[wd]) & bit)) atomicOr(&nextb[wd], bit);
+    if (!((visb[wd] | nextb[wd]) & bit)) {
+        // the claim that makes a word non-zero records it in the summary (sparse builds)
+        const uint32_t old = atomicOr(&nextb[wd], bit);
+        if (summb && old == 0u) atomicOr(&summb[wd >> 5], 1u << (wd & 31));
+    }
+}
+
+// The instance's summary bitmap (sparse builds) or null.
+__device__ __forceinline__ uint32_t* summary_of(const SampleLayer& p, int64_t inst) {
+    return p.summ ? p.summ + inst * p.nsw : nullptr;
 }
 
 // Load one tile of up to 1024 weights (from list offset base) into an LDS
@@ -803,6 +889,7 @@ __device__ __forceinline__ void load_run(const SampleLayer& p, int64_t e, bool v
     R.beg = valid ? p.fbeg[e] : 0;
     R.d = valid ? p.fdeg[e] : 0;
     R.pinfo = valid ? p.fpos[e] : 0;
+    if (R.v < p.vlo || R.v >= p.vhi) R.c = 0;  // another partition's entry (out-of-memory schedule)
     R.k = R.kind = R.do_claim = 0;
     R.c0 = 0;
     R.key = 0;
@@ -886,7 +973,8 @@ __device__ __forceinline__ void emit_slots(const SampleLayer& p, const EntryInfo
         const int32_t x = p.g.col[E.beg + pos];
         p.src[E.o + lane] = E.v;
         p.dst[E.o + lane] = x;
-        claim(E.do_claim, p.visited + (int64_t)E.inst * p.nwp, p.next + (int64_t)E.inst * p.nwp, x);
+        claim(E.do_claim, p.visited + (int64_t)E.inst * p.nwp, p.next + (int64_t)E.inst * p.nwp, summary_of(p, E.inst),
+              x);
     }
 }
 
@@ -900,6 +988,7 @@ __device__ void select_entry(const SampleLayer& p, const EntryInfo& E) {
     if (route_of(E.kind, E.k, E.P, E.d, E.wide) != kRouteWave) return;  // long-list path
     const uint32_t* visb = p.visited + (int64_t)E.inst * p.nwp;
     uint32_t* nextb = p.next + (int64_t)E.inst * p.nwp;
+    uint32_t* summb = summary_of(p, E.inst);
     const bool weighted = E.kind != kUniform;
     const uint32_t* w = weighted ? (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg : nullptr;
     const int32_t* col = p.g.col + E.beg;
@@ -914,7 +1003,7 @@ __device__ void select_entry(const SampleLayer& p, const EntryInfo& E) {
                 const int32_t x = col[j];
                 src[j] = E.v;
                 dst[j] = x;
-                claim(E.do_claim, visb, nextb, x);
+                claim(E.do_claim, visb, nextb, summb, x);
             }
         } else {
             int64_t run = 0;
@@ -935,7 +1024,7 @@ __device__ void select_entry(const SampleLayer& p, const EntryInfo& E) {
                         const int32_t nb = col[idx];
                         src[slot] = E.v;
                         dst[slot] = nb;
-                        claim(E.do_claim, visb, nextb, nb);
+                        claim(E.do_claim, visb, nextb, summb, nb);
                     }
                     run += __popcll(mask);
                 }
@@ -1099,7 +1188,7 @@ __device__ uint64_t select_groups(const SampleLayer& p, const RunLds& R, uint64_
             const int32_t nb = p.g.col[beg + pos];
             p.src[o + slot] = v;
             p.dst[o + slot] = nb;
-            claim(do_claim, p.visited + (int64_t)inst * p.nwp, p.next + (int64_t)inst * p.nwp, nb);
+            claim(do_claim, p.visited + (int64_t)inst * p.nwp, p.next + (int64_t)inst * p.nwp, summary_of(p, inst), nb);
         }
     }
     return back;
@@ -1604,9 +1693,48 @@ __global__ void k_clear_visited(ClearVisited c) {
     }
 }
 
+// Frontier entries and their edges per vertex-range partition of a layer
+// (out-of-memory schedule): partition p holds vertices [bounds[p],
+// bounds[p+1]); block-local sums in LDS, one atomic per partition and block.
+constexpr int kMaxPartitions = 64;
+
+__global__ void __launch_bounds__(kBlock) k_partition_work(const int32_t* __restrict__ fv,
+                                                           const int32_t* __restrict__ cnt, const SampleCtl* ctl,
+                                                           int32_t layer, const int64_t* __restrict__ bounds,
+                                                           int32_t np, unsigned long long* __restrict__ work) {
+    __shared__ unsigned long long s_work[2 * kMaxPartitions];
+    for (int i = threadIdx.x; i < 2 * kMaxPartitions; i += blockDim.x) s_work[i] = 0ull;
+    __syncthreads();
+    const int64_t fcount = ctl->fcount[layer];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < fcount;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = fv[e];
+        int32_t lo = 0, hi = np;  // the partition: largest p with bounds[p] <= v
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (bounds[mid] <= v) lo = mid;
+            else hi = mid;
+        }
+        atomicAdd(&s_work[2 * lo], 1ull);
+        atomicAdd(&s_work[2 * lo + 1], (unsigned long long)cnt[e]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * np; i += blockDim.x)
+        if (s_work[i]) atomicAdd(&work[i], s_work[i]);
+}
+
 }  // namespace
 
+// ---------------------------------------------------------------- launchers}  // namespace
+
 // ---------------------------------------------------------------- launchers
+void launch_partition_work(const int32_t* fv, const int32_t* cnt, const SampleCtl* ctl, int32_t layer,
+                           int64_t capacity, const int64_t* bounds, int32_t np, unsigned long long* work,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_partition_work, dim3(grid_for(capacity, kBlock, 1024)), dim3(kBlock), 0, s, fv, cnt, ctl,
+                       layer, bounds, np, work);
+}
+
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, kBlock, 65536)), dim3(kBlock), 0, s, p, value, count);
@@ -1627,10 +1755,11 @@ void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n,
 }
 
 void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* seed_offsets, int32_t ni,
-                       int64_t n, uint32_t* next, int64_t nwp, SampleCtl* ctl, hipStream_t s) {
+                       int64_t n, uint32_t* next, int64_t nwp, uint32_t* summ, int64_t nsw, SampleCtl* ctl,
+                       hipStream_t s) {
     if (num_seeds <= 0) return;
     hipLaunchKernelGGL(k_mark_seeds, dim3(grid_for(num_seeds, kBlock, 65536)), dim3(kBlock), 0, s, seeds,
-                       num_seeds, seed_offsets, ni, n, next, nwp, ctl);
+                       num_seeds, seed_offsets, ni, n, next, nwp, summ, nsw, ctl);
 }
 
 // Bitmap words per thread of the frontier build: one up to 2^20 words (one
@@ -1644,13 +1773,30 @@ int64_t frontier_build_blocks(int64_t words) {
 }
 
 void launch_frontier_build(const FrontierBuild& fb, hipStream_t s, LaunchEvents ev) {
+    if (fb.summ) {  // sparse: compact the summary, then one thread per dirty word
+        hipLaunchKernelGGL(k_dirty_compact, dim3((unsigned)fb.nb_dirty), dim3(kBlock), 0, s, fb);
+        launch_kernel(fb.burn ? k_frontier_build<1, 1, true, true> : k_frontier_build<1, 1, false, true>,
+                      dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
+        return;
+    }
     const bool wide = frontier_build_words(fb.nwords) == 16;
     if (fb.burn)
-        launch_kernel(wide ? k_frontier_build<4, 4, true> : k_frontier_build<1, 1, true>, dim3((unsigned)fb.nb),
-                      dim3(kBlock), s, ev, fb);
+        launch_kernel(wide ? k_frontier_build<4, 4, true, false> : k_frontier_build<1, 1, true, false>,
+                      dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
     else
-        launch_kernel(wide ? k_frontier_build<4, 4, false> : k_frontier_build<1, 1, false>, dim3((unsigned)fb.nb),
-                      dim3(kBlock), s, ev, fb);
+        launch_kernel(wide ? k_frontier_build<4, 4, false, false> : k_frontier_build<1, 1, false, false>,
+                      dim3((unsigned)fb.nb), dim3(kBlock), s, ev, fb);
+}
+
+int64_t sparse_build_blocks(int64_t capacity) {
+    const int64_t nb = (capacity + kBlock - 1) / kBlock;
+    return nb > 0 ? nb : 1;
+}
+
+int64_t dirty_compact_blocks(int64_t summary_words) {
+    const int64_t per = (int64_t)kBlock * 4;
+    const int64_t nb = (summary_words + per - 1) / per;
+    return nb > 0 ? nb : 1;
 }
 
 void launch_select(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {

@@ -449,6 +449,47 @@ __device__ __forceinline__ int64_t walk_step_n2v(const WalkParams& p, WalkLds<tr
     return m;
 }
 
+// First-order weighted step on a list longer than kWaveMaxD, through the
+// graph's per-list totals and chunk prefix table instead of a pass over the
+// list: r is drawn in [0, W) with W the list's total; the chunk holding r is
+// found from the chunk totals (one per lane, 64 chunks at a time, scan and
+// ballot), the 16-weight group from the chunk's inclusive group prefixes (one
+// per lane), and the candidate from the group's weights. Every sum is exact,
+// so m = max{i : S_i <= r} is the same as a scan of the whole list gives.
+__device__ __forceinline__ int64_t walk_step_long(const uint32_t* __restrict__ w, const uint64_t* __restrict__ gtab,
+                                                  uint64_t W, Key key, uint32_t c0, int32_t s, int32_t v,
+                                                  int64_t beg, int64_t d, bool& stop) {
+    const int lane = lane_id();
+    stop = W == 0;
+    if (stop) return 0;
+    const uint64_t r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+    const uint64_t* G = gtab + (beg >> kTabShift) * kChunkGroups;
+    const int64_t nch = (d + kChunk - 1) / kChunk;
+    uint64_t acc = 0;  // total of the chunks before chunk j
+    int64_t j = nch - 1;
+    for (int64_t j0 = 0; j0 < nch; j0 += kWave) {
+        const int64_t jj = j0 + lane;
+        const uint64_t t = jj < nch ? G[jj * kChunkGroups + kChunkGroups - 1] : 0ull;
+        const uint64_t incl = wave_incl_scan_u64(t);
+        const uint64_t tot = readlane_u64(incl, kWave - 1);
+        if (acc + tot > r) {
+            const int q = __popcll(ballot(jj < nch && acc + incl <= r));
+            j = j0 + q;
+            if (q > 0) acc += readlane_u64(incl, q - 1);
+            break;
+        }
+        acc += tot;
+    }
+    const uint64_t gp = G[j * kChunkGroups + lane];  // inclusive prefix of groups 0..lane of chunk j
+    const int gi = __popcll(ballot(acc + gp <= r));  // the group holding r
+    const uint64_t before = gi > 0 ? readlane_u64(gp, gi - 1) : 0ull;
+    const int64_t i0 = j * kChunk + (int64_t)gi * 16;
+    const bool in = lane < 16 && i0 + lane < d;
+    const uint64_t x = in ? (uint64_t)w[beg + i0 + lane] : 0ull;
+    const uint64_t incl = wave_incl_scan_u64(x);
+    return i0 + __popcll(ballot(in && acc + before + incl <= r));
+}
+
 template <bool kN2v, bool kMoves>
 __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
     __shared__ WalkLds<kN2v> lds_all[kWavesPerBlock];
@@ -493,7 +534,14 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
                     if (d <= kWalkBits) m = walk_step_n2v(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
                     else m = walk_step_biased<true>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
                 } else {
-                    m = walk_step_biased<false>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
+                    const bool dg = p.bias == kNeighborDegree;
+                    const uint64_t* gt = dg ? p.g.gtab_deg : p.g.gtab_ew;
+                    if (d > kWaveMaxD && gt) {
+                        const uint64_t W = (uint64_t)uniform_i64((int64_t)(dg ? p.g.wtot_deg : p.g.wtot_ew)[v]);
+                        m = walk_step_long(dg ? p.g.degw : p.g.ew, gt, W, key, c0, s, v, beg, d, stop);
+                    } else {
+                        m = walk_step_biased<false>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
+                    }
                 }
                 if (stop) break;
             }

@@ -13,6 +13,8 @@
 //                     executor, cancellation, executors that cannot allocate
 //   driver scale      served request shapes on a 2^26-vertex graph: 8,192-seed
 //                     sampling requests and 65,536-walker walks of length 80
+//   driver streamed   the partitioned (out-of-memory) graph against the
+//                     stand-in's definition, several partition and slot counts
 //
 // Exit status 0 and a last line "ok <scenario>" on success.
 #include <algorithm>
@@ -272,6 +274,65 @@ void scenario_runtime() {
     (void)hipFree(dst);
     (void)hipFree(paths);
     OK(csaw_graph_destroy(d.g));
+    (void)hipStreamDestroy(s);
+}
+
+// ----------------------------------------------------------------- streamed
+// The partitioned (out-of-memory) graph: every call equals the in-memory
+// definition, with several partition counts and slot counts; the selection
+// reads each partition's data through shifted base pointers into its slot,
+// so a wrong shift reads outside the slot's allocation.
+void scenario_streamed() {
+    hipStream_t s;
+    CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess);
+    const Host h = make_graph(1 << 14, 16 << 14, 23);
+    const int32_t kinds[3] = {CSAW_BIAS_UNIFORM, CSAW_BIAS_EDGE_WEIGHT, CSAW_BIAS_NEIGHBOR_DEGREE};
+    for (auto [np, res] : {std::pair<int, int>{4, 2}, {1, 1}, {7, 7}, {16, 1}}) {
+        csaw_pgraph pg = nullptr;
+        OK(csaw_pgraph_create(h.n, (int64_t)h.col.size(), h.rp.data(), h.col.data(), h.ew.data(), np, res, s, &pg));
+        for (int32_t ni : {1, 9, 40}) {
+            std::vector<int64_t> soff(1, 0);
+            std::vector<int32_t> seeds, fan, bias;
+            const int32_t L = 3;
+            for (int32_t i = 0; i < ni; ++i) {
+                const auto sd = pick_seeds(h, 1 + (i * 53) % 300, 300 + i + np);
+                seeds.insert(seeds.end(), sd.begin(), sd.end());
+                soff.push_back((int64_t)seeds.size());
+                const int32_t rows[3][3] = {{25, 10, 5}, {10, 5, 0}, {-1, 3, 2}};
+                fan.insert(fan.end(), rows[i % 3], rows[i % 3] + 3);
+                bias.push_back(kinds[(i + np) % 3]);
+            }
+            const Edges ref = reference_sample(h, soff, seeds, L, fan, bias);
+            csaw_sample_args a{};
+            a.num_instances = ni;
+            a.seed_offsets = soff.data();
+            int32_t* dseeds = dev_copy(seeds);
+            a.seeds = dseeds;
+            a.num_layers = L;
+            a.fanouts = fan.data();
+            a.fanout_stride = L;
+            a.bias_kinds = bias.data();
+            a.rng_seed = 7;
+            const int64_t cap = (int64_t)ref.src.size() + 10;
+            csaw_sample_out o{};
+            o.src = dev_copy(std::vector<int32_t>((size_t)cap, -9));
+            o.dst = dev_copy(std::vector<int32_t>((size_t)cap, -9));
+            o.edge_capacity = cap;
+            o.offsets = dev_copy(std::vector<int64_t>((size_t)L * ni + 1, -9));
+            csaw_stream_stats stats{};
+            OK(csaw_sample_streamed(pg, &a, &o, s, &stats));
+            CHECK(o.num_edges == (int64_t)ref.src.size());
+            CHECK(std::equal(ref.src.begin(), ref.src.end(), o.src));
+            CHECK(std::equal(ref.dst.begin(), ref.dst.end(), o.dst));
+            CHECK(std::equal(ref.offsets.begin(), ref.offsets.end(), o.offsets));
+            CHECK(stats.partition_loads >= 0 && (stats.partition_loads == 0) == (stats.bytes_loaded == 0));
+            (void)hipFree(dseeds);
+            (void)hipFree(o.src);
+            (void)hipFree(o.dst);
+            (void)hipFree(o.offsets);
+        }
+        OK(csaw_pgraph_destroy(pg));
+    }
     (void)hipStreamDestroy(s);
 }
 
@@ -580,8 +641,9 @@ int main(int argc, char** argv) {
     else if (what == "server") scenario_server();
     else if (what == "failures") scenario_failures();
     else if (what == "scale") scenario_scale();
+    else if (what == "streamed") scenario_streamed();
     else {
-        std::fprintf(stderr, "usage: driver runtime|server|failures|scale\n");
+        std::fprintf(stderr, "usage: driver runtime|server|failures|scale|streamed\n");
         return 2;
     }
     std::printf("ok %s\n", what.c_str());

@@ -52,6 +52,18 @@ uint64_t mix(uint64_t z) {
 
 }  // namespace
 
+void launch_partition_work(const int32_t* fv, const int32_t* cnt, const SampleCtl* ctl, int32_t layer, int64_t,
+                           const int64_t* bounds, int32_t np, unsigned long long* work, hipStream_t s) {
+    hipsim::enqueue(s, [=] {
+        for (int64_t e = 0; e < ctl->fcount[layer]; ++e) {
+            int32_t q = 0;
+            while (q + 1 < np && bounds[q + 1] <= fv[e]) ++q;
+            work[2 * q] += 1;
+            work[2 * q + 1] += (unsigned long long)cnt[e];
+        }
+    });
+}
+
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
     if (count <= 0) return;
     hipsim::enqueue(s, [=] { std::fill(p, p + count, value); });
@@ -102,7 +114,7 @@ void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uin
 }
 
 void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* seed_off, int32_t ni, int64_t n,
-                       uint32_t* next, int64_t nwp, SampleCtl* ctl, hipStream_t s) {
+                       uint32_t* next, int64_t nwp, uint32_t* summ, int64_t nsw, SampleCtl* ctl, hipStream_t s) {
     if (num_seeds <= 0) return;
     hipsim::enqueue(s, [=] {
         int32_t i = 0;
@@ -114,9 +126,13 @@ void launch_mark_seeds(const int32_t* seeds, int64_t num_seeds, const int64_t* s
                 continue;
             }
             next[(int64_t)i * nwp + (v >> 5)] |= 1u << (v & 31);
+            if (summ) summ[(int64_t)i * nsw + (v >> 10)] |= 1u << ((v >> 5) & 31);
         }
     });
 }
+
+int64_t sparse_build_blocks(int64_t capacity) { return capacity > 0 ? (capacity + 255) / 256 : 1; }
+int64_t dirty_compact_blocks(int64_t summary_words) { return summary_words > 0 ? (summary_words + 1023) / 1024 : 1; }
 
 int64_t frontier_build_blocks(int64_t words) {
     const int64_t per = 256 * (words > (int64_t(1) << 20) ? 16 : 1);
@@ -128,7 +144,16 @@ void launch_frontier_build(const FrontierBuild& fb, hipStream_t s, LaunchEvents)
     hipsim::enqueue(s, [fb] {
         SampleCtl* ctl = fb.ctl;
         const int64_t out_base = ctl->out_base[fb.layer];
-        int64_t pos = 0, eoff = 0, nbig = 0;
+        int64_t pos = 0, eoff = 0, nbig = 0, ndirty = 0;
+        if (fb.summ) {  // sparse: the dirty list from the summary, which is cleared
+            for (int64_t i = 0; i < (int64_t)fb.num_instances * fb.nsw; ++i) {
+                const int64_t inst = i / fb.nsw;
+                for (uint32_t bits = fb.summ[i]; bits; bits &= bits - 1)
+                    fb.dirty[ndirty++] = inst * fb.nwp + (i - inst * fb.nsw) * 32 + __builtin_ctz(bits);
+                fb.summ[i] = 0;
+            }
+            ctl->ndirty[fb.layer] = ndirty;
+        }
         for (int64_t iw = 0; iw < fb.nwords; ++iw) {
             const int64_t inst = iw / fb.nwp, local = iw - inst * fb.nwp;
             if (local == 0 && fb.offsets && fb.layer < fb.num_layers)
@@ -196,6 +221,7 @@ void launch_select(const SampleLayer& p, int, hipStream_t s, LaunchEvents) {
                 continue;
             }
             const int32_t v = p.fv[e], inst = p.fi[e], kind = p.bias[inst];
+            if (v < p.vlo || v >= p.vhi) continue;
             const uint32_t* w = weights(p.g, kind);
             const int64_t beg = p.fbeg[e], d = p.fdeg[e];
             const bool claim = p.fanout_next[inst] != 0;
@@ -208,7 +234,10 @@ void launch_select(const SampleLayer& p, int, hipStream_t s, LaunchEvents) {
                 ++j;
                 const int64_t wd = (int64_t)inst * p.nwp + (x >> 5);
                 const uint32_t bit = 1u << (x & 31);
-                if (claim && !(p.visited[wd] & bit)) p.next[wd] |= bit;
+                if (claim && !(p.visited[wd] & bit)) {
+                    if (p.summ && p.next[wd] == 0) p.summ[(int64_t)inst * p.nsw + ((x >> 5) >> 5)] |= 1u << ((x >> 5) & 31);
+                    p.next[wd] |= bit;
+                }
             }
         }
     });

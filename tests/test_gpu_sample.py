@@ -547,3 +547,33 @@ def test_caller_allocator(csaw):
         assert calls["alloc"] >= 2 and calls["free"] == calls["alloc"]
     finally:
         csaw.set_allocator(None, None)
+
+
+@pytest.mark.parametrize("rng_seed", [3, 4])
+def test_sparse_frontier_build(csaw, rng_seed):
+    """Instance bitmaps of more than 2^23 words (1,100 instances of a 2^18-vertex
+    graph) take the sparse frontier build: claims record dirty words in a
+    summary bitmap, which is compacted into an ordered dirty-word list. Empty
+    seed sets (also first and last), instances that stop early and long gaps
+    of instances without frontier entries give the segment offsets every
+    case; whole outputs against the oracle, and the next call on the same
+    workspace is exact too (summary and bitmaps left clean)."""
+    rp, col = inputs.rmat_csr(18, 16 << 18, 181)
+    ew = inputs.dst_outdeg_weights(rp, col)
+    g = csaw.Graph(rp, col, ew)
+    gen = inputs.rng(rng_seed)
+    ni = 1100
+    pool = inputs.non_isolated(rp, col)
+    counts = gen.integers(0, 40, size=ni)
+    counts[0] = counts[-1] = 0
+    counts[300:420] = 0
+    seeds = [inputs.distinct_seeds(gen, pool, int(c)) for c in counts]
+    offs = np.zeros(ni + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(x) for x in seeds])
+    rows = np.array([[10, 5, 3], [25, 0, 0], [5, 5, 5], [-1, 2, 0]], dtype=np.int32)
+    fan = rows[gen.integers(0, len(rows), size=ni)]
+    bias = gen.integers(0, 3, size=ni).astype(np.int32)
+    seeds = np.concatenate(seeds).astype(np.int32)
+    assert ni * ((len(rp) - 1 + 31) // 32) > (1 << 23)
+    run_both(csaw, g, rp, col, ew, offs, seeds, fan, bias, rng_seed, instance_base=77)
+    run_both(csaw, g, rp, col, ew, offs, seeds, fan, bias, rng_seed + 10)

@@ -44,6 +44,31 @@ def test_first_order_walks(csaw, bias):
     run_both(csaw, g, rp, col, ew, starts, 40, bias, 5, walker_base=123)
 
 
+@pytest.mark.parametrize("wide", [False, True])
+def test_weighted_walk_long_lists(csaw, wide):
+    """Lists longer than 512 take the chunk-table step: a 200,000-neighbor hub
+    whose weights hold zero runs (whole 16-weight groups and a whole
+    1,024-weight chunk of zeros) and, with `wide`, weights near 2^32 so the
+    list's total needs 64 bits; every walker starts at the hub, and walks
+    from the hub's neighbors come back to it."""
+    n = 200_001
+    hub = 0
+    edges = [(hub, i) for i in range(1, n)] + [(i, hub) for i in range(1, n)]
+    edges += [(i, i % (n - 1) + 1) for i in range(1, n, 7)]
+    rp, col = inputs.csr_from_edges(n, edges)
+    gen = inputs.rng(31)
+    hi = (1 << 32) - 1 if wide else 1000
+    ew = gen.integers(0, hi, size=len(col), dtype=np.uint64).astype(np.uint32)
+    b = int(rp[hub])
+    ew[b + 16:b + 48] = 0                 # two zero groups
+    ew[b + 3 * 1024:b + 4 * 1024] = 0     # a zero chunk
+    ew[b + 100_000:b + 100_005] = 0
+    g = csaw.Graph(rp, col, ew)
+    starts = np.concatenate([np.zeros(3000, dtype=np.int32), inputs.walker_starts(rp, col, 1000, 8)])
+    run_both(csaw, g, rp, col, ew, starts, 12, 1, 17, walker_base=5)
+    run_both(csaw, g, rp, col, ew, starts, 12, 2, 18)
+
+
 @pytest.mark.parametrize("weights", [(1, 2, 4), (4, 1, 2), (0, 1, 3), (3, 3, 3)])
 def test_node2vec(csaw, weights):
     rp, col = inputs.rmat_csr(14, 8 << 14, 22, symmetrize=True)

@@ -10,7 +10,8 @@ library's results against that placeholder's definition and every server
 result against the same request run alone. Failure injection covers a
 failing request inside a batch, decreasing device-written segment offsets, an
 impossible device step count, a request larger than an executor's memory,
-cancellation and executors that cannot allocate.
+cancellation and executors that cannot allocate. The partitioned
+(out-of-memory) graph is checked against the same definition.
 """
 import os
 import shutil
@@ -55,7 +56,7 @@ def run(exe, scenario, timeout=600):
     assert res.returncode == 0 and res.stdout.strip().endswith("ok " + scenario), res.stdout[-6000:]
 
 
-@pytest.mark.parametrize("scenario", ["runtime", "server", "failures"])
+@pytest.mark.parametrize("scenario", ["runtime", "server", "failures", "streamed"])
 @pytest.mark.parametrize("kind", ["asan", "tsan"])
 def test_host_code_under_sanitizers(drivers, kind, scenario):
     run(drivers[kind], scenario)
