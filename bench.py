@@ -368,15 +368,20 @@ def walk_step_bytes(rowptr, paths):
     """Algorithmic bytes of first-order weighted walk steps, per step from v
     with d = deg(v): 8 (row-offset pair) + 4 (neighbor id at the pick) + 4
     (path entry), plus the biases the selection needs: for d <= 512, the d
-    weights of N(v) (4 d); for longer lists, the list's total (8), its chunk
-    totals (8 per 1,024 weights), one chunk's 64 group prefixes (512) and one
-    16-weight group (64), read through the graph's per-list tables."""
+    weights of N(v) (4 d); for longer lists, read through the graph's
+    per-list tables, the running chunk totals the search visits (8 per
+    1,024-weight chunk up to 64 chunks; longer lists 64 evenly spaced totals
+    and then at most 64 of one range), one chunk's 64 group prefixes (512)
+    and one 16-weight group (64). The neighbor ids the kernel loads beside
+    the weights (to save a dependent load) are not counted."""
     deg = np.diff(rowptr)
     cur, nxt = paths[:, :-1], paths[:, 1:]
     taken = nxt >= 0
     d = deg[cur[taken]].astype(np.float64)
     long_ = d > WAVE_MAX_D
-    sel = np.where(long_, 8.0 + 8.0 * np.ceil(d / 1024.0) + 512.0 + 64.0, 4.0 * d)
+    nch = np.ceil(d / 1024.0)
+    totals = 8.0 * np.minimum(nch, 64.0) + np.where(nch > 64.0, 8.0 * np.minimum(np.ceil(nch / 64.0), 64.0), 0.0)
+    sel = np.where(long_, totals + 512.0 + 64.0, 4.0 * d)
     return 16.0 * taken.sum() + sel.sum(), int(taken.sum())
 
 
@@ -484,7 +489,7 @@ def bench_served(args):
     ew = inputs.dst_outdeg_weights(rp, col)
     g = csaw.Graph(rp, col, ew)
     log("graph n=%d m=%d ready in %.1fs" % (len(rp) - 1, len(col), time.perf_counter() - t0))
-    served_kw = dict(num_streams=3, max_batch=256, memory_budget_bytes=48 << 30)
+    served_kw = dict(num_streams=3, max_batch=256, memory_budget_bytes=48 << 30, max_batch_walkers=1 << 16)
     plain_kw = dict(num_streams=1, max_batch=1, memory_budget_bytes=16 << 30)
     qps_list = args.qps or [400.0, 1600.0, 6400.0, 25600.0]
     points = []
@@ -515,6 +520,7 @@ def bench_served(args):
             wsteps += st
     walk_ms = kernels["walk"]["ms"]
     achieved = wbytes / (walk_ms * 1e-3) / 1e9 if walk_ms > 0 else 0.0
+    copy_gbps = measured_copy_gbps()
     line = {
         "metric": "sampled edges/sec (SEPS) + HBM roofline % on 1 GPU; p50/p99 served latency",
         "value": best["served"]["seps"], "unit": "sampled edges/s", "n_gpus": 1, "steps": len(points),
@@ -527,8 +533,10 @@ def bench_served(args):
         "p50_ms": best["served"]["p50_ms"], "p99_ms": best["served"]["p99_ms"],
         "points": points,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "walk (k_walk_wave, edge-weight walks)", "launches": kernels["walk"]["launches"],
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("traffic_walk_served_rmat26.md", WALK_SOURCES),
+                     "measured_copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
+                     "kernel": "walk (k_walk_wave_first, edge-weight walks)", "launches": kernels["walk"]["launches"],
                      "avg_launch_us": walk_ms * 1e3 / max(kernels["walk"]["launches"], 1),
                      "alg_bytes_per_launch": wbytes / max(kernels["walk"]["launches"], 1),
                      "steps": wsteps},
@@ -869,6 +877,25 @@ def bench_node2vec(args):
     }
 
 
+def measured_copy_gbps(reps=5):
+    """Read + write bandwidth of a plain 1 GiB device copy (the measured
+    ceiling beside the published 8 TB/s)."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / dt / 1e9
+
+
 def bench_copy(args):
     """A plain device-to-device copy of 1 GiB (torch), K times: the known
     byte count that scales the FETCH_SIZE / WRITE_SIZE counters."""
@@ -892,6 +919,8 @@ def bench_copy(args):
 
 KERNEL_SOURCES = ("paper_2009_09103_amd/csrc/sample_kernels.hip", "paper_2009_09103_amd/csrc/device_common.h",
                   "paper_2009_09103_amd/csrc/kernels.h")
+WALK_SOURCES = ("paper_2009_09103_amd/csrc/walk_kernels.hip", "paper_2009_09103_amd/csrc/device_common.h",
+                "paper_2009_09103_amd/csrc/kernels.h")
 
 
 def kernel_source_sha(files=KERNEL_SOURCES):
@@ -903,13 +932,13 @@ def kernel_source_sha(files=KERNEL_SOURCES):
     return h.hexdigest()
 
 
-def measured_traffic(record):
+def measured_traffic(record, sources=KERNEL_SOURCES):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when the kernel sources have changed since it was taken."""
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
         return None
-    sha = kernel_source_sha()
+    sha = kernel_source_sha(sources)
     fields = {}
     with open(path) as f:
         for ln in f:

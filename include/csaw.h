@@ -436,8 +436,11 @@ csaw_status csaw_set_allocator(csaw_alloc_fn alloc_fn, csaw_free_fn free_fn, voi
  * head of the queue and, if it is a sampling request, every waiting sampling
  * request whose addition keeps the batch's exact device need (seeds, edge
  * outputs, offsets, frontiers, instance bitmaps) within the block, into one
- * multi-instance csaw_sample-equivalent call (continuous batching); walk
- * requests run one per call. Requests that arrive while others run are
+ * multi-instance csaw_sample-equivalent call (continuous batching); a walk
+ * request takes every waiting walk request of the same bias kind and node2vec
+ * weights whose paths and tables still fit the block into one launch, each
+ * walker keyed by its own request's rng_seed, id and length. Requests that
+ * arrive while others run are
  * admitted as executors and memory free up, and their work overlaps on the
  * device. Serving allocates no device memory: the server holds exactly the
  * blocks it allocated at creation. A request's result is bit-identical to
@@ -452,6 +455,8 @@ typedef struct {
     int32_t max_batch;            /* most sampling requests per call (0: 512)        */
     int32_t queue_capacity;       /* most waiting requests before BUSY (0: 65536)    */
     int32_t num_streams;          /* executor threads/streams, 1..16 (0: 2)          */
+    int64_t max_batch_walkers;    /* most walkers per walk call; a single larger
+                                     request still runs alone (0: 262144)          */
 } csaw_server_config;
 
 typedef enum { CSAW_REQUEST_SAMPLE = 0, CSAW_REQUEST_WALK = 1 } csaw_request_kind;
@@ -491,6 +496,7 @@ typedef struct {
     /* latency, microseconds from submit */
     double queued_us;             /* until its batch started                       */
     double total_us;              /* until its result was in host memory           */
+    int32_t batch_requests;       /* requests served by the same call (1: alone)   */
 } csaw_result;
 
 /* Errors: INVALID_ARG (bad config); OUT_OF_MEMORY if the executors' device

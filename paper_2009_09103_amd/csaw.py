@@ -84,7 +84,8 @@ class Tuning(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
-                ("queue_capacity", ctypes.c_int32), ("num_streams", ctypes.c_int32)]
+                ("queue_capacity", ctypes.c_int32), ("num_streams", ctypes.c_int32),
+                ("max_batch_walkers", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):
@@ -101,7 +102,7 @@ class Result(ctypes.Structure):
                 ("num_layers", ctypes.c_int32), ("layer_offsets", ctypes.POINTER(ctypes.c_int64)),
                 ("paths", ctypes.POINTER(ctypes.c_int32)), ("num_walkers", ctypes.c_int64),
                 ("length", ctypes.c_int32), ("steps", ctypes.c_int64), ("queued_us", ctypes.c_double),
-                ("total_us", ctypes.c_double)]
+                ("total_us", ctypes.c_double), ("batch_requests", ctypes.c_int32)]
 
 
 EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample", "csaw_sample_noalloc",
@@ -510,23 +511,47 @@ def profile_read(prefix: str):
     return t.value, c.value
 
 
-class ServedResult:
-    """A finished server request (host arrays, copied out of the library)."""
+class _ResultMemory:
+    """Owns a server result (csaw_result); frees it once no array views it."""
 
-    def __init__(self, r: Result):
+    def __init__(self, rp):
+        self.rp = rp
+
+    def __del__(self):
+        try:
+            lib.csaw_result_free(self.rp)
+        except Exception:
+            pass
+
+
+def _result_view(owner: _ResultMemory, cptr, n: int) -> np.ndarray:
+    """int32 array over n elements of a result's host memory, without a copy:
+    the array keeps the result alive."""
+    buf = (ctypes.c_int32 * max(n, 1)).from_address(ctypes.cast(cptr, ctypes.c_void_p).value)
+    buf._owner = owner
+    return np.frombuffer(buf, dtype=np.int32)[:n]
+
+
+class ServedResult:
+    """A finished server request. Its edge and path arrays are views of the
+    library's result memory (no copy), freed when the last of them goes."""
+
+    def __init__(self, rp):
+        r = rp.contents
+        owner = _ResultMemory(rp)
         self.status = r.status
         self.kind = r.kind
         self.queued_us, self.total_us = r.queued_us, r.total_us
+        self.batch_requests = r.batch_requests  # requests served by the same call
         if r.kind == 0 and r.status == 0:
             ne = r.num_edges
-            self.src = np.ctypeslib.as_array(r.src, shape=(max(ne, 1),))[:ne].copy()
-            self.dst = np.ctypeslib.as_array(r.dst, shape=(max(ne, 1),))[:ne].copy()
+            self.src = _result_view(owner, r.src, ne)
+            self.dst = _result_view(owner, r.dst, ne)
             self.layer_offsets = np.ctypeslib.as_array(r.layer_offsets, shape=(r.num_layers + 1,)).copy()
             self.num_edges = ne
         elif r.kind == 1 and r.status == 0:
             n = r.num_walkers * (r.length + 1)
-            arr = np.ctypeslib.as_array(r.paths, shape=(max(n, 1),))[:n].copy()
-            self.paths = arr.reshape(r.num_walkers, r.length + 1)
+            self.paths = _result_view(owner, r.paths, n).reshape(r.num_walkers, r.length + 1)
             self.steps = r.steps
             self.num_edges = r.steps
 
@@ -534,8 +559,10 @@ class ServedResult:
 class Server:
     """Request server over a resident graph (csaw_server_*)."""
 
-    def __init__(self, graph: Graph, memory_budget_bytes=0, max_batch=0, queue_capacity=0, num_streams=0):
-        cfg = ServerConfig(int(memory_budget_bytes), int(max_batch), int(queue_capacity), int(num_streams))
+    def __init__(self, graph: Graph, memory_budget_bytes=0, max_batch=0, queue_capacity=0, num_streams=0,
+                 max_batch_walkers=0):
+        cfg = ServerConfig(int(memory_budget_bytes), int(max_batch), int(queue_capacity), int(num_streams),
+                           int(max_batch_walkers))
         h = ctypes.c_void_p()
         _check(lib.csaw_server_create(graph._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -563,10 +590,7 @@ class Server:
         return t.value
 
     def _take(self, rp):
-        try:
-            return ServedResult(rp.contents)
-        finally:
-            lib.csaw_result_free(rp)
+        return ServedResult(rp)
 
     def poll(self, ticket: int):
         rp = ctypes.POINTER(Result)()

@@ -34,6 +34,10 @@ struct GraphDev {
     const uint64_t* gtab_deg;
     const uint64_t* wtot_ew;   // n: total weight of each list, per weight array
     const uint64_t* wtot_deg;
+    // running chunk totals of the same lists, one per chunk row: row
+    // (b >> 9) + j holds the total of chunks 0..j (null on partitioned graphs)
+    const uint64_t* ctab_ew;
+    const uint64_t* ctab_deg;
 };
 
 constexpr int kWaveMaxD = 512;   // longest weighted list of the wavefront kernels
@@ -152,7 +156,8 @@ void launch_select_small(const SampleLayer& p, int grid, hipStream_t s, LaunchEv
 // Chunk prefix table of every list longer than kWaveMaxD (GraphDev::gtab_*),
 // rows ((m >> kTabShift) + 1) * kChunkGroups uint64.
 int64_t chunk_table_rows(int64_t m);
-void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, hipStream_t s);
+void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
+                        hipStream_t s);
 void launch_select_big(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
 // Clears the visited bits of every frontier entry of the call's layers.
 struct ClearVisited {
@@ -185,6 +190,20 @@ void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n,
                             hipStream_t s);
 
 // --- walks (walk_kernels.hip)
+// Several walk requests of one bias kind in one launch: walker w belongs to
+// request req[w], whose Philox key, length, first walker, walker id of that
+// first walker and first path entry are given per request; steps are counted
+// per request. req == null: the launch is the one request of WalkParams.
+struct WalkBatch {
+    const int32_t* req;              // [nw] request of each walker
+    const uint64_t* key;             // [nreq] Philox key (rng seed)
+    const int32_t* length;           // [nreq]
+    const int64_t* first;            // [nreq] first walker of the request
+    const uint64_t* base;            // [nreq] walker id of that walker
+    const int64_t* path;             // [nreq] first path entry (int32 units)
+    unsigned long long* steps;       // [nreq] device counters
+};
+
 struct WalkParams {
     GraphDev g;
     int32_t bias;
@@ -199,6 +218,7 @@ struct WalkParams {
     int32_t* paths;
     unsigned long long* steps;       // device counter
     int32_t* bad_start;              // device flag
+    WalkBatch batch;                 // batch.req null: a single request
 };
 void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev = {});
 

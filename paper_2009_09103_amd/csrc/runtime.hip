@@ -224,6 +224,8 @@ struct csaw_graph_s {
     uint64_t* gtab_deg = nullptr;
     uint64_t* wtot_ew = nullptr;   // list totals per weight array
     uint64_t* wtot_deg = nullptr;
+    uint64_t* ctab_ew = nullptr;   // running chunk totals of the long lists
+    uint64_t* ctab_deg = nullptr;
     std::mutex mu;                       // lazy preparation + workspace pool
     std::vector<Workspace*> pool;
     std::atomic<int32_t> bound16{kDefaultBound16}, bound32{kDefaultBound32};  // sub-wave buckets
@@ -242,6 +244,8 @@ struct csaw_graph_s {
         g.gtab_deg = gtab_deg;
         g.wtot_ew = wtot_ew;
         g.wtot_deg = wtot_deg;
+        g.ctab_ew = ctab_ew;
+        g.ctab_deg = ctab_deg;
         return g;
     }
 };
@@ -340,9 +344,10 @@ csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
         if (!g->gtab_ew)
             HIP_OR_FAIL(hipMalloc((void**)&g->gtab_ew, (size_t)chunk_table_rows(g->m) * kChunkGroups * sizeof(uint64_t)));
         if (!g->wtot_ew) HIP_OR_FAIL(hipMalloc((void**)&g->wtot_ew, std::max<int64_t>(g->n, 1) * sizeof(uint64_t)));
+        if (!g->ctab_ew) HIP_OR_FAIL(hipMalloc((void**)&g->ctab_ew, (size_t)chunk_table_rows(g->m) * sizeof(uint64_t)));
         HIP_OR_FAIL(hipMalloc((void**)&pp, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
         launch_positive_counts(g->rowptr, g->ew, g->n, pp, g->wtot_ew, s);
-        launch_chunk_table(g->rowptr, g->ew, g->n, g->gtab_ew, s);
+        launch_chunk_table(g->rowptr, g->ew, g->n, g->gtab_ew, g->ctab_ew, s);
         const hipError_t e = hipGetLastError() != hipSuccess ? hipErrorLaunchFailure : hipStreamSynchronize(s);
         if (e != hipSuccess) {
             (void)hipFree(pp);
@@ -356,10 +361,11 @@ csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
         if (!g->gtab_deg)
             HIP_OR_FAIL(hipMalloc((void**)&g->gtab_deg, (size_t)chunk_table_rows(g->m) * kChunkGroups * sizeof(uint64_t)));
         if (!g->wtot_deg) HIP_OR_FAIL(hipMalloc((void**)&g->wtot_deg, std::max<int64_t>(g->n, 1) * sizeof(uint64_t)));
+        if (!g->ctab_deg) HIP_OR_FAIL(hipMalloc((void**)&g->ctab_deg, (size_t)chunk_table_rows(g->m) * sizeof(uint64_t)));
         HIP_OR_FAIL(hipMalloc((void**)&pp, std::max<int64_t>(g->n, 1) * sizeof(int32_t)));
         launch_degree_weights(g->rowptr, g->col, g->m, g->degw, s);
         launch_positive_counts(g->rowptr, g->degw, g->n, pp, g->wtot_deg, s);
-        launch_chunk_table(g->rowptr, g->degw, g->n, g->gtab_deg, s);
+        launch_chunk_table(g->rowptr, g->degw, g->n, g->gtab_deg, g->ctab_deg, s);
         const hipError_t e = hipGetLastError() != hipSuccess ? hipErrorLaunchFailure : hipStreamSynchronize(s);
         if (e != hipSuccess) {
             (void)hipFree(pp);
@@ -622,6 +628,8 @@ csaw_status csaw_graph_destroy(csaw_graph g) {
     if (g->gtab_deg) (void)hipFree(g->gtab_deg);
     if (g->wtot_ew) (void)hipFree(g->wtot_ew);
     if (g->wtot_deg) (void)hipFree(g->wtot_deg);
+    if (g->ctab_ew) (void)hipFree(g->ctab_ew);
+    if (g->ctab_deg) (void)hipFree(g->ctab_deg);
     delete g;
     return CSAW_OK;
 }
@@ -930,7 +938,8 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
             const GraphDev gd = g->dev();
             for (const void* q : {(const void*)gd.rowptr, (const void*)gd.col, (const void*)gd.ew, (const void*)gd.degw,
                                   (const void*)gd.ppos_ew, (const void*)gd.ppos_deg, (const void*)gd.gtab_ew,
-                                  (const void*)gd.gtab_deg, (const void*)gd.wtot_ew, (const void*)gd.wtot_deg})
+                                  (const void*)gd.gtab_deg, (const void*)gd.wtot_ew, (const void*)gd.wtot_deg,
+                                  (const void*)gd.ctab_ew, (const void*)gd.ctab_deg})
                 key.push_back((int64_t)(intptr_t)q);
             key.push_back((int64_t)P.uses_deg);
             key.push_back((int64_t)P.uses_ew);
@@ -1290,7 +1299,7 @@ csaw_status csaw_pgraph_create(int64_t n, int64_t m, const int64_t* rowptr, cons
         launch_degree_weights(g->rowptr, x.d_col, ne, x.d_degw, s);
         if (nvq > 0) {
             launch_positive_counts(g->rowptr + v0, x.d_degw - e0, nvq, g->ppos_deg + v0, g->wtot_deg + v0, s);
-            launch_chunk_table(g->rowptr + v0, x.d_degw - e0, nvq, x.d_gtab_deg - r0 * kChunkGroups, s);
+            launch_chunk_table(g->rowptr + v0, x.d_degw - e0, nvq, x.d_gtab_deg - r0 * kChunkGroups, nullptr, s);
         }
         if (pg->has_ew) {
             if (ne > 0 && (e = hipMemcpyAsync(x.d_ew, pg->h_ew + e0, (size_t)ne * 4, hipMemcpyHostToDevice, s)) !=
@@ -1298,7 +1307,7 @@ csaw_status csaw_pgraph_create(int64_t n, int64_t m, const int64_t* rowptr, cons
                 return cleanup(fail(CSAW_ERR_DEVICE, "upload: %s", hipGetErrorString(e)));
             if (nvq > 0) {
                 launch_positive_counts(g->rowptr + v0, x.d_ew - e0, nvq, g->ppos_ew + v0, g->wtot_ew + v0, s);
-                launch_chunk_table(g->rowptr + v0, x.d_ew - e0, nvq, x.d_gtab_ew - r0 * kChunkGroups, s);
+                launch_chunk_table(g->rowptr + v0, x.d_ew - e0, nvq, x.d_gtab_ew - r0 * kChunkGroups, nullptr, s);
             }
         }
         if ((e = hipGetLastError()) != hipSuccess ||
@@ -1392,29 +1401,59 @@ csaw_status csaw_autotune_sample(csaw_graph g, const csaw_sample_args* a, csaw_s
 
 // One walk call; its two device counters live in a pooled workspace, or in
 // `scratch` (kWalkScratchBytes of device memory) when that is set.
-static csaw_status walk_call(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int64_t* total_steps,
-                             csaw_stream stream, char* scratch) {
+// Checks of a walk call's kind and thresholds, and the tables its kind
+// needs: built here, or (calls in caller memory, which must not allocate)
+// required to exist already.
+static csaw_status walk_prepare(csaw_graph g, const csaw_walk_args* a, hipStream_t s, bool in_caller_memory) {
     if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
     if (!a) return fail(CSAW_ERR_INVALID_ARG, "args is NULL");
     if (a->bias_kind < kUniform || a->bias_kind > kMetropolis) return fail(CSAW_ERR_INVALID_ARG, "bad bias kind");
     if (a->bias_kind == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
     if (a->bias_kind == kNode2vec && !g->sorted) return fail(CSAW_ERR_INVALID_ARG, "NODE2VEC needs sorted adjacency lists");
-    if (a->num_walkers < 0 || a->length < 0) return fail(CSAW_ERR_INVALID_ARG, "negative num_walkers or length");
     if ((uint64_t)a->restart_threshold + (uint64_t)a->jump_threshold > (uint64_t(1) << 32))
         return fail(CSAW_ERR_INVALID_ARG, "restart_threshold + jump_threshold exceeds 2^32");
-    if (a->num_walkers > 0 && (!a->starts || !paths)) return fail(CSAW_ERR_INVALID_ARG, "starts/paths is NULL");
-    hipStream_t s = (hipStream_t)stream;
     HIP_OR_FAIL(hipSetDevice(g->device));
-    csaw_status st;
-    if (a->bias_kind == kNeighborDegree) {
-        if (scratch) {
+    if (a->bias_kind == kNeighborDegree || a->bias_kind == kEdgeWeight) {
+        if (in_caller_memory) {
             std::lock_guard<std::mutex> lk(g->mu);
-            if (!g->ppos_deg)
-                return fail(CSAW_ERR_NOT_READY, "the NEIGHBOR_DEGREE tables of this graph are not built yet");
-        } else if ((st = prepare_bias(g, kNeighborDegree, s)) != CSAW_OK) {
-            return st;
+            if (!(a->bias_kind == kNeighborDegree ? g->ppos_deg : g->ppos_ew))
+                return fail(CSAW_ERR_NOT_READY, "the tables of this bias kind are not built yet");
+        } else {
+            const csaw_status st = prepare_bias(g, a->bias_kind, s);
+            if (st != CSAW_OK) return st;
         }
     }
+    return CSAW_OK;
+}
+
+static WalkParams walk_params(csaw_graph g, const csaw_walk_args* a) {
+    WalkParams p;
+    p.g = g->dev();
+    p.bias = a->bias_kind;
+    p.w_return = a->w_return;
+    p.w_common = a->w_common;
+    p.w_outward = a->w_outward;
+    p.num_walkers = a->num_walkers;
+    p.starts = a->starts;
+    p.walker_base = a->walker_base;
+    p.length = a->length;
+    p.k0 = (uint32_t)a->rng_seed;
+    p.k1 = (uint32_t)(a->rng_seed >> 32);
+    p.walker_ids = a->walker_ids;
+    p.restart = a->restart_threshold;
+    p.jump = a->jump_threshold;
+    p.batch = WalkBatch{};
+    return p;
+}
+
+static csaw_status walk_call(csaw_graph g, const csaw_walk_args* a, int32_t* paths, int64_t* total_steps,
+                             csaw_stream stream, char* scratch) {
+    if (a && (a->num_walkers < 0 || a->length < 0))
+        return fail(CSAW_ERR_INVALID_ARG, "negative num_walkers or length");
+    if (a && a->num_walkers > 0 && (!a->starts || !paths)) return fail(CSAW_ERR_INVALID_ARG, "starts/paths is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    csaw_status st;
+    if ((st = walk_prepare(g, a, s, scratch != nullptr)) != CSAW_OK) return st;
     if (total_steps) *total_steps = 0;
     if (a->num_walkers == 0) return CSAW_OK;
     Lease rel{g, nullptr, s};
@@ -1434,21 +1473,7 @@ static csaw_status walk_call(csaw_graph g, const csaw_walk_args* a, int32_t* pat
     unsigned long long* d_steps = (unsigned long long*)dev;
     int32_t* d_bad = (int32_t*)(dev + 256);
     HIP_OR_FAIL(hipMemsetAsync(dev, 0, kWalkScratchBytes, s));
-    WalkParams p;
-    p.g = g->dev();
-    p.bias = a->bias_kind;
-    p.w_return = a->w_return;
-    p.w_common = a->w_common;
-    p.w_outward = a->w_outward;
-    p.num_walkers = a->num_walkers;
-    p.starts = a->starts;
-    p.walker_base = a->walker_base;
-    p.length = a->length;
-    p.k0 = (uint32_t)a->rng_seed;
-    p.k1 = (uint32_t)(a->rng_seed >> 32);
-    p.walker_ids = a->walker_ids;
-    p.restart = a->restart_threshold;
-    p.jump = a->jump_threshold;
+    WalkParams p = walk_params(g, a);
     p.paths = paths;
     p.steps = d_steps;
     p.bad_start = d_bad;
@@ -1644,6 +1669,90 @@ csaw_status walk_in_scratch(csaw_graph g, const csaw_walk_args* a, int32_t* path
     t_err.clear();
     if (!scratch) return fail(CSAW_ERR_INVALID_ARG, "scratch is NULL");
     return walk_call(g, a, paths, total_steps, stream, scratch);
+}
+
+WalkBatchLayout walk_batch_layout(int32_t nreq, int64_t nw) {
+    WalkBatchLayout y;
+    Carver c;
+    y.o_req = c.take<int32_t>((size_t)std::max<int64_t>(nw, 1));
+    y.o_key = c.take<uint64_t>((size_t)std::max(nreq, 1));
+    y.o_len = c.take<int32_t>((size_t)std::max(nreq, 1));
+    y.o_first = c.take<int64_t>((size_t)std::max(nreq, 1));
+    y.o_base = c.take<uint64_t>((size_t)std::max(nreq, 1));
+    y.o_path = c.take<int64_t>((size_t)std::max(nreq, 1));
+    y.o_steps = c.take<uint64_t>((size_t)std::max(nreq, 1) + 1);  // counters, then the start-vertex flag
+    y.o_bad = y.o_steps + (size_t)std::max(nreq, 1) * sizeof(uint64_t);
+    y.bytes = c.off;
+    return y;
+}
+
+void walk_batch_image(const WalkBatchReq* reqs, int32_t nreq, const int64_t* path_offset, char* image) {
+    int64_t nw = 0;
+    for (int32_t q = 0; q < nreq; ++q) nw += reqs[q].num_walkers;
+    const WalkBatchLayout y = walk_batch_layout(nreq, nw);
+    std::memset(image, 0, y.bytes);
+    int32_t* req = (int32_t*)(image + y.o_req);
+    int64_t first = 0;
+    for (int32_t q = 0; q < nreq; ++q) {
+        ((uint64_t*)(image + y.o_key))[q] = reqs[q].rng_seed;
+        ((int32_t*)(image + y.o_len))[q] = reqs[q].length;
+        ((int64_t*)(image + y.o_first))[q] = first;
+        ((uint64_t*)(image + y.o_base))[q] = reqs[q].walker_base;
+        ((int64_t*)(image + y.o_path))[q] = path_offset[q];
+        std::fill(req + first, req + first + reqs[q].num_walkers, q);
+        first += reqs[q].num_walkers;
+    }
+}
+
+csaw_status walk_batch_in_scratch(csaw_graph g, const csaw_walk_args* common, const WalkBatchReq* reqs,
+                                  int32_t nreq, const int32_t* d_starts, int32_t* d_paths, char* d_tables,
+                                  int64_t* steps, hipStream_t s) {
+    t_err.clear();
+    if (nreq <= 0 || !reqs || !d_tables || !steps) return fail(CSAW_ERR_INVALID_ARG, "empty walk batch");
+    int64_t nw = 0;
+    for (int32_t q = 0; q < nreq; ++q) {
+        if (reqs[q].num_walkers < 0 || reqs[q].length < 0)
+            return fail(CSAW_ERR_INVALID_ARG, "negative num_walkers or length");
+        nw += reqs[q].num_walkers;
+    }
+    if (nw > 0 && (!d_starts || !d_paths)) return fail(CSAW_ERR_INVALID_ARG, "starts/paths is NULL");
+    csaw_status st;
+    if ((st = walk_prepare(g, common, s, true)) != CSAW_OK) return st;
+    for (int32_t q = 0; q < nreq; ++q) steps[q] = 0;
+    if (nw == 0) return CSAW_OK;
+    const WalkBatchLayout y = walk_batch_layout(nreq, nw);
+    WalkParams p = walk_params(g, common);
+    p.num_walkers = nw;
+    p.starts = d_starts;
+    p.walker_ids = nullptr;
+    p.paths = d_paths;
+    p.steps = (unsigned long long*)(d_tables + y.o_steps);
+    p.bad_start = (int32_t*)(d_tables + y.o_bad);
+    p.batch.req = (const int32_t*)(d_tables + y.o_req);
+    p.batch.key = (const uint64_t*)(d_tables + y.o_key);
+    p.batch.length = (const int32_t*)(d_tables + y.o_len);
+    p.batch.first = (const int64_t*)(d_tables + y.o_first);
+    p.batch.base = (const uint64_t*)(d_tables + y.o_base);
+    p.batch.path = (const int64_t*)(d_tables + y.o_path);
+    p.batch.steps = (unsigned long long*)(d_tables + y.o_steps);
+    {
+        ProfScope ps(common->bias_kind == kNode2vec ? "walk_node2vec" : "walk", s, true);
+        launch_walk(p, 65536, s, ps.ev());
+    }
+    HIP_OR_FAIL(hipGetLastError());
+    std::vector<uint64_t> back((size_t)nreq + 1, 0);
+    HIP_OR_FAIL(hipMemcpyAsync(back.data(), d_tables + y.o_steps, back.size() * sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    if ((int32_t)back[nreq]) return fail(CSAW_ERR_INVALID_ARG, "a start vertex is outside [0, n)");
+    for (int32_t q = 0; q < nreq; ++q) {
+        // a device-written count: at most one step per walker and step index
+        if (back[q] > (uint64_t)reqs[q].num_walkers * (uint64_t)reqs[q].length)
+            return fail(CSAW_ERR_DEVICE, "the device reported %llu steps for %lld walkers of length %d",
+                        (unsigned long long)back[q], (long long)reqs[q].num_walkers, reqs[q].length);
+        steps[q] = (int64_t)back[q];
+    }
+    return CSAW_OK;
 }
 
 csaw_status prepare_bias_tables(csaw_graph g, int32_t kind, hipStream_t stream) {

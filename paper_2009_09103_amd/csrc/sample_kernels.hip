@@ -1279,9 +1279,11 @@ __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
 // list starting at edge b. A list of d > 512 weights spans at least
 // floor(d / 512) >= ceil(d / 1024) rows of 512 edges, so the rows of
 // different lists never meet, and every row is below (m >> kTabShift).
+// ctab (may be null) gets the list's running total at the end of each chunk:
+// ctab[(b >> kTabShift) + j] = total weight of chunks 0..j.
 __global__ void __launch_bounds__(kBlock) k_chunk_table(const int64_t* __restrict__ rowptr,
                                                         const uint32_t* __restrict__ w, int64_t n,
-                                                        uint64_t* __restrict__ tab) {
+                                                        uint64_t* __restrict__ tab, uint64_t* __restrict__ ctab) {
     __shared__ uint32_t tiles[kWavesPerBlock][kTilePad];
     const int wid = uniform_i32(threadIdx.x / kWave);
     const int lane = lane_id();
@@ -1291,12 +1293,44 @@ __global__ void __launch_bounds__(kBlock) k_chunk_table(const int64_t* __restric
         const int64_t d = uniform_i64(rowptr[v + 1]) - b;
         if (d <= kWaveMaxD) continue;
         uint64_t* row = tab + (b >> kTabShift) * kChunkGroups;
+        uint64_t run = 0;
         for (int64_t j = 0; j < chunks_of(d); ++j) {
             const int64_t len = d - j * kChunk < kChunk ? d - j * kChunk : kChunk;
             const uint64_t s = tile_group_sums(w + b + j * kChunk, 0, len, tiles[wid]);
-            row[j * kChunkGroups + lane] = wave_incl_scan_u64(s);
+            const uint64_t incl = wave_incl_scan_u64(s);
+            row[j * kChunkGroups + lane] = incl;
+            run += readlane_u64(incl, kWave - 1);
+            if (ctab && lane == 0) ctab[(b >> kTabShift) + j] = run;
         }
     }
+}
+
+// The group of chunk row `row` (64 inclusive group prefixes) that holds r,
+// given the total acc before the chunk: the first i with acc + row[i] > r,
+// and the prefix before it. Two rounds of eight independent loads (octant
+// ends, then the octant) instead of a six-step binary search.
+__device__ __forceinline__ int32_t row_group(const uint64_t* __restrict__ row, uint64_t acc, uint64_t r,
+                                             uint64_t& before) {
+    uint64_t ends[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ends[q] = row[8 * q + 7];
+    int32_t o = 0;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) o += acc + ends[q] <= r ? 1 : 0;  // r lies inside the chunk: octant 7 ends past it
+    uint64_t g8[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g8[k] = row[8 * o + k];
+    int32_t c = 0;
+    before = 0;
+    for (int q = 0; q < 8; ++q)
+        if (q < o) before = ends[q];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const bool le = acc + g8[k] <= r;
+        c += le ? 1 : 0;
+        before = le ? g8[k] : before;
+    }
+    return 8 * o + c;
 }
 
 // Per-lane search of a long list through its chunk prefixes (pass 1) and a
@@ -1331,19 +1365,8 @@ __device__ __forceinline__ void unit_search(const UnitPool& pl, uint64_t r, int6
         if (acc + t > r) break;
         acc += t;
     }
-    const uint64_t* row = pl.G + j * kChunkGroups;
-    int32_t glo = -1, ghi = kChunkGroups - 1;  // first group i with acc + row[i] > r
-    uint64_t before = 0;
-    while (ghi - glo > 1) {
-        const int32_t mid = (glo + ghi) >> 1;
-        const uint64_t v = row[mid];
-        if (acc + v > r) {
-            ghi = mid;
-        } else {
-            glo = mid;
-            before = v;
-        }
-    }
+    uint64_t before;
+    const int32_t ghi = row_group(pl.G + j * kChunkGroups, acc, r, before);
     const int64_t i = j * kChunk + (int64_t)ghi * 16;
     const int64_t end = i + 16 < pl.d ? i + 16 : pl.d;
     fine_scan_global(pl.w, i, end, acc + before, r, m, Sm, bm);
@@ -1498,19 +1521,8 @@ __device__ __forceinline__ void list_search(const uint32_t* __restrict__ w, cons
         if (acc + t > r) break;
         acc += t;
     }
-    const uint64_t* row = G + j * kChunkGroups;
-    int32_t glo = -1, ghi = kChunkGroups - 1;  // first group i with acc + row[i] > r
-    uint64_t before = 0;
-    while (ghi - glo > 1) {
-        const int32_t mid = (glo + ghi) >> 1;
-        const uint64_t v = row[mid];
-        if (acc + v > r) {
-            ghi = mid;
-        } else {
-            glo = mid;
-            before = v;
-        }
-    }
+    uint64_t before;
+    const int32_t ghi = row_group(G + j * kChunkGroups, acc, r, before);
     const int64_t i = j * kChunk + (int64_t)ghi * 16;
     fine_scan_global(w, i, i + 16 < d ? i + 16 : d, acc + before, r, m, Sm, bm);
 }
@@ -1819,10 +1831,11 @@ void launch_layer_sample(const LayerParams& p, hipStream_t s, LaunchEvents ev) {
 
 int64_t chunk_table_rows(int64_t m) { return (m >> kTabShift) + 1; }
 
-void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, hipStream_t s) {
+void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
+                        hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_chunk_table, dim3(grid_for(n, kWavesPerBlock, 65536)), dim3(kBlock), 0, s, rowptr, w, n,
-                       tab);
+                       tab, ctab);
 }
 
 void launch_select_big(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev) {

@@ -5,8 +5,8 @@
 // memory allocated when the server is created (the memory budget split
 // evenly), plus two pinned host staging buffers. A sampling batch lays out its
 // seeds, edge outputs, segment offsets and the sampling call's scratch in
-// that block; requests join a batch while the batch's exact device need
-// fits. Serving therefore allocates no device memory: what the server holds is
+// that block, a walk batch its starts, paths and per-request tables;
+// requests join a batch while the batch's exact device need fits. Serving therefore allocates no device memory: what the server holds is
 // fixed at creation, and admission is by the very bytes a batch occupies.
 // Results travel device -> pinned staging -> the result's host arrays in
 // chunks, so no copy targets pageable memory.
@@ -102,9 +102,37 @@ BatchLayout batch_layout(csaw_graph g, const BatchShape& b) {
     return y;
 }
 
-size_t walk_need(int64_t nw, int32_t length) {
-    return align_up((size_t)std::max<int64_t>(nw, 1) * sizeof(int32_t)) +
-           align_up((size_t)std::max<int64_t>(nw, 1) * ((size_t)length + 1) * sizeof(int32_t)) + csaw::kWalkScratch;
+// Aggregate shape of a walk batch, and its device layout in an executor's
+// block: every walker's start, every request's paths, the batch's tables.
+struct WalkShape {
+    int32_t nreq = 0;
+    int64_t walkers = 0, path_elems = 0;
+    void add(const Request& r) {
+        ++nreq;
+        walkers += (int64_t)r.starts.size();
+        path_elems += (int64_t)r.starts.size() * ((int64_t)r.length + 1);
+    }
+};
+
+struct WalkLayout {
+    size_t o_starts, o_paths, o_tab, total;
+};
+
+WalkLayout walk_layout(const WalkShape& b) {
+    WalkLayout y;
+    size_t at = 0;
+    y.o_starts = at;
+    at = align_up(at + (size_t)std::max<int64_t>(b.walkers, 1) * sizeof(int32_t));
+    y.o_paths = at;
+    at = align_up(at + (size_t)std::max<int64_t>(b.path_elems, 1) * sizeof(int32_t));
+    y.o_tab = at;
+    y.total = align_up(at + csaw::walk_batch_layout(b.nreq, b.walkers).bytes);
+    return y;
+}
+
+// Walk requests that one launch can serve: same bias kind and node2vec weights.
+bool same_walk_kind(const Request& a, const Request& b) {
+    return a.bias == b.bias && a.wr == b.wr && a.wc == b.wc && a.wo == b.wo;
 }
 
 }  // namespace
@@ -171,7 +199,7 @@ struct csaw_server_s {
 
     void worker(Exec& x);
     void run_sample_batch(std::vector<Request*>& batch, Exec& x, Clock::time_point t0);
-    void run_walk(Request* r, Exec& x, Clock::time_point t0);
+    void run_walk_batch(std::vector<Request*>& batch, Exec& x, Clock::time_point t0);
     void finish(Request* r, csaw_result* res);
     void free_execs();
 };
@@ -183,45 +211,89 @@ void csaw_server_s::finish(Request* r, csaw_result* res) {
     cv_done.notify_all();
 }
 
-void csaw_server_s::run_walk(Request* r, Exec& x, Clock::time_point t0) {
-    const int64_t nw = (int64_t)r->starts.size();
-    const int64_t L1 = (int64_t)r->length + 1;
-    csaw_result* res = new_result(CSAW_REQUEST_WALK, CSAW_OK);
-    if (!res) return finish(r, nullptr);
-    res->num_walkers = nw;
-    res->length = r->length;
-    res->queued_us = us_between(r->t_submit, t0);
-    res->paths = (int32_t*)std::malloc((size_t)std::max<int64_t>(nw * L1, 1) * sizeof(int32_t));
-    csaw_status stt = res->paths ? CSAW_OK : CSAW_ERR_OUT_OF_MEMORY;
-    char* d_starts = x.dev;
-    char* d_paths = x.dev + align_up((size_t)std::max<int64_t>(nw, 1) * sizeof(int32_t));
-    char* d_scratch = d_paths + align_up((size_t)std::max<int64_t>(nw, 1) * (size_t)L1 * sizeof(int32_t));
-    if (stt == CSAW_OK && nw > 0 && !x.to_device(d_starts, (const char*)r->starts.data(), (size_t)nw * sizeof(int32_t)))
+void csaw_server_s::run_walk_batch(std::vector<Request*>& batch, Exec& x, Clock::time_point t0) {
+    // longest walks first: their walkers are dispatched first and the
+    // launch's tail is short ones; each walker's path row and counters are
+    // its own, so the order changes no result
+    std::stable_sort(batch.begin(), batch.end(), [](const Request* a, const Request* b) { return a->length > b->length; });
+    const int32_t nreq = (int32_t)batch.size();
+    WalkShape shape;
+    for (Request* r : batch) shape.add(*r);
+    const WalkLayout lay = walk_layout(shape);
+    std::vector<csaw::WalkBatchReq> reqs((size_t)nreq);
+    std::vector<int64_t> path_off((size_t)nreq + 1, 0), steps((size_t)nreq, 0);
+    std::vector<int32_t> starts((size_t)shape.walkers);
+    std::vector<csaw_result*> res((size_t)nreq, nullptr);
+    csaw_status stt = lay.total <= x.bytes ? CSAW_OK : CSAW_ERR_OUT_OF_MEMORY;  // batches are formed to fit
+    int64_t w0 = 0;
+    for (int32_t q = 0; q < nreq; ++q) {
+        const Request* r = batch[q];
+        const int64_t nw = (int64_t)r->starts.size();
+        reqs[q] = csaw::WalkBatchReq{nw, r->length, r->rng_seed, r->id};
+        path_off[q + 1] = path_off[q] + nw * ((int64_t)r->length + 1);
+        std::copy(r->starts.begin(), r->starts.end(), starts.begin() + w0);
+        w0 += nw;
+        res[q] = new_result(CSAW_REQUEST_WALK, CSAW_OK);
+        if (!res[q]) continue;
+        res[q]->num_walkers = nw;
+        res[q]->length = r->length;
+        res[q]->batch_requests = nreq;
+        res[q]->paths = (int32_t*)std::malloc((size_t)std::max<int64_t>(nw * ((int64_t)r->length + 1), 1) *
+                                              sizeof(int32_t));
+        if (!res[q]->paths) stt = CSAW_ERR_OUT_OF_MEMORY;
+    }
+    for (csaw_result* r : res)
+        if (!r) stt = CSAW_ERR_OUT_OF_MEMORY;
+    const csaw::WalkBatchLayout tl = csaw::walk_batch_layout(nreq, shape.walkers);
+    std::vector<char> image(stt == CSAW_OK ? tl.bytes : 0);
+    if (stt == CSAW_OK) csaw::walk_batch_image(reqs.data(), nreq, path_off.data(), image.data());
+    if (stt == CSAW_OK && shape.walkers > 0 &&
+        !x.to_device(x.dev + lay.o_starts, (const char*)starts.data(), (size_t)shape.walkers * sizeof(int32_t)))
         stt = CSAW_ERR_DEVICE;
+    if (stt == CSAW_OK && !x.to_device(x.dev + lay.o_tab, image.data(), tl.bytes)) stt = CSAW_ERR_DEVICE;
     if (stt == CSAW_OK) {
-        csaw_walk_args a{};
-        a.bias_kind = r->bias;
-        a.w_return = r->wr;
-        a.w_common = r->wc;
-        a.w_outward = r->wo;
-        a.num_walkers = nw;
-        a.starts = (const int32_t*)d_starts;
-        a.walker_base = r->id;
-        a.length = r->length;
-        a.rng_seed = r->rng_seed;
-        int64_t steps = 0;
-        stt = csaw::walk_in_scratch(g, &a, (int32_t*)d_paths, &steps, x.st, d_scratch);
-        res->steps = steps;
+        csaw_walk_args common{};
+        common.bias_kind = batch[0]->bias;
+        common.w_return = batch[0]->wr;
+        common.w_common = batch[0]->wc;
+        common.w_outward = batch[0]->wo;
+        stt = csaw::walk_batch_in_scratch(g, &common, reqs.data(), nreq, (const int32_t*)(x.dev + lay.o_starts),
+                                          (int32_t*)(x.dev + lay.o_paths), x.dev + lay.o_tab, steps.data(), x.st);
     }
-    if (stt == CSAW_OK && nw > 0) {
-        char* out = (char*)res->paths;
-        if (!x.to_host(d_paths, (size_t)(nw * L1) * sizeof(int32_t),
-                       [out](size_t off, const char* p, size_t len) { std::memcpy(out + off, p, len); }))
-            stt = CSAW_ERR_DEVICE;
+    if (stt != CSAW_OK && nreq > 1) {  // isolate: every request on its own, so only a faulty one fails
+        for (csaw_result* r : res) csaw_result_free(r);
+        for (Request* r : batch) {
+            std::vector<Request*> one{r};
+            run_walk_batch(one, x, t0);
+        }
+        return;
     }
-    res->status = stt;
-    res->total_us = us_between(r->t_submit, Clock::now());
-    finish(r, res);
+    if (stt == CSAW_OK && path_off[nreq] > 0) {
+        // chunk [off, off + len) of the batch's paths goes to the requests it overlaps
+        auto sink = [&](size_t off, const char* p, size_t len) {
+            const int64_t e0 = (int64_t)(off / sizeof(int32_t)), e1 = e0 + (int64_t)(len / sizeof(int32_t));
+            for (int32_t q = 0; q < nreq; ++q) {
+                const int64_t s0 = std::max(e0, path_off[q]), s1 = std::min(e1, path_off[q + 1]);
+                if (s0 >= s1) continue;
+                std::memcpy(res[q]->paths + (s0 - path_off[q]), p + (s0 - e0) * sizeof(int32_t),
+                            (size_t)(s1 - s0) * sizeof(int32_t));
+            }
+        };
+        if (!x.to_host(x.dev + lay.o_paths, (size_t)path_off[nreq] * sizeof(int32_t), sink)) stt = CSAW_ERR_DEVICE;
+    }
+    const Clock::time_point t_end = Clock::now();
+    for (int32_t q = 0; q < nreq; ++q) {
+        if (res[q] && stt != CSAW_OK) {
+            csaw_result_free(res[q]);
+            res[q] = new_result(CSAW_REQUEST_WALK, stt);
+        }
+        if (res[q]) {
+            res[q]->steps = stt == CSAW_OK ? steps[q] : 0;
+            res[q]->queued_us = us_between(batch[q]->t_submit, t0);
+            res[q]->total_us = us_between(batch[q]->t_submit, t_end);
+        }
+        finish(batch[q], res[q]);
+    }
 }
 
 void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Clock::time_point t0) {
@@ -273,6 +345,7 @@ void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Cloc
         }
         csaw_result* res = new_result(CSAW_REQUEST_SAMPLE, stt);
         if (res) {
+            res->batch_requests = 1;
             res->queued_us = us_between(batch[0]->t_submit, t0);
             res->total_us = us_between(batch[0]->t_submit, Clock::now());
         }
@@ -343,6 +416,7 @@ void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Cloc
             res[i] = new_result(CSAW_REQUEST_SAMPLE, CSAW_ERR_DEVICE);
         }
         if (res[i]) {
+            res[i]->batch_requests = ni;
             res[i]->queued_us = us_between(batch[i]->t_submit, t0);
             res[i]->total_us = us_between(batch[i]->t_submit, t_end);
         }
@@ -361,7 +435,28 @@ void csaw_server_s::worker(Exec& x) {
             Request* head = queue.front();
             queue.pop_front();
             batch.push_back(head);
-            if (head->kind == CSAW_REQUEST_SAMPLE) {
+            if (head->kind == CSAW_REQUEST_WALK) {
+                // waiting walks of the same kind join while the batch's
+                // device layout fits this executor's block and its walkers
+                // stay within max_batch_walkers (smaller walk calls spread
+                // the walks, and their copies to the host, over executors)
+                WalkShape shape;
+                shape.add(*head);
+                for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < cfg.max_batch;) {
+                    Request* r = *it;
+                    if (r->kind == CSAW_REQUEST_WALK && same_walk_kind(*r, *head)) {
+                        WalkShape with = shape;
+                        with.add(*r);
+                        if (with.walkers <= cfg.max_batch_walkers && walk_layout(with).total <= x.bytes) {
+                            shape = with;
+                            batch.push_back(r);
+                            it = queue.erase(it);
+                            continue;
+                        }
+                    }
+                    ++it;
+                }
+            } else if (head->kind == CSAW_REQUEST_SAMPLE) {
                 // continuous batching: every waiting sampling request that still
                 // fits this executor's block joins, in arrival order
                 BatchShape shape;
@@ -385,7 +480,7 @@ void csaw_server_s::worker(Exec& x) {
         }
         const Clock::time_point t0 = Clock::now();
         if (batch[0]->kind == CSAW_REQUEST_SAMPLE) run_sample_batch(batch, x, t0);
-        else run_walk(batch[0], x, t0);
+        else run_walk_batch(batch, x, t0);
         for (Request* r : batch) delete r;
     }
 }
@@ -410,12 +505,14 @@ csaw_status csaw_server_create(csaw_graph g, const csaw_server_config* cfg, csaw
     *out = nullptr;
     csaw_server_config c{};
     if (cfg) c = *cfg;
-    if (c.memory_budget_bytes < 0 || c.max_batch < 0 || c.queue_capacity < 0 || c.num_streams < 0)
+    if (c.memory_budget_bytes < 0 || c.max_batch < 0 || c.queue_capacity < 0 || c.num_streams < 0 ||
+        c.max_batch_walkers < 0)
         return CSAW_ERR_INVALID_ARG;
     if (c.memory_budget_bytes == 0) c.memory_budget_bytes = int64_t(32) << 30;
     if (c.max_batch == 0) c.max_batch = 512;
     if (c.queue_capacity == 0) c.queue_capacity = 65536;
     if (c.num_streams == 0) c.num_streams = 2;
+    if (c.max_batch_walkers == 0) c.max_batch_walkers = int64_t(1) << 18;
     if (c.num_streams > 16 || c.max_batch > (1 << 20)) return CSAW_ERR_INVALID_ARG;
     csaw_server s = new csaw_server_s();
     s->g = g;
@@ -513,7 +610,9 @@ csaw_status csaw_server_submit(csaw_server s, const csaw_request* q, uint64_t* t
         r->wr = q->w_return;
         r->wc = q->w_common;
         r->wo = q->w_outward;
-        r->need = walk_need(q->num_walkers, q->length);
+        WalkShape one;
+        one.add(*r);
+        r->need = walk_layout(one).total;
     } else {
         delete r;
         return CSAW_ERR_INVALID_ARG;

@@ -41,19 +41,53 @@ __device__ __forceinline__ bool walk_move(const WalkParams& p, Key key, uint32_t
     return false;
 }
 
+// Walker w's Philox key, length, walker id (counter word 0), path row and
+// step counter: from the call, or from its request's entries in a batch.
+struct WalkerCtx {
+    Key key;
+    int32_t length;
+    uint32_t c0;
+    int32_t* path;
+    unsigned long long* steps;
+};
+
+__device__ __forceinline__ WalkerCtx walker_ctx(const WalkParams& p, int64_t w) {
+    WalkerCtx c;
+    if (p.batch.req) {
+        const int32_t q = p.batch.req[w];
+        const uint64_t k = p.batch.key[q];
+        c.key = Key{(uint32_t)k, (uint32_t)(k >> 32)};
+        c.length = p.batch.length[q];
+        const int64_t i = w - p.batch.first[q];
+        c.c0 = (uint32_t)(p.batch.base[q] + (uint64_t)i);
+        c.path = p.paths + p.batch.path[q] + i * ((int64_t)c.length + 1);
+        c.steps = p.batch.steps + q;
+    } else {
+        c.key = Key{p.k0, p.k1};
+        c.length = p.length;
+        c.c0 = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
+        c.path = p.paths + w * ((int64_t)p.length + 1);
+        c.steps = p.steps;
+    }
+    return c;
+}
+
 // kMH: Metropolis-Hastings (Section II-A): the uniform pick u is a proposal,
 // accepted iff x * deg(u) < deg(v) * 2^32 for x in [0, 2^32) drawn with
 // counter (walker id, step, v, 4); a rejected proposal is a step that stays.
 template <bool kMH>
 __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
-    const Key key{p.k0, p.k1};
-    const int64_t L1 = (int64_t)p.length + 1;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t w0 = blockIdx.x * (int64_t)blockDim.x; w0 < p.num_walkers; w0 += stride) {
         const int64_t w = w0 + threadIdx.x;
         int64_t my_steps = 0;
+        unsigned long long* my_counter = p.steps;
         if (w < p.num_walkers) {
-            int32_t* path = p.paths + w * L1;
+            const WalkerCtx wc = walker_ctx(p, w);
+            const Key key = wc.key;
+            const int64_t L1 = (int64_t)wc.length + 1;
+            int32_t* path = wc.path;
+            my_counter = wc.steps;
             int32_t v = p.starts[w];
             int32_t s = 0;
             if (v < 0 || (int64_t)v >= p.g.n) {
@@ -62,8 +96,8 @@ __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
             } else {
                 path[0] = v;
                 const int32_t start = v;
-                const uint32_t c0 = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
-                for (; s < p.length; ++s) {
+                const uint32_t c0 = wc.c0;
+                for (; s < wc.length; ++s) {
                     int32_t to;
                     if (walk_move(p, key, c0, s, v, start, to)) {
                         v = to;
@@ -88,8 +122,12 @@ __global__ void __launch_bounds__(kBlock) k_walk_uniform(WalkParams p) {
             }
             my_steps = s;
         }
-        const int64_t ws = wave_sum_i64(my_steps);
-        if (lane_id() == 0 && ws) atomicAdd(p.steps, (unsigned long long)ws);
+        if (p.batch.req) {  // lanes of one wave may belong to different requests
+            if (my_steps) atomicAdd(my_counter, (unsigned long long)my_steps);
+        } else {
+            const int64_t ws = wave_sum_i64(my_steps);
+            if (lane_id() == 0 && ws) atomicAdd(p.steps, (unsigned long long)ws);
+        }
     }
 }
 
@@ -449,58 +487,130 @@ __device__ __forceinline__ int64_t walk_step_n2v(const WalkParams& p, WalkLds<tr
     return m;
 }
 
-// First-order weighted step on a list longer than kWaveMaxD, through the
-// graph's per-list totals and chunk prefix table instead of a pass over the
-// list: r is drawn in [0, W) with W the list's total; the chunk holding r is
-// found from the chunk totals (one per lane, 64 chunks at a time, scan and
-// ballot), the 16-weight group from the chunk's inclusive group prefixes (one
-// per lane), and the candidate from the group's weights. Every sum is exact,
-// so m = max{i : S_i <= r} is the same as a scan of the whole list gives.
-__device__ __forceinline__ int64_t walk_step_long(const uint32_t* __restrict__ w, const uint64_t* __restrict__ gtab,
-                                                  uint64_t W, Key key, uint32_t c0, int32_t s, int32_t v,
-                                                  int64_t beg, int64_t d, bool& stop) {
+// First-order weighted step on a list of at most kWaveMaxD candidates, in one
+// memory round trip: lane i loads candidates i, i + 64, ... of the list,
+// weights and neighbor ids together (coalesced). The weights pass through LDS
+// so that lane i holds the run [8i, 8i + 8); the lanes' totals are scanned,
+// r is drawn in [0, W) and m = #{i : S_(i+1) <= r} (the candidate whose
+// interval [S_i, S_(i+1)) holds r) is the number of whole runs below r plus
+// the count inside the run that holds it. Returns the neighbor id.
+constexpr int kShortPer = kWaveMaxD / kWave;  // 8
+static_assert(sizeof(WalkLds<false>::tab) >= kWaveMaxD * sizeof(uint32_t), "short-list staging fits the LDS table");
+__device__ __forceinline__ int32_t walk_step_short(const uint32_t* __restrict__ w, const int32_t* __restrict__ col,
+                                                   uint32_t* sh, Key key, uint32_t c0, int32_t s, int32_t v,
+                                                   int64_t beg, int32_t d, bool& stop) {
     const int lane = lane_id();
+    uint32_t x[kShortPer];
+    int32_t y[kShortPer];
+#pragma unroll
+    for (int q = 0; q < kShortPer; ++q) {
+        const int32_t i = q * kWave + lane;
+        const bool in = i < d;
+        x[q] = in ? w[beg + i] : 0u;
+        y[q] = in ? col[beg + i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kShortPer; ++q) sh[q * kWave + lane] = x[q];
+    wave_lds_sync();
+    uint32_t a[kShortPer];
+#pragma unroll
+    for (int k = 0; k < kShortPer; ++k) a[k] = sh[lane * kShortPer + k];
+    wave_lds_sync();  // the next step rewrites sh
+    uint64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kShortPer; ++k) t += a[k];
+    const uint64_t incl = wave_incl_scan_u64(t);
+    const uint64_t W = readlane_u64(incl, kWave - 1);
     stop = W == 0;
-    if (stop) return 0;
+    if (stop) return -1;
     const uint64_t r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
-    const uint64_t* G = gtab + (beg >> kTabShift) * kChunkGroups;
+    const int L = __popcll(ballot(incl <= r));  // whole runs below r: lane L's run holds it
+    uint64_t acc = incl - t;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kShortPer; ++k) {
+        acc += a[k];
+        c += acc <= r ? 1u : 0u;
+    }
+    const int32_t m = L * kShortPer + (int32_t)readlane_u32(c, L);
+    const int qm = m / kWave;
+    int32_t nb = y[0];
+#pragma unroll
+    for (int q = 1; q < kShortPer; ++q) nb = q == qm ? y[q] : nb;
+    return readlane_i32(nb, m % kWave);
+}
+
+// First-order weighted step on a list longer than kWaveMaxD, through the
+// graph's tables instead of a pass over the list: ctab holds the list's
+// running total at the end of each 1024-weight chunk (so W is its last
+// entry), gtab each chunk's inclusive 16-weight group prefixes. The chunk
+// holding r is found by ballot over up to 64 running totals (lists of more
+// than 64 chunks first narrow the range with 64 evenly spaced totals), the
+// group by ballot over the chunk's 64 group prefixes, and the candidate from
+// the group's 16 weights, loaded with their neighbor ids. Every sum is exact,
+// so the pick is the one a scan of the whole list gives. Returns the neighbor.
+__device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w, const int32_t* __restrict__ col,
+                                                  const uint64_t* __restrict__ gtab,
+                                                  const uint64_t* __restrict__ ctab, Key key, uint32_t c0, int32_t s,
+                                                  int32_t v, int64_t beg, int64_t d, bool& stop) {
+    const int lane = lane_id();
+    const int64_t row0 = beg >> kTabShift;
+    const uint64_t* C = ctab + row0;
     const int64_t nch = (d + kChunk - 1) / kChunk;
-    uint64_t acc = 0;  // total of the chunks before chunk j
-    int64_t j = nch - 1;
-    for (int64_t j0 = 0; j0 < nch; j0 += kWave) {
-        const int64_t jj = j0 + lane;
-        const uint64_t t = jj < nch ? G[jj * kChunkGroups + kChunkGroups - 1] : 0ull;
-        const uint64_t incl = wave_incl_scan_u64(t);
-        const uint64_t tot = readlane_u64(incl, kWave - 1);
-        if (acc + tot > r) {
-            const int q = __popcll(ballot(jj < nch && acc + incl <= r));
-            j = j0 + q;
-            if (q > 0) acc += readlane_u64(incl, q - 1);
+    int64_t lo = 0, hi = nch;  // r lies in chunks [lo, hi)
+    uint64_t acc = 0;          // running total before chunk lo
+    uint64_t r = 0;
+    bool drawn = false;
+    int64_t j = 0;
+    while (true) {
+        const int64_t len = hi - lo;
+        const int64_t stride = (len + kWave - 1) / kWave;
+        const int64_t nb = (len + stride - 1) / stride;  // sampled totals (lanes in use)
+        const bool in = lane < nb;
+        int64_t idx = lo + (int64_t)(lane + 1) * stride - 1;
+        idx = idx < hi ? idx : hi - 1;
+        const uint64_t e = in ? C[idx] : ~0ull;
+        if (!drawn) {
+            const uint64_t W = readlane_u64(e, (int)nb - 1);  // total of the whole list
+            stop = W == 0;
+            if (stop) return -1;
+            r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+            drawn = true;
+        }
+        const int c = __popcll(ballot(in && e <= r));  // sampled ranges ending at or below r
+        if (c > 0) acc = readlane_u64(e, c - 1);
+        if (stride == 1) {
+            j = lo + c;
             break;
         }
-        acc += tot;
+        lo += (int64_t)c * stride;
+        hi = lo + stride < hi ? lo + stride : hi;
     }
-    const uint64_t gp = G[j * kChunkGroups + lane];  // inclusive prefix of groups 0..lane of chunk j
-    const int gi = __popcll(ballot(acc + gp <= r));  // the group holding r
-    const uint64_t before = gi > 0 ? readlane_u64(gp, gi - 1) : 0ull;
+    const uint64_t gp = gtab[(row0 + j) * kChunkGroups + lane];  // inclusive prefix of groups 0..lane of chunk j
+    const int gi = __popcll(ballot(acc + gp <= r));              // the group holding r
+    const uint64_t before = acc + (gi > 0 ? readlane_u64(gp, gi - 1) : 0ull);
     const int64_t i0 = j * kChunk + (int64_t)gi * 16;
     const bool in = lane < 16 && i0 + lane < d;
     const uint64_t x = in ? (uint64_t)w[beg + i0 + lane] : 0ull;
+    const int32_t y = in ? col[beg + i0 + lane] : 0;
     const uint64_t incl = wave_incl_scan_u64(x);
-    return i0 + __popcll(ballot(in && acc + before + incl <= r));
+    const int k = __popcll(ballot(in && before + incl <= r));
+    return readlane_i32(y, k);
 }
 
 template <bool kN2v, bool kMoves>
-__global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
+__device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
     __shared__ WalkLds<kN2v> lds_all[kWavesPerBlock];
     const int lane = lane_id();
     const int wid = uniform_i32(threadIdx.x / kWave);
     WalkLds<kN2v>& lds = lds_all[wid];
-    const Key key{p.k0, p.k1};
-    const int64_t L1 = (int64_t)p.length + 1;
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t w = blockIdx.x * (int64_t)kWavesPerBlock + wid; w < p.num_walkers; w += waves) {
-        int32_t* path = p.paths + w * L1;
+        const WalkerCtx wc = walker_ctx(p, w);
+        const Key key{(uint32_t)uniform_i32((int32_t)wc.key.k0), (uint32_t)uniform_i32((int32_t)wc.key.k1)};
+        const int32_t length = uniform_i32(wc.length);
+        const int64_t L1 = (int64_t)length + 1;
+        int32_t* path = wc.path;
         int32_t v = uniform_i32(p.starts[w]);
         if (v < 0 || (int64_t)v >= p.g.n) {
             if (lane == 0) *p.bad_start = 1;
@@ -508,12 +618,12 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
             continue;
         }
         if (lane == 0) path[0] = v;
-        const uint32_t c0 = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
+        const uint32_t c0 = (uint32_t)uniform_i32((int32_t)wc.c0);
         const int32_t start = v;
         int32_t t = -1;
         int64_t tb = 0, te = 0;
         int32_t s = 0;
-        for (; s < p.length; ++s) {
+        for (; s < length; ++s) {
             int32_t to;
             if (kMoves && walk_move(p, key, c0, s, v, start, to)) {  // uniform: the draw depends on wave-uniform values
                 if (lane == 0) path[s + 1] = to;
@@ -525,7 +635,8 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
             const int64_t beg = uniform_i64(p.g.rowptr[v]);
             const int64_t d = uniform_i64(p.g.rowptr[v + 1]) - beg;
             if (d == 0) break;
-            int64_t m;
+            int64_t m = -1;  // position of the pick (paths that return the neighbor itself leave -1)
+            int32_t nx = -1;
             bool stop = false;
             if (kN2v && t < 0) {  // first step: no previous vertex, every bias is 1
                 m = (int64_t)draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, (uint64_t)d);
@@ -535,17 +646,22 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
                     else m = walk_step_biased<true>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
                 } else {
                     const bool dg = p.bias == kNeighborDegree;
+                    const uint32_t* wts = dg ? p.g.degw : p.g.ew;
                     const uint64_t* gt = dg ? p.g.gtab_deg : p.g.gtab_ew;
-                    if (d > kWaveMaxD && gt) {
-                        const uint64_t W = (uint64_t)uniform_i64((int64_t)(dg ? p.g.wtot_deg : p.g.wtot_ew)[v]);
-                        m = walk_step_long(dg ? p.g.degw : p.g.ew, gt, W, key, c0, s, v, beg, d, stop);
+                    const uint64_t* ct = dg ? p.g.ctab_deg : p.g.ctab_ew;
+                    if (d <= kWaveMaxD) {
+                        nx = walk_step_short(wts, p.g.col, reinterpret_cast<uint32_t*>(lds.tab), key, c0, s, v, beg,
+                                             (int32_t)d, stop);
+                    } else if (gt && ct) {
+                        nx = walk_step_long(wts, p.g.col, gt, ct, key, c0, s, v, beg, d, stop);
                     } else {
                         m = walk_step_biased<false>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
                     }
                 }
                 if (stop) break;
             }
-            const int32_t nx = uniform_i32(p.g.col[beg + m]);
+            if (m >= 0) nx = uniform_i32(p.g.col[beg + m]);
+            nx = uniform_i32(nx);
             if (lane == 0) path[s + 1] = nx;
             t = v;
             tb = beg;
@@ -553,8 +669,21 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave(WalkParams p) {
             v = nx;
         }
         for (int64_t q = s + 1 + lane; q < L1; q += kWave) path[q] = -1;
-        if (lane == 0 && s) atomicAdd(p.steps, (unsigned long long)s);
+        if (lane == 0 && s) atomicAdd(wc.steps, (unsigned long long)s);
     }
+}
+
+// First-order walks are bound by the latency of their dependent loads, so
+// they are held to 8 waves per SIMD (the scalar registers this needs spill
+// to vector lanes, not to memory); node2vec keeps its larger register set.
+template <bool kMoves>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_walk_wave_first(WalkParams p) {
+    walk_wave_body<false, kMoves>(p);
+}
+
+template <bool kMoves>
+__global__ void __launch_bounds__(kBlock) k_walk_wave_n2v(WalkParams p) {
+    walk_wave_body<true, kMoves>(p);
 }
 
 }  // namespace
@@ -573,11 +702,11 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev) 
         if (g > grid) g = grid;
         const bool moves = (p.restart | p.jump) != 0;
         if (p.bias == kNode2vec) {
-            if (moves) launch_kernel(k_walk_wave<true, true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
-            else launch_kernel(k_walk_wave<true, false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            if (moves) launch_kernel(k_walk_wave_n2v<true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            else launch_kernel(k_walk_wave_n2v<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
         } else {
-            if (moves) launch_kernel(k_walk_wave<false, true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
-            else launch_kernel(k_walk_wave<false, false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            if (moves) launch_kernel(k_walk_wave_first<true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            else launch_kernel(k_walk_wave_first<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
         }
     }
 }

@@ -34,7 +34,7 @@
 
 namespace hipsim_hooks {
 extern std::atomic<uint32_t> fail_instance, corrupt_instance, slow_instance;
-extern std::atomic<uint64_t> walk_extra_steps;
+extern std::atomic<uint64_t> walk_extra_steps, walk_extra_for;
 }  // namespace hipsim_hooks
 
 namespace {
@@ -571,9 +571,48 @@ void scenario_failures() {
             csaw_result* res = nullptr;
             OK(csaw_server_wait(srv, t[k], -1, &res));
             CHECK(res && res->status == ((k == 2 || k == 4) ? CSAW_ERR_CANCELLED : CSAW_OK));
+            // the three walks left queued behind the running request share one launch
+            if (k == 1 || k == 3 || k == 5) CHECK(res->batch_requests == 3);
             csaw_result_free(res);
         }
         hipsim_hooks::slow_instance = 0xFFFFFFFFu;
+    }
+    // 5b. a walk batch whose device step count is impossible for one of its
+    // requests: the batch is run again request by request, only that one fails
+    {
+        hipsim_hooks::slow_instance = (uint32_t)trace[0].id;
+        std::vector<uint64_t> t(4);
+        OK(submit(srv, trace[0], &t[0]));
+        std::this_thread::sleep_for(std::chrono::milliseconds(20));  // it starts and sleeps
+        hipsim_hooks::walk_extra_for = 202;
+        hipsim_hooks::walk_extra_steps = 1u << 30;
+        std::vector<Req> walks(3);
+        for (int k = 0; k < 3; ++k) {
+            walks[k].kind = 1;
+            walks[k].id = 201 + k;
+            walks[k].starts = pick_seeds(h, 25, 201 + k);
+            walks[k].length = 6;
+            walks[k].bias = CSAW_BIAS_UNIFORM;
+            OK(submit(srv, walks[k], &t[1 + k]));
+        }
+        for (int k = 0; k < 4; ++k) {
+            csaw_result* res = nullptr;
+            OK(csaw_server_wait(srv, t[k], -1, &res));
+            CHECK(res && res->status == (k == 2 ? CSAW_ERR_DEVICE : CSAW_OK));
+            if (k == 1 || k == 3) CHECK(res->batch_requests == 1);  // rerun alone
+            csaw_result_free(res);
+        }
+        hipsim_hooks::walk_extra_steps = 0;
+        hipsim_hooks::walk_extra_for = ~0ull;
+        hipsim_hooks::slow_instance = 0xFFFFFFFFu;
+        for (int k = 0; k < 3; k += 2) {  // and their paths are those of the request alone
+            uint64_t tk = 0;
+            OK(submit(srv, walks[k], &tk));
+            csaw_result* res = nullptr;
+            OK(csaw_server_wait(srv, tk, -1, &res));
+            check_alone(d, walks[k], res, s);
+            csaw_result_free(res);
+        }
     }
     OK(csaw_server_destroy(srv));
     // 6. executors whose blocks cannot be allocated: creation fails cleanly

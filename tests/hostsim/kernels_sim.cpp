@@ -24,7 +24,8 @@ namespace hipsim_hooks {
 std::atomic<uint32_t> fail_instance{0xFFFFFFFFu};    // a call holding this instance id reports UNSUPPORTED
 std::atomic<uint32_t> corrupt_instance{0xFFFFFFFFu}; // ... writes decreasing segment offsets
 std::atomic<uint32_t> slow_instance{0xFFFFFFFFu};    // ... takes 50 ms
-std::atomic<uint64_t> walk_extra_steps{0};           // walks report this many steps too many
+std::atomic<uint64_t> walk_extra_steps{0};           // walks report this many steps too many ...
+std::atomic<uint64_t> walk_extra_for{~0ull};         // ... only the request with this walker base (all: ~0)
 }  // namespace hipsim_hooks
 
 namespace csaw {
@@ -93,12 +94,14 @@ void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n,
 
 int64_t chunk_table_rows(int64_t m) { return (m >> kTabShift) + 1; }
 
-void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, hipStream_t s) {
+void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
+                        hipStream_t s) {
     hipsim::enqueue(s, [=] {
         for (int64_t v = 0; v < n; ++v) {
             const int64_t b = rowptr[v], d = rowptr[v + 1] - b;
             if (d <= kWaveMaxD) continue;
             uint64_t* row = tab + (b >> kTabShift) * kChunkGroups;
+            uint64_t run = 0;
             for (int64_t j = 0; j * kChunk < d; ++j) {
                 uint64_t acc = 0;
                 for (int q = 0; q < kChunkGroups; ++q) {
@@ -108,6 +111,8 @@ void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uin
                     }
                     row[j * kChunkGroups + q] = acc;
                 }
+                run += acc;
+                if (ctab) ctab[(b >> kTabShift) + j] = run;
             }
         }
     });
@@ -265,29 +270,50 @@ void launch_call_setup(uint32_t* ctl, int64_t nctl, const uint32_t* host_tab, ui
 // A walk step from v moves to neighbor hash(walker id, step) mod deg(v).
 void launch_walk(const WalkParams& p, int, hipStream_t s, LaunchEvents) {
     hipsim::enqueue(s, [p] {
-        const int64_t L1 = (int64_t)p.length + 1;
-        uint64_t steps = 0;
+        // walker w's key, length, id, path row and counter, as the kernels
+        // resolve them (from the call, or from its request in a batch)
+        if (!p.batch.req) *p.steps = 0;
         for (int64_t w = 0; w < p.num_walkers; ++w) {
-            int32_t* path = p.paths + w * L1;
+            uint64_t key = p.k0, id;
+            int32_t len = p.length;
+            int32_t* path;
+            unsigned long long* counter = p.steps;
+            if (p.batch.req) {
+                const int32_t q = p.batch.req[w];
+                key = (uint32_t)p.batch.key[q];
+                len = p.batch.length[q];
+                const int64_t i = w - p.batch.first[q];
+                id = (uint32_t)(p.batch.base[q] + (uint64_t)i);
+                path = p.paths + p.batch.path[q] + i * ((int64_t)len + 1);
+                counter = p.batch.steps + q;
+            } else {
+                id = (uint32_t)(p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w);
+                path = p.paths + w * ((int64_t)len + 1);
+            }
             int32_t v = p.starts[w];
             if (v < 0 || v >= p.g.n) {
                 *p.bad_start = 1;
                 continue;
             }
-            const uint64_t id = p.walker_ids ? p.walker_ids[w] : p.walker_base + (uint64_t)w;
             path[0] = v;
-            for (int32_t t = 0; t < p.length; ++t) {
+            for (int32_t t = 0; t < len; ++t) {
                 const int64_t b = p.g.rowptr[v], d = p.g.rowptr[v + 1] - b;
                 if (d == 0) {
-                    for (int32_t r = t; r < p.length; ++r) path[r + 1] = -1;
+                    for (int32_t r = t; r < len; ++r) path[r + 1] = -1;
                     break;
                 }
-                v = p.g.col[b + (int64_t)(mix(id * 131 + (uint64_t)t + ((uint64_t)p.k0 << 32)) % (uint64_t)d)];
+                v = p.g.col[b + (int64_t)(mix(id * 131 + (uint64_t)t + (key << 32)) % (uint64_t)d)];
                 path[t + 1] = v;
-                ++steps;
+                ++*counter;
             }
         }
-        *p.steps = steps + hipsim_hooks::walk_extra_steps.load();
+        const uint64_t extra = hipsim_hooks::walk_extra_steps.load(), only = hipsim_hooks::walk_extra_for.load();
+        if (!p.batch.req) {
+            if (only == ~0ull || only == p.walker_base) *p.steps += extra;
+        } else {
+            for (int32_t q = 0; p.num_walkers > 0 && q <= p.batch.req[p.num_walkers - 1]; ++q)
+                if (only == ~0ull || only == p.batch.base[q]) p.batch.steps[q] += extra;
+        }
     });
 }
 

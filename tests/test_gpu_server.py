@@ -132,3 +132,25 @@ def test_cancel_queued_requests(setup):
     with pytest.raises(csaw.CsawError):
         srv.cancel(1 << 40)  # unknown ticket
     srv.close()
+
+
+def test_walks_share_launches(setup):
+    """Walk requests queued behind a running one are served by one launch per
+    bias kind; each result is still the request alone (and the oracle)."""
+    csaw, rp, col, ew, g, trace = setup
+    say("server walk batching")
+    srv = csaw.Server(g, num_streams=1, memory_budget_bytes=1 << 30, max_batch=64)
+    busy = srv.submit_walk(inputs.walker_starts(rp, col, 40000, 5), 80, 1, rng_seed=1, request_id=1)
+    reqs = []
+    for i in range(12):
+        r = dict(kind="walk", id=100 + i, rng_seed=7 * i + 3, bias=1 + (i % 2),
+                 starts=inputs.walker_starts(rp, col, 300 + 250 * i, 20 + i), length=5 + 6 * i)
+        reqs.append(r)
+    tickets = [submit(srv, r) for r in reqs]
+    assert srv.wait(busy).status == 0
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for k, (r, res) in enumerate(zip(reqs, results)):
+        check_alone(csaw, g, rp, col, ew, r, res, with_oracle=(k % 4 == 0))
+    assert max(res.batch_requests for res in results) > 1, [res.batch_requests for res in results]
+    assert all(1 <= res.batch_requests <= 6 for res in results)  # six requests of each bias kind
