@@ -343,6 +343,7 @@ def bench_batched(args):
     torch.cuda.synchronize()
     pdt = time.perf_counter() - t0
     assert plain_edges == edges
+    split = batched_split(g, offs, seeds, fanouts, bias, args, edges)
     return {
         "metric": "sampled edges/sec (SEPS), batched multi-instance vs plain per-instance calls",
         "value": edges / dt, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps,
@@ -361,7 +362,62 @@ def bench_batched(args):
         "kernel_ms_per_step": {k: v[0] for k, v in times.items()},
         "plain_calls": {"value": plain_edges / pdt, "calls": ni, "seconds": pdt},
         "batched_over_plain": (edges / dt) / (plain_edges / pdt),
+        "split_streams_ms": split,
     }
+
+
+def batched_split(g, offs, seeds, fanouts, bias, args, edges):
+    """The batch's layer barrier, measured: the instances split into k
+    interleaved sub-batches (instance i in sub-batch i mod k, ids kept, so
+    every instance draws the same edges) run as k concurrent calls on k
+    streams from k host threads. If the barrier's tail (a layer waiting for
+    its slowest instances) cost time, independent sub-batches would fill each
+    other's tails and finish sooner; per-instance layer progression is the
+    limit k = number of instances. Returns ms per step for each k."""
+    import threading
+    import torch
+    dev = g.device
+    ni = len(offs) - 1
+    out = {}
+    for k in (1, 2, 4):
+        subs = []
+        for j in range(k):
+            ids = np.arange(j, ni, k)
+            cnt = (offs[ids + 1] - offs[ids]).astype(np.int64)
+            so = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+            sd = np.concatenate([seeds[offs[i]:offs[i + 1]] for i in ids]).astype(np.int32)
+            fo, bi = fanouts[ids], bias[ids]
+            cap = g.sample_bound(so, fo, bi)
+            o = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+                 torch.empty(fanouts.shape[1] * len(ids) + 1, dtype=torch.int64, device=dev))
+            subs.append(dict(so=so, sd=torch.from_numpy(sd).to(dev), fo=fo, bi=bi, ids=ids.astype(np.uint64), out=o,
+                             stream=torch.cuda.Stream(device=dev)))
+        counts = [0] * k
+
+        def run(j):
+            b = subs[j]
+            r = g.sample(b["so"], b["sd"], b["fo"], b["bi"], rng_seed=1, rounds=args.rounds, out=b["out"],
+                         instance_ids=b["ids"], stream=b["stream"])
+            counts[j] = r.num_edges
+
+        def step():
+            th = [threading.Thread(target=run, args=(j,)) for j in range(k)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+
+        for _ in range(max(args.warmup, 1)):
+            step()
+        torch.cuda.synchronize()
+        assert sum(counts) == edges, (k, sum(counts), edges)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        out[str(k)] = (time.perf_counter() - t0) / args.steps * 1e3
+        log("batched split into %d concurrent sub-batches: %.2f ms per step" % (k, out[str(k)]))
+    return out
 
 
 def walk_step_bytes(rowptr, paths):
@@ -489,8 +545,10 @@ def bench_served(args):
     ew = inputs.dst_outdeg_weights(rp, col)
     g = csaw.Graph(rp, col, ew)
     log("graph n=%d m=%d ready in %.1fs" % (len(rp) - 1, len(col), time.perf_counter() - t0))
-    served_kw = dict(num_streams=3, max_batch=256, memory_budget_bytes=48 << 30, max_batch_walkers=1 << 16)
-    plain_kw = dict(num_streams=1, max_batch=1, memory_budget_bytes=16 << 30)
+    pool = 2 << 30  # host result memory populated at creation, for both paths
+    served_kw = dict(num_streams=3, max_batch=256, memory_budget_bytes=48 << 30, max_batch_walkers=1 << 16,
+                     result_pool_bytes=pool)
+    plain_kw = dict(num_streams=1, max_batch=1, memory_budget_bytes=16 << 30, result_pool_bytes=pool)
     qps_list = args.qps or [400.0, 1600.0, 6400.0, 25600.0]
     points = []
     for qps in qps_list:
@@ -972,6 +1030,8 @@ def main():
     ap.add_argument("--n2v-stride", type=int, default=64)
     ap.add_argument("--partitions", type=int, default=4)
     ap.add_argument("--resident", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="served workload: skip the batched multi-instance summary added to its line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs the whole path on a single MI355X "
@@ -989,6 +1049,13 @@ def main():
         line = bench_batched(args)
     elif args.workload == "served":
         line = bench_served(args)
+        if not args.no_batched:
+            # the batched multi-instance workload (4,096 instances in one call
+            # against 4,096 plain calls, and split over concurrent streams),
+            # summarised beside the served line
+            b = bench_batched(argparse.Namespace(**dict(vars(args), steps=5, warmup=2)))
+            line["batched_rmat22"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "config", "roofline",
+                                                        "plain_calls", "batched_over_plain", "split_streams_ms")}
     elif args.workload == "streamed":
         line = bench_streamed(args)
     elif args.workload == "node2vec":

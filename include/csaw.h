@@ -457,6 +457,10 @@ typedef struct {
     int32_t num_streams;          /* executor threads/streams, 1..16 (0: 2)          */
     int64_t max_batch_walkers;    /* most walkers per walk call; a single larger
                                      request still runs alone (0: 262144)          */
+    int64_t result_pool_bytes;    /* host memory mapped and populated at creation
+                                     for result arrays, which are then written
+                                     without page faults; arrays that do not fit
+                                     come from the heap (0: none)                  */
 } csaw_server_config;
 
 typedef enum { CSAW_REQUEST_SAMPLE = 0, CSAW_REQUEST_WALK = 1 } csaw_request_kind;
@@ -520,7 +524,9 @@ void csaw_result_free(csaw_result* r);
  * done; INVALID_ARG for an unknown ticket. */
 csaw_status csaw_server_cancel(csaw_server s, uint64_t ticket);
 /* HOST outputs (each nullable): device bytes and pinned host bytes the server
- * holds (fixed from creation to destruction). */
+ * holds (fixed from creation to destruction); the result pool
+ * (result_pool_bytes) is held on top, until the server and the last result
+ * using it are freed. */
 csaw_status csaw_server_memory(csaw_server s, int64_t* device_bytes, int64_t* pinned_host_bytes);
 /* Finishes every submitted request, stops the executors and frees the
  * server. Results not fetched are freed. */

@@ -85,7 +85,7 @@ class Tuning(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("num_streams", ctypes.c_int32),
-                ("max_batch_walkers", ctypes.c_int64)]
+                ("max_batch_walkers", ctypes.c_int64), ("result_pool_bytes", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):
@@ -560,9 +560,9 @@ class Server:
     """Request server over a resident graph (csaw_server_*)."""
 
     def __init__(self, graph: Graph, memory_budget_bytes=0, max_batch=0, queue_capacity=0, num_streams=0,
-                 max_batch_walkers=0):
+                 max_batch_walkers=0, result_pool_bytes=0):
         cfg = ServerConfig(int(memory_budget_bytes), int(max_batch), int(queue_capacity), int(num_streams),
-                           int(max_batch_walkers))
+                           int(max_batch_walkers), int(result_pool_bytes))
         h = ctypes.c_void_p()
         _check(lib.csaw_server_create(graph._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -11,15 +11,20 @@
 // Results travel device -> pinned staging -> the result's host arrays in
 // chunks, so no copy targets pageable memory.
 #include <hip/hip_runtime.h>
+#include <sys/mman.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <functional>
+#include <map>
 #include <mutex>
+#include <new>
+#include <type_traits>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -54,13 +59,112 @@ double us_between(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration<double, std::micro>(b - a).count();
 }
 
-csaw_result* new_result(int32_t kind, csaw_status st) {
-    csaw_result* r = (csaw_result*)std::calloc(1, sizeof(csaw_result));
-    if (r) {
-        r->status = st;
-        r->kind = kind;
+// Host memory for result arrays, mapped and populated when the server is
+// created: writing results into pages that are already mapped runs about ten
+// times faster than into a fresh allocation, whose pages fault in one at a
+// time. Ranges are handed out first fit (4 KiB granules) and coalesced when
+// given back; the pool is reference counted (the server and every result
+// holding a range of it), so results may outlive the server.
+class HostPool {
+public:
+    static HostPool* create(size_t bytes) {
+        void* p = mmap(nullptr, bytes, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_POPULATE, -1, 0);
+        if (p == MAP_FAILED) return nullptr;
+        HostPool* h = new (std::nothrow) HostPool();
+        if (!h) {
+            munmap(p, bytes);
+            return nullptr;
+        }
+        h->base_ = (char*)p;
+        h->bytes_ = bytes;
+        h->free_[0] = bytes;
+        return h;
     }
-    return r;
+    void ref() { refs_.fetch_add(1); }
+    void unref() {
+        if (refs_.fetch_sub(1) == 1) delete this;
+    }
+    bool owns(const void* p) const { return (const char*)p >= base_ && (const char*)p < base_ + bytes_; }
+    // n bytes, or null when no free range is large enough
+    void* take(size_t n) {
+        n = (std::max<size_t>(n, 1) + kGranule - 1) / kGranule * kGranule;
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[off + n] = len - n;
+            used_[off] = n;
+            return base_ + off;
+        }
+        return nullptr;
+    }
+    void give(void* p) {
+        const size_t off = (size_t)((char*)p - base_);
+        std::lock_guard<std::mutex> lk(mu_);
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t at = off, len = u->second;
+        used_.erase(u);
+        auto next = free_.lower_bound(at);
+        if (next != free_.end() && next->first == at + len) {  // merge with the range after
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {  // and with the range before
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == at) {
+                at = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[at] = len;
+    }
+
+private:
+    static constexpr size_t kGranule = 4096;
+    HostPool() = default;
+    ~HostPool() { munmap(base_, bytes_); }
+    char* base_ = nullptr;
+    size_t bytes_ = 0;
+    std::atomic<int64_t> refs_{1};
+    std::mutex mu_;
+    std::map<size_t, size_t> free_;            // offset -> length
+    std::unordered_map<size_t, size_t> used_;  // offset -> length
+};
+
+// A result as the library allocates it: what callers see, then the pool its
+// arrays may come from (csaw_result_free gives them back).
+struct ResultBox {
+    csaw_result pub;
+    HostPool* pool;
+};
+static_assert(std::is_standard_layout<ResultBox>::value, "a csaw_result* is its box's address");
+
+csaw_result* new_result(int32_t kind, csaw_status st) {
+    ResultBox* b = new (std::nothrow) ResultBox();
+    if (!b) return nullptr;
+    b->pub.status = st;
+    b->pub.kind = kind;
+    b->pool = nullptr;
+    return &b->pub;
+}
+
+// n bytes for one of r's arrays: a range of the pool when one is free, else
+// the heap.
+void* result_array(HostPool* pool, csaw_result* r, size_t n) {
+    if (pool) {
+        if (void* p = pool->take(n)) {
+            ResultBox* b = reinterpret_cast<ResultBox*>(r);
+            if (!b->pool) {
+                b->pool = pool;
+                pool->ref();
+            }
+            return p;
+        }
+    }
+    return std::malloc(std::max<size_t>(n, 1));
 }
 
 // Aggregate shape of a sampling batch: everything its device layout depends on.
@@ -186,6 +290,7 @@ struct csaw_server_s {
     int64_t n = 0;
     std::vector<Exec> execs;
     size_t exec_bytes = 0;
+    HostPool* pool = nullptr;  // result arrays (null: the heap)
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request*> queue;
@@ -238,8 +343,8 @@ void csaw_server_s::run_walk_batch(std::vector<Request*>& batch, Exec& x, Clock:
         res[q]->num_walkers = nw;
         res[q]->length = r->length;
         res[q]->batch_requests = nreq;
-        res[q]->paths = (int32_t*)std::malloc((size_t)std::max<int64_t>(nw * ((int64_t)r->length + 1), 1) *
-                                              sizeof(int32_t));
+        res[q]->paths = (int32_t*)result_array(
+            pool, res[q], (size_t)std::max<int64_t>(nw * ((int64_t)r->length + 1), 1) * sizeof(int32_t));
         if (!res[q]->paths) stt = CSAW_ERR_OUT_OF_MEMORY;
     }
     for (csaw_result* r : res)
@@ -371,8 +476,8 @@ void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Cloc
         for (int32_t l = 0; l < L; ++l) cnt += h_off[(size_t)l * ni + i + 1] - h_off[(size_t)l * ni + i];
         res[i]->num_edges = cnt;
         res[i]->num_layers = Li;
-        res[i]->src = (int32_t*)std::malloc((size_t)std::max<int64_t>(cnt, 1) * sizeof(int32_t));
-        res[i]->dst = (int32_t*)std::malloc((size_t)std::max<int64_t>(cnt, 1) * sizeof(int32_t));
+        res[i]->src = (int32_t*)result_array(pool, res[i], (size_t)std::max<int64_t>(cnt, 1) * sizeof(int32_t));
+        res[i]->dst = (int32_t*)result_array(pool, res[i], (size_t)std::max<int64_t>(cnt, 1) * sizeof(int32_t));
         res[i]->layer_offsets = (int64_t*)std::malloc(((size_t)Li + 1) * sizeof(int64_t));
         if (!res[i]->src || !res[i]->dst || !res[i]->layer_offsets) {
             res[i]->status = CSAW_ERR_OUT_OF_MEMORY;
@@ -496,6 +601,8 @@ void csaw_server_s::free_execs() {
         if (x.st) (void)hipStreamDestroy(x.st);
     }
     execs.clear();
+    if (pool) pool->unref();  // results still holding ranges keep it alive
+    pool = nullptr;
 }
 
 extern "C" {
@@ -506,7 +613,7 @@ csaw_status csaw_server_create(csaw_graph g, const csaw_server_config* cfg, csaw
     csaw_server_config c{};
     if (cfg) c = *cfg;
     if (c.memory_budget_bytes < 0 || c.max_batch < 0 || c.queue_capacity < 0 || c.num_streams < 0 ||
-        c.max_batch_walkers < 0)
+        c.max_batch_walkers < 0 || c.result_pool_bytes < 0)
         return CSAW_ERR_INVALID_ARG;
     if (c.memory_budget_bytes == 0) c.memory_budget_bytes = int64_t(32) << 30;
     if (c.max_batch == 0) c.max_batch = 512;
@@ -527,7 +634,10 @@ csaw_status csaw_server_create(csaw_graph g, const csaw_server_config* cfg, csaw
     s->exec_bytes = (size_t)(c.memory_budget_bytes / c.num_streams) / kAlign * kAlign;
     s->execs.resize(c.num_streams);
     csaw_status st = CSAW_OK;
+    if (c.result_pool_bytes > 0 && !(s->pool = HostPool::create((size_t)c.result_pool_bytes)))
+        st = CSAW_ERR_OUT_OF_MEMORY;
     for (Exec& x : s->execs) {
+        if (st != CSAW_OK) break;
         x.bytes = s->exec_bytes;
         if (hipStreamCreateWithFlags(&x.st, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&x.ev[0], hipEventDisableTiming) != hipSuccess ||
@@ -691,11 +801,13 @@ csaw_status csaw_server_memory(csaw_server s, int64_t* device_bytes, int64_t* pi
 
 void csaw_result_free(csaw_result* r) {
     if (!r) return;
-    std::free(r->src);
-    std::free(r->dst);
-    std::free(r->layer_offsets);
-    std::free(r->paths);
-    std::free(r);
+    ResultBox* b = reinterpret_cast<ResultBox*>(r);
+    for (void* p : {(void*)r->src, (void*)r->dst, (void*)r->layer_offsets, (void*)r->paths}) {
+        if (b->pool && b->pool->owns(p)) b->pool->give(p);
+        else std::free(p);
+    }
+    if (b->pool) b->pool->unref();
+    delete b;
 }
 
 csaw_status csaw_server_destroy(csaw_server s) {

@@ -549,6 +549,7 @@ __device__ __forceinline__ int32_t walk_step_short(const uint32_t* __restrict__ 
 // group by ballot over the chunk's 64 group prefixes, and the candidate from
 // the group's 16 weights, loaded with their neighbor ids. Every sum is exact,
 // so the pick is the one a scan of the whole list gives. Returns the neighbor.
+constexpr int kWalkTotLoads = 4;  // lists of up to 4 * 64 chunks read every running total at once
 __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w, const int32_t* __restrict__ col,
                                                   const uint64_t* __restrict__ gtab,
                                                   const uint64_t* __restrict__ ctab, Key key, uint32_t c0, int32_t s,
@@ -562,7 +563,38 @@ __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w
     uint64_t r = 0;
     bool drawn = false;
     int64_t j = 0;
-    while (true) {
+    if (nch <= (int64_t)kWave * kWalkTotLoads) {
+        // every running total at once: lane L holds totals q * 64 + L, all
+        // loads issued before any is used (one memory round trip); j is the
+        // number of totals at or below r (they never decrease)
+        uint64_t e[kWalkTotLoads];
+#pragma unroll
+        for (int q = 0; q < kWalkTotLoads; ++q) {
+            const int64_t i = (int64_t)q * kWave + lane;
+            e[q] = ~0ull;
+            if ((int64_t)q * kWave < nch && i < nch) e[q] = C[i];
+        }
+        const int64_t last = nch - 1;
+        uint64_t el = e[0];
+#pragma unroll
+        for (int q = 1; q < kWalkTotLoads; ++q) el = q == (int)(last / kWave) ? e[q] : el;
+        const uint64_t W = readlane_u64(el, (int)(last % kWave));  // total of the whole list
+        stop = W == 0;
+        if (stop) return -1;
+        r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+        int64_t c = 0;
+#pragma unroll
+        for (int q = 0; q < kWalkTotLoads; ++q) c += __popcll(ballot(e[q] <= r));
+        j = c;
+        if (c > 0) {
+            uint64_t ec = e[0];
+#pragma unroll
+            for (int q = 1; q < kWalkTotLoads; ++q) ec = q == (int)((c - 1) / kWave) ? e[q] : ec;
+            acc = readlane_u64(ec, (int)((c - 1) % kWave));
+        }
+        lo = hi;  // done: skip the sampled search below
+    }
+    while (lo < hi) {
         const int64_t len = hi - lo;
         const int64_t stride = (len + kWave - 1) / kWave;
         const int64_t nb = (len + stride - 1) / stride;  // sampled totals (lanes in use)
@@ -675,10 +707,14 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
 
 // First-order walks are bound by the latency of their dependent loads, so
 // they are held to 8 waves per SIMD (the scalar registers this needs spill
-// to vector lanes, not to memory); node2vec keeps its larger register set.
-template <bool kMoves>
+// to vector lanes, not to memory); walks with restart / jump moves and
+// node2vec keep their larger register sets.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_walk_wave_first(WalkParams p) {
-    walk_wave_body<false, kMoves>(p);
+    walk_wave_body<false, false>(p);
+}
+
+__global__ void __launch_bounds__(kBlock) k_walk_wave_moves(WalkParams p) {
+    walk_wave_body<false, true>(p);
 }
 
 template <bool kMoves>
@@ -705,8 +741,8 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev) 
             if (moves) launch_kernel(k_walk_wave_n2v<true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
             else launch_kernel(k_walk_wave_n2v<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
         } else {
-            if (moves) launch_kernel(k_walk_wave_first<true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
-            else launch_kernel(k_walk_wave_first<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            if (moves) launch_kernel(k_walk_wave_moves, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            else launch_kernel(k_walk_wave_first, dim3((unsigned)g), dim3(kBlock), s, ev, p);
         }
     }
 }

@@ -468,6 +468,31 @@ void scenario_server() {
         (void)before;
         OK(csaw_server_destroy(srv));
     }
+    // a result pool too small for every result (the rest come from the heap);
+    // half of the results are freed only after the server is gone
+    {
+        csaw_server_config cfg{};
+        cfg.memory_budget_bytes = int64_t(64) << 20;
+        cfg.num_streams = 2;
+        cfg.result_pool_bytes = int64_t(1) << 20;
+        csaw_server srv = nullptr;
+        OK(csaw_server_create(d.g, &cfg, &srv));
+        const int nreq = 48;
+        std::vector<uint64_t> t(nreq);
+        for (int k = 0; k < nreq; ++k) OK(submit(srv, trace[k], &t[k]));
+        std::vector<csaw_result*> res(nreq, nullptr);
+        for (int k = 0; k < nreq; ++k) {
+            OK(csaw_server_wait(srv, t[k], -1, &res[k]));
+            check_alone(d, trace[k], res[k], s);
+        }
+        for (int k = 0; k < nreq; k += 2) csaw_result_free(res[k]);
+        OK(csaw_server_destroy(srv));
+        for (int k = 1; k < nreq; k += 2) {  // still readable, then freed
+            CHECK(res[k]->status == CSAW_OK);
+            if (trace[k].kind == 1) CHECK(res[k]->paths[0] == trace[k].starts[0]);
+            csaw_result_free(res[k]);
+        }
+    }
     OK(csaw_graph_destroy(d.g));
     (void)hipStreamDestroy(s);
 }

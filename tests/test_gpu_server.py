@@ -63,11 +63,13 @@ def check_alone(csaw, g, rp, col, ew, r, res, with_oracle):
             np.testing.assert_array_equal(res.paths, ref)
 
 
-@pytest.mark.parametrize("streams,budget", [(2, 1 << 30), (3, 24 << 20), (1, 1 << 30)])
-def test_mix_equals_alone(setup, streams, budget):
+@pytest.mark.parametrize("streams,budget,pool", [(2, 1 << 30, 0), (3, 24 << 20, 0), (1, 1 << 30, 0),
+                                                 (2, 1 << 30, 8 << 20)])
+def test_mix_equals_alone(setup, streams, budget, pool):
+    """pool: a result pool too small for every result (the rest from the heap)."""
     csaw, rp, col, ew, g, trace = setup
-    say("server streams=%d budget=%d, %d requests" % (streams, budget, len(trace)))
-    srv = csaw.Server(g, memory_budget_bytes=budget, num_streams=streams, max_batch=64)
+    say("server streams=%d budget=%d pool=%d, %d requests" % (streams, budget, pool, len(trace)))
+    srv = csaw.Server(g, memory_budget_bytes=budget, num_streams=streams, max_batch=64, result_pool_bytes=pool)
     dev_bytes, pinned = srv.memory()
     assert budget - 256 * streams < dev_bytes <= budget and pinned > 0
     tickets = [submit(srv, r) for r in trace]
