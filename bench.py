@@ -579,6 +579,10 @@ def bench_served(args):
     walk_ms = kernels["walk"]["ms"]
     achieved = wbytes / (walk_ms * 1e-3) / 1e9 if walk_ms > 0 else 0.0
     copy_gbps = measured_copy_gbps()
+    # HBM bytes per walk launch of this pass: the counter record's bytes per
+    # step (taken on the same trace) times this pass's steps per launch
+    per_step = measured_traffic("traffic_walk_served_rmat26.md", WALK_SOURCES, "hbm_bytes_per_step")
+    walk_traffic = per_step * wsteps / max(kernels["walk"]["launches"], 1) if per_step else None
     line = {
         "metric": "sampled edges/sec (SEPS) + HBM roofline % on 1 GPU; p50/p99 served latency",
         "value": best["served"]["seps"], "unit": "sampled edges/s", "n_gpus": 1, "steps": len(points),
@@ -592,7 +596,7 @@ def bench_served(args):
         "points": points,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("traffic_walk_served_rmat26.md", WALK_SOURCES),
+                     "traffic": walk_traffic,
                      "measured_copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
                      "kernel": "walk (k_walk_wave_first, edge-weight walks)", "launches": kernels["walk"]["launches"],
                      "avg_launch_us": walk_ms * 1e3 / max(kernels["walk"]["launches"], 1),
@@ -990,9 +994,10 @@ def kernel_source_sha(files=KERNEL_SOURCES):
     return h.hexdigest()
 
 
-def measured_traffic(record, sources=KERNEL_SOURCES):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when the kernel sources have changed since it was taken."""
+def measured_traffic(record, sources=KERNEL_SOURCES, field="hbm_bytes_per_launch"):
+    """HBM bytes per launch (or, with field="hbm_bytes_per_step", per walk
+    step) of the dominant kernel from the committed counter summary, or None
+    when the kernel sources have changed since it was taken."""
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
         return None
@@ -1006,7 +1011,7 @@ def measured_traffic(record, sources=KERNEL_SOURCES):
     if fields.get("kernel_source_sha256") != sha:
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(fields[field])
     except (KeyError, ValueError):
         return None
 
