@@ -934,7 +934,7 @@ def bench_node2vec(args):
         "config": {"workload": rec["name"], "scale": scale, "walkers": int(len(ids)), "length": rec["length"],
                    "node2vec_weights": list(rec["node2vec"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_walk_wave<node2vec>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_walk_wave_n2v",
                      "launches": kn, "avg_launch_us": kms / max(kn, 1) * 1e3, "alg_bytes_per_launch": alg},
     }
 
