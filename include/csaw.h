@@ -121,7 +121,9 @@ typedef void* csaw_stream; /* hipStream_t */
  *   out           receives the handle
  * Errors: INVALID_ARG for any violated bound above (checked on the host in
  * O(n + m)); OUT_OF_MEMORY if the device allocations fail. Whether every
- * adjacency list is sorted is recorded; NODE2VEC walks need it. */
+ * adjacency list is sorted is recorded; NODE2VEC walks need it. On the
+ * device the row offsets are 32-bit words when m < 2^32 and 64-bit
+ * otherwise. */
 csaw_status csaw_graph_create(int64_t num_vertices, int64_t num_edges, const int64_t* rowptr,
                               const int32_t* col, const uint32_t* edge_weight, uint32_t flags,
                               csaw_stream stream, csaw_graph* out);
@@ -297,7 +299,9 @@ typedef struct {
  * the start, entries after a stop are -1.
  * total_steps: HOST int64 or NULL, receives the number of steps taken by all
  * walkers (sampled edges).
- * Errors: INVALID_ARG (bad argument, unsorted lists for NODE2VEC, missing
+ * Errors: INVALID_ARG (bad argument, unsorted lists for NODE2VEC, NODE2VEC
+ * on a graph where some edge (u, x) has no reverse edge (x, u) -- checked on
+ * the device by the graph's first NODE2VEC walk, then remembered -- missing
  * edge weights, or a start outside [0, n) detected on the device). */
 csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* args, int32_t* paths,
                       int64_t* total_steps, csaw_stream stream);

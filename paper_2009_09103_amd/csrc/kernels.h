@@ -19,9 +19,22 @@ constexpr int32_t kWideList = (int32_t)0x80000000u;  // ppos flag: the list's to
 enum BiasKind : int32_t { kUniform = 0, kEdgeWeight = 1, kNeighborDegree = 2, kNode2vec = 3, kMetropolis = 4 };
 
 // Graph resident in HBM.
+// CSR row offsets: 32-bit words when every offset fits (m < 2^32), else
+// 64-bit; v's list is [rowptr[v], rowptr[v + 1]). Exactly one pointer is set.
+struct RowPtr {
+    const uint32_t* p32;
+    const int64_t* p64;
+    __host__ __device__ __forceinline__ int64_t operator[](int64_t v) const {
+        return p32 ? (int64_t)p32[v] : p64[v];
+    }
+    // the same offsets seen from vertex v0 on (index v means vertex v0 + v)
+    RowPtr shifted(int64_t v0) const { return RowPtr{p32 ? p32 + v0 : nullptr, p64 ? p64 + v0 : nullptr}; }
+    const void* data() const { return p32 ? (const void*)p32 : (const void*)p64; }
+};
+
 struct GraphDev {
     int64_t n, m;
-    const int64_t* rowptr;     // n+1
+    RowPtr rowptr;             // n+1
     const int32_t* col;        // m
     const uint32_t* ew;        // m or null (EDGE_WEIGHT)
     const uint32_t* degw;      // m or null (NEIGHBOR_DEGREE, materialised)
@@ -156,7 +169,7 @@ void launch_select_small(const SampleLayer& p, int grid, hipStream_t s, LaunchEv
 // Chunk prefix table of every list longer than kWaveMaxD (GraphDev::gtab_*),
 // rows ((m >> kTabShift) + 1) * kChunkGroups uint64.
 int64_t chunk_table_rows(int64_t m);
-void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
+void launch_chunk_table(RowPtr rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
                         hipStream_t s);
 void launch_select_big(const SampleLayer& p, int grid, hipStream_t s, LaunchEvents ev = {});
 // Clears the visited bits of every frontier entry of the call's layers.
@@ -184,9 +197,9 @@ void launch_partition_work(const int32_t* fv, const int32_t* cnt, const SampleCt
                            hipStream_t s);
 
 // --- graph preparation (sample_kernels.hip)
-void launch_degree_weights(const int64_t* rowptr, const int32_t* col, int64_t m, uint32_t* degw,
+void launch_degree_weights(RowPtr rowptr, const int32_t* col, int64_t m, uint32_t* degw,
                            hipStream_t s);
-void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n, int32_t* ppos, uint64_t* wtot,
+void launch_positive_counts(RowPtr rowptr, const uint32_t* w, int64_t n, int32_t* ppos, uint64_t* wtot,
                             hipStream_t s);
 
 // --- walks (walk_kernels.hip)
@@ -221,6 +234,9 @@ struct WalkParams {
     WalkBatch batch;                 // batch.req null: a single request
 };
 void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev = {});
+// Sets *flag to 1 if some edge (u, x) has no reverse edge (x, u); lists must
+// be sorted (each reverse edge is found by binary search).
+void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_t* flag, hipStream_t s);
 
 // --- multi-dimensional random walk (mdrw_kernels.hip)
 constexpr int kMaxPool = 2048;

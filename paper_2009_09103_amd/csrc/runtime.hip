@@ -214,7 +214,10 @@ struct csaw_graph_s {
     int device = 0;
     bool sorted = true;
     bool ew_streamed = false;  // edge weights exist but are streamed by partition (out-of-memory graph)
-    int64_t* rowptr = nullptr;
+    void* rowptr_mem = nullptr;    // device row offsets (32- or 64-bit, see RowPtr)
+    int32_t* dflag = nullptr;      // device word for checks over the whole graph
+    int32_t symmetric = -1;        // every edge has its reverse (-1: not checked yet)
+    RowPtr rowptr{nullptr, nullptr};
     int32_t* col = nullptr;
     uint32_t* ew = nullptr;
     uint32_t* degw = nullptr;
@@ -541,6 +544,29 @@ bool layout_sample(int32_t ni, int32_t L, const std::vector<int64_t>& fcap, int6
 
 // Host check of a CSR graph (O(n + m)): bounds, monotone offsets, ids in
 // range; reports the longest list and whether every list is sorted.
+// Device row offsets from the host's int64 array: 32-bit words when every
+// offset fits (m < 2^32; half the bytes of each row read on the device),
+// else 64-bit. *mem is the allocation, *rp the view kernels use. The
+// narrowing goes through a host buffer that must outlive the copy, so the
+// copy is waited for.
+hipError_t upload_rowptr(int64_t n, int64_t m, const int64_t* host, void** mem, RowPtr* rp, hipStream_t s) {
+    const bool narrow = m <= (int64_t)UINT32_MAX;
+    const size_t bytes = (size_t)(n + 1) * (narrow ? sizeof(uint32_t) : sizeof(int64_t));
+    hipError_t e = hipMalloc(mem, bytes);
+    if (e != hipSuccess) return e;
+    if (narrow) {
+        std::vector<uint32_t> w32((size_t)n + 1);
+        for (int64_t v = 0; v <= n; ++v) w32[(size_t)v] = (uint32_t)host[v];
+        if ((e = hipMemcpyAsync(*mem, w32.data(), bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        *rp = RowPtr{(const uint32_t*)*mem, nullptr};
+    } else {
+        if ((e = hipMemcpyAsync(*mem, host, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        *rp = RowPtr{nullptr, (const int64_t*)*mem};
+    }
+    return hipSuccess;
+}
+
 csaw_status validate_csr(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col, int64_t* max_deg_out = nullptr,
                          bool* sorted_out = nullptr) {
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(CSAW_ERR_INVALID_ARG, "num_vertices out of range");
@@ -597,12 +623,13 @@ csaw_status csaw_graph_create(int64_t n, int64_t m, const int64_t* rowptr, const
     };
     if (hipGetDevice(&g->device) != hipSuccess) return cleanup(fail(CSAW_ERR_DEVICE, "hipGetDevice failed"));
     hipError_t e;
-    if ((e = hipMalloc((void**)&g->rowptr, (n + 1) * sizeof(int64_t))) != hipSuccess ||
+    if ((e = upload_rowptr(n, m, rowptr, &g->rowptr_mem, &g->rowptr, s)) != hipSuccess)
+        return cleanup(fail(CSAW_ERR_OUT_OF_MEMORY, "row offsets: %s", hipGetErrorString(e)));
+    if ((e = hipMalloc((void**)&g->dflag, 256)) != hipSuccess ||
         (e = hipMalloc((void**)&g->col, std::max<int64_t>(m, 1) * sizeof(int32_t))) != hipSuccess ||
         (edge_weight && (e = hipMalloc((void**)&g->ew, std::max<int64_t>(m, 1) * sizeof(uint32_t))) != hipSuccess))
         return cleanup(fail(CSAW_ERR_OUT_OF_MEMORY, "graph allocation failed: %s", hipGetErrorString(e)));
-    if ((e = hipMemcpyAsync(g->rowptr, rowptr, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (m > 0 && (e = hipMemcpyAsync(g->col, col, m * sizeof(int32_t), hipMemcpyHostToDevice, s)) != hipSuccess) ||
+    if ((m > 0 && (e = hipMemcpyAsync(g->col, col, m * sizeof(int32_t), hipMemcpyHostToDevice, s)) != hipSuccess) ||
         (edge_weight && m > 0 &&
          (e = hipMemcpyAsync(g->ew, edge_weight, m * sizeof(uint32_t), hipMemcpyHostToDevice, s)) != hipSuccess) ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -618,7 +645,8 @@ csaw_status csaw_graph_create(int64_t n, int64_t m, const int64_t* rowptr, const
 csaw_status csaw_graph_destroy(csaw_graph g) {
     if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
     for (Workspace* w : g->pool) delete w;
-    if (g->rowptr) (void)hipFree(g->rowptr);
+    if (g->rowptr_mem) (void)hipFree(g->rowptr_mem);
+    if (g->dflag) (void)hipFree(g->dflag);
     if (g->col) (void)hipFree(g->col);
     if (g->ew) (void)hipFree(g->ew);
     if (g->degw) (void)hipFree(g->degw);
@@ -936,7 +964,7 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
             // bias tables of a weight array appear on its first use, so a
             // sequence captured before then must not serve a later call
             const GraphDev gd = g->dev();
-            for (const void* q : {(const void*)gd.rowptr, (const void*)gd.col, (const void*)gd.ew, (const void*)gd.degw,
+            for (const void* q : {gd.rowptr.data(), (const void*)gd.col, (const void*)gd.ew, (const void*)gd.degw,
                                   (const void*)gd.ppos_ew, (const void*)gd.ppos_deg, (const void*)gd.gtab_ew,
                                   (const void*)gd.gtab_deg, (const void*)gd.wtot_ew, (const void*)gd.wtot_deg,
                                   (const void*)gd.ctab_ew, (const void*)gd.ctab_deg})
@@ -1237,8 +1265,9 @@ csaw_status csaw_pgraph_create(int64_t n, int64_t m, const int64_t* rowptr, cons
     }
     const int64_t nv = std::max<int64_t>(n, 1);
     hipError_t e;
-    if ((e = hipMalloc((void**)&g->rowptr, (n + 1) * sizeof(int64_t))) != hipSuccess ||
-        (e = hipMalloc((void**)&g->ppos_deg, nv * sizeof(int32_t))) != hipSuccess ||
+    if ((e = upload_rowptr(n, m, rowptr, &g->rowptr_mem, &g->rowptr, s)) != hipSuccess)
+        return cleanup(fail(CSAW_ERR_OUT_OF_MEMORY, "row offsets: %s", hipGetErrorString(e)));
+    if ((e = hipMalloc((void**)&g->ppos_deg, nv * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc((void**)&g->wtot_deg, nv * sizeof(uint64_t))) != hipSuccess ||
         (pg->has_ew && (e = hipMalloc((void**)&g->ppos_ew, nv * sizeof(int32_t))) != hipSuccess) ||
         (pg->has_ew && (e = hipMalloc((void**)&g->wtot_ew, nv * sizeof(uint64_t))) != hipSuccess) ||
@@ -1282,9 +1311,8 @@ csaw_status csaw_pgraph_create(int64_t n, int64_t m, const int64_t* rowptr, cons
             (e = hipEventCreateWithFlags(&x.idle, hipEventDisableTiming)) != hipSuccess)
             return cleanup(fail(CSAW_ERR_DEVICE, "event: %s", hipGetErrorString(e)));
     }
-    if ((e = hipMemcpyAsync(g->rowptr, rowptr, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(pg->d_vb, pg->vb.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
-            hipSuccess)
+    if ((e = hipMemcpyAsync(pg->d_vb, pg->vb.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
         return cleanup(fail(CSAW_ERR_DEVICE, "upload: %s", hipGetErrorString(e)));
     // per-partition preparation through slot 0: the degree bias of every edge,
     // the positive counts and totals of the partition's lists, their chunk
@@ -1298,16 +1326,16 @@ csaw_status csaw_pgraph_create(int64_t n, int64_t m, const int64_t* rowptr, cons
             return cleanup(fail(CSAW_ERR_DEVICE, "upload: %s", hipGetErrorString(e)));
         launch_degree_weights(g->rowptr, x.d_col, ne, x.d_degw, s);
         if (nvq > 0) {
-            launch_positive_counts(g->rowptr + v0, x.d_degw - e0, nvq, g->ppos_deg + v0, g->wtot_deg + v0, s);
-            launch_chunk_table(g->rowptr + v0, x.d_degw - e0, nvq, x.d_gtab_deg - r0 * kChunkGroups, nullptr, s);
+            launch_positive_counts(g->rowptr.shifted(v0), x.d_degw - e0, nvq, g->ppos_deg + v0, g->wtot_deg + v0, s);
+            launch_chunk_table(g->rowptr.shifted(v0), x.d_degw - e0, nvq, x.d_gtab_deg - r0 * kChunkGroups, nullptr, s);
         }
         if (pg->has_ew) {
             if (ne > 0 && (e = hipMemcpyAsync(x.d_ew, pg->h_ew + e0, (size_t)ne * 4, hipMemcpyHostToDevice, s)) !=
                               hipSuccess)
                 return cleanup(fail(CSAW_ERR_DEVICE, "upload: %s", hipGetErrorString(e)));
             if (nvq > 0) {
-                launch_positive_counts(g->rowptr + v0, x.d_ew - e0, nvq, g->ppos_ew + v0, g->wtot_ew + v0, s);
-                launch_chunk_table(g->rowptr + v0, x.d_ew - e0, nvq, x.d_gtab_ew - r0 * kChunkGroups, nullptr, s);
+                launch_positive_counts(g->rowptr.shifted(v0), x.d_ew - e0, nvq, g->ppos_ew + v0, g->wtot_ew + v0, s);
+                launch_chunk_table(g->rowptr.shifted(v0), x.d_ew - e0, nvq, x.d_gtab_ew - r0 * kChunkGroups, nullptr, s);
             }
         }
         if ((e = hipGetLastError()) != hipSuccess ||
@@ -1413,6 +1441,22 @@ static csaw_status walk_prepare(csaw_graph g, const csaw_walk_args* a, hipStream
     if ((uint64_t)a->restart_threshold + (uint64_t)a->jump_threshold > (uint64_t(1) << 32))
         return fail(CSAW_ERR_INVALID_ARG, "restart_threshold + jump_threshold exceeds 2^32");
     HIP_OR_FAIL(hipSetDevice(g->device));
+    if (a->bias_kind == kNode2vec) {
+        // node2vec's second-order bias is defined on undirected graphs: the
+        // first such walk checks on the device that every edge has its
+        // reverse (no allocation: the graph's flag word), later ones reuse it
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (g->symmetric < 0) {
+            int32_t h = 0;
+            HIP_OR_FAIL(hipMemsetAsync(g->dflag, 0, sizeof(int32_t), s));
+            launch_symmetric_check(g->rowptr, g->col, g->n, g->dflag, s);
+            HIP_OR_FAIL(hipGetLastError());
+            HIP_OR_FAIL(hipMemcpyAsync(&h, g->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            g->symmetric = h ? 0 : 1;
+        }
+        if (!g->symmetric) return fail(CSAW_ERR_INVALID_ARG, "NODE2VEC needs a symmetric graph (an edge has no reverse)");
+    }
     if (a->bias_kind == kNeighborDegree || a->bias_kind == kEdgeWeight) {
         if (in_caller_memory) {
             std::lock_guard<std::mutex> lk(g->mu);

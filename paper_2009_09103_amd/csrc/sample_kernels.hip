@@ -40,7 +40,7 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
         p[i] = v;
 }
 
-__global__ void k_degree_weights(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+__global__ void k_degree_weights(RowPtr rowptr, const int32_t* __restrict__ col,
                                  int64_t m, uint32_t* __restrict__ degw) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -52,7 +52,7 @@ __global__ void k_degree_weights(const int64_t* __restrict__ rowptr, const int32
 // one wavefront per vertex: number of positive weights in its list, with
 // kWideList set when the list's total weight needs more than 32 bits, and
 // the total itself
-__global__ void k_positive_counts(const int64_t* __restrict__ rowptr, const uint32_t* __restrict__ w,
+__global__ void k_positive_counts(RowPtr rowptr, const uint32_t* __restrict__ w,
                                   int64_t n, int32_t* __restrict__ ppos, uint64_t* __restrict__ wtot) {
     const int lane = lane_id();
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -1281,7 +1281,7 @@ __global__ void __launch_bounds__(kBlock) k_select(SampleLayer p) {
 // different lists never meet, and every row is below (m >> kTabShift).
 // ctab (may be null) gets the list's running total at the end of each chunk:
 // ctab[(b >> kTabShift) + j] = total weight of chunks 0..j.
-__global__ void __launch_bounds__(kBlock) k_chunk_table(const int64_t* __restrict__ rowptr,
+__global__ void __launch_bounds__(kBlock) k_chunk_table(RowPtr rowptr,
                                                         const uint32_t* __restrict__ w, int64_t n,
                                                         uint64_t* __restrict__ tab, uint64_t* __restrict__ ctab) {
     __shared__ uint32_t tiles[kWavesPerBlock][kTilePad];
@@ -1752,14 +1752,14 @@ void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) 
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, kBlock, 65536)), dim3(kBlock), 0, s, p, value, count);
 }
 
-void launch_degree_weights(const int64_t* rowptr, const int32_t* col, int64_t m, uint32_t* degw,
+void launch_degree_weights(RowPtr rowptr, const int32_t* col, int64_t m, uint32_t* degw,
                            hipStream_t s) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_degree_weights, dim3(grid_for(m, kBlock, 65536)), dim3(kBlock), 0, s, rowptr, col,
                        m, degw);
 }
 
-void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n, int32_t* ppos, uint64_t* wtot,
+void launch_positive_counts(RowPtr rowptr, const uint32_t* w, int64_t n, int32_t* ppos, uint64_t* wtot,
                             hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_positive_counts, dim3(grid_for(n, kWavesPerBlock, 65536)), dim3(kBlock), 0, s,
@@ -1831,7 +1831,7 @@ void launch_layer_sample(const LayerParams& p, hipStream_t s, LaunchEvents ev) {
 
 int64_t chunk_table_rows(int64_t m) { return (m >> kTabShift) + 1; }
 
-void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
+void launch_chunk_table(RowPtr rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
                         hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_chunk_table, dim3(grid_for(n, kWavesPerBlock, 65536)), dim3(kBlock), 0, s, rowptr, w, n,

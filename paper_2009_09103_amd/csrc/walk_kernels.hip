@@ -722,7 +722,30 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave_n2v(WalkParams p) {
     walk_wave_body<true, kMoves>(p);
 }
 
+// One wavefront per vertex u, a lane per edge (u, x): is u in the sorted N(x)?
+__global__ void __launch_bounds__(kBlock) k_symmetric_check(RowPtr rowptr, const int32_t* __restrict__ col,
+                                                            int64_t n, int32_t* __restrict__ flag) {
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t u = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; u < n; u += waves) {
+        const int64_t b = rowptr[u], e = rowptr[u + 1];
+        bool missing = false;
+        for (int64_t i = b + lane; i < e; i += kWave) {
+            const int32_t x = col[i];
+            missing |= !in_sorted(col, rowptr[x], rowptr[x + 1], (int32_t)u);
+        }
+        if (ballot(missing) && lane == 0) atomicOr(flag, 1);
+    }
+}
+
 }  // namespace
+
+void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_t* flag, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t g = (n + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_symmetric_check, dim3((unsigned)g), dim3(kBlock), 0, s, rowptr, col, n, flag);
+}
 
 void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev) {
     if (p.num_walkers <= 0) return;

@@ -271,6 +271,43 @@ void scenario_runtime() {
             ++count;
         }
     CHECK(count == steps);
+    // node2vec needs a symmetric graph: this directed one is refused (twice:
+    // the first call checks on the device, the second uses the kept answer)
+    w.bias_kind = CSAW_BIAS_NODE2VEC;
+    w.w_return = 1;
+    w.w_common = 2;
+    w.w_outward = 4;
+    CHECK(csaw_walk(d.g, &w, paths, &steps, s) == CSAW_ERR_INVALID_ARG);
+    CHECK(csaw_walk(d.g, &w, paths, &steps, s) == CSAW_ERR_INVALID_ARG);
+    {  // a ring with chords, every edge in both directions: accepted
+        const int64_t rn = 64;
+        std::vector<std::vector<int32_t>> adj(rn);
+        for (int64_t v = 0; v < rn; ++v)
+            for (int64_t k : {1, 5}) {
+                adj[v].push_back((int32_t)((v + k) % rn));
+                adj[(v + k) % rn].push_back((int32_t)v);
+            }
+        std::vector<int64_t> rrp(1, 0);
+        std::vector<int32_t> rcol;
+        for (auto& a : adj) {
+            std::sort(a.begin(), a.end());
+            rcol.insert(rcol.end(), a.begin(), a.end());
+            rrp.push_back((int64_t)rcol.size());
+        }
+        csaw_graph rg = nullptr;
+        OK(csaw_graph_create(rn, (int64_t)rcol.size(), rrp.data(), rcol.data(), nullptr, 0, s, &rg));
+        std::vector<int32_t> rs(40);
+        for (size_t k = 0; k < rs.size(); ++k) rs[k] = (int32_t)(k % rn);
+        int32_t* rdst = dev_copy(rs);
+        int32_t* rpaths = dev_copy(std::vector<int32_t>(rs.size() * (len + 1), 0));
+        w.num_walkers = (int64_t)rs.size();
+        w.starts = rdst;
+        OK(csaw_walk(rg, &w, rpaths, &steps, s));
+        OK(csaw_walk(rg, &w, rpaths, &steps, s));
+        (void)hipFree(rdst);
+        (void)hipFree(rpaths);
+        OK(csaw_graph_destroy(rg));
+    }
     (void)hipFree(dst);
     (void)hipFree(paths);
     OK(csaw_graph_destroy(d.g));

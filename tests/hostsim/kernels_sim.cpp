@@ -70,13 +70,13 @@ void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) 
     hipsim::enqueue(s, [=] { std::fill(p, p + count, value); });
 }
 
-void launch_degree_weights(const int64_t* rowptr, const int32_t* col, int64_t m, uint32_t* degw, hipStream_t s) {
+void launch_degree_weights(RowPtr rowptr, const int32_t* col, int64_t m, uint32_t* degw, hipStream_t s) {
     hipsim::enqueue(s, [=] {
         for (int64_t e = 0; e < m; ++e) degw[e] = (uint32_t)(rowptr[col[e] + 1] - rowptr[col[e]]);
     });
 }
 
-void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n, int32_t* ppos, uint64_t* wtot,
+void launch_positive_counts(RowPtr rowptr, const uint32_t* w, int64_t n, int32_t* ppos, uint64_t* wtot,
                             hipStream_t s) {
     hipsim::enqueue(s, [=] {
         for (int64_t v = 0; v < n; ++v) {
@@ -94,7 +94,7 @@ void launch_positive_counts(const int64_t* rowptr, const uint32_t* w, int64_t n,
 
 int64_t chunk_table_rows(int64_t m) { return (m >> kTabShift) + 1; }
 
-void launch_chunk_table(const int64_t* rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
+void launch_chunk_table(RowPtr rowptr, const uint32_t* w, int64_t n, uint64_t* tab, uint64_t* ctab,
                         hipStream_t s) {
     hipsim::enqueue(s, [=] {
         for (int64_t v = 0; v < n; ++v) {
@@ -314,6 +314,16 @@ void launch_walk(const WalkParams& p, int, hipStream_t s, LaunchEvents) {
             for (int32_t q = 0; p.num_walkers > 0 && q <= p.batch.req[p.num_walkers - 1]; ++q)
                 if (only == ~0ull || only == p.batch.base[q]) p.batch.steps[q] += extra;
         }
+    });
+}
+
+void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_t* flag, hipStream_t s) {
+    hipsim::enqueue(s, [=] {
+        for (int64_t u = 0; u < n; ++u)
+            for (int64_t i = rowptr[u]; i < rowptr[u + 1]; ++i) {
+                const int32_t x = col[i];
+                if (!std::binary_search(col + rowptr[x], col + rowptr[x + 1], (int32_t)u)) *flag = 1;
+            }
     });
 }
 

@@ -109,6 +109,24 @@ def test_node2vec_long_list_membership(csaw):
     run_both(csaw, g, rp, col, None, starts, 24, 3, 5, node2vec=(4, 1, 2))
 
 
+def test_node2vec_needs_a_symmetric_graph(csaw):
+    """node2vec's bias is defined on undirected graphs: a walk on a directed
+    graph is refused (the device check finds an edge without its reverse),
+    before and after other calls on the graph; its symmetrised version walks."""
+    rp, col = inputs.rmat_csr(12, 8 << 12, 33)
+    g = csaw.Graph(rp, col)
+    starts = inputs.walker_starts(rp, col, 100, 3)
+    say("node2vec on a directed graph")
+    for _ in range(2):
+        with pytest.raises(csaw.CsawError) as ei:
+            g.walk(starts, 10, csaw.NODE2VEC, node2vec=(1, 2, 4))
+        assert ei.value.status == 1
+        g.walk(starts, 10, csaw.UNIFORM)
+    srp, scol = inputs.rmat_csr(12, 8 << 12, 33, symmetrize=True)
+    run_both(csaw, csaw.Graph(srp, scol), srp, scol, None, inputs.walker_starts(srp, scol, 100, 3), 10, 3, 2,
+             node2vec=(1, 2, 4))
+
+
 def test_walk_edge_cases(csaw):
     rp = np.array([0, 1, 1], dtype=np.int64)
     col = np.array([1], dtype=np.int32)
