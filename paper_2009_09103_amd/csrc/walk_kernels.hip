@@ -494,11 +494,24 @@ __device__ __forceinline__ int64_t walk_step_n2v(const WalkParams& p, WalkLds<tr
 // r is drawn in [0, W) and m = #{i : S_(i+1) <= r} (the candidate whose
 // interval [S_i, S_(i+1)) holds r) is the number of whole runs below r plus
 // the count inside the run that holds it. Returns the neighbor id.
+// The step's Philox word on the vector unit. A walk step is wave-uniform, so
+// its Philox rounds would otherwise run on the scalar unit (one per compute
+// unit), which the step's other uniform work (addresses, loop control)
+// already keeps busy; the vector unit forms each 32 x 32 -> 64-bit product in
+// one instruction. The same rounds as philox_u64: the empty asm only places
+// the counter words in vector registers. The caller takes it at the top of
+// the step (the counter is known before any list data arrives) and reduces it
+// to [0, W) with range_reduce once W is known.
+__device__ __forceinline__ uint64_t philox_vec(Key key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+    uint32_t k0 = key.k0, k1 = key.k1;
+    asm volatile("" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(k0), "+v"(k1));
+    return (uint64_t)uniform_i64((int64_t)philox_u64(k0, k1, c0, c1, c2, c3));
+}
+
 constexpr int kShortPer = kWaveMaxD / kWave;  // 8
 static_assert(sizeof(WalkLds<false>::tab) >= kWaveMaxD * sizeof(uint32_t), "short-list staging fits the LDS table");
 __device__ __forceinline__ int32_t walk_step_short(const uint32_t* __restrict__ w, const int32_t* __restrict__ col,
-                                                   uint32_t* sh, Key key, uint32_t c0, int32_t s, int32_t v,
-                                                   int64_t beg, int32_t d, bool& stop) {
+                                                   uint32_t* sh, uint64_t u, int64_t beg, int32_t d, bool& stop) {
     const int lane = lane_id();
     uint32_t x[kShortPer];
     int32_t y[kShortPer];
@@ -523,7 +536,7 @@ __device__ __forceinline__ int32_t walk_step_short(const uint32_t* __restrict__ 
     const uint64_t W = readlane_u64(incl, kWave - 1);
     stop = W == 0;
     if (stop) return -1;
-    const uint64_t r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+    const uint64_t r = range_reduce(u, W);
     const int L = __popcll(ballot(incl <= r));  // whole runs below r: lane L's run holds it
     uint64_t acc = incl - t;
     uint32_t c = 0;
@@ -552,8 +565,8 @@ __device__ __forceinline__ int32_t walk_step_short(const uint32_t* __restrict__ 
 constexpr int kWalkTotLoads = 4;  // lists of up to 4 * 64 chunks read every running total at once
 __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w, const int32_t* __restrict__ col,
                                                   const uint64_t* __restrict__ gtab,
-                                                  const uint64_t* __restrict__ ctab, Key key, uint32_t c0, int32_t s,
-                                                  int32_t v, int64_t beg, int64_t d, bool& stop) {
+                                                  const uint64_t* __restrict__ ctab, uint64_t u, int64_t beg, int64_t d,
+                                                  bool& stop) {
     const int lane = lane_id();
     const int64_t row0 = beg >> kTabShift;
     const uint64_t* C = ctab + row0;
@@ -581,7 +594,7 @@ __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w
         const uint64_t W = readlane_u64(el, (int)(last % kWave));  // total of the whole list
         stop = W == 0;
         if (stop) return -1;
-        r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+        r = range_reduce(u, W);
         int64_t c = 0;
 #pragma unroll
         for (int q = 0; q < kWalkTotLoads; ++q) c += __popcll(ballot(e[q] <= r));
@@ -606,7 +619,7 @@ __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w
             const uint64_t W = readlane_u64(e, (int)nb - 1);  // total of the whole list
             stop = W == 0;
             if (stop) return -1;
-            r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+            r = range_reduce(u, W);
             drawn = true;
         }
         const int c = __popcll(ballot(in && e <= r));  // sampled ranges ending at or below r
@@ -666,6 +679,9 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
             }
             const int64_t beg = uniform_i64(p.g.rowptr[v]);
             const int64_t d = uniform_i64(p.g.rowptr[v + 1]) - beg;
+            // first-order steps: the draw's Philox word while the row offsets load
+            uint64_t u = 0;
+            if constexpr (!kN2v) u = philox_vec(key, c0, (uint32_t)s, (uint32_t)v, 0u);
             if (d == 0) break;
             int64_t m = -1;  // position of the pick (paths that return the neighbor itself leave -1)
             int32_t nx = -1;
@@ -681,11 +697,12 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
                     const uint32_t* wts = dg ? p.g.degw : p.g.ew;
                     const uint64_t* gt = dg ? p.g.gtab_deg : p.g.gtab_ew;
                     const uint64_t* ct = dg ? p.g.ctab_deg : p.g.ctab_ew;
-                    if (d <= kWaveMaxD) {
-                        nx = walk_step_short(wts, p.g.col, reinterpret_cast<uint32_t*>(lds.tab), key, c0, s, v, beg,
-                                             (int32_t)d, stop);
-                    } else if (gt && ct) {
-                        nx = walk_step_long(wts, p.g.col, gt, ct, key, c0, s, v, beg, d, stop);
+                    if (d <= kWaveMaxD || (gt && ct)) {
+                        if (d <= kWaveMaxD)
+                            nx = walk_step_short(wts, p.g.col, reinterpret_cast<uint32_t*>(lds.tab), u, beg, (int32_t)d,
+                                                 stop);
+                        else
+                            nx = walk_step_long(wts, p.g.col, gt, ct, u, beg, d, stop);
                     } else {
                         m = walk_step_biased<false>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
                     }
