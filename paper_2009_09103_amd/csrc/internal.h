@@ -60,8 +60,8 @@ csaw_status walk_batch_in_scratch(csaw_graph g, const csaw_walk_args* common, co
                                   int32_t nreq, const int32_t* d_starts, int32_t* d_paths, char* d_tables,
                                   int64_t* steps, hipStream_t stream);
 
-// Builds the tables of a bias kind now, if they do not exist yet (their
-// first use otherwise builds them).
+// Builds the tables of a bias kind now, with its walk guide tables, if they
+// do not exist yet (their first use otherwise builds them).
 csaw_status prepare_bias_tables(csaw_graph g, int32_t bias_kind, hipStream_t stream);
 
 }  // namespace csaw

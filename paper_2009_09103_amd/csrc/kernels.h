@@ -51,6 +51,14 @@ struct GraphDev {
     // (b >> 9) + j holds the total of chunks 0..j (null on partitioned graphs)
     const uint64_t* ctab_ew;
     const uint64_t* ctab_deg;
+    // walk guide tables of the lists longer than kWaveMaxD (null until the
+    // first weighted walk of the weight array): wpre[e] = inclusive prefix of
+    // edge e in its list; wgd[(b >> 4) + k] = first position i of the list
+    // starting at edge b with S_(i+1) > k * 2^s, for its guide_buckets()
+    const uint64_t* wpre_ew;
+    const uint64_t* wpre_deg;
+    const uint32_t* wgd_ew;
+    const uint32_t* wgd_deg;
 };
 
 constexpr int kWaveMaxD = 512;   // longest weighted list of the wavefront kernels
@@ -234,6 +242,23 @@ struct WalkParams {
     WalkBatch batch;                 // batch.req null: a single request
 };
 void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev = {});
+// The walk guide tables of weight array w (list totals wtot): pre[m], gd[(m >> 4) + 1].
+void launch_walk_guides(RowPtr rowptr, const uint32_t* w, const uint64_t* wtot, int64_t n, uint64_t* pre,
+                        uint32_t* gd, hipStream_t s);
+
+// Buckets of a list's walk guide: width 2^s, K = ((W - 1) >> s) + 1 of them,
+// s the smallest shift that keeps K within the list's d / 16 table entries
+// (d > kWaveMaxD, W > 0). Shared by the table builder and the walk step.
+__host__ __device__ __forceinline__ int guide_shift(uint64_t W, int64_t d) {
+    const uint64_t kmax = (uint64_t)(d >> 4), top = W - 1;
+    if (top < kmax) return 0;
+    // bit lengths: top >> s < kmax needs s >= len(top) - len(kmax), and at
+    // most one more
+    int s = (64 - __builtin_clzll(top)) - (64 - __builtin_clzll(kmax));
+    if (s < 0) s = 0;
+    while ((top >> s) >= kmax) ++s;
+    return s;
+}
 // Sets *flag to 1 if some edge (u, x) has no reverse edge (x, u); lists must
 // be sorted (each reverse edge is found by binary search).
 void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_t* flag, hipStream_t s);

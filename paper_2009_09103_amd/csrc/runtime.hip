@@ -229,6 +229,10 @@ struct csaw_graph_s {
     uint64_t* wtot_deg = nullptr;
     uint64_t* ctab_ew = nullptr;   // running chunk totals of the long lists
     uint64_t* ctab_deg = nullptr;
+    uint64_t* wpre_ew = nullptr;   // walk guides: per-edge prefixes and bucket brackets
+    uint64_t* wpre_deg = nullptr;
+    uint32_t* wgd_ew = nullptr;
+    uint32_t* wgd_deg = nullptr;
     std::mutex mu;                       // lazy preparation + workspace pool
     std::vector<Workspace*> pool;
     std::atomic<int32_t> bound16{kDefaultBound16}, bound32{kDefaultBound32};  // sub-wave buckets
@@ -249,6 +253,10 @@ struct csaw_graph_s {
         g.wtot_deg = wtot_deg;
         g.ctab_ew = ctab_ew;
         g.ctab_deg = ctab_deg;
+        g.wpre_ew = wpre_ew;
+        g.wpre_deg = wpre_deg;
+        g.wgd_ew = wgd_ew;
+        g.wgd_deg = wgd_deg;
         return g;
     }
 };
@@ -376,6 +384,36 @@ csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
         }
         g->ppos_deg = pp;
     }
+    return CSAW_OK;
+}
+
+// The walk guide tables of a weight array whose bias tables exist (per-edge
+// prefixes, 8 bytes per edge, and bucket brackets, a quarter byte per edge),
+// built once; a graph without them walks through the chunk tables.
+csaw_status prepare_walk_guides(csaw_graph g, int32_t kind, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    const bool dg = kind == kNeighborDegree;
+    if (kind != kEdgeWeight && !dg) return CSAW_OK;
+    if ((dg ? g->wgd_deg : g->wgd_ew) || g->m <= 0) return CSAW_OK;
+    const uint32_t* w = dg ? g->degw : g->ew;
+    const uint64_t* tot = dg ? g->wtot_deg : g->wtot_ew;
+    if (!w || !tot || !(dg ? g->ppos_deg : g->ppos_ew)) return CSAW_OK;
+    uint64_t* pre = nullptr;
+    uint32_t* gd = nullptr;
+    if (hipMalloc((void**)&pre, (size_t)g->m * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void**)&gd, (size_t)((g->m >> 4) + 1) * sizeof(uint32_t)) != hipSuccess) {
+        if (pre) (void)hipFree(pre);
+        return fail(CSAW_ERR_OUT_OF_MEMORY, "walk guide tables: allocation failed");
+    }
+    launch_walk_guides(g->rowptr, w, tot, g->n, pre, gd, s);
+    const hipError_t e = hipGetLastError() != hipSuccess ? hipErrorLaunchFailure : hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(pre);
+        (void)hipFree(gd);
+        return fail(CSAW_ERR_DEVICE, "building the walk guide tables: %s", hipGetErrorString(e));
+    }
+    (dg ? g->wpre_deg : g->wpre_ew) = pre;
+    (dg ? g->wgd_deg : g->wgd_ew) = gd;
     return CSAW_OK;
 }
 
@@ -658,6 +696,8 @@ csaw_status csaw_graph_destroy(csaw_graph g) {
     if (g->wtot_deg) (void)hipFree(g->wtot_deg);
     if (g->ctab_ew) (void)hipFree(g->ctab_ew);
     if (g->ctab_deg) (void)hipFree(g->ctab_deg);
+    for (void* q : {(void*)g->wpre_ew, (void*)g->wpre_deg, (void*)g->wgd_ew, (void*)g->wgd_deg})
+        if (q) (void)hipFree(q);
     delete g;
     return CSAW_OK;
 }
@@ -967,7 +1007,8 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
             for (const void* q : {gd.rowptr.data(), (const void*)gd.col, (const void*)gd.ew, (const void*)gd.degw,
                                   (const void*)gd.ppos_ew, (const void*)gd.ppos_deg, (const void*)gd.gtab_ew,
                                   (const void*)gd.gtab_deg, (const void*)gd.wtot_ew, (const void*)gd.wtot_deg,
-                                  (const void*)gd.ctab_ew, (const void*)gd.ctab_deg})
+                                  (const void*)gd.ctab_ew, (const void*)gd.ctab_deg, (const void*)gd.wpre_ew,
+                                  (const void*)gd.wpre_deg, (const void*)gd.wgd_ew, (const void*)gd.wgd_deg})
                 key.push_back((int64_t)(intptr_t)q);
             key.push_back((int64_t)P.uses_deg);
             key.push_back((int64_t)P.uses_ew);
@@ -1463,7 +1504,8 @@ static csaw_status walk_prepare(csaw_graph g, const csaw_walk_args* a, hipStream
             if (!(a->bias_kind == kNeighborDegree ? g->ppos_deg : g->ppos_ew))
                 return fail(CSAW_ERR_NOT_READY, "the tables of this bias kind are not built yet");
         } else {
-            const csaw_status st = prepare_bias(g, a->bias_kind, s);
+            csaw_status st = prepare_bias(g, a->bias_kind, s);
+            if (st == CSAW_OK) st = prepare_walk_guides(g, a->bias_kind, s);
             if (st != CSAW_OK) return st;
         }
     }
@@ -1805,7 +1847,8 @@ csaw_status prepare_bias_tables(csaw_graph g, int32_t kind, hipStream_t stream) 
     if (kind == kEdgeWeight && !g->ew) return fail(CSAW_ERR_INVALID_ARG, "EDGE_WEIGHT bias without edge weights");
     if (kind != kEdgeWeight && kind != kNeighborDegree) return CSAW_OK;
     HIP_OR_FAIL(hipSetDevice(g->device));
-    return prepare_bias(g, kind, stream);
+    const csaw_status st = prepare_bias(g, kind, stream);
+    return st != CSAW_OK ? st : prepare_walk_guides(g, kind, stream);
 }
 
 }  // namespace csaw

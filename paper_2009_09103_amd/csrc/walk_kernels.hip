@@ -41,6 +41,28 @@ __device__ __forceinline__ bool walk_move(const WalkParams& p, Key key, uint32_t
     return false;
 }
 
+// A wave-uniform read through the scalar data cache (constant address space):
+// such reads issue back to back and are waited for together, where vector
+// loads of one value each were waited for one at a time.
+template <class T>
+__device__ __forceinline__ T ld_uniform(const T* p) {
+    typedef const __attribute__((address_space(4))) T ConstT;
+    return *(ConstT*)p;
+}
+
+// v's list [beg, beg + d) with both row offsets read at once (v wave-uniform)
+__device__ __forceinline__ void row_uniform(const RowPtr& rp, int64_t v, int64_t& beg, int64_t& d) {
+    if (rp.p32) {
+        const uint32_t a = ld_uniform(rp.p32 + v), b = ld_uniform(rp.p32 + v + 1);
+        beg = a;
+        d = (int64_t)b - (int64_t)a;
+    } else {
+        const int64_t a = ld_uniform(rp.p64 + v), b = ld_uniform(rp.p64 + v + 1);
+        beg = a;
+        d = b - a;
+    }
+}
+
 // Walker w's Philox key, length, walker id (counter word 0), path row and
 // step counter: from the call, or from its request's entries in a batch.
 struct WalkerCtx {
@@ -636,11 +658,49 @@ __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w
     const uint64_t before = acc + (gi > 0 ? readlane_u64(gp, gi - 1) : 0ull);
     const int64_t i0 = j * kChunk + (int64_t)gi * 16;
     const bool in = lane < 16 && i0 + lane < d;
-    const uint64_t x = in ? (uint64_t)w[beg + i0 + lane] : 0ull;
-    const int32_t y = in ? col[beg + i0 + lane] : 0;
+    // the group's weights and ids at clamped positions, lanes past it zeroed
+    const int64_t ii = beg + (in ? i0 + lane : i0);
+    uint64_t x = (uint64_t)w[ii];
+    const int32_t y = col[ii];
+    x = in ? x : 0ull;
     const uint64_t incl = wave_incl_scan_u64(x);
     const int k = __popcll(ballot(in && before + incl <= r));
     return readlane_i32(y, k);
+}
+
+// First-order weighted step on a list longer than kWaveMaxD through its walk
+// guide: r is drawn in [0, W) (W, the list's total, came with the row
+// offsets), its bucket k = r >> s gives the bracket [G[k], G[k+1]] that holds
+// the pick (every position before G[k] ends at or below k * 2^s <= r, and
+// G[k+1] ends past (k+1) * 2^s > r), and one load of the bracket's exact
+// prefixes and neighbor ids finds m = #{i : S_(i+1) <= r} by ballot. Three
+// dependent loads per step (row offsets and W, the bracket, its prefixes).
+// Returns the neighbor, or -2 when the bracket is wider than a wavefront (many
+// small weights in one bucket), which the caller takes through the chunk
+// tables.
+__device__ __forceinline__ int32_t walk_step_guide(const uint64_t* __restrict__ pre, const uint32_t* __restrict__ gd,
+                                                   const int32_t* __restrict__ col, uint64_t r, uint64_t W,
+                                                   int64_t beg, int64_t d) {
+    const int lane = lane_id();
+    const int sh = guide_shift(W, d);
+    const uint64_t K = ((W - 1) >> sh) + 1;
+    const uint64_t k = r >> sh;
+    const uint32_t* G = gd + (beg >> 4);
+    const uint32_t g0 = ld_uniform(G + k), g1 = ld_uniform(G + (k + 1 < K ? k + 1 : k));
+    const int64_t lo = g0;
+    const int64_t hi = k + 1 < K ? (int64_t)g1 : d - 1;
+    const int64_t n = hi - lo + 1;
+    if (n > kWave) return -2;
+    // both loads issued at clamped positions, then the lanes past the
+    // bracket masked: guarded loads were waited for one after the other
+    const bool in = lane < n;
+    const int64_t j = beg + lo + (in ? lane : n - 1);
+    uint64_t S = pre[j];
+    const int32_t y = col[j];
+    __builtin_amdgcn_sched_barrier(0);  // both loads in flight before either is used
+    S = in ? S : ~0ull;
+    const int c = __popcll(ballot(S <= r));
+    return readlane_i32(y, c);
 }
 
 template <bool kN2v, bool kMoves>
@@ -677,11 +737,17 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
                 tb = te = 0;
                 continue;
             }
-            const int64_t beg = uniform_i64(p.g.rowptr[v]);
-            const int64_t d = uniform_i64(p.g.rowptr[v + 1]) - beg;
-            // first-order steps: the draw's Philox word while the row offsets load
-            uint64_t u = 0;
-            if constexpr (!kN2v) u = philox_vec(key, c0, (uint32_t)s, (uint32_t)v, 0u);
+            int64_t beg, d;
+            row_uniform(p.g.rowptr, v, beg, d);
+            // first-order steps: the list's total (for the walk guide) with the
+            // row offsets, and the draw's Philox word while they load
+            uint64_t u = 0, wt = 0;
+            if constexpr (!kN2v) {
+                const bool dg = p.bias == kNeighborDegree;
+                const uint64_t* tots = dg ? p.g.wtot_deg : p.g.wtot_ew;
+                if ((dg ? p.g.wgd_deg : p.g.wgd_ew) != nullptr) wt = ld_uniform(tots + v);
+                u = philox_vec(key, c0, (uint32_t)s, (uint32_t)v, 0u);
+            }
             if (d == 0) break;
             int64_t m = -1;  // position of the pick (paths that return the neighbor itself leave -1)
             int32_t nx = -1;
@@ -697,19 +763,27 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
                     const uint32_t* wts = dg ? p.g.degw : p.g.ew;
                     const uint64_t* gt = dg ? p.g.gtab_deg : p.g.gtab_ew;
                     const uint64_t* ct = dg ? p.g.ctab_deg : p.g.ctab_ew;
+                    const uint64_t* pre = dg ? p.g.wpre_deg : p.g.wpre_ew;
+                    const uint32_t* gd = dg ? p.g.wgd_deg : p.g.wgd_ew;
                     if (d <= kWaveMaxD || (gt && ct)) {
-                        if (d <= kWaveMaxD)
+                        if (d <= kWaveMaxD) {
                             nx = walk_step_short(wts, p.g.col, reinterpret_cast<uint32_t*>(lds.tab), u, beg, (int32_t)d,
                                                  stop);
-                        else
-                            nx = walk_step_long(wts, p.g.col, gt, ct, u, beg, d, stop);
+                        } else {
+                            nx = -2;
+                            if (gd) {
+                                stop = wt == 0;
+                                if (!stop) nx = walk_step_guide(pre, gd, p.g.col, range_reduce(u, wt), wt, beg, d);
+                            }
+                            if (nx == -2 && !stop) nx = walk_step_long(wts, p.g.col, gt, ct, u, beg, d, stop);
+                        }
                     } else {
                         m = walk_step_biased<false>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
                     }
                 }
                 if (stop) break;
             }
-            if (m >= 0) nx = uniform_i32(p.g.col[beg + m]);
+            if (m >= 0) nx = ld_uniform(p.g.col + beg + m);
             nx = uniform_i32(nx);
             if (lane == 0) path[s + 1] = nx;
             t = v;
@@ -755,7 +829,51 @@ __global__ void __launch_bounds__(kBlock) k_symmetric_check(RowPtr rowptr, const
     }
 }
 
+// Walk guide tables, one wavefront per list longer than kWaveMaxD: the
+// inclusive prefix of every edge (64 at a time, one scan each, carried), and
+// for each bucket k < K of the list's guide, the position i whose interval
+// [S_i, S_(i+1)) holds k * 2^s (each position writes the buckets it covers).
+__global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const uint32_t* __restrict__ w,
+                                                        const uint64_t* __restrict__ wtot, int64_t n,
+                                                        uint64_t* __restrict__ pre, uint32_t* __restrict__ gd) {
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t v = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; v < n; v += waves) {
+        const int64_t b = rowptr[v], d = rowptr[v + 1] - b;
+        const uint64_t W = wtot[v];
+        if (d <= kWaveMaxD || W == 0) continue;
+        const int sh = guide_shift(W, d);
+        const uint64_t K = ((W - 1) >> sh) + 1;
+        const uint64_t low = (uint64_t(1) << sh) - 1;
+        uint32_t* G = gd + (b >> 4);
+        uint64_t run = 0;
+        for (int64_t base = 0; base < d; base += kWave) {
+            const int64_t i = base + lane;
+            const uint64_t x = i < d ? (uint64_t)w[b + i] : 0ull;
+            const uint64_t incl = run + wave_incl_scan_u64(x);
+            const uint64_t excl = incl - x;
+            if (i < d) {
+                pre[b + i] = incl;
+                // buckets k with excl <= k * 2^s < incl: k from ceil(excl / 2^s) to ceil(incl / 2^s) - 1
+                const uint64_t k0 = (excl >> sh) + ((excl & low) != 0);
+                uint64_t k1 = (incl >> sh) + ((incl & low) != 0);
+                k1 = k1 < K ? k1 : K;
+                for (uint64_t k = k0; k < k1; ++k) G[k] = (uint32_t)i;
+            }
+            run = readlane_u64(incl, kWave - 1);
+        }
+    }
+}
+
 }  // namespace
+
+void launch_walk_guides(RowPtr rowptr, const uint32_t* w, const uint64_t* wtot, int64_t n, uint64_t* pre,
+                        uint32_t* gd, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t g = (n + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_walk_guides, dim3((unsigned)g), dim3(kBlock), 0, s, rowptr, w, wtot, n, pre, gd);
+}
 
 void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_t* flag, hipStream_t s) {
     if (n <= 0) return;

@@ -327,6 +327,25 @@ void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_
     });
 }
 
+void launch_walk_guides(RowPtr rowptr, const uint32_t* w, const uint64_t* wtot, int64_t n, uint64_t* pre,
+                        uint32_t* gd, hipStream_t s) {
+    hipsim::enqueue(s, [=] {
+        for (int64_t v = 0; v < n; ++v) {
+            const int64_t b = rowptr[v], d = rowptr[v + 1] - b;
+            const uint64_t W = wtot[v];
+            if (d <= kWaveMaxD || W == 0) continue;
+            const int sh = guide_shift(W, d);
+            const uint64_t K = ((W - 1) >> sh) + 1;
+            uint64_t run = 0, k = 0;
+            for (int64_t i = 0; i < d; ++i) {
+                run += w[b + i];
+                pre[b + i] = run;
+                for (; k < K && (k << sh) < run; ++k) gd[(b >> 4) + k] = (uint32_t)i;
+            }
+        }
+    });
+}
+
 void launch_layer_sample(const LayerParams& p, hipStream_t s, LaunchEvents) {
     hipsim::enqueue(s, [p] {
         for (int64_t i = 0; i < (int64_t)p.num_instances * p.L; ++i) p.counts[i] = 0;

@@ -69,6 +69,27 @@ def test_weighted_walk_long_lists(csaw, wide):
     run_both(csaw, g, rp, col, ew, starts, 12, 2, 18)
 
 
+def test_weighted_walk_guide_brackets(csaw):
+    """Long lists walk through their guide: a hub of 10,050 neighbors where
+    every 201st weight is 10^5 and the others 100, so a bucket (2^14 wide here)
+    inside a heavy weight brackets one or two positions, while one inside a
+    run of light weights brackets more than a wavefront and the step goes
+    through the chunk tables instead; both routes against the oracle, also
+    with the degree bias and from other start vertices."""
+    n = 10_051
+    hub = 0
+    edges = [(hub, i) for i in range(1, n)] + [(i, hub) for i in range(1, n)]
+    edges += [(i, i % (n - 1) + 1) for i in range(1, n, 3)]
+    rp, col = inputs.csr_from_edges(n, edges)
+    ew = np.full(len(col), 100, dtype=np.uint32)
+    b = int(rp[hub])
+    ew[b:b + n - 1:201] = 100_000
+    g = csaw.Graph(rp, col, ew)
+    starts = np.concatenate([np.zeros(4000, dtype=np.int32), inputs.walker_starts(rp, col, 500, 9)])
+    run_both(csaw, g, rp, col, ew, starts, 10, 1, 41, walker_base=3)
+    run_both(csaw, g, rp, col, ew, starts, 10, 2, 42)
+
+
 @pytest.mark.parametrize("weights", [(1, 2, 4), (4, 1, 2), (0, 1, 3), (3, 3, 3)])
 def test_node2vec(csaw, weights):
     rp, col = inputs.rmat_csr(14, 8 << 14, 22, symmetrize=True)
