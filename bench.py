@@ -422,22 +422,19 @@ def batched_split(g, offs, seeds, fanouts, bias, args, edges):
 
 def walk_step_bytes(rowptr, paths):
     """Algorithmic bytes of first-order weighted walk steps, per step from v
-    with d = deg(v): 8 (row-offset pair) + 4 (neighbor id at the pick) + 4
-    (path entry), plus the biases the selection needs: for d <= 512, the d
-    weights of N(v) (4 d); for longer lists, read through the graph's
-    per-list tables, the running chunk totals the search visits (8 per
-    1,024-weight chunk up to 64 chunks; longer lists 64 evenly spaced totals
-    and then at most 64 of one range), one chunk's 64 group prefixes (512)
-    and one 16-weight group (64). The neighbor ids the kernel loads beside
-    the weights (to save a dependent load) are not counted."""
+    with d = deg(v): 8 (the two 32-bit row offsets) + 4 (the pick's neighbor
+    id) + 4 (the path entry), plus what the selection reads: for d <= 512
+    the d weights of N(v) (4 d); for longer lists the walk guide's route,
+    counted at its minimum: the list's total (8), the two bracket bounds (8)
+    and one exact prefix (8). A bracket holds one position or a few (more
+    only in runs of small weights, where the draw rarely lands), so this is a
+    lower bound on the bytes the route needs."""
     deg = np.diff(rowptr)
     cur, nxt = paths[:, :-1], paths[:, 1:]
     taken = nxt >= 0
     d = deg[cur[taken]].astype(np.float64)
     long_ = d > WAVE_MAX_D
-    nch = np.ceil(d / 1024.0)
-    totals = 8.0 * np.minimum(nch, 64.0) + np.where(nch > 64.0, 8.0 * np.minimum(np.ceil(nch / 64.0), 64.0), 0.0)
-    sel = np.where(long_, totals + 512.0 + 64.0, 4.0 * d)
+    sel = np.where(long_, 24.0, 4.0 * d)
     return 16.0 * taken.sum() + sel.sum(), int(taken.sum())
 
 
@@ -601,7 +598,10 @@ def bench_served(args):
                      "kernel": "walk (k_walk_wave_first, edge-weight walks)", "launches": kernels["walk"]["launches"],
                      "avg_launch_us": walk_ms * 1e3 / max(kernels["walk"]["launches"], 1),
                      "alg_bytes_per_launch": wbytes / max(kernels["walk"]["launches"], 1),
-                     "steps": wsteps},
+                     "steps": wsteps,
+                     # the walk step is a chain of dependent loads: its rate is
+                     # bound by wavefront slots over the chain's latency, not HBM
+                     "steps_per_s": wsteps / (walk_ms * 1e-3) if walk_ms > 0 else 0.0},
         "kernels_ms": {k: v["ms"] for k, v in kernels.items()},
     }
     if not args.no_cpu_baseline:

@@ -145,6 +145,32 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A wave-uniform read through the scalar data cache (constant address space):
+// such reads issue back to back and are waited for together, where vector
+// loads of one value each, made uniform with readfirstlane, were waited for
+// one at a time. Only for data no kernel of the same launch writes.
+template <class T>
+__device__ __forceinline__ T ld_uniform(const T* p) {
+    typedef const __attribute__((address_space(4))) T ConstT;
+    return *(ConstT*)p;
+}
+
+// v's list [beg, beg + d) of a CSR row-offset view (32-bit words p32 or
+// 64-bit p64, one of them set) with both offsets read at once through the
+// scalar data cache (v wave-uniform)
+template <class Rows>
+__device__ __forceinline__ void row_uniform(const Rows& rp, int64_t v, int64_t& beg, int64_t& d) {
+    if (rp.p32) {
+        const uint32_t a = ld_uniform(rp.p32 + v), b = ld_uniform(rp.p32 + v + 1);
+        beg = a;
+        d = (int64_t)b - (int64_t)a;
+    } else {
+        const int64_t a = ld_uniform(rp.p64 + v), b = ld_uniform(rp.p64 + v + 1);
+        beg = a;
+        d = b - a;
+    }
+}
+
 // wave-uniform value (forces an SGPR)
 __device__ __forceinline__ int32_t uniform_i32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ int64_t uniform_i64(int64_t x) {

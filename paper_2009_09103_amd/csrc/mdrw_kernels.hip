@@ -71,9 +71,10 @@ __global__ void __launch_bounds__(kWave) k_mdrw(MdrwParams p) {
             const uint32_t d = (uint32_t)uniform_i32((int32_t)pd[j]);
             const int64_t beg = uniform_i64(pb[j]);
             const uint64_t m = draw(key, iid, (uint32_t)s, (uint32_t)v, 1u, (uint64_t)d);
-            const int32_t u = uniform_i32(p.g.col[beg + (int64_t)m]);
-            const int64_t ub = uniform_i64(p.g.rowptr[u]);
-            const uint32_t ud = (uint32_t)(uniform_i64(p.g.rowptr[u + 1]) - ub);
+            const int32_t u = ld_uniform(p.g.col + beg + (int64_t)m);
+            int64_t ub, udl;
+            row_uniform(p.g.rowptr, u, ub, udl);
+            const uint32_t ud = (uint32_t)udl;
             wave_lds_sync();
             if (lane == 0) {
                 pv[j] = u;

@@ -41,28 +41,6 @@ __device__ __forceinline__ bool walk_move(const WalkParams& p, Key key, uint32_t
     return false;
 }
 
-// A wave-uniform read through the scalar data cache (constant address space):
-// such reads issue back to back and are waited for together, where vector
-// loads of one value each were waited for one at a time.
-template <class T>
-__device__ __forceinline__ T ld_uniform(const T* p) {
-    typedef const __attribute__((address_space(4))) T ConstT;
-    return *(ConstT*)p;
-}
-
-// v's list [beg, beg + d) with both row offsets read at once (v wave-uniform)
-__device__ __forceinline__ void row_uniform(const RowPtr& rp, int64_t v, int64_t& beg, int64_t& d) {
-    if (rp.p32) {
-        const uint32_t a = ld_uniform(rp.p32 + v), b = ld_uniform(rp.p32 + v + 1);
-        beg = a;
-        d = (int64_t)b - (int64_t)a;
-    } else {
-        const int64_t a = ld_uniform(rp.p64 + v), b = ld_uniform(rp.p64 + v + 1);
-        beg = a;
-        d = b - a;
-    }
-}
-
 // Walker w's Philox key, length, walker id (counter word 0), path row and
 // step counter: from the call, or from its request's entries in a batch.
 struct WalkerCtx {
