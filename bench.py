@@ -423,18 +423,17 @@ def batched_split(g, offs, seeds, fanouts, bias, args, edges):
 def walk_step_bytes(rowptr, paths):
     """Algorithmic bytes of first-order weighted walk steps, per step from v
     with d = deg(v): 8 (the two 32-bit row offsets) + 4 (the pick's neighbor
-    id) + 4 (the path entry), plus what the selection reads: for d <= 512
-    the d weights of N(v) (4 d); for longer lists the walk guide's route,
-    counted at its minimum: the list's total (8), the two bracket bounds (8)
-    and one exact prefix (8). A bracket holds one position or a few (more
-    only in runs of small weights, where the draw rarely lands), so this is a
-    lower bound on the bytes the route needs."""
+    id) + 4 (the path entry), plus what the selection reads at least: through
+    the walk guide, the list's total (8), the two bracket bounds (8) and one
+    exact prefix (8); a list of at most 512 weights may instead be read whole
+    (4 d), which a wavefront per walker does, so the smaller of the two is
+    counted. A bracket holds one position or a few, so this is a lower bound
+    on the bytes any route needs."""
     deg = np.diff(rowptr)
     cur, nxt = paths[:, :-1], paths[:, 1:]
     taken = nxt >= 0
     d = deg[cur[taken]].astype(np.float64)
-    long_ = d > WAVE_MAX_D
-    sel = np.where(long_, 24.0, 4.0 * d)
+    sel = np.where(d <= WAVE_MAX_D, np.minimum(4.0 * d, 24.0), 24.0)
     return 16.0 * taken.sum() + sel.sum(), int(taken.sum())
 
 

@@ -306,6 +306,26 @@ typedef struct {
 csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* args, int32_t* paths,
                       int64_t* total_steps, csaw_stream stream);
 
+/* Walk guide (weighted first-order walks, EDGE_WEIGHT and NEIGHBOR_DEGREE;
+ * the inverse transform selection of Section II-B, Eq. equ:tp, served in
+ * a constant expected number of loads). On a weight
+ * array's first walk the graph builds, once: the exact inclusive prefix of
+ * every edge in its list (8 bytes per edge), and per list of total W and
+ * degree d a table of K <= 2 d equal buckets of width 2^s over [0, W), each
+ * holding the first position whose interval reaches its start (4 bytes per
+ * bucket, 2 m + n entries). A step's draw r then lies between the positions
+ * of buckets r >> s and (r >> s) + 1, and one lane per walker finds
+ * m = #{i : S_(i+1) <= r} from a few exact prefixes: the same pick as a
+ * search of the whole prefix. About 16 bytes per edge per weight array
+ * (17 GB for 2^30 edges); with the guide off (or not yet built in a caller
+ * memory call) walks take the chunk tables with one wavefront per walker,
+ * with the same paths.
+ * enable: 1 (default) or 0. A walk already running keeps its route. INVALID_ARG
+ * otherwise. Turning the guide off does not free built tables. */
+csaw_status csaw_set_walk_guides(csaw_graph g, int32_t enable);
+/* HOST out: enable. */
+csaw_status csaw_get_walk_guides(csaw_graph g, int32_t* enable);
+
 /* ------------------------------------------- multi-dimensional random walk */
 
 /* Multi-dimensional random walk, a.k.a. frontier sampling (Section II-A;

@@ -106,7 +106,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["csaw_graph_create", "csaw_graph_destroy", "csaw_graph_info", "csaw_sample", "csaw_sample_noalloc",
-           "csaw_sample_bound", "csaw_set_tuning", "csaw_get_tuning", "csaw_autotune_sample", "csaw_walk",
+           "csaw_sample_bound", "csaw_set_tuning", "csaw_get_tuning", "csaw_set_walk_guides", "csaw_get_walk_guides", "csaw_autotune_sample", "csaw_walk",
            "csaw_mdrw", "csaw_layer_sample", "csaw_set_allocator", "csaw_profile_enable", "csaw_profile_reset", "csaw_profile_read", "csaw_last_error", "csaw_version", "csaw_server_create",
            "csaw_server_submit", "csaw_server_poll", "csaw_server_wait", "csaw_server_cancel",
            "csaw_server_memory", "csaw_result_free", "csaw_server_destroy", "csaw_pgraph_create",
@@ -126,6 +126,8 @@ def _load():
     L.csaw_sample_bound.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(ctypes.c_int64)]
     L.csaw_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.csaw_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.csaw_set_walk_guides.argtypes = [vp, i32]
+    L.csaw_get_walk_guides.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.csaw_autotune_sample.argtypes = [vp, ctypes.POINTER(SampleArgs), ctypes.POINTER(SampleOut), i32, vp,
                                        ctypes.POINTER(Tuning)]
     L.csaw_walk.argtypes = [vp, ctypes.POINTER(WalkArgs), vp, ctypes.POINTER(ctypes.c_int64), vp]
@@ -348,6 +350,16 @@ class Graph:
         t = Tuning()
         _check(lib.csaw_get_tuning(self._h, ctypes.byref(t)))
         return t.bound16, t.bound32
+
+    def set_walk_guides(self, enable: bool):
+        """Weighted walks through the walk guide (True, the default) or the
+        chunk tables (csaw_set_walk_guides)."""
+        _check(lib.csaw_set_walk_guides(self._h, 1 if enable else 0))
+
+    def get_walk_guides(self) -> bool:
+        e = ctypes.c_int32()
+        _check(lib.csaw_get_walk_guides(self._h, ctypes.byref(e)))
+        return bool(e.value)
 
     def _run_sample(self, call, seed_offsets, seeds, fanouts, bias, rng_seed, instance_base, capacity, out,
                     instance_ids, rng_seeds, rounds=0, burn=0) -> SampleResult:

@@ -51,10 +51,11 @@ struct GraphDev {
     // (b >> 9) + j holds the total of chunks 0..j (null on partitioned graphs)
     const uint64_t* ctab_ew;
     const uint64_t* ctab_deg;
-    // walk guide tables of the lists longer than kWaveMaxD (null until the
+    // walk guide tables of every list with a positive total (null until the
     // first weighted walk of the weight array): wpre[e] = inclusive prefix of
-    // edge e in its list; wgd[(b >> 4) + k] = first position i of the list
-    // starting at edge b with S_(i+1) > k * 2^s, for its guide_buckets()
+    // edge e in its list; the list v starting at edge b owns the bracket
+    // entries wgd[2 b + v + k], k < K (at most 2 d of its 2 d + 1 slots; K
+    // and s from guide_shift): the first position i with S_(i+1) > k * 2^s
     const uint64_t* wpre_ew;
     const uint64_t* wpre_deg;
     const uint32_t* wgd_ew;
@@ -242,15 +243,20 @@ struct WalkParams {
     WalkBatch batch;                 // batch.req null: a single request
 };
 void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev = {});
-// The walk guide tables of weight array w (list totals wtot): pre[m], gd[(m >> 4) + 1].
+// The walk guide tables of weight array w (list totals wtot): pre[m],
+// gd[2 m + n].
 void launch_walk_guides(RowPtr rowptr, const uint32_t* w, const uint64_t* wtot, int64_t n, uint64_t* pre,
                         uint32_t* gd, hipStream_t s);
+constexpr int kGuideBucketsPerEdge = 2;  // a list of d edges gets at most 2 d buckets
 
 // Buckets of a list's walk guide: width 2^s, K = ((W - 1) >> s) + 1 of them,
-// s the smallest shift that keeps K within the list's d / 16 table entries
-// (d > kWaveMaxD, W > 0). Shared by the table builder and the walk step.
+// s the smallest shift that keeps K within kGuideBucketsPerEdge * d (d >= 1,
+// W > 0). A draw r lies in bucket r >> s, whose entry and the next one's
+// bracket the positions that can hold it; with buckets no wider than the
+// list's mean weight a bracket holds about two positions on average
+// whatever the weights are. Shared by the table builder and the walk steps.
 __host__ __device__ __forceinline__ int guide_shift(uint64_t W, int64_t d) {
-    const uint64_t kmax = (uint64_t)(d >> 4), top = W - 1;
+    const uint64_t kmax = (uint64_t)d * kGuideBucketsPerEdge, top = W - 1;
     if (top < kmax) return 0;
     // bit lengths: top >> s < kmax needs s >= len(top) - len(kmax), and at
     // most one more
@@ -259,6 +265,8 @@ __host__ __device__ __forceinline__ int guide_shift(uint64_t W, int64_t d) {
     while ((top >> s) >= kmax) ++s;
     return s;
 }
+// Entry 0 of list v's guide (first edge b).
+__host__ __device__ __forceinline__ int64_t guide_base(int64_t b, int64_t v) { return kGuideBucketsPerEdge * b + v; }
 // Sets *flag to 1 if some edge (u, x) has no reverse edge (x, u); lists must
 // be sorted (each reverse edge is found by binary search).
 void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_t* flag, hipStream_t s);

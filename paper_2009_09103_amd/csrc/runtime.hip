@@ -236,6 +236,7 @@ struct csaw_graph_s {
     std::mutex mu;                       // lazy preparation + workspace pool
     std::vector<Workspace*> pool;
     std::atomic<int32_t> bound16{kDefaultBound16}, bound32{kDefaultBound32};  // sub-wave buckets
+    std::atomic<int32_t> walk_guides{1};  // weighted walks build and use the walk guides
 
     GraphDev dev() const {
         GraphDev g;
@@ -401,7 +402,7 @@ csaw_status prepare_walk_guides(csaw_graph g, int32_t kind, hipStream_t s) {
     uint64_t* pre = nullptr;
     uint32_t* gd = nullptr;
     if (hipMalloc((void**)&pre, (size_t)g->m * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc((void**)&gd, (size_t)((g->m >> 4) + 1) * sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc((void**)&gd, (size_t)(kGuideBucketsPerEdge * g->m + g->n) * sizeof(uint32_t)) != hipSuccess) {
         if (pre) (void)hipFree(pre);
         return fail(CSAW_ERR_OUT_OF_MEMORY, "walk guide tables: allocation failed");
     }
@@ -1425,6 +1426,21 @@ csaw_status csaw_set_tuning(csaw_graph g, const csaw_tuning* t) {
     return CSAW_OK;
 }
 
+csaw_status csaw_set_walk_guides(csaw_graph g, int32_t enable) {
+    t_err.clear();
+    if (!g) return fail(CSAW_ERR_INVALID_ARG, "graph is NULL");
+    if (enable != 0 && enable != 1) return fail(CSAW_ERR_INVALID_ARG, "enable must be 0 or 1");
+    g->walk_guides.store(enable);
+    return CSAW_OK;
+}
+
+csaw_status csaw_get_walk_guides(csaw_graph g, int32_t* enable) {
+    t_err.clear();
+    if (!g || !enable) return fail(CSAW_ERR_INVALID_ARG, "graph or enable is NULL");
+    *enable = g->walk_guides.load();
+    return CSAW_OK;
+}
+
 csaw_status csaw_get_tuning(csaw_graph g, csaw_tuning* t) {
     t_err.clear();
     if (!g || !t) return fail(CSAW_ERR_INVALID_ARG, "graph or tuning is NULL");
@@ -1505,7 +1521,7 @@ static csaw_status walk_prepare(csaw_graph g, const csaw_walk_args* a, hipStream
                 return fail(CSAW_ERR_NOT_READY, "the tables of this bias kind are not built yet");
         } else {
             csaw_status st = prepare_bias(g, a->bias_kind, s);
-            if (st == CSAW_OK) st = prepare_walk_guides(g, a->bias_kind, s);
+            if (st == CSAW_OK && g->walk_guides.load()) st = prepare_walk_guides(g, a->bias_kind, s);
             if (st != CSAW_OK) return st;
         }
     }
@@ -1515,6 +1531,10 @@ static csaw_status walk_prepare(csaw_graph g, const csaw_walk_args* a, hipStream
 static WalkParams walk_params(csaw_graph g, const csaw_walk_args* a) {
     WalkParams p;
     p.g = g->dev();
+    if (!g->walk_guides.load()) {  // weighted walks take the chunk tables
+        p.g.wpre_ew = p.g.wpre_deg = nullptr;
+        p.g.wgd_ew = p.g.wgd_deg = nullptr;
+    }
     p.bias = a->bias_kind;
     p.w_return = a->w_return;
     p.w_common = a->w_common;
@@ -1848,7 +1868,7 @@ csaw_status prepare_bias_tables(csaw_graph g, int32_t kind, hipStream_t stream) 
     if (kind != kEdgeWeight && kind != kNeighborDegree) return CSAW_OK;
     HIP_OR_FAIL(hipSetDevice(g->device));
     const csaw_status st = prepare_bias(g, kind, stream);
-    return st != CSAW_OK ? st : prepare_walk_guides(g, kind, stream);
+    return st != CSAW_OK || !g->walk_guides.load() ? st : prepare_walk_guides(g, kind, stream);
 }
 
 }  // namespace csaw

@@ -6,9 +6,15 @@
 // independent, so no host round trip is needed between steps.
 //   - unbiased walks: one lane per walker (a step is two row-offset loads,
 //     one Philox draw and one neighbor load);
-//   - biased walks: one wavefront per walker; pass 1 streams the biases of
-//     N(v) into a coarse prefix table in LDS, r is drawn in [0, W), and pass
-//     2 rescans only the group of the table that holds r (scan + ballot).
+//   - edge-weight and degree-biased walks through the graph's walk guide
+//     (exact per-edge prefixes and a bucket table per list; a step is three
+//     rounds of loads): one lane per walker in launches of at least
+//     kLaneWalkMin walkers, else one wavefront per walker (lists of at most
+//     512 scanned whole); with the guide off, one wavefront per walker
+//     through the chunk tables;
+//   - other biased walks: one wavefront per walker; pass 1 streams the
+//     biases of N(v) into a coarse prefix table in LDS, r is drawn in [0, W),
+//     and pass 2 rescans only the group of the table that holds r.
 //   - node2vec: the bias of x in N(v) needs "is x adjacent to the previous
 //     vertex t"; adjacency lists are sorted, so N(v) is merged with N(t)
 //     (or, for a much longer N(t), each candidate binary-searches it).
@@ -647,23 +653,23 @@ __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w
 }
 
 // First-order weighted step on a list longer than kWaveMaxD through its walk
-// guide: r is drawn in [0, W) (W, the list's total, came with the row
-// offsets), its bucket k = r >> s gives the bracket [G[k], G[k+1]] that holds
-// the pick (every position before G[k] ends at or below k * 2^s <= r, and
-// G[k+1] ends past (k+1) * 2^s > r), and one load of the bracket's exact
-// prefixes and neighbor ids finds m = #{i : S_(i+1) <= r} by ballot. Three
-// dependent loads per step (row offsets and W, the bracket, its prefixes).
-// Returns the neighbor, or -2 when the bracket is wider than a wavefront (many
-// small weights in one bucket), which the caller takes through the chunk
-// tables.
+// guide, one wavefront per walker: r is drawn in [0, W) (W, the list's total,
+// came with the row offsets), its bucket k = r >> s gives the bracket
+// [G[k], G[k+1]] that holds the pick (every position before G[k] ends at or
+// below k * 2^s <= r, and G[k+1] ends past (k+1) * 2^s > r), and one load of
+// the bracket's exact prefixes and neighbor ids finds m = #{i : S_(i+1) <= r}
+// by ballot. Three dependent loads per step (row offsets and W, the bracket,
+// its prefixes). Returns the neighbor, or -2 when the bracket is wider than a
+// wavefront (many small weights in one bucket), which the caller takes
+// through the chunk tables.
 __device__ __forceinline__ int32_t walk_step_guide(const uint64_t* __restrict__ pre, const uint32_t* __restrict__ gd,
                                                    const int32_t* __restrict__ col, uint64_t r, uint64_t W,
-                                                   int64_t beg, int64_t d) {
+                                                   int64_t beg, int64_t d, int64_t v) {
     const int lane = lane_id();
     const int sh = guide_shift(W, d);
     const uint64_t K = ((W - 1) >> sh) + 1;
     const uint64_t k = r >> sh;
-    const uint32_t* G = gd + (beg >> 4);
+    const uint32_t* G = gd + guide_base(beg, v);
     const uint32_t g0 = ld_uniform(G + k), g1 = ld_uniform(G + (k + 1 < K ? k + 1 : k));
     const int64_t lo = g0;
     const int64_t hi = k + 1 < K ? (int64_t)g1 : d - 1;
@@ -751,7 +757,7 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
                             nx = -2;
                             if (gd) {
                                 stop = wt == 0;
-                                if (!stop) nx = walk_step_guide(pre, gd, p.g.col, range_reduce(u, wt), wt, beg, d);
+                                if (!stop) nx = walk_step_guide(pre, gd, p.g.col, range_reduce(u, wt), wt, beg, d, v);
                             }
                             if (nx == -2 && !stop) nx = walk_step_long(wts, p.g.col, gt, ct, u, beg, d, stop);
                         }
@@ -791,6 +797,116 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave_n2v(WalkParams p) {
     walk_wave_body<true, kMoves>(p);
 }
 
+// Weighted first-order walks through the walk guide, one lane per walker
+// (64 walkers per wavefront, each with its own chain of loads). A step:
+// the row offsets and the list's total W (one round of loads; the Philox
+// word is formed meanwhile), r = floor(u W / 2^64), the bracket
+// [G[k], G[k+1]] of bucket k = r >> s (one round), then the exact prefixes of
+// the bracket's first kLaneProbe - 1 positions and the neighbor ids of its
+// first kLaneProbe (one round): m = lo + #{j : S_(lo+j+1) <= r}. Positions
+// past the bracket's end are read at the end instead, whose prefix exceeds r,
+// so every load stays inside the list and needs no mask. A bracket longer
+// than the probe (rare: a run of small weights inside one bucket) takes
+// further rounds from where the last one stopped. A list of one edge skips
+// the bracket. The pick is the same m as a scan of the whole list.
+constexpr int kLaneProbe = 8;
+// A lane's round waits for the slowest of its wavefront's 64 scattered
+// loads, so a lane step takes about three times a wavefront step (9.5 against
+// 3.4 us unloaded); the lane kernel wins once a launch has enough walkers to
+// keep many lanes' chains in flight.
+constexpr int64_t kLaneWalkMin = 32768;
+
+template <bool kMoves>
+__global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
+    const bool dg = p.bias == kNeighborDegree;
+    const uint64_t* __restrict__ tots = dg ? p.g.wtot_deg : p.g.wtot_ew;
+    const uint64_t* __restrict__ pre = dg ? p.g.wpre_deg : p.g.wpre_ew;
+    const uint32_t* __restrict__ gd = dg ? p.g.wgd_deg : p.g.wgd_ew;
+    const int32_t* __restrict__ col = p.g.col;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w0 = blockIdx.x * (int64_t)blockDim.x; w0 < p.num_walkers; w0 += stride) {
+        const int64_t w = w0 + threadIdx.x;
+        int64_t my_steps = 0;
+        unsigned long long* my_counter = p.steps;
+        if (w < p.num_walkers) {
+            const WalkerCtx wc = walker_ctx(p, w);
+            const Key key = wc.key;
+            const int64_t L1 = (int64_t)wc.length + 1;
+            int32_t* path = wc.path;
+            my_counter = wc.steps;
+            int32_t v = p.starts[w];
+            int32_t s = 0;
+            if (v < 0 || (int64_t)v >= p.g.n) {
+                *p.bad_start = 1;
+                for (int64_t q = 0; q < L1; ++q) path[q] = -1;
+            } else {
+                path[0] = v;
+                const int32_t start = v;
+                const uint32_t c0 = wc.c0;
+                for (; s < wc.length; ++s) {
+                    int32_t to;
+                    if (kMoves && walk_move(p, key, c0, s, v, start, to)) {
+                        v = to;
+                        path[s + 1] = v;
+                        continue;
+                    }
+                    int64_t beg, d;
+                    row_lane(p.g.rowptr, v, beg, d);
+                    const uint64_t W = tots[v];
+                    uint64_t u = philox_u64(key.k0, key.k1, c0, (uint32_t)s, (uint32_t)v, 0u);
+                    // formed while the offsets load, not sunk past the test below
+                    asm volatile("" : "+v"(u));
+                    if (d == 0 || W == 0) break;
+                    const uint64_t r = range_reduce(u, W);
+                    int64_t lo = 0, hi = 0;
+                    if (d > 1) {
+                        const int sh = guide_shift(W, d);
+                        const uint64_t K = ((W - 1) >> sh) + 1;
+                        const uint64_t k = r >> sh;
+                        const uint32_t* G = gd + guide_base(beg, v);
+                        const bool last = k + 1 >= K;
+                        const uint32_t g0 = G[k], g1 = G[last ? k : k + 1];
+                        lo = g0;
+                        hi = last ? d - 1 : (int64_t)g1;
+                    }
+                    int32_t nx;
+                    for (;;) {
+                        uint64_t S[kLaneProbe - 1];
+                        int32_t y[kLaneProbe];
+#pragma unroll
+                        for (int j = 0; j < kLaneProbe; ++j) {
+                            const int64_t q = beg + (lo + j < hi ? lo + j : hi);
+                            if (j < kLaneProbe - 1) S[j] = pre[q];
+                            y[j] = col[q];
+                        }
+                        int c = 0;
+#pragma unroll
+                        for (int j = 0; j < kLaneProbe - 1; ++j) c += S[j] <= r ? 1 : 0;
+                        nx = y[0];
+#pragma unroll
+                        for (int j = 1; j < kLaneProbe; ++j) nx = c == j ? y[j] : nx;
+                        // keeps the id loads in this round: left to itself the
+                        // compiler sinks them past the loop, a round of their own
+                        asm volatile("" ::"v"(nx));
+                        if (c < kLaneProbe - 1 || lo + kLaneProbe - 1 >= hi) break;
+                        lo += kLaneProbe - 1;
+                    }
+                    v = nx;
+                    path[s + 1] = v;
+                }
+                for (int64_t q = s + 1; q < L1; ++q) path[q] = -1;
+            }
+            my_steps = s;
+        }
+        if (p.batch.req) {  // lanes of one wave may belong to different requests
+            if (my_steps) atomicAdd(my_counter, (unsigned long long)my_steps);
+        } else {
+            const int64_t ws = wave_sum_i64(my_steps);
+            if (lane_id() == 0 && ws) atomicAdd(p.steps, (unsigned long long)ws);
+        }
+    }
+}
+
 // One wavefront per vertex u, a lane per edge (u, x): is u in the sorted N(x)?
 __global__ void __launch_bounds__(kBlock) k_symmetric_check(RowPtr rowptr, const int32_t* __restrict__ col,
                                                             int64_t n, int32_t* __restrict__ flag) {
@@ -807,36 +923,47 @@ __global__ void __launch_bounds__(kBlock) k_symmetric_check(RowPtr rowptr, const
     }
 }
 
-// Walk guide tables, one wavefront per list longer than kWaveMaxD: the
-// inclusive prefix of every edge (64 at a time, one scan each, carried), and
-// for each bucket k < K of the list's guide, the position i whose interval
-// [S_i, S_(i+1)) holds k * 2^s (each position writes the buckets it covers).
+// Walk guide tables, one wavefront per list with a positive total: the inclusive prefix of every edge (64 at a time, one
+// scan each, carried), and for each bucket k < K of the list's guide the
+// position i whose interval [S_i, S_(i+1)) holds k * 2^s. Edge i covers the
+// buckets from ceil(S_i / 2^s) to ceil(S_(i+1) / 2^s) - 1 (none for a zero
+// weight), so every bucket is written once. A lane writes up to
+// kGuideLaneFill buckets itself; an edge heavier than that many buckets is
+// written by the whole wavefront, 64 buckets at a time.
+constexpr uint64_t kGuideLaneFill = 8;
 __global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const uint32_t* __restrict__ w,
                                                         const uint64_t* __restrict__ wtot, int64_t n,
                                                         uint64_t* __restrict__ pre, uint32_t* __restrict__ gd) {
     const int lane = lane_id();
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t v = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; v < n; v += waves) {
-        const int64_t b = rowptr[v], d = rowptr[v + 1] - b;
-        const uint64_t W = wtot[v];
-        if (d <= kWaveMaxD || W == 0) continue;
+        int64_t b, d;
+        row_uniform(rowptr, v, b, d);
+        const uint64_t W = ld_uniform(wtot + v);
+        if (W == 0) continue;
         const int sh = guide_shift(W, d);
         const uint64_t K = ((W - 1) >> sh) + 1;
         const uint64_t low = (uint64_t(1) << sh) - 1;
-        uint32_t* G = gd + (b >> 4);
+        uint32_t* G = gd + guide_base(b, v);
         uint64_t run = 0;
         for (int64_t base = 0; base < d; base += kWave) {
             const int64_t i = base + lane;
             const uint64_t x = i < d ? (uint64_t)w[b + i] : 0ull;
             const uint64_t incl = run + wave_incl_scan_u64(x);
             const uint64_t excl = incl - x;
+            const uint64_t k0 = (excl >> sh) + ((excl & low) != 0);
+            uint64_t k1 = (incl >> sh) + ((incl & low) != 0);
+            k1 = k1 < K ? k1 : K;
+            const uint64_t nk = i < d && k1 > k0 ? k1 - k0 : 0;
             if (i < d) {
                 pre[b + i] = incl;
-                // buckets k with excl <= k * 2^s < incl: k from ceil(excl / 2^s) to ceil(incl / 2^s) - 1
-                const uint64_t k0 = (excl >> sh) + ((excl & low) != 0);
-                uint64_t k1 = (incl >> sh) + ((incl & low) != 0);
-                k1 = k1 < K ? k1 : K;
-                for (uint64_t k = k0; k < k1; ++k) G[k] = (uint32_t)i;
+                if (nk <= kGuideLaneFill)
+                    for (uint64_t k = k0; k < k1; ++k) G[k] = (uint32_t)i;
+            }
+            for (uint64_t wide = ballot(nk > kGuideLaneFill); wide; wide &= wide - 1) {
+                const int src = __ffsll((unsigned long long)wide) - 1;
+                const uint64_t a0 = readlane_u64(k0, src), a1 = readlane_u64(k1, src);
+                for (uint64_t k = a0 + lane; k < a1; k += kWave) G[k] = (uint32_t)(base + src);
             }
             run = readlane_u64(incl, kWave - 1);
         }
@@ -877,8 +1004,18 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev) 
             if (moves) launch_kernel(k_walk_wave_n2v<true>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
             else launch_kernel(k_walk_wave_n2v<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
         } else {
-            if (moves) launch_kernel(k_walk_wave_moves, dim3((unsigned)g), dim3(kBlock), s, ev, p);
-            else launch_kernel(k_walk_wave_first, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            const bool dg = p.bias == kNeighborDegree;
+            if ((dg ? p.g.wgd_deg : p.g.wgd_ew) && (dg ? p.g.wpre_deg : p.g.wpre_ew) &&
+                p.num_walkers >= kLaneWalkMin) {
+                int64_t gl = (p.num_walkers + kBlock - 1) / kBlock;
+                if (gl > grid) gl = grid;
+                if (moves) launch_kernel(k_walk_lane<true>, dim3((unsigned)gl), dim3(kBlock), s, ev, p);
+                else launch_kernel(k_walk_lane<false>, dim3((unsigned)gl), dim3(kBlock), s, ev, p);
+            } else if (moves) {
+                launch_kernel(k_walk_wave_moves, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            } else {
+                launch_kernel(k_walk_wave_first, dim3((unsigned)g), dim3(kBlock), s, ev, p);
+            }
         }
     }
 }

@@ -333,14 +333,15 @@ void launch_walk_guides(RowPtr rowptr, const uint32_t* w, const uint64_t* wtot, 
         for (int64_t v = 0; v < n; ++v) {
             const int64_t b = rowptr[v], d = rowptr[v + 1] - b;
             const uint64_t W = wtot[v];
-            if (d <= kWaveMaxD || W == 0) continue;
+            if (W == 0) continue;
             const int sh = guide_shift(W, d);
             const uint64_t K = ((W - 1) >> sh) + 1;
+            uint32_t* G = gd + guide_base(b, v);
             uint64_t run = 0, k = 0;
             for (int64_t i = 0; i < d; ++i) {
                 run += w[b + i];
                 pre[b + i] = run;
-                for (; k < K && (k << sh) < run; ++k) gd[(b >> 4) + k] = (uint32_t)i;
+                for (; k < K && (k << sh) < run; ++k) G[k] = (uint32_t)i;
             }
         }
     });

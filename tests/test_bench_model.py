@@ -48,8 +48,9 @@ def test_byte_model_counts_entries_and_edges():
 
 def test_walk_step_bytes_by_route():
     """Per step 16 B (two 32-bit row offsets, the pick's id, the path entry)
-    plus 4 d for a list of at most 512 weights and 24 B for a longer one;
-    steps after a walk ended (-1) are not counted."""
+    plus the cheaper selection: 4 d for a list of at most 512 weights read
+    whole, or 24 B through the guide (total, bracket, one prefix); steps after
+    a walk ended (-1) are not counted."""
     bench = load_bench()
     deg = np.array([3, 600, 512, 0, 1])
     rp = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
@@ -59,4 +60,4 @@ def test_walk_step_bytes_by_route():
     b, steps = bench.walk_step_bytes(rp, paths)
     # taken steps leave 0, 1, 2, 4 (row 0); 1, 1 (row 1)
     assert steps == 6
-    assert b == 16 * 6 + 4 * 3 + 24 + 4 * 512 + 4 * 1 + 24 + 24
+    assert b == 16 * 6 + 4 * 3 + 24 + 24 + 4 * 1 + 24 + 24

@@ -23,29 +23,133 @@ def csaw():
     return c
 
 
-def run_both(csaw, g, rp, col, ew, starts, length, bias, rng_seed, walker_base=0, node2vec=(1, 1, 1)):
-    say("walk n=%d nw=%d len=%d bias=%d n2v=%s" % (len(rp) - 1, len(starts), length, bias, node2vec))
-    paths, steps = g.walk(starts, length, bias, rng_seed=rng_seed, walker_base=walker_base, node2vec=node2vec)
-    rp_, rs, _ = oracle.walk(rp, col, ew, starts, length, bias_kind=bias, rng_seed=rng_seed,
-                             walker_base=walker_base, node2vec=node2vec)
-    np.testing.assert_array_equal(paths.cpu().numpy(), rp_)
-    assert steps == int(rs.sum())
+def run_both(csaw, g, rp, col, ew, starts, length, bias, rng_seed, walker_base=0, node2vec=(1, 1, 1),
+             restart=0, jump=0, check_every=1):
+    """The GPU walk against the oracle: every walker, or (check_every > 1)
+    walkers 0, check_every, 2 check_every, ... by their ids, which fix the
+    draws."""
+    say("walk n=%d nw=%d len=%d bias=%d n2v=%s restart=%d jump=%d" % (len(rp) - 1, len(starts), length, bias,
+                                                                     node2vec, restart, jump))
+    paths, steps = g.walk(starts, length, bias, rng_seed=rng_seed, walker_base=walker_base, node2vec=node2vec,
+                          restart=restart, jump=jump)
+    idx = np.arange(0, len(starts), check_every)
+    ids = None if check_every == 1 else (walker_base + idx).astype(np.uint64)
+    rp_, rs, _ = oracle.walk(rp, col, ew, starts[idx], length, bias_kind=bias, rng_seed=rng_seed,
+                             walker_base=walker_base, walker_ids=ids, node2vec=node2vec, restart=restart, jump=jump)
+    got = paths.cpu().numpy()
+    np.testing.assert_array_equal(got[idx], rp_)
+    if check_every == 1:
+        assert steps == int(rs.sum())
+    else:
+        assert steps == int((got[:, 1:] >= 0).sum())
     return paths, steps
 
 
-@pytest.mark.parametrize("bias", [0, 1, 2])
-def test_first_order_walks(csaw, bias):
+@pytest.mark.parametrize("bias,guides", [(0, True), (1, True), (2, True), (1, False), (2, False)])
+def test_first_order_walks(csaw, bias, guides):
+    """Weighted walks take the walk guide (a lane per walker) or, with the
+    guide off, the chunk tables (a wavefront per walker): same paths."""
     rp, col = inputs.rmat_csr(14, 16 << 14, 21)
     g0 = inputs.rng(2)
     ew = g0.integers(0, 20, size=len(col)).astype(np.uint32)
     ew[g0.random(len(col)) < 0.2] = 0                     # W = 0 stops happen
     starts = inputs.walker_starts(rp, col, 5000, 3)
     g = csaw.Graph(rp, col, ew)
+    g.set_walk_guides(guides)
+    assert g.get_walk_guides() == guides
     run_both(csaw, g, rp, col, ew, starts, 40, bias, 5, walker_base=123)
 
 
-@pytest.mark.parametrize("wide", [False, True])
-def test_weighted_walk_long_lists(csaw, wide):
+def test_walk_guide_switch(csaw):
+    """The guide can be turned off after it was built (the wavefront route
+    then runs beside the kept tables) and on again; bad values are refused."""
+    rp, col = inputs.rmat_csr(12, 16 << 12, 5)
+    ew = inputs.dst_outdeg_weights(rp, col)
+    starts = inputs.walker_starts(rp, col, 2000, 6)
+    g = csaw.Graph(rp, col, ew)
+    for guides in (True, False, True):
+        g.set_walk_guides(guides)
+        run_both(csaw, g, rp, col, ew, starts, 20, 1, 7)
+        run_both(csaw, g, rp, col, ew, starts, 20, 2, 8)
+    with pytest.raises(csaw.CsawError) as ei:
+        csaw._check(csaw.lib.csaw_set_walk_guides(g._h, 2))
+    assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("bias,restart,jump", [(1, 0, 0), (2, 0, 0), (1, 1 << 29, 1 << 28), (2, 0, 1 << 30)])
+def test_lane_walks(csaw, bias, restart, jump):
+    """Launches of at least 32,768 walkers take one lane per walker through
+    the guide: weights with zeros (W = 0 stops), sinks, restart / jump moves,
+    every walker against the oracle; the same walkers in a launch below that
+    size (a wavefront each) give the same paths."""
+    rp, col = inputs.rmat_csr(14, 16 << 14, 21)
+    g0 = inputs.rng(4)
+    ew = g0.integers(0, 20, size=len(col)).astype(np.uint32)
+    ew[g0.random(len(col)) < 0.2] = 0
+    starts = inputs.walker_starts(rp, col, 40_000, 13)
+    g = csaw.Graph(rp, col, ew)
+    paths, _ = run_both(csaw, g, rp, col, ew, starts, 30, bias, 15, walker_base=77, restart=restart, jump=jump)
+    small, _ = g.walk(starts[:3000], 30, bias, rng_seed=15, walker_base=77, restart=restart, jump=jump)
+    np.testing.assert_array_equal(small.cpu().numpy(), paths.cpu().numpy()[:3000])
+
+
+@pytest.mark.parametrize("guides", [True, False])
+def test_weighted_walk_brackets_of_light_runs(csaw, guides):
+    """Lists whose light weights pack many positions into one guide bucket: a
+    hub of 20 blocks of one heavy weight and 20 weights of 1 (a bucket inside
+    a light run brackets more than the 8 positions one lane probes per round),
+    a hub of 8 blocks of one heavy weight and 100 ones (brackets of more than
+    64 positions, which the wavefront route takes through the chunk tables),
+    lists of one edge, and lists of two or three weights near 2^32 (a total of
+    64 bits). Every walker of the first 6,000 starts at a hub."""
+    n = 4_000
+    edges, ew = [], []
+    h1, h2 = 0, 1
+    for blk in range(20):
+        edges.append((h1, 2 + blk * 21))
+        ew.append(43_000)
+        for j in range(20):
+            edges.append((h1, 2 + blk * 21 + j + 1))
+            ew.append(1)
+    for blk in range(8):
+        edges.append((h2, 500 + blk * 101))
+        ew.append(207_000)
+        for j in range(100):
+            edges.append((h2, 500 + blk * 101 + j + 1))
+            ew.append(1)
+    for v in range(2, n):
+        r = v % 4
+        if r == 0:
+            edges += [(v, h1)]
+            ew += [5]
+        elif r == 1:
+            edges += [(v, h2), (v, h1)]
+            ew += [(1 << 32) - 1, (1 << 32) - 7]
+        elif r == 2:
+            edges += [(v, h1), (v, h2), (v, (v * 7) % n)]
+            ew += [(1 << 32) - 3, 3, (1 << 31) + 5]
+        else:
+            edges += [(v, h2), (v, h1)]
+            ew += [1, 2]
+    order = sorted(range(len(edges)), key=lambda i: edges[i])
+    edges = [edges[i] for i in order]
+    w = np.array([ew[i] for i in order], dtype=np.uint64).astype(np.uint32)
+    rp, col = inputs.csr_from_edges(n, edges)
+    assert len(col) == len(w)
+    g = csaw.Graph(rp, col, w)
+    g.set_walk_guides(guides)
+    starts = np.concatenate([np.full(3000, h1, dtype=np.int32), np.full(3000, h2, dtype=np.int32),
+                             inputs.walker_starts(rp, col, 2000, 12)])
+    run_both(csaw, g, rp, col, w, starts, 16, 1, 61, walker_base=11)
+    run_both(csaw, g, rp, col, w, starts, 16, 2, 62)
+    if guides:  # the same lists, one lane per walker
+        big = np.concatenate([starts, np.full(30_000, h1, dtype=np.int32), np.full(10_000, h2, dtype=np.int32)])
+        run_both(csaw, g, rp, col, w, big, 16, 1, 63, walker_base=5)
+        run_both(csaw, g, rp, col, w, big, 16, 2, 64)
+
+
+@pytest.mark.parametrize("wide,guides", [(False, True), (True, True), (True, False)])
+def test_weighted_walk_long_lists(csaw, wide, guides):
     """Lists longer than 512 take the chunk-table step: a 200,000-neighbor hub
     whose weights hold zero runs (whole 16-weight groups and a whole
     1,024-weight chunk of zeros) and, with `wide`, weights near 2^32 so the
@@ -64,12 +168,17 @@ def test_weighted_walk_long_lists(csaw, wide):
     ew[b + 3 * 1024:b + 4 * 1024] = 0     # a zero chunk
     ew[b + 100_000:b + 100_005] = 0
     g = csaw.Graph(rp, col, ew)
+    g.set_walk_guides(guides)
     starts = np.concatenate([np.zeros(3000, dtype=np.int32), inputs.walker_starts(rp, col, 1000, 8)])
     run_both(csaw, g, rp, col, ew, starts, 12, 1, 17, walker_base=5)
     run_both(csaw, g, rp, col, ew, starts, 12, 2, 18)
+    if guides:  # one lane per walker, every 10th walker checked
+        big = np.concatenate([np.zeros(30_000, dtype=np.int32), inputs.walker_starts(rp, col, 10_000, 9)])
+        run_both(csaw, g, rp, col, ew, big, 12, 1, 19, walker_base=3, check_every=10)
 
 
-def test_weighted_walk_guide_brackets(csaw):
+@pytest.mark.parametrize("guides", [True, False])
+def test_weighted_walk_guide_brackets(csaw, guides):
     """Long lists walk through their guide: a hub of 10,050 neighbors where
     every 201st weight is 10^5 and the others 100, so a bucket (2^14 wide here)
     inside a heavy weight brackets one or two positions, while one inside a
@@ -85,6 +194,7 @@ def test_weighted_walk_guide_brackets(csaw):
     b = int(rp[hub])
     ew[b:b + n - 1:201] = 100_000
     g = csaw.Graph(rp, col, ew)
+    g.set_walk_guides(guides)
     starts = np.concatenate([np.zeros(4000, dtype=np.int32), inputs.walker_starts(rp, col, 500, 9)])
     run_both(csaw, g, rp, col, ew, starts, 10, 1, 41, walker_base=3)
     run_both(csaw, g, rp, col, ew, starts, 10, 2, 42)
@@ -181,15 +291,18 @@ def test_node2vec_rmat24_shape_subset(csaw):
     assert steps == len(starts) * 80
 
 
-@pytest.mark.parametrize("bias,restart,jump", [(0, 1 << 30, 0), (1, 0, 1 << 29), (2, 1 << 29, 1 << 28),
-                                               (3, 1 << 30, 1 << 29), (3, 0, 1 << 31)])
-def test_restart_and_jump(csaw, bias, restart, jump):
+@pytest.mark.parametrize("bias,restart,jump,guides", [(0, 1 << 30, 0, True), (1, 0, 1 << 29, True),
+                                                      (2, 1 << 29, 1 << 28, True), (1, 0, 1 << 29, False),
+                                                      (2, 1 << 29, 1 << 28, False), (3, 1 << 30, 1 << 29, True),
+                                                      (3, 0, 1 << 31, True)])
+def test_restart_and_jump(csaw, bias, restart, jump, guides):
     """Random walk with restart / with jump: the per-step move rule (to the
     start, or to a uniform vertex) on every kernel route, bit for bit."""
     rp, col = inputs.rmat_csr(14, 8 << 14, 24, symmetrize=True)
     ew = inputs.dst_outdeg_weights(rp, col)
     starts = inputs.walker_starts(rp, col, 3000, 6)
     g = csaw.Graph(rp, col, ew)
+    g.set_walk_guides(guides)
     w = (1, 2, 4) if bias == 3 else (1, 1, 1)
     say("walk restart=%d jump=%d bias=%d" % (restart, jump, bias))
     paths, steps = g.walk(starts, 25, bias, rng_seed=31, walker_base=7, node2vec=w, restart=restart, jump=jump)
