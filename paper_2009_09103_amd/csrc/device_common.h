@@ -171,20 +171,6 @@ __device__ __forceinline__ void row_uniform(const Rows& rp, int64_t v, int64_t& 
     }
 }
 
-// The same for a vertex that differs per lane: the offsets are read as 32-bit
-// words of either width in one block of four loads, so they are issued
-// together (a branch on the width would put them in blocks of their own, each
-// waited for before the next).
-template <class Rows>
-__device__ __forceinline__ void row_lane(const Rows& rp, int64_t v, int64_t& beg, int64_t& d) {
-    const bool wide = rp.p32 == nullptr;
-    const uint32_t* q = wide ? reinterpret_cast<const uint32_t*>(rp.p64) + 2 * v : rp.p32 + v;
-    const uint32_t w0 = q[0], w1 = q[1], w2 = q[wide ? 2 : 1], w3 = q[wide ? 3 : 1];
-    beg = wide ? (int64_t)(((uint64_t)w1 << 32) | w0) : (int64_t)w0;
-    const int64_t end = wide ? (int64_t)(((uint64_t)w3 << 32) | w2) : (int64_t)w1;
-    d = end - beg;
-}
-
 // wave-uniform value (forces an SGPR)
 __device__ __forceinline__ int32_t uniform_i32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ int64_t uniform_i64(int64_t x) {

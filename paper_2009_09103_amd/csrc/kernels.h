@@ -32,6 +32,23 @@ struct RowPtr {
     const void* data() const { return p32 ? (const void*)p32 : (const void*)p64; }
 };
 
+// One edge of the walk guide: the inclusive prefix S_(i+1) of edge i in its
+// list beside the edge's neighbor, so that a probe of a few positions reads
+// one run of 16-byte records.
+struct alignas(16) WalkEdge {
+    uint64_t S;
+    int32_t col;
+    uint32_t pad;
+};
+
+// One vertex of the walk guide (graphs with m < 2^32): its list
+// [beg, beg + d) and the list's total W in one 16-byte record.
+struct alignas(16) WalkVertex {
+    uint64_t W;
+    uint32_t beg;
+    uint32_t d;
+};
+
 struct GraphDev {
     int64_t n, m;
     RowPtr rowptr;             // n+1
@@ -51,13 +68,17 @@ struct GraphDev {
     // (b >> 9) + j holds the total of chunks 0..j (null on partitioned graphs)
     const uint64_t* ctab_ew;
     const uint64_t* ctab_deg;
-    // walk guide tables of every list with a positive total (null until the
-    // first weighted walk of the weight array): wpre[e] = inclusive prefix of
-    // edge e in its list; the list v starting at edge b owns the bracket
-    // entries wgd[2 b + v + k], k < K (at most 2 d of its 2 d + 1 slots; K
-    // and s from guide_shift): the first position i with S_(i+1) > k * 2^s
-    const uint64_t* wpre_ew;
-    const uint64_t* wpre_deg;
+    // walk guide tables (null until the first weighted walk of the weight
+    // array): wrec[e] = edge e's inclusive prefix in its list and its
+    // neighbor (lists with a positive total); wvtx[v] = v's list and total
+    // (every vertex; null when m >= 2^32); the list v starting at edge b
+    // owns the bracket entries wgd[2 b + v + k], k < K (at most 2 d of its
+    // 2 d + 1 slots; K and s from guide_shift): the first position i with
+    // S_(i+1) > k * 2^s
+    const WalkEdge* wrec_ew;
+    const WalkEdge* wrec_deg;
+    const WalkVertex* wvtx_ew;
+    const WalkVertex* wvtx_deg;
     const uint32_t* wgd_ew;
     const uint32_t* wgd_deg;
 };
@@ -243,10 +264,10 @@ struct WalkParams {
     WalkBatch batch;                 // batch.req null: a single request
 };
 void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev = {});
-// The walk guide tables of weight array w (list totals wtot): pre[m],
-// gd[2 m + n].
-void launch_walk_guides(RowPtr rowptr, const uint32_t* w, const uint64_t* wtot, int64_t n, uint64_t* pre,
-                        uint32_t* gd, hipStream_t s);
+// The walk guide tables of weight array w (list totals wtot): rec[m],
+// vtx[n] (may be null), gd[2 m + n].
+void launch_walk_guides(RowPtr rowptr, const int32_t* col, const uint32_t* w, const uint64_t* wtot, int64_t n,
+                        WalkEdge* rec, WalkVertex* vtx, uint32_t* gd, hipStream_t s);
 constexpr int kGuideBucketsPerEdge = 2;  // a list of d edges gets at most 2 d buckets
 
 // Buckets of a list's walk guide: width 2^s, K = ((W - 1) >> s) + 1 of them,

@@ -229,8 +229,10 @@ struct csaw_graph_s {
     uint64_t* wtot_deg = nullptr;
     uint64_t* ctab_ew = nullptr;   // running chunk totals of the long lists
     uint64_t* ctab_deg = nullptr;
-    uint64_t* wpre_ew = nullptr;   // walk guides: per-edge prefixes and bucket brackets
-    uint64_t* wpre_deg = nullptr;
+    WalkEdge* wrec_ew = nullptr;   // walk guides: per-edge prefixes and neighbors,
+    WalkEdge* wrec_deg = nullptr;  // per-vertex lists and totals, bucket brackets
+    WalkVertex* wvtx_ew = nullptr;
+    WalkVertex* wvtx_deg = nullptr;
     uint32_t* wgd_ew = nullptr;
     uint32_t* wgd_deg = nullptr;
     std::mutex mu;                       // lazy preparation + workspace pool
@@ -254,8 +256,10 @@ struct csaw_graph_s {
         g.wtot_deg = wtot_deg;
         g.ctab_ew = ctab_ew;
         g.ctab_deg = ctab_deg;
-        g.wpre_ew = wpre_ew;
-        g.wpre_deg = wpre_deg;
+        g.wrec_ew = wrec_ew;
+        g.wrec_deg = wrec_deg;
+        g.wvtx_ew = wvtx_ew;
+        g.wvtx_deg = wvtx_deg;
         g.wgd_ew = wgd_ew;
         g.wgd_deg = wgd_deg;
         return g;
@@ -389,8 +393,9 @@ csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
 }
 
 // The walk guide tables of a weight array whose bias tables exist (per-edge
-// prefixes, 8 bytes per edge, and bucket brackets, a quarter byte per edge),
-// built once; a graph without them walks through the chunk tables.
+// prefix and neighbor records, 16 bytes per edge; per-vertex list records,
+// 16 bytes per vertex, when m < 2^32; bucket brackets, at most 8 bytes per
+// edge), built once; a graph without them walks through the chunk tables.
 csaw_status prepare_walk_guides(csaw_graph g, int32_t kind, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g->mu);
     const bool dg = kind == kNeighborDegree;
@@ -399,21 +404,27 @@ csaw_status prepare_walk_guides(csaw_graph g, int32_t kind, hipStream_t s) {
     const uint32_t* w = dg ? g->degw : g->ew;
     const uint64_t* tot = dg ? g->wtot_deg : g->wtot_ew;
     if (!w || !tot || !(dg ? g->ppos_deg : g->ppos_ew)) return CSAW_OK;
-    uint64_t* pre = nullptr;
+    WalkEdge* rec = nullptr;
+    WalkVertex* vtx = nullptr;
     uint32_t* gd = nullptr;
-    if (hipMalloc((void**)&pre, (size_t)g->m * sizeof(uint64_t)) != hipSuccess ||
+    const bool small = g->m < (int64_t(1) << 32);  // vertex records hold 32-bit list offsets
+    if (hipMalloc((void**)&rec, (size_t)g->m * sizeof(WalkEdge)) != hipSuccess ||
+        (small && hipMalloc((void**)&vtx, (size_t)std::max<int64_t>(g->n, 1) * sizeof(WalkVertex)) != hipSuccess) ||
         hipMalloc((void**)&gd, (size_t)(kGuideBucketsPerEdge * g->m + g->n) * sizeof(uint32_t)) != hipSuccess) {
-        if (pre) (void)hipFree(pre);
+        if (rec) (void)hipFree(rec);
+        if (vtx) (void)hipFree(vtx);
         return fail(CSAW_ERR_OUT_OF_MEMORY, "walk guide tables: allocation failed");
     }
-    launch_walk_guides(g->rowptr, w, tot, g->n, pre, gd, s);
+    launch_walk_guides(g->rowptr, g->col, w, tot, g->n, rec, vtx, gd, s);
     const hipError_t e = hipGetLastError() != hipSuccess ? hipErrorLaunchFailure : hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        (void)hipFree(pre);
+        (void)hipFree(rec);
+        if (vtx) (void)hipFree(vtx);
         (void)hipFree(gd);
         return fail(CSAW_ERR_DEVICE, "building the walk guide tables: %s", hipGetErrorString(e));
     }
-    (dg ? g->wpre_deg : g->wpre_ew) = pre;
+    (dg ? g->wrec_deg : g->wrec_ew) = rec;
+    (dg ? g->wvtx_deg : g->wvtx_ew) = vtx;
     (dg ? g->wgd_deg : g->wgd_ew) = gd;
     return CSAW_OK;
 }
@@ -697,7 +708,8 @@ csaw_status csaw_graph_destroy(csaw_graph g) {
     if (g->wtot_deg) (void)hipFree(g->wtot_deg);
     if (g->ctab_ew) (void)hipFree(g->ctab_ew);
     if (g->ctab_deg) (void)hipFree(g->ctab_deg);
-    for (void* q : {(void*)g->wpre_ew, (void*)g->wpre_deg, (void*)g->wgd_ew, (void*)g->wgd_deg})
+    for (void* q : {(void*)g->wrec_ew, (void*)g->wrec_deg, (void*)g->wvtx_ew, (void*)g->wvtx_deg, (void*)g->wgd_ew,
+                    (void*)g->wgd_deg})
         if (q) (void)hipFree(q);
     delete g;
     return CSAW_OK;
@@ -1008,8 +1020,9 @@ static csaw_status sample_call(csaw_graph g, const csaw_sample_args* a, csaw_sam
             for (const void* q : {gd.rowptr.data(), (const void*)gd.col, (const void*)gd.ew, (const void*)gd.degw,
                                   (const void*)gd.ppos_ew, (const void*)gd.ppos_deg, (const void*)gd.gtab_ew,
                                   (const void*)gd.gtab_deg, (const void*)gd.wtot_ew, (const void*)gd.wtot_deg,
-                                  (const void*)gd.ctab_ew, (const void*)gd.ctab_deg, (const void*)gd.wpre_ew,
-                                  (const void*)gd.wpre_deg, (const void*)gd.wgd_ew, (const void*)gd.wgd_deg})
+                                  (const void*)gd.ctab_ew, (const void*)gd.ctab_deg, (const void*)gd.wrec_ew,
+                                  (const void*)gd.wrec_deg, (const void*)gd.wvtx_ew, (const void*)gd.wvtx_deg,
+                                  (const void*)gd.wgd_ew, (const void*)gd.wgd_deg})
                 key.push_back((int64_t)(intptr_t)q);
             key.push_back((int64_t)P.uses_deg);
             key.push_back((int64_t)P.uses_ew);
@@ -1532,7 +1545,8 @@ static WalkParams walk_params(csaw_graph g, const csaw_walk_args* a) {
     WalkParams p;
     p.g = g->dev();
     if (!g->walk_guides.load()) {  // weighted walks take the chunk tables
-        p.g.wpre_ew = p.g.wpre_deg = nullptr;
+        p.g.wrec_ew = p.g.wrec_deg = nullptr;
+        p.g.wvtx_ew = p.g.wvtx_deg = nullptr;
         p.g.wgd_ew = p.g.wgd_deg = nullptr;
     }
     p.bias = a->bias_kind;

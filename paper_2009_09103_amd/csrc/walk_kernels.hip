@@ -662,9 +662,8 @@ __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w
 // its prefixes). Returns the neighbor, or -2 when the bracket is wider than a
 // wavefront (many small weights in one bucket), which the caller takes
 // through the chunk tables.
-__device__ __forceinline__ int32_t walk_step_guide(const uint64_t* __restrict__ pre, const uint32_t* __restrict__ gd,
-                                                   const int32_t* __restrict__ col, uint64_t r, uint64_t W,
-                                                   int64_t beg, int64_t d, int64_t v) {
+__device__ __forceinline__ int32_t walk_step_guide(const WalkEdge* __restrict__ er, const uint32_t* __restrict__ gd,
+                                                   uint64_t r, uint64_t W, int64_t beg, int64_t d, int64_t v) {
     const int lane = lane_id();
     const int sh = guide_shift(W, d);
     const uint64_t K = ((W - 1) >> sh) + 1;
@@ -679,8 +678,8 @@ __device__ __forceinline__ int32_t walk_step_guide(const uint64_t* __restrict__ 
     // bracket masked: guarded loads were waited for one after the other
     const bool in = lane < n;
     const int64_t j = beg + lo + (in ? lane : n - 1);
-    uint64_t S = pre[j];
-    const int32_t y = col[j];
+    uint64_t S = er[j].S;
+    const int32_t y = er[j].col;
     __builtin_amdgcn_sched_barrier(0);  // both loads in flight before either is used
     S = in ? S : ~0ull;
     const int c = __popcll(ballot(S <= r));
@@ -747,7 +746,7 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
                     const uint32_t* wts = dg ? p.g.degw : p.g.ew;
                     const uint64_t* gt = dg ? p.g.gtab_deg : p.g.gtab_ew;
                     const uint64_t* ct = dg ? p.g.ctab_deg : p.g.ctab_ew;
-                    const uint64_t* pre = dg ? p.g.wpre_deg : p.g.wpre_ew;
+                    const WalkEdge* er = dg ? p.g.wrec_deg : p.g.wrec_ew;
                     const uint32_t* gd = dg ? p.g.wgd_deg : p.g.wgd_ew;
                     if (d <= kWaveMaxD || (gt && ct)) {
                         if (d <= kWaveMaxD) {
@@ -757,7 +756,7 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
                             nx = -2;
                             if (gd) {
                                 stop = wt == 0;
-                                if (!stop) nx = walk_step_guide(pre, gd, p.g.col, range_reduce(u, wt), wt, beg, d, v);
+                                if (!stop) nx = walk_step_guide(er, gd, range_reduce(u, wt), wt, beg, d, v);
                             }
                             if (nx == -2 && !stop) nx = walk_step_long(wts, p.g.col, gt, ct, u, beg, d, stop);
                         }
@@ -799,11 +798,13 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave_n2v(WalkParams p) {
 
 // Weighted first-order walks through the walk guide, one lane per walker
 // (64 walkers per wavefront, each with its own chain of loads). A step:
-// the row offsets and the list's total W (one round of loads; the Philox
+// the vertex's record, its list and total W (one 16-byte load; the Philox
 // word is formed meanwhile), r = floor(u W / 2^64), the bracket
-// [G[k], G[k+1]] of bucket k = r >> s (one round), then the exact prefixes of
-// the bracket's first kLaneProbe - 1 positions and the neighbor ids of its
-// first kLaneProbe (one round): m = lo + #{j : S_(lo+j+1) <= r}. Positions
+// [G[k], G[k+1]] of bucket k = r >> s (one load), then the edge records of
+// the bracket's first kLaneProbe positions, exact prefixes beside neighbor
+// ids (one round): m = lo + #{j : S_(lo+j+1) <= r}. The walk is bound by
+// the 128-byte lines these scattered reads pull from HBM, so each round
+// reads one line where it can. Positions
 // past the bracket's end are read at the end instead, whose prefix exceeds r,
 // so every load stays inside the list and needs no mask. A bracket longer
 // than the probe (rare: a run of small weights inside one bucket) takes
@@ -819,10 +820,9 @@ constexpr int64_t kLaneWalkMin = 32768;
 template <bool kMoves>
 __global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
     const bool dg = p.bias == kNeighborDegree;
-    const uint64_t* __restrict__ tots = dg ? p.g.wtot_deg : p.g.wtot_ew;
-    const uint64_t* __restrict__ pre = dg ? p.g.wpre_deg : p.g.wpre_ew;
+    const WalkVertex* __restrict__ vt = dg ? p.g.wvtx_deg : p.g.wvtx_ew;
+    const WalkEdge* __restrict__ er = dg ? p.g.wrec_deg : p.g.wrec_ew;
     const uint32_t* __restrict__ gd = dg ? p.g.wgd_deg : p.g.wgd_ew;
-    const int32_t* __restrict__ col = p.g.col;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t w0 = blockIdx.x * (int64_t)blockDim.x; w0 < p.num_walkers; w0 += stride) {
         const int64_t w = w0 + threadIdx.x;
@@ -850,9 +850,9 @@ __global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
                         path[s + 1] = v;
                         continue;
                     }
-                    int64_t beg, d;
-                    row_lane(p.g.rowptr, v, beg, d);
-                    const uint64_t W = tots[v];
+                    const WalkVertex x = vt[v];
+                    const int64_t beg = x.beg, d = x.d;
+                    const uint64_t W = x.W;
                     uint64_t u = philox_u64(key.k0, key.k1, c0, (uint32_t)s, (uint32_t)v, 0u);
                     // formed while the offsets load, not sunk past the test below
                     asm volatile("" : "+v"(u));
@@ -876,8 +876,8 @@ __global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
 #pragma unroll
                         for (int j = 0; j < kLaneProbe; ++j) {
                             const int64_t q = beg + (lo + j < hi ? lo + j : hi);
-                            if (j < kLaneProbe - 1) S[j] = pre[q];
-                            y[j] = col[q];
+                            if (j < kLaneProbe - 1) S[j] = er[q].S;
+                            y[j] = er[q].col;
                         }
                         int c = 0;
 #pragma unroll
@@ -931,15 +931,18 @@ __global__ void __launch_bounds__(kBlock) k_symmetric_check(RowPtr rowptr, const
 // kGuideLaneFill buckets itself; an edge heavier than that many buckets is
 // written by the whole wavefront, 64 buckets at a time.
 constexpr uint64_t kGuideLaneFill = 8;
-__global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const uint32_t* __restrict__ w,
+__global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const int32_t* __restrict__ col,
+                                                        const uint32_t* __restrict__ w,
                                                         const uint64_t* __restrict__ wtot, int64_t n,
-                                                        uint64_t* __restrict__ pre, uint32_t* __restrict__ gd) {
+                                                        WalkEdge* __restrict__ rec, WalkVertex* __restrict__ vtx,
+                                                        uint32_t* __restrict__ gd) {
     const int lane = lane_id();
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t v = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; v < n; v += waves) {
         int64_t b, d;
         row_uniform(rowptr, v, b, d);
         const uint64_t W = ld_uniform(wtot + v);
+        if (vtx && lane == 0) vtx[v] = WalkVertex{W, (uint32_t)b, (uint32_t)d};
         if (W == 0) continue;
         const int sh = guide_shift(W, d);
         const uint64_t K = ((W - 1) >> sh) + 1;
@@ -956,7 +959,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const uin
             k1 = k1 < K ? k1 : K;
             const uint64_t nk = i < d && k1 > k0 ? k1 - k0 : 0;
             if (i < d) {
-                pre[b + i] = incl;
+                rec[b + i] = WalkEdge{incl, col[b + i], 0u};
                 if (nk <= kGuideLaneFill)
                     for (uint64_t k = k0; k < k1; ++k) G[k] = (uint32_t)i;
             }
@@ -972,12 +975,12 @@ __global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const uin
 
 }  // namespace
 
-void launch_walk_guides(RowPtr rowptr, const uint32_t* w, const uint64_t* wtot, int64_t n, uint64_t* pre,
-                        uint32_t* gd, hipStream_t s) {
+void launch_walk_guides(RowPtr rowptr, const int32_t* col, const uint32_t* w, const uint64_t* wtot, int64_t n,
+                        WalkEdge* rec, WalkVertex* vtx, uint32_t* gd, hipStream_t s) {
     if (n <= 0) return;
     int64_t g = (n + kWavesPerBlock - 1) / kWavesPerBlock;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_walk_guides, dim3((unsigned)g), dim3(kBlock), 0, s, rowptr, w, wtot, n, pre, gd);
+    hipLaunchKernelGGL(k_walk_guides, dim3((unsigned)g), dim3(kBlock), 0, s, rowptr, col, w, wtot, n, rec, vtx, gd);
 }
 
 void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_t* flag, hipStream_t s) {
@@ -1005,8 +1008,8 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev) 
             else launch_kernel(k_walk_wave_n2v<false>, dim3((unsigned)g), dim3(kBlock), s, ev, p);
         } else {
             const bool dg = p.bias == kNeighborDegree;
-            if ((dg ? p.g.wgd_deg : p.g.wgd_ew) && (dg ? p.g.wpre_deg : p.g.wpre_ew) &&
-                p.num_walkers >= kLaneWalkMin) {
+            if ((dg ? p.g.wgd_deg : p.g.wgd_ew) && (dg ? p.g.wrec_deg : p.g.wrec_ew) &&
+                (dg ? p.g.wvtx_deg : p.g.wvtx_ew) && p.num_walkers >= kLaneWalkMin) {
                 int64_t gl = (p.num_walkers + kBlock - 1) / kBlock;
                 if (gl > grid) gl = grid;
                 if (moves) launch_kernel(k_walk_lane<true>, dim3((unsigned)gl), dim3(kBlock), s, ev, p);

@@ -11,6 +11,7 @@
 // tests are about the host code, and a result depends only on its own
 // request, as the real one does.
 #include <algorithm>
+#include <cstdlib>
 #include <atomic>
 #include <chrono>
 #include <cstring>
@@ -327,20 +328,22 @@ void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_
     });
 }
 
-void launch_walk_guides(RowPtr rowptr, const uint32_t* w, const uint64_t* wtot, int64_t n, uint64_t* pre,
-                        uint32_t* gd, hipStream_t s) {
+void launch_walk_guides(RowPtr rowptr, const int32_t* col, const uint32_t* w, const uint64_t* wtot, int64_t n,
+                        WalkEdge* rec, WalkVertex* vtx, uint32_t* gd, hipStream_t s) {
     hipsim::enqueue(s, [=] {
         for (int64_t v = 0; v < n; ++v) {
             const int64_t b = rowptr[v], d = rowptr[v + 1] - b;
             const uint64_t W = wtot[v];
+            if (vtx) vtx[v] = WalkVertex{W, (uint32_t)b, (uint32_t)d};
             if (W == 0) continue;
             const int sh = guide_shift(W, d);
             const uint64_t K = ((W - 1) >> sh) + 1;
+            if (K > (uint64_t)(kGuideBucketsPerEdge * d)) abort();  // the list's slots hold its buckets
             uint32_t* G = gd + guide_base(b, v);
             uint64_t run = 0, k = 0;
             for (int64_t i = 0; i < d; ++i) {
                 run += w[b + i];
-                pre[b + i] = run;
+                rec[b + i] = WalkEdge{run, col[b + i], 0u};
                 for (; k < K && (k << sh) < run; ++k) G[k] = (uint32_t)i;
             }
         }
