@@ -481,10 +481,11 @@ typedef struct {
     int32_t num_streams;          /* executor threads/streams, 1..16 (0: 2)          */
     int64_t max_batch_walkers;    /* most walkers per walk call; a single larger
                                      request still runs alone (0: 262144)          */
-    int64_t result_pool_bytes;    /* host memory mapped and populated at creation
-                                     for result arrays, which are then written
-                                     without page faults; arrays that do not fit
-                                     come from the heap (0: none)                  */
+    int64_t result_pool_bytes;    /* pinned host memory allocated at creation for
+                                     result arrays: walk paths are copied from the
+                                     device straight into them, the rest without
+                                     page faults; arrays that do not fit come from
+                                     the heap, through staging (0: none)          */
 } csaw_server_config;
 
 typedef enum { CSAW_REQUEST_SAMPLE = 0, CSAW_REQUEST_WALK = 1 } csaw_request_kind;

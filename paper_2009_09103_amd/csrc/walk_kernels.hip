@@ -817,6 +817,29 @@ constexpr int kLaneProbe = 8;
 // keep many lanes' chains in flight.
 constexpr int64_t kLaneWalkMin = 32768;
 
+// A lane's path entries, written kPathRun at a time: a 4-byte store into a row
+// of its own per step leaves each line part written in the L2 when it is
+// evicted, over and over; a run of consecutive entries reaches its line at
+// once.
+constexpr int kPathRun = 8;
+struct PathRun {
+    int32_t e[kPathRun] = {};
+    int n = 0;
+    int64_t at = 1;  // path index of e[0]
+    __device__ __forceinline__ void flush(int32_t* path) {
+#pragma unroll
+        for (int j = 0; j < kPathRun; ++j)
+            if (j < n) path[at + j] = e[j];
+        at += n;
+        n = 0;
+    }
+    __device__ __forceinline__ void push(int32_t* path, int32_t x) {
+#pragma unroll
+        for (int j = 0; j < kPathRun; ++j) e[j] = n == j ? x : e[j];
+        if (++n == kPathRun) flush(path);
+    }
+};
+
 template <bool kMoves>
 __global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
     const bool dg = p.bias == kNeighborDegree;
@@ -843,11 +866,12 @@ __global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
                 path[0] = v;
                 const int32_t start = v;
                 const uint32_t c0 = wc.c0;
+                PathRun run;
                 for (; s < wc.length; ++s) {
                     int32_t to;
                     if (kMoves && walk_move(p, key, c0, s, v, start, to)) {
                         v = to;
-                        path[s + 1] = v;
+                        run.push(path, v);
                         continue;
                     }
                     const WalkVertex x = vt[v];
@@ -892,8 +916,9 @@ __global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
                         lo += kLaneProbe - 1;
                     }
                     v = nx;
-                    path[s + 1] = v;
+                    run.push(path, v);
                 }
+                run.flush(path);
                 for (int64_t q = s + 1; q < L1; ++q) path[q] = -1;
             }
             my_steps = s;
