@@ -219,6 +219,10 @@ void launch_clear_visited(const ClearVisited& c, hipStream_t s, LaunchEvents ev 
 void launch_call_setup(uint32_t* ctl, int64_t nctl, const uint32_t* host_tab, uint32_t* tab, int64_t ntab,
                        hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+// Segment j = edges [off[j], off[j+1]) of src / dst to to_src[j] / to_dst[j]
+// (device-visible addresses, null: skipped); off is device memory.
+void launch_scatter_segments(const int32_t* src, const int32_t* dst, const int64_t* off, int64_t nseg,
+                             int32_t* const* to_src, int32_t* const* to_dst, hipStream_t s);
 // Out-of-memory schedule: work[2p] = frontier entries and work[2p+1] = their
 // edges in partition p (vertices [bounds[p], bounds[p+1])), accumulated.
 constexpr int kMaxPartitionsHost = 64;

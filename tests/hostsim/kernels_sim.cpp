@@ -66,6 +66,20 @@ void launch_partition_work(const int32_t* fv, const int32_t* cnt, const SampleCt
     });
 }
 
+void launch_scatter_segments(const int32_t* src, const int32_t* dst, const int64_t* off, int64_t nseg,
+                             int32_t* const* to_src, int32_t* const* to_dst, hipStream_t s) {
+    if (nseg <= 0) return;
+    hipsim::enqueue(s, [=] {
+        for (int64_t j = 0; j < nseg; ++j) {
+            if (!to_src[j] || !to_dst[j]) continue;
+            for (int64_t k = off[j]; k < off[j + 1]; ++k) {
+                to_src[j][k - off[j]] = src[k];
+                to_dst[j][k - off[j]] = dst[k];
+            }
+        }
+    });
+}
+
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
     if (count <= 0) return;
     hipsim::enqueue(s, [=] { std::fill(p, p + count, value); });
