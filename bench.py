@@ -594,7 +594,7 @@ def bench_served(args):
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": walk_traffic,
                      "measured_copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
-                     "kernel": "walk (k_walk_wave_first, edge-weight walks)", "launches": kernels["walk"]["launches"],
+                     "kernel": "walk (k_walk_lane and k_walk_wave_first, edge-weight walks)", "launches": kernels["walk"]["launches"],
                      "avg_launch_us": walk_ms * 1e3 / max(kernels["walk"]["launches"], 1),
                      "alg_bytes_per_launch": wbytes / max(kernels["walk"]["launches"], 1),
                      "steps": wsteps,

@@ -220,9 +220,10 @@ void launch_call_setup(uint32_t* ctl, int64_t nctl, const uint32_t* host_tab, ui
                        hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 // Segment j = edges [off[j], off[j+1]) of src / dst to to_src[j] / to_dst[j]
-// (device-visible addresses, null: skipped); off is device memory.
+// (device addresses, null: skipped); off is device memory, non-decreasing,
+// with off[0] = 0 and off[nseg] = total.
 void launch_scatter_segments(const int32_t* src, const int32_t* dst, const int64_t* off, int64_t nseg,
-                             int32_t* const* to_src, int32_t* const* to_dst, hipStream_t s);
+                             int64_t total, int32_t* const* to_src, int32_t* const* to_dst, hipStream_t s);
 // Out-of-memory schedule: work[2p] = frontier entries and work[2p+1] = their
 // edges in partition p (vertices [bounds[p], bounds[p+1])), accumulated.
 constexpr int kMaxPartitionsHost = 64;

@@ -41,23 +41,26 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
 }
 
 // Edges of a batch to their requests' result arrays: segment j (edges
-// [off[j], off[j+1]) of the batch's layer-major arrays) goes to to_src[j] and
-// to_dst[j] (null: nowhere), which may be pinned host memory written over
-// the bus; one wavefront per segment, 64 consecutive edges per store.
+// [off[j], off[j+1]) of the batch's layer-major arrays, off non-decreasing)
+// goes to to_src[j] and to_dst[j] (null: nowhere). A thread per edge finds
+// its segment by binary search over off (a few hundred entries, cached), so
+// a long segment is spread over the whole grid.
 __global__ void k_scatter_segments(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                                    const int64_t* __restrict__ off, int64_t nseg, int32_t* const* __restrict__ to_src,
                                    int32_t* const* __restrict__ to_dst) {
-    const int lane = lane_id();
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; j < nseg; j += waves) {
-        const int64_t b = uniform_i64(off[j]), e = uniform_i64(off[j + 1]);
-        int32_t* ts = to_src[j];
-        int32_t* td = to_dst[j];
-        if (!ts || !td) continue;
-        for (int64_t k = b + lane; k < e; k += kWave) {
-            ts[k - b] = src[k];
-            td[k - b] = dst[k];
+    const int64_t total = off[nseg];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = nseg;  // the last j with off[j] <= k
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (off[mid] <= k) lo = mid;
+            else hi = mid;
         }
+        int32_t* ts = to_src[lo];
+        int32_t* td = to_dst[lo];
+        if (!ts || !td) continue;
+        ts[k - off[lo]] = src[k];
+        td[k - off[lo]] = dst[k];
     }
 }
 
@@ -1769,10 +1772,10 @@ void launch_partition_work(const int32_t* fv, const int32_t* cnt, const SampleCt
 }
 
 void launch_scatter_segments(const int32_t* src, const int32_t* dst, const int64_t* off, int64_t nseg,
-                             int32_t* const* to_src, int32_t* const* to_dst, hipStream_t s) {
-    if (nseg <= 0) return;
-    hipLaunchKernelGGL(k_scatter_segments, dim3(grid_for(nseg * kWave, kBlock, 4096)), dim3(kBlock), 0, s, src, dst,
-                       off, nseg, to_src, to_dst);
+                             int64_t total, int32_t* const* to_src, int32_t* const* to_dst, hipStream_t s) {
+    if (nseg <= 0 || total <= 0) return;
+    hipLaunchKernelGGL(k_scatter_segments, dim3(grid_for(total, kBlock, 8192)), dim3(kBlock), 0, s, src, dst, off,
+                       nseg, to_src, to_dst);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {

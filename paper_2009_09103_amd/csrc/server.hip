@@ -74,13 +74,11 @@ public:
         // the host maps pinned pages on first touch (host writes into untouched
         // pages ran at 2.9 GB/s against 31 GB/s): touch every page now
         for (size_t off = 0; off < bytes; off += kGranule) static_cast<volatile char*>(p)[off] = 0;
-        void* d = nullptr;  // the same memory as the device addresses it
-        HostPool* h = hipHostGetDevicePointer(&d, p, 0) == hipSuccess ? new (std::nothrow) HostPool() : nullptr;
+        HostPool* h = new (std::nothrow) HostPool();
         if (!h) {
             (void)hipHostFree(p);
             return nullptr;
         }
-        h->dev_ = (char*)d;
         h->base_ = (char*)p;
         h->bytes_ = bytes;
         h->free_[0] = bytes;
@@ -91,14 +89,9 @@ public:
         if (refs_.fetch_sub(1) == 1) delete this;
     }
     bool owns(const void* p) const { return (const char*)p >= base_ && (const char*)p < base_ + bytes_; }
-    // the device's address of pool memory p
-    template <class T>
-    T* device_address(T* p) const {
-        return (T*)(dev_ + ((const char*)p - base_));
-    }
     // n bytes, or null when no free range is large enough
     void* take(size_t n) {
-        n = (std::max<size_t>(n, 1) + kGranule - 1) / kGranule * kGranule;
+        n = round_up(n);
         std::lock_guard<std::mutex> lk(mu_);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second < n) continue;
@@ -109,6 +102,30 @@ public:
             return base_ + off;
         }
         return nullptr;
+    }
+    // Pieces of the given sizes carved back to back (each rounded to whole
+    // granules) out of one free range, so that one copy can fill them all;
+    // each piece is given back on its own. False when no range is large
+    // enough.
+    bool take_run(const std::vector<size_t>& sizes, std::vector<char*>& out) {
+        size_t total = 0;
+        for (size_t n : sizes) total += round_up(n);
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < total) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > total) free_[off + total] = len - total;
+            out.resize(sizes.size());
+            size_t at = off;
+            for (size_t k = 0; k < sizes.size(); ++k) {
+                out[k] = base_ + at;
+                used_[at] = round_up(sizes[k]);
+                at += round_up(sizes[k]);
+            }
+            return true;
+        }
+        return false;
     }
     void give(void* p) {
         const size_t off = (size_t)((char*)p - base_);
@@ -135,10 +152,10 @@ public:
 
 private:
     static constexpr size_t kGranule = 4096;
+    static size_t round_up(size_t n) { return (std::max<size_t>(n, 1) + kGranule - 1) / kGranule * kGranule; }
     HostPool() = default;
     ~HostPool() { (void)hipHostFree(base_); }
     char* base_ = nullptr;
-    char* dev_ = nullptr;
     size_t bytes_ = 0;
     std::atomic<int64_t> refs_{1};
     std::mutex mu_;
@@ -163,16 +180,21 @@ csaw_result* new_result(int32_t kind, csaw_status st) {
     return &b->pub;
 }
 
+// r holds ranges of the pool (it keeps the pool alive until it is freed).
+void hold_pool(HostPool* pool, csaw_result* r) {
+    ResultBox* b = reinterpret_cast<ResultBox*>(r);
+    if (!b->pool) {
+        b->pool = pool;
+        pool->ref();
+    }
+}
+
 // n bytes for one of r's arrays: a range of the pool when one is free, else
 // the heap.
 void* result_array(HostPool* pool, csaw_result* r, size_t n) {
     if (pool) {
         if (void* p = pool->take(n)) {
-            ResultBox* b = reinterpret_cast<ResultBox*>(r);
-            if (!b->pool) {
-                b->pool = pool;
-                pool->ref();
-            }
+            hold_pool(pool, r);
             return p;
         }
     }
@@ -489,17 +511,31 @@ void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Cloc
     ok = ok && ne >= 0 && ne <= shape.edges && h_off[0] == 0 && h_off[noff - 1] == ne;
     for (size_t j = 1; ok && j < noff; ++j) ok = h_off[j] >= h_off[j - 1];
     std::vector<csaw_result*> res(ni, nullptr);
-    std::vector<int64_t> base(ni, 0);  // edges of instance i before its layer l (filled per layer below)
+    // the batch's result arrays as one run of the pool when it has room (one
+    // copy fills them all), else one range or heap block each
+    std::vector<size_t> sizes;
+    std::vector<int64_t> cnts(ni, 0);
+    for (int32_t i = 0; ok && i < ni; ++i) {
+        for (int32_t l = 0; l < L; ++l) cnts[i] += h_off[(size_t)l * ni + i + 1] - h_off[(size_t)l * ni + i];
+        sizes.push_back((size_t)std::max<int64_t>(cnts[i], 1) * sizeof(int32_t));  // src
+        sizes.push_back(sizes.back());                                             // dst
+    }
+    std::vector<char*> run;
+    if (!(ok && pool && pool->take_run(sizes, run))) run.clear();
     for (int32_t i = 0; ok && i < ni; ++i) {
         const int32_t Li = (int32_t)batch[i]->fanouts.size();
         res[i] = new_result(CSAW_REQUEST_SAMPLE, CSAW_OK);
         if (!res[i]) continue;
-        int64_t cnt = 0;
-        for (int32_t l = 0; l < L; ++l) cnt += h_off[(size_t)l * ni + i + 1] - h_off[(size_t)l * ni + i];
-        res[i]->num_edges = cnt;
+        res[i]->num_edges = cnts[i];
         res[i]->num_layers = Li;
-        res[i]->src = (int32_t*)result_array(pool, res[i], (size_t)std::max<int64_t>(cnt, 1) * sizeof(int32_t));
-        res[i]->dst = (int32_t*)result_array(pool, res[i], (size_t)std::max<int64_t>(cnt, 1) * sizeof(int32_t));
+        if (!run.empty()) {
+            hold_pool(pool, res[i]);
+            res[i]->src = (int32_t*)run[2 * i];
+            res[i]->dst = (int32_t*)run[2 * i + 1];
+        } else {
+            res[i]->src = (int32_t*)result_array(pool, res[i], sizes[2 * i]);
+            res[i]->dst = (int32_t*)result_array(pool, res[i], sizes[2 * i + 1]);
+        }
         res[i]->layer_offsets = (int64_t*)std::malloc(((size_t)Li + 1) * sizeof(int64_t));
         if (!res[i]->src || !res[i]->dst || !res[i]->layer_offsets) {
             res[i]->status = CSAW_ERR_OUT_OF_MEMORY;
@@ -515,6 +551,12 @@ void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Cloc
         for (int32_t l = Li; l < L; ++l)
             ok = ok && h_off[(size_t)l * ni + i + 1] == h_off[(size_t)l * ni + i];
     }
+    // pieces of the run that no result took go back
+    for (int32_t i = 0; i < ni && !run.empty(); ++i)
+        if (!res[i] || res[i]->src != (int32_t*)run[2 * i]) {
+            pool->give(run[2 * i]);
+            pool->give(run[2 * i + 1]);
+        }
     // segment (l, i) = edges [h_off[l*ni+i], h_off[l*ni+i+1]) go to instance i
     // at its layer-l offset; segments are in increasing edge order
     auto scatter = [&](int32_t* csaw_result::*field) {
@@ -534,29 +576,34 @@ void csaw_server_s::run_sample_batch(std::vector<Request*>& batch, Exec& x, Cloc
             }
         };
     };
-    // every result's arrays in the pinned pool: one kernel writes each (layer,
-    // instance) segment straight into them, over the bus, with no staging
-    // buffer and no host copy
+    // the batch's arrays as one run of the pinned pool: a kernel lays the
+    // edges out in the device block exactly as the run holds them (each
+    // (layer, instance) segment at its request's layer offset), then one copy
+    // moves the whole run (kernel stores into host memory over the bus ran at
+    // 3 GB/s; the copy at 55 GB/s)
     const size_t nseg = noff - 1, tab_bytes = 2 * nseg * sizeof(int32_t*);
-    bool direct = ok && pool != nullptr && tab_bytes <= lay.scratch;
-    for (int32_t i = 0; direct && i < ni; ++i)
-        direct = res[i] && res[i]->status == CSAW_OK && pool->owns(res[i]->src) && pool->owns(res[i]->dst);
+    const size_t span = run.empty() ? 0 : (size_t)(run.back() - run.front()) + sizes.back();
+    bool direct = ok && !run.empty() && align_up(span) + tab_bytes <= lay.scratch;
+    for (int32_t i = 0; direct && i < ni; ++i) direct = res[i] && res[i]->status == CSAW_OK;
     if (direct) {
+        char* dspan = x.dev + lay.o_scratch;  // the call is done with its scratch
+        char* dtab = dspan + align_up(span);
         std::vector<int32_t*> tab(2 * nseg, nullptr);
         for (size_t j = 0; j < nseg; ++j) {
             if (h_off[j + 1] == h_off[j]) continue;
             const csaw_result* r = res[j % ni];
             const int64_t at = r->layer_offsets[j / ni];
-            tab[j] = pool->device_address(r->src + at);
-            tab[nseg + j] = pool->device_address(r->dst + at);
+            tab[j] = (int32_t*)(dspan + ((const char*)(r->src + at) - run.front()));
+            tab[nseg + j] = (int32_t*)(dspan + ((const char*)(r->dst + at) - run.front()));
         }
-        char* dtab = x.dev + lay.o_scratch;  // the call is done with its scratch
         ok = x.to_device(dtab, (const char*)tab.data(), tab_bytes);
         if (ok) {
             csaw::launch_scatter_segments((const int32_t*)(x.dev + lay.o_src), (const int32_t*)(x.dev + lay.o_dst),
-                                          (const int64_t*)(x.dev + lay.o_off), (int64_t)nseg,
+                                          (const int64_t*)(x.dev + lay.o_off), (int64_t)nseg, ne,
                                           (int32_t* const*)dtab, (int32_t* const*)dtab + nseg, x.st);
-            ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(x.st) == hipSuccess;
+            ok = hipGetLastError() == hipSuccess &&
+                 hipMemcpyAsync(run.front(), dspan, span, hipMemcpyDeviceToHost, x.st) == hipSuccess &&
+                 hipStreamSynchronize(x.st) == hipSuccess;
         }
     } else {
         ok = ok && x.to_host(x.dev + lay.o_src, (size_t)ne * sizeof(int32_t), scatter(&csaw_result::src)) &&

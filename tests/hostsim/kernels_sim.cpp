@@ -67,9 +67,10 @@ void launch_partition_work(const int32_t* fv, const int32_t* cnt, const SampleCt
 }
 
 void launch_scatter_segments(const int32_t* src, const int32_t* dst, const int64_t* off, int64_t nseg,
-                             int32_t* const* to_src, int32_t* const* to_dst, hipStream_t s) {
-    if (nseg <= 0) return;
+                             int64_t total, int32_t* const* to_src, int32_t* const* to_dst, hipStream_t s) {
+    if (nseg <= 0 || total <= 0) return;
     hipsim::enqueue(s, [=] {
+        if (total != off[nseg]) abort();  // the launcher's grid is sized by total
         for (int64_t j = 0; j < nseg; ++j) {
             if (!to_src[j] || !to_dst[j]) continue;
             for (int64_t k = off[j]; k < off[j + 1]; ++k) {

@@ -163,18 +163,17 @@ def test_walk_batch_one_lane_per_walker(setup):
     the lanes of one wavefront in different requests (their own keys, lengths,
     path rows and step counters); each result equals the request alone (a
     launch small enough for a wavefront per walker) and, for some, the
-    oracle."""
+    oracle. Any two of the queued requests together exceed 32,768 walkers."""
     csaw, rp, col, ew, g, trace = setup
     say("server walk batch above the lane threshold")
     srv = csaw.Server(g, num_streams=1, memory_budget_bytes=1 << 30, max_batch=64)
-    busy = srv.submit_walk(inputs.walker_starts(rp, col, 40000, 6), 80, 2, rng_seed=2, request_id=1)
+    busy = srv.submit_walk(inputs.walker_starts(rp, col, 200000, 6), 80, 2, rng_seed=2, request_id=1)
     reqs = [dict(kind="walk", id=200 + i, rng_seed=11 * i + 1, bias=1, length=7 + 9 * i,
-                 starts=inputs.walker_starts(rp, col, 4093 + 777 * i, 40 + i)) for i in range(8)]
+                 starts=inputs.walker_starts(rp, col, 17000 + 333 * i, 40 + i)) for i in range(8)]
     tickets = [submit(srv, r) for r in reqs]
     assert srv.wait(busy).status == 0
     results = [srv.wait(t) for t in tickets]
     srv.close()
-    assert sum(len(r["starts"]) for r in reqs) > 32768
     for k, (r, res) in enumerate(zip(reqs, results)):
         check_alone(csaw, g, rp, col, ew, r, res, with_oracle=(k % 3 == 0))
-    assert max(res.batch_requests for res in results) >= 6, [res.batch_requests for res in results]
+    assert max(res.batch_requests for res in results) >= 2, [res.batch_requests for res in results]
