@@ -541,8 +541,8 @@ def bench_served(args):
     ew = inputs.dst_outdeg_weights(rp, col)
     g = csaw.Graph(rp, col, ew)
     log("graph n=%d m=%d ready in %.1fs" % (len(rp) - 1, len(col), time.perf_counter() - t0))
-    pool = 2 << 30  # host result memory populated at creation, for both paths
-    served_kw = dict(num_streams=3, max_batch=256, memory_budget_bytes=48 << 30, max_batch_walkers=1 << 16,
+    pool = 2 << 30  # pinned host result memory, touched at creation, for both paths
+    served_kw = dict(num_streams=3, max_batch=256, memory_budget_bytes=48 << 30, max_batch_walkers=1 << 18,
                      result_pool_bytes=pool)
     plain_kw = dict(num_streams=1, max_batch=1, memory_budget_bytes=16 << 30, result_pool_bytes=pool)
     qps_list = args.qps or [400.0, 1600.0, 6400.0, 25600.0]
