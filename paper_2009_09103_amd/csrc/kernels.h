@@ -49,6 +49,16 @@ struct alignas(16) WalkVertex {
     uint32_t d;
 };
 
+// One bucket of a list's walk guide: the position i whose interval
+// [S_i, S_(i+1)) holds the bucket's start, with that position's exact
+// prefix S_(i+1) and neighbor, so that a bracket of one or two positions
+// needs no edge record.
+struct alignas(16) WalkBucket {
+    uint64_t S;
+    uint32_t pos;
+    int32_t col;
+};
+
 struct GraphDev {
     int64_t n, m;
     RowPtr rowptr;             // n+1
@@ -72,15 +82,15 @@ struct GraphDev {
     // array): wrec[e] = edge e's inclusive prefix in its list and its
     // neighbor (lists with a positive total); wvtx[v] = v's list and total
     // (every vertex; null when m >= 2^32); the list v starting at edge b
-    // owns the bracket entries wgd[2 b + v + k], k < K (at most 2 d of its
-    // 2 d + 1 slots; K and s from guide_shift): the first position i with
-    // S_(i+1) > k * 2^s
+    // owns the buckets wgd[2 b + v + k], k < K (at most 2 d of its 2 d + 1
+    // slots; K and s from guide_shift): the first position i with
+    // S_(i+1) > k * 2^s, its S_(i+1) and its neighbor
     const WalkEdge* wrec_ew;
     const WalkEdge* wrec_deg;
     const WalkVertex* wvtx_ew;
     const WalkVertex* wvtx_deg;
-    const uint32_t* wgd_ew;
-    const uint32_t* wgd_deg;
+    const WalkBucket* wgd_ew;
+    const WalkBucket* wgd_deg;
 };
 
 constexpr int kWaveMaxD = 512;   // longest weighted list of the wavefront kernels
@@ -272,7 +282,7 @@ void launch_walk(const WalkParams& p, int grid, hipStream_t s, LaunchEvents ev =
 // The walk guide tables of weight array w (list totals wtot): rec[m],
 // vtx[n] (may be null), gd[2 m + n].
 void launch_walk_guides(RowPtr rowptr, const int32_t* col, const uint32_t* w, const uint64_t* wtot, int64_t n,
-                        WalkEdge* rec, WalkVertex* vtx, uint32_t* gd, hipStream_t s);
+                        WalkEdge* rec, WalkVertex* vtx, WalkBucket* gd, hipStream_t s);
 constexpr int kGuideBucketsPerEdge = 2;  // a list of d edges gets at most 2 d buckets
 
 // Buckets of a list's walk guide: width 2^s, K = ((W - 1) >> s) + 1 of them,

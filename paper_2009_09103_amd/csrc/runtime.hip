@@ -233,8 +233,8 @@ struct csaw_graph_s {
     WalkEdge* wrec_deg = nullptr;  // per-vertex lists and totals, bucket brackets
     WalkVertex* wvtx_ew = nullptr;
     WalkVertex* wvtx_deg = nullptr;
-    uint32_t* wgd_ew = nullptr;
-    uint32_t* wgd_deg = nullptr;
+    WalkBucket* wgd_ew = nullptr;
+    WalkBucket* wgd_deg = nullptr;
     std::mutex mu;                       // lazy preparation + workspace pool
     std::vector<Workspace*> pool;
     std::atomic<int32_t> bound16{kDefaultBound16}, bound32{kDefaultBound32};  // sub-wave buckets
@@ -394,8 +394,9 @@ csaw_status prepare_bias(csaw_graph g, int32_t kind, hipStream_t s) {
 
 // The walk guide tables of a weight array whose bias tables exist (per-edge
 // prefix and neighbor records, 16 bytes per edge; per-vertex list records,
-// 16 bytes per vertex, when m < 2^32; bucket brackets, at most 8 bytes per
-// edge), built once; a graph without them walks through the chunk tables.
+// 16 bytes per vertex, when m < 2^32; buckets, 16 bytes each and at most two
+// per edge), built once; a graph without them walks through the chunk
+// tables.
 csaw_status prepare_walk_guides(csaw_graph g, int32_t kind, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g->mu);
     const bool dg = kind == kNeighborDegree;
@@ -406,11 +407,11 @@ csaw_status prepare_walk_guides(csaw_graph g, int32_t kind, hipStream_t s) {
     if (!w || !tot || !(dg ? g->ppos_deg : g->ppos_ew)) return CSAW_OK;
     WalkEdge* rec = nullptr;
     WalkVertex* vtx = nullptr;
-    uint32_t* gd = nullptr;
+    WalkBucket* gd = nullptr;
     const bool small = g->m < (int64_t(1) << 32);  // vertex records hold 32-bit list offsets
     if (hipMalloc((void**)&rec, (size_t)g->m * sizeof(WalkEdge)) != hipSuccess ||
         (small && hipMalloc((void**)&vtx, (size_t)std::max<int64_t>(g->n, 1) * sizeof(WalkVertex)) != hipSuccess) ||
-        hipMalloc((void**)&gd, (size_t)(kGuideBucketsPerEdge * g->m + g->n) * sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc((void**)&gd, (size_t)(kGuideBucketsPerEdge * g->m + g->n) * sizeof(WalkBucket)) != hipSuccess) {
         if (rec) (void)hipFree(rec);
         if (vtx) (void)hipFree(vtx);
         return fail(CSAW_ERR_OUT_OF_MEMORY, "walk guide tables: allocation failed");

@@ -659,19 +659,29 @@ __device__ __forceinline__ int32_t walk_step_long(const uint32_t* __restrict__ w
 // below k * 2^s <= r, and G[k+1] ends past (k+1) * 2^s > r), and one load of
 // the bracket's exact prefixes and neighbor ids finds m = #{i : S_(i+1) <= r}
 // by ballot. Three dependent loads per step (row offsets and W, the bracket,
-// its prefixes). Returns the neighbor, or -2 when the bracket is wider than a
+// its prefixes), two when the bracket holds one or two positions (the
+// buckets carry their positions' prefixes and ids). Returns the neighbor,
+// or -2 when the bracket is wider than a
 // wavefront (many small weights in one bucket), which the caller takes
 // through the chunk tables.
-__device__ __forceinline__ int32_t walk_step_guide(const WalkEdge* __restrict__ er, const uint32_t* __restrict__ gd,
-                                                   uint64_t r, uint64_t W, int64_t beg, int64_t d, int64_t v) {
+__device__ __forceinline__ int32_t walk_step_guide(const WalkEdge* __restrict__ er,
+                                                   const WalkBucket* __restrict__ gd, uint64_t r, uint64_t W,
+                                                   int64_t beg, int64_t d, int64_t v) {
     const int lane = lane_id();
     const int sh = guide_shift(W, d);
     const uint64_t K = ((W - 1) >> sh) + 1;
     const uint64_t k = r >> sh;
-    const uint32_t* G = gd + guide_base(beg, v);
-    const uint32_t g0 = ld_uniform(G + k), g1 = ld_uniform(G + (k + 1 < K ? k + 1 : k));
-    const int64_t lo = g0;
-    const int64_t hi = k + 1 < K ? (int64_t)g1 : d - 1;
+    const WalkBucket* G = gd + guide_base(beg, v);
+    const bool last = k + 1 >= K;
+    const WalkBucket* q0 = G + k;
+    const WalkBucket* q1 = G + (last ? k : k + 1);
+    const WalkBucket b0{ld_uniform(&q0->S), ld_uniform(&q0->pos), ld_uniform(&q0->col)};
+    const WalkBucket b1{ld_uniform(&q1->S), ld_uniform(&q1->pos), ld_uniform(&q1->col)};
+    const int64_t lo = b0.pos;
+    const int64_t hi = last ? d - 1 : (int64_t)b1.pos;
+    // a bracket of one or two positions: the buckets hold their prefixes and ids
+    if (hi == lo) return b0.col;
+    if (!last && hi == lo + 1) return b0.S > r ? b0.col : b1.col;
     const int64_t n = hi - lo + 1;
     if (n > kWave) return -2;
     // both loads issued at clamped positions, then the lanes past the
@@ -747,7 +757,7 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
                     const uint64_t* gt = dg ? p.g.gtab_deg : p.g.gtab_ew;
                     const uint64_t* ct = dg ? p.g.ctab_deg : p.g.ctab_ew;
                     const WalkEdge* er = dg ? p.g.wrec_deg : p.g.wrec_ew;
-                    const uint32_t* gd = dg ? p.g.wgd_deg : p.g.wgd_ew;
+                    const WalkBucket* gd = dg ? p.g.wgd_deg : p.g.wgd_ew;
                     if (d <= kWaveMaxD || (gt && ct)) {
                         if (d <= kWaveMaxD) {
                             nx = walk_step_short(wts, p.g.col, reinterpret_cast<uint32_t*>(lds.tab), u, beg, (int32_t)d,
@@ -800,11 +810,13 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave_n2v(WalkParams p) {
 // (64 walkers per wavefront, each with its own chain of loads). A step:
 // the vertex's record, its list and total W (one 16-byte load; the Philox
 // word is formed meanwhile), r = floor(u W / 2^64), the bracket
-// [G[k], G[k+1]] of bucket k = r >> s (one load), then the edge records of
-// the bracket's first kLaneProbe positions, exact prefixes beside neighbor
-// ids (one round): m = lo + #{j : S_(lo+j+1) <= r}. The walk is bound by
-// the 128-byte lines these scattered reads pull from HBM, so each round
-// reads one line where it can. Positions
+// [G[k], G[k+1]] of bucket k = r >> s (one load of two 16-byte buckets; a
+// bracket of one or two positions is decided by the buckets' own prefixes
+// and ids, about 80% of steps), else the edge records of the bracket's first
+// kLaneProbe positions, exact prefixes beside neighbor ids (one round):
+// m = lo + #{j : S_(lo+j+1) <= r}. The walk is bound by the 128-byte lines
+// these scattered reads pull from HBM, so each round reads one line where
+// it can. Positions
 // past the bracket's end are read at the end instead, whose prefix exceeds r,
 // so every load stays inside the list and needs no mask. A bracket longer
 // than the probe (rare: a run of small weights inside one bucket) takes
@@ -845,7 +857,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
     const bool dg = p.bias == kNeighborDegree;
     const WalkVertex* __restrict__ vt = dg ? p.g.wvtx_deg : p.g.wvtx_ew;
     const WalkEdge* __restrict__ er = dg ? p.g.wrec_deg : p.g.wrec_ew;
-    const uint32_t* __restrict__ gd = dg ? p.g.wgd_deg : p.g.wgd_ew;
+    const WalkBucket* __restrict__ gd = dg ? p.g.wgd_deg : p.g.wgd_ew;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t w0 = blockIdx.x * (int64_t)blockDim.x; w0 < p.num_walkers; w0 += stride) {
         const int64_t w = w0 + threadIdx.x;
@@ -883,18 +895,27 @@ __global__ void __launch_bounds__(kBlock) k_walk_lane(WalkParams p) {
                     if (d == 0 || W == 0) break;
                     const uint64_t r = range_reduce(u, W);
                     int64_t lo = 0, hi = 0;
+                    int32_t nx = -1;
+                    bool done = false;
                     if (d > 1) {
                         const int sh = guide_shift(W, d);
                         const uint64_t K = ((W - 1) >> sh) + 1;
                         const uint64_t k = r >> sh;
-                        const uint32_t* G = gd + guide_base(beg, v);
+                        const WalkBucket* G = gd + guide_base(beg, v);
                         const bool last = k + 1 >= K;
-                        const uint32_t g0 = G[k], g1 = G[last ? k : k + 1];
-                        lo = g0;
-                        hi = last ? d - 1 : (int64_t)g1;
+                        const WalkBucket b0 = G[k], b1 = G[last ? k : k + 1];
+                        lo = b0.pos;
+                        hi = last ? d - 1 : (int64_t)b1.pos;
+                        // a bracket of one or two positions needs no edge record
+                        if (hi == lo) {
+                            nx = b0.col;
+                            done = true;
+                        } else if (!last && hi == lo + 1) {
+                            nx = b0.S > r ? b0.col : b1.col;
+                            done = true;
+                        }
                     }
-                    int32_t nx;
-                    for (;;) {
+                    while (!done) {
                         uint64_t S[kLaneProbe - 1];
                         int32_t y[kLaneProbe];
 #pragma unroll
@@ -960,7 +981,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const int
                                                         const uint32_t* __restrict__ w,
                                                         const uint64_t* __restrict__ wtot, int64_t n,
                                                         WalkEdge* __restrict__ rec, WalkVertex* __restrict__ vtx,
-                                                        uint32_t* __restrict__ gd) {
+                                                        WalkBucket* __restrict__ gd) {
     const int lane = lane_id();
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t v = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; v < n; v += waves) {
@@ -972,11 +993,12 @@ __global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const int
         const int sh = guide_shift(W, d);
         const uint64_t K = ((W - 1) >> sh) + 1;
         const uint64_t low = (uint64_t(1) << sh) - 1;
-        uint32_t* G = gd + guide_base(b, v);
+        WalkBucket* G = gd + guide_base(b, v);
         uint64_t run = 0;
         for (int64_t base = 0; base < d; base += kWave) {
             const int64_t i = base + lane;
             const uint64_t x = i < d ? (uint64_t)w[b + i] : 0ull;
+            const int32_t y = i < d ? col[b + i] : 0;
             const uint64_t incl = run + wave_incl_scan_u64(x);
             const uint64_t excl = incl - x;
             const uint64_t k0 = (excl >> sh) + ((excl & low) != 0);
@@ -984,14 +1006,15 @@ __global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const int
             k1 = k1 < K ? k1 : K;
             const uint64_t nk = i < d && k1 > k0 ? k1 - k0 : 0;
             if (i < d) {
-                rec[b + i] = WalkEdge{incl, col[b + i], 0u};
+                rec[b + i] = WalkEdge{incl, y, 0u};
                 if (nk <= kGuideLaneFill)
-                    for (uint64_t k = k0; k < k1; ++k) G[k] = (uint32_t)i;
+                    for (uint64_t k = k0; k < k1; ++k) G[k] = WalkBucket{incl, (uint32_t)i, y};
             }
             for (uint64_t wide = ballot(nk > kGuideLaneFill); wide; wide &= wide - 1) {
                 const int src = __ffsll((unsigned long long)wide) - 1;
                 const uint64_t a0 = readlane_u64(k0, src), a1 = readlane_u64(k1, src);
-                for (uint64_t k = a0 + lane; k < a1; k += kWave) G[k] = (uint32_t)(base + src);
+                const WalkBucket e{readlane_u64(incl, src), (uint32_t)(base + src), readlane_i32(y, src)};
+                for (uint64_t k = a0 + lane; k < a1; k += kWave) G[k] = e;
             }
             run = readlane_u64(incl, kWave - 1);
         }
@@ -1001,7 +1024,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const int
 }  // namespace
 
 void launch_walk_guides(RowPtr rowptr, const int32_t* col, const uint32_t* w, const uint64_t* wtot, int64_t n,
-                        WalkEdge* rec, WalkVertex* vtx, uint32_t* gd, hipStream_t s) {
+                        WalkEdge* rec, WalkVertex* vtx, WalkBucket* gd, hipStream_t s) {
     if (n <= 0) return;
     int64_t g = (n + kWavesPerBlock - 1) / kWavesPerBlock;
     if (g > 65536) g = 65536;

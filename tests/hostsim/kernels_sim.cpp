@@ -344,7 +344,7 @@ void launch_symmetric_check(RowPtr rowptr, const int32_t* col, int64_t n, int32_
 }
 
 void launch_walk_guides(RowPtr rowptr, const int32_t* col, const uint32_t* w, const uint64_t* wtot, int64_t n,
-                        WalkEdge* rec, WalkVertex* vtx, uint32_t* gd, hipStream_t s) {
+                        WalkEdge* rec, WalkVertex* vtx, WalkBucket* gd, hipStream_t s) {
     hipsim::enqueue(s, [=] {
         for (int64_t v = 0; v < n; ++v) {
             const int64_t b = rowptr[v], d = rowptr[v + 1] - b;
@@ -354,12 +354,12 @@ void launch_walk_guides(RowPtr rowptr, const int32_t* col, const uint32_t* w, co
             const int sh = guide_shift(W, d);
             const uint64_t K = ((W - 1) >> sh) + 1;
             if (K > (uint64_t)(kGuideBucketsPerEdge * d)) abort();  // the list's slots hold its buckets
-            uint32_t* G = gd + guide_base(b, v);
+            WalkBucket* G = gd + guide_base(b, v);
             uint64_t run = 0, k = 0;
             for (int64_t i = 0; i < d; ++i) {
                 run += w[b + i];
                 rec[b + i] = WalkEdge{run, col[b + i], 0u};
-                for (; k < K && (k << sh) < run; ++k) G[k] = (uint32_t)i;
+                for (; k < K && (k << sh) < run; ++k) G[k] = WalkBucket{run, (uint32_t)i, col[b + i]};
             }
         }
     });
