@@ -312,14 +312,15 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* args, int32_t* paths,
  * array's first walk the graph builds, once: the exact inclusive prefix of
  * every edge in its list (8 bytes per edge), and per list of total W and
  * degree d a table of K <= 2 d equal buckets of width 2^s over [0, W), each
- * holding the first position whose interval reaches its start (4 bytes per
- * bucket, 2 m + n entries). A step's draw r then lies between the positions
- * of buckets r >> s and (r >> s) + 1, and one lane per walker finds
- * m = #{i : S_(i+1) <= r} from a few exact prefixes: the same pick as a
- * search of the whole prefix. About 16 bytes per edge per weight array
- * (17 GB for 2^30 edges); with the guide off (or not yet built in a caller
- * memory call) walks take the chunk tables with one wavefront per walker,
- * with the same paths.
+ * holding the first position whose interval reaches its start, with that
+ * position's prefix and neighbor (16 bytes per bucket, 2 m + n entries),
+ * and per vertex its list and W (16 bytes, when m < 2^32). A step's draw r
+ * then lies between the positions of buckets r >> s and (r >> s) + 1, and
+ * m = #{i : S_(i+1) <= r} follows from the two buckets or a few exact
+ * prefixes: the same pick as a search of the whole prefix. About 48 bytes
+ * per edge per weight array (51 GB for 2^30 edges); with the guide off (or
+ * not yet built in a caller memory call) walks take the chunk tables with
+ * one wavefront per walker, with the same paths.
  * enable: 1 (default) or 0. A walk already running keeps its route. INVALID_ARG
  * otherwise. Turning the guide off does not free built tables. */
 csaw_status csaw_set_walk_guides(csaw_graph g, int32_t enable);

@@ -824,10 +824,11 @@ __global__ void __launch_bounds__(kBlock) k_walk_wave_n2v(WalkParams p) {
 // the bracket. The pick is the same m as a scan of the whole list.
 constexpr int kLaneProbe = 8;
 // A lane's round waits for the slowest of its wavefront's 64 scattered
-// loads, so a lane step takes about three times a wavefront step (9.5 against
-// 3.4 us unloaded); the lane kernel wins once a launch has enough walkers to
-// keep many lanes' chains in flight.
-constexpr int64_t kLaneWalkMin = 32768;
+// loads, so an unloaded lane step takes longer than a wavefront step (3.3
+// against 2.0 us at 2,048 walkers); the lane kernel wins once a launch has
+// enough walkers to keep many lanes' chains in flight (measured: behind at
+// 8,192 walkers, ahead at 16,384).
+constexpr int64_t kLaneWalkMin = 12288;
 
 // A lane's path entries, written kPathRun at a time: a 4-byte store into a row
 // of its own per step leaves each line part written in the L2 when it is

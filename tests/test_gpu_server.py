@@ -159,11 +159,10 @@ def test_walks_share_launches(setup):
 
 
 def test_walk_batch_one_lane_per_walker(setup):
-    """A walk batch of more than 32,768 walkers runs one lane per walker, with
-    the lanes of one wavefront in different requests (their own keys, lengths,
-    path rows and step counters); each result equals the request alone (a
-    launch small enough for a wavefront per walker) and, for some, the
-    oracle. Any two of the queued requests together exceed 32,768 walkers."""
+    """A walk batch of several requests runs one lane per walker, with the
+    lanes of one wavefront in different requests (their own keys, lengths,
+    path rows and step counters); each result equals the request alone and,
+    for some, the oracle."""
     csaw, rp, col, ew, g, trace = setup
     say("server walk batch above the lane threshold")
     srv = csaw.Server(g, num_streams=1, memory_budget_bytes=1 << 30, max_batch=64)

@@ -78,7 +78,7 @@ def test_walk_guide_switch(csaw):
 
 @pytest.mark.parametrize("bias,restart,jump", [(1, 0, 0), (2, 0, 0), (1, 1 << 29, 1 << 28), (2, 0, 1 << 30)])
 def test_lane_walks(csaw, bias, restart, jump):
-    """Launches of at least 32,768 walkers take one lane per walker through
+    """Launches of at least 12,288 walkers take one lane per walker through
     the guide: weights with zeros (W = 0 stops), sinks, restart / jump moves,
     every walker against the oracle; the same walkers in a launch below that
     size (a wavefront each) give the same paths."""
