@@ -320,7 +320,10 @@ csaw_status csaw_walk(csaw_graph g, const csaw_walk_args* args, int32_t* paths,
  * prefixes: the same pick as a search of the whole prefix. About 48 bytes
  * per edge per weight array (51 GB for 2^30 edges); with the guide off (or
  * not yet built in a caller memory call) walks take the chunk tables with
- * one wavefront per walker, with the same paths.
+ * one wavefront per walker, with the same paths. Sampling calls draw from
+ * the long lists (more than 512 edges) of a weight array through its guide
+ * when it is built and on (a walk or a server builds it), else through the
+ * chunk tables: the same edges either way.
  * enable: 1 (default) or 0. A walk already running keeps its route. INVALID_ARG
  * otherwise. Turning the guide off does not free built tables. */
 csaw_status csaw_set_walk_guides(csaw_graph g, int32_t enable);

@@ -33,12 +33,13 @@ struct RowPtr {
 };
 
 // One edge of the walk guide: the inclusive prefix S_(i+1) of edge i in its
-// list beside the edge's neighbor, so that a probe of a few positions reads
-// one run of 16-byte records.
+// list beside the edge's neighbor and weight, so that a probe of a few
+// positions reads one run of 16-byte records (a sampling draw also needs the
+// exclusive prefix S_i = S_(i+1) - w and the weight of its pick).
 struct alignas(16) WalkEdge {
     uint64_t S;
     int32_t col;
-    uint32_t pad;
+    uint32_t w;
 };
 
 // One vertex of the walk guide (graphs with m < 2^32): its list

@@ -262,6 +262,11 @@ struct csaw_graph_s {
         g.wvtx_deg = wvtx_deg;
         g.wgd_ew = wgd_ew;
         g.wgd_deg = wgd_deg;
+        if (!walk_guides.load()) {  // walks and long-list draws take the chunk tables
+            g.wrec_ew = g.wrec_deg = nullptr;
+            g.wvtx_ew = g.wvtx_deg = nullptr;
+            g.wgd_ew = g.wgd_deg = nullptr;
+        }
         return g;
     }
 };
@@ -1241,6 +1246,9 @@ static csaw_status stream_layer(Streamer& st, const SampleLayer& p, int32_t l, i
         pp.g.degw = x.d_degw ? x.d_degw - e0 : nullptr;
         pp.g.gtab_ew = x.d_gtab_ew ? x.d_gtab_ew - r0 * kChunkGroups : nullptr;
         pp.g.gtab_deg = x.d_gtab_deg ? x.d_gtab_deg - r0 * kChunkGroups : nullptr;
+        pp.g.wrec_ew = pp.g.wrec_deg = nullptr;  // streamed lists have no walk guide
+        pp.g.wvtx_ew = pp.g.wvtx_deg = nullptr;
+        pp.g.wgd_ew = pp.g.wgd_deg = nullptr;
         pp.vlo = (int32_t)pg->vb[q];
         pp.vhi = (int32_t)std::min<int64_t>(pg->vb[q + 1], INT32_MAX);
         if (big_path) launch_select_big(pp, (int)std::min<int64_t>(std::max<int64_t>((cap + 3) / 4, 1), 2048), s);
@@ -1545,11 +1553,6 @@ static csaw_status walk_prepare(csaw_graph g, const csaw_walk_args* a, hipStream
 static WalkParams walk_params(csaw_graph g, const csaw_walk_args* a) {
     WalkParams p;
     p.g = g->dev();
-    if (!g->walk_guides.load()) {  // weighted walks take the chunk tables
-        p.g.wrec_ew = p.g.wrec_deg = nullptr;
-        p.g.wvtx_ew = p.g.wvtx_deg = nullptr;
-        p.g.wgd_ew = p.g.wgd_deg = nullptr;
-    }
     p.bias = a->bias_kind;
     p.w_return = a->w_return;
     p.w_common = a->w_common;

@@ -1363,6 +1363,59 @@ __device__ __forceinline__ int32_t row_group(const uint64_t* __restrict__ row, u
 // LDS, the chunk by a walk over the unit's chunk totals, the group by binary
 // search in the chunk's G row and the candidate by scanning the group's
 // weights (global memory / L2).
+// A list's walk guide (when the graph has one for its weight array): its
+// buckets and edge records, total W and bucket shift.
+struct GuidePool {
+    const WalkBucket* G;
+    const WalkEdge* er;
+    uint64_t W, K;
+    int64_t d;
+    int sh;
+};
+
+// m = max{i : S_i <= r} with S_m and b_m through the walk guide, per lane:
+// the bracket [G[k].pos, G[k+1].pos] of bucket k = r >> s (every position
+// before it ends at or below k * 2^s <= r; its last ends past (k+1) * 2^s,
+// or is the list's last), then the bracket's edge records 8 at a time
+// (positions past its end read the end, whose prefix exceeds r):
+// m = lo + #{j : S_(lo+j+1) <= r}, S_m = S_(m+1) - b_m. Two dependent loads
+// for a bracket of up to 8 positions, whatever the list's length.
+__device__ __forceinline__ void guide_search(const GuidePool& gp, uint64_t r, int64_t& m, uint64_t& Sm,
+                                             uint32_t& bm) {
+    const uint64_t k = r >> gp.sh;
+    const bool last = k + 1 >= gp.K;
+    int64_t lo = gp.G[k].pos;
+    const uint32_t p1 = gp.G[last ? k : k + 1].pos;
+    const int64_t hi = last ? gp.d - 1 : (int64_t)p1;
+    for (;;) {
+        uint64_t S[8];
+        uint32_t b[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t q = lo + j < hi ? lo + j : hi;
+            S[j] = gp.er[q].S;
+            b[j] = gp.er[q].w;
+        }
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) c += S[j] <= r ? 1 : 0;
+        if (c < 7 || lo + 7 >= hi) {
+            uint64_t s = S[0];
+            uint32_t x = b[0];
+#pragma unroll
+            for (int j = 1; j < 8; ++j) {
+                s = c == j ? S[j] : s;
+                x = c == j ? b[j] : x;
+            }
+            m = lo + c;
+            Sm = s - x;
+            bm = x;
+            return;
+        }
+        lo += 7;
+    }
+}
+
 struct UnitPool {
     const uint64_t* tab;    // LDS, nu + 1 entries
     int64_t nu;
@@ -1413,12 +1466,25 @@ __device__ void select_big_entry(const SampleLayer& p, const EntryInfo& E, uint6
         return;
     }
     const int64_t d = E.d;
+    const Key key{(uint32_t)E.key, (uint32_t)(E.key >> 32)};
+    const uint32_t c0 = E.c0, c1 = (uint32_t)p.layer, c2 = (uint32_t)E.v;
+    const bool ew = E.kind == kEdgeWeight;
+    const WalkBucket* gb = ew ? p.g.wgd_ew : p.g.wgd_deg;
+    const WalkEdge* ge = ew ? p.g.wrec_ew : p.g.wrec_deg;
+    if (gb && ge) {  // the list's walk guide: no table to build, two loads a draw
+        const uint64_t W = ld_uniform((ew ? p.g.wtot_ew : p.g.wtot_deg) + E.v);
+        const int sh = guide_shift(W, d);
+        const GuidePool gp{gb + guide_base(E.beg, E.v), ge + E.beg, W, ((W - 1) >> sh) + 1, d, sh};
+        const auto search = [&gp](uint64_t r, int64_t& m, uint64_t& Sm, uint32_t& bm) {
+            guide_search(gp, r, m, Sm, bm);
+        };
+        emit_slots(p, E, draw_slots(key, c0, c1, c2, E.k, p.rounds, W, search, search));
+        return;
+    }
     const int64_t nch = chunks_of(d);
     const uint32_t* w = (E.kind == kEdgeWeight ? p.g.ew : p.g.degw) + E.beg;
     const uint64_t* G = (E.kind == kEdgeWeight ? p.g.gtab_ew : p.g.gtab_deg) + (E.beg >> kTabShift) * kChunkGroups;
     const bool onchip = d <= kWaveMaxD;  // one chunk, not in the table
-    const Key key{(uint32_t)E.key, (uint32_t)(E.key >> 32)};
-    const uint32_t c0 = E.c0, c1 = (uint32_t)p.layer, c2 = (uint32_t)E.v;
     int64_t pos;
     if (d <= kGroupTabD) {
         const int64_t nc = (d + 15) / 16;

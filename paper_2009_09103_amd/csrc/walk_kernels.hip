@@ -1007,7 +1007,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_guides(RowPtr rowptr, const int
             k1 = k1 < K ? k1 : K;
             const uint64_t nk = i < d && k1 > k0 ? k1 - k0 : 0;
             if (i < d) {
-                rec[b + i] = WalkEdge{incl, y, 0u};
+                rec[b + i] = WalkEdge{incl, y, (uint32_t)x};
                 if (nk <= kGuideLaneFill)
                     for (uint64_t k = k0; k < k1; ++k) G[k] = WalkBucket{incl, (uint32_t)i, y};
             }

@@ -358,7 +358,7 @@ void launch_walk_guides(RowPtr rowptr, const int32_t* col, const uint32_t* w, co
             uint64_t run = 0, k = 0;
             for (int64_t i = 0; i < d; ++i) {
                 run += w[b + i];
-                rec[b + i] = WalkEdge{run, col[b + i], 0u};
+                rec[b + i] = WalkEdge{run, col[b + i], w[b + i]};
                 for (; k < K && (k << sh) < run; ++k) G[k] = WalkBucket{run, (uint32_t)i, col[b + i]};
             }
         }

@@ -577,3 +577,61 @@ def test_sparse_frontier_build(csaw, rng_seed):
     assert ni * ((len(rp) - 1 + 31) // 32) > (1 << 23)
     run_both(csaw, g, rp, col, ew, offs, seeds, fan, bias, rng_seed, instance_base=77)
     run_both(csaw, g, rp, col, ew, offs, seeds, fan, bias, rng_seed + 10)
+
+
+def light_run_hub(heavy, runs, run_len):
+    """Vertex 0 adjacent to runs * (run_len + 1) leaves: per run one weight
+    `heavy` then run_len weights of 1 (the leaves point back to vertex 0)."""
+    d = runs * (run_len + 1)
+    rp = np.concatenate([[0, d], np.arange(d + 1, 2 * d + 1)]).astype(np.int64)
+    col = np.concatenate([np.arange(1, d + 1), np.zeros(d)]).astype(np.int32)
+    ew = np.ones(2 * d, dtype=np.uint32)
+    ew[0:d:run_len + 1] = heavy
+    return rp, col, ew
+
+
+@pytest.mark.parametrize("case", ["giant_hub", "rmat16_degree", "direct_only", "wide", "light_runs"])
+def test_long_lists_through_the_walk_guide(csaw, case):
+    """Weighted long lists draw through the walk guide once a weighted walk
+    has built it for their weight array (two dependent loads a draw), and
+    through the chunk tables before that or with the guide off: the same
+    edges every time, equal to the oracle. Cases: a 200,000-neighbor hub with
+    a few dominant weights; degree bias on R-MAT 16; no repeated-sampling
+    rounds (every slot by the direct draw, whose held-candidate sums need
+    each pick's exclusive prefix and weight); weights near 2^32 (totals of
+    64 bits); runs of unit weights inside guide buckets (brackets longer
+    than a probe)."""
+    rounds = 0
+    if case == "giant_hub":
+        d = 200_000
+        rp = np.array([0, d] + [d] * d, dtype=np.int64)
+        col = np.arange(1, d + 1, dtype=np.int32)
+        ew = inputs.rng(9).integers(0, 1000, size=d).astype(np.uint32)
+        ew[:5] = 1 << 28
+        offs, seeds, fan, bias = np.arange(41, dtype=np.int64), np.zeros(40, dtype=np.int32), [64], 1
+    elif case in ("rmat16_degree", "direct_only"):
+        rp, col = inputs.rmat_csr(16, 16 << 16, 61)
+        ew = None
+        offs, seeds = inputs.single_instance_seeds(rp, col, 3000, 62)
+        fan, bias = [25, 10], 2
+        rounds = -1 if case == "direct_only" else 0
+    elif case == "wide":
+        rp, col = inputs.rmat_csr(15, 16 << 15, 63)
+        ew = inputs.rng(64).integers((1 << 32) - 1000, 1 << 32, size=len(col), dtype=np.uint64).astype(np.uint32)
+        offs, seeds = inputs.single_instance_seeds(rp, col, 2000, 65)
+        fan, bias = [25, 10], 1
+    else:
+        rp, col, ew = light_run_hub(207_000, 8, 100)
+        offs, seeds, fan, bias = np.arange(65, dtype=np.int64), np.zeros(64, dtype=np.int32), [40], 1
+    assert np.diff(rp).max() > 512
+    orc_rounds = {-1: 0, 0: 8}.get(rounds, rounds)
+    ref = oracle.sample(rp, col, ew, offs, seeds, fan, bias_kind=bias, rng_seed=71, rounds=orc_rounds)
+    g = csaw.Graph(rp, col, ew)
+    say("long lists %s: chunk tables" % case)
+    assert_same(g.sample(offs, seeds, fan, bias, rng_seed=71, rounds=rounds), ref)
+    g.walk(np.array([int(seeds[0])], dtype=np.int32), 1, bias, rng_seed=1)  # builds the guide
+    say("long lists %s: walk guide" % case)
+    assert_same(g.sample(offs, seeds, fan, bias, rng_seed=71, rounds=rounds), ref)
+    g.set_walk_guides(False)
+    say("long lists %s: guide off" % case)
+    assert_same(g.sample(offs, seeds, fan, bias, rng_seed=71, rounds=rounds), ref)
