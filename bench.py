@@ -21,8 +21,9 @@ setting is autotuned on the timed call first (--tuning).
 Other workloads: batched (4,096 instances in one call against 4,096 plain
 calls), node2vec (R-MAT 24 walks), mdrw (multi-dimensional random walks),
 forest_fire (burning probability 0.7, depth 2), metropolis
-(Metropolis-Hastings walks), layer (layer sampling), copy (a 1 GiB device
-copy, the HBM counter calibration).
+(Metropolis-Hastings walks), layer (layer sampling), walks (edge-weight
+walks on the served R-MAT 26 graph, --walkers per call, one lane per walker
+from 12,288), copy (a 1 GiB device copy, the HBM counter calibration).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -781,6 +782,80 @@ def bench_metropolis(args):
     }
 
 
+def bench_walks(args):
+    """Edge-weight walks on the served graph (R-MAT 26, weight = out-degree of
+    the destination), resident in HBM with the walk guide built: --walkers
+    walkers (default 262,144: one lane each) from uniform starts, length 80,
+    Philox seeds cycling 1..3. The roofline is the lane kernel's: algorithmic
+    bytes per step (walk_step_bytes) over its event time, and the measured
+    HBM bytes per step of the committed counter record."""
+    import torch
+    from paper_2009_09103_amd import csaw, inputs
+
+    rec = inputs.SERVED
+    scale = args.served_scale or rec["scale"]
+    nw, L = args.walkers, 80
+    log("generating R-MAT %d graph" % scale)
+    rp, col = inputs.graph_for(rec, scale=scale, num_edges=16 << scale)
+    ew = inputs.dst_outdeg_weights(rp, col)
+    g = csaw.Graph(rp, col, ew)
+    starts = torch.from_numpy(inputs.walker_starts(rp, col, nw, 2026)).to(g.device)
+    paths = torch.empty((nw, L + 1), dtype=torch.int32, device=g.device)
+    t0 = time.perf_counter()
+    g.walk(starts[:64], 1, csaw.EDGE_WEIGHT, rng_seed=1)  # builds the walk guide
+    torch.cuda.synchronize()
+    log("walk guide built in %.1f ms" % ((time.perf_counter() - t0) * 1e3))
+    for i in range(args.warmup):
+        g.walk(starts, L, csaw.EDGE_WEIGHT, rng_seed=1 + i % 3, paths=paths)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    for i in range(args.steps):
+        steps += g.walk(starts, L, csaw.EDGE_WEIGHT, rng_seed=1 + i % 3, paths=paths)[1]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    csaw.profile_reset()
+    csaw.profile_enable(True)
+    _, st = g.walk(starts, L, csaw.EDGE_WEIGHT, rng_seed=1, paths=paths)
+    torch.cuda.synchronize()
+    kms, kn = csaw.profile_read("walk")
+    csaw.profile_enable(False)
+    csaw.profile_reset()
+    alg, wsteps = walk_step_bytes(rp, paths.cpu().numpy())
+    achieved = alg / (kms / 1e3) / 1e9 if kms > 0 else 0.0
+    per_step = measured_traffic("traffic_walk_lane_rmat26.md", WALK_SOURCES, "hbm_bytes_per_step")
+    copy_gbps = measured_copy_gbps()
+    line = {
+        "metric": "walk steps/s (sampled edges/s), edge-weight random walk",
+        "value": steps / args.steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 bias / u64 prefix (integer)", "data": "synthetic",
+        "config": {"workload": "walks_rmat%d" % scale, "graph": "R-MAT scale %d, edge factor 16, edge weight = "
+                   "out-degree of the destination" % scale, "n": len(rp) - 1, "m": len(col), "walkers": nw,
+                   "length": L},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": per_step * wsteps / max(kn, 1) if per_step else None,
+                     "traffic_GBps": per_step * wsteps / (kms / 1e3) / 1e9 if per_step and kms > 0 else None,
+                     "measured_copy_GBps": copy_gbps, "kernel": "k_walk_lane<false>" if nw >= 12288 else
+                     "k_walk_wave_first", "launches": kn, "avg_launch_us": kms / max(kn, 1) * 1e3,
+                     "alg_bytes_per_launch": alg / max(kn, 1), "steps_per_s": wsteps / (kms / 1e3)},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on every 4096th walker id (ids fix the draws), timed
+        import oracle
+        idx = np.arange(0, nw, 4096)
+        st_h = starts.cpu().numpy()[idx]
+        t0 = time.perf_counter()
+        _, osteps, _ = oracle.walk(rp, col, ew, st_h, L, bias_kind=1, rng_seed=1, walker_ids=idx.astype(np.uint64),
+                                   nthreads=1)
+        t1 = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": float(osteps.sum()) / t1, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                                "sample": "%d walkers (every 4096th id) x %d steps, %.1f s on one thread" % (
+                                    len(idx), L, t1)}
+    return line
+
+
 def bench_layer(args):
     """Layer sampling on the degree-biased R-MAT 22 graph: 2,000 instances of
     512 sorted seeds, fanouts [64, 64], out-degree bias."""
@@ -1032,6 +1107,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--qps", type=float, nargs="*", default=None)
     ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--walkers", type=int, default=1 << 18, help="walks workload: walkers per call")
     ap.add_argument("--passes", type=int, default=5,
                     help="served workload: passes of the trace per QPS point and path; the median is reported")
     ap.add_argument("--served-scale", type=int, default=0)
@@ -1083,6 +1159,8 @@ def main():
         line = bench_mdrw(args)
     elif args.workload == "copy":
         line = bench_copy(args)
+    elif args.workload == "walks":
+        line = bench_walks(args)
     else:
         print("unknown workload %s" % args.workload, file=sys.stderr)
         sys.exit(2)
