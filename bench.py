@@ -842,16 +842,16 @@ def bench_walks(args):
                      "alg_bytes_per_launch": alg / max(kn, 1), "steps_per_s": wsteps / (kms / 1e3)},
     }
     if not args.no_cpu_baseline:
-        # the oracle on every 128th walker id (ids fix the draws), timed
+        # the oracle on every 64th walker id (ids fix the draws), timed
         import oracle
-        idx = np.arange(0, nw, 128)
+        idx = np.arange(0, nw, 64)
         st_h = starts.cpu().numpy()[idx]
         t0 = time.perf_counter()
         _, osteps, _ = oracle.walk(rp, col, ew, st_h, L, bias_kind=1, rng_seed=1, walker_ids=idx.astype(np.uint64),
                                    nthreads=1)
         t1 = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": float(osteps.sum()) / t1, "unit": "steps/s", "cores": 1, "kind": "oracle",
-                                "sample": "%d walkers (every 128th id) x %d steps, %.1f s on one thread" % (
+                                "sample": "%d walkers (every 64th id) x %d steps, %.1f s on one thread" % (
                                     len(idx), L, t1)}
     return line
 
