@@ -696,6 +696,65 @@ __device__ __forceinline__ int32_t walk_step_guide(const WalkEdge* __restrict__ 
     return readlane_i32(y, c);
 }
 
+// node2vec step from v when the previous vertex t has a short list (fewer
+// than 64 entries) and N(v) a long one: instead of merging all of N(v) with
+// N(t), lane k takes the k-th entry x of N(t) and binary-searches both ends
+// of x's run in N(v) (lane d_t does the same for t itself), so membership
+// costs about log2(d_v) dependent loads whatever d_v is. The pick is found
+// without reading N(v) again: with C(j) = common candidates below position j
+// (a wave sum over the lanes' runs; a repeated x counts once) and T(j) =
+// copies of t below j, the exclusive prefix is
+// S(j) = w_out (j - C - T) + w_common C + w_return T, and m is the smallest i
+// with S(i + 1) > r, by binary search over i: the same m as the merge.
+constexpr int64_t kShortPrevMinD = 2048;  // shorter N(v): the merge is cheaper
+__device__ __forceinline__ int64_t walk_step_n2v_short_prev(const WalkParams& p, Key key, uint32_t c0, int32_t s,
+                                                            int32_t v, int64_t beg, int64_t d, int32_t t,
+                                                            int64_t tb, int64_t te, bool& stop) {
+    const int lane = lane_id();
+    const int32_t* __restrict__ col = p.g.col;
+    const int64_t dt = te - tb;  // < kWave
+    const bool act = lane <= dt;
+    const int32_t x = lane < dt ? col[tb + lane] : t;
+    // [lo1, lo2): the run of x in N(v) (lower and upper bound, side by side)
+    int64_t lo1 = 0, hi1 = act ? d : 0, lo2 = 0, hi2 = act ? d : 0;
+    while (ballot(lo1 < hi1 || lo2 < hi2)) {
+        const bool s1 = lo1 < hi1, s2 = lo2 < hi2;
+        const int64_t m1 = (lo1 + hi1) >> 1, m2 = (lo2 + hi2) >> 1;
+        const int32_t y1 = col[beg + (s1 ? m1 : 0)];
+        const int32_t y2 = col[beg + (s2 ? m2 : 0)];
+        if (s1) {
+            if (y1 < x) lo1 = m1 + 1;
+            else hi1 = m1;
+        }
+        if (s2) {
+            if (y2 <= x) lo2 = m2 + 1;
+            else hi2 = m2;
+        }
+    }
+    const int32_t xprev = __shfl_up(x, 1, kWave);
+    const bool common = lane < dt && (lane == 0 || xprev != x) && x != t && lo2 > lo1;
+    const int64_t cnt = lo2 - lo1;
+    const int64_t pos_t = readlane_i64(lo1, (int)dt);
+    const int64_t n_t = readlane_i64(lo2, (int)dt) - pos_t;
+    const uint64_t c = (uint64_t)wave_sum_i64(common ? cnt : 0);
+    const uint64_t wo = p.w_outward, wc = p.w_common, wr = p.w_return;
+    const uint64_t W = wo * ((uint64_t)d - c - (uint64_t)n_t) + wc * c + wr * (uint64_t)n_t;
+    stop = W == 0;
+    if (stop) return 0;
+    const uint64_t r = draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, W);
+    int64_t a = 0, b = d - 1;  // S(d) = W > r
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1, j = mid + 1;
+        const int64_t below = j - lo1 < 0 ? 0 : (j - lo1 < cnt ? j - lo1 : cnt);
+        const uint64_t C = (uint64_t)wave_sum_i64(common ? below : 0);
+        const uint64_t T = j <= pos_t ? 0 : (uint64_t)(j - pos_t < n_t ? j - pos_t : n_t);
+        const uint64_t S = wo * ((uint64_t)j - C - T) + wc * C + wr * T;
+        if (S > r) b = mid;
+        else a = mid + 1;
+    }
+    return a;
+}
+
 template <bool kN2v, bool kMoves>
 __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
     __shared__ WalkLds<kN2v> lds_all[kWavesPerBlock];
@@ -749,7 +808,9 @@ __device__ __forceinline__ void walk_wave_body(const WalkParams& p) {
                 m = (int64_t)draw(key, c0, (uint32_t)s, (uint32_t)v, 0u, (uint64_t)d);
             } else {
                 if constexpr (kN2v) {
-                    if (d <= kWalkBits) m = walk_step_n2v(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
+                    if (te - tb < kWave && d >= kShortPrevMinD)
+                        m = walk_step_n2v_short_prev(p, key, c0, s, v, beg, d, t, tb, te, stop);
+                    else if (d <= kWalkBits) m = walk_step_n2v(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
                     else m = walk_step_biased<true>(p, lds, key, c0, s, v, beg, d, t, tb, te, stop);
                 } else {
                     const bool dg = p.bias == kNeighborDegree;

@@ -240,6 +240,35 @@ def test_node2vec_long_list_membership(csaw):
     run_both(csaw, g, rp, col, None, starts, 24, 3, 5, node2vec=(4, 1, 2))
 
 
+def test_node2vec_short_previous_list_with_duplicate_edges(csaw):
+    """From a hub of 3,000 leaves (each repeated up to three times in its
+    list, and the hub repeated as often in the leaf's) after a leaf whose
+    list is short: the step finds N(t)'s members by binary search in N(v)
+    (both ends of each run, a repeated x counted once, the copies of t at
+    the return weight) and the pick without a merge. Leaves form a ring, so
+    a leaf's list holds the hub and two other leaves."""
+    nl = 3000
+    lists = {0: []}
+    for i in range(1, nl + 1):
+        rep = 1 + (i % 3)
+        lists[0] += [i] * rep
+        ring = [i % nl + 1, (i - 2) % nl + 1]
+        lists[i] = [0] * rep + ring
+    n = nl + 1
+    rp = np.zeros(n + 1, dtype=np.int64)
+    cols = []
+    for v in range(n):
+        lst = sorted(lists[v])
+        rp[v + 1] = rp[v] + len(lst)
+        cols += lst
+    col = np.array(cols, dtype=np.int32)
+    g = csaw.Graph(rp, col)
+    starts = np.arange(1, nl + 1, 3, dtype=np.int32)
+    run_both(csaw, g, rp, col, None, starts, 12, 3, 19, node2vec=(1, 2, 4))
+    run_both(csaw, g, rp, col, None, starts, 12, 3, 20, node2vec=(3, 1, 2))
+    run_both(csaw, g, rp, col, None, starts, 12, 3, 21, node2vec=(0, 1, 1))
+
+
 def test_node2vec_needs_a_symmetric_graph(csaw):
     """node2vec's bias is defined on undirected graphs: a walk on a directed
     graph is refused (the device check finds an edge without its reverse),
