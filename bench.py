@@ -962,8 +962,11 @@ def walk_bytes_node2vec(rowptr, paths):
     """Algorithmic bytes of node2vec walks from their paths: a step from v
     with previous vertex t reads v's row offsets (16), N(v) (4 d_v: biases
     and the pick), N(t) (4 d_t: membership) and writes the next vertex (4);
-    the first step (no t) is an unbiased draw: offsets, one neighbor id, the
-    write (24)."""
+    when N(t) is short (d_t < 64) and N(v) long (d_v >= 2048) the step reads
+    N(t) and, for each of its entries and t, the two ends of a binary search
+    in N(v) (8 per level, ceil(log2(d_v + 1)) levels) plus the pick's id,
+    instead of N(v) whole; the first step (no t) is an unbiased draw:
+    offsets, one neighbor id, the write (24)."""
     deg = np.diff(rowptr).astype(np.float64)
     P = paths
     steps = (P[:, 1:] >= 0)
@@ -971,7 +974,11 @@ def walk_bytes_node2vec(rowptr, paths):
     later = steps[:, 1:]
     v = np.where(later, P[:, 1:-1], 0)
     t = np.where(later, P[:, :-2], 0)
-    rest = (20.0 * later + 4.0 * deg[v] * later + 4.0 * deg[t] * later).sum()
+    dv, dt = deg[v], deg[t]
+    short = (dt < 64) & (dv >= 2048)
+    levels = np.ceil(np.log2(dv + 1.0))
+    nv = np.where(short, 8.0 * (dt + 1.0) * levels + 4.0, 4.0 * dv)
+    rest = ((20.0 + nv + 4.0 * dt) * later).sum()
     return float(first + rest), int(steps.sum())
 
 

@@ -61,3 +61,18 @@ def test_walk_step_bytes_by_route():
     # taken steps leave 0, 1, 2, 4 (row 0); 1, 1 (row 1)
     assert steps == 6
     assert b == 16 * 6 + 4 * 3 + 24 + 24 + 4 * 1 + 24 + 24
+
+
+def test_node2vec_bytes_by_route():
+    """A node2vec step costs 20 + 4 d_v + 4 d_t, or with a short previous
+    list (d_t < 64) and a long current one (d_v >= 2,048) 20 + 4 d_t plus
+    8 (d_t + 1) ceil(log2(d_v + 1)) + 4; the first step 24."""
+    bench = load_bench()
+    deg = np.array([3, 3000, 10, 100])
+    rp = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    paths = np.array([[0, 1, 2, 3, -1]], dtype=np.int32)
+    b, steps = bench.walk_bytes_node2vec(rp, paths)
+    assert steps == 3
+    lv = np.ceil(np.log2(3001.0))
+    exp = 24 + (20 + 8 * 4 * lv + 4 + 4 * 3) + (20 + 4 * 10 + 4 * 3000)
+    assert abs(b - exp) < 1e-6
