@@ -546,7 +546,9 @@ def bench_served(args):
     served_kw = dict(num_streams=3, max_batch=256, memory_budget_bytes=48 << 30, max_batch_walkers=1 << 18,
                      result_pool_bytes=pool)
     plain_kw = dict(num_streams=1, max_batch=1, memory_budget_bytes=16 << 30, result_pool_bytes=pool)
-    qps_list = args.qps or [400.0, 1600.0, 6400.0, 25600.0]
+    # up to 102,400 QPS, where the 400 requests arrive within 4 ms and the
+    # server runs saturated
+    qps_list = args.qps or [400.0, 1600.0, 6400.0, 25600.0, 102400.0]
     points = []
     for qps in qps_list:
         trace = inputs.request_trace(rp, col, args.requests, qps, rec["trace_rng"], rec["sample_fraction"])
