@@ -5,7 +5,11 @@ and one batch of 320 sampling requests whose instance bitmaps take 5.4 GB
 (more than 2^32 bytes, indexed past 2^30 words). Every request's result
 equals the same request run alone; a subset is checked against the oracle
 (sampling whole, walks on every 16th walker id, an exact subset since each
-walker's draws are keyed by its own id)."""
+walker's draws are keyed by its own id). The walks workload's own launch on
+this graph (262,144 edge-weight walkers of length 80, one lane each) and a
+launch of 4,096 walkers (a wavefront each) are checked against the oracle on
+strided walker ids, with every step of every 8th walker an edge of positive
+weight."""
 import sys
 
 import numpy as np
@@ -122,3 +126,49 @@ def test_served_rmat26_mix_equals_alone_and_oracle(served):
                 ref, _, _ = oracle.walk(rp, col, ew, r["starts"][sub], r["length"], bias_kind=r["bias"],
                                         rng_seed=r["rng_seed"], walker_ids=r["id"] + sub.astype(np.uint64))
                 np.testing.assert_array_equal(res.paths[sub], ref)
+
+
+def check_steps_are_edges(rp, col, ew, paths):
+    """Every consecutive pair (u, v) of a path is an edge of positive weight
+    (vectorised lower bound of v in N(u)), and a path that stops early stops
+    at a vertex whose list has no positive weight."""
+    u = paths[:, :-1].reshape(-1).astype(np.int64)
+    v = paths[:, 1:].reshape(-1)
+    keep = v >= 0
+    u, v = u[keep], v[keep]
+    assert np.all(u >= 0)
+    lo, hi = rp[u].copy(), rp[u + 1].copy()
+    end = hi.copy()
+    while True:
+        open_ = lo < hi
+        if not open_.any():
+            break
+        mid = (lo + hi) // 2
+        below = col[np.minimum(mid, len(col) - 1)] < v
+        lo = np.where(open_ & below, mid + 1, lo)
+        hi = np.where(open_ & ~below, mid, hi)
+    assert np.all(lo < end)
+    np.testing.assert_array_equal(col[lo], v)
+    assert np.all(ew[lo] > 0)
+    stopped = (paths[:, -1] < 0) & (paths[:, 0] >= 0)
+    last = (paths[stopped] >= 0).sum(axis=1) - 1
+    for x in np.unique(paths[stopped][np.arange(len(last)), last]):
+        assert int(ew[rp[x]:rp[x + 1]].astype(np.uint64).sum()) == 0
+
+
+@pytest.mark.parametrize("num_walkers,stride", [(262144, 256), (4096, 8)])
+def test_walks_workload_against_oracle(served, num_walkers, stride):
+    csaw, rp, col, ew, g, _ = served
+    length = 80
+    starts = inputs.walker_starts(rp, col, num_walkers, 2026)
+    say("%d edge-weight walkers of length %d, Philox seed 1" % (num_walkers, length))
+    paths, steps = g.walk(starts, length, csaw.EDGE_WEIGHT, rng_seed=1)
+    paths = paths.cpu().numpy()
+    assert 0 < steps <= num_walkers * length
+    sub = np.arange(0, num_walkers, stride)
+    say("oracle on %d walkers" % len(sub))
+    ref, _, _ = oracle.walk(rp, col, ew, starts[sub], length, bias_kind=oracle.EDGE_WEIGHT, rng_seed=1,
+                            walker_ids=sub.astype(np.uint64))
+    np.testing.assert_array_equal(paths[sub], ref)
+    say("steps of every 8th walker")
+    check_steps_are_edges(rp, col, ew, paths[::8])
